@@ -1,0 +1,382 @@
+// LCG reference oracle -- TEST INFRASTRUCTURE ONLY.
+//
+// A plain, slow, single-threaded CPU implementation of the stable locally
+// consistent grammar construction (BuildGram), of MergeGrams and of grammar
+// expansion, written from the paper "Efficient terabyte-scale text
+// compression via stable local consistency and parallel grammar processing"
+// (Diaz-Dominguez, arXiv 2411.12439).  Only the test suite, the smoke check
+// and the CPU-baseline leg of the benchmark load it.  It shares no code,
+// header, table or constant generator with the HIP library; the product path
+// never calls it.
+//
+// Readings of points the paper leaves open (all fixed here, and mirrored by
+// the HIP library through its own, independent code):
+//   * Hash family (Sec. 2.4 and 3.2, Eq. 2 and Eq. 4): one prime
+//     p = 2^61 - 1 for every level, fingerprint range m = 2^32.  The
+//     coefficients (a_i, b_i, c_i) of levels i = 0..63 are drawn in that
+//     order from successive outputs of the SplitMix64 generator (Steele,
+//     Lea and Flood, 2014, in Vigna's formulation) seeded with the caller's
+//     seed; each output is reduced mod p and a zero result is drawn again,
+//     so all three lie in [1, p-1] as Sec. 3.2 asks.
+//   * h^0(s) = ((a_0 s + b_0) mod p) mod 2^32 for byte values s = 0..255
+//     (terminals are raw bytes).
+//   * Eq. 4: F[X] = ((a_i * sum_{j=1..q} F[Q[j]] c_i^{j-1} + b_i) mod p) mod 2^32,
+//     leftmost symbol unscaled.
+//   * Types follow Eq. 3 on fingerprints only (collisions count as equal);
+//     the trailing equal-symbol run of a string has no type and no break
+//     (Sec. 3.3); position 1 always starts a phrase; there is no sentinel.
+//   * Nonterminals are per-level ranks (App. A.1) assigned in order of first
+//     occurrence (string order, then position).  Sec. 3.3 allows any order.
+//   * A string of length one is compressed at level 0: C[j] = its byte.
+//     Empty strings and empty collections are rejected.
+//   * Merge is Sec. 3.6 in rank form (App. A.1): the offsets L_a, L_b only
+//     convert ranks to global ids and are not materialised.
+
+#include <cstdint>
+#include <cstring>
+#include <cstdio>
+#include <string>
+#include <vector>
+#include <unordered_map>
+
+namespace {
+
+const uint64_t kP = (1ULL << 61) - 1;  // Mersenne prime 2^61 - 1
+const int kLevels = 64;                // size of the hash family H
+
+thread_local std::string g_err;
+
+uint64_t mulmod(uint64_t x, uint64_t y) {
+  return (uint64_t)(((unsigned __int128)x * y) % kP);
+}
+uint64_t addmod(uint64_t x, uint64_t y) {
+  return (uint64_t)(((unsigned __int128)x + y) % kP);
+}
+
+// SplitMix64: state advances by the golden-ratio increment, the output is
+// the state passed through two xor-shift-multiply rounds and a final xorshift.
+struct SplitMix64 {
+  uint64_t s;
+  uint64_t next() {
+    s += 0x9E3779B97F4A7C15ULL;
+    uint64_t z = s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+  }
+  uint64_t next_nonzero_mod_p() {
+    for (;;) {
+      uint64_t v = next() % kP;
+      if (v != 0) return v;
+    }
+  }
+};
+
+struct HashFamily {
+  uint64_t seed;
+  uint64_t a[kLevels], b[kLevels], c[kLevels];
+  explicit HashFamily(uint64_t sd) : seed(sd) {
+    SplitMix64 g{sd};
+    for (int i = 0; i < kLevels; ++i) {
+      a[i] = g.next_nonzero_mod_p();
+      b[i] = g.next_nonzero_mod_p();
+      c[i] = g.next_nonzero_mod_p();
+    }
+  }
+  // h^0 on a terminal (Sec. 2.4, universal hash; Sec. 3.2).
+  uint32_t h0(uint32_t s) const {
+    return (uint32_t)(addmod(mulmod(a[0], s), b[0]) & 0xFFFFFFFFULL);
+  }
+  // Eq. 4 before the final "mod m": (a_i * sum F[Q_j] c_i^{j-1} + b_i) mod p.
+  uint64_t poly(int i, const std::vector<uint32_t>& fq) const {
+    uint64_t sum = 0, pw = 1;
+    for (size_t j = 0; j < fq.size(); ++j) {
+      sum = addmod(sum, mulmod(fq[j], pw));
+      pw = mulmod(pw, c[i]);
+    }
+    return addmod(mulmod(a[i], sum), b[i]);
+  }
+};
+
+struct Level {
+  std::vector<uint64_t> rhs_off{0};  // u + 1 offsets into rhs
+  std::vector<uint32_t> rhs;         // level-(i-1) ranks (bytes at level 1)
+  std::vector<uint32_t> fp;          // F^i of each rule
+  uint32_t size() const { return (uint32_t)fp.size(); }
+};
+
+struct RoundStat {
+  uint64_t n_in;      // total length of the active strings entering the round
+  uint64_t phrases;   // phrases produced (d_i)
+  uint64_t new_rules; // distinct phrases = rules of the level (u_i)
+  uint64_t rhs_len;   // sum of rhs lengths of the new rules (Q_i)
+  uint64_t active;    // strings still active after the round
+};
+
+struct VecHash {
+  size_t operator()(const std::vector<uint32_t>& v) const {
+    uint64_t h = 1469598103934665603ULL;  // FNV-1a over the symbols
+    for (uint32_t x : v) {
+      for (int k = 0; k < 4; ++k) {
+        h ^= (x >> (8 * k)) & 0xFF;
+        h *= 1099511628211ULL;
+      }
+    }
+    return (size_t)h;
+  }
+};
+typedef std::unordered_map<std::vector<uint32_t>, uint32_t, VecHash> Dict;
+
+}  // namespace
+
+struct OracleGrammar {
+  HashFamily H;
+  std::vector<Level> levels;       // levels[i-1] holds level i
+  std::vector<uint8_t> c_level;    // level of C[j]
+  std::vector<uint32_t> c_sym;     // rank (or byte at level 0) of C[j]
+  std::vector<RoundStat> stats;
+  explicit OracleGrammar(uint64_t seed) : H(seed) {}
+};
+
+namespace {
+
+// Fingerprint of a level-(i-1) symbol: h^0 for bytes, stored F otherwise.
+uint32_t fp_of(const OracleGrammar& g, int level, uint32_t sym) {
+  if (level == 0) return g.H.h0(sym);
+  return g.levels[level - 1].fp[sym];
+}
+
+// Eq. 3 types from right to left.  0 = undefined (trailing equal run),
+// 1 = L, 2 = S.  LMS positions (S preceded by L) are the breaks, together
+// with the first position (phrase rule of Sec. 3.3).
+void parse_breaks(const std::vector<uint32_t>& f, std::vector<uint8_t>& brk) {
+  size_t n = f.size();
+  std::vector<uint8_t> type(n, 0);
+  brk.assign(n, 0);
+  if (n == 0) return;
+  type[n - 1] = 0;
+  for (size_t l = n - 1; l-- > 0;) {
+    if (f[l] > f[l + 1]) type[l] = 1;
+    else if (f[l] < f[l + 1]) type[l] = 2;
+    else type[l] = type[l + 1];
+  }
+  brk[0] = 1;
+  for (size_t l = 1; l < n; ++l)
+    if (type[l] == 2 && type[l - 1] == 1) brk[l] = 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* oracle_last_error(void) { return g_err.c_str(); }
+
+void oracle_hash_params(uint64_t seed, uint64_t* a, uint64_t* b, uint64_t* c) {
+  HashFamily H(seed);
+  for (int i = 0; i < kLevels; ++i) { a[i] = H.a[i]; b[i] = H.b[i]; c[i] = H.c[i]; }
+}
+
+// Round-1 breaks of one string (1 = phrase starts here), for parser pins.
+void oracle_round1_breaks(const uint8_t* s, uint64_t n, uint64_t seed, uint8_t* out) {
+  HashFamily H(seed);
+  std::vector<uint32_t> f(n);
+  for (uint64_t i = 0; i < n; ++i) f[i] = H.h0(s[i]);
+  std::vector<uint8_t> brk;
+  parse_breaks(f, brk);
+  for (uint64_t i = 0; i < n; ++i) out[i] = brk[i];
+}
+
+// BuildGram(T, H) (Sec. 3.3): rounds of RandLMSPar over the active strings,
+// one dictionary per level shared by all strings, until no string is active.
+OracleGrammar* oracle_build(const uint8_t* text, const uint64_t* offsets, uint32_t k,
+                            uint64_t seed) {
+  if (k == 0) { g_err = "empty collection"; return nullptr; }
+  OracleGrammar* g = new OracleGrammar(seed);
+  g->c_level.assign(k, 0);
+  g->c_sym.assign(k, 0);
+  std::vector<std::vector<uint32_t>> cur(k);
+  std::vector<uint8_t> active(k, 0);
+  size_t n_active = 0;
+  for (uint32_t j = 0; j < k; ++j) {
+    if (offsets[j + 1] < offsets[j]) { g_err = "offsets decrease"; delete g; return nullptr; }
+    uint64_t len = offsets[j + 1] - offsets[j];
+    if (len == 0) { g_err = "empty string"; delete g; return nullptr; }
+    if (len == 1) { g->c_level[j] = 0; g->c_sym[j] = text[offsets[j]]; continue; }
+    cur[j].assign(text + offsets[j], text + offsets[j + 1]);
+    active[j] = 1;
+    ++n_active;
+  }
+  for (int i = 1; n_active > 0; ++i) {
+    if (i >= kLevels) { g_err = "hash family exhausted"; delete g; return nullptr; }
+    g->levels.emplace_back();
+    Level& L = g->levels.back();
+    Dict dict;
+    RoundStat st{0, 0, 0, 0, 0};
+    std::vector<uint32_t> f, q, fq;
+    std::vector<uint8_t> brk;
+    for (uint32_t j = 0; j < k; ++j) {
+      if (!active[j]) continue;
+      const std::vector<uint32_t>& S = cur[j];
+      st.n_in += S.size();
+      f.resize(S.size());
+      for (size_t l = 0; l < S.size(); ++l) f[l] = fp_of(*g, i - 1, S[l]);
+      parse_breaks(f, brk);
+      std::vector<uint32_t> next;
+      size_t start = 0;
+      for (size_t l = 1; l <= S.size(); ++l) {
+        if (l < S.size() && !brk[l]) continue;
+        q.assign(S.begin() + start, S.begin() + l);
+        auto it = dict.find(q);
+        uint32_t r;
+        if (it != dict.end()) {
+          r = it->second;
+        } else {
+          r = L.size();
+          dict.emplace(q, r);
+          fq.assign(f.begin() + start, f.begin() + l);
+          uint64_t P = g->H.poly(i, fq);
+          L.fp.push_back((uint32_t)(P & 0xFFFFFFFFULL));
+          L.rhs.insert(L.rhs.end(), q.begin(), q.end());
+          L.rhs_off.push_back(L.rhs.size());
+          st.rhs_len += q.size();
+        }
+        next.push_back(r);
+        start = l;
+      }
+      st.phrases += next.size();
+      cur[j].swap(next);
+      if (cur[j].size() == 1) {
+        g->c_level[j] = (uint8_t)i;
+        g->c_sym[j] = cur[j][0];
+        active[j] = 0;
+        --n_active;
+        std::vector<uint32_t>().swap(cur[j]);
+      }
+    }
+    st.new_rules = L.size();
+    st.active = n_active;
+    g->stats.push_back(st);
+  }
+  return g;
+}
+
+// Build a grammar directly from arrays (used to encode the paper's worked
+// merge example by hand).  rhs_off has u_i + 1 entries per level.
+OracleGrammar* oracle_from_arrays(uint64_t seed, uint32_t n_levels, const uint32_t* u,
+                                  const uint64_t* const* rhs_off, const uint32_t* const* rhs,
+                                  const uint32_t* const* fp, uint32_t k,
+                                  const uint8_t* c_level, const uint32_t* c_sym) {
+  OracleGrammar* g = new OracleGrammar(seed);
+  for (uint32_t i = 0; i < n_levels; ++i) {
+    g->levels.emplace_back();
+    Level& L = g->levels.back();
+    L.rhs_off.assign(rhs_off[i], rhs_off[i] + u[i] + 1);
+    L.rhs.assign(rhs[i], rhs[i] + rhs_off[i][u[i]]);
+    L.fp.assign(fp[i], fp[i] + u[i]);
+  }
+  g->c_level.assign(c_level, c_level + k);
+  g->c_sym.assign(c_sym, c_sym + k);
+  return g;
+}
+
+// MergeGrams(G_a, G_b) (Sec. 3.5 and 3.6): G_a absorbs G_b level by level.
+// For each level i, every rule of G_b (its rhs already renamed into G_a's
+// level-(i-1) ranks) is looked up among G_a's level-i right-hand sides; a hit
+// reuses G_a's rank, a miss appends the rule at the end of level i.  The
+// resulting rank map M renames the next level of G_b and the entries of C_b
+// at level i.  Finally C_a becomes C_a . C_b.  G_b is left unchanged.
+int oracle_merge(OracleGrammar* a, const OracleGrammar* b) {
+  if (a->H.seed != b->H.seed) { g_err = "hash families differ"; return -3; }
+  size_t la = a->levels.size(), lb = b->levels.size();
+  std::vector<std::vector<uint32_t>> M(lb + 1);  // M[i]: b-rank -> a-rank, level i
+  while (a->levels.size() < lb) a->levels.emplace_back();
+  (void)la;
+  for (size_t i = 1; i <= lb; ++i) {
+    Level& A = a->levels[i - 1];
+    const Level& B = b->levels[i - 1];
+    Dict H;
+    for (uint32_t r = 0; r < A.size(); ++r)
+      H.emplace(std::vector<uint32_t>(A.rhs.begin() + A.rhs_off[r],
+                                      A.rhs.begin() + A.rhs_off[r + 1]), r);
+    M[i].assign(B.size(), 0);
+    std::vector<uint32_t> q;
+    for (uint32_t rb = 0; rb < B.size(); ++rb) {
+      q.assign(B.rhs.begin() + B.rhs_off[rb], B.rhs.begin() + B.rhs_off[rb + 1]);
+      if (i >= 2)
+        for (uint32_t& x : q) x = M[i - 1][x];
+      auto it = H.find(q);
+      if (it != H.end()) {
+        M[i][rb] = it->second;
+      } else {
+        uint32_t r = A.size();
+        M[i][rb] = r;
+        A.rhs.insert(A.rhs.end(), q.begin(), q.end());
+        A.rhs_off.push_back(A.rhs.size());
+        A.fp.push_back(B.fp[rb]);
+        H.emplace(q, r);
+      }
+    }
+  }
+  for (size_t j = 0; j < b->c_level.size(); ++j) {
+    uint8_t lv = b->c_level[j];
+    a->c_level.push_back(lv);
+    a->c_sym.push_back(lv == 0 ? b->c_sym[j] : M[lv][b->c_sym[j]]);
+  }
+  return 0;
+}
+
+// exp(C[j]) by recursive substitution of right-hand sides down to level 0.
+// Returns the expansion length; writes at most cap bytes.
+uint64_t oracle_expand(const OracleGrammar* g, uint32_t j, uint8_t* out, uint64_t cap) {
+  uint64_t len = 0;
+  std::vector<std::pair<int, uint32_t>> stack;
+  stack.push_back({g->c_level[j], g->c_sym[j]});
+  while (!stack.empty()) {
+    std::pair<int, uint32_t> t = stack.back();
+    stack.pop_back();
+    if (t.first == 0) {
+      if (len < cap) out[len] = (uint8_t)t.second;
+      ++len;
+      continue;
+    }
+    const Level& L = g->levels[t.first - 1];
+    for (uint64_t x = L.rhs_off[t.second + 1]; x-- > L.rhs_off[t.second];)
+      stack.push_back({t.first - 1, L.rhs[x]});
+  }
+  return len;
+}
+
+// ---- accessors -------------------------------------------------------
+uint32_t oracle_num_levels(const OracleGrammar* g) { return (uint32_t)g->levels.size(); }
+uint32_t oracle_num_strings(const OracleGrammar* g) { return (uint32_t)g->c_level.size(); }
+uint64_t oracle_seed(const OracleGrammar* g) { return g->H.seed; }
+void oracle_level_size(const OracleGrammar* g, uint32_t level, uint32_t* u, uint64_t* rhs_len) {
+  const Level& L = g->levels[level - 1];
+  *u = L.size();
+  *rhs_len = L.rhs.size();
+}
+void oracle_level_copy(const OracleGrammar* g, uint32_t level, uint64_t* rhs_off,
+                       uint32_t* rhs, uint32_t* fp) {
+  const Level& L = g->levels[level - 1];
+  std::memcpy(rhs_off, L.rhs_off.data(), L.rhs_off.size() * sizeof(uint64_t));
+  std::memcpy(rhs, L.rhs.data(), L.rhs.size() * sizeof(uint32_t));
+  std::memcpy(fp, L.fp.data(), L.fp.size() * sizeof(uint32_t));
+}
+void oracle_c_copy(const OracleGrammar* g, uint8_t* lvl, uint32_t* sym) {
+  std::memcpy(lvl, g->c_level.data(), g->c_level.size());
+  std::memcpy(sym, g->c_sym.data(), g->c_sym.size() * sizeof(uint32_t));
+}
+uint32_t oracle_num_rounds(const OracleGrammar* g) { return (uint32_t)g->stats.size(); }
+// Five counters per round: n_in, phrases, new_rules, rhs_len, active.
+void oracle_stats_copy(const OracleGrammar* g, uint64_t* out) {
+  for (size_t i = 0; i < g->stats.size(); ++i) {
+    out[5 * i + 0] = g->stats[i].n_in;
+    out[5 * i + 1] = g->stats[i].phrases;
+    out[5 * i + 2] = g->stats[i].new_rules;
+    out[5 * i + 3] = g->stats[i].rhs_len;
+    out[5 * i + 4] = g->stats[i].active;
+  }
+}
+void oracle_free(OracleGrammar* g) { delete g; }
+
+}  // extern "C"
