@@ -1,0 +1,172 @@
+/*
+ * lcg.h -- C ABI of liblcg, the MI355X (gfx950) construction of stable
+ * locally consistent grammars (LCG) from Diaz-Dominguez, "Efficient
+ * terabyte-scale text compression via stable local consistency and parallel
+ * grammar processing" (arXiv 2411.12439).
+ *
+ * Every operation runs as HIP kernels on the device; the host only sizes
+ * buffers, launches and reads back a few counters per parsing round.
+ *
+ * Conventions
+ *   - Pointers named d_* are HIP device memory (for instance the data_ptr()
+ *     of a torch tensor on the current device).  Pointers named h_* are host
+ *     memory owned by the caller.
+ *   - Work is enqueued on the given stream and ordered with the caller's
+ *     other work on it.  Calls that return counters (lcg_build*, lcg_merge,
+ *     lcg_expand, lcg_level_size, lcg_*_copy, lcg_stats) synchronise that
+ *     stream before returning.  The caller's input buffers must stay valid
+ *     until the call returns.
+ *   - Grammars (lcg_grammar_t) own their device memory, which comes from the
+ *     library's per-device caching pool; lcg_free returns it to the pool and
+ *     lcg_release_pool gives the pool back to the driver.
+ *   - Every entry point returns an lcg_status; C++ exceptions never cross the
+ *     ABI.  On error nothing is written to output handles and
+ *     lcg_last_error() describes the failure (thread-local string).
+ *   - Nonterminals are per-level ranks (App. A.1 of the paper): rule r of
+ *     level i is the r-th rule of that level, its right-hand side holds ranks
+ *     of level i-1 (byte values at level 1).  The library numbers the new
+ *     rules of a level in order of first occurrence (string order, then
+ *     position), which Sec. 3.3 allows; the CPU oracle does the same, so the
+ *     two agree rank for rank.
+ *   - Terminals are raw byte values 0..255.  Strings must be non-empty; a
+ *     string of length one is compressed at level 0 (C[j] is its byte).
+ */
+#ifndef LCG_H
+#define LCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lcg_grammar* lcg_grammar_t;
+
+typedef enum {
+  LCG_OK = 0,
+  LCG_EINVAL = -1,    /* bad argument: k = 0, empty string, offsets not increasing, bad level */
+  LCG_ENOMEM = -2,    /* device allocation failed or hbm_budget exceeded */
+  LCG_ESEED = -3,     /* merging grammars built with different hash families */
+  LCG_EOVERFLOW = -4, /* a round needs >= 2^32 phrases, or more than 63 rounds */
+  LCG_ETABLE = -5,    /* dictionary still overflowing after the allowed regrowths */
+  LCG_EHIP = -6       /* a HIP runtime call failed (message in lcg_last_error) */
+} lcg_status;
+
+enum {
+  LCG_MODE_BATCHED = 0, /* one launch sequence per round over all strings, shared dictionaries */
+  LCG_MODE_PLAIN = 1    /* one launch sequence per string per round, then MergeGrams */
+};
+
+enum {
+  LCG_FLAG_TIMING = 1u  /* record per-round device time in the round statistics */
+};
+
+typedef struct {
+  uint64_t seed;       /* selects the hash family H = {h^0..h^63}; grammars merge only if equal */
+  uint32_t mode;       /* LCG_MODE_BATCHED or LCG_MODE_PLAIN */
+  uint32_t flags;      /* LCG_FLAG_* */
+  uint64_t hbm_budget; /* bytes of device working memory a call may hold; 0 = unlimited */
+  uint32_t key_bits;   /* test hook: if 1..30, every phrase is keyed by only this many
+                          fingerprint bits, so that dictionary lookups rely on the full
+                          right-hand-side comparison; 0 = normal keys */
+  uint32_t table_min_log2; /* smallest dictionary capacity, log2 (6..34; 0 = 12) */
+  uint32_t reserved[2];     /* must be zero */
+} lcg_opts;
+
+/* Fill *o with the defaults (seed 0, batched mode, unlimited budget). */
+void lcg_opts_init(lcg_opts* o);
+
+/*
+ * BuildGram(T, H) = G (Sec. 3.3, with the fingerprint array of Sec. 3.4).
+ *   d_text     device bytes of all strings, concatenated
+ *   d_offsets  device uint64[k+1]; string j is d_text[offsets[j] .. offsets[j+1]),
+ *              offsets[0] = 0, strictly increasing (every string non-empty)
+ *   k          number of strings, >= 1
+ *   opts       NULL for defaults
+ *   out        receives a new grammar; free it with lcg_free
+ * Rounds of RandLMSPar (Eq. 3) parse every active string, phrases are
+ * fingerprinted with Eq. 4, deduplicated exactly (full right-hand-side
+ * comparison behind a 64-bit key) into the level's nonterminals, and the
+ * strings are rewritten for the next round until every string has length
+ * one.  Errors: LCG_EINVAL, LCG_ENOMEM, LCG_EOVERFLOW, LCG_ETABLE, LCG_EHIP.
+ */
+lcg_status lcg_build(const uint8_t* d_text, const uint64_t* d_offsets, uint32_t k,
+                     const lcg_opts* opts, hipStream_t stream, lcg_grammar_t* out);
+
+/*
+ * BuildGram(T, H, G_a, G_b) = G_a with G_a = G_b = g (App. A.2): compress a
+ * new batch of strings into an existing grammar.  Each phrase is first looked
+ * up in g's level dictionaries and only phrases absent from g become new
+ * rules, appended to g's levels; the batch's strings are appended to C.
+ * The result equals MergeGrams(g, BuildGram(batch)).
+ *   first_index  receives the index in C of the batch's first string (may be NULL)
+ * Same input conventions and errors as lcg_build, plus LCG_ESEED if
+ * opts->seed differs from g's seed.
+ */
+lcg_status lcg_build_into(lcg_grammar_t g, const uint8_t* d_text, const uint64_t* d_offsets,
+                          uint32_t k, const lcg_opts* opts, hipStream_t stream,
+                          uint32_t* first_index);
+
+/*
+ * MergeGrams(G_a, G_b) (Sec. 3.5-3.6), in the rank encoding of App. A.1:
+ * level by level, every rule of b (right-hand side renamed into a's ranks of
+ * the level below) is looked up in a's dictionary of that level; a hit reuses
+ * a's rank, a miss appends the rule to a.  C_a becomes C_a . C_b.  a is
+ * modified in place, b is left unchanged.  Errors: LCG_ESEED, LCG_ENOMEM,
+ * LCG_EOVERFLOW, LCG_EHIP.
+ */
+lcg_status lcg_merge(lcg_grammar_t a, lcg_grammar_t b, hipStream_t stream);
+
+/*
+ * exp(C[j]) (Sec. 2.2): expand string j top-down, level by level, into
+ * d_out (device, cap bytes).  *out_len receives the expansion length; if it
+ * exceeds cap nothing is written and LCG_EINVAL is returned.
+ */
+lcg_status lcg_expand(lcg_grammar_t g, uint32_t j, uint8_t* d_out, uint64_t cap,
+                      uint64_t* out_len, hipStream_t stream);
+
+/* An empty grammar with hash family `seed` (no levels, no strings). */
+lcg_status lcg_new(uint64_t seed, lcg_grammar_t* out);
+
+/* ---- inspection (host copies) ------------------------------------------- */
+lcg_status lcg_info(lcg_grammar_t g, uint64_t* seed, uint32_t* n_levels, uint32_t* k);
+/* u = number of rules of level (1..n_levels), rhs_len = sum of their lengths. */
+lcg_status lcg_level_size(lcg_grammar_t g, uint32_t level, uint32_t* u, uint64_t* rhs_len);
+/* h_rhs_off: uint64[u+1]; h_rhs: uint32[rhs_len] (bytes widened at level 1); h_fp: uint32[u]. */
+lcg_status lcg_level_copy(lcg_grammar_t g, uint32_t level, uint64_t* h_rhs_off, uint32_t* h_rhs,
+                          uint32_t* h_fp);
+/* h_level: uint8[k] level of C[j]; h_sym: uint32[k] rank (byte value at level 0). */
+lcg_status lcg_c_copy(lcg_grammar_t g, uint8_t* h_level, uint32_t* h_sym);
+
+/*
+ * Per-round statistics of the builds that produced g, LCG_STATS_FIELDS
+ * uint64 per round: total active length n_i, phrases d_i, new rules u_i, new
+ * right-hand-side symbols Q_i, strings still active, dictionary probes (sum
+ * over phrases), full right-hand-side comparisons, dictionary capacity,
+ * device time in nanoseconds (0 without LCG_FLAG_TIMING).  Rounds of later
+ * builds (lcg_build_into, plain-mode per-string builds) are appended.
+ */
+#define LCG_STATS_FIELDS 9
+lcg_status lcg_stats(lcg_grammar_t g, uint64_t* h_out, uint32_t cap_rounds, uint32_t* n_rounds);
+/* Reset the statistics of g. */
+lcg_status lcg_stats_clear(lcg_grammar_t g);
+
+/* Upper bound of the device working memory (bytes) one lcg_build call over n
+ * bytes in k strings may hold besides the grammar itself (worst case: every
+ * phrase of length two).  hbm_budget is checked against it. */
+uint64_t lcg_build_bytes(uint64_t n, uint32_t k);
+
+void lcg_free(lcg_grammar_t g);
+/* Return the library's cached free device blocks to the driver. */
+void lcg_release_pool(void);
+/* Thread-local description of the last failure. */
+const char* lcg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LCG_H */

@@ -1,0 +1,83 @@
+// Device-side building blocks of liblcg: Mersenne-61 arithmetic for the
+// level fingerprints (Eq. 2 and Eq. 4 of the paper), the 64-bit dictionary
+// keys, and the dictionary slot layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lcg {
+
+constexpr uint64_t kP61 = (1ULL << 61) - 1;  // p_i of every level
+constexpr uint64_t kEmpty = ~0ULL;           // free dictionary slot
+constexpr uint32_t kNone = 0xFFFFFFFFu;      // no rank / no occurrence
+constexpr uint64_t kLongTag = 1ULL << 63;    // key bit 63: long phrase (fingerprint key)
+constexpr uint64_t kHiMask = 0xFFFFFFFF00000000ULL;
+
+// One dictionary slot (16 bytes).  w0 is the claimed word:
+//   short phrase : exact key (bit 63 = 0), never equal to kEmpty;
+//   long phrase  : kLongTag | h31 << 32 | ref, where h31 is 31 bits of the
+//                  phrase fingerprint and ref is the phrase occurrence that
+//                  claimed the slot while the round runs, or the rule's rank
+//                  once committed.
+// minocc is the smallest occurrence index holding the phrase in the running
+// round (first occurrence); rank is kNone until the rule is committed.
+struct Slot {
+  uint64_t w0;
+  uint32_t minocc;
+  uint32_t rank;
+};
+static_assert(sizeof(Slot) == 16, "slot layout");
+
+// Coefficients of one level of the hash family.
+struct LevelHash {
+  uint64_t a, b, c;
+};
+
+// x * y mod 2^61-1 for x, y < 2^61: the 122-bit product is folded with
+// 2^61 = 1 (mod p).
+__device__ __forceinline__ uint64_t mulmod61(uint64_t x, uint64_t y) {
+  uint64_t lo = x * y;
+  uint64_t hi = __umul64hi(x, y);
+  uint64_t r = (lo & kP61) + ((lo >> 61) | (hi << 3));
+  r = (r & kP61) + (r >> 61);
+  return r >= kP61 ? r - kP61 : r;
+}
+
+__device__ __forceinline__ uint64_t addmod61(uint64_t x, uint64_t y) {
+  uint64_t r = x + y;
+  return r >= kP61 ? r - kP61 : r;
+}
+
+// MurmurHash3's 64-bit finaliser (Appleby), used to place keys in the table.
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdULL;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ULL;
+  k ^= k >> 33;
+  return k;
+}
+
+// The part of w0 that decides where a key lives and what a probe compares.
+__host__ __device__ __forceinline__ uint64_t probe_key(uint64_t w0) {
+  return (w0 & kLongTag) ? (w0 & kHiMask) : w0;
+}
+
+// Exact keys.  Level 1 (bytes): up to 7 bytes, q in bits 56..58.  Levels >= 2
+// (ranks): q in bits 58..60 and the ranks packed in 58 bits when they fit
+// (q = 1 any rank; q = 2 ranks < 2^29; q = 3 ranks < 2^19; q = 4 ranks < 2^14).
+// The encoding is injective per level, so equal keys mean equal phrases.
+__device__ __forceinline__ int rank_bits_for(uint32_t q) {
+  return q == 1 ? 32 : q == 2 ? 29 : q == 3 ? 19 : q == 4 ? 14 : 0;
+}
+
+// The long-phrase key: tag plus 31 bits of the 61-bit fingerprint P
+// (optionally truncated by the key_bits test hook).
+__device__ __forceinline__ uint64_t long_key(uint64_t P, uint32_t key_bits) {
+  uint64_t h = (P >> 29) & 0x7FFFFFFFULL;
+  if (key_bits) h &= (1ULL << key_bits) - 1;
+  return kLongTag | (h << 32);
+}
+
+}  // namespace lcg

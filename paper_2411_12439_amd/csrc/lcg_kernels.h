@@ -1,0 +1,89 @@
+// Host-side launchers of the liblcg HIP kernels (defined in lcg_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lcg_device.h"
+
+namespace lcg {
+
+constexpr int kBlock = 256;                 // threads per block of the position kernels
+constexpr int kItems = 16;                  // positions per thread
+constexpr int kTile = kBlock * kItems;      // positions per tile (4096)
+constexpr int kTileWords = kTile / 64;      // break-bit words per tile
+constexpr int kHllLog2 = 9;                 // HyperLogLog registers (512)
+constexpr int kHll = 1 << kHllLog2;
+
+// Device counters of one round.
+struct Counters {
+  unsigned long long won;       // slots claimed in the running insert
+  unsigned long long probes;    // slots inspected
+  unsigned long long compares;  // full right-hand-side comparisons
+  unsigned int overflow;        // a probe sequence hit the limit or the table passed its load cap
+  unsigned int active;          // strings still longer than one symbol
+  unsigned int hll[kHll];       // HyperLogLog registers of the round's phrase keys
+};
+
+// Everything one round of the position kernels needs.
+struct RoundIn {
+  const void* sym;          // uint8_t (level 1) or uint32_t symbols of T^i
+  const uint32_t* fp;       // F of each symbol (levels >= 2); NULL at level 1
+  const uint32_t* lut;      // h^0 of the 256 byte values (level 1)
+  const uint64_t* off;      // k+1 segment offsets of T^i
+  uint32_t k;
+  uint64_t n;               // length of T^i
+  bool bytes;               // symbols are bytes
+};
+
+void launch_f0_lut(uint32_t* lut, uint64_t a0, uint64_t b0, hipStream_t s);
+void launch_fill_slots(Slot* t, uint64_t cap, hipStream_t s);
+void launch_zero(void* p, size_t bytes, hipStream_t s);
+
+void launch_classify(const RoundIn& in, uint64_t* bits, uint64_t* tile_cnt, hipStream_t s);
+void launch_emit(const RoundIn& in, const uint64_t* bits, const uint64_t* tile_base, LevelHash h,
+                 uint32_t key_bits, uint64_t* pstart, uint32_t* plen, uint64_t* key, uint32_t* fnew,
+                 Counters* ctr, hipStream_t s);
+
+// Exclusive scan of n uint64 values into out[0..n]; out[n] receives the total.
+// tmp must hold scan_tmp_words(n) uint64.
+size_t scan_tmp_words(uint64_t n);
+void scan_exclusive(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s);
+
+void launch_insert(bool bytes, uint64_t d, const uint64_t* key, const uint64_t* pstart,
+                   const uint32_t* plen, const void* content, const uint64_t* rule_off,
+                   const void* rule_rhs, uint32_t u_committed, Slot* table, uint64_t mask,
+                   uint32_t* slot_idx, Counters* ctr, hipStream_t s);
+void launch_newflags(uint64_t d, const uint32_t* slot_idx, const Slot* table, const uint32_t* plen,
+                     uint64_t* newbits, uint64_t* wcnt, uint64_t* wlen, hipStream_t s);
+void launch_commit(bool bytes, uint64_t d, const uint32_t* slot_idx, Slot* table,
+                   const uint64_t* newbits, const uint64_t* wcnt_base, const uint64_t* wlen_base,
+                   const uint64_t* pstart, const uint32_t* plen, const void* content,
+                   const uint32_t* fnew, uint32_t u_prev, uint64_t q_prev, uint64_t* rule_off,
+                   void* rule_rhs, uint32_t* rule_fp, uint32_t* sym_next, hipStream_t s);
+void launch_rehash(const Slot* old_t, uint64_t old_cap, Slot* new_t, uint64_t new_mask,
+                   Counters* ctr, hipStream_t s);
+
+void launch_c_init(const uint8_t* text, const uint64_t* off, uint32_t k, uint8_t* c_level,
+                   uint32_t* c_sym, hipStream_t s);
+void launch_segments(const uint64_t* off, uint32_t k, const uint64_t* pstart, uint64_t d,
+                     uint64_t* new_off, hipStream_t s);
+void launch_finish(const uint64_t* off, const uint64_t* new_off, uint32_t k,
+                   const uint32_t* sym_next, uint32_t level, uint8_t* c_level, uint32_t* c_sym,
+                   Counters* ctr, hipStream_t s);
+
+// Merge: prepare G_b's level-i rules as phrases over G_a's level-(i-1) ranks.
+void launch_merge_prepare(bool bytes, uint32_t u_b, const uint64_t* b_off, const void* b_rhs,
+                          const uint32_t* remap_prev, const uint32_t* f_prev, LevelHash h,
+                          uint32_t key_bits, void* content, uint64_t* pstart, uint32_t* plen,
+                          uint64_t* key, hipStream_t s);
+void launch_c_merge(const uint8_t* b_level, const uint32_t* b_sym, uint32_t kb, uint32_t level,
+                    const uint32_t* remap, uint8_t* out_level, uint32_t* out_sym, hipStream_t s);
+
+// Expansion (top-down, one level per call).
+void launch_expand_lens(const uint32_t* cur, uint64_t m, const uint64_t* rule_off, uint64_t* lens,
+                        hipStream_t s);
+void launch_expand_emit(bool bytes, const uint32_t* cur, uint64_t m, const uint64_t* rule_off,
+                        const void* rule_rhs, const uint64_t* pos, void* next, hipStream_t s);
+
+}  // namespace lcg

@@ -1,0 +1,816 @@
+// HIP kernels of liblcg for gfx950 (wave64).
+//
+// One parsing round of BuildGram (Sec. 3.3 of the paper) over the flat buffer
+// of all active strings T^i runs as:
+//   classify  Eq. 3 on fingerprints -> one break bit per position, count per tile
+//   scan      exclusive prefix of the tile counts -> phrase index of each break
+//   emit      per phrase: extent, Eq. 4 fingerprint (61-bit), dictionary key,
+//             HyperLogLog sketch of the keys (sizes the dictionary)
+//   insert    open-addressing dictionary, exact: short phrases carry their
+//             content in the key, long phrases are compared in full
+//   newflags  a phrase is new if it is the first occurrence of an uncommitted slot
+//   scan      ranks (first-occurrence order) and right-hand-side offsets
+//   commit    rewrite T^{i+1} with ranks, append the new rules and their F
+//   segments  next-round offsets per string; strings reduced to one symbol
+//             store it in C and become inactive (Sec. 3.3)
+// MergeGrams (Sec. 3.6) reuses insert/newflags/scan/commit with G_b's rules
+// as the phrases.
+#include <stdexcept>
+#include <string>
+
+#include "lcg_kernels.h"
+
+namespace lcg {
+
+#define LCG_LAUNCH_CHECK(name)                                                        \
+  do {                                                                                \
+    hipError_t e_ = hipGetLastError();                                                \
+    if (e_ != hipSuccess)                                                             \
+      throw std::runtime_error(std::string("launch of " name ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr uint32_t kMaxProbe = 1u << 14;
+
+static inline unsigned grid_for(uint64_t n, int block) {
+  uint64_t g = (n + block - 1) / block;
+  if (g == 0) g = 1;
+  if (g > 0x7FFFFFFFULL) throw std::runtime_error("grid too large");
+  return (unsigned)g;
+}
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// largest j in [lo, hi] with off[j] <= x (requires off[lo] <= x)
+__device__ __forceinline__ uint32_t seg_search(const uint64_t* off, uint32_t lo, uint32_t hi,
+                                               uint64_t x) {
+  while (lo < hi) {
+    uint32_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Exclusive block scan of one value per thread (kBlock threads).
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T* s_wave, T* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  T x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    T y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) s_wave[wid] = x;
+  __syncthreads();
+  T base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) {
+    T sw = s_wave[w];
+    if (w < wid) base += sw;
+    tot += sw;
+  }
+  __syncthreads();
+  if (total) *total = tot;
+  return base + x - v;
+}
+
+template <bool BYTES>
+__device__ __forceinline__ uint32_t fval(const RoundIn& in, const uint32_t* s_lut, uint64_t i) {
+  if constexpr (BYTES) return s_lut[static_cast<const uint8_t*>(in.sym)[i]];
+  else return in.fp[i];
+}
+
+// first break position in [pos, lim), or lim
+__device__ __forceinline__ uint64_t next_break(const uint64_t* bits, uint64_t pos, uint64_t lim) {
+  while (pos < lim) {
+    uint64_t w = bits[pos >> 6] >> (pos & 63);
+    if (w) {
+      uint64_t r = pos + __builtin_ctzll(w);
+      return r < lim ? r : lim;
+    }
+    pos = (pos | 63) + 1;
+  }
+  return lim;
+}
+
+// Dictionary key of a phrase sym[p .. p+q) with fingerprint P (see lcg_device.h).
+template <bool BYTES>
+__device__ __forceinline__ uint64_t make_key(const void* sym, uint64_t p, uint64_t q, uint64_t P,
+                                             uint32_t key_bits) {
+  if (key_bits == 0) {
+    if constexpr (BYTES) {
+      if (q <= 7) {
+        const uint8_t* s = static_cast<const uint8_t*>(sym) + p;
+        uint64_t k = q << 56;
+        for (uint32_t x = 0; x < q; ++x) k |= (uint64_t)s[x] << (8 * x);
+        return k;
+      }
+    } else {
+      if (q <= 4) {
+        const uint32_t* s = static_cast<const uint32_t*>(sym) + p;
+        const int rb = rank_bits_for((uint32_t)q);
+        uint64_t k = 0;
+        bool fits = true;
+        for (uint32_t x = 0; x < q; ++x) {
+          uint64_t r = s[x];
+          if (rb < 32 && (r >> rb)) fits = false;
+          k = (k << rb) | r;
+        }
+        if (fits) return (q << 58) | k;
+      }
+    }
+  }
+  return long_key(P, key_bits);
+}
+
+// ------------------------------------------------------------------ small kernels
+__global__ void k_f0_lut(uint32_t* lut, uint64_t a0, uint64_t b0) {
+  const uint64_t s = threadIdx.x;
+  lut[s] = (uint32_t)(addmod61(mulmod61(a0, s), b0) & 0xFFFFFFFFULL);
+}
+
+void launch_f0_lut(uint32_t* lut, uint64_t a0, uint64_t b0, hipStream_t s) {
+  k_f0_lut<<<1, 256, 0, s>>>(lut, a0, b0);
+  LCG_LAUNCH_CHECK("f0_lut");
+}
+
+__global__ void k_fill_slots(Slot* t, uint64_t cap) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    t[i] = Slot{kEmpty, kNone, kNone};
+}
+
+void launch_fill_slots(Slot* t, uint64_t cap, hipStream_t s) {
+  unsigned g = grid_for(cap, 256);
+  if (g > 8192) g = 8192;
+  k_fill_slots<<<g, 256, 0, s>>>(t, cap);
+  LCG_LAUNCH_CHECK("fill_slots");
+}
+
+__global__ void k_zero(uint32_t* p, uint64_t words) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < words;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes % 4) throw std::runtime_error("launch_zero: size not a multiple of 4");
+  uint64_t w = bytes / 4;
+  if (!w) return;
+  unsigned g = grid_for(w, 256);
+  if (g > 4096) g = 4096;
+  k_zero<<<g, 256, 0, s>>>(static_cast<uint32_t*>(p), w);
+  LCG_LAUNCH_CHECK("zero");
+}
+
+// ------------------------------------------------------------------ classify
+// Position l of segment [s, e) starts a phrase iff l == s (and e - s >= 2),
+// or l is LMS-type (Eq. 3): F[l-1] > F[l] and the first position r > l with
+// F[r] != F[l] lies inside the segment and has F[r] > F[l].  Positions of the
+// trailing equal run never qualify: there r does not exist.
+template <bool BYTES>
+__global__ __launch_bounds__(kBlock) void k_classify(RoundIn in, uint64_t* __restrict__ bits,
+                                                     uint64_t* __restrict__ tile_cnt) {
+  __shared__ uint32_t s_lut[256];
+  __shared__ uint32_t s_seg[2];
+  __shared__ uint32_t s_mask[kBlock];
+  __shared__ uint32_t s_cnt;
+  const uint64_t t0 = (uint64_t)blockIdx.x * kTile;
+  if constexpr (BYTES) s_lut[threadIdx.x] = in.lut[threadIdx.x];
+  if (threadIdx.x == 0) {
+    uint64_t tl = (t0 + kTile < in.n ? t0 + kTile : in.n) - 1;
+    uint32_t lo = seg_search(in.off, 0, in.k - 1, t0);
+    s_seg[0] = lo;
+    s_seg[1] = seg_search(in.off, lo, in.k - 1, tl);
+    s_cnt = 0;
+  }
+  __syncthreads();
+  const uint64_t b = t0 + (uint64_t)threadIdx.x * kItems;
+  uint32_t mask = 0;
+  if (b < in.n) {
+    uint32_t fw[kItems + 2];
+#pragma unroll
+    for (int x = 0; x < kItems + 2; ++x) {
+      uint64_t p = b - 1 + x;  // b - 1 wraps for b = 0 and is then out of range
+      fw[x] = p < in.n ? fval<BYTES>(in, s_lut, p) : 0u;
+    }
+    uint32_t desc = 0, eq = 0, gt = 0;
+#pragma unroll
+    for (int x = 0; x < kItems; ++x) {
+      desc |= (uint32_t)(fw[x] > fw[x + 1]) << x;       // F[l-1] > F[l]
+      eq |= (uint32_t)(fw[x + 1] == fw[x + 2]) << x;    // F[l] == F[l+1]
+      gt |= (uint32_t)(fw[x + 2] > fw[x + 1]) << x;     // F[l+1] > F[l]
+    }
+    uint32_t j = seg_search(in.off, s_seg[0], s_seg[1], b);
+    uint64_t s_start = in.off[j], s_end = in.off[j + 1];
+    for (int x = 0; x < kItems; ++x) {
+      const uint64_t l = b + x;
+      if (l >= in.n) break;
+      while (l >= s_end) {
+        ++j;
+        s_start = in.off[j];
+        s_end = in.off[j + 1];
+      }
+      bool brk = false;
+      if (l == s_start) {
+        brk = s_end - s_start >= 2;
+      } else if ((desc >> x) & 1u) {
+        uint32_t ne = (~eq >> x) & ((1u << (kItems - x)) - 1u);
+        if (ne) {
+          uint32_t y = __builtin_ctz(ne);
+          uint64_t r = l + y + 1;
+          brk = r < s_end && ((gt >> (x + y)) & 1u);
+        } else {
+          // the run continues past the window: walk it in memory
+          const uint32_t fl = fval<BYTES>(in, s_lut, l);
+          uint64_t r = b + kItems + 1;
+          while (r < s_end && fval<BYTES>(in, s_lut, r) == fl) ++r;
+          brk = r < s_end && fval<BYTES>(in, s_lut, r) > fl;
+        }
+      }
+      mask |= (uint32_t)brk << x;
+    }
+  }
+  s_mask[threadIdx.x] = mask;
+  atomicAdd(&s_cnt, (uint32_t)__builtin_popcount(mask));
+  __syncthreads();
+  if (threadIdx.x < kTileWords) {
+    const int t = threadIdx.x * 4;
+    uint64_t w = (uint64_t)s_mask[t] | ((uint64_t)s_mask[t + 1] << 16) |
+                 ((uint64_t)s_mask[t + 2] << 32) | ((uint64_t)s_mask[t + 3] << 48);
+    bits[(uint64_t)blockIdx.x * kTileWords + threadIdx.x] = w;
+  }
+  if (threadIdx.x == 0) tile_cnt[blockIdx.x] = s_cnt;
+}
+
+void launch_classify(const RoundIn& in, uint64_t* bits, uint64_t* tile_cnt, hipStream_t s) {
+  static_assert(kItems == 16 && kBlock == 256, "bit packing assumes 16 positions per thread");
+  unsigned tiles = grid_for(in.n, kTile);
+  if (in.bytes) k_classify<true><<<tiles, kBlock, 0, s>>>(in, bits, tile_cnt);
+  else k_classify<false><<<tiles, kBlock, 0, s>>>(in, bits, tile_cnt);
+  LCG_LAUNCH_CHECK("classify");
+}
+
+// ------------------------------------------------------------------ emit
+template <bool BYTES>
+__global__ __launch_bounds__(kBlock) void k_emit(RoundIn in, const uint64_t* __restrict__ bits,
+                                                 const uint64_t* __restrict__ tile_base, uint64_t tiles,
+                                                 LevelHash h, uint32_t key_bits,
+                                                 uint64_t* __restrict__ pstart, uint32_t* __restrict__ plen,
+                                                 uint64_t* __restrict__ key, uint32_t* __restrict__ fnew,
+                                                 Counters* __restrict__ ctr) {
+  __shared__ uint32_t s_lut[256];
+  __shared__ uint32_t s_seg[2];
+  __shared__ uint32_t s_wave[kBlock / 64];
+  __shared__ uint32_t s_hll[kHll];
+  if constexpr (BYTES) s_lut[threadIdx.x] = in.lut[threadIdx.x];
+  for (int i = threadIdx.x; i < kHll; i += kBlock) s_hll[i] = 0;
+  for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const uint64_t t0 = tile * kTile;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t tl = (t0 + kTile < in.n ? t0 + kTile : in.n) - 1;
+      uint32_t lo = seg_search(in.off, 0, in.k - 1, t0);
+      s_seg[0] = lo;
+      s_seg[1] = seg_search(in.off, lo, in.k - 1, tl);
+    }
+    const uint64_t b = t0 + (uint64_t)threadIdx.x * kItems;
+    uint32_t mask = (uint32_t)(bits[tile * kTileWords + threadIdx.x / 4] >> ((threadIdx.x & 3) * 16)) &
+                    0xFFFFu;
+    uint32_t excl = block_excl_scan<uint32_t>((uint32_t)__builtin_popcount(mask), s_wave, nullptr);
+    if (mask == 0) continue;
+    uint64_t o = tile_base[tile] + excl;
+    uint32_t j = seg_search(in.off, s_seg[0], s_seg[1], b);
+    uint64_t s_end = in.off[j + 1];
+    while (mask) {
+      const int x = __builtin_ctz(mask);
+      mask &= mask - 1;
+      const uint64_t l = b + x;
+      while (l >= s_end) s_end = in.off[++j + 1];
+      const uint64_t e = next_break(bits, l + 1, s_end);
+      // Eq. 4 by Horner's rule from the right: sum_j F[Q_j] c^(j-1)
+      uint64_t S = 0;
+      for (uint64_t p = e; p-- > l;) S = addmod61(mulmod61(S, h.c), fval<BYTES>(in, s_lut, p));
+      const uint64_t P = addmod61(mulmod61(h.a, S), h.b);
+      const uint64_t kk = make_key<BYTES>(in.sym, l, e - l, P, key_bits);
+      pstart[o] = l;
+      plen[o] = (uint32_t)(e - l);
+      key[o] = kk;
+      fnew[o] = (uint32_t)(P & 0xFFFFFFFFULL);
+      const uint64_t hh = mix64(probe_key(kk));
+      const uint32_t idx = (uint32_t)(hh >> (64 - kHllLog2));
+      const uint64_t rest = hh << kHllLog2;
+      const uint32_t rho = rest ? (uint32_t)__builtin_clzll(rest) + 1 : 64 - kHllLog2 + 1;
+      atomicMax(&s_hll[idx], rho);
+      ++o;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kHll; i += kBlock) {
+    uint32_t v = s_hll[i];
+    if (v && ctr->hll[i] < v) atomicMax(&ctr->hll[i], v);
+  }
+}
+
+void launch_emit(const RoundIn& in, const uint64_t* bits, const uint64_t* tile_base, LevelHash h,
+                 uint32_t key_bits, uint64_t* pstart, uint32_t* plen, uint64_t* key, uint32_t* fnew,
+                 Counters* ctr, hipStream_t s) {
+  uint64_t tiles = grid_for(in.n, kTile);
+  unsigned g = tiles > 2048 ? 2048 : (unsigned)tiles;
+  if (in.bytes)
+    k_emit<true><<<g, kBlock, 0, s>>>(in, bits, tile_base, tiles, h, key_bits, pstart, plen, key,
+                                      fnew, ctr);
+  else
+    k_emit<false><<<g, kBlock, 0, s>>>(in, bits, tile_base, tiles, h, key_bits, pstart, plen, key,
+                                       fnew, ctr);
+  LCG_LAUNCH_CHECK("emit");
+}
+
+// ------------------------------------------------------------------ scan
+constexpr int kScanItems = 4;
+constexpr int kScanPer = kBlock * kScanItems;
+
+__global__ __launch_bounds__(kBlock) void k_scan_block(const uint64_t* __restrict__ in,
+                                                       uint64_t* __restrict__ out, uint64_t n,
+                                                       uint64_t* __restrict__ block_sums) {
+  __shared__ uint64_t s_wave[kBlock / 64];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanPer + (uint64_t)threadIdx.x * kScanItems;
+  uint64_t v[kScanItems];
+  uint64_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = base + i < n ? in[base + i] : 0;
+    sum += v[i];
+  }
+  uint64_t tot;
+  uint64_t run = block_excl_scan<uint64_t>(sum, s_wave, &tot);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) out[base + i] = run;
+    run += v[i];
+  }
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_add(uint64_t* __restrict__ out, uint64_t n, const uint64_t* __restrict__ offs) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] += offs[i / kScanPer];
+}
+
+__global__ void k_copy_word(uint64_t* dst, const uint64_t* src) { *dst = *src; }
+
+size_t scan_tmp_words(uint64_t n) {
+  if (n <= (uint64_t)kScanPer) return 0;
+  uint64_t nb = (n + kScanPer - 1) / kScanPer;
+  return nb + (nb + 1) + scan_tmp_words(nb);
+}
+
+void scan_exclusive(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s) {
+  if (n <= (uint64_t)kScanPer) {
+    k_scan_block<<<1, kBlock, 0, s>>>(in, out, n, out + n);
+    LCG_LAUNCH_CHECK("scan_block");
+    return;
+  }
+  uint64_t nb = (n + kScanPer - 1) / kScanPer;
+  uint64_t* sums = tmp;
+  uint64_t* offs = tmp + nb;
+  k_scan_block<<<grid_for(nb * kScanPer, kScanPer), kBlock, 0, s>>>(in, out, n, sums);
+  LCG_LAUNCH_CHECK("scan_block");
+  scan_exclusive(sums, offs, nb, tmp + nb + nb + 1, s);
+  k_scan_add<<<grid_for(n, 256), 256, 0, s>>>(out, n, offs);
+  LCG_LAUNCH_CHECK("scan_add");
+  k_copy_word<<<1, 1, 0, s>>>(out + n, offs + nb);
+  LCG_LAUNCH_CHECK("copy_word");
+}
+
+// ------------------------------------------------------------------ insert
+template <typename Sym>
+__device__ __forceinline__ bool same_seq(const Sym* a, const Sym* b, uint32_t len) {
+  for (uint32_t i = 0; i < len; ++i)
+    if (a[i] != b[i]) return false;
+  return true;
+}
+
+// Insert-or-find every phrase.  A claimed slot keeps the claimer's key; a
+// long phrase whose 31 key bits match is compared symbol by symbol against
+// the slot's phrase (the claiming occurrence, or the committed rule).
+template <typename Sym>
+__global__ __launch_bounds__(256) void k_insert(uint64_t d, const uint64_t* __restrict__ key,
+                                                const uint64_t* __restrict__ pstart,
+                                                const uint32_t* __restrict__ plen,
+                                                const Sym* __restrict__ content,
+                                                const uint64_t* __restrict__ rule_off,
+                                                const Sym* __restrict__ rule_rhs, uint32_t u_committed,
+                                                Slot* table, uint64_t mask,
+                                                uint32_t* __restrict__ slot_idx,
+                                                Counters* __restrict__ ctr) {
+  const uint64_t o = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  unsigned long long won = 0, probes = 0, cmps = 0;
+  if (o < d) {
+    const uint64_t kk = key[o];
+    const bool is_long = (kk & kLongTag) != 0;
+    const uint64_t want = is_long ? (kk | o) : kk;
+    uint64_t my_pos = 0;
+    uint32_t my_len = 0;
+    if (is_long) {
+      my_pos = pstart[o];
+      my_len = plen[o];
+    }
+    uint64_t pos = mix64(kk) & mask;
+    uint32_t result = kNone;
+    for (uint32_t probe = 0; probe < kMaxProbe; ++probe) {
+      Slot* sl = &table[pos];
+      ++probes;
+      uint64_t w = __hip_atomic_load(&sl->w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (w == kEmpty) {
+        unsigned long long prev =
+            atomicCAS(reinterpret_cast<unsigned long long*>(&sl->w0), (unsigned long long)kEmpty,
+                      (unsigned long long)want);
+        if (prev == kEmpty) {
+          result = (uint32_t)pos;
+          won = 1;
+          break;
+        }
+        w = prev;
+      }
+      if (!is_long) {
+        if (w == kk) {
+          result = (uint32_t)pos;
+          break;
+        }
+      } else if ((w & kHiMask) == kk) {
+        const uint32_t rk = __hip_atomic_load(&sl->rank, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t ref = (uint32_t)w;
+        // a committed rule is compared with its stored right-hand side, a slot
+        // claimed in this pass with the claiming occurrence; anything else (a
+        // slot left by an interrupted call) cannot match
+        const bool committed = rk != kNone && rk < u_committed;
+        const bool inflight = rk == kNone && ref < d;
+        uint64_t opos = 0;
+        uint32_t olen = 0xFFFFFFFFu;
+        const Sym* arr = content;
+        if (committed) {
+          opos = rule_off[rk];
+          olen = (uint32_t)(rule_off[rk + 1] - opos);
+          arr = rule_rhs;
+        } else if (inflight) {
+          opos = pstart[ref];
+          olen = plen[ref];
+        }
+        ++cmps;
+        if (olen == my_len && same_seq<Sym>(content + my_pos, arr + opos, my_len)) {
+          result = (uint32_t)pos;
+          break;
+        }
+      }
+      pos = (pos + 1) & mask;
+    }
+    if (result == kNone) {
+      atomicOr(&ctr->overflow, 1u);
+    } else {
+      Slot* sl = &table[result];
+      if (__hip_atomic_load(&sl->rank, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == kNone &&
+          __hip_atomic_load(&sl->minocc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > (uint32_t)o)
+        atomicMin(&sl->minocc, (uint32_t)o);
+    }
+    slot_idx[o] = result;
+  }
+  won = wave_sum(won);
+  probes = wave_sum(probes);
+  cmps = wave_sum(cmps);
+  if ((threadIdx.x & 63) == 0) {
+    if (won) atomicAdd(&ctr->won, won);
+    if (probes) atomicAdd(&ctr->probes, probes);
+    if (cmps) atomicAdd(&ctr->compares, cmps);
+  }
+}
+
+void launch_insert(bool bytes, uint64_t d, const uint64_t* key, const uint64_t* pstart,
+                   const uint32_t* plen, const void* content, const uint64_t* rule_off,
+                   const void* rule_rhs, uint32_t u_committed, Slot* table, uint64_t mask,
+                   uint32_t* slot_idx, Counters* ctr, hipStream_t s) {
+  if (!d) return;
+  if (bytes)
+    k_insert<uint8_t><<<grid_for(d, 256), 256, 0, s>>>(
+        d, key, pstart, plen, static_cast<const uint8_t*>(content), rule_off,
+        static_cast<const uint8_t*>(rule_rhs), u_committed, table, mask, slot_idx, ctr);
+  else
+    k_insert<uint32_t><<<grid_for(d, 256), 256, 0, s>>>(
+        d, key, pstart, plen, static_cast<const uint32_t*>(content), rule_off,
+        static_cast<const uint32_t*>(rule_rhs), u_committed, table, mask, slot_idx, ctr);
+  LCG_LAUNCH_CHECK("insert");
+}
+
+// ------------------------------------------------------------------ newflags
+__global__ __launch_bounds__(256) void k_newflags(uint64_t d, const uint32_t* __restrict__ slot_idx,
+                                                  const Slot* __restrict__ table,
+                                                  const uint32_t* __restrict__ plen,
+                                                  uint64_t* __restrict__ newbits,
+                                                  uint64_t* __restrict__ wcnt,
+                                                  uint64_t* __restrict__ wlen) {
+  const uint64_t o = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  bool f = false;
+  unsigned long long len = 0;
+  if (o < d) {
+    const uint32_t sidx = slot_idx[o];
+    if (sidx != kNone) {
+      const Slot sl = table[sidx];
+      f = sl.rank == kNone && sl.minocc == (uint32_t)o;
+    }
+    if (f) len = plen[o];
+  }
+  const uint64_t bal = __ballot(f);
+  len = wave_sum(len);
+  const uint64_t w = o >> 6;
+  if ((threadIdx.x & 63) == 0 && (w << 6) < d) {
+    newbits[w] = bal;
+    wcnt[w] = __builtin_popcountll(bal);
+    wlen[w] = len;
+  }
+}
+
+void launch_newflags(uint64_t d, const uint32_t* slot_idx, const Slot* table, const uint32_t* plen,
+                     uint64_t* newbits, uint64_t* wcnt, uint64_t* wlen, hipStream_t s) {
+  if (!d) return;
+  k_newflags<<<grid_for(d, 256), 256, 0, s>>>(d, slot_idx, table, plen, newbits, wcnt, wlen);
+  LCG_LAUNCH_CHECK("newflags");
+}
+
+// ------------------------------------------------------------------ commit
+__device__ __forceinline__ uint64_t rank1(const uint64_t* newbits, const uint64_t* wcnt_base,
+                                          uint64_t m) {
+  const uint64_t w = newbits[m >> 6] & ((1ULL << (m & 63)) - 1ULL);
+  return wcnt_base[m >> 6] + __builtin_popcountll(w);
+}
+
+template <typename Sym>
+__global__ __launch_bounds__(256) void k_commit(uint64_t d, const uint32_t* __restrict__ slot_idx,
+                                                Slot* table, const uint64_t* __restrict__ newbits,
+                                                const uint64_t* __restrict__ wcnt_base,
+                                                const uint64_t* __restrict__ wlen_base,
+                                                const uint64_t* __restrict__ pstart,
+                                                const uint32_t* __restrict__ plen,
+                                                const Sym* __restrict__ content,
+                                                const uint32_t* __restrict__ fnew, uint32_t u_prev,
+                                                uint64_t q_prev, uint64_t* __restrict__ rule_off,
+                                                Sym* __restrict__ rule_rhs,
+                                                uint32_t* __restrict__ rule_fp,
+                                                uint32_t* __restrict__ sym_next) {
+  const uint64_t o = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (o >= d) return;
+  const uint32_t sidx = slot_idx[o];
+  if (sidx == kNone) {  // only after an overflow; the round is then redone
+    sym_next[o] = 0;
+    return;
+  }
+  Slot* sl = &table[sidx];
+  uint32_t r = __hip_atomic_load(&sl->rank, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (r == kNone) r = u_prev + (uint32_t)rank1(newbits, wcnt_base, sl->minocc);
+  sym_next[o] = r;
+  const uint64_t w = newbits[o >> 6];
+  if ((w >> (o & 63)) & 1ULL) {
+    uint64_t below = w & ((1ULL << (o & 63)) - 1ULL);
+    uint64_t q = q_prev + wlen_base[o >> 6];
+    const uint64_t wbase = o & ~63ULL;
+    while (below) {
+      q += plen[wbase + __builtin_ctzll(below)];
+      below &= below - 1;
+    }
+    const uint32_t L = plen[o];
+    const Sym* src = content + pstart[o];
+    for (uint32_t i = 0; i < L; ++i) rule_rhs[q + i] = src[i];
+    rule_off[r + 1] = q + L;
+    rule_fp[r] = fnew[o];
+    __hip_atomic_store(&sl->rank, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t w0 = sl->w0;
+    if (w0 & kLongTag) sl->w0 = (w0 & kHiMask) | r;
+  }
+}
+
+void launch_commit(bool bytes, uint64_t d, const uint32_t* slot_idx, Slot* table,
+                   const uint64_t* newbits, const uint64_t* wcnt_base, const uint64_t* wlen_base,
+                   const uint64_t* pstart, const uint32_t* plen, const void* content,
+                   const uint32_t* fnew, uint32_t u_prev, uint64_t q_prev, uint64_t* rule_off,
+                   void* rule_rhs, uint32_t* rule_fp, uint32_t* sym_next, hipStream_t s) {
+  if (!d) return;
+  if (bytes)
+    k_commit<uint8_t><<<grid_for(d, 256), 256, 0, s>>>(
+        d, slot_idx, table, newbits, wcnt_base, wlen_base, pstart, plen,
+        static_cast<const uint8_t*>(content), fnew, u_prev, q_prev, rule_off,
+        static_cast<uint8_t*>(rule_rhs), rule_fp, sym_next);
+  else
+    k_commit<uint32_t><<<grid_for(d, 256), 256, 0, s>>>(
+        d, slot_idx, table, newbits, wcnt_base, wlen_base, pstart, plen,
+        static_cast<const uint32_t*>(content), fnew, u_prev, q_prev, rule_off,
+        static_cast<uint32_t*>(rule_rhs), rule_fp, sym_next);
+  LCG_LAUNCH_CHECK("commit");
+}
+
+// ------------------------------------------------------------------ rehash
+__global__ void k_rehash(const Slot* __restrict__ old_t, uint64_t old_cap, Slot* new_t,
+                         uint64_t mask, Counters* ctr) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < old_cap;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const Slot sl = old_t[i];
+    if (sl.w0 == kEmpty || sl.rank == kNone) continue;
+    uint64_t pos = mix64(probe_key(sl.w0)) & mask;
+    bool done = false;
+    for (uint64_t t = 0; t <= mask; ++t) {
+      unsigned long long prev = atomicCAS(reinterpret_cast<unsigned long long*>(&new_t[pos].w0),
+                                          (unsigned long long)kEmpty, (unsigned long long)sl.w0);
+      if (prev == kEmpty) {
+        new_t[pos].rank = sl.rank;
+        done = true;
+        break;
+      }
+      pos = (pos + 1) & mask;
+    }
+    if (!done) atomicOr(&ctr->overflow, 1u);
+  }
+}
+
+void launch_rehash(const Slot* old_t, uint64_t old_cap, Slot* new_t, uint64_t new_mask,
+                   Counters* ctr, hipStream_t s) {
+  if (!old_cap) return;
+  unsigned g = grid_for(old_cap, 256);
+  if (g > 8192) g = 8192;
+  k_rehash<<<g, 256, 0, s>>>(old_t, old_cap, new_t, new_mask, ctr);
+  LCG_LAUNCH_CHECK("rehash");
+}
+
+// ------------------------------------------------------------------ strings
+__global__ void k_c_init(const uint8_t* __restrict__ text, const uint64_t* __restrict__ off,
+                         uint32_t k, uint8_t* __restrict__ c_level, uint32_t* __restrict__ c_sym) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  if (off[j + 1] - off[j] == 1) {
+    c_level[j] = 0;
+    c_sym[j] = text[off[j]];
+  } else {
+    c_level[j] = 0xFF;
+    c_sym[j] = kNone;
+  }
+}
+
+void launch_c_init(const uint8_t* text, const uint64_t* off, uint32_t k, uint8_t* c_level,
+                   uint32_t* c_sym, hipStream_t s) {
+  k_c_init<<<grid_for(k, 256), 256, 0, s>>>(text, off, k, c_level, c_sym);
+  LCG_LAUNCH_CHECK("c_init");
+}
+
+__global__ void k_segments(const uint64_t* __restrict__ off, uint32_t k,
+                           const uint64_t* __restrict__ pstart, uint64_t d,
+                           uint64_t* __restrict__ new_off) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > k) return;
+  if (j == k) {
+    new_off[k] = d;
+    return;
+  }
+  const uint64_t x = off[j];
+  uint64_t lo = 0, hi = d;
+  while (lo < hi) {
+    uint64_t mid = (lo + hi) >> 1;
+    if (pstart[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  new_off[j] = lo;
+}
+
+void launch_segments(const uint64_t* off, uint32_t k, const uint64_t* pstart, uint64_t d,
+                     uint64_t* new_off, hipStream_t s) {
+  k_segments<<<grid_for((uint64_t)k + 1, 256), 256, 0, s>>>(off, k, pstart, d, new_off);
+  LCG_LAUNCH_CHECK("segments");
+}
+
+__global__ void k_finish(const uint64_t* __restrict__ off, const uint64_t* __restrict__ new_off,
+                         uint32_t k, const uint32_t* __restrict__ sym_next, uint32_t level,
+                         uint8_t* __restrict__ c_level, uint32_t* __restrict__ c_sym,
+                         Counters* __restrict__ ctr) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long act = 0;
+  if (j < k) {
+    const uint64_t lo = off[j + 1] - off[j];
+    const uint64_t ln = new_off[j + 1] - new_off[j];
+    if (lo >= 2 && ln == 1) {
+      c_level[j] = (uint8_t)level;
+      c_sym[j] = sym_next[new_off[j]];
+    }
+    act = ln >= 2;
+  }
+  act = wave_sum(act);
+  if ((threadIdx.x & 63) == 0 && act) atomicAdd(&ctr->active, (unsigned int)act);
+}
+
+void launch_finish(const uint64_t* off, const uint64_t* new_off, uint32_t k,
+                   const uint32_t* sym_next, uint32_t level, uint8_t* c_level, uint32_t* c_sym,
+                   Counters* ctr, hipStream_t s) {
+  k_finish<<<grid_for(k, 256), 256, 0, s>>>(off, new_off, k, sym_next, level, c_level, c_sym, ctr);
+  LCG_LAUNCH_CHECK("finish");
+}
+
+// ------------------------------------------------------------------ merge
+template <typename Sym>
+__global__ void k_merge_prepare(uint32_t u_b, const uint64_t* __restrict__ b_off,
+                                const Sym* __restrict__ b_rhs, const uint32_t* __restrict__ remap_prev,
+                                const uint32_t* __restrict__ f_prev, LevelHash h, uint32_t key_bits,
+                                Sym* __restrict__ content, uint64_t* __restrict__ pstart,
+                                uint32_t* __restrict__ plen, uint64_t* __restrict__ key) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= u_b) return;
+  const uint64_t p0 = b_off[r], p1 = b_off[r + 1];
+  for (uint64_t x = p0; x < p1; ++x) {
+    Sym v = b_rhs[x];
+    if (remap_prev) v = (Sym)remap_prev[v];
+    content[x] = v;
+  }
+  uint64_t S = 0;
+  for (uint64_t x = p1; x-- > p0;) S = addmod61(mulmod61(S, h.c), f_prev[content[x]]);
+  const uint64_t P = addmod61(mulmod61(h.a, S), h.b);
+  pstart[r] = p0;
+  plen[r] = (uint32_t)(p1 - p0);
+  key[r] = make_key<sizeof(Sym) == 1>(content, p0, p1 - p0, P, key_bits);
+}
+
+void launch_merge_prepare(bool bytes, uint32_t u_b, const uint64_t* b_off, const void* b_rhs,
+                          const uint32_t* remap_prev, const uint32_t* f_prev, LevelHash h,
+                          uint32_t key_bits, void* content, uint64_t* pstart, uint32_t* plen,
+                          uint64_t* key, hipStream_t s) {
+  if (!u_b) return;
+  if (bytes)
+    k_merge_prepare<uint8_t><<<grid_for(u_b, 256), 256, 0, s>>>(
+        u_b, b_off, static_cast<const uint8_t*>(b_rhs), nullptr, f_prev, h, key_bits,
+        static_cast<uint8_t*>(content), pstart, plen, key);
+  else
+    k_merge_prepare<uint32_t><<<grid_for(u_b, 256), 256, 0, s>>>(
+        u_b, b_off, static_cast<const uint32_t*>(b_rhs), remap_prev, f_prev, h, key_bits,
+        static_cast<uint32_t*>(content), pstart, plen, key);
+  LCG_LAUNCH_CHECK("merge_prepare");
+}
+
+__global__ void k_c_merge(const uint8_t* __restrict__ b_level, const uint32_t* __restrict__ b_sym,
+                          uint32_t kb, uint32_t level, const uint32_t* __restrict__ remap,
+                          uint8_t* __restrict__ out_level, uint32_t* __restrict__ out_sym) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= kb) return;
+  const uint8_t L = b_level[j];
+  if (level == 0) {
+    out_level[j] = L;
+    if (L == 0) out_sym[j] = b_sym[j];
+  } else if (L == level) {
+    out_sym[j] = remap[b_sym[j]];
+  }
+}
+
+void launch_c_merge(const uint8_t* b_level, const uint32_t* b_sym, uint32_t kb, uint32_t level,
+                    const uint32_t* remap, uint8_t* out_level, uint32_t* out_sym, hipStream_t s) {
+  if (!kb) return;
+  k_c_merge<<<grid_for(kb, 256), 256, 0, s>>>(b_level, b_sym, kb, level, remap, out_level, out_sym);
+  LCG_LAUNCH_CHECK("c_merge");
+}
+
+// ------------------------------------------------------------------ expand
+__global__ void k_expand_lens(const uint32_t* __restrict__ cur, uint64_t m,
+                              const uint64_t* __restrict__ rule_off, uint64_t* __restrict__ lens) {
+  const uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (x >= m) return;
+  const uint32_t r = cur[x];
+  lens[x] = rule_off[r + 1] - rule_off[r];
+}
+
+void launch_expand_lens(const uint32_t* cur, uint64_t m, const uint64_t* rule_off, uint64_t* lens,
+                        hipStream_t s) {
+  if (!m) return;
+  k_expand_lens<<<grid_for(m, 256), 256, 0, s>>>(cur, m, rule_off, lens);
+  LCG_LAUNCH_CHECK("expand_lens");
+}
+
+template <typename Sym>
+__global__ void k_expand_emit(const uint32_t* __restrict__ cur, uint64_t m,
+                              const uint64_t* __restrict__ rule_off, const Sym* __restrict__ rule_rhs,
+                              const uint64_t* __restrict__ pos, Sym* __restrict__ next) {
+  const uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (x >= m) return;
+  const uint32_t r = cur[x];
+  const uint64_t p0 = rule_off[r], p1 = rule_off[r + 1];
+  const uint64_t dst = pos[x];
+  for (uint64_t t = p0; t < p1; ++t) next[dst + (t - p0)] = rule_rhs[t];
+}
+
+void launch_expand_emit(bool bytes, const uint32_t* cur, uint64_t m, const uint64_t* rule_off,
+                        const void* rule_rhs, const uint64_t* pos, void* next, hipStream_t s) {
+  if (!m) return;
+  if (bytes)
+    k_expand_emit<uint8_t><<<grid_for(m, 256), 256, 0, s>>>(
+        cur, m, rule_off, static_cast<const uint8_t*>(rule_rhs), pos, static_cast<uint8_t*>(next));
+  else
+    k_expand_emit<uint32_t><<<grid_for(m, 256), 256, 0, s>>>(
+        cur, m, rule_off, static_cast<const uint32_t*>(rule_rhs), pos, static_cast<uint32_t*>(next));
+  LCG_LAUNCH_CHECK("expand_emit");
+}
+
+}  // namespace lcg

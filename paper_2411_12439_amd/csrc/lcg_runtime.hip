@@ -1,0 +1,761 @@
+// Host runtime and C ABI of liblcg (declared in include/lcg.h).
+//
+// The host plans: it validates inputs, sizes buffers from a few counters read
+// back per round, grows dictionaries and launches the kernels of
+// lcg_kernels.hip.  Every operation on the data runs on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/lcg.h"
+#include "lcg_kernels.h"
+
+namespace lcg {
+
+// ------------------------------------------------------------------ errors
+struct LcgError {
+  lcg_status status;
+  std::string msg;
+};
+
+static thread_local std::string g_last_error;
+
+#define HIP_CHECK(x)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess)                                                              \
+      throw LcgError{LCG_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)};        \
+  } while (0)
+
+// ------------------------------------------------------------------ hash family
+// Coefficients (a_i, b_i, c_i) of levels 0..63 in [1, p-1], drawn in that
+// order from SplitMix64 (Steele, Lea, Flood 2014; Vigna's constants) seeded
+// with the grammar seed, each output reduced mod 2^61-1, zeros redrawn.
+struct HashFamily {
+  static constexpr int kLevels = 64;
+  LevelHash lv[kLevels];
+  explicit HashFamily(uint64_t seed) {
+    uint64_t state = seed;
+    auto draw = [&state]() {
+      for (;;) {
+        state += 0x9E3779B97F4A7C15ULL;
+        uint64_t z = state;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        z ^= z >> 31;
+        uint64_t v = z % kP61;
+        if (v) return v;
+      }
+    };
+    for (int i = 0; i < kLevels; ++i) {
+      lv[i].a = draw();
+      lv[i].b = draw();
+      lv[i].c = draw();
+    }
+  }
+};
+
+// ------------------------------------------------------------------ device pool
+// Caching pool of device blocks: calls reuse blocks instead of paying for
+// hipMalloc/hipFree (which synchronise the device) every round.
+class Pool {
+ public:
+  void* alloc(size_t bytes) {
+    size_t sz = round_size(bytes);
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      auto it = free_.lower_bound(sz);
+      if (it != free_.end() && it->first <= sz + sz / 2) {
+        void* p = it->second;
+        size_t got = it->first;
+        free_.erase(it);
+        used_[p] = got;
+        return p;
+      }
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, sz);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      trim();
+      e = hipMalloc(&p, sz);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw LcgError{LCG_ENOMEM, "hipMalloc of " + std::to_string(sz) + " bytes failed"};
+      }
+    }
+    std::lock_guard<std::mutex> lk(mu_);
+    used_[p] = sz;
+    return p;
+  }
+  size_t size_of(void* p) {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = used_.find(p);
+    return it == used_.end() ? 0 : it->second;
+  }
+  void release(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = used_.find(p);
+    if (it == used_.end()) return;
+    free_.insert({it->second, p});
+    used_.erase(it);
+  }
+  void trim() {
+    std::lock_guard<std::mutex> lk(mu_);
+    for (auto& kv : free_) (void)hipFree(kv.second);
+    free_.clear();
+  }
+
+ private:
+  static size_t round_size(size_t b) {
+    if (b < 256) b = 256;
+    if (b <= (1u << 20)) {
+      size_t p = 256;
+      while (p < b) p <<= 1;
+      return p;
+    }
+    const size_t g = 2u << 20;
+    return (b + g - 1) / g * g;
+  }
+  std::mutex mu_;
+  std::multimap<size_t, void*> free_;
+  std::unordered_map<void*, size_t> used_;
+};
+
+static Pool& pool() {
+  static Pool* p = new Pool();  // never destroyed: blocks may outlive static destructors
+  return *p;
+}
+
+template <typename T>
+struct DBuf {
+  T* p = nullptr;
+  size_t cap = 0;  // elements
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), cap(o.cap) { o.p = nullptr; o.cap = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { reset(); p = o.p; cap = o.cap; o.p = nullptr; o.cap = 0; }
+    return *this;
+  }
+  ~DBuf() { reset(); }
+  void reset() {
+    if (p) pool().release(p);
+    p = nullptr;
+    cap = 0;
+  }
+  // capacity >= n, old contents discarded
+  void need(size_t n) {
+    if (n <= cap && p) return;
+    reset();
+    size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    p = static_cast<T*>(pool().alloc(bytes));
+    cap = pool().size_of(p) / sizeof(T);
+  }
+  // capacity >= n, first `used` elements kept
+  void grow(size_t n, size_t used, hipStream_t s) {
+    if (n <= cap && p) return;
+    size_t want = std::max<size_t>(n, cap + cap / 2);
+    T* np = static_cast<T*>(pool().alloc(std::max<size_t>(want, 1) * sizeof(T)));
+    if (used) HIP_CHECK(hipMemcpyAsync(np, p, used * sizeof(T), hipMemcpyDeviceToDevice, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    reset();
+    p = np;
+    cap = pool().size_of(np) / sizeof(T);
+  }
+};
+
+// ------------------------------------------------------------------ grammar
+struct Level {
+  uint32_t u = 0;      // rules
+  uint64_t q = 0;      // total rhs length
+  DBuf<uint64_t> off;  // u + 1 offsets
+  DBuf<uint8_t> rhs8;  // level 1: bytes
+  DBuf<uint32_t> rhs32;
+  DBuf<uint32_t> fp;   // F^i of each rule
+  DBuf<Slot> table;    // dictionary H^i: every committed rule holds one slot
+  uint64_t tcap = 0;
+};
+
+using Stat = std::array<uint64_t, LCG_STATS_FIELDS>;
+
+}  // namespace lcg
+
+struct lcg_grammar {
+  uint64_t seed;
+  lcg::HashFamily H;
+  std::vector<lcg::Level> levels;  // levels[i-1] = level i
+  uint32_t k = 0;
+  lcg::DBuf<uint8_t> c_level;
+  lcg::DBuf<uint32_t> c_sym;
+  std::vector<lcg::Stat> stats;
+  explicit lcg_grammar(uint64_t s) : seed(s), H(s) {}
+};
+
+namespace lcg {
+
+struct Opts {
+  uint64_t seed = 0;
+  uint32_t mode = LCG_MODE_BATCHED;
+  uint32_t flags = 0;
+  uint64_t budget = 0;
+  uint32_t key_bits = 0;
+  uint32_t table_min_log2 = 12;
+};
+
+static Opts read_opts(const lcg_opts* o) {
+  Opts r;
+  if (!o) return r;
+  r.seed = o->seed;
+  r.mode = o->mode;
+  r.flags = o->flags;
+  r.budget = o->hbm_budget;
+  r.key_bits = o->key_bits;
+  if (o->table_min_log2) r.table_min_log2 = o->table_min_log2;
+  if (r.mode != LCG_MODE_BATCHED && r.mode != LCG_MODE_PLAIN)
+    throw LcgError{LCG_EINVAL, "unknown mode"};
+  if (r.key_bits > 30) throw LcgError{LCG_EINVAL, "key_bits must be 0..30"};
+  if (r.table_min_log2 < 6 || r.table_min_log2 > 34) throw LcgError{LCG_EINVAL, "table_min_log2 out of range"};
+  return r;
+}
+
+template <typename T>
+static T read_dev(const T* p, hipStream_t s) {
+  T v;
+  HIP_CHECK(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  return v;
+}
+
+static uint64_t next_pow2(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// HyperLogLog estimate (Flajolet et al. 2007) with the linear-counting
+// correction for small cardinalities.
+static double hll_estimate(const unsigned int* regs) {
+  const double m = kHll;
+  double sum = 0;
+  int zeros = 0;
+  for (int i = 0; i < kHll; ++i) {
+    sum += std::ldexp(1.0, -(int)regs[i]);
+    if (regs[i] == 0) ++zeros;
+  }
+  double e = (0.7213 / (1.0 + 1.079 / m)) * m * m / sum;
+  if (e <= 2.5 * m && zeros) e = m * std::log(m / zeros);
+  return e;
+}
+
+// Working memory of one build call, worst case (every phrase of length two).
+static uint64_t build_bytes(uint64_t n, uint32_t k) {
+  return 17 * n + 96ull * k + (64ull << 20);
+}
+
+// Reusable per-call scratch.
+struct Work {
+  DBuf<uint64_t> bits, tile_cnt, tile_base, scan_tmp;
+  DBuf<uint64_t> pstart, key;
+  DBuf<uint32_t> plen, slot_idx;
+  DBuf<uint32_t> sym[2], fpv[2];
+  DBuf<uint64_t> off[2];
+  DBuf<uint64_t> newbits, wcnt, wlen, wcnt_base, wlen_base;
+  DBuf<uint32_t> lut;
+  DBuf<Counters> ctr;
+  DBuf<uint8_t> content8;
+  DBuf<uint32_t> content32, remap[2];
+};
+
+static void zero_counters(Counters* c, hipStream_t s) { launch_zero(c, sizeof(Counters), s); }
+
+// Make room in level L's dictionary for `need` committed + new keys at load <= 1/2.
+static void ensure_table(Level& L, uint64_t need, uint32_t min_log2, Work& w, hipStream_t s,
+                         bool force_grow = false) {
+  uint64_t want = std::max<uint64_t>(next_pow2(2 * std::max<uint64_t>(need, 1)), 1ull << min_log2);
+  if (force_grow) want = std::max<uint64_t>(want, L.tcap * 4);
+  if (L.tcap >= want && L.table.p) return;
+  if (want > (1ull << 34)) throw LcgError{LCG_ETABLE, "dictionary capacity limit reached"};
+  DBuf<Slot> nt;
+  nt.need(want);
+  launch_fill_slots(nt.p, want, s);
+  if (L.tcap && L.u) {
+    zero_counters(w.ctr.p, s);
+    launch_rehash(L.table.p, L.tcap, nt.p, want - 1, w.ctr.p, s);
+    if (read_dev(&w.ctr.p->overflow, s)) throw LcgError{LCG_ETABLE, "rehash failed"};
+  }
+  HIP_CHECK(hipStreamSynchronize(s));
+  L.table = std::move(nt);
+  L.tcap = want;
+}
+
+static void ensure_level(lcg_grammar* g, size_t i, hipStream_t s) {
+  while (g->levels.size() < i) {
+    g->levels.emplace_back();
+    Level& L = g->levels.back();
+    L.off.need(1);
+    HIP_CHECK(hipMemsetAsync(L.off.p, 0, sizeof(uint64_t), s));
+  }
+}
+
+struct DedupResult {
+  uint32_t u_new;
+  uint64_t q_new;
+  uint64_t probes, compares;
+};
+
+// insert -> newflags -> scan -> commit for d phrases of level `lv` (1-based).
+// content holds the phrases (bytes at level 1), fnew their F values; ranks
+// land in sym_next.  Regrows the dictionary and retries on overflow.
+static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const void* content,
+                                const uint32_t* fnew, uint32_t* sym_next, uint64_t est_new,
+                                const Opts& o, Work& w, hipStream_t s) {
+  Level& L = g->levels[lv - 1];
+  const bool bytes = lv == 1;
+  ensure_table(L, (uint64_t)L.u + est_new, o.table_min_log2, w, s);
+  const uint64_t W = (d + 63) / 64;
+  w.slot_idx.need(d);
+  w.newbits.need(W);
+  w.wcnt.need(W);
+  w.wlen.need(W);
+  w.wcnt_base.need(W + 1);
+  w.wlen_base.need(W + 1);
+  w.scan_tmp.need(std::max<size_t>(scan_tmp_words(W), 1));
+  Counters hc;
+  for (int attempt = 0;; ++attempt) {
+    zero_counters(w.ctr.p, s);
+    const void* rule_rhs = bytes ? (const void*)L.rhs8.p : (const void*)L.rhs32.p;
+    launch_insert(bytes, d, w.key.p, w.pstart.p, w.plen.p, content, L.off.p, rule_rhs, L.u,
+                  L.table.p, L.tcap - 1, w.slot_idx.p, w.ctr.p, s);
+    launch_newflags(d, w.slot_idx.p, L.table.p, w.plen.p, w.newbits.p, w.wcnt.p, w.wlen.p, s);
+    scan_exclusive(w.wcnt.p, w.wcnt_base.p, W, w.scan_tmp.p, s);
+    scan_exclusive(w.wlen.p, w.wlen_base.p, W, w.scan_tmp.p, s);
+    HIP_CHECK(hipMemcpyAsync(&hc, w.ctr.p, offsetof(Counters, hll), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (!hc.overflow) break;
+    if (attempt >= 6) throw LcgError{LCG_ETABLE, "dictionary overflow persists after regrowth"};
+    ensure_table(L, (uint64_t)L.u + std::max<uint64_t>(est_new, hc.won), o.table_min_log2, w, s,
+                 /*force_grow=*/true);
+  }
+  uint64_t u_new = read_dev(w.wcnt_base.p + W, s);
+  uint64_t q_new = read_dev(w.wlen_base.p + W, s);
+  if ((uint64_t)L.u + u_new >= kNone) throw LcgError{LCG_EOVERFLOW, "level needs 2^32 ranks"};
+  L.off.grow(L.u + u_new + 1, L.u + 1, s);
+  L.fp.grow(L.u + u_new, L.u, s);
+  void* rule_rhs;
+  if (bytes) {
+    L.rhs8.grow(L.q + q_new, L.q, s);
+    rule_rhs = L.rhs8.p;
+  } else {
+    L.rhs32.grow(L.q + q_new, L.q, s);
+    rule_rhs = L.rhs32.p;
+  }
+  launch_commit(bytes, d, w.slot_idx.p, L.table.p, w.newbits.p, w.wcnt_base.p, w.wlen_base.p,
+                w.pstart.p, w.plen.p, content, fnew, L.u, L.q, L.off.p, rule_rhs, L.fp.p, sym_next, s);
+  L.u += (uint32_t)u_new;
+  L.q += q_new;
+  return DedupResult{(uint32_t)u_new, q_new, hc.probes, hc.compares};
+}
+
+// BuildGram of k strings into g (fresh or existing): the batched form.
+static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_off, uint32_t k,
+                       const std::vector<uint64_t>& h_off, const Opts& o, Work& w, hipStream_t s) {
+  const uint64_t n = h_off[k];
+  const uint32_t c_base = g->k;
+  g->c_level.grow(c_base + k, c_base, s);
+  g->c_sym.grow(c_base + k, c_base, s);
+  launch_c_init(d_text, d_off, k, g->c_level.p + c_base, g->c_sym.p + c_base, s);
+  g->k += k;
+  uint32_t active = 0;
+  for (uint32_t j = 0; j < k; ++j) active += (h_off[j + 1] - h_off[j]) >= 2;
+  if (!active) {
+    HIP_CHECK(hipStreamSynchronize(s));
+    return;
+  }
+  w.lut.need(256);
+  w.ctr.need(1);
+  launch_f0_lut(w.lut.p, g->H.lv[0].a, g->H.lv[0].b, s);
+  const uint64_t* cur_off = d_off;
+  uint64_t n_i = n;
+  int cur = 0;  // ping-pong index of T^{i+1}
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  const bool timing = (o.flags & LCG_FLAG_TIMING) != 0;
+  if (timing) {
+    HIP_CHECK(hipEventCreate(&ev0));
+    HIP_CHECK(hipEventCreate(&ev1));
+  }
+  try {
+    for (uint32_t lv = 1;; ++lv) {
+      if (lv >= (uint32_t)HashFamily::kLevels) throw LcgError{LCG_EOVERFLOW, "more than 63 rounds"};
+      ensure_level(g, lv, s);
+      if (timing) HIP_CHECK(hipEventRecord(ev0, s));
+      const bool bytes = lv == 1;
+      RoundIn in;
+      in.sym = bytes ? (const void*)d_text : (const void*)w.sym[cur ^ 1].p;
+      in.fp = bytes ? nullptr : w.fpv[cur ^ 1].p;
+      in.lut = w.lut.p;
+      in.off = cur_off;
+      in.k = k;
+      in.n = n_i;
+      in.bytes = bytes;
+      const uint64_t tiles = (n_i + kTile - 1) / kTile;
+      w.bits.need(tiles * kTileWords);
+      w.tile_cnt.need(tiles);
+      w.tile_base.need(tiles + 1);
+      w.scan_tmp.need(std::max<size_t>(scan_tmp_words(tiles), 1));
+      launch_classify(in, w.bits.p, w.tile_cnt.p, s);
+      scan_exclusive(w.tile_cnt.p, w.tile_base.p, tiles, w.scan_tmp.p, s);
+      const uint64_t d = read_dev(w.tile_base.p + tiles, s);
+      if (d == 0) throw LcgError{LCG_EINVAL, "internal: active strings produced no phrase"};
+      if (d >= kNone) throw LcgError{LCG_EOVERFLOW, "a round has 2^32 phrases"};
+      w.pstart.need(d);
+      w.plen.need(d);
+      w.key.need(d);
+      w.sym[cur].need(d);
+      w.fpv[cur].need(d);
+      w.off[cur].need(k + 1);
+      zero_counters(w.ctr.p, s);
+      launch_emit(in, w.bits.p, w.tile_base.p, g->H.lv[lv], o.key_bits, w.pstart.p, w.plen.p,
+                  w.key.p, w.fpv[cur].p, w.ctr.p, s);
+      std::vector<unsigned int> regs(kHll);
+      HIP_CHECK(hipMemcpyAsync(regs.data(), w.ctr.p->hll, sizeof(unsigned int) * kHll,
+                               hipMemcpyDeviceToHost, s));
+      HIP_CHECK(hipStreamSynchronize(s));
+      const uint64_t est = std::min<uint64_t>(d, (uint64_t)(hll_estimate(regs.data()) * 1.25) + 64);
+      const void* content = bytes ? (const void*)d_text : (const void*)w.sym[cur ^ 1].p;
+      DedupResult r = dedup_commit(g, lv, d, content, w.fpv[cur].p, w.sym[cur].p, est, o, w, s);
+      zero_counters(w.ctr.p, s);
+      launch_segments(cur_off, k, w.pstart.p, d, w.off[cur].p, s);
+      launch_finish(cur_off, w.off[cur].p, k, w.sym[cur].p, lv, g->c_level.p + c_base,
+                    g->c_sym.p + c_base, w.ctr.p, s);
+      active = read_dev(&w.ctr.p->active, s);
+      uint64_t ns = 0;
+      if (timing) {
+        HIP_CHECK(hipEventRecord(ev1, s));
+        HIP_CHECK(hipEventSynchronize(ev1));
+        float ms = 0;
+        HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
+        ns = (uint64_t)(ms * 1e6);
+      }
+      g->stats.push_back(Stat{n_i, d, r.u_new, r.q_new, active, r.probes, r.compares,
+                              g->levels[lv - 1].tcap, ns});
+      if (!active) break;
+      cur_off = w.off[cur].p;
+      n_i = d;
+      cur ^= 1;
+    }
+  } catch (...) {
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    throw;
+  }
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+}
+
+// MergeGrams(a, b): a absorbs b level by level (Sec. 3.6).
+static void merge_core(lcg_grammar* a, const lcg_grammar* b, Work& w, hipStream_t s) {
+  if (a->seed != b->seed) throw LcgError{LCG_ESEED, "grammars use different hash families"};
+  const uint32_t ka = a->k, kb = b->k;
+  a->c_level.grow(ka + kb, ka, s);
+  a->c_sym.grow(ka + kb, ka, s);
+  launch_c_merge(b->c_level.p, b->c_sym.p, kb, 0, nullptr, a->c_level.p + ka, a->c_sym.p + ka, s);
+  w.lut.need(256);
+  w.ctr.need(1);
+  launch_f0_lut(w.lut.p, a->H.lv[0].a, a->H.lv[0].b, s);
+  Opts o;
+  int cur = 0;
+  const uint32_t* remap_prev = nullptr;
+  for (size_t lv = 1; lv <= b->levels.size(); ++lv) {
+    ensure_level(a, lv, s);
+    const Level& B = b->levels[lv - 1];
+    const bool bytes = lv == 1;
+    const uint32_t ub = B.u;
+    w.remap[cur].need(std::max<uint32_t>(ub, 1));
+    if (ub) {
+      w.pstart.need(ub);
+      w.plen.need(ub);
+      w.key.need(ub);
+      const void* content;
+      const uint32_t* f_prev = bytes ? w.lut.p : a->levels[lv - 2].fp.p;
+      if (bytes) {
+        w.content8.need(B.q);
+        content = w.content8.p;
+        launch_merge_prepare(true, ub, B.off.p, B.rhs8.p, nullptr, f_prev, a->H.lv[lv], 0,
+                             w.content8.p, w.pstart.p, w.plen.p, w.key.p, s);
+      } else {
+        w.content32.need(B.q);
+        content = w.content32.p;
+        launch_merge_prepare(false, ub, B.off.p, B.rhs32.p, remap_prev, f_prev, a->H.lv[lv], 0,
+                             w.content32.p, w.pstart.p, w.plen.p, w.key.p, s);
+      }
+      dedup_commit(a, (uint32_t)lv, ub, content, B.fp.p, w.remap[cur].p, ub, o, w, s);
+      launch_c_merge(b->c_level.p, b->c_sym.p, kb, (uint32_t)lv, w.remap[cur].p,
+                     a->c_level.p + ka, a->c_sym.p + ka, s);
+    }
+    remap_prev = w.remap[cur].p;
+    cur ^= 1;
+  }
+  a->k += kb;
+  HIP_CHECK(hipStreamSynchronize(s));
+}
+
+static std::vector<uint64_t> fetch_offsets(const uint64_t* d_off, uint32_t k, hipStream_t s) {
+  if (k == 0) throw LcgError{LCG_EINVAL, "k must be >= 1"};
+  if (!d_off) throw LcgError{LCG_EINVAL, "offsets are NULL"};
+  std::vector<uint64_t> h(k + 1);
+  HIP_CHECK(hipMemcpyAsync(h.data(), d_off, sizeof(uint64_t) * (k + 1), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  if (h[0] != 0) throw LcgError{LCG_EINVAL, "offsets[0] must be 0"};
+  for (uint32_t j = 0; j < k; ++j)
+    if (h[j + 1] <= h[j]) throw LcgError{LCG_EINVAL, "string " + std::to_string(j) + " is empty or offsets decrease"};
+  return h;
+}
+
+static void check_budget(const Opts& o, uint64_t n, uint32_t k) {
+  if (o.budget && build_bytes(n, k) > o.budget)
+    throw LcgError{LCG_ENOMEM, "input needs more than hbm_budget bytes of working memory"};
+}
+
+static void build_any(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_off, uint32_t k,
+                      const Opts& o, hipStream_t s) {
+  std::vector<uint64_t> h_off = fetch_offsets(d_off, k, s);
+  if (!d_text) throw LcgError{LCG_EINVAL, "text is NULL"};
+  Work w;
+  if (o.mode == LCG_MODE_BATCHED) {
+    check_budget(o, h_off[k], k);
+    build_core(g, d_text, d_off, k, h_off, o, w, s);
+    return;
+  }
+  // plain form: one grammar per string (its own launches every round), then MergeGrams
+  uint64_t max_len = 0;
+  for (uint32_t j = 0; j < k; ++j) max_len = std::max(max_len, h_off[j + 1] - h_off[j]);
+  check_budget(o, max_len, 1);
+  std::vector<uint64_t> pairs(2 * (size_t)k);
+  for (uint32_t j = 0; j < k; ++j) {
+    pairs[2 * j] = 0;
+    pairs[2 * j + 1] = h_off[j + 1] - h_off[j];
+  }
+  DBuf<uint64_t> d_pairs;
+  d_pairs.need(pairs.size());
+  HIP_CHECK(hipMemcpyAsync(d_pairs.p, pairs.data(), sizeof(uint64_t) * pairs.size(),
+                           hipMemcpyHostToDevice, s));
+  for (uint32_t j = 0; j < k; ++j) {
+    lcg_grammar gj(g->seed);
+    std::vector<uint64_t> one{0, pairs[2 * j + 1]};
+    build_core(&gj, d_text + h_off[j], d_pairs.p + 2 * j, 1, one, o, w, s);
+    merge_core(g, &gj, w, s);
+    g->stats.insert(g->stats.end(), gj.stats.begin(), gj.stats.end());
+  }
+}
+
+static void expand_core(lcg_grammar* g, uint32_t j, uint8_t* d_out, uint64_t cap, uint64_t* out_len,
+                        hipStream_t s) {
+  if (j >= g->k) throw LcgError{LCG_EINVAL, "string index out of range"};
+  uint8_t lvl;
+  uint32_t sym;
+  HIP_CHECK(hipMemcpyAsync(&lvl, g->c_level.p + j, 1, hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(&sym, g->c_sym.p + j, 4, hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  if (lvl == 0) {
+    if (out_len) *out_len = 1;
+    if (cap < 1) throw LcgError{LCG_EINVAL, "output buffer too small"};
+    HIP_CHECK(hipMemcpyAsync(d_out, &sym, 1, hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    return;
+  }
+  DBuf<uint32_t> cur, nxt;
+  DBuf<uint64_t> lens, pos, tmp;
+  cur.need(1);
+  HIP_CHECK(hipMemcpyAsync(cur.p, &sym, 4, hipMemcpyHostToDevice, s));
+  uint64_t m = 1;
+  for (uint32_t lv = lvl; lv >= 1; --lv) {
+    const Level& L = g->levels[lv - 1];
+    lens.need(m);
+    pos.need(m + 1);
+    tmp.need(std::max<size_t>(scan_tmp_words(m), 1));
+    launch_expand_lens(cur.p, m, L.off.p, lens.p, s);
+    scan_exclusive(lens.p, pos.p, m, tmp.p, s);
+    const uint64_t total = read_dev(pos.p + m, s);
+    if (lv == 1) {
+      if (out_len) *out_len = total;
+      if (total > cap) throw LcgError{LCG_EINVAL, "output buffer too small"};
+      launch_expand_emit(true, cur.p, m, L.off.p, L.rhs8.p, pos.p, d_out, s);
+      HIP_CHECK(hipStreamSynchronize(s));
+      return;
+    }
+    nxt.need(total);
+    launch_expand_emit(false, cur.p, m, L.off.p, L.rhs32.p, pos.p, nxt.p, s);
+    std::swap(cur, nxt);
+    m = total;
+  }
+}
+
+template <typename F>
+static lcg_status guard(F&& f) {
+  try {
+    f();
+    return LCG_OK;
+  } catch (const LcgError& e) {
+    g_last_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return LCG_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return LCG_EHIP;
+  }
+}
+
+}  // namespace lcg
+
+using namespace lcg;
+
+extern "C" {
+
+void lcg_opts_init(lcg_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->mode = LCG_MODE_BATCHED;
+}
+
+lcg_status lcg_new(uint64_t seed, lcg_grammar_t* out) {
+  return guard([&] {
+    if (!out) throw LcgError{LCG_EINVAL, "out is NULL"};
+    *out = new lcg_grammar(seed);
+  });
+}
+
+lcg_status lcg_build(const uint8_t* d_text, const uint64_t* d_offsets, uint32_t k,
+                     const lcg_opts* opts, hipStream_t stream, lcg_grammar_t* out) {
+  return guard([&] {
+    if (!out) throw LcgError{LCG_EINVAL, "out is NULL"};
+    Opts o = read_opts(opts);
+    lcg_grammar* g = new lcg_grammar(o.seed);
+    try {
+      build_any(g, d_text, d_offsets, k, o, stream);
+    } catch (...) {
+      (void)hipStreamSynchronize(stream);
+      delete g;
+      throw;
+    }
+    *out = g;
+  });
+}
+
+lcg_status lcg_build_into(lcg_grammar_t g, const uint8_t* d_text, const uint64_t* d_offsets,
+                          uint32_t k, const lcg_opts* opts, hipStream_t stream,
+                          uint32_t* first_index) {
+  return guard([&] {
+    if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    Opts o = read_opts(opts);
+    if (opts && o.seed != g->seed) throw LcgError{LCG_ESEED, "opts seed differs from the grammar's"};
+    Opts oo = o;
+    oo.mode = LCG_MODE_BATCHED;
+    uint32_t first = g->k;
+    build_any(g, d_text, d_offsets, k, oo, stream);
+    if (first_index) *first_index = first;
+  });
+}
+
+lcg_status lcg_merge(lcg_grammar_t a, lcg_grammar_t b, hipStream_t stream) {
+  return guard([&] {
+    if (!a || !b) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    if (a == b) throw LcgError{LCG_EINVAL, "cannot merge a grammar into itself"};
+    Work w;
+    merge_core(a, b, w, stream);
+  });
+}
+
+lcg_status lcg_expand(lcg_grammar_t g, uint32_t j, uint8_t* d_out, uint64_t cap, uint64_t* out_len,
+                      hipStream_t stream) {
+  return guard([&] {
+    if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    expand_core(g, j, d_out, cap, out_len, stream);
+  });
+}
+
+lcg_status lcg_info(lcg_grammar_t g, uint64_t* seed, uint32_t* n_levels, uint32_t* k) {
+  return guard([&] {
+    if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    if (seed) *seed = g->seed;
+    if (n_levels) *n_levels = (uint32_t)g->levels.size();
+    if (k) *k = g->k;
+  });
+}
+
+lcg_status lcg_level_size(lcg_grammar_t g, uint32_t level, uint32_t* u, uint64_t* rhs_len) {
+  return guard([&] {
+    if (!g || level == 0 || level > g->levels.size()) throw LcgError{LCG_EINVAL, "bad level"};
+    if (u) *u = g->levels[level - 1].u;
+    if (rhs_len) *rhs_len = g->levels[level - 1].q;
+  });
+}
+
+lcg_status lcg_level_copy(lcg_grammar_t g, uint32_t level, uint64_t* h_rhs_off, uint32_t* h_rhs,
+                          uint32_t* h_fp) {
+  return guard([&] {
+    if (!g || level == 0 || level > g->levels.size()) throw LcgError{LCG_EINVAL, "bad level"};
+    const Level& L = g->levels[level - 1];
+    HIP_CHECK(hipDeviceSynchronize());
+    if (h_rhs_off) HIP_CHECK(hipMemcpy(h_rhs_off, L.off.p, sizeof(uint64_t) * (L.u + 1), hipMemcpyDeviceToHost));
+    if (h_fp && L.u) HIP_CHECK(hipMemcpy(h_fp, L.fp.p, sizeof(uint32_t) * L.u, hipMemcpyDeviceToHost));
+    if (h_rhs && L.q) {
+      if (level == 1) {
+        std::vector<uint8_t> tmp(L.q);
+        HIP_CHECK(hipMemcpy(tmp.data(), L.rhs8.p, L.q, hipMemcpyDeviceToHost));
+        for (uint64_t i = 0; i < L.q; ++i) h_rhs[i] = tmp[i];
+      } else {
+        HIP_CHECK(hipMemcpy(h_rhs, L.rhs32.p, sizeof(uint32_t) * L.q, hipMemcpyDeviceToHost));
+      }
+    }
+  });
+}
+
+lcg_status lcg_c_copy(lcg_grammar_t g, uint8_t* h_level, uint32_t* h_sym) {
+  return guard([&] {
+    if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    HIP_CHECK(hipDeviceSynchronize());
+    if (g->k && h_level) HIP_CHECK(hipMemcpy(h_level, g->c_level.p, g->k, hipMemcpyDeviceToHost));
+    if (g->k && h_sym) HIP_CHECK(hipMemcpy(h_sym, g->c_sym.p, 4ull * g->k, hipMemcpyDeviceToHost));
+  });
+}
+
+lcg_status lcg_stats(lcg_grammar_t g, uint64_t* h_out, uint32_t cap_rounds, uint32_t* n_rounds) {
+  return guard([&] {
+    if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    if (n_rounds) *n_rounds = (uint32_t)g->stats.size();
+    for (uint32_t r = 0; r < cap_rounds && r < g->stats.size(); ++r)
+      for (int f = 0; f < LCG_STATS_FIELDS; ++f) h_out[(size_t)r * LCG_STATS_FIELDS + f] = g->stats[r][f];
+  });
+}
+
+lcg_status lcg_stats_clear(lcg_grammar_t g) {
+  return guard([&] {
+    if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    g->stats.clear();
+  });
+}
+
+uint64_t lcg_build_bytes(uint64_t n, uint32_t k) { return build_bytes(n, k); }
+
+void lcg_free(lcg_grammar_t g) { delete g; }
+
+void lcg_release_pool(void) { pool().trim(); }
+
+const char* lcg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,255 @@
+"""ctypes binding of liblcg.so (the HIP/gfx950 LCG library; C ABI in include/lcg.h).
+
+Argument marshalling only: every step of the construction runs in the
+library's kernels.  Device buffers are torch tensors on the current HIP
+device; the stream is torch's current stream unless one is given.  If the
+library has not been built this module raises -- there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblcg.so")
+STATS_FIELDS = 9
+STAT_NAMES = ("n", "phrases", "new_rules", "new_rhs", "active", "probes", "compares",
+              "table_cap", "time_ns")
+
+MODE_BATCHED = 0
+MODE_PLAIN = 1
+FLAG_TIMING = 1
+
+_STATUS = {0: "LCG_OK", -1: "LCG_EINVAL", -2: "LCG_ENOMEM", -3: "LCG_ESEED",
+           -4: "LCG_EOVERFLOW", -5: "LCG_ETABLE", -6: "LCG_EHIP"}
+
+# Every symbol include/lcg.h declares (checked by the CPU test suite).
+EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_expand", "lcg_new",
+           "lcg_info", "lcg_level_size", "lcg_level_copy", "lcg_c_copy", "lcg_stats",
+           "lcg_stats_clear", "lcg_build_bytes", "lcg_free", "lcg_release_pool", "lcg_last_error")
+
+
+class LcgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
+        self.status = status
+        self.name = _STATUS.get(status, str(status))
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("mode", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("hbm_budget", ctypes.c_uint64), ("key_bits", ctypes.c_uint32),
+                ("table_min_log2", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
+
+
+_lib = None
+
+
+def lib():
+    """Load liblcg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("liblcg.so is not built (run __graft_entry__.build() or "
+                           "python paper_2411_12439_amd/build_lib.py)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u8p, u32p, u64p = (ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint8),
+                           ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64))
+    st = ctypes.c_int
+    L.lcg_opts_init.argtypes = [ctypes.POINTER(Opts)]
+    L.lcg_opts_init.restype = None
+    L.lcg_build.argtypes = [vp, vp, ctypes.c_uint32, ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
+    L.lcg_build.restype = st
+    L.lcg_build_into.argtypes = [vp, vp, vp, ctypes.c_uint32, ctypes.POINTER(Opts), vp, u32p]
+    L.lcg_build_into.restype = st
+    L.lcg_merge.argtypes = [vp, vp, vp]
+    L.lcg_merge.restype = st
+    L.lcg_expand.argtypes = [vp, ctypes.c_uint32, vp, ctypes.c_uint64, u64p, vp]
+    L.lcg_expand.restype = st
+    L.lcg_new.argtypes = [ctypes.c_uint64, ctypes.POINTER(vp)]
+    L.lcg_new.restype = st
+    L.lcg_info.argtypes = [vp, u64p, u32p, u32p]
+    L.lcg_info.restype = st
+    L.lcg_level_size.argtypes = [vp, ctypes.c_uint32, u32p, u64p]
+    L.lcg_level_size.restype = st
+    L.lcg_level_copy.argtypes = [vp, ctypes.c_uint32, u64p, u32p, u32p]
+    L.lcg_level_copy.restype = st
+    L.lcg_c_copy.argtypes = [vp, u8p, u32p]
+    L.lcg_c_copy.restype = st
+    L.lcg_stats.argtypes = [vp, u64p, ctypes.c_uint32, u32p]
+    L.lcg_stats.restype = st
+    L.lcg_stats_clear.argtypes = [vp]
+    L.lcg_stats_clear.restype = st
+    L.lcg_build_bytes.argtypes = [ctypes.c_uint64, ctypes.c_uint32]
+    L.lcg_build_bytes.restype = ctypes.c_uint64
+    L.lcg_free.argtypes = [vp]
+    L.lcg_free.restype = None
+    L.lcg_release_pool.argtypes = []
+    L.lcg_release_pool.restype = None
+    L.lcg_last_error.argtypes = []
+    L.lcg_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise LcgError(rc, lib().lcg_last_error().decode())
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_inputs(text, offsets):
+    import torch
+    if not (text.is_cuda and offsets.is_cuda):
+        raise ValueError("text and offsets must be device tensors")
+    if text.dtype != torch.uint8 or offsets.dtype not in (torch.int64, torch.uint64):
+        raise ValueError("text must be uint8 and offsets int64/uint64")
+    if not (text.is_contiguous() and offsets.is_contiguous()):
+        raise ValueError("text and offsets must be contiguous")
+    if offsets.numel() < 2:
+        raise ValueError("need at least one string")
+
+
+def make_opts(seed=0, mode=MODE_BATCHED, flags=0, hbm_budget=0, key_bits=0, table_min_log2=0):
+    o = Opts()
+    lib().lcg_opts_init(ctypes.byref(o))
+    o.seed = seed
+    o.mode = mode
+    o.flags = flags
+    o.hbm_budget = hbm_budget
+    o.key_bits = key_bits
+    o.table_min_log2 = table_min_log2
+    return o
+
+
+class Grammar:
+    """Owning handle of a device-resident grammar."""
+
+    def __init__(self, handle):
+        self.h = handle
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.lcg_free(self.h)
+            self.h = None
+
+    def free(self):
+        if self.h:
+            lib().lcg_free(self.h)
+            self.h = None
+
+    def info(self):
+        seed, nl, k = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().lcg_info(self.h, ctypes.byref(seed), ctypes.byref(nl), ctypes.byref(k)))
+        return seed.value, nl.value, k.value
+
+    def level_sizes(self):
+        _, nl, _ = self.info()
+        out = []
+        for i in range(1, nl + 1):
+            u, q = ctypes.c_uint32(), ctypes.c_uint64()
+            _check(lib().lcg_level_size(self.h, i, ctypes.byref(u), ctypes.byref(q)))
+            out.append((u.value, q.value))
+        return out
+
+    def export(self):
+        """Host copy: {"seed", "levels": [{"rhs_off", "rhs", "fp"}], "c_level", "c_sym"}."""
+        seed, nl, k = self.info()
+        levels = []
+        for i, (u, q) in enumerate(self.level_sizes(), start=1):
+            off = np.zeros(u + 1, np.uint64)
+            rhs = np.zeros(max(q, 1), np.uint32)
+            fp = np.zeros(max(u, 1), np.uint32)
+            _check(lib().lcg_level_copy(self.h, i, _ptr(off, ctypes.c_uint64),
+                                        _ptr(rhs, ctypes.c_uint32), _ptr(fp, ctypes.c_uint32)))
+            levels.append({"rhs_off": off, "rhs": rhs[:q], "fp": fp[:u]})
+        cl = np.zeros(max(k, 1), np.uint8)
+        cs = np.zeros(max(k, 1), np.uint32)
+        _check(lib().lcg_c_copy(self.h, _ptr(cl, ctypes.c_uint8), _ptr(cs, ctypes.c_uint32)))
+        return {"seed": seed, "levels": levels, "c_level": cl[:k], "c_sym": cs[:k]}
+
+    def stats(self):
+        n = ctypes.c_uint32()
+        _check(lib().lcg_stats(self.h, None, 0, ctypes.byref(n)))
+        out = np.zeros((max(n.value, 1), STATS_FIELDS), np.uint64)
+        _check(lib().lcg_stats(self.h, _ptr(out, ctypes.c_uint64), n.value, ctypes.byref(n)))
+        return out[:n.value]
+
+    def clear_stats(self):
+        _check(lib().lcg_stats_clear(self.h))
+
+    def merge(self, other, stream=None):
+        """MergeGrams(self, other): self absorbs other (other unchanged)."""
+        _check(lib().lcg_merge(self.h, other.h, _stream(stream)))
+        return self
+
+    def expand(self, j, out=None, stream=None):
+        """exp(C[j]) as a device uint8 tensor (written into `out` if given)."""
+        import torch
+        n = ctypes.c_uint64()
+        if out is None:
+            rc = lib().lcg_expand(self.h, j, None, 0, ctypes.byref(n), _stream(stream))
+            if rc not in (0, -1):
+                _check(rc)
+            out = torch.empty(max(n.value, 1), dtype=torch.uint8, device="cuda")
+        _check(lib().lcg_expand(self.h, j, ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                ctypes.byref(n), _stream(stream)))
+        return out[:n.value]
+
+
+def new(seed):
+    h = ctypes.c_void_p()
+    _check(lib().lcg_new(seed, ctypes.byref(h)))
+    return Grammar(h.value)
+
+
+def build(text, offsets, seed=0, mode=MODE_BATCHED, flags=0, hbm_budget=0, key_bits=0,
+          table_min_log2=0, stream=None):
+    """BuildGram over the strings text[offsets[j]:offsets[j+1]] (device tensors)."""
+    _check_inputs(text, offsets)
+    o = make_opts(seed, mode, flags, hbm_budget, key_bits, table_min_log2)
+    h = ctypes.c_void_p()
+    _check(lib().lcg_build(ctypes.c_void_p(text.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
+                           offsets.numel() - 1, ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+    return Grammar(h.value)
+
+
+def build_into(g, text, offsets, seed=None, flags=0, hbm_budget=0, key_bits=0, table_min_log2=0,
+               stream=None):
+    """Compress a batch into an existing grammar; returns the C index of its first string."""
+    _check_inputs(text, offsets)
+    if seed is None:
+        seed = g.info()[0]
+    o = make_opts(seed, MODE_BATCHED, flags, hbm_budget, key_bits, table_min_log2)
+    first = ctypes.c_uint32()
+    _check(lib().lcg_build_into(g.h, ctypes.c_void_p(text.data_ptr()),
+                                ctypes.c_void_p(offsets.data_ptr()), offsets.numel() - 1,
+                                ctypes.byref(o), _stream(stream), ctypes.byref(first)))
+    return first.value
+
+
+def build_bytes(n, k):
+    """Upper bound of the working memory of one build over n bytes in k strings."""
+    return int(lib().lcg_build_bytes(n, k))
+
+
+def release_pool():
+    lib().lcg_release_pool()
+
+
+def to_device(text, offsets, device="cuda"):
+    """numpy (text uint8, offsets uint64) -> device tensors (int64 offsets)."""
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(text, np.uint8)).to(device)
+    o = torch.from_numpy(np.ascontiguousarray(offsets, np.uint64).view(np.int64)).to(device)
+    return t, o

@@ -1,0 +1,72 @@
+"""The C-ABI library loads and exports every symbol include/lcg.h declares (no GPU calls)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lcg.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lcg_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lcgmod():
+    from paper_2411_12439_amd import lcg
+    if not os.path.exists(lcg.LIB_PATH):
+        from paper_2411_12439_amd import build_lib
+        build_lib.build()
+    return lcg
+
+
+def test_header_declares_the_binding_exports():
+    from paper_2411_12439_amd import lcg
+    assert _declared() == sorted(lcg.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lcgmod):
+    L = lcgmod.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", lcgmod.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    syms = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for name in _declared():
+        assert name in syms, name
+
+
+def test_host_only_entry_points(lcgmod):
+    """Calls that touch no device: defaults, error reporting, sizing."""
+    o = lcgmod.make_opts(seed=5)
+    assert o.mode == lcgmod.MODE_BATCHED and o.seed == 5
+    assert lcgmod.build_bytes(1000, 2) >= 17 * 1000
+    g = lcgmod.new(42)
+    assert g.info() == (42, 0, 0)
+    assert g.level_sizes() == []
+    assert g.stats().shape == (0, lcgmod.STATS_FIELDS)
+    with pytest.raises(lcgmod.LcgError) as e:
+        lcgmod._check(lcgmod.lib().lcg_level_size(g.h, 1, None, None))
+    assert e.value.name == "LCG_EINVAL"
+    g.free()
+
+
+def test_product_path_has_no_fallback():
+    """The binding refuses to run without the HIP library instead of computing elsewhere."""
+    import importlib
+    from paper_2411_12439_amd import lcg
+    src = open(lcg.__file__).read()
+    assert "oracle" not in src
+    mod = importlib.import_module("paper_2411_12439_amd.lcg")
+    saved_path, saved_lib = mod.LIB_PATH, mod._lib
+    try:
+        mod.LIB_PATH = "/nonexistent/liblcg.so"
+        mod._lib = None
+        with pytest.raises(RuntimeError):
+            mod.lib()
+    finally:
+        mod.LIB_PATH, mod._lib = saved_path, saved_lib

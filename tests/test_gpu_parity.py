@@ -1,0 +1,212 @@
+"""Parity of the HIP library (through the C ABI) with the CPU oracle.
+
+Both sides number a level's new rules by first occurrence, so the comparison
+is exact, rank for rank (the grammar is integer data: zero tolerance).  At
+full benchmark sizes, where the oracle would take minutes, sampled strings are
+checked one by one: each string's sub-grammar inside the GPU grammar must
+equal the oracle's grammar of that string alone (stability, Def. 1), and its
+expansion must equal the input.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2411_12439_amd import canon as CN
+from paper_2411_12439_amd import datagen as D
+
+pytestmark = pytest.mark.gpu
+SEED = D.HASH_SEED
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2411_12439_amd import lcg
+    lcg.lib()
+    return lcg
+
+
+def _pack(strings):
+    from oracle import oracle as O
+    return O.pack(strings)
+
+
+def _gpu(L, text, off, **kw):
+    t, o = L.to_device(text, off)
+    return L.build(t, o, seed=kw.pop("seed", SEED), **kw)
+
+
+def _assert_same(got, want):
+    assert CN.exports_equal(got, want), CN.first_difference(got, want)
+
+
+def _oracle(text, off, seed=SEED):
+    from oracle import oracle as O
+    return O.build(text, off, seed)
+
+
+# ---------------------------------------------------------------- tiny config
+@pytest.mark.parametrize("mode", [0, 1], ids=["batched", "plain"])
+def test_tiny_config_equals_oracle(L, mode):
+    text, off = D.make_config("tiny")
+    g = _gpu(L, text, off, mode=mode)
+    _assert_same(g.export(), _oracle(text, off).export())
+
+
+def test_tiny_config_round_statistics(L):
+    text, off = D.make_config("tiny")
+    st = _gpu(L, text, off).stats()
+    want = _oracle(text, off).stats()
+    assert st.shape[0] == want.shape[0]
+    # n_in, phrases, new rules, new rhs symbols, active strings
+    assert np.array_equal(st[:, :5], want)
+
+
+def test_round_trip_expand(L):
+    text, off = D.make_config("tiny", scale=0.3)
+    g = _gpu(L, text, off)
+    for j in range(len(off) - 1):
+        assert np.array_equal(g.expand(j).cpu().numpy(), text[off[j]:off[j + 1]])
+
+
+def test_deterministic(L):
+    text, off = D.make_config("tiny", scale=0.5)
+    a = _gpu(L, text, off).export()
+    b = _gpu(L, text, off).export()
+    _assert_same(a, b)
+
+
+# ---------------------------------------------------------------- edge cases
+EDGE = {
+    "single_byte": [b"A"],
+    "two_bytes": [b"AB"],
+    "only_singletons": [b"x", b"y", b"x"],
+    "singletons_mixed": [b"A", b"ACGTACGGTCA", b"T", b"GG", b"C"],
+    "homopolymer_crosses_tiles": [b"G" * 20000],
+    "homopolymer_tail": [b"ACGTTGCA" * 700 + b"T" * 9000],
+    "run_at_tile_edges": [b"AC" * 2047 + b"G" * 4 + b"CA" * 3000, b"T" * 4095 + b"A" + b"T" * 4097],
+    "tile_sized": [bytes(np.random.default_rng(1).integers(65, 69, n, dtype=np.uint8))
+                   for n in (4095, 4096, 4097, 8192, 8193)],
+    "period2": [b"AC" * 6000],
+    "binary_runs": [bytes(np.random.default_rng(2).choice(np.frombuffer(b"AC", np.uint8), 3000))
+                    for _ in range(20)],
+    "all_bytes": [bytes(np.random.default_rng(3).integers(0, 256, 5000, dtype=np.uint8)),
+                  bytes(range(256)) * 3, bytes(range(255, -1, -1))],
+    "tandem_repeats": [(b"ACGTTG" * 500 + b"A" * 700 + b"GATTACA" * 300) for _ in range(3)],
+}
+
+
+@pytest.mark.parametrize("case", sorted(EDGE))
+@pytest.mark.parametrize("mode", [0, 1], ids=["batched", "plain"])
+def test_edge_cases(L, case, mode):
+    text, off = _pack(EDGE[case])
+    g = _gpu(L, text, off, mode=mode)
+    _assert_same(g.export(), _oracle(text, off).export())
+
+
+def test_exhaustive_short_dna(L):
+    strings = [bytes(t) for n in range(1, 7) for t in itertools.product(b"ACGT", repeat=n)]
+    text, off = _pack(strings)
+    _assert_same(_gpu(L, text, off).export(), _oracle(text, off).export())
+
+
+@pytest.mark.parametrize("key_bits", [3, 12])
+def test_truncated_keys_rely_on_full_comparison(L, key_bits):
+    """Keys cut to a few bits collide constantly; exact comparison must still dedup correctly."""
+    text, off = D.make_config("tiny", scale=0.05)
+    g = _gpu(L, text, off, key_bits=key_bits)
+    _assert_same(g.export(), _oracle(text, off).export())
+    assert g.stats()[:, 6].sum() > 0  # full comparisons happened
+
+
+def test_small_tables_regrow(L):
+    text, off = D.make_config("tiny", scale=0.2)
+    g = _gpu(L, text, off, table_min_log2=6)
+    _assert_same(g.export(), _oracle(text, off).export())
+
+
+# ---------------------------------------------------------------- merge / build_into
+@pytest.mark.parametrize("cut", [1, 3, 7])
+def test_merge_equals_build_of_concatenation(L, cut):
+    text, off = D.make_config("tiny", scale=0.1)
+    ta, oa = text[:off[cut]], off[:cut + 1]
+    tb, ob = text[off[cut]:], off[cut:] - off[cut]
+    ga = _gpu(L, ta, oa)
+    gb = _gpu(L, tb, ob)
+    ga.merge(gb)
+    _assert_same(ga.export(), _oracle(text, off).export())
+    _assert_same(gb.export(), _oracle(tb, ob).export())  # b unchanged
+
+
+def test_build_into_equals_oracle(L):
+    text, off = D.make_config("tiny", scale=0.1)
+    g = L.new(SEED)
+    for lo, hi in ((0, 2), (2, 3), (3, 8)):
+        t, o = L.to_device(text[off[lo]:off[hi]], off[lo:hi + 1] - off[lo])
+        first = L.build_into(g, t, o)
+        assert first == lo
+    _assert_same(g.export(), _oracle(text, off).export())
+
+
+def test_errors(L):
+    import torch
+    t, o = L.to_device(np.frombuffer(b"ABC", np.uint8), np.array([0, 2, 2, 3], np.uint64))
+    with pytest.raises(L.LcgError) as e:
+        L.build(t, o, seed=SEED)
+    assert e.value.name == "LCG_EINVAL"
+    t, o = L.to_device(np.frombuffer(b"ABCABD", np.uint8), np.array([0, 6], np.uint64))
+    with pytest.raises(L.LcgError) as e:
+        L.build(t, o, seed=SEED, hbm_budget=1024)
+    assert e.value.name == "LCG_ENOMEM"
+    ga = L.build(t, o, seed=1)
+    gb = L.build(t, o, seed=2)
+    with pytest.raises(L.LcgError) as e:
+        ga.merge(gb)
+    assert e.value.name == "LCG_ESEED"
+    torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------- other configurations (scaled)
+@pytest.mark.parametrize("name,scale", [("repeats", 0.004), ("batched", 0.001), ("bacterial", 0.01)])
+def test_scaled_configs_equal_oracle(L, name, scale):
+    text, off = D.make_config(name, scale=scale)
+    _assert_same(_gpu(L, text, off).export(), _oracle(text, off).export())
+
+
+# ---------------------------------------------------------------- full benchmark size
+@pytest.fixture(scope="module")
+def bacterial_full(L):
+    text, off = D.make_config("bacterial")
+    t, o = L.to_device(text, off)
+    g = L.build(t, o, seed=SEED)
+    return text, off, t, o, g
+
+
+@pytest.mark.parametrize("j", [0, 17, 42, 63])
+def test_full_bacterial_sampled_strings(L, bacterial_full, j):
+    """Each sampled string: sub-grammar == oracle grammar of the string alone; expansion == input."""
+    from oracle import oracle as O
+    text, off, t, o, g = bacterial_full
+    got = CN.subgrammar(g.export(), [j])
+    alone = O.build(text[off[j]:off[j + 1]], np.array([0, off[j + 1] - off[j]], np.uint64), SEED)
+    assert CN.canon(got) == CN.canon(alone.export())
+    assert np.array_equal(g.expand(j).cpu().numpy(), text[off[j]:off[j + 1]])
+
+
+def test_full_bacterial_plain_equals_batched(L, bacterial_full):
+    text, off, t, o, g = bacterial_full
+    gp = L.build(t, o, seed=SEED, mode=L.MODE_PLAIN)
+    _assert_same(gp.export(), g.export())
+
+
+def test_full_bacterial_invariants(L, bacterial_full):
+    text, off, t, o, g = bacterial_full
+    st = g.stats()
+    active = len(off) - 1
+    for n_in, d, u, q, act in st[:, :5].astype(np.int64):
+        assert 2 * d <= n_in + active
+        assert u <= d and q <= n_in
+        active = act
+    assert st[-1, 4] == 0
