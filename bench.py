@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Benchmark of the LCG construction on one MI355X.
+
+A step is one complete construction of the grammar of the workload's
+collection in the batched form: every parsing round (classify, fingerprint,
+dictionary, rewrite) over all strings at once, the merge being implicit in the
+shared per-level dictionaries.  Inputs are resident in device memory before
+the timed region; nothing is skipped inside it.  The plain form (one launch
+sequence per string per round, then MergeGrams of the per-string grammars) is
+timed on the same collection for the batched-vs-plain ratio.
+
+Prints one JSON line (see the keys below).  Extra fields:
+  p50_gbps / p99_gbps    input GB/s over the timed steps (p99 = slowest steps)
+  plain_gbps, batched_vs_plain
+  alg_bytes_per_input_byte, alg_gbps, alg_frac_hbm   algorithmic-byte model of
+                         the whole path (per round: symbols + fingerprints read,
+                         rank written, one dictionary key per phrase, new slots
+                         and rules) over the step time, against 8 TB/s
+  roofline               the dominant kernel, its algorithmic bytes per launch
+                         over its mean launch time (HIP events recorded by the
+                         library on the stream its kernels run on)
+  cpu_baseline           the CPU oracle (single-threaded) on a bounded sample
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "input GB/s of LCG build+merge at 1 GPU (batched vs plain), % HBM peak; p50/p99"
+WORKLOADS = {
+    "bacterial": "bacterial-like collection: 64 strings of ~5 MB (~320 MB) from 4 random 5 Mbp "
+                 "bases, 1% subs, 0.1% indels, 0.5% inserted 1-20 kb segments, 0.01% N",
+    "batched": "2,000 strings, lognormal lengths (median 2 MB, clipped 50 KB-12 MB, ~5 GB) from "
+               "32 bases at 0.5-2% divergence",
+    "repeats": "8 strings of 250 MB from one base with 5% tandem repeats and homopolymer runs",
+    "tiny": "8 strings of 128 KiB, mutated copies of one base",
+}
+# per-phase algorithmic bytes (per round i with n_i symbols, d_i phrases, u_i new
+# rules, Q_i new rhs symbols; s_i = 1 byte at round 1, else 4; f = 4-byte fingerprint)
+PHASES = ("classify", "emit", "insert", "rank", "commit", "segments")
+
+
+def phase_alg_bytes(st):
+    """dict phase -> algorithmic bytes summed over rounds (stats rows of one build)."""
+    out = {p: 0.0 for p in PHASES}
+    for i, row in enumerate(st, start=1):
+        n, d, u, q = (float(x) for x in row[:4])
+        s = 1.0 if i == 1 else 4.0
+        f = 0.0 if i == 1 else 4.0
+        out["classify"] += n * (s if i == 1 else f)   # the order test reads each fingerprint once
+        out["emit"] += n * (s + f) + d * 4.0           # phrase contents + fingerprints in, F of T^{i+1} out
+        out["insert"] += d * 8.0 + u * 16.0            # one 8-byte key per phrase, one slot per new rule
+        out["rank"] += d * 0.125                       # one first-occurrence bit per phrase
+        out["commit"] += d * 4.0 + u * 8.0 + q * s     # rank per phrase, new rule offset + F, new rhs
+        out["segments"] += 0.0
+    return out
+
+
+def path_alg_bytes(st):
+    """Algorithmic bytes of the whole path (per round: read symbols, read fingerprints,
+    write rank, one dictionary probe per phrase, new slot/rank/F per rule, new rhs)."""
+    tot = 0.0
+    for i, row in enumerate(st, start=1):
+        n, d, u, q = (float(x) for x in row[:4])
+        s = 1.0 if i == 1 else 4.0
+        tot += n * s + (n * 4.0 if i >= 2 else 0.0) + d * (4 + 8) + u * (8 + 4 + 4) + q * s
+    return tot
+
+
+def cpu_baseline(text, off, seed, n_strings):
+    from oracle import oracle as O
+    k = min(n_strings, len(off) - 1)
+    t_sub = text[:off[k]]
+    o_sub = off[:k + 1]
+    t0 = time.perf_counter()
+    g = O.build(t_sub, o_sub, seed)
+    dt = time.perf_counter() - t0
+    del g
+    nb = int(o_sub[-1])
+    return {"value": nb / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of %d strings (%d bytes), one thread, build of the sample; "
+                      "%.1f s" % (k, len(off) - 1, nb, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="bacterial", choices=sorted(WORKLOADS))
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--cpu-strings", type=int, default=4, help="strings in the oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the collection would be split across GPUs by whole strings and the per-GPU "
+              "grammars merged; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2411_12439_amd import datagen, lcg
+
+    seed = datagen.HASH_SEED
+    text, off = datagen.make_config(args.config, scale=args.scale)
+    n = int(off[-1])
+    k = len(off) - 1
+    t, o = lcg.to_device(text, off)
+    torch.cuda.synchronize()
+    print("[bench] %s: %d strings, %d bytes on device" % (args.config, k, n), file=sys.stderr,
+          flush=True)
+
+    for i in range(args.warmup):
+        g = lcg.build(t, o, seed=seed, flags=lcg.FLAG_TIMING)
+        g.free()
+        print("[bench] warmup %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+
+    step_s = []
+    phase_ns = {p: 0.0 for p in PHASES}
+    launches = 0
+    stats = None
+    t_all = time.perf_counter()
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = lcg.build(t, o, seed=seed, flags=lcg.FLAG_TIMING)
+        torch.cuda.synchronize()
+        step_s.append(time.perf_counter() - t0)
+        st = g.stats()
+        stats = st
+        for j, p in enumerate(PHASES):
+            phase_ns[p] += float(st[:, 9 + j].sum())
+        launches += st.shape[0]
+        g.free()
+        print("[bench] step %d: %.2f ms" % (i, step_s[-1] * 1e3), file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t_all
+    torch.cuda.synchronize()
+
+    step_s = np.array(step_s)
+    gbps = n / step_s / 1e9
+    value = n * args.steps / step_s.sum() / 1e9
+    alg = path_alg_bytes(stats)
+    alg_gbps = alg / step_s.mean() / 1e9
+
+    # dominant kernel and its roofline
+    dom = max(PHASES, key=lambda p: phase_ns[p])
+    per_alg = phase_alg_bytes(stats)
+    dom_ns_per_step = phase_ns[dom] / args.steps
+    achieved = per_alg[dom] / (dom_ns_per_step * 1e-9) / 1e9 if dom_ns_per_step else 0.0
+    rounds = stats.shape[0]
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                "kernel": dom, "launches_per_step": rounds,
+                "mean_launch_us": round(dom_ns_per_step / rounds / 1e3, 2),
+                "alg_bytes_per_launch": round(per_alg[dom] / rounds, 1),
+                "phase_ms_per_step": {p: round(phase_ns[p] / args.steps / 1e6, 3) for p in PHASES}}
+
+    out = {"metric": METRIC, "value": round(value, 4), "unit": "GB/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(float(step_s.mean()) * 1e3, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": WORKLOADS[args.config], "name": args.config, "scale": args.scale,
+                      "strings": k, "bytes": n, "form": "batched", "hash_seed": seed,
+                      "data_seed": datagen.CONFIG_SEEDS[args.config], "rounds": rounds},
+           "p50_gbps": round(float(np.percentile(gbps, 50)), 4),
+           "p99_gbps": round(float(np.percentile(gbps, 1)), 4),
+           "alg_bytes_per_input_byte": round(alg / n, 3),
+           "alg_gbps": round(alg_gbps, 2),
+           "alg_frac_hbm": round(alg_gbps / HBM_PEAK_GBPS, 4),
+           "timed_wall_s": round(wall, 3),
+           "roofline": roofline}
+
+    if not args.no_plain:
+        g = lcg.build(t, o, seed=seed, mode=lcg.MODE_PLAIN)
+        g.free()
+        ps = []
+        for i in range(max(1, args.plain_steps)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g = lcg.build(t, o, seed=seed, mode=lcg.MODE_PLAIN)
+            torch.cuda.synchronize()
+            ps.append(time.perf_counter() - t0)
+            g.free()
+            print("[bench] plain step %d: %.2f ms" % (i, ps[-1] * 1e3), file=sys.stderr, flush=True)
+        plain = n / float(np.mean(ps)) / 1e9
+        out["plain_gbps"] = round(plain, 4)
+        out["batched_vs_plain"] = round(value / plain, 2)
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(text, off, seed, args.cpu_strings)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

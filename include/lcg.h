@@ -143,13 +143,16 @@ lcg_status lcg_c_copy(lcg_grammar_t g, uint8_t* h_level, uint32_t* h_sym);
 
 /*
  * Per-round statistics of the builds that produced g, LCG_STATS_FIELDS
- * uint64 per round: total active length n_i, phrases d_i, new rules u_i, new
- * right-hand-side symbols Q_i, strings still active, dictionary probes (sum
- * over phrases), full right-hand-side comparisons, dictionary capacity,
- * device time in nanoseconds (0 without LCG_FLAG_TIMING).  Rounds of later
- * builds (lcg_build_into, plain-mode per-string builds) are appended.
+ * uint64 per round, in this order: total active length n_i, phrases d_i, new
+ * rules u_i, new right-hand-side symbols Q_i, strings still active after the
+ * round, dictionary probes, full right-hand-side comparisons, dictionary
+ * capacity, then device nanoseconds (0 without LCG_FLAG_TIMING) of the round's
+ * kernels (sum of the following), of classify + tile scan, of emit, of
+ * insert, of rank (new flags + scans), of commit, and of the segment update.
+ * Rounds of later builds (lcg_build_into, the per-string builds of the plain
+ * form) are appended.
  */
-#define LCG_STATS_FIELDS 9
+#define LCG_STATS_FIELDS 15
 lcg_status lcg_stats(lcg_grammar_t g, uint64_t* h_out, uint32_t cap_rounds, uint32_t* n_rounds);
 /* Reset the statistics of g. */
 lcg_status lcg_stats_clear(lcg_grammar_t g);

@@ -20,8 +20,9 @@ struct Counters {
   unsigned long long won;       // slots claimed in the running insert
   unsigned long long probes;    // slots inspected
   unsigned long long compares;  // full right-hand-side comparisons
-  unsigned int overflow;        // a probe sequence hit the limit or the table passed its load cap
+  unsigned int overflow;        // phrases whose probe sequence ran out of budget
   unsigned int active;          // strings still longer than one symbol
+  unsigned long long active_len;  // their total length
   unsigned int hll[kHll];       // HyperLogLog registers of the round's phrase keys
 };
 

@@ -208,9 +208,9 @@ __global__ __launch_bounds__(kBlock) void k_classify(RoundIn in, uint64_t* __res
     }
     uint32_t j = seg_search(in.off, s_seg[0], s_seg[1], b);
     uint64_t s_start = in.off[j], s_end = in.off[j + 1];
-    for (int x = 0; x < kItems; ++x) {
+    const int xe = in.n - b < (uint64_t)kItems ? (int)(in.n - b) : kItems;
+    for (int x = 0; x < xe; ++x) {
       const uint64_t l = b + x;
-      if (l >= in.n) break;
       while (l >= s_end) {
         ++j;
         s_start = in.off[j];
@@ -390,10 +390,10 @@ void scan_exclusive(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* tmp
 
 // ------------------------------------------------------------------ insert
 template <typename Sym>
-__device__ __forceinline__ bool same_seq(const Sym* a, const Sym* b, uint32_t len) {
-  for (uint32_t i = 0; i < len; ++i)
-    if (a[i] != b[i]) return false;
-  return true;
+__device__ __noinline__ bool same_seq(const Sym* a, const Sym* b, uint32_t len) {
+  uint32_t diff = 0;
+  for (uint32_t i = 0; i < len && diff == 0; ++i) diff = a[i] != b[i];
+  return diff == 0;
 }
 
 // Insert-or-find every phrase.  A claimed slot keeps the claimer's key; a
@@ -423,55 +423,56 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t d, const uint64_t* __re
     }
     uint64_t pos = mix64(kk) & mask;
     uint32_t result = kNone;
-    for (uint32_t probe = 0; probe < kMaxProbe; ++probe) {
+    // single-exit probe loop: a slot is taken (claimed or matched) or the
+    // probe budget runs out
+    for (uint32_t probe = 0; probe < kMaxProbe && result == kNone; ++probe) {
       Slot* sl = &table[pos];
       ++probes;
       uint64_t w = __hip_atomic_load(&sl->w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      bool hit = false;
       if (w == kEmpty) {
         unsigned long long prev =
             atomicCAS(reinterpret_cast<unsigned long long*>(&sl->w0), (unsigned long long)kEmpty,
                       (unsigned long long)want);
         if (prev == kEmpty) {
-          result = (uint32_t)pos;
+          hit = true;
           won = 1;
-          break;
-        }
-        w = prev;
-      }
-      if (!is_long) {
-        if (w == kk) {
-          result = (uint32_t)pos;
-          break;
-        }
-      } else if ((w & kHiMask) == kk) {
-        const uint32_t rk = __hip_atomic_load(&sl->rank, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t ref = (uint32_t)w;
-        // a committed rule is compared with its stored right-hand side, a slot
-        // claimed in this pass with the claiming occurrence; anything else (a
-        // slot left by an interrupted call) cannot match
-        const bool committed = rk != kNone && rk < u_committed;
-        const bool inflight = rk == kNone && ref < d;
-        uint64_t opos = 0;
-        uint32_t olen = 0xFFFFFFFFu;
-        const Sym* arr = content;
-        if (committed) {
-          opos = rule_off[rk];
-          olen = (uint32_t)(rule_off[rk + 1] - opos);
-          arr = rule_rhs;
-        } else if (inflight) {
-          opos = pstart[ref];
-          olen = plen[ref];
-        }
-        ++cmps;
-        if (olen == my_len && same_seq<Sym>(content + my_pos, arr + opos, my_len)) {
-          result = (uint32_t)pos;
-          break;
+        } else {
+          w = prev;
         }
       }
-      pos = (pos + 1) & mask;
+      if (!hit) {
+        if (!is_long) {
+          hit = w == kk;
+        } else if ((w & kHiMask) == kk) {
+          const uint32_t rk =
+              __hip_atomic_load(&sl->rank, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const uint32_t ref = (uint32_t)w;
+          // a committed rule is compared with its stored right-hand side, a
+          // slot claimed in this pass with the claiming occurrence; anything
+          // else (a slot left by an interrupted call) cannot match
+          const bool committed = rk != kNone && rk < u_committed;
+          const bool inflight = rk == kNone && ref < d;
+          uint64_t opos = 0;
+          uint32_t olen = 0xFFFFFFFFu;
+          const Sym* arr = content;
+          if (committed) {
+            opos = rule_off[rk];
+            olen = (uint32_t)(rule_off[rk + 1] - opos);
+            arr = rule_rhs;
+          } else if (inflight) {
+            opos = pstart[ref];
+            olen = plen[ref];
+          }
+          ++cmps;
+          hit = olen == my_len && same_seq<Sym>(content + my_pos, arr + opos, my_len);
+        }
+      }
+      if (hit) result = (uint32_t)pos;
+      else pos = (pos + 1) & mask;
     }
     if (result == kNone) {
-      atomicOr(&ctr->overflow, 1u);
+      atomicAdd(&ctr->overflow, 1u);
     } else {
       Slot* sl = &table[result];
       if (__hip_atomic_load(&sl->rank, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == kNone &&
@@ -620,15 +621,12 @@ __global__ void k_rehash(const Slot* __restrict__ old_t, uint64_t old_cap, Slot*
     if (sl.w0 == kEmpty || sl.rank == kNone) continue;
     uint64_t pos = mix64(probe_key(sl.w0)) & mask;
     bool done = false;
-    for (uint64_t t = 0; t <= mask; ++t) {
+    for (uint64_t t = 0; t <= mask && !done; ++t) {
       unsigned long long prev = atomicCAS(reinterpret_cast<unsigned long long*>(&new_t[pos].w0),
                                           (unsigned long long)kEmpty, (unsigned long long)sl.w0);
-      if (prev == kEmpty) {
-        new_t[pos].rank = sl.rank;
-        done = true;
-        break;
-      }
-      pos = (pos + 1) & mask;
+      done = prev == kEmpty;
+      if (done) new_t[pos].rank = sl.rank;
+      else pos = (pos + 1) & mask;
     }
     if (!done) atomicOr(&ctr->overflow, 1u);
   }
@@ -692,7 +690,7 @@ __global__ void k_finish(const uint64_t* __restrict__ off, const uint64_t* __res
                          uint8_t* __restrict__ c_level, uint32_t* __restrict__ c_sym,
                          Counters* __restrict__ ctr) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long act = 0;
+  unsigned long long act = 0, act_len = 0;
   if (j < k) {
     const uint64_t lo = off[j + 1] - off[j];
     const uint64_t ln = new_off[j + 1] - new_off[j];
@@ -701,9 +699,14 @@ __global__ void k_finish(const uint64_t* __restrict__ off, const uint64_t* __res
       c_sym[j] = sym_next[new_off[j]];
     }
     act = ln >= 2;
+    act_len = ln >= 2 ? ln : 0;
   }
   act = wave_sum(act);
-  if ((threadIdx.x & 63) == 0 && act) atomicAdd(&ctr->active, (unsigned int)act);
+  act_len = wave_sum(act_len);
+  if ((threadIdx.x & 63) == 0 && act) {
+    atomicAdd(&ctr->active, (unsigned int)act);
+    atomicAdd(&ctr->active_len, act_len);
+  }
 }
 
 void launch_finish(const uint64_t* off, const uint64_t* new_off, uint32_t k,

@@ -9,6 +9,7 @@
 #include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -281,6 +282,44 @@ struct Work {
 
 static void zero_counters(Counters* c, hipStream_t s) { launch_zero(c, sizeof(Counters), s); }
 
+// LCG_DEBUG=1 in the environment traces the per-round planning on stderr.
+static bool debug_on() {
+  static const bool on = [] {
+    const char* e = std::getenv("LCG_DEBUG");
+    return e && *e && *e != '0';
+  }();
+  return on;
+}
+
+// HIP events at the phase boundaries of one round (LCG_FLAG_TIMING):
+// 0 start, 1 classified and counted, 2 emit start, 8 emitted, 3 dictionary
+// sized, 4 inserted, 5 ranked, 6 committed, 7 segments done.  The host reads
+// between phases 1 and 2 and between 8 and 3 are not counted.
+struct PhaseEvents {
+  static constexpr int N = 9;
+  hipEvent_t e[N] = {};
+  bool on;
+  explicit PhaseEvents(bool enable) : on(enable) {
+    if (on)
+      for (auto& x : e) HIP_CHECK(hipEventCreate(&x));
+  }
+  PhaseEvents(const PhaseEvents&) = delete;
+  PhaseEvents& operator=(const PhaseEvents&) = delete;
+  ~PhaseEvents() {
+    for (auto x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+  void rec(int i, hipStream_t s) {
+    if (on) HIP_CHECK(hipEventRecord(e[i], s));
+  }
+  uint64_t ns(int a, int b) {
+    if (!on) return 0;
+    float ms = 0;
+    HIP_CHECK(hipEventElapsedTime(&ms, e[a], e[b]));
+    return (uint64_t)((double)ms * 1e6);
+  }
+};
+
 // Make room in level L's dictionary for `need` committed + new keys at load <= 1/2.
 static void ensure_table(Level& L, uint64_t need, uint32_t min_log2, Work& w, hipStream_t s,
                          bool force_grow = false) {
@@ -321,7 +360,7 @@ struct DedupResult {
 // land in sym_next.  Regrows the dictionary and retries on overflow.
 static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const void* content,
                                 const uint32_t* fnew, uint32_t* sym_next, uint64_t est_new,
-                                const Opts& o, Work& w, hipStream_t s) {
+                                const Opts& o, Work& w, hipStream_t s, PhaseEvents* pe = nullptr) {
   Level& L = g->levels[lv - 1];
   const bool bytes = lv == 1;
   ensure_table(L, (uint64_t)L.u + est_new, o.table_min_log2, w, s);
@@ -337,13 +376,20 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
   for (int attempt = 0;; ++attempt) {
     zero_counters(w.ctr.p, s);
     const void* rule_rhs = bytes ? (const void*)L.rhs8.p : (const void*)L.rhs32.p;
+    if (pe) pe->rec(3, s);
     launch_insert(bytes, d, w.key.p, w.pstart.p, w.plen.p, content, L.off.p, rule_rhs, L.u,
                   L.table.p, L.tcap - 1, w.slot_idx.p, w.ctr.p, s);
+    if (pe) pe->rec(4, s);
     launch_newflags(d, w.slot_idx.p, L.table.p, w.plen.p, w.newbits.p, w.wcnt.p, w.wlen.p, s);
     scan_exclusive(w.wcnt.p, w.wcnt_base.p, W, w.scan_tmp.p, s);
     scan_exclusive(w.wlen.p, w.wlen_base.p, W, w.scan_tmp.p, s);
+    if (pe) pe->rec(5, s);
     HIP_CHECK(hipMemcpyAsync(&hc, w.ctr.p, offsetof(Counters, hll), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
+    if (debug_on())
+      std::fprintf(stderr, "[lcg] level %u attempt %d: d=%llu est=%llu cap=%llu won=%llu probes=%llu cmp=%llu overflow=%u\n",
+                   lv, attempt, (unsigned long long)d, (unsigned long long)est_new,
+                   (unsigned long long)L.tcap, hc.won, hc.probes, hc.compares, hc.overflow);
     if (!hc.overflow) break;
     if (attempt >= 6) throw LcgError{LCG_ETABLE, "dictionary overflow persists after regrowth"};
     ensure_table(L, (uint64_t)L.u + std::max<uint64_t>(est_new, hc.won), o.table_min_log2, w, s,
@@ -364,6 +410,7 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
   }
   launch_commit(bytes, d, w.slot_idx.p, L.table.p, w.newbits.p, w.wcnt_base.p, w.wlen_base.p,
                 w.pstart.p, w.plen.p, content, fnew, L.u, L.q, L.off.p, rule_rhs, L.fp.p, sym_next, s);
+  if (pe) pe->rec(6, s);
   L.u += (uint32_t)u_new;
   L.q += q_new;
   return DedupResult{(uint32_t)u_new, q_new, hc.probes, hc.compares};
@@ -379,7 +426,12 @@ static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_
   launch_c_init(d_text, d_off, k, g->c_level.p + c_base, g->c_sym.p + c_base, s);
   g->k += k;
   uint32_t active = 0;
-  for (uint32_t j = 0; j < k; ++j) active += (h_off[j + 1] - h_off[j]) >= 2;
+  uint64_t active_len = 0;  // total length of the strings longer than one symbol
+  for (uint32_t j = 0; j < k; ++j) {
+    const uint64_t len = h_off[j + 1] - h_off[j];
+    active += len >= 2;
+    active_len += len >= 2 ? len : 0;
+  }
   if (!active) {
     HIP_CHECK(hipStreamSynchronize(s));
     return;
@@ -390,79 +442,71 @@ static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_
   const uint64_t* cur_off = d_off;
   uint64_t n_i = n;
   int cur = 0;  // ping-pong index of T^{i+1}
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  const bool timing = (o.flags & LCG_FLAG_TIMING) != 0;
-  if (timing) {
-    HIP_CHECK(hipEventCreate(&ev0));
-    HIP_CHECK(hipEventCreate(&ev1));
+  PhaseEvents pe((o.flags & LCG_FLAG_TIMING) != 0);
+  for (uint32_t lv = 1;; ++lv) {
+    if (lv >= (uint32_t)HashFamily::kLevels) throw LcgError{LCG_EOVERFLOW, "more than 63 rounds"};
+    ensure_level(g, lv, s);
+    pe.rec(0, s);
+    const bool bytes = lv == 1;
+    RoundIn in;
+    in.sym = bytes ? (const void*)d_text : (const void*)w.sym[cur ^ 1].p;
+    in.fp = bytes ? nullptr : w.fpv[cur ^ 1].p;
+    in.lut = w.lut.p;
+    in.off = cur_off;
+    in.k = k;
+    in.n = n_i;
+    in.bytes = bytes;
+    const uint64_t tiles = (n_i + kTile - 1) / kTile;
+    w.bits.need(tiles * kTileWords);
+    w.tile_cnt.need(tiles);
+    w.tile_base.need(tiles + 1);
+    w.scan_tmp.need(std::max<size_t>(scan_tmp_words(tiles), 1));
+    launch_classify(in, w.bits.p, w.tile_cnt.p, s);
+    scan_exclusive(w.tile_cnt.p, w.tile_base.p, tiles, w.scan_tmp.p, s);
+    pe.rec(1, s);
+    const uint64_t d = read_dev(w.tile_base.p + tiles, s);
+    if (d == 0) throw LcgError{LCG_EINVAL, "internal: active strings produced no phrase"};
+    if (d >= kNone) throw LcgError{LCG_EOVERFLOW, "a round has 2^32 phrases"};
+    w.pstart.need(d);
+    w.plen.need(d);
+    w.key.need(d);
+    w.sym[cur].need(d);
+    w.fpv[cur].need(d);
+    w.off[cur].need(k + 1);
+    zero_counters(w.ctr.p, s);
+    pe.rec(2, s);
+    launch_emit(in, w.bits.p, w.tile_base.p, g->H.lv[lv], o.key_bits, w.pstart.p, w.plen.p,
+                w.key.p, w.fpv[cur].p, w.ctr.p, s);
+    pe.rec(8, s);
+    std::vector<unsigned int> regs(kHll);
+    HIP_CHECK(hipMemcpyAsync(regs.data(), w.ctr.p->hll, sizeof(unsigned int) * kHll,
+                             hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    const uint64_t t_classify = pe.ns(0, 1), t_emit = pe.ns(2, 8);
+    const uint64_t est = std::min<uint64_t>(d, (uint64_t)(hll_estimate(regs.data()) * 1.25) + 64);
+    const void* content = bytes ? (const void*)d_text : (const void*)w.sym[cur ^ 1].p;
+    DedupResult r = dedup_commit(g, lv, d, content, w.fpv[cur].p, w.sym[cur].p, est, o, w, s, &pe);
+    zero_counters(w.ctr.p, s);
+    launch_segments(cur_off, k, w.pstart.p, d, w.off[cur].p, s);
+    launch_finish(cur_off, w.off[cur].p, k, w.sym[cur].p, lv, g->c_level.p + c_base,
+                  g->c_sym.p + c_base, w.ctr.p, s);
+    pe.rec(7, s);
+    Counters hc;
+    HIP_CHECK(hipMemcpyAsync(&hc, w.ctr.p, offsetof(Counters, hll), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    active = hc.active;
+    const uint64_t t_insert = pe.ns(3, 4), t_rank = pe.ns(4, 5), t_commit = pe.ns(5, 6),
+                   t_seg = pe.ns(6, 7);
+    g->stats.push_back(Stat{active_len, d, r.u_new, r.q_new, active, r.probes, r.compares,
+                            g->levels[lv - 1].tcap,
+                            t_classify + t_emit + t_insert + t_rank + t_commit + t_seg, t_classify,
+                            t_emit, t_insert, t_rank, t_commit, t_seg});
+    active_len = hc.active_len;
+    if (!active) break;
+    cur_off = w.off[cur].p;
+    n_i = d;
+    cur ^= 1;
   }
-  try {
-    for (uint32_t lv = 1;; ++lv) {
-      if (lv >= (uint32_t)HashFamily::kLevels) throw LcgError{LCG_EOVERFLOW, "more than 63 rounds"};
-      ensure_level(g, lv, s);
-      if (timing) HIP_CHECK(hipEventRecord(ev0, s));
-      const bool bytes = lv == 1;
-      RoundIn in;
-      in.sym = bytes ? (const void*)d_text : (const void*)w.sym[cur ^ 1].p;
-      in.fp = bytes ? nullptr : w.fpv[cur ^ 1].p;
-      in.lut = w.lut.p;
-      in.off = cur_off;
-      in.k = k;
-      in.n = n_i;
-      in.bytes = bytes;
-      const uint64_t tiles = (n_i + kTile - 1) / kTile;
-      w.bits.need(tiles * kTileWords);
-      w.tile_cnt.need(tiles);
-      w.tile_base.need(tiles + 1);
-      w.scan_tmp.need(std::max<size_t>(scan_tmp_words(tiles), 1));
-      launch_classify(in, w.bits.p, w.tile_cnt.p, s);
-      scan_exclusive(w.tile_cnt.p, w.tile_base.p, tiles, w.scan_tmp.p, s);
-      const uint64_t d = read_dev(w.tile_base.p + tiles, s);
-      if (d == 0) throw LcgError{LCG_EINVAL, "internal: active strings produced no phrase"};
-      if (d >= kNone) throw LcgError{LCG_EOVERFLOW, "a round has 2^32 phrases"};
-      w.pstart.need(d);
-      w.plen.need(d);
-      w.key.need(d);
-      w.sym[cur].need(d);
-      w.fpv[cur].need(d);
-      w.off[cur].need(k + 1);
-      zero_counters(w.ctr.p, s);
-      launch_emit(in, w.bits.p, w.tile_base.p, g->H.lv[lv], o.key_bits, w.pstart.p, w.plen.p,
-                  w.key.p, w.fpv[cur].p, w.ctr.p, s);
-      std::vector<unsigned int> regs(kHll);
-      HIP_CHECK(hipMemcpyAsync(regs.data(), w.ctr.p->hll, sizeof(unsigned int) * kHll,
-                               hipMemcpyDeviceToHost, s));
-      HIP_CHECK(hipStreamSynchronize(s));
-      const uint64_t est = std::min<uint64_t>(d, (uint64_t)(hll_estimate(regs.data()) * 1.25) + 64);
-      const void* content = bytes ? (const void*)d_text : (const void*)w.sym[cur ^ 1].p;
-      DedupResult r = dedup_commit(g, lv, d, content, w.fpv[cur].p, w.sym[cur].p, est, o, w, s);
-      zero_counters(w.ctr.p, s);
-      launch_segments(cur_off, k, w.pstart.p, d, w.off[cur].p, s);
-      launch_finish(cur_off, w.off[cur].p, k, w.sym[cur].p, lv, g->c_level.p + c_base,
-                    g->c_sym.p + c_base, w.ctr.p, s);
-      active = read_dev(&w.ctr.p->active, s);
-      uint64_t ns = 0;
-      if (timing) {
-        HIP_CHECK(hipEventRecord(ev1, s));
-        HIP_CHECK(hipEventSynchronize(ev1));
-        float ms = 0;
-        HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
-        ns = (uint64_t)(ms * 1e6);
-      }
-      g->stats.push_back(Stat{n_i, d, r.u_new, r.q_new, active, r.probes, r.compares,
-                              g->levels[lv - 1].tcap, ns});
-      if (!active) break;
-      cur_off = w.off[cur].p;
-      n_i = d;
-      cur ^= 1;
-    }
-  } catch (...) {
-    if (ev0) (void)hipEventDestroy(ev0);
-    if (ev1) (void)hipEventDestroy(ev1);
-    throw;
-  }
-  if (ev0) (void)hipEventDestroy(ev0);
-  if (ev1) (void)hipEventDestroy(ev1);
 }
 
 // MergeGrams(a, b): a absorbs b level by level (Sec. 3.6).
