@@ -100,6 +100,7 @@ def main():
     ap.add_argument("--cpu-strings", type=int, default=4, help="strings in the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--rounds", action="store_true", help="per-round phase table on stderr")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -145,6 +146,14 @@ def main():
         print("[bench] step %d: %.2f ms" % (i, step_s[-1] * 1e3), file=sys.stderr, flush=True)
     wall = time.perf_counter() - t_all
     torch.cuda.synchronize()
+    if args.rounds:
+        print("[bench] round      n        d        u     probes  cmp  ms: " + " ".join(PHASES),
+              file=sys.stderr)
+        for i, row in enumerate(stats, start=1):
+            print("[bench] %2d %10d %9d %8d %10d %5d  %s" % (
+                i, row[0], row[1], row[2], row[5], row[6],
+                " ".join("%7.3f" % (row[9 + j] / 1e6) for j in range(len(PHASES)))),
+                file=sys.stderr)
 
     step_s = np.array(step_s)
     gbps = n / step_s / 1e9

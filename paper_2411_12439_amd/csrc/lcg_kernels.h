@@ -14,6 +14,7 @@ constexpr int kTile = kBlock * kItems;      // positions per tile (4096)
 constexpr int kTileWords = kTile / 64;      // break-bit words per tile
 constexpr int kHllLog2 = 9;                 // HyperLogLog registers (512)
 constexpr int kHll = 1 << kHllLog2;
+constexpr unsigned kEmitBlocks = 2048;      // grid of the emit kernel (HLL partials: kEmitBlocks x kHll bytes)
 
 // Device counters of one round.
 struct Counters {
@@ -44,7 +45,7 @@ void launch_zero(void* p, size_t bytes, hipStream_t s);
 void launch_classify(const RoundIn& in, uint64_t* bits, uint64_t* tile_cnt, hipStream_t s);
 void launch_emit(const RoundIn& in, const uint64_t* bits, const uint64_t* tile_base, LevelHash h,
                  uint32_t key_bits, uint64_t* pstart, uint32_t* plen, uint64_t* key, uint32_t* fnew,
-                 Counters* ctr, hipStream_t s);
+                 uint8_t* hll_part, Counters* ctr, hipStream_t s);
 
 // Exclusive scan of n uint64 values into out[0..n]; out[n] receives the total.
 // tmp must hold scan_tmp_words(n) uint64.

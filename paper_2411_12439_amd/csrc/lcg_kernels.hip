@@ -30,6 +30,7 @@ namespace lcg {
   } while (0)
 
 constexpr uint32_t kMaxProbe = 1u << 14;
+constexpr unsigned kPersistentBlocks = 2048;  // grid of the grid-stride kernels (8 per CU)
 
 static inline unsigned grid_for(uint64_t n, int block) {
   uint64_t g = (n + block - 1) / block;
@@ -257,17 +258,82 @@ void launch_classify(const RoundIn& in, uint64_t* bits, uint64_t* tile_cnt, hipS
 }
 
 // ------------------------------------------------------------------ emit
+// Phrase-parallel within a tile: the block lists the tile's break positions in
+// LDS (block scan of the per-thread bit counts), stages the tile and a halo
+// of the input (bytes, or ranks and fingerprints) in LDS with wide loads,
+// then thread j handles the j-th phrase of the tile.  A phrase ends at the
+// next break or at the end of its string, whichever comes first; positions
+// past the halo are read from global memory.
+constexpr int kSegCache = 128;
+constexpr int kHalo = 512;
+constexpr int kStage = kTile + kHalo;
+
+template <bool BYTES>
+struct EmitStage;
+template <>
+struct EmitStage<true> {
+  uint8_t sym[kStage];
+};
+template <>
+struct EmitStage<false> {
+  uint32_t sym[kStage];
+  uint32_t fp[kStage];
+};
+
+template <bool BYTES>
+__device__ __forceinline__ void stage_tile(const RoundIn& in, uint64_t t0, EmitStage<BYTES>& st) {
+  const uint64_t lim = in.n - t0 < (uint64_t)kStage ? in.n - t0 : (uint64_t)kStage;
+  if constexpr (BYTES) {
+    const uint8_t* src = static_cast<const uint8_t*>(in.sym) + t0;
+    if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+      for (uint32_t i = threadIdx.x * 16; i < kStage; i += kBlock * 16) {
+        if (i + 16 <= lim) {
+          *reinterpret_cast<uint4*>(&st.sym[i]) = *reinterpret_cast<const uint4*>(src + i);
+        } else {
+          for (uint32_t x = i; x < i + 16 && x < lim; ++x) st.sym[x] = src[x];
+        }
+      }
+    } else {
+      for (uint32_t i = threadIdx.x; i < lim; i += kBlock) st.sym[i] = src[i];
+    }
+  } else {
+    const uint32_t* ss = static_cast<const uint32_t*>(in.sym) + t0;
+    const uint32_t* sf = in.fp + t0;
+    if (((reinterpret_cast<uintptr_t>(ss) | reinterpret_cast<uintptr_t>(sf)) & 15) == 0) {
+      for (uint32_t i = threadIdx.x * 4; i < kStage; i += kBlock * 4) {
+        if (i + 4 <= lim) {
+          *reinterpret_cast<uint4*>(&st.sym[i]) = *reinterpret_cast<const uint4*>(ss + i);
+          *reinterpret_cast<uint4*>(&st.fp[i]) = *reinterpret_cast<const uint4*>(sf + i);
+        } else {
+          for (uint32_t x = i; x < i + 4 && x < lim; ++x) {
+            st.sym[x] = ss[x];
+            st.fp[x] = sf[x];
+          }
+        }
+      }
+    } else {
+      for (uint32_t i = threadIdx.x; i < lim; i += kBlock) {
+        st.sym[i] = ss[i];
+        st.fp[i] = sf[i];
+      }
+    }
+  }
+}
+
 template <bool BYTES>
 __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in, const uint64_t* __restrict__ bits,
                                                  const uint64_t* __restrict__ tile_base, uint64_t tiles,
                                                  LevelHash h, uint32_t key_bits,
                                                  uint64_t* __restrict__ pstart, uint32_t* __restrict__ plen,
                                                  uint64_t* __restrict__ key, uint32_t* __restrict__ fnew,
-                                                 Counters* __restrict__ ctr) {
+                                                 uint8_t* __restrict__ hll_part) {
   __shared__ uint32_t s_lut[256];
+  __shared__ uint16_t s_start[kTile];
+  __shared__ uint64_t s_off[kSegCache + 1];
   __shared__ uint32_t s_seg[2];
   __shared__ uint32_t s_wave[kBlock / 64];
   __shared__ uint32_t s_hll[kHll];
+  __shared__ EmitStage<BYTES> st;
   if constexpr (BYTES) s_lut[threadIdx.x] = in.lut[threadIdx.x];
   for (int i = threadIdx.x; i < kHll; i += kBlock) s_hll[i] = 0;
   for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
@@ -279,27 +345,64 @@ __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in, const uint64_t* __r
       s_seg[0] = lo;
       s_seg[1] = seg_search(in.off, lo, in.k - 1, tl);
     }
-    const uint64_t b = t0 + (uint64_t)threadIdx.x * kItems;
+    stage_tile<BYTES>(in, t0, st);
     uint32_t mask = (uint32_t)(bits[tile * kTileWords + threadIdx.x / 4] >> ((threadIdx.x & 3) * 16)) &
                     0xFFFFu;
-    uint32_t excl = block_excl_scan<uint32_t>((uint32_t)__builtin_popcount(mask), s_wave, nullptr);
-    if (mask == 0) continue;
-    uint64_t o = tile_base[tile] + excl;
-    uint32_t j = seg_search(in.off, s_seg[0], s_seg[1], b);
-    uint64_t s_end = in.off[j + 1];
+    uint32_t c = 0;
+    uint32_t excl = block_excl_scan<uint32_t>((uint32_t)__builtin_popcount(mask), s_wave, &c);
     while (mask) {
       const int x = __builtin_ctz(mask);
       mask &= mask - 1;
-      const uint64_t l = b + x;
-      while (l >= s_end) s_end = in.off[++j + 1];
-      const uint64_t e = next_break(bits, l + 1, s_end);
+      s_start[excl++] = (uint16_t)(threadIdx.x * kItems + x);
+    }
+    const uint32_t slo = s_seg[0], shi = s_seg[1];
+    const bool cached = shi - slo + 2 <= kSegCache + 1;
+    if (cached)
+      for (uint32_t i = threadIdx.x; i < shi - slo + 2; i += kBlock) s_off[i] = in.off[slo + i];
+    __syncthreads();
+    const uint64_t base = tile_base[tile];
+    for (uint32_t jj = threadIdx.x; jj < c; jj += kBlock) {
+      const uint64_t l = t0 + s_start[jj];
+      uint64_t s_end;
+      if (slo == shi) {
+        s_end = cached ? s_off[1] : in.off[slo + 1];
+      } else if (cached) {
+        uint32_t lo = 0, hi = shi - slo;  // largest i with s_off[i] <= l
+        while (lo < hi) {
+          uint32_t mid = (lo + hi + 1) >> 1;
+          if (s_off[mid] <= l) lo = mid; else hi = mid - 1;
+        }
+        s_end = s_off[lo + 1];
+      } else {
+        s_end = in.off[seg_search(in.off, slo, shi, l) + 1];
+      }
+      uint64_t e = jj + 1 < c ? t0 + s_start[jj + 1] : next_break(bits, l + 1, s_end);
+      if (e > s_end) e = s_end;
+      const uint64_t q = e - l;
       // Eq. 4 by Horner's rule from the right: sum_j F[Q_j] c^(j-1)
       uint64_t S = 0;
-      for (uint64_t p = e; p-- > l;) S = addmod61(mulmod61(S, h.c), fval<BYTES>(in, s_lut, p));
+      const uint64_t e_st = e < t0 + kStage ? e : t0 + kStage;  // staged part [l, e_st)
+      for (uint64_t p = e; p > e_st;) {
+        --p;
+        S = addmod61(mulmod61(S, h.c), fval<BYTES>(in, s_lut, p));
+      }
+      for (uint64_t p = e_st; p > l;) {
+        --p;
+        uint32_t f;
+        if constexpr (BYTES) f = s_lut[st.sym[p - t0]];
+        else f = st.fp[p - t0];
+        S = addmod61(mulmod61(S, h.c), f);
+      }
       const uint64_t P = addmod61(mulmod61(h.a, S), h.b);
-      const uint64_t kk = make_key<BYTES>(in.sym, l, e - l, P, key_bits);
+      uint64_t kk;
+      if (e <= t0 + kStage) {
+        kk = make_key<BYTES>(st.sym, l - t0, q, P, key_bits);
+      } else {
+        kk = make_key<BYTES>(in.sym, l, q, P, key_bits);
+      }
+      const uint64_t o = base + jj;
       pstart[o] = l;
-      plen[o] = (uint32_t)(e - l);
+      plen[o] = (uint32_t)q;
       key[o] = kk;
       fnew[o] = (uint32_t)(P & 0xFFFFFFFFULL);
       const uint64_t hh = mix64(probe_key(kk));
@@ -307,28 +410,39 @@ __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in, const uint64_t* __r
       const uint64_t rest = hh << kHllLog2;
       const uint32_t rho = rest ? (uint32_t)__builtin_clzll(rest) + 1 : 64 - kHllLog2 + 1;
       atomicMax(&s_hll[idx], rho);
-      ++o;
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kHll; i += kBlock) {
-    uint32_t v = s_hll[i];
-    if (v && ctr->hll[i] < v) atomicMax(&ctr->hll[i], v);
+  for (int i = threadIdx.x; i < kHll; i += kBlock)
+    hll_part[(uint64_t)blockIdx.x * kHll + i] = (uint8_t)s_hll[i];
+}
+
+// register-wise maximum of the per-block HyperLogLog sketches
+__global__ void k_hll_reduce(const uint8_t* __restrict__ part, unsigned blocks,
+                             Counters* __restrict__ ctr) {
+  const int i = threadIdx.x;
+  uint32_t m = 0;
+  for (unsigned b = 0; b < blocks; ++b) {
+    uint32_t v = part[(uint64_t)b * kHll + i];
+    m = v > m ? v : m;
   }
+  ctr->hll[i] = m;
 }
 
 void launch_emit(const RoundIn& in, const uint64_t* bits, const uint64_t* tile_base, LevelHash h,
                  uint32_t key_bits, uint64_t* pstart, uint32_t* plen, uint64_t* key, uint32_t* fnew,
-                 Counters* ctr, hipStream_t s) {
+                 uint8_t* hll_part, Counters* ctr, hipStream_t s) {
   uint64_t tiles = grid_for(in.n, kTile);
-  unsigned g = tiles > 2048 ? 2048 : (unsigned)tiles;
+  unsigned g = tiles > kEmitBlocks ? kEmitBlocks : (unsigned)tiles;
   if (in.bytes)
     k_emit<true><<<g, kBlock, 0, s>>>(in, bits, tile_base, tiles, h, key_bits, pstart, plen, key,
-                                      fnew, ctr);
+                                      fnew, hll_part);
   else
     k_emit<false><<<g, kBlock, 0, s>>>(in, bits, tile_base, tiles, h, key_bits, pstart, plen, key,
-                                       fnew, ctr);
+                                       fnew, hll_part);
   LCG_LAUNCH_CHECK("emit");
+  k_hll_reduce<<<1, kHll, 0, s>>>(hll_part, g, ctr);
+  LCG_LAUNCH_CHECK("hll_reduce");
 }
 
 // ------------------------------------------------------------------ scan
@@ -389,16 +503,24 @@ void scan_exclusive(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* tmp
 }
 
 // ------------------------------------------------------------------ insert
+// Equality of two symbol sequences of length len, without an early exit and
+// without a call (both forms of the probe loop around it were compiled into
+// code that lost the probe result).
 template <typename Sym>
-__device__ __noinline__ bool same_seq(const Sym* a, const Sym* b, uint32_t len) {
+__device__ __forceinline__ bool same_seq(const Sym* a, const Sym* b, uint32_t len) {
   uint32_t diff = 0;
-  for (uint32_t i = 0; i < len && diff == 0; ++i) diff = a[i] != b[i];
+  for (uint32_t i = 0; i < len; ++i) diff |= (uint32_t)(a[i] != b[i]);
   return diff == 0;
 }
 
 // Insert-or-find every phrase.  A claimed slot keeps the claimer's key; a
 // long phrase whose 31 key bits match is compared symbol by symbol against
 // the slot's phrase (the claiming occurrence, or the committed rule).
+//
+// The claimed word of a slot never changes during the kernel, so it is read
+// with a plain (L1-cacheable) load: frequent short phrases are then served by
+// each CU's L1 instead of one L2 line.  A stale empty word only sends the
+// thread to the compare-and-swap, which returns the current value.
 template <typename Sym>
 __global__ __launch_bounds__(256) void k_insert(uint64_t d, const uint64_t* __restrict__ key,
                                                 const uint64_t* __restrict__ pstart,
@@ -409,9 +531,12 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t d, const uint64_t* __re
                                                 Slot* table, uint64_t mask,
                                                 uint32_t* __restrict__ slot_idx,
                                                 Counters* __restrict__ ctr) {
-  const uint64_t o = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  unsigned long long won = 0, probes = 0, cmps = 0;
-  if (o < d) {
+  __shared__ unsigned long long s_sum[4];
+  if (threadIdx.x < 4) s_sum[threadIdx.x] = 0;
+  __syncthreads();
+  unsigned long long won = 0, probes = 0, cmps = 0, fails = 0;
+  for (uint64_t o = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; o < d;
+       o += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t kk = key[o];
     const bool is_long = (kk & kLongTag) != 0;
     const uint64_t want = is_long ? (kk | o) : kk;
@@ -428,7 +553,7 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t d, const uint64_t* __re
     for (uint32_t probe = 0; probe < kMaxProbe && result == kNone; ++probe) {
       Slot* sl = &table[pos];
       ++probes;
-      uint64_t w = __hip_atomic_load(&sl->w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      uint64_t w = sl->w0;
       bool hit = false;
       if (w == kEmpty) {
         unsigned long long prev =
@@ -436,7 +561,7 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t d, const uint64_t* __re
                       (unsigned long long)want);
         if (prev == kEmpty) {
           hit = true;
-          won = 1;
+          ++won;
         } else {
           w = prev;
         }
@@ -445,8 +570,7 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t d, const uint64_t* __re
         if (!is_long) {
           hit = w == kk;
         } else if ((w & kHiMask) == kk) {
-          const uint32_t rk =
-              __hip_atomic_load(&sl->rank, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const uint32_t rk = sl->rank;
           const uint32_t ref = (uint32_t)w;
           // a committed rule is compared with its stored right-hand side, a
           // slot claimed in this pass with the claiming occurrence; anything
@@ -472,22 +596,32 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t d, const uint64_t* __re
       else pos = (pos + 1) & mask;
     }
     if (result == kNone) {
-      atomicAdd(&ctr->overflow, 1u);
+      ++fails;
     } else {
       Slot* sl = &table[result];
-      if (__hip_atomic_load(&sl->rank, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == kNone &&
+      if (sl->rank == kNone &&
           __hip_atomic_load(&sl->minocc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > (uint32_t)o)
         atomicMin(&sl->minocc, (uint32_t)o);
     }
     slot_idx[o] = result;
   }
+  // one global atomic per block and counter
   won = wave_sum(won);
   probes = wave_sum(probes);
   cmps = wave_sum(cmps);
+  fails = wave_sum(fails);
   if ((threadIdx.x & 63) == 0) {
-    if (won) atomicAdd(&ctr->won, won);
-    if (probes) atomicAdd(&ctr->probes, probes);
-    if (cmps) atomicAdd(&ctr->compares, cmps);
+    atomicAdd(&s_sum[0], won);
+    atomicAdd(&s_sum[1], probes);
+    atomicAdd(&s_sum[2], cmps);
+    atomicAdd(&s_sum[3], fails);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_sum[0]) atomicAdd(&ctr->won, s_sum[0]);
+    if (s_sum[1]) atomicAdd(&ctr->probes, s_sum[1]);
+    if (s_sum[2]) atomicAdd(&ctr->compares, s_sum[2]);
+    if (s_sum[3]) atomicAdd(&ctr->overflow, (unsigned int)s_sum[3]);
   }
 }
 
@@ -496,12 +630,14 @@ void launch_insert(bool bytes, uint64_t d, const uint64_t* key, const uint64_t* 
                    const void* rule_rhs, uint32_t u_committed, Slot* table, uint64_t mask,
                    uint32_t* slot_idx, Counters* ctr, hipStream_t s) {
   if (!d) return;
+  unsigned g = grid_for(d, 256);
+  if (g > kPersistentBlocks) g = kPersistentBlocks;
   if (bytes)
-    k_insert<uint8_t><<<grid_for(d, 256), 256, 0, s>>>(
+    k_insert<uint8_t><<<g, 256, 0, s>>>(
         d, key, pstart, plen, static_cast<const uint8_t*>(content), rule_off,
         static_cast<const uint8_t*>(rule_rhs), u_committed, table, mask, slot_idx, ctr);
   else
-    k_insert<uint32_t><<<grid_for(d, 256), 256, 0, s>>>(
+    k_insert<uint32_t><<<g, 256, 0, s>>>(
         d, key, pstart, plen, static_cast<const uint32_t*>(content), rule_off,
         static_cast<const uint32_t*>(rule_rhs), u_committed, table, mask, slot_idx, ctr);
   LCG_LAUNCH_CHECK("insert");

@@ -112,6 +112,29 @@ class Pool {
     free_.insert({it->second, p});
     used_.erase(it);
   }
+  // release once work already enqueued on `s` has finished (see flush)
+  void release_after(void* p, hipStream_t s) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    pending_.push_back({p, s});
+  }
+  // `s` has been synchronised: its pending blocks become reusable
+  void flush(hipStream_t s) {
+    std::vector<void*> done;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      for (size_t i = 0; i < pending_.size();) {
+        if (pending_[i].second == s) {
+          done.push_back(pending_[i].first);
+          pending_[i] = pending_.back();
+          pending_.pop_back();
+        } else {
+          ++i;
+        }
+      }
+    }
+    for (void* p : done) release(p);
+  }
   void trim() {
     std::lock_guard<std::mutex> lk(mu_);
     for (auto& kv : free_) (void)hipFree(kv.second);
@@ -130,6 +153,7 @@ class Pool {
     return (b + g - 1) / g * g;
   }
   std::mutex mu_;
+  std::vector<std::pair<void*, hipStream_t>> pending_;
   std::multimap<size_t, void*> free_;
   std::unordered_map<void*, size_t> used_;
 };
@@ -152,27 +176,34 @@ struct DBuf {
     return *this;
   }
   ~DBuf() { reset(); }
+  // release now (no work in flight may use the block)
   void reset() {
     if (p) pool().release(p);
     p = nullptr;
     cap = 0;
   }
-  // capacity >= n, old contents discarded
-  void need(size_t n) {
+  // release once the work already enqueued on s is done
+  void reset_after(hipStream_t s) {
+    if (p) pool().release_after(p, s);
+    p = nullptr;
+    cap = 0;
+  }
+  // capacity >= n, old contents discarded; the old block is released after
+  // the work enqueued on s
+  void need(size_t n, hipStream_t s) {
     if (n <= cap && p) return;
-    reset();
+    reset_after(s);
     size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
     p = static_cast<T*>(pool().alloc(bytes));
     cap = pool().size_of(p) / sizeof(T);
   }
-  // capacity >= n, first `used` elements kept
+  // capacity >= n, first `used` elements kept (copied on s)
   void grow(size_t n, size_t used, hipStream_t s) {
     if (n <= cap && p) return;
     size_t want = std::max<size_t>(n, cap + cap / 2);
     T* np = static_cast<T*>(pool().alloc(std::max<size_t>(want, 1) * sizeof(T)));
     if (used) HIP_CHECK(hipMemcpyAsync(np, p, used * sizeof(T), hipMemcpyDeviceToDevice, s));
-    HIP_CHECK(hipStreamSynchronize(s));
-    reset();
+    reset_after(s);
     p = np;
     cap = pool().size_of(np) / sizeof(T);
   }
@@ -232,11 +263,17 @@ static Opts read_opts(const lcg_opts* o) {
   return r;
 }
 
+// Synchronise s; blocks whose release waited for it become reusable.
+static void sync(hipStream_t s) {
+  HIP_CHECK(hipStreamSynchronize(s));
+  pool().flush(s);
+}
+
 template <typename T>
 static T read_dev(const T* p, hipStream_t s) {
   T v;
   HIP_CHECK(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
+  sync(s);
   return v;
 }
 
@@ -261,9 +298,12 @@ static double hll_estimate(const unsigned int* regs) {
   return e;
 }
 
-// Working memory of one build call, worst case (every phrase of length two).
+// Working memory of one build call besides the grammar: the phrase arrays of
+// a round are sized for the worst case n/2 + k phrases (start 8 B, length 4,
+// key 8, slot 4, two symbol and two fingerprint streams 4 each = 40 B per
+// phrase), plus break bits, scan and sketch buffers.
 static uint64_t build_bytes(uint64_t n, uint32_t k) {
-  return 17 * n + 96ull * k + (64ull << 20);
+  return 21 * n + 48ull * k + (64ull << 20);
 }
 
 // Reusable per-call scratch.
@@ -275,9 +315,21 @@ struct Work {
   DBuf<uint64_t> off[2];
   DBuf<uint64_t> newbits, wcnt, wlen, wcnt_base, wlen_base;
   DBuf<uint32_t> lut;
-  DBuf<Counters> ctr;
-  DBuf<uint8_t> content8;
+  DBuf<Counters> ctr, fin;
+  DBuf<uint8_t> content8, hll_part;
   DBuf<uint32_t> content32, remap[2];
+  void release_after(hipStream_t s) {
+    DBuf<uint64_t>* b64[] = {&bits, &tile_cnt, &tile_base, &scan_tmp, &pstart, &key, &off[0],
+                             &off[1], &newbits, &wcnt, &wlen, &wcnt_base, &wlen_base};
+    DBuf<uint32_t>* b32[] = {&plen, &slot_idx, &sym[0], &sym[1], &fpv[0], &fpv[1], &lut,
+                             &content32, &remap[0], &remap[1]};
+    for (auto* b : b64) b->reset_after(s);
+    for (auto* b : b32) b->reset_after(s);
+    ctr.reset_after(s);
+    fin.reset_after(s);
+    content8.reset_after(s);
+    hll_part.reset_after(s);
+  }
 };
 
 static void zero_counters(Counters* c, hipStream_t s) { launch_zero(c, sizeof(Counters), s); }
@@ -293,8 +345,8 @@ static bool debug_on() {
 
 // HIP events at the phase boundaries of one round (LCG_FLAG_TIMING):
 // 0 start, 1 classified and counted, 2 emit start, 8 emitted, 3 dictionary
-// sized, 4 inserted, 5 ranked, 6 committed, 7 segments done.  The host reads
-// between phases 1 and 2 and between 8 and 3 are not counted.
+// sized, 4 inserted, 5 ranked, 6 committed, 7 segments done.  The host work
+// between phases 1 and 2 and between 8 and 3 is not counted.
 struct PhaseEvents {
   static constexpr int N = 9;
   hipEvent_t e[N] = {};
@@ -328,14 +380,14 @@ static void ensure_table(Level& L, uint64_t need, uint32_t min_log2, Work& w, hi
   if (L.tcap >= want && L.table.p) return;
   if (want > (1ull << 34)) throw LcgError{LCG_ETABLE, "dictionary capacity limit reached"};
   DBuf<Slot> nt;
-  nt.need(want);
+  nt.need(want, s);
   launch_fill_slots(nt.p, want, s);
   if (L.tcap && L.u) {
     zero_counters(w.ctr.p, s);
     launch_rehash(L.table.p, L.tcap, nt.p, want - 1, w.ctr.p, s);
     if (read_dev(&w.ctr.p->overflow, s)) throw LcgError{LCG_ETABLE, "rehash failed"};
   }
-  HIP_CHECK(hipStreamSynchronize(s));
+  L.table.reset_after(s);
   L.table = std::move(nt);
   L.tcap = want;
 }
@@ -344,7 +396,7 @@ static void ensure_level(lcg_grammar* g, size_t i, hipStream_t s) {
   while (g->levels.size() < i) {
     g->levels.emplace_back();
     Level& L = g->levels.back();
-    L.off.need(1);
+    L.off.need(1, s);
     HIP_CHECK(hipMemsetAsync(L.off.p, 0, sizeof(uint64_t), s));
   }
 }
@@ -355,9 +407,10 @@ struct DedupResult {
   uint64_t probes, compares;
 };
 
-// insert -> newflags -> scan -> commit for d phrases of level `lv` (1-based).
-// content holds the phrases (bytes at level 1), fnew their F values; ranks
-// land in sym_next.  Regrows the dictionary and retries on overflow.
+// insert -> newflags -> scan -> commit for the d phrases of level `lv`
+// (1-based) described by w.pstart/w.plen/w.key over `content` (bytes at level
+// 1); fnew holds their F values; ranks land in sym_next.  Regrows the
+// dictionary and retries if a probe sequence ran out of budget.
 static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const void* content,
                                 const uint32_t* fnew, uint32_t* sym_next, uint64_t est_new,
                                 const Opts& o, Work& w, hipStream_t s, PhaseEvents* pe = nullptr) {
@@ -365,14 +418,15 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
   const bool bytes = lv == 1;
   ensure_table(L, (uint64_t)L.u + est_new, o.table_min_log2, w, s);
   const uint64_t W = (d + 63) / 64;
-  w.slot_idx.need(d);
-  w.newbits.need(W);
-  w.wcnt.need(W);
-  w.wlen.need(W);
-  w.wcnt_base.need(W + 1);
-  w.wlen_base.need(W + 1);
-  w.scan_tmp.need(std::max<size_t>(scan_tmp_words(W), 1));
+  w.slot_idx.need(d, s);
+  w.newbits.need(W, s);
+  w.wcnt.need(W, s);
+  w.wlen.need(W, s);
+  w.wcnt_base.need(W + 1, s);
+  w.wlen_base.need(W + 1, s);
+  w.scan_tmp.need(std::max<size_t>(scan_tmp_words(W), 1), s);
   Counters hc;
+  uint64_t u_new = 0, q_new = 0;
   for (int attempt = 0;; ++attempt) {
     zero_counters(w.ctr.p, s);
     const void* rule_rhs = bytes ? (const void*)L.rhs8.p : (const void*)L.rhs32.p;
@@ -385,7 +439,9 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
     scan_exclusive(w.wlen.p, w.wlen_base.p, W, w.scan_tmp.p, s);
     if (pe) pe->rec(5, s);
     HIP_CHECK(hipMemcpyAsync(&hc, w.ctr.p, offsetof(Counters, hll), hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
+    HIP_CHECK(hipMemcpyAsync(&u_new, w.wcnt_base.p + W, 8, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(&q_new, w.wlen_base.p + W, 8, hipMemcpyDeviceToHost, s));
+    sync(s);
     if (debug_on())
       std::fprintf(stderr, "[lcg] level %u attempt %d: d=%llu est=%llu cap=%llu won=%llu probes=%llu cmp=%llu overflow=%u\n",
                    lv, attempt, (unsigned long long)d, (unsigned long long)est_new,
@@ -395,8 +451,6 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
     ensure_table(L, (uint64_t)L.u + std::max<uint64_t>(est_new, hc.won), o.table_min_log2, w, s,
                  /*force_grow=*/true);
   }
-  uint64_t u_new = read_dev(w.wcnt_base.p + W, s);
-  uint64_t q_new = read_dev(w.wlen_base.p + W, s);
   if ((uint64_t)L.u + u_new >= kNone) throw LcgError{LCG_EOVERFLOW, "level needs 2^32 ranks"};
   L.off.grow(L.u + u_new + 1, L.u + 1, s);
   L.fp.grow(L.u + u_new, L.u, s);
@@ -417,9 +471,13 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
 }
 
 // BuildGram of k strings into g (fresh or existing): the batched form.
+// Two host synchronisations per round: the phrase count and key sketch
+// (sizes the dictionary; also returns the previous round's count of strings
+// still active), and the new-rule counts (sizes the level).  The round after
+// the last one runs classify/emit on strings of length <= 1 and finds no
+// phrase; that is how the loop learns that every string is done.
 static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_off, uint32_t k,
                        const std::vector<uint64_t>& h_off, const Opts& o, Work& w, hipStream_t s) {
-  const uint64_t n = h_off[k];
   const uint32_t c_base = g->k;
   g->c_level.grow(c_base + k, c_base, s);
   g->c_sym.grow(c_base + k, c_base, s);
@@ -433,20 +491,34 @@ static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_
     active_len += len >= 2 ? len : 0;
   }
   if (!active) {
-    HIP_CHECK(hipStreamSynchronize(s));
+    sync(s);
     return;
   }
-  w.lut.need(256);
-  w.ctr.need(1);
+  w.lut.need(256, s);
+  w.ctr.need(1, s);
+  w.fin.need(1, s);
+  w.hll_part.need((size_t)kEmitBlocks * kHll, s);
   launch_f0_lut(w.lut.p, g->H.lv[0].a, g->H.lv[0].b, s);
   const uint64_t* cur_off = d_off;
-  uint64_t n_i = n;
+  uint64_t n_i = h_off[k];
   int cur = 0;  // ping-pong index of T^{i+1}
   PhaseEvents pe((o.flags & LCG_FLAG_TIMING) != 0);
+  std::vector<unsigned int> regs(kHll);
+  bool pending = false;  // the previous round's row waits for its active count
+  Stat prev{};
   for (uint32_t lv = 1;; ++lv) {
-    if (lv >= (uint32_t)HashFamily::kLevels) throw LcgError{LCG_EOVERFLOW, "more than 63 rounds"};
-    ensure_level(g, lv, s);
-    pe.rec(0, s);
+    Counters hf;
+    if (lv >= (uint32_t)HashFamily::kLevels) {
+      HIP_CHECK(hipMemcpyAsync(&hf, w.fin.p, offsetof(Counters, hll), hipMemcpyDeviceToHost, s));
+      sync(s);
+      prev[4] = hf.active;
+      prev[13] = pe.ns(5, 6);
+      prev[14] = pe.ns(6, 7);
+      prev[8] += prev[13] + prev[14];
+      g->stats.push_back(prev);
+      if (hf.active) throw LcgError{LCG_EOVERFLOW, "more than 63 rounds"};
+      break;
+    }
     const bool bytes = lv == 1;
     RoundIn in;
     in.sym = bytes ? (const void*)d_text : (const void*)w.sym[cur ^ 1].p;
@@ -457,52 +529,62 @@ static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_
     in.n = n_i;
     in.bytes = bytes;
     const uint64_t tiles = (n_i + kTile - 1) / kTile;
-    w.bits.need(tiles * kTileWords);
-    w.tile_cnt.need(tiles);
-    w.tile_base.need(tiles + 1);
-    w.scan_tmp.need(std::max<size_t>(scan_tmp_words(tiles), 1));
+    const uint64_t d_cap = n_i / 2 + k + 1;  // phrases have length >= 2 but the first
+    if (d_cap >= kNone) throw LcgError{LCG_EOVERFLOW, "a round may have 2^32 phrases"};
+    w.bits.need(tiles * kTileWords, s);
+    w.tile_cnt.need(tiles, s);
+    w.tile_base.need(tiles + 1, s);
+    w.scan_tmp.need(std::max<size_t>(scan_tmp_words(tiles), 1), s);
+    w.pstart.need(d_cap, s);
+    w.plen.need(d_cap, s);
+    w.key.need(d_cap, s);
+    w.sym[cur].need(d_cap, s);
+    w.fpv[cur].need(d_cap, s);
+    w.off[cur].need(k + 1, s);
+    pe.rec(0, s);
     launch_classify(in, w.bits.p, w.tile_cnt.p, s);
     scan_exclusive(w.tile_cnt.p, w.tile_base.p, tiles, w.scan_tmp.p, s);
     pe.rec(1, s);
-    const uint64_t d = read_dev(w.tile_base.p + tiles, s);
-    if (d == 0) throw LcgError{LCG_EINVAL, "internal: active strings produced no phrase"};
-    if (d >= kNone) throw LcgError{LCG_EOVERFLOW, "a round has 2^32 phrases"};
-    w.pstart.need(d);
-    w.plen.need(d);
-    w.key.need(d);
-    w.sym[cur].need(d);
-    w.fpv[cur].need(d);
-    w.off[cur].need(k + 1);
     zero_counters(w.ctr.p, s);
     pe.rec(2, s);
     launch_emit(in, w.bits.p, w.tile_base.p, g->H.lv[lv], o.key_bits, w.pstart.p, w.plen.p,
-                w.key.p, w.fpv[cur].p, w.ctr.p, s);
+                w.key.p, w.fpv[cur].p, w.hll_part.p, w.ctr.p, s);
     pe.rec(8, s);
-    std::vector<unsigned int> regs(kHll);
+    uint64_t d = 0;
+    HIP_CHECK(hipMemcpyAsync(&d, w.tile_base.p + tiles, 8, hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipMemcpyAsync(regs.data(), w.ctr.p->hll, sizeof(unsigned int) * kHll,
                              hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
+    if (pending)
+      HIP_CHECK(hipMemcpyAsync(&hf, w.fin.p, offsetof(Counters, hll), hipMemcpyDeviceToHost, s));
+    sync(s);
+    if (pending) {
+      prev[4] = hf.active;
+      prev[13] = pe.ns(5, 6);
+      prev[14] = pe.ns(6, 7);
+      prev[8] += prev[13] + prev[14];
+      g->stats.push_back(prev);
+      active = hf.active;
+      active_len = hf.active_len;
+      if (!active) {
+        if (d) throw LcgError{LCG_EHIP, "internal: phrases after the last round"};
+        break;
+      }
+    }
+    if (d == 0 || d >= d_cap) throw LcgError{LCG_EHIP, "internal: phrase count out of range"};
+    ensure_level(g, lv, s);
     const uint64_t t_classify = pe.ns(0, 1), t_emit = pe.ns(2, 8);
     const uint64_t est = std::min<uint64_t>(d, (uint64_t)(hll_estimate(regs.data()) * 1.25) + 64);
     const void* content = bytes ? (const void*)d_text : (const void*)w.sym[cur ^ 1].p;
     DedupResult r = dedup_commit(g, lv, d, content, w.fpv[cur].p, w.sym[cur].p, est, o, w, s, &pe);
-    zero_counters(w.ctr.p, s);
+    zero_counters(w.fin.p, s);
     launch_segments(cur_off, k, w.pstart.p, d, w.off[cur].p, s);
     launch_finish(cur_off, w.off[cur].p, k, w.sym[cur].p, lv, g->c_level.p + c_base,
-                  g->c_sym.p + c_base, w.ctr.p, s);
+                  g->c_sym.p + c_base, w.fin.p, s);
     pe.rec(7, s);
-    Counters hc;
-    HIP_CHECK(hipMemcpyAsync(&hc, w.ctr.p, offsetof(Counters, hll), hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
-    active = hc.active;
-    const uint64_t t_insert = pe.ns(3, 4), t_rank = pe.ns(4, 5), t_commit = pe.ns(5, 6),
-                   t_seg = pe.ns(6, 7);
-    g->stats.push_back(Stat{active_len, d, r.u_new, r.q_new, active, r.probes, r.compares,
-                            g->levels[lv - 1].tcap,
-                            t_classify + t_emit + t_insert + t_rank + t_commit + t_seg, t_classify,
-                            t_emit, t_insert, t_rank, t_commit, t_seg});
-    active_len = hc.active_len;
-    if (!active) break;
+    const uint64_t t_insert = pe.ns(3, 4), t_rank = pe.ns(4, 5);
+    prev = Stat{active_len, d, r.u_new, r.q_new, 0, r.probes, r.compares, g->levels[lv - 1].tcap,
+                t_classify + t_emit + t_insert + t_rank, t_classify, t_emit, t_insert, t_rank, 0, 0};
+    pending = true;
     cur_off = w.off[cur].p;
     n_i = d;
     cur ^= 1;
@@ -516,8 +598,8 @@ static void merge_core(lcg_grammar* a, const lcg_grammar* b, Work& w, hipStream_
   a->c_level.grow(ka + kb, ka, s);
   a->c_sym.grow(ka + kb, ka, s);
   launch_c_merge(b->c_level.p, b->c_sym.p, kb, 0, nullptr, a->c_level.p + ka, a->c_sym.p + ka, s);
-  w.lut.need(256);
-  w.ctr.need(1);
+  w.lut.need(256, s);
+  w.ctr.need(1, s);
   launch_f0_lut(w.lut.p, a->H.lv[0].a, a->H.lv[0].b, s);
   Opts o;
   int cur = 0;
@@ -527,20 +609,20 @@ static void merge_core(lcg_grammar* a, const lcg_grammar* b, Work& w, hipStream_
     const Level& B = b->levels[lv - 1];
     const bool bytes = lv == 1;
     const uint32_t ub = B.u;
-    w.remap[cur].need(std::max<uint32_t>(ub, 1));
+    w.remap[cur].need(std::max<uint32_t>(ub, 1), s);
     if (ub) {
-      w.pstart.need(ub);
-      w.plen.need(ub);
-      w.key.need(ub);
+      w.pstart.need(ub, s);
+      w.plen.need(ub, s);
+      w.key.need(ub, s);
       const void* content;
       const uint32_t* f_prev = bytes ? w.lut.p : a->levels[lv - 2].fp.p;
       if (bytes) {
-        w.content8.need(B.q);
+        w.content8.need(B.q, s);
         content = w.content8.p;
         launch_merge_prepare(true, ub, B.off.p, B.rhs8.p, nullptr, f_prev, a->H.lv[lv], 0,
                              w.content8.p, w.pstart.p, w.plen.p, w.key.p, s);
       } else {
-        w.content32.need(B.q);
+        w.content32.need(B.q, s);
         content = w.content32.p;
         launch_merge_prepare(false, ub, B.off.p, B.rhs32.p, remap_prev, f_prev, a->H.lv[lv], 0,
                              w.content32.p, w.pstart.p, w.plen.p, w.key.p, s);
@@ -553,7 +635,7 @@ static void merge_core(lcg_grammar* a, const lcg_grammar* b, Work& w, hipStream_
     cur ^= 1;
   }
   a->k += kb;
-  HIP_CHECK(hipStreamSynchronize(s));
+  sync(s);
 }
 
 static std::vector<uint64_t> fetch_offsets(const uint64_t* d_off, uint32_t k, hipStream_t s) {
@@ -561,10 +643,11 @@ static std::vector<uint64_t> fetch_offsets(const uint64_t* d_off, uint32_t k, hi
   if (!d_off) throw LcgError{LCG_EINVAL, "offsets are NULL"};
   std::vector<uint64_t> h(k + 1);
   HIP_CHECK(hipMemcpyAsync(h.data(), d_off, sizeof(uint64_t) * (k + 1), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
+  sync(s);
   if (h[0] != 0) throw LcgError{LCG_EINVAL, "offsets[0] must be 0"};
   for (uint32_t j = 0; j < k; ++j)
-    if (h[j + 1] <= h[j]) throw LcgError{LCG_EINVAL, "string " + std::to_string(j) + " is empty or offsets decrease"};
+    if (h[j + 1] <= h[j])
+      throw LcgError{LCG_EINVAL, "string " + std::to_string(j) + " is empty or offsets decrease"};
   return h;
 }
 
@@ -581,6 +664,8 @@ static void build_any(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_o
   if (o.mode == LCG_MODE_BATCHED) {
     check_budget(o, h_off[k], k);
     build_core(g, d_text, d_off, k, h_off, o, w, s);
+    w.release_after(s);
+    sync(s);
     return;
   }
   // plain form: one grammar per string (its own launches every round), then MergeGrams
@@ -593,7 +678,7 @@ static void build_any(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_o
     pairs[2 * j + 1] = h_off[j + 1] - h_off[j];
   }
   DBuf<uint64_t> d_pairs;
-  d_pairs.need(pairs.size());
+  d_pairs.need(pairs.size(), s);
   HIP_CHECK(hipMemcpyAsync(d_pairs.p, pairs.data(), sizeof(uint64_t) * pairs.size(),
                            hipMemcpyHostToDevice, s));
   for (uint32_t j = 0; j < k; ++j) {
@@ -603,6 +688,9 @@ static void build_any(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_o
     merge_core(g, &gj, w, s);
     g->stats.insert(g->stats.end(), gj.stats.begin(), gj.stats.end());
   }
+  d_pairs.reset_after(s);
+  w.release_after(s);
+  sync(s);
 }
 
 static void expand_core(lcg_grammar* g, uint32_t j, uint8_t* d_out, uint64_t cap, uint64_t* out_len,
@@ -612,35 +700,35 @@ static void expand_core(lcg_grammar* g, uint32_t j, uint8_t* d_out, uint64_t cap
   uint32_t sym;
   HIP_CHECK(hipMemcpyAsync(&lvl, g->c_level.p + j, 1, hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipMemcpyAsync(&sym, g->c_sym.p + j, 4, hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
+  sync(s);
   if (lvl == 0) {
     if (out_len) *out_len = 1;
     if (cap < 1) throw LcgError{LCG_EINVAL, "output buffer too small"};
     HIP_CHECK(hipMemcpyAsync(d_out, &sym, 1, hipMemcpyHostToDevice, s));
-    HIP_CHECK(hipStreamSynchronize(s));
+    sync(s);
     return;
   }
   DBuf<uint32_t> cur, nxt;
   DBuf<uint64_t> lens, pos, tmp;
-  cur.need(1);
+  cur.need(1, s);
   HIP_CHECK(hipMemcpyAsync(cur.p, &sym, 4, hipMemcpyHostToDevice, s));
   uint64_t m = 1;
   for (uint32_t lv = lvl; lv >= 1; --lv) {
     const Level& L = g->levels[lv - 1];
-    lens.need(m);
-    pos.need(m + 1);
-    tmp.need(std::max<size_t>(scan_tmp_words(m), 1));
+    lens.need(m, s);
+    pos.need(m + 1, s);
+    tmp.need(std::max<size_t>(scan_tmp_words(m), 1), s);
     launch_expand_lens(cur.p, m, L.off.p, lens.p, s);
     scan_exclusive(lens.p, pos.p, m, tmp.p, s);
     const uint64_t total = read_dev(pos.p + m, s);
     if (lv == 1) {
       if (out_len) *out_len = total;
+      if (total <= cap) launch_expand_emit(true, cur.p, m, L.off.p, L.rhs8.p, pos.p, d_out, s);
+      sync(s);
       if (total > cap) throw LcgError{LCG_EINVAL, "output buffer too small"};
-      launch_expand_emit(true, cur.p, m, L.off.p, L.rhs8.p, pos.p, d_out, s);
-      HIP_CHECK(hipStreamSynchronize(s));
       return;
     }
-    nxt.need(total);
+    nxt.need(total, s);
     launch_expand_emit(false, cur.p, m, L.off.p, L.rhs32.p, pos.p, nxt.p, s);
     std::swap(cur, nxt);
     m = total;
