@@ -101,6 +101,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--rounds", action="store_true", help="per-round phase table on stderr")
+    ap.add_argument("--serving-seconds", type=float, default=4.0,
+                    help="seconds per offered load of the serving leg (0 = skip)")
+    ap.add_argument("--serving-loads", default="0.5,2,8")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -204,6 +207,22 @@ def main():
         plain = n / float(np.mean(ps)) / 1e9
         out["plain_gbps"] = round(plain, 4)
         out["batched_vs_plain"] = round(value / plain, 2)
+
+    if args.serving_seconds > 0:
+        from paper_2411_12439_amd import serve
+        del t, o
+        src = datagen.ServingSource()
+        pool = serve.PinnedPool(src)
+        rows = []
+        for load in (float(x) for x in args.serving_loads.split(",")):
+            summary, srv, reqs = serve.run_load(pool, load, args.serving_seconds)
+            rng = np.random.default_rng(0)
+            sample = rng.choice(len(reqs), size=min(4, len(reqs)), replace=False)
+            summary["alone_vs_mix_checked"] = serve.check_alone_vs_mix(srv, pool, reqs, sample)
+            rows.append(summary)
+            print("[bench] serving %s" % json.dumps(summary), file=sys.stderr, flush=True)
+            del srv
+        out["serving"] = rows
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(text, off, seed, args.cpu_strings)

@@ -417,16 +417,22 @@ __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in, const uint64_t* __r
     hll_part[(uint64_t)blockIdx.x * kHll + i] = (uint8_t)s_hll[i];
 }
 
-// register-wise maximum of the per-block HyperLogLog sketches
-__global__ void k_hll_reduce(const uint8_t* __restrict__ part, unsigned blocks,
-                             Counters* __restrict__ ctr) {
-  const int i = threadIdx.x;
+// register-wise maximum of the per-block HyperLogLog sketches: block i
+// reduces register i over all rows
+__global__ __launch_bounds__(256) void k_hll_reduce(const uint8_t* __restrict__ part,
+                                                    unsigned blocks, Counters* __restrict__ ctr) {
+  __shared__ uint32_t s_max;
+  const uint32_t i = blockIdx.x;
+  if (threadIdx.x == 0) s_max = 0;
+  __syncthreads();
   uint32_t m = 0;
-  for (unsigned b = 0; b < blocks; ++b) {
-    uint32_t v = part[(uint64_t)b * kHll + i];
+  for (unsigned b = threadIdx.x; b < blocks; b += blockDim.x) {
+    const uint32_t v = part[(uint64_t)b * kHll + i];
     m = v > m ? v : m;
   }
-  ctr->hll[i] = m;
+  if (m) atomicMax(&s_max, m);
+  __syncthreads();
+  if (threadIdx.x == 0) ctr->hll[i] = s_max;
 }
 
 void launch_emit(const RoundIn& in, const uint64_t* bits, const uint64_t* tile_base, LevelHash h,
@@ -441,7 +447,7 @@ void launch_emit(const RoundIn& in, const uint64_t* bits, const uint64_t* tile_b
     k_emit<false><<<g, kBlock, 0, s>>>(in, bits, tile_base, tiles, h, key_bits, pstart, plen, key,
                                        fnew, hll_part);
   LCG_LAUNCH_CHECK("emit");
-  k_hll_reduce<<<1, kHll, 0, s>>>(hll_part, g, ctr);
+  k_hll_reduce<<<kHll, 256, 0, s>>>(hll_part, g, ctr);
   LCG_LAUNCH_CHECK("hll_reduce");
 }
 
@@ -706,7 +712,9 @@ __global__ __launch_bounds__(256) void k_commit(uint64_t d, const uint32_t* __re
     return;
   }
   Slot* sl = &table[sidx];
-  uint32_t r = __hip_atomic_load(&sl->rank, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // a rank committed concurrently by the first occurrence may not be seen yet;
+  // the first-occurrence count gives the same rank
+  uint32_t r = sl->rank;
   if (r == kNone) r = u_prev + (uint32_t)rank1(newbits, wcnt_base, sl->minocc);
   sym_next[o] = r;
   const uint64_t w = newbits[o >> 6];

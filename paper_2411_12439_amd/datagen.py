@@ -222,27 +222,45 @@ def make_config(name, seed=None, scale=1.0, **kw):
 
 
 class ServingSource:
-    """Request generator for the serving form: Poisson arrivals, lognormal sizes."""
+    """Request generator of the serving form.
 
-    def __init__(self, seed=CONFIG_SEEDS["serving"], scale=1.0, n_bases=16):
+    Bases of 50 MB (scaled) each get `variants` copies at 1 % divergence
+    (0.9 % substitutions, 0.1 % indels of 1-10 bp), made once; a request is a
+    random window of a random variant, of lognormal size (median 1 MB, sigma
+    1.5) clipped to [10 KB, 50 MB] (scaled).  Inter-arrival gaps are
+    exponential for a given offered load (bytes per second).
+    """
+
+    def __init__(self, seed=CONFIG_SEEDS["serving"], scale=1.0, n_bases=16, variants=2):
         self.rng = _rng(seed)
         self.scale = scale
         self.BL = max(1024, int(50_000_000 * scale))
-        self.bases = [random_bases(self.rng, self.BL) for _ in range(n_bases)]
+        self.variants = []
+        for _ in range(n_bases):
+            base = random_bases(self.rng, self.BL)
+            for _ in range(variants):
+                v = substitute(self.rng, base.copy(), 0.009)
+                self.variants.append(indels(self.rng, v, 0.001))
 
-    def request(self):
+    def draw(self):
+        """(variant index, start, length) of the next request."""
         s = self.scale
         L = float(np.exp(self.rng.normal(np.log(1e6 * s), 1.5)))
         L = int(np.clip(L, 10_000 * s, 50_000_000 * s))
-        L = max(2, min(L, self.BL))
-        b = self.bases[int(self.rng.integers(0, len(self.bases)))]
-        st = int(self.rng.integers(0, self.BL - L + 1))
-        x = substitute(self.rng, b[st:st + L].copy(), 0.009)
-        return indels(self.rng, x, 0.001)
+        v = int(self.rng.integers(0, len(self.variants)))
+        L = max(2, min(L, len(self.variants[v])))
+        st = int(self.rng.integers(0, len(self.variants[v]) - L + 1))
+        return v, st, L
 
-    def arrivals(self, load_bytes_per_s, n, mean_size=None):
-        """n inter-arrival gaps (seconds) for the offered load."""
-        if mean_size is None:
-            mean_size = 1e6 * self.scale * np.exp(1.5 ** 2 / 2)
-        lam = load_bytes_per_s / mean_size
+    def request(self):
+        v, st, L = self.draw()
+        return self.variants[v][st:st + L]
+
+    def mean_size(self):
+        s = self.scale
+        return 1e6 * s * np.exp(1.5 ** 2 / 2)
+
+    def arrivals(self, load_bytes_per_s, n):
+        """n exponential inter-arrival gaps (seconds) for the offered load."""
+        lam = load_bytes_per_s / self.mean_size()
         return self.rng.exponential(1.0 / lam, size=n)

@@ -1,0 +1,96 @@
+"""Serving form: ring allocator (CPU) and continuous batching into a running grammar (GPU)."""
+import random
+
+import numpy as np
+import pytest
+
+from paper_2411_12439_amd import datagen as D
+from paper_2411_12439_amd.serve import RingBuffer
+
+
+class _HostRing(RingBuffer):
+    def __init__(self, n):  # no device buffer: allocation logic only
+        self.cap = n
+        self.head = self.tail = self.used = 0
+        self.wrapped = False
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_ring_allocations_never_overlap(seed):
+    r = _HostRing(100)
+    live = []
+    rng = random.Random(seed)
+    for _ in range(20000):
+        if live and rng.random() < 0.45:
+            m = rng.randint(1, len(live))
+            tot = sum(n for _, n in live[:m])
+            live = live[m:]
+            r.release(tot, live[0][0] if live else 0)
+        else:
+            n = rng.randint(1, 60)
+            off = r.alloc(n)
+            if off is not None:
+                assert off + n <= 100
+                for o2, n2 in live:
+                    assert off + n <= o2 or o2 + n2 <= off
+                live.append((off, n))
+        assert r.used == sum(n for _, n in live)
+
+
+def test_ring_rejects_oversized_request():
+    with pytest.raises(ValueError):
+        _HostRing(10).alloc(11)
+
+
+@pytest.fixture(scope="module")
+def served():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2411_12439_amd import serve
+    src = D.ServingSource(scale=0.02, n_bases=4)
+    pool = serve.PinnedPool(src)
+    # a high offered load so that requests queue up and batches form; a small
+    # ring so that it wraps
+    summary, srv, reqs = serve.run_load(pool, load_gbps=5.0, seconds=30.0, max_requests=60,
+                                        ring_bytes=4 << 20)
+    return serve, pool, summary, srv, reqs
+
+
+@pytest.mark.gpu
+def test_serving_completes_every_request(served):
+    serve, pool, summary, srv, reqs = served
+    assert summary["requests"] == 60 == len(srv.completed)
+    assert sum(srv.batch_sizes) == 60
+    assert summary["max_batch"] >= 2, "no batch formed under load"
+    assert summary["p99_ms"] >= summary["p50_ms"] > 0
+    assert sorted(r.c_index for r, _ in reqs) == list(range(60))
+
+
+@pytest.mark.gpu
+def test_serving_alone_equals_in_the_mix(served):
+    """Def. 1: each request's rules inside the running grammar == the request built alone."""
+    serve, pool, summary, srv, reqs = served
+    assert serve.check_alone_vs_mix(srv, pool, reqs, range(len(reqs))) == len(reqs)
+
+
+@pytest.mark.gpu
+def test_serving_round_trip(served):
+    serve, pool, summary, srv, reqs = served
+    for req, (v, st, L) in reqs[::7]:
+        got = srv.g.expand(req.c_index).cpu().numpy()
+        assert np.array_equal(got, pool.source.variants[v][st:st + L])
+
+
+@pytest.mark.gpu
+def test_serving_grammar_equals_oracle_of_the_stream(served):
+    """The running grammar equals (canonically) the oracle's grammar of all requests
+    in completion order: incremental merging loses nothing and adds nothing."""
+    from oracle import oracle as O
+    from paper_2411_12439_amd import canon as CN
+    serve, pool, summary, srv, reqs = served
+    order = sorted(reqs, key=lambda x: x[0].c_index)
+    strings = [pool.source.variants[v][st:st + L] for _, (v, st, L) in order]
+    text, off = D.pack(strings)
+    want = O.build(text, off, D.HASH_SEED).export()
+    got = srv.g.export()
+    assert CN.canon(got) == CN.canon(want)
