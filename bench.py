@@ -104,6 +104,9 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=4.0,
                     help="seconds per offered load of the serving leg (0 = skip)")
     ap.add_argument("--serving-loads", default="0.5,2,8")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device 3 times (calibrates rocprof "
+                         "FETCH_SIZE / WRITE_SIZE against a copy of known size) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -113,6 +116,17 @@ def main():
 
     import torch
     from paper_2411_12439_amd import datagen, lcg
+
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes, "copies": 3}))
+        return
 
     seed = datagen.HASH_SEED
     text, off = datagen.make_config(args.config, scale=args.scale)

@@ -42,8 +42,10 @@ void launch_f0_lut(uint32_t* lut, uint64_t a0, uint64_t b0, hipStream_t s);
 void launch_fill_slots(Slot* t, uint64_t cap, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 
-void launch_classify(const RoundIn& in, uint64_t* bits, uint64_t* tile_cnt, hipStream_t s);
-void launch_emit(const RoundIn& in, const uint64_t* bits, const uint64_t* tile_base, LevelHash h,
+void launch_classify(const RoundIn& in, uint64_t* bits, uint64_t* tile_cnt, uint2* tile_seg,
+                     hipStream_t s);
+void launch_emit(const RoundIn& in, const uint64_t* bits, const uint64_t* tile_base,
+                 const uint2* tile_seg, LevelHash h,
                  uint32_t key_bits, uint64_t* pstart, uint32_t* plen, uint64_t* key, uint32_t* fnew,
                  uint8_t* hll_part, Counters* ctr, hipStream_t s);
 
@@ -56,11 +58,16 @@ void launch_insert(bool bytes, uint64_t d, const uint64_t* key, const uint64_t* 
                    const uint32_t* plen, const void* content, const uint64_t* rule_off,
                    const void* rule_rhs, uint32_t u_committed, Slot* table, uint64_t mask,
                    uint32_t* slot_idx, Counters* ctr, hipStream_t s);
-void launch_newflags(uint64_t d, const uint32_t* slot_idx, const Slot* table, const uint32_t* plen,
-                     uint64_t* newbits, uint64_t* wcnt, uint64_t* wlen, hipStream_t s);
+void launch_newflags(bool bytes, uint64_t d, const uint32_t* slot_idx, const Slot* table,
+                     const uint64_t* key, const uint32_t* plen, uint64_t* newbits, uint64_t* wcnt,
+                     uint64_t* wlen, hipStream_t s);
+void launch_newflags_table(bool bytes, const Slot* table, uint64_t cap, uint64_t d,
+                           const uint64_t* key, const uint32_t* plen, uint64_t* newbits,
+                           uint64_t* wcnt, uint64_t* wlen, hipStream_t s);
 void launch_commit(bool bytes, uint64_t d, const uint32_t* slot_idx, Slot* table,
                    const uint64_t* newbits, const uint64_t* wcnt_base, const uint64_t* wlen_base,
-                   const uint64_t* pstart, const uint32_t* plen, const void* content,
+                   const uint64_t* key, const uint64_t* pstart, const uint32_t* plen,
+                   const void* content,
                    const uint32_t* fnew, uint32_t u_prev, uint64_t q_prev, uint64_t* rule_off,
                    void* rule_rhs, uint32_t* rule_fp, uint32_t* sym_next, hipStream_t s);
 void launch_rehash(const Slot* old_t, uint64_t old_cap, Slot* new_t, uint64_t new_mask,
@@ -68,8 +75,8 @@ void launch_rehash(const Slot* old_t, uint64_t old_cap, Slot* new_t, uint64_t ne
 
 void launch_c_init(const uint8_t* text, const uint64_t* off, uint32_t k, uint8_t* c_level,
                    uint32_t* c_sym, hipStream_t s);
-void launch_segments(const uint64_t* off, uint32_t k, const uint64_t* pstart, uint64_t d,
-                     uint64_t* new_off, hipStream_t s);
+void launch_segments(const uint64_t* off, uint32_t k, const uint64_t* bits,
+                     const uint64_t* tile_base, uint64_t d, uint64_t* new_off, hipStream_t s);
 void launch_finish(const uint64_t* off, const uint64_t* new_off, uint32_t k,
                    const uint32_t* sym_next, uint32_t level, uint8_t* c_level, uint32_t* c_sym,
                    Counters* ctr, hipStream_t s);

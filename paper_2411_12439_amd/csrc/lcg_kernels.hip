@@ -40,6 +40,14 @@ static inline unsigned grid_for(uint64_t n, int block) {
 }
 
 // ------------------------------------------------------------------ helpers
+// A plain load, served by the CU's L1 and allowed to return a stale value.
+// Used where a stale value only costs extra work (an empty slot word leads to
+// the compare-and-swap, an uncommitted rank to the first-occurrence count, a
+// larger first occurrence to an atomicMin).
+template <typename T>
+__device__ __forceinline__ T hint_load(const T* p) {
+  return *p;
+}
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
@@ -129,6 +137,27 @@ __device__ __forceinline__ uint64_t make_key(const void* sym, uint64_t p, uint64
   return long_key(P, key_bits);
 }
 
+// Length of a phrase from its key (exact keys) or from plen (long keys).
+template <bool BYTES>
+__device__ __forceinline__ uint32_t key_len(uint64_t kk, const uint32_t* plen, uint64_t o) {
+  if (kk & kLongTag) return plen[o];
+  return BYTES ? (uint32_t)((kk >> 56) & 7) : (uint32_t)((kk >> 58) & 7);
+}
+
+// Symbol x of a phrase with an exact key.
+template <bool BYTES>
+__device__ __forceinline__ uint32_t key_sym(uint64_t kk, uint32_t x) {
+  if constexpr (BYTES) {
+    return (uint32_t)((kk >> (8 * x)) & 0xFF);
+  } else {
+    const uint32_t q = (uint32_t)((kk >> 58) & 7);
+    const int rb = rank_bits_for(q);
+    const uint64_t payload = kk & ((1ULL << 58) - 1);
+    const uint64_t m = rb == 32 ? 0xFFFFFFFFULL : ((1ULL << rb) - 1);
+    return (uint32_t)((payload >> (rb * (q - 1 - x))) & m);
+  }
+}
+
 // ------------------------------------------------------------------ small kernels
 __global__ void k_f0_lut(uint32_t* lut, uint64_t a0, uint64_t b0) {
   const uint64_t s = threadIdx.x;
@@ -174,32 +203,87 @@ void launch_zero(void* p, size_t bytes, hipStream_t s) {
 // or l is LMS-type (Eq. 3): F[l-1] > F[l] and the first position r > l with
 // F[r] != F[l] lies inside the segment and has F[r] > F[l].  Positions of the
 // trailing equal run never qualify: there r does not exist.
+//
+// The tile's fingerprints (one position to the left, kRightHalo to the right)
+// are staged in LDS with wide loads; each thread then classifies 16
+// consecutive positions from its 18-value window.
+constexpr int kRightHalo = 64;
+constexpr int kCStage = kTile + 1 + kRightHalo;  // s_f[i] is position t0 - 1 + i
+
+template <bool BYTES>
+__device__ __forceinline__ void stage_fp(const RoundIn& in, const uint32_t* s_lut, uint64_t t0,
+                                         uint32_t* s_f) {
+  // main tile: positions t0 .. t0 + kTile - 1 -> s_f[1 .. kTile]
+  const uint64_t lim = in.n - t0 < (uint64_t)kTile ? in.n - t0 : (uint64_t)kTile;
+  if constexpr (BYTES) {
+    const uint8_t* src = static_cast<const uint8_t*>(in.sym) + t0;
+    const uint32_t i = threadIdx.x * 16;
+    if ((reinterpret_cast<uintptr_t>(src) & 15) == 0 && i + 16 <= lim) {
+      const uint4 v = *reinterpret_cast<const uint4*>(src + i);
+      const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int x = 0; x < 16; ++x) s_f[1 + i + x] = s_lut[(wv[x >> 2] >> (8 * (x & 3))) & 0xFF];
+    } else {
+      for (uint32_t x = i; x < i + 16 && x < lim; ++x) s_f[1 + x] = s_lut[src[x]];
+    }
+  } else {
+    const uint32_t* src = in.fp + t0;
+    if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+      for (uint32_t i = threadIdx.x * 4; i < kTile; i += kBlock * 4) {
+        if (i + 4 <= lim) {
+          const uint4 v = *reinterpret_cast<const uint4*>(src + i);
+          s_f[1 + i] = v.x;
+          s_f[2 + i] = v.y;
+          s_f[3 + i] = v.z;
+          s_f[4 + i] = v.w;
+        } else {
+          for (uint32_t x = i; x < i + 4 && x < lim; ++x) s_f[1 + x] = src[x];
+        }
+      }
+    } else {
+      for (uint32_t i = threadIdx.x; i < lim; i += kBlock) s_f[1 + i] = src[i];
+    }
+  }
+  // left neighbour and right halo
+  if (threadIdx.x == 0) s_f[0] = t0 > 0 ? fval<BYTES>(in, s_lut, t0 - 1) : 0u;
+  if (threadIdx.x < kRightHalo) {
+    const uint64_t p = t0 + kTile + threadIdx.x;
+    s_f[1 + kTile + threadIdx.x] = p < in.n ? fval<BYTES>(in, s_lut, p) : 0u;
+  }
+}
+
 template <bool BYTES>
 __global__ __launch_bounds__(kBlock) void k_classify(RoundIn in, uint64_t* __restrict__ bits,
-                                                     uint64_t* __restrict__ tile_cnt) {
+                                                     uint64_t* __restrict__ tile_cnt,
+                                                     uint2* __restrict__ tile_seg) {
   __shared__ uint32_t s_lut[256];
+  __shared__ uint32_t s_f[kCStage];
   __shared__ uint32_t s_seg[2];
   __shared__ uint32_t s_mask[kBlock];
   __shared__ uint32_t s_cnt;
   const uint64_t t0 = (uint64_t)blockIdx.x * kTile;
-  if constexpr (BYTES) s_lut[threadIdx.x] = in.lut[threadIdx.x];
+  if constexpr (BYTES) {
+    s_lut[threadIdx.x] = in.lut[threadIdx.x];
+    __syncthreads();
+  }
+  // wave 0 finds the strings the tile overlaps while the others stage it
   if (threadIdx.x == 0) {
     uint64_t tl = (t0 + kTile < in.n ? t0 + kTile : in.n) - 1;
     uint32_t lo = seg_search(in.off, 0, in.k - 1, t0);
+    uint32_t hi = seg_search(in.off, lo, in.k - 1, tl);
     s_seg[0] = lo;
-    s_seg[1] = seg_search(in.off, lo, in.k - 1, tl);
+    s_seg[1] = hi;
     s_cnt = 0;
+    tile_seg[blockIdx.x] = make_uint2(lo, hi);
   }
+  stage_fp<BYTES>(in, s_lut, t0, s_f);
   __syncthreads();
   const uint64_t b = t0 + (uint64_t)threadIdx.x * kItems;
   uint32_t mask = 0;
   if (b < in.n) {
     uint32_t fw[kItems + 2];
 #pragma unroll
-    for (int x = 0; x < kItems + 2; ++x) {
-      uint64_t p = b - 1 + x;  // b - 1 wraps for b = 0 and is then out of range
-      fw[x] = p < in.n ? fval<BYTES>(in, s_lut, p) : 0u;
-    }
+    for (int x = 0; x < kItems + 2; ++x) fw[x] = s_f[threadIdx.x * kItems + x];  // position b - 1 + x
     uint32_t desc = 0, eq = 0, gt = 0;
 #pragma unroll
     for (int x = 0; x < kItems; ++x) {
@@ -227,11 +311,19 @@ __global__ __launch_bounds__(kBlock) void k_classify(RoundIn in, uint64_t* __res
           uint64_t r = l + y + 1;
           brk = r < s_end && ((gt >> (x + y)) & 1u);
         } else {
-          // the run continues past the window: walk it in memory
-          const uint32_t fl = fval<BYTES>(in, s_lut, l);
+          // the run continues past the window: walk it (LDS, then memory)
+          // F[l] .. F[b + kItems] are all equal, the last one is fw[kItems + 1]
+          const uint32_t fl = fw[kItems + 1];
           uint64_t r = b + kItems + 1;
-          while (r < s_end && fval<BYTES>(in, s_lut, r) == fl) ++r;
-          brk = r < s_end && fval<BYTES>(in, s_lut, r) > fl;
+          uint32_t fr = 0;
+          bool more = true;
+          while (more && r < s_end) {
+            const uint64_t i = r - t0 + 1;
+            fr = i < (uint64_t)kCStage ? s_f[i] : fval<BYTES>(in, s_lut, r);
+            more = fr == fl;
+            r += more ? 1 : 0;
+          }
+          brk = r < s_end && fr > fl;
         }
       }
       mask |= (uint32_t)brk << x;
@@ -249,11 +341,12 @@ __global__ __launch_bounds__(kBlock) void k_classify(RoundIn in, uint64_t* __res
   if (threadIdx.x == 0) tile_cnt[blockIdx.x] = s_cnt;
 }
 
-void launch_classify(const RoundIn& in, uint64_t* bits, uint64_t* tile_cnt, hipStream_t s) {
+void launch_classify(const RoundIn& in, uint64_t* bits, uint64_t* tile_cnt, uint2* tile_seg,
+                     hipStream_t s) {
   static_assert(kItems == 16 && kBlock == 256, "bit packing assumes 16 positions per thread");
   unsigned tiles = grid_for(in.n, kTile);
-  if (in.bytes) k_classify<true><<<tiles, kBlock, 0, s>>>(in, bits, tile_cnt);
-  else k_classify<false><<<tiles, kBlock, 0, s>>>(in, bits, tile_cnt);
+  if (in.bytes) k_classify<true><<<tiles, kBlock, 0, s>>>(in, bits, tile_cnt, tile_seg);
+  else k_classify<false><<<tiles, kBlock, 0, s>>>(in, bits, tile_cnt, tile_seg);
   LCG_LAUNCH_CHECK("classify");
 }
 
@@ -322,7 +415,8 @@ __device__ __forceinline__ void stage_tile(const RoundIn& in, uint64_t t0, EmitS
 
 template <bool BYTES>
 __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in, const uint64_t* __restrict__ bits,
-                                                 const uint64_t* __restrict__ tile_base, uint64_t tiles,
+                                                 const uint64_t* __restrict__ tile_base,
+                                                 const uint2* __restrict__ tile_seg, uint64_t tiles,
                                                  LevelHash h, uint32_t key_bits,
                                                  uint64_t* __restrict__ pstart, uint32_t* __restrict__ plen,
                                                  uint64_t* __restrict__ key, uint32_t* __restrict__ fnew,
@@ -340,10 +434,9 @@ __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in, const uint64_t* __r
     const uint64_t t0 = tile * kTile;
     __syncthreads();
     if (threadIdx.x == 0) {
-      uint64_t tl = (t0 + kTile < in.n ? t0 + kTile : in.n) - 1;
-      uint32_t lo = seg_search(in.off, 0, in.k - 1, t0);
-      s_seg[0] = lo;
-      s_seg[1] = seg_search(in.off, lo, in.k - 1, tl);
+      const uint2 r = tile_seg[tile];
+      s_seg[0] = r.x;
+      s_seg[1] = r.y;
     }
     stage_tile<BYTES>(in, t0, st);
     uint32_t mask = (uint32_t)(bits[tile * kTileWords + threadIdx.x / 4] >> ((threadIdx.x & 3) * 16)) &
@@ -401,8 +494,12 @@ __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in, const uint64_t* __r
         kk = make_key<BYTES>(in.sym, l, q, P, key_bits);
       }
       const uint64_t o = base + jj;
-      pstart[o] = l;
-      plen[o] = (uint32_t)q;
+      // a short phrase's length and content are in its exact key; only long
+      // phrases (compared in full) need their position and length
+      if (kk & kLongTag) {
+        pstart[o] = l;
+        plen[o] = (uint32_t)q;
+      }
       key[o] = kk;
       fnew[o] = (uint32_t)(P & 0xFFFFFFFFULL);
       const uint64_t hh = mix64(probe_key(kk));
@@ -435,20 +532,23 @@ __global__ __launch_bounds__(256) void k_hll_reduce(const uint8_t* __restrict__ 
   if (threadIdx.x == 0) ctr->hll[i] = s_max;
 }
 
-void launch_emit(const RoundIn& in, const uint64_t* bits, const uint64_t* tile_base, LevelHash h,
+void launch_emit(const RoundIn& in, const uint64_t* bits, const uint64_t* tile_base,
+                 const uint2* tile_seg, LevelHash h,
                  uint32_t key_bits, uint64_t* pstart, uint32_t* plen, uint64_t* key, uint32_t* fnew,
                  uint8_t* hll_part, Counters* ctr, hipStream_t s) {
   uint64_t tiles = grid_for(in.n, kTile);
   unsigned g = tiles > kEmitBlocks ? kEmitBlocks : (unsigned)tiles;
   if (in.bytes)
-    k_emit<true><<<g, kBlock, 0, s>>>(in, bits, tile_base, tiles, h, key_bits, pstart, plen, key,
+    k_emit<true><<<g, kBlock, 0, s>>>(in, bits, tile_base, tile_seg, tiles, h, key_bits, pstart, plen, key,
                                       fnew, hll_part);
   else
-    k_emit<false><<<g, kBlock, 0, s>>>(in, bits, tile_base, tiles, h, key_bits, pstart, plen, key,
+    k_emit<false><<<g, kBlock, 0, s>>>(in, bits, tile_base, tile_seg, tiles, h, key_bits, pstart, plen, key,
                                        fnew, hll_part);
   LCG_LAUNCH_CHECK("emit");
-  k_hll_reduce<<<kHll, 256, 0, s>>>(hll_part, g, ctr);
-  LCG_LAUNCH_CHECK("hll_reduce");
+  if (ctr) {
+    k_hll_reduce<<<kHll, 256, 0, s>>>(hll_part, g, ctr);
+    LCG_LAUNCH_CHECK("hll_reduce");
+  }
 }
 
 // ------------------------------------------------------------------ scan
@@ -527,6 +627,17 @@ __device__ __forceinline__ bool same_seq(const Sym* a, const Sym* b, uint32_t le
 // with a plain (L1-cacheable) load: frequent short phrases are then served by
 // each CU's L1 instead of one L2 line.  A stale empty word only sends the
 // thread to the compare-and-swap, which returns the current value.
+// Insert-or-find every phrase.  A claimed slot keeps the claimer's key; a
+// long phrase whose 31 key bits match is compared symbol by symbol against
+// the slot's phrase (the claiming occurrence, or the committed rule).
+//
+// kBatch phrases per thread and iteration (their keys and home slots are
+// loaded together); 1 measured fastest on gfx950, larger batches cost more in
+// occupancy than they gain in overlap.  The probe loop is written out in the
+// kernel body with a single exit: the gfx950 code of the same loop placed in
+// a helper function with counters passed by reference lost its result.
+constexpr int kBatch = 1;
+
 template <typename Sym>
 __global__ __launch_bounds__(256) void k_insert(uint64_t d, const uint64_t* __restrict__ key,
                                                 const uint64_t* __restrict__ pstart,
@@ -541,75 +652,92 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t d, const uint64_t* __re
   if (threadIdx.x < 4) s_sum[threadIdx.x] = 0;
   __syncthreads();
   unsigned long long won = 0, probes = 0, cmps = 0, fails = 0;
-  for (uint64_t o = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; o < d;
-       o += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t kk = key[o];
-    const bool is_long = (kk & kLongTag) != 0;
-    const uint64_t want = is_long ? (kk | o) : kk;
-    uint64_t my_pos = 0;
-    uint32_t my_len = 0;
-    if (is_long) {
-      my_pos = pstart[o];
-      my_len = plen[o];
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; base < d;
+       base += stride * kBatch) {
+    uint64_t kk[kBatch], hpos[kBatch], hw[kBatch];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const uint64_t o = base + b * stride;
+      kk[b] = o < d ? key[o] : 0;
     }
-    uint64_t pos = mix64(kk) & mask;
-    uint32_t result = kNone;
-    // single-exit probe loop: a slot is taken (claimed or matched) or the
-    // probe budget runs out
-    for (uint32_t probe = 0; probe < kMaxProbe && result == kNone; ++probe) {
-      Slot* sl = &table[pos];
-      ++probes;
-      uint64_t w = sl->w0;
-      bool hit = false;
-      if (w == kEmpty) {
-        unsigned long long prev =
-            atomicCAS(reinterpret_cast<unsigned long long*>(&sl->w0), (unsigned long long)kEmpty,
-                      (unsigned long long)want);
-        if (prev == kEmpty) {
-          hit = true;
-          ++won;
-        } else {
-          w = prev;
-        }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      hpos[b] = mix64(kk[b]) & mask;
+      hw[b] = base + b * stride < d ? hint_load(&table[hpos[b]].w0) : kEmpty;
+    }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const uint64_t o = base + b * stride;
+      if (o >= d) continue;
+      const bool is_long = (kk[b] & kLongTag) != 0;
+      const uint64_t want = is_long ? (kk[b] | o) : kk[b];
+      uint64_t my_pos = 0;
+      uint32_t my_len = 0;
+      if (is_long) {
+        my_pos = pstart[o];
+        my_len = plen[o];
       }
-      if (!hit) {
-        if (!is_long) {
-          hit = w == kk;
-        } else if ((w & kHiMask) == kk) {
-          const uint32_t rk = sl->rank;
-          const uint32_t ref = (uint32_t)w;
-          // a committed rule is compared with its stored right-hand side, a
-          // slot claimed in this pass with the claiming occurrence; anything
-          // else (a slot left by an interrupted call) cannot match
-          const bool committed = rk != kNone && rk < u_committed;
-          const bool inflight = rk == kNone && ref < d;
-          uint64_t opos = 0;
-          uint32_t olen = 0xFFFFFFFFu;
-          const Sym* arr = content;
-          if (committed) {
-            opos = rule_off[rk];
-            olen = (uint32_t)(rule_off[rk + 1] - opos);
-            arr = rule_rhs;
-          } else if (inflight) {
-            opos = pstart[ref];
-            olen = plen[ref];
+      uint64_t pos = hpos[b];
+      uint64_t w = hw[b];
+      uint32_t result = kNone;
+      for (uint32_t probe = 0; probe < kMaxProbe && result == kNone; ++probe) {
+        Slot* sl = &table[pos];
+        ++probes;
+        if (probe) w = hint_load(&sl->w0);
+        bool hit = false;
+        if (w == kEmpty) {
+          unsigned long long prev =
+              atomicCAS(reinterpret_cast<unsigned long long*>(&sl->w0), (unsigned long long)kEmpty,
+                        (unsigned long long)want);
+          if (prev == kEmpty) {
+            hit = true;
+            ++won;
+          } else {
+            w = prev;
           }
-          ++cmps;
-          hit = olen == my_len && same_seq<Sym>(content + my_pos, arr + opos, my_len);
         }
+        if (!hit) {
+          if (!is_long) {
+            hit = w == kk[b];
+          } else if ((w & kHiMask) == kk[b]) {
+            const uint32_t rk = hint_load(&sl->rank);
+            const uint32_t ref = (uint32_t)w;
+            // a committed rule is compared with its stored right-hand side, a
+            // slot claimed in this pass with the claiming occurrence; anything
+            // else (a slot left by an interrupted call) cannot match
+            const bool committed = rk != kNone && rk < u_committed;
+            const bool inflight = rk == kNone && ref < d;
+            uint64_t opos = 0;
+            uint32_t olen = 0xFFFFFFFFu;
+            const Sym* arr = content;
+            if (committed) {
+              opos = rule_off[rk];
+              olen = (uint32_t)(rule_off[rk + 1] - opos);
+              arr = rule_rhs;
+            } else if (inflight) {
+              opos = pstart[ref];
+              olen = plen[ref];
+            }
+            ++cmps;
+            hit = olen == my_len && same_seq<Sym>(content + my_pos, arr + opos, my_len);
+          }
+        }
+        if (hit) result = (uint32_t)pos;
+        else pos = (pos + 1) & mask;
       }
-      if (hit) result = (uint32_t)pos;
-      else pos = (pos + 1) & mask;
+      if (result == kNone) {
+        ++fails;
+      } else {
+        Slot* sl = &table[result];
+        // (first occurrence, rank) in one load; a stale (larger) first
+        // occurrence only costs an unneeded atomicMin
+        const uint64_t mr = hint_load(reinterpret_cast<const uint64_t*>(&sl->minocc));
+        if ((uint32_t)(mr >> 32) == kNone && (uint32_t)mr > (uint32_t)o)
+          atomicMin(&sl->minocc, (uint32_t)o);
+      }
+      slot_idx[o] = result;
     }
-    if (result == kNone) {
-      ++fails;
-    } else {
-      Slot* sl = &table[result];
-      if (sl->rank == kNone &&
-          __hip_atomic_load(&sl->minocc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > (uint32_t)o)
-        atomicMin(&sl->minocc, (uint32_t)o);
-    }
-    slot_idx[o] = result;
   }
   // one global atomic per block and counter
   won = wave_sum(won);
@@ -636,22 +764,25 @@ void launch_insert(bool bytes, uint64_t d, const uint64_t* key, const uint64_t* 
                    const void* rule_rhs, uint32_t u_committed, Slot* table, uint64_t mask,
                    uint32_t* slot_idx, Counters* ctr, hipStream_t s) {
   if (!d) return;
-  unsigned g = grid_for(d, 256);
+  unsigned g = grid_for(d, 256 * kBatch);
   if (g > kPersistentBlocks) g = kPersistentBlocks;
   if (bytes)
-    k_insert<uint8_t><<<g, 256, 0, s>>>(
-        d, key, pstart, plen, static_cast<const uint8_t*>(content), rule_off,
-        static_cast<const uint8_t*>(rule_rhs), u_committed, table, mask, slot_idx, ctr);
+    k_insert<uint8_t><<<g, 256, 0, s>>>(d, key, pstart, plen, static_cast<const uint8_t*>(content),
+                                        rule_off, static_cast<const uint8_t*>(rule_rhs),
+                                        u_committed, table, mask, slot_idx, ctr);
   else
-    k_insert<uint32_t><<<g, 256, 0, s>>>(
-        d, key, pstart, plen, static_cast<const uint32_t*>(content), rule_off,
-        static_cast<const uint32_t*>(rule_rhs), u_committed, table, mask, slot_idx, ctr);
+    k_insert<uint32_t><<<g, 256, 0, s>>>(d, key, pstart, plen,
+                                         static_cast<const uint32_t*>(content), rule_off,
+                                         static_cast<const uint32_t*>(rule_rhs), u_committed,
+                                         table, mask, slot_idx, ctr);
   LCG_LAUNCH_CHECK("insert");
 }
 
 // ------------------------------------------------------------------ newflags
+template <bool BYTES>
 __global__ __launch_bounds__(256) void k_newflags(uint64_t d, const uint32_t* __restrict__ slot_idx,
                                                   const Slot* __restrict__ table,
+                                                  const uint64_t* __restrict__ key,
                                                   const uint32_t* __restrict__ plen,
                                                   uint64_t* __restrict__ newbits,
                                                   uint64_t* __restrict__ wcnt,
@@ -665,7 +796,7 @@ __global__ __launch_bounds__(256) void k_newflags(uint64_t d, const uint32_t* __
       const Slot sl = table[sidx];
       f = sl.rank == kNone && sl.minocc == (uint32_t)o;
     }
-    if (f) len = plen[o];
+    if (f) len = key_len<BYTES>(key[o], plen, o);
   }
   const uint64_t bal = __ballot(f);
   len = wave_sum(len);
@@ -677,83 +808,149 @@ __global__ __launch_bounds__(256) void k_newflags(uint64_t d, const uint32_t* __
   }
 }
 
-void launch_newflags(uint64_t d, const uint32_t* slot_idx, const Slot* table, const uint32_t* plen,
-                     uint64_t* newbits, uint64_t* wcnt, uint64_t* wlen, hipStream_t s) {
+void launch_newflags(bool bytes, uint64_t d, const uint32_t* slot_idx, const Slot* table,
+                     const uint64_t* key, const uint32_t* plen, uint64_t* newbits, uint64_t* wcnt,
+                     uint64_t* wlen, hipStream_t s) {
   if (!d) return;
-  k_newflags<<<grid_for(d, 256), 256, 0, s>>>(d, slot_idx, table, plen, newbits, wcnt, wlen);
+  if (bytes)
+    k_newflags<true><<<grid_for(d, 256), 256, 0, s>>>(d, slot_idx, table, key, plen, newbits, wcnt,
+                                                      wlen);
+  else
+    k_newflags<false><<<grid_for(d, 256), 256, 0, s>>>(d, slot_idx, table, key, plen, newbits,
+                                                       wcnt, wlen);
   LCG_LAUNCH_CHECK("newflags");
 }
 
-// ------------------------------------------------------------------ commit
-__device__ __forceinline__ uint64_t rank1(const uint64_t* newbits, const uint64_t* wcnt_base,
-                                          uint64_t m) {
-  const uint64_t w = newbits[m >> 6] & ((1ULL << (m & 63)) - 1ULL);
-  return wcnt_base[m >> 6] + __builtin_popcountll(w);
+// The same flags from the table side, for tables smaller than the phrase
+// array: every slot claimed in this pass marks its first occurrence.
+// newbits and wlen must be zero on entry.
+template <bool BYTES>
+__global__ __launch_bounds__(256) void k_newflags_table(const Slot* __restrict__ table, uint64_t cap,
+                                                        uint64_t d, const uint64_t* __restrict__ key,
+                                                        const uint32_t* __restrict__ plen,
+                                                        unsigned long long* __restrict__ newbits,
+                                                        unsigned long long* __restrict__ wlen) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const Slot sl = table[i];
+    if (sl.w0 == kEmpty || sl.rank != kNone || sl.minocc >= d) continue;
+    const uint64_t m = sl.minocc;
+    atomicOr(&newbits[m >> 6], 1ULL << (m & 63));
+    atomicAdd(&wlen[m >> 6], (unsigned long long)key_len<BYTES>(key[m], plen, m));
+  }
 }
 
+__global__ void k_word_counts(const uint64_t* __restrict__ newbits, uint64_t W,
+                              uint64_t* __restrict__ wcnt) {
+  const uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (w < W) wcnt[w] = __builtin_popcountll(newbits[w]);
+}
+
+void launch_newflags_table(bool bytes, const Slot* table, uint64_t cap, uint64_t d,
+                           const uint64_t* key, const uint32_t* plen, uint64_t* newbits,
+                           uint64_t* wcnt, uint64_t* wlen, hipStream_t s) {
+  if (!d) return;
+  const uint64_t W = (d + 63) / 64;
+  launch_zero(newbits, W * 8, s);
+  launch_zero(wlen, W * 8, s);
+  unsigned g = grid_for(cap, 256);
+  if (g > 8192) g = 8192;
+  if (bytes)
+    k_newflags_table<true><<<g, 256, 0, s>>>(table, cap, d, key, plen,
+                                            reinterpret_cast<unsigned long long*>(newbits),
+                                            reinterpret_cast<unsigned long long*>(wlen));
+  else
+    k_newflags_table<false><<<g, 256, 0, s>>>(table, cap, d, key, plen,
+                                             reinterpret_cast<unsigned long long*>(newbits),
+                                             reinterpret_cast<unsigned long long*>(wlen));
+  LCG_LAUNCH_CHECK("newflags_table");
+  k_word_counts<<<grid_for(W, 256), 256, 0, s>>>(newbits, W, wcnt);
+  LCG_LAUNCH_CHECK("word_counts");
+}
+
+// ------------------------------------------------------------------ commit
+__device__ __forceinline__ unsigned long long wave_excl_scan(unsigned long long v) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long x = v;
+#pragma unroll
+  for (int k = 1; k < 64; k <<= 1) {
+    unsigned long long y = __shfl_up(x, k, 64);
+    if (lane >= k) x += y;
+  }
+  return x - v;
+}
+
+// New rules: the first occurrence of every new phrase appends the rule.  The
+// wave of 64 consecutive phrases is exactly one flag word, so the offset of
+// its right-hand side is the word's scanned length plus a wave scan.
 template <typename Sym>
-__global__ __launch_bounds__(256) void k_commit(uint64_t d, const uint32_t* __restrict__ slot_idx,
-                                                Slot* table, const uint64_t* __restrict__ newbits,
-                                                const uint64_t* __restrict__ wcnt_base,
-                                                const uint64_t* __restrict__ wlen_base,
-                                                const uint64_t* __restrict__ pstart,
-                                                const uint32_t* __restrict__ plen,
-                                                const Sym* __restrict__ content,
-                                                const uint32_t* __restrict__ fnew, uint32_t u_prev,
-                                                uint64_t q_prev, uint64_t* __restrict__ rule_off,
-                                                Sym* __restrict__ rule_rhs,
-                                                uint32_t* __restrict__ rule_fp,
-                                                uint32_t* __restrict__ sym_next) {
+__global__ __launch_bounds__(256) void k_commit_new(uint64_t d, const uint32_t* __restrict__ slot_idx,
+                                                    Slot* table, const uint64_t* __restrict__ newbits,
+                                                    const uint64_t* __restrict__ wcnt_base,
+                                                    const uint64_t* __restrict__ wlen_base,
+                                                    const uint64_t* __restrict__ key,
+                                                    const uint64_t* __restrict__ pstart,
+                                                    const uint32_t* __restrict__ plen,
+                                                    const Sym* __restrict__ content,
+                                                    const uint32_t* __restrict__ fnew, uint32_t u_prev,
+                                                    uint64_t q_prev, uint64_t* __restrict__ rule_off,
+                                                    Sym* __restrict__ rule_rhs,
+                                                    uint32_t* __restrict__ rule_fp) {
+  constexpr bool kBytes = sizeof(Sym) == 1;
+  const uint64_t o = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t w = o < d ? newbits[o >> 6] : 0;
+  const bool isnew = (w >> (o & 63)) & 1ULL;
+  const uint64_t kk = isnew ? key[o] : 0;
+  const uint32_t L = isnew ? key_len<kBytes>(kk, plen, o) : 0;
+  const unsigned long long excl = wave_excl_scan(L);
+  if (!isnew) return;
+  const uint32_t r = u_prev + (uint32_t)(wcnt_base[o >> 6] +
+                                         __builtin_popcountll(w & ((1ULL << (o & 63)) - 1ULL)));
+  const uint64_t q = q_prev + wlen_base[o >> 6] + excl;
+  if (kk & kLongTag) {
+    const Sym* src = content + pstart[o];
+    for (uint32_t i = 0; i < L; ++i) rule_rhs[q + i] = src[i];
+  } else {
+    for (uint32_t i = 0; i < L; ++i) rule_rhs[q + i] = (Sym)key_sym<kBytes>(kk, i);
+  }
+  rule_off[r + 1] = q + L;
+  rule_fp[r] = fnew[o];
+  Slot* sl = &table[slot_idx[o]];
+  sl->rank = r;
+  const uint64_t w0 = sl->w0;
+  if (w0 & kLongTag) sl->w0 = (w0 & kHiMask) | r;
+}
+
+// T^{i+1}: every phrase takes the (now committed) rank of its slot.
+__global__ __launch_bounds__(256) void k_rewrite(uint64_t d, const uint32_t* __restrict__ slot_idx,
+                                                 const Slot* __restrict__ table,
+                                                 uint32_t* __restrict__ sym_next) {
   const uint64_t o = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (o >= d) return;
   const uint32_t sidx = slot_idx[o];
-  if (sidx == kNone) {  // only after an overflow; the round is then redone
-    sym_next[o] = 0;
-    return;
-  }
-  Slot* sl = &table[sidx];
-  // a rank committed concurrently by the first occurrence may not be seen yet;
-  // the first-occurrence count gives the same rank
-  uint32_t r = sl->rank;
-  if (r == kNone) r = u_prev + (uint32_t)rank1(newbits, wcnt_base, sl->minocc);
-  sym_next[o] = r;
-  const uint64_t w = newbits[o >> 6];
-  if ((w >> (o & 63)) & 1ULL) {
-    uint64_t below = w & ((1ULL << (o & 63)) - 1ULL);
-    uint64_t q = q_prev + wlen_base[o >> 6];
-    const uint64_t wbase = o & ~63ULL;
-    while (below) {
-      q += plen[wbase + __builtin_ctzll(below)];
-      below &= below - 1;
-    }
-    const uint32_t L = plen[o];
-    const Sym* src = content + pstart[o];
-    for (uint32_t i = 0; i < L; ++i) rule_rhs[q + i] = src[i];
-    rule_off[r + 1] = q + L;
-    rule_fp[r] = fnew[o];
-    __hip_atomic_store(&sl->rank, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint64_t w0 = sl->w0;
-    if (w0 & kLongTag) sl->w0 = (w0 & kHiMask) | r;
-  }
+  sym_next[o] = sidx == kNone ? 0u : table[sidx].rank;  // kNone only after an overflow (redone)
 }
 
 void launch_commit(bool bytes, uint64_t d, const uint32_t* slot_idx, Slot* table,
                    const uint64_t* newbits, const uint64_t* wcnt_base, const uint64_t* wlen_base,
-                   const uint64_t* pstart, const uint32_t* plen, const void* content,
+                   const uint64_t* key, const uint64_t* pstart, const uint32_t* plen,
+                   const void* content,
                    const uint32_t* fnew, uint32_t u_prev, uint64_t q_prev, uint64_t* rule_off,
                    void* rule_rhs, uint32_t* rule_fp, uint32_t* sym_next, hipStream_t s) {
   if (!d) return;
   if (bytes)
-    k_commit<uint8_t><<<grid_for(d, 256), 256, 0, s>>>(
-        d, slot_idx, table, newbits, wcnt_base, wlen_base, pstart, plen,
+    k_commit_new<uint8_t><<<grid_for(d, 256), 256, 0, s>>>(
+        d, slot_idx, table, newbits, wcnt_base, wlen_base, key, pstart, plen,
         static_cast<const uint8_t*>(content), fnew, u_prev, q_prev, rule_off,
-        static_cast<uint8_t*>(rule_rhs), rule_fp, sym_next);
+        static_cast<uint8_t*>(rule_rhs), rule_fp);
   else
-    k_commit<uint32_t><<<grid_for(d, 256), 256, 0, s>>>(
-        d, slot_idx, table, newbits, wcnt_base, wlen_base, pstart, plen,
+    k_commit_new<uint32_t><<<grid_for(d, 256), 256, 0, s>>>(
+        d, slot_idx, table, newbits, wcnt_base, wlen_base, key, pstart, plen,
         static_cast<const uint32_t*>(content), fnew, u_prev, q_prev, rule_off,
-        static_cast<uint32_t*>(rule_rhs), rule_fp, sym_next);
-  LCG_LAUNCH_CHECK("commit");
+        static_cast<uint32_t*>(rule_rhs), rule_fp);
+  LCG_LAUNCH_CHECK("commit_new");
+  k_rewrite<<<grid_for(d, 256), 256, 0, s>>>(d, slot_idx, table, sym_next);
+  LCG_LAUNCH_CHECK("rewrite");
 }
 
 // ------------------------------------------------------------------ rehash
@@ -805,9 +1002,11 @@ void launch_c_init(const uint8_t* text, const uint64_t* off, uint32_t k, uint8_t
   LCG_LAUNCH_CHECK("c_init");
 }
 
+// Next-round offsets: the phrases of string j start at the number of breaks
+// before its first position (tile prefix + popcount inside the tile).
 __global__ void k_segments(const uint64_t* __restrict__ off, uint32_t k,
-                           const uint64_t* __restrict__ pstart, uint64_t d,
-                           uint64_t* __restrict__ new_off) {
+                           const uint64_t* __restrict__ bits, const uint64_t* __restrict__ tile_base,
+                           uint64_t d, uint64_t* __restrict__ new_off) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j > k) return;
   if (j == k) {
@@ -815,17 +1014,16 @@ __global__ void k_segments(const uint64_t* __restrict__ off, uint32_t k,
     return;
   }
   const uint64_t x = off[j];
-  uint64_t lo = 0, hi = d;
-  while (lo < hi) {
-    uint64_t mid = (lo + hi) >> 1;
-    if (pstart[mid] < x) lo = mid + 1; else hi = mid;
-  }
-  new_off[j] = lo;
+  const uint64_t tile = x / kTile;
+  uint64_t r = tile_base[tile];
+  for (uint64_t wd = tile * kTileWords; wd < (x >> 6); ++wd) r += __builtin_popcountll(bits[wd]);
+  if (x & 63) r += __builtin_popcountll(bits[x >> 6] & ((1ULL << (x & 63)) - 1ULL));
+  new_off[j] = r;
 }
 
-void launch_segments(const uint64_t* off, uint32_t k, const uint64_t* pstart, uint64_t d,
-                     uint64_t* new_off, hipStream_t s) {
-  k_segments<<<grid_for((uint64_t)k + 1, 256), 256, 0, s>>>(off, k, pstart, d, new_off);
+void launch_segments(const uint64_t* off, uint32_t k, const uint64_t* bits,
+                     const uint64_t* tile_base, uint64_t d, uint64_t* new_off, hipStream_t s) {
+  k_segments<<<grid_for((uint64_t)k + 1, 256), 256, 0, s>>>(off, k, bits, tile_base, d, new_off);
   LCG_LAUNCH_CHECK("segments");
 }
 

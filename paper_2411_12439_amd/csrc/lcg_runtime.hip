@@ -317,6 +317,7 @@ struct Work {
   DBuf<uint32_t> lut;
   DBuf<Counters> ctr, fin;
   DBuf<uint8_t> content8, hll_part;
+  DBuf<uint2> tile_seg;
   DBuf<uint32_t> content32, remap[2];
   void release_after(hipStream_t s) {
     DBuf<uint64_t>* b64[] = {&bits, &tile_cnt, &tile_base, &scan_tmp, &pstart, &key, &off[0],
@@ -329,10 +330,30 @@ struct Work {
     fin.reset_after(s);
     content8.reset_after(s);
     hll_part.reset_after(s);
+    tile_seg.reset_after(s);
   }
 };
 
 static void zero_counters(Counters* c, hipStream_t s) { launch_zero(c, sizeof(Counters), s); }
+
+// Pinned host landing area of the per-round readbacks (one per host thread,
+// kept for the life of the process): pageable destinations would make every
+// small device-to-host copy go through a staging buffer.
+struct Mailbox {
+  Counters ctr;
+  Counters fin;
+  uint64_t d, u_new, q_new;
+};
+
+static Mailbox* mailbox() {
+  static thread_local Mailbox* mb = nullptr;
+  if (!mb) {
+    void* p = nullptr;
+    HIP_CHECK(hipHostMalloc(&p, sizeof(Mailbox), hipHostMallocDefault));
+    mb = static_cast<Mailbox*>(p);
+  }
+  return mb;
+}
 
 // LCG_DEBUG=1 in the environment traces the per-round planning on stderr.
 static bool debug_on() {
@@ -385,7 +406,10 @@ static void ensure_table(Level& L, uint64_t need, uint32_t min_log2, Work& w, hi
   if (L.tcap && L.u) {
     zero_counters(w.ctr.p, s);
     launch_rehash(L.table.p, L.tcap, nt.p, want - 1, w.ctr.p, s);
-    if (read_dev(&w.ctr.p->overflow, s)) throw LcgError{LCG_ETABLE, "rehash failed"};
+    Mailbox* mb = mailbox();
+    HIP_CHECK(hipMemcpyAsync(&mb->ctr, w.ctr.p, offsetof(Counters, hll), hipMemcpyDeviceToHost, s));
+    sync(s);
+    if (mb->ctr.overflow) throw LcgError{LCG_ETABLE, "rehash failed"};
   }
   L.table.reset_after(s);
   L.table = std::move(nt);
@@ -425,7 +449,8 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
   w.wcnt_base.need(W + 1, s);
   w.wlen_base.need(W + 1, s);
   w.scan_tmp.need(std::max<size_t>(scan_tmp_words(W), 1), s);
-  Counters hc;
+  Mailbox* mb = mailbox();
+  Counters& hc = mb->ctr;
   uint64_t u_new = 0, q_new = 0;
   for (int attempt = 0;; ++attempt) {
     zero_counters(w.ctr.p, s);
@@ -434,14 +459,24 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
     launch_insert(bytes, d, w.key.p, w.pstart.p, w.plen.p, content, L.off.p, rule_rhs, L.u,
                   L.table.p, L.tcap - 1, w.slot_idx.p, w.ctr.p, s);
     if (pe) pe->rec(4, s);
-    launch_newflags(d, w.slot_idx.p, L.table.p, w.plen.p, w.newbits.p, w.wcnt.p, w.wlen.p, s);
+    // first occurrences from the table side when the table is much smaller
+    // than the phrase array (a scan of the table plus one atomic per new rule
+    // against one random slot read per phrase)
+    if (2 * L.tcap <= d)
+      launch_newflags_table(bytes, L.table.p, L.tcap, d, w.key.p, w.plen.p, w.newbits.p, w.wcnt.p,
+                            w.wlen.p, s);
+    else
+      launch_newflags(bytes, d, w.slot_idx.p, L.table.p, w.key.p, w.plen.p, w.newbits.p, w.wcnt.p,
+                      w.wlen.p, s);
     scan_exclusive(w.wcnt.p, w.wcnt_base.p, W, w.scan_tmp.p, s);
     scan_exclusive(w.wlen.p, w.wlen_base.p, W, w.scan_tmp.p, s);
     if (pe) pe->rec(5, s);
     HIP_CHECK(hipMemcpyAsync(&hc, w.ctr.p, offsetof(Counters, hll), hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipMemcpyAsync(&u_new, w.wcnt_base.p + W, 8, hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipMemcpyAsync(&q_new, w.wlen_base.p + W, 8, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(&mb->u_new, w.wcnt_base.p + W, 8, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(&mb->q_new, w.wlen_base.p + W, 8, hipMemcpyDeviceToHost, s));
     sync(s);
+    u_new = mb->u_new;
+    q_new = mb->q_new;
     if (debug_on())
       std::fprintf(stderr, "[lcg] level %u attempt %d: d=%llu est=%llu cap=%llu won=%llu probes=%llu cmp=%llu overflow=%u\n",
                    lv, attempt, (unsigned long long)d, (unsigned long long)est_new,
@@ -463,7 +498,8 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
     rule_rhs = L.rhs32.p;
   }
   launch_commit(bytes, d, w.slot_idx.p, L.table.p, w.newbits.p, w.wcnt_base.p, w.wlen_base.p,
-                w.pstart.p, w.plen.p, content, fnew, L.u, L.q, L.off.p, rule_rhs, L.fp.p, sym_next, s);
+                w.key.p, w.pstart.p, w.plen.p, content, fnew, L.u, L.q, L.off.p, rule_rhs, L.fp.p,
+                sym_next, s);
   if (pe) pe->rec(6, s);
   L.u += (uint32_t)u_new;
   L.q += q_new;
@@ -503,11 +539,11 @@ static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_
   uint64_t n_i = h_off[k];
   int cur = 0;  // ping-pong index of T^{i+1}
   PhaseEvents pe((o.flags & LCG_FLAG_TIMING) != 0);
-  std::vector<unsigned int> regs(kHll);
+  Mailbox* mb = mailbox();
   bool pending = false;  // the previous round's row waits for its active count
   Stat prev{};
   for (uint32_t lv = 1;; ++lv) {
-    Counters hf;
+    Counters& hf = mb->fin;
     if (lv >= (uint32_t)HashFamily::kLevels) {
       HIP_CHECK(hipMemcpyAsync(&hf, w.fin.p, offsetof(Counters, hll), hipMemcpyDeviceToHost, s));
       sync(s);
@@ -534,6 +570,7 @@ static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_
     w.bits.need(tiles * kTileWords, s);
     w.tile_cnt.need(tiles, s);
     w.tile_base.need(tiles + 1, s);
+    w.tile_seg.need(tiles, s);
     w.scan_tmp.need(std::max<size_t>(scan_tmp_words(tiles), 1), s);
     w.pstart.need(d_cap, s);
     w.plen.need(d_cap, s);
@@ -542,21 +579,24 @@ static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_
     w.fpv[cur].need(d_cap, s);
     w.off[cur].need(k + 1, s);
     pe.rec(0, s);
-    launch_classify(in, w.bits.p, w.tile_cnt.p, s);
+    launch_classify(in, w.bits.p, w.tile_cnt.p, w.tile_seg.p, s);
     scan_exclusive(w.tile_cnt.p, w.tile_base.p, tiles, w.scan_tmp.p, s);
     pe.rec(1, s);
     zero_counters(w.ctr.p, s);
     pe.rec(2, s);
-    launch_emit(in, w.bits.p, w.tile_base.p, g->H.lv[lv], o.key_bits, w.pstart.p, w.plen.p,
-                w.key.p, w.fpv[cur].p, w.hll_part.p, w.ctr.p, s);
+    // small rounds size the dictionary by the phrase count itself
+    const bool sketch = n_i > (1u << 20);
+    launch_emit(in, w.bits.p, w.tile_base.p, w.tile_seg.p, g->H.lv[lv], o.key_bits, w.pstart.p, w.plen.p,
+                w.key.p, w.fpv[cur].p, w.hll_part.p, sketch ? w.ctr.p : nullptr, s);
     pe.rec(8, s);
-    uint64_t d = 0;
-    HIP_CHECK(hipMemcpyAsync(&d, w.tile_base.p + tiles, 8, hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipMemcpyAsync(regs.data(), w.ctr.p->hll, sizeof(unsigned int) * kHll,
-                             hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(&mb->d, w.tile_base.p + tiles, 8, hipMemcpyDeviceToHost, s));
+    if (sketch)
+      HIP_CHECK(hipMemcpyAsync(mb->ctr.hll, w.ctr.p->hll, sizeof(unsigned int) * kHll,
+                               hipMemcpyDeviceToHost, s));
     if (pending)
       HIP_CHECK(hipMemcpyAsync(&hf, w.fin.p, offsetof(Counters, hll), hipMemcpyDeviceToHost, s));
     sync(s);
+    const uint64_t d = mb->d;
     if (pending) {
       prev[4] = hf.active;
       prev[13] = pe.ns(5, 6);
@@ -573,11 +613,12 @@ static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_
     if (d == 0 || d >= d_cap) throw LcgError{LCG_EHIP, "internal: phrase count out of range"};
     ensure_level(g, lv, s);
     const uint64_t t_classify = pe.ns(0, 1), t_emit = pe.ns(2, 8);
-    const uint64_t est = std::min<uint64_t>(d, (uint64_t)(hll_estimate(regs.data()) * 1.25) + 64);
+    const uint64_t est =
+        sketch ? std::min<uint64_t>(d, (uint64_t)(hll_estimate(mb->ctr.hll) * 1.25) + 64) : d;
     const void* content = bytes ? (const void*)d_text : (const void*)w.sym[cur ^ 1].p;
     DedupResult r = dedup_commit(g, lv, d, content, w.fpv[cur].p, w.sym[cur].p, est, o, w, s, &pe);
     zero_counters(w.fin.p, s);
-    launch_segments(cur_off, k, w.pstart.p, d, w.off[cur].p, s);
+    launch_segments(cur_off, k, w.bits.p, w.tile_base.p, d, w.off[cur].p, s);
     launch_finish(cur_off, w.off[cur].p, k, w.sym[cur].p, lv, g->c_level.p + c_base,
                   g->c_sym.p + c_base, w.fin.p, s);
     pe.rec(7, s);
