@@ -42,9 +42,18 @@ WORKLOADS = {
     "repeats": "8 strings of 250 MB from one base with 5% tandem repeats and homopolymer runs",
     "tiny": "8 strings of 128 KiB, mutated copies of one base",
 }
-# per-phase algorithmic bytes (per round i with n_i symbols, d_i phrases, u_i new
-# rules, Q_i new rhs symbols; s_i = 1 byte at round 1, else 4; f = 4-byte fingerprint)
+# Per-round algorithmic bytes (round i: n_i symbols, d_i phrases, u_i new
+# rules, Q_i new right-hand-side symbols; s_i = 1 byte at round 1, else 4;
+# f = 4-byte fingerprint; kappa = 8-byte dictionary key):
+#   n_i s_i + [i >= 2] n_i f + d_i (4 + kappa) + u_i (kappa + 4 + f) + Q_i s_i
+# split by the kernel that moves them: classify reads the order keys (bytes,
+# or F), emit the symbols, insert one key probe per phrase and the claimed key
+# per new rule, commit the new rule's rank, F and right-hand side, rewrite the
+# rank of every phrase.
 PHASES = ("classify", "emit", "insert", "rank", "commit", "segments")
+ROOFLINE_KERNEL = "k_insert<unsigned int>"
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2411_12439_amd", "csrc", "lcg_kernels.hip")
 
 
 def phase_alg_bytes(st):
@@ -53,14 +62,46 @@ def phase_alg_bytes(st):
     for i, row in enumerate(st, start=1):
         n, d, u, q = (float(x) for x in row[:4])
         s = 1.0 if i == 1 else 4.0
-        f = 0.0 if i == 1 else 4.0
-        out["classify"] += n * (s if i == 1 else f)   # the order test reads each fingerprint once
-        out["emit"] += n * (s + f) + d * 4.0           # phrase contents + fingerprints in, F of T^{i+1} out
-        out["insert"] += d * 8.0 + u * 16.0            # one 8-byte key per phrase, one slot per new rule
-        out["rank"] += d * 0.125                       # one first-occurrence bit per phrase
-        out["commit"] += d * 4.0 + u * 8.0 + q * s     # rank per phrase, new rule offset + F, new rhs
-        out["segments"] += 0.0
+        out["classify"] += n * (1.0 if i == 1 else 4.0)
+        out["emit"] += n * s
+        out["insert"] += d * 8.0 + u * 8.0
+        out["commit"] += u * 8.0 + q * s + d * 4.0
     return out
+
+
+def insert_rounds(st):
+    """Rows whose insert phase is exactly one k_insert<unsigned int> launch:
+    rounds >= 2 with one insert per phrase (dict_mode 0)."""
+    return [r for i, r in enumerate(st, start=1) if i >= 2 and int(r[15]) == 0 and r[1] > 0]
+
+
+def source_digest():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def profile_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed PMC summary of the
+    workload, or None when there is none or the kernel source has changed
+    since its counters were taken."""
+    name = "%s_%s_traffic.txt" % (kernel.replace("<", "_").replace(">", "").replace(" ", "_"),
+                                  workload)
+    path = os.path.join(PROFILE_DIR, name)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != source_digest():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def path_alg_bytes(st):
@@ -178,18 +219,26 @@ def main():
     alg = path_alg_bytes(stats)
     alg_gbps = alg / step_s.mean() / 1e9
 
-    # dominant kernel and its roofline
-    dom = max(PHASES, key=lambda p: phase_ns[p])
+    # The roofline of the dominant kernel, k_insert<unsigned int>: in the
+    # rounds listed by insert_rounds its phase events bracket exactly its one
+    # launch, so the mean below is its mean launch duration.
     per_alg = phase_alg_bytes(stats)
-    dom_ns_per_step = phase_ns[dom] / args.steps
-    achieved = per_alg[dom] / (dom_ns_per_step * 1e-9) / 1e9 if dom_ns_per_step else 0.0
+    rows = insert_rounds(stats)
+    launches = len(rows)
+    ins_ns = float(sum(r[11] for r in rows))
+    ins_alg = float(sum(r[1] * 8.0 + r[2] * 8.0 for r in rows))
+    achieved = ins_alg / (ins_ns * 1e-9) / 1e9 if ins_ns else 0.0
     rounds = stats.shape[0]
+    traffic = profile_traffic(ROOFLINE_KERNEL, args.config)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
-                "kernel": dom, "launches_per_step": rounds,
-                "mean_launch_us": round(dom_ns_per_step / rounds / 1e3, 2),
-                "alg_bytes_per_launch": round(per_alg[dom] / rounds, 1),
-                "phase_ms_per_step": {p: round(phase_ns[p] / args.steps / 1e6, 3) for p in PHASES}}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": None if traffic is None else round(traffic, 1),
+                "kernel": ROOFLINE_KERNEL, "launches_per_step": launches,
+                "mean_launch_us": round(ins_ns / max(launches, 1) / 1e3, 2),
+                "alg_bytes_per_launch": round(ins_alg / max(launches, 1), 1),
+                "phase_ms_per_step": {p: round(phase_ns[p] / args.steps / 1e6, 3) for p in PHASES},
+                "phase_alg_gbps": {p: round(per_alg[p] / (phase_ns[p] / args.steps * 1e-9) / 1e9, 1)
+                                   for p in PHASES if phase_ns[p] and per_alg[p]}}
 
     out = {"metric": METRIC, "value": round(value, 4), "unit": "GB/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup,

@@ -148,11 +148,14 @@ lcg_status lcg_c_copy(lcg_grammar_t g, uint8_t* h_level, uint32_t* h_sym);
  * round, dictionary probes, full right-hand-side comparisons, dictionary
  * capacity, then device nanoseconds (0 without LCG_FLAG_TIMING) of the round's
  * kernels (sum of the following), of classify + tile scan, of emit, of
- * insert, of rank (new flags + scans), of commit, and of the segment update.
+ * insert, of rank (new flags + scans), of commit, and of the segment update;
+ * last, the dictionary mode of the round (0: one insert per phrase, 1: equal
+ * keys combined per chunk of phrases first, chosen when the round's key
+ * sketch estimates few distinct keys per phrase).
  * Rounds of later builds (lcg_build_into, the per-string builds of the plain
  * form) are appended.
  */
-#define LCG_STATS_FIELDS 15
+#define LCG_STATS_FIELDS 16
 lcg_status lcg_stats(lcg_grammar_t g, uint64_t* h_out, uint32_t cap_rounds, uint32_t* n_rounds);
 /* Reset the statistics of g. */
 lcg_status lcg_stats_clear(lcg_grammar_t g);

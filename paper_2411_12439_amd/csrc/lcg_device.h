@@ -20,8 +20,10 @@ constexpr uint64_t kHiMask = 0xFFFFFFFF00000000ULL;
 //                  phrase fingerprint and ref is the phrase occurrence that
 //                  claimed the slot while the round runs, or the rule's rank
 //                  once committed.
-// minocc is the smallest occurrence index holding the phrase in the running
-// round (first occurrence); rank is kNone until the rule is committed.
+// While the rule is uncommitted (rank == kNone), minocc is the smallest
+// occurrence index holding the phrase in the running round (its first
+// occurrence); once committed, the same word holds the rule's fingerprint F,
+// so that (F, rank) is one 8-byte load.
 struct Slot {
   uint64_t w0;
   uint32_t minocc;

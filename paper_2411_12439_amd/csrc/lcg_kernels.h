@@ -24,6 +24,8 @@ struct Counters {
   unsigned int overflow;        // phrases whose probe sequence ran out of budget
   unsigned int active;          // strings still longer than one symbol
   unsigned long long active_len;  // their total length
+  unsigned int rest_len;        // phrases left to the plain insert by the combining one
+  unsigned int pad;
   unsigned int hll[kHll];       // HyperLogLog registers of the round's phrase keys
 };
 
@@ -54,10 +56,13 @@ void launch_emit(const RoundIn& in, const uint64_t* bits, const uint64_t* tile_b
 size_t scan_tmp_words(uint64_t n);
 void scan_exclusive(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s);
 
+// combine: the rounds where few keys take most phrases (rest: d uint32 of
+// scratch, its count in ctr->rest_len, zero on entry).
 void launch_insert(bool bytes, uint64_t d, const uint64_t* key, const uint64_t* pstart,
                    const uint32_t* plen, const void* content, const uint64_t* rule_off,
                    const void* rule_rhs, uint32_t u_committed, Slot* table, uint64_t mask,
-                   uint32_t* slot_idx, Counters* ctr, hipStream_t s);
+                   uint32_t* slot_idx, bool combine, uint32_t* rest, uint32_t* rest_len,
+                   Counters* ctr, hipStream_t s);
 void launch_newflags(bool bytes, uint64_t d, const uint32_t* slot_idx, const Slot* table,
                      const uint64_t* key, const uint32_t* plen, uint64_t* newbits, uint64_t* wcnt,
                      uint64_t* wlen, hipStream_t s);
@@ -67,9 +72,10 @@ void launch_newflags_table(bool bytes, const Slot* table, uint64_t cap, uint64_t
 void launch_commit(bool bytes, uint64_t d, const uint32_t* slot_idx, Slot* table,
                    const uint64_t* newbits, const uint64_t* wcnt_base, const uint64_t* wlen_base,
                    const uint64_t* key, const uint64_t* pstart, const uint32_t* plen,
-                   const void* content,
-                   const uint32_t* fnew, uint32_t u_prev, uint64_t q_prev, uint64_t* rule_off,
-                   void* rule_rhs, uint32_t* rule_fp, uint32_t* sym_next, hipStream_t s);
+                   const void* content, const uint32_t* fnew, const uint32_t* fprev, LevelHash h,
+                   uint32_t u_prev, uint64_t q_prev, uint64_t* rule_off, void* rule_rhs,
+                   uint32_t* rule_fp, uint32_t* sym_next, uint32_t* fnext, bool combine,
+                   hipStream_t s);
 void launch_rehash(const Slot* old_t, uint64_t old_cap, Slot* new_t, uint64_t new_mask,
                    Counters* ctr, hipStream_t s);
 

@@ -15,8 +15,10 @@
 //             store it in C and become inactive (Sec. 3.3)
 // MergeGrams (Sec. 3.6) reuses insert/newflags/scan/commit with G_b's rules
 // as the phrases.
+#include <mutex>
 #include <stdexcept>
 #include <string>
+#include <unordered_map>
 
 #include "lcg_kernels.h"
 
@@ -31,6 +33,25 @@ namespace lcg {
 
 constexpr uint32_t kMaxProbe = 1u << 14;
 constexpr unsigned kPersistentBlocks = 2048;  // grid of the grid-stride kernels (8 per CU)
+
+// Blocks of `kernel` the device holds at once (occupancy x CUs, cached per
+// kernel): the grid of a persistent kernel, so that no block waits for a
+// whole other block to finish.
+static unsigned resident_blocks(const void* kernel, int block) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, unsigned> cache;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find(kernel);
+  if (it != cache.end()) return it->second;
+  int dev = 0, per_cu = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    throw std::runtime_error("occupancy query failed");
+  const unsigned v = (unsigned)(per_cu > 0 ? per_cu : 1) * (unsigned)(cus > 0 ? cus : 1);
+  cache.emplace(kernel, v);
+  return v;
+}
 
 static inline unsigned grid_for(uint64_t n, int block) {
   uint64_t g = (n + block - 1) / block;
@@ -107,33 +128,38 @@ __device__ __forceinline__ uint64_t next_break(const uint64_t* bits, uint64_t po
   return lim;
 }
 
-// Dictionary key of a phrase sym[p .. p+q) with fingerprint P (see lcg_device.h).
+// Exact dictionary key of a phrase sym[p .. p+q) if its content fits one
+// (see lcg_device.h); such keys need no fingerprint.
+template <bool BYTES>
+__device__ __forceinline__ bool exact_key(const void* sym, uint64_t p, uint64_t q, uint64_t& k) {
+  if constexpr (BYTES) {
+    if (q > 7) return false;
+    const uint8_t* s = static_cast<const uint8_t*>(sym) + p;
+    k = q << 56;
+    for (uint32_t x = 0; x < q; ++x) k |= (uint64_t)s[x] << (8 * x);
+    return true;
+  } else {
+    if (q > 4) return false;
+    const uint32_t* s = static_cast<const uint32_t*>(sym) + p;
+    const int rb = rank_bits_for((uint32_t)q);
+    uint64_t kk = 0;
+    bool fits = true;
+    for (uint32_t x = 0; x < q; ++x) {
+      uint64_t r = s[x];
+      if (rb < 32 && (r >> rb)) fits = false;
+      kk = (kk << rb) | r;
+    }
+    k = (q << 58) | kk;
+    return fits;
+  }
+}
+
+// Dictionary key of a phrase with fingerprint P.
 template <bool BYTES>
 __device__ __forceinline__ uint64_t make_key(const void* sym, uint64_t p, uint64_t q, uint64_t P,
                                              uint32_t key_bits) {
-  if (key_bits == 0) {
-    if constexpr (BYTES) {
-      if (q <= 7) {
-        const uint8_t* s = static_cast<const uint8_t*>(sym) + p;
-        uint64_t k = q << 56;
-        for (uint32_t x = 0; x < q; ++x) k |= (uint64_t)s[x] << (8 * x);
-        return k;
-      }
-    } else {
-      if (q <= 4) {
-        const uint32_t* s = static_cast<const uint32_t*>(sym) + p;
-        const int rb = rank_bits_for((uint32_t)q);
-        uint64_t k = 0;
-        bool fits = true;
-        for (uint32_t x = 0; x < q; ++x) {
-          uint64_t r = s[x];
-          if (rb < 32 && (r >> rb)) fits = false;
-          k = (k << rb) | r;
-        }
-        if (fits) return (q << 58) | k;
-      }
-    }
-  }
+  uint64_t k;
+  if (key_bits == 0 && exact_key<BYTES>(sym, p, q, k)) return k;
   return long_key(P, key_bits);
 }
 
@@ -208,7 +234,11 @@ void launch_zero(void* p, size_t bytes, hipStream_t s) {
 // are staged in LDS with wide loads; each thread then classifies 16
 // consecutive positions from its 18-value window.
 constexpr int kRightHalo = 64;
-constexpr int kCStage = kTile + 1 + kRightHalo;  // s_f[i] is position t0 - 1 + i
+constexpr int kCStage = kTile + 1 + kRightHalo;  // staged position t0 - 1 + i ...
+// ... lives at s_f[cpad(i)]: one padding word per 16 keeps the per-thread
+// 16-position windows on distinct LDS banks
+__device__ __forceinline__ uint32_t cpad(uint32_t i) { return i + (i >> 4); }
+constexpr int kCStagePadded = kCStage + kCStage / 16 + 1;
 
 template <bool BYTES>
 __device__ __forceinline__ void stage_fp(const RoundIn& in, const uint32_t* s_lut, uint64_t t0,
@@ -222,9 +252,9 @@ __device__ __forceinline__ void stage_fp(const RoundIn& in, const uint32_t* s_lu
       const uint4 v = *reinterpret_cast<const uint4*>(src + i);
       const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-      for (int x = 0; x < 16; ++x) s_f[1 + i + x] = s_lut[(wv[x >> 2] >> (8 * (x & 3))) & 0xFF];
+      for (int x = 0; x < 16; ++x) s_f[cpad(1 + i + x)] = s_lut[(wv[x >> 2] >> (8 * (x & 3))) & 0xFF];
     } else {
-      for (uint32_t x = i; x < i + 16 && x < lim; ++x) s_f[1 + x] = s_lut[src[x]];
+      for (uint32_t x = i; x < i + 16 && x < lim; ++x) s_f[cpad(1 + x)] = s_lut[src[x]];
     }
   } else {
     const uint32_t* src = in.fp + t0;
@@ -232,32 +262,46 @@ __device__ __forceinline__ void stage_fp(const RoundIn& in, const uint32_t* s_lu
       for (uint32_t i = threadIdx.x * 4; i < kTile; i += kBlock * 4) {
         if (i + 4 <= lim) {
           const uint4 v = *reinterpret_cast<const uint4*>(src + i);
-          s_f[1 + i] = v.x;
-          s_f[2 + i] = v.y;
-          s_f[3 + i] = v.z;
-          s_f[4 + i] = v.w;
+          s_f[cpad(1 + i)] = v.x;
+          s_f[cpad(2 + i)] = v.y;
+          s_f[cpad(3 + i)] = v.z;
+          s_f[cpad(4 + i)] = v.w;
         } else {
-          for (uint32_t x = i; x < i + 4 && x < lim; ++x) s_f[1 + x] = src[x];
+          for (uint32_t x = i; x < i + 4 && x < lim; ++x) s_f[cpad(1 + x)] = src[x];
         }
       }
     } else {
-      for (uint32_t i = threadIdx.x; i < lim; i += kBlock) s_f[1 + i] = src[i];
+      for (uint32_t i = threadIdx.x; i < lim; i += kBlock) s_f[cpad(1 + i)] = src[i];
     }
   }
   // left neighbour and right halo
   if (threadIdx.x == 0) s_f[0] = t0 > 0 ? fval<BYTES>(in, s_lut, t0 - 1) : 0u;
   if (threadIdx.x < kRightHalo) {
     const uint64_t p = t0 + kTile + threadIdx.x;
-    s_f[1 + kTile + threadIdx.x] = p < in.n ? fval<BYTES>(in, s_lut, p) : 0u;
+    s_f[cpad(1 + kTile + threadIdx.x)] = p < in.n ? fval<BYTES>(in, s_lut, p) : 0u;
   }
+}
+
+// The first and last string each tile overlaps (one thread per tile, so the
+// binary searches over the offsets run side by side, not inside the tile's
+// block).
+__global__ void k_tile_seg(const uint64_t* __restrict__ off, uint32_t k, uint64_t n,
+                           uint64_t tiles, uint2* __restrict__ tile_seg) {
+  const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (t >= tiles) return;
+  const uint64_t t0 = t * kTile;
+  const uint64_t tl = (t0 + kTile < n ? t0 + kTile : n) - 1;
+  const uint32_t lo = seg_search(off, 0, k - 1, t0);
+  const uint32_t hi = seg_search(off, lo, k - 1, tl);
+  tile_seg[t] = make_uint2(lo, hi);
 }
 
 template <bool BYTES>
 __global__ __launch_bounds__(kBlock) void k_classify(RoundIn in, uint64_t* __restrict__ bits,
                                                      uint64_t* __restrict__ tile_cnt,
-                                                     uint2* __restrict__ tile_seg) {
+                                                     const uint2* __restrict__ tile_seg) {
   __shared__ uint32_t s_lut[256];
-  __shared__ uint32_t s_f[kCStage];
+  __shared__ uint32_t s_f[kCStagePadded];
   __shared__ uint32_t s_seg[2];
   __shared__ uint32_t s_mask[kBlock];
   __shared__ uint32_t s_cnt;
@@ -266,15 +310,11 @@ __global__ __launch_bounds__(kBlock) void k_classify(RoundIn in, uint64_t* __res
     s_lut[threadIdx.x] = in.lut[threadIdx.x];
     __syncthreads();
   }
-  // wave 0 finds the strings the tile overlaps while the others stage it
   if (threadIdx.x == 0) {
-    uint64_t tl = (t0 + kTile < in.n ? t0 + kTile : in.n) - 1;
-    uint32_t lo = seg_search(in.off, 0, in.k - 1, t0);
-    uint32_t hi = seg_search(in.off, lo, in.k - 1, tl);
-    s_seg[0] = lo;
-    s_seg[1] = hi;
+    const uint2 r = tile_seg[blockIdx.x];
+    s_seg[0] = r.x;
+    s_seg[1] = r.y;
     s_cnt = 0;
-    tile_seg[blockIdx.x] = make_uint2(lo, hi);
   }
   stage_fp<BYTES>(in, s_lut, t0, s_f);
   __syncthreads();
@@ -283,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(RoundIn in, uint64_t* __res
   if (b < in.n) {
     uint32_t fw[kItems + 2];
 #pragma unroll
-    for (int x = 0; x < kItems + 2; ++x) fw[x] = s_f[threadIdx.x * kItems + x];  // position b - 1 + x
+    for (int x = 0; x < kItems + 2; ++x) fw[x] = s_f[cpad(threadIdx.x * kItems + x)];  // position b - 1 + x
     uint32_t desc = 0, eq = 0, gt = 0;
 #pragma unroll
     for (int x = 0; x < kItems; ++x) {
@@ -319,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(RoundIn in, uint64_t* __res
           bool more = true;
           while (more && r < s_end) {
             const uint64_t i = r - t0 + 1;
-            fr = i < (uint64_t)kCStage ? s_f[i] : fval<BYTES>(in, s_lut, r);
+            fr = i < (uint64_t)kCStage ? s_f[cpad((uint32_t)i)] : fval<BYTES>(in, s_lut, r);
             more = fr == fl;
             r += more ? 1 : 0;
           }
@@ -345,6 +385,8 @@ void launch_classify(const RoundIn& in, uint64_t* bits, uint64_t* tile_cnt, uint
                      hipStream_t s) {
   static_assert(kItems == 16 && kBlock == 256, "bit packing assumes 16 positions per thread");
   unsigned tiles = grid_for(in.n, kTile);
+  k_tile_seg<<<grid_for(tiles, 256), 256, 0, s>>>(in.off, in.k, in.n, tiles, tile_seg);
+  LCG_LAUNCH_CHECK("tile_seg");
   if (in.bytes) k_classify<true><<<tiles, kBlock, 0, s>>>(in, bits, tile_cnt, tile_seg);
   else k_classify<false><<<tiles, kBlock, 0, s>>>(in, bits, tile_cnt, tile_seg);
   LCG_LAUNCH_CHECK("classify");
@@ -413,6 +455,70 @@ __device__ __forceinline__ void stage_tile(const RoundIn& in, uint64_t t0, EmitS
   }
 }
 
+// End of the phrase starting at tile offset s_start[jj]: the next break in
+// the tile, else the next break after it, but never past its string's end.
+__device__ __forceinline__ uint64_t phrase_end(uint32_t jj, uint32_t c, uint64_t t0,
+                                               const uint16_t* s_start, uint32_t slo, uint32_t shi,
+                                               bool cached, const uint64_t* s_off,
+                                               const uint64_t* off, const uint64_t* bits) {
+  const uint64_t l = t0 + s_start[jj];
+  uint64_t s_end;
+  if (slo == shi) {
+    s_end = cached ? s_off[1] : off[slo + 1];
+  } else if (cached) {
+    uint32_t lo = 0, hi = shi - slo;  // largest i with s_off[i] <= l
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= l) lo = mid; else hi = mid - 1;
+    }
+    s_end = s_off[lo + 1];
+  } else {
+    s_end = off[seg_search(off, slo, shi, l) + 1];
+  }
+  uint64_t e = jj + 1 < c ? t0 + s_start[jj + 1] : next_break(bits, l + 1, s_end);
+  return e > s_end ? s_end : e;
+}
+
+// One key into the block's HyperLogLog registers (32-bit mix of the key:
+// enough for a sizing estimate).
+__device__ __forceinline__ void hll_add(uint32_t* s_hll, uint64_t kk) {
+  uint32_t h = (uint32_t)kk * 0x9E3779B1u ^ (uint32_t)(kk >> 32) * 0x85EBCA77u;
+  h ^= h >> 16;
+  h *= 0x7FEB352Du;
+  h ^= h >> 15;
+  h *= 0x846CA68Bu;
+  h ^= h >> 16;
+  const uint32_t idx = h >> (32 - kHllLog2);
+  const uint32_t rest = h << kHllLog2;
+  const uint32_t rho = rest ? (uint32_t)__builtin_clz(rest) + 1 : 32 - kHllLog2 + 1;
+  if (s_hll[idx] < rho) atomicMax(&s_hll[idx], rho);  // frequent keys: a read, no atomic
+}
+
+// Eq. 4 of the phrase [l, e) by Horner's rule from the right:
+// P = a * sum_j F[Q_j] c^(j-1) + b (mod p); the staged part of the tile is
+// read from LDS, the rest from memory.
+template <bool BYTES>
+__device__ __forceinline__ uint64_t phrase_fp(const RoundIn& in, const uint32_t* s_lut,
+                                              const EmitStage<BYTES>& st, uint64_t t0, uint64_t l,
+                                              uint64_t e, LevelHash h) {
+  uint64_t S = 0;
+  const uint64_t e_st = e < t0 + kStage ? e : t0 + kStage;  // staged part [l, e_st)
+  for (uint64_t p = e; p > e_st;) {
+    --p;
+    S = addmod61(mulmod61(S, h.c), fval<BYTES>(in, s_lut, p));
+  }
+  for (uint64_t p = e_st; p > l;) {
+    --p;
+    uint32_t f;
+    if constexpr (BYTES) f = s_lut[st.sym[p - t0]];
+    else f = st.fp[p - t0];
+    S = addmod61(mulmod61(S, h.c), f);
+  }
+  return addmod61(mulmod61(h.a, S), h.b);
+}
+
+constexpr uint32_t kLongList = 2048;  // long phrases deferred per tile; more are done inline
+
 template <bool BYTES>
 __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in, const uint64_t* __restrict__ bits,
                                                  const uint64_t* __restrict__ tile_base,
@@ -423,9 +529,11 @@ __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in, const uint64_t* __r
                                                  uint8_t* __restrict__ hll_part) {
   __shared__ uint32_t s_lut[256];
   __shared__ uint16_t s_start[kTile];
+  __shared__ uint16_t s_long[kLongList];
   __shared__ uint64_t s_off[kSegCache + 1];
   __shared__ uint32_t s_seg[2];
   __shared__ uint32_t s_wave[kBlock / 64];
+  __shared__ uint32_t s_nlong;
   __shared__ uint32_t s_hll[kHll];
   __shared__ EmitStage<BYTES> st;
   if constexpr (BYTES) s_lut[threadIdx.x] = in.lut[threadIdx.x];
@@ -437,6 +545,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in, const uint64_t* __r
       const uint2 r = tile_seg[tile];
       s_seg[0] = r.x;
       s_seg[1] = r.y;
+      s_nlong = 0;
     }
     stage_tile<BYTES>(in, t0, st);
     uint32_t mask = (uint32_t)(bits[tile * kTileWords + threadIdx.x / 4] >> ((threadIdx.x & 3) * 16)) &
@@ -454,59 +563,55 @@ __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in, const uint64_t* __r
       for (uint32_t i = threadIdx.x; i < shi - slo + 2; i += kBlock) s_off[i] = in.off[slo + i];
     __syncthreads();
     const uint64_t base = tile_base[tile];
+    // Short phrases: their key is their content, taken from the staged tile.
+    // Their fingerprint is computed once per new rule when the rule is
+    // stored, not once per occurrence.  Long phrases (compared in full, keyed
+    // by their fingerprint) are listed and done in a second pass with full
+    // waves, instead of idling the lanes of every wave that holds one.
     for (uint32_t jj = threadIdx.x; jj < c; jj += kBlock) {
       const uint64_t l = t0 + s_start[jj];
-      uint64_t s_end;
-      if (slo == shi) {
-        s_end = cached ? s_off[1] : in.off[slo + 1];
-      } else if (cached) {
-        uint32_t lo = 0, hi = shi - slo;  // largest i with s_off[i] <= l
-        while (lo < hi) {
-          uint32_t mid = (lo + hi + 1) >> 1;
-          if (s_off[mid] <= l) lo = mid; else hi = mid - 1;
-        }
-        s_end = s_off[lo + 1];
-      } else {
-        s_end = in.off[seg_search(in.off, slo, shi, l) + 1];
-      }
-      uint64_t e = jj + 1 < c ? t0 + s_start[jj + 1] : next_break(bits, l + 1, s_end);
-      if (e > s_end) e = s_end;
+      const uint64_t e = phrase_end(jj, c, t0, s_start, slo, shi, cached, s_off, in.off, bits);
       const uint64_t q = e - l;
-      // Eq. 4 by Horner's rule from the right: sum_j F[Q_j] c^(j-1)
-      uint64_t S = 0;
-      const uint64_t e_st = e < t0 + kStage ? e : t0 + kStage;  // staged part [l, e_st)
-      for (uint64_t p = e; p > e_st;) {
-        --p;
-        S = addmod61(mulmod61(S, h.c), fval<BYTES>(in, s_lut, p));
+      uint64_t kk = 0;
+      bool exact = false;
+      if (key_bits == 0) {
+        if (e <= t0 + kStage) exact = exact_key<BYTES>(st.sym, l - t0, q, kk);
+        else exact = exact_key<BYTES>(in.sym, l, q, kk);
       }
-      for (uint64_t p = e_st; p > l;) {
-        --p;
-        uint32_t f;
-        if constexpr (BYTES) f = s_lut[st.sym[p - t0]];
-        else f = st.fp[p - t0];
-        S = addmod61(mulmod61(S, h.c), f);
-      }
-      const uint64_t P = addmod61(mulmod61(h.a, S), h.b);
-      uint64_t kk;
-      if (e <= t0 + kStage) {
-        kk = make_key<BYTES>(st.sym, l - t0, q, P, key_bits);
+      if (exact) {
+        key[base + jj] = kk;
+        hll_add(s_hll, kk);
       } else {
-        kk = make_key<BYTES>(in.sym, l, q, P, key_bits);
+        const uint32_t slot = atomicAdd(&s_nlong, 1u);
+        if (slot < kLongList) {
+          s_long[slot] = (uint16_t)jj;
+        } else {
+          const uint64_t o = base + jj;
+          const uint64_t P = phrase_fp<BYTES>(in, s_lut, st, t0, l, e, h);
+          kk = long_key(P, key_bits);
+          pstart[o] = l;
+          plen[o] = (uint32_t)q;
+          fnew[o] = (uint32_t)(P & 0xFFFFFFFFULL);
+          key[o] = kk;
+          hll_add(s_hll, kk);
+        }
       }
+    }
+    __syncthreads();
+    const uint32_t nlong = s_nlong < kLongList ? s_nlong : kLongList;
+    for (uint32_t i = threadIdx.x; i < nlong; i += kBlock) {
+      const uint32_t jj = s_long[i];
+      const uint64_t l = t0 + s_start[jj];
+      const uint64_t e = phrase_end(jj, c, t0, s_start, slo, shi, cached, s_off, in.off, bits);
+      const uint64_t q = e - l;
       const uint64_t o = base + jj;
-      // a short phrase's length and content are in its exact key; only long
-      // phrases (compared in full) need their position and length
-      if (kk & kLongTag) {
-        pstart[o] = l;
-        plen[o] = (uint32_t)q;
-      }
-      key[o] = kk;
+      const uint64_t P = phrase_fp<BYTES>(in, s_lut, st, t0, l, e, h);
+      const uint64_t kk = long_key(P, key_bits);
+      pstart[o] = l;
+      plen[o] = (uint32_t)q;
       fnew[o] = (uint32_t)(P & 0xFFFFFFFFULL);
-      const uint64_t hh = mix64(probe_key(kk));
-      const uint32_t idx = (uint32_t)(hh >> (64 - kHllLog2));
-      const uint64_t rest = hh << kHllLog2;
-      const uint32_t rho = rest ? (uint32_t)__builtin_clzll(rest) + 1 : 64 - kHllLog2 + 1;
-      atomicMax(&s_hll[idx], rho);
+      key[o] = kk;
+      hll_add(s_hll, kk);
     }
   }
   __syncthreads();
@@ -537,7 +642,9 @@ void launch_emit(const RoundIn& in, const uint64_t* bits, const uint64_t* tile_b
                  uint32_t key_bits, uint64_t* pstart, uint32_t* plen, uint64_t* key, uint32_t* fnew,
                  uint8_t* hll_part, Counters* ctr, hipStream_t s) {
   uint64_t tiles = grid_for(in.n, kTile);
-  unsigned g = tiles > kEmitBlocks ? kEmitBlocks : (unsigned)tiles;
+  unsigned g = resident_blocks(in.bytes ? (const void*)k_emit<true> : (const void*)k_emit<false>, kBlock);
+  if (g > kEmitBlocks) g = kEmitBlocks;  // rows of hll_part
+  if (g > tiles) g = (unsigned)tiles;
   if (in.bytes)
     k_emit<true><<<g, kBlock, 0, s>>>(in, bits, tile_base, tile_seg, tiles, h, key_bits, pstart, plen, key,
                                       fnew, hll_part);
@@ -611,11 +718,20 @@ void scan_exclusive(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* tmp
 // ------------------------------------------------------------------ insert
 // Equality of two symbol sequences of length len, without an early exit and
 // without a call (both forms of the probe loop around it were compiled into
-// code that lost the probe result).
+// code that lost the probe result).  Eight symbols of each side per step, so
+// that their loads are in flight together.
 template <typename Sym>
 __device__ __forceinline__ bool same_seq(const Sym* a, const Sym* b, uint32_t len) {
   uint32_t diff = 0;
-  for (uint32_t i = 0; i < len; ++i) diff |= (uint32_t)(a[i] != b[i]);
+  for (uint32_t i = 0; i < len; i += 8) {
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) {
+      const bool in = i + k < len;
+      const Sym x = in ? a[i + k] : Sym(0);
+      const Sym y = in ? b[i + k] : Sym(0);
+      diff |= (uint32_t)(x != y);
+    }
+  }
   return diff == 0;
 }
 
@@ -627,19 +743,20 @@ __device__ __forceinline__ bool same_seq(const Sym* a, const Sym* b, uint32_t le
 // with a plain (L1-cacheable) load: frequent short phrases are then served by
 // each CU's L1 instead of one L2 line.  A stale empty word only sends the
 // thread to the compare-and-swap, which returns the current value.
-// Insert-or-find every phrase.  A claimed slot keeps the claimer's key; a
-// long phrase whose 31 key bits match is compared symbol by symbol against
-// the slot's phrase (the claiming occurrence, or the committed rule).
 //
-// kBatch phrases per thread and iteration (their keys and home slots are
-// loaded together); 1 measured fastest on gfx950, larger batches cost more in
-// occupancy than they gain in overlap.  The probe loop is written out in the
-// kernel body with a single exit: the gfx950 code of the same loop placed in
-// a helper function with counters passed by reference lost its result.
-constexpr int kBatch = 1;
-
+// One phrase per thread and iteration (batches of several measured slower on
+// gfx950: they cost more in occupancy than they gain in overlap).  The probe
+// loop is written out in the kernel body with a single exit: the gfx950 code
+// of the same loop placed in a helper function with counters passed by
+// reference lost its result.
+//
+// The phrases are o = begin .. end-1, or o = list[begin .. *list_len-1] when
+// a list is given; d is the round's phrase count.
 template <typename Sym>
-__global__ __launch_bounds__(256) void k_insert(uint64_t d, const uint64_t* __restrict__ key,
+__global__ __launch_bounds__(256) void k_insert(uint64_t begin, uint64_t end, uint64_t d,
+                                                const uint32_t* __restrict__ list,
+                                                const uint32_t* __restrict__ list_len,
+                                                const uint64_t* __restrict__ key,
                                                 const uint64_t* __restrict__ pstart,
                                                 const uint32_t* __restrict__ plen,
                                                 const Sym* __restrict__ content,
@@ -653,91 +770,77 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t d, const uint64_t* __re
   __syncthreads();
   unsigned long long won = 0, probes = 0, cmps = 0, fails = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; base < d;
-       base += stride * kBatch) {
-    uint64_t kk[kBatch], hpos[kBatch], hw[kBatch];
-#pragma unroll
-    for (int b = 0; b < kBatch; ++b) {
-      const uint64_t o = base + b * stride;
-      kk[b] = o < d ? key[o] : 0;
+  const uint64_t lim = list ? (uint64_t)*list_len : end;
+  for (uint64_t i = begin + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < lim; i += stride) {
+    const uint64_t o = list ? (uint64_t)list[i] : i;
+    const uint64_t kk = key[o];
+    uint64_t pos = mix64(kk) & mask;
+    uint64_t w = hint_load(&table[pos].w0);
+    const bool is_long = (kk & kLongTag) != 0;
+    const uint64_t want = is_long ? (kk | o) : kk;
+    uint64_t my_pos = 0;
+    uint32_t my_len = 0;
+    if (is_long) {
+      my_pos = pstart[o];
+      my_len = plen[o];
     }
-#pragma unroll
-    for (int b = 0; b < kBatch; ++b) {
-      hpos[b] = mix64(kk[b]) & mask;
-      hw[b] = base + b * stride < d ? hint_load(&table[hpos[b]].w0) : kEmpty;
-    }
-#pragma unroll
-    for (int b = 0; b < kBatch; ++b) {
-      const uint64_t o = base + b * stride;
-      if (o >= d) continue;
-      const bool is_long = (kk[b] & kLongTag) != 0;
-      const uint64_t want = is_long ? (kk[b] | o) : kk[b];
-      uint64_t my_pos = 0;
-      uint32_t my_len = 0;
-      if (is_long) {
-        my_pos = pstart[o];
-        my_len = plen[o];
-      }
-      uint64_t pos = hpos[b];
-      uint64_t w = hw[b];
-      uint32_t result = kNone;
-      for (uint32_t probe = 0; probe < kMaxProbe && result == kNone; ++probe) {
-        Slot* sl = &table[pos];
-        ++probes;
-        if (probe) w = hint_load(&sl->w0);
-        bool hit = false;
-        if (w == kEmpty) {
-          unsigned long long prev =
-              atomicCAS(reinterpret_cast<unsigned long long*>(&sl->w0), (unsigned long long)kEmpty,
-                        (unsigned long long)want);
-          if (prev == kEmpty) {
-            hit = true;
-            ++won;
-          } else {
-            w = prev;
-          }
+    uint32_t result = kNone;
+    for (uint32_t probe = 0; probe < kMaxProbe && result == kNone; ++probe) {
+      Slot* sl = &table[pos];
+      ++probes;
+      if (probe) w = hint_load(&sl->w0);
+      bool hit = false;
+      if (w == kEmpty) {
+        unsigned long long prev =
+            atomicCAS(reinterpret_cast<unsigned long long*>(&sl->w0), (unsigned long long)kEmpty,
+                      (unsigned long long)want);
+        if (prev == kEmpty) {
+          hit = true;
+          ++won;
+        } else {
+          w = prev;
         }
-        if (!hit) {
-          if (!is_long) {
-            hit = w == kk[b];
-          } else if ((w & kHiMask) == kk[b]) {
-            const uint32_t rk = hint_load(&sl->rank);
-            const uint32_t ref = (uint32_t)w;
-            // a committed rule is compared with its stored right-hand side, a
-            // slot claimed in this pass with the claiming occurrence; anything
-            // else (a slot left by an interrupted call) cannot match
-            const bool committed = rk != kNone && rk < u_committed;
-            const bool inflight = rk == kNone && ref < d;
-            uint64_t opos = 0;
-            uint32_t olen = 0xFFFFFFFFu;
-            const Sym* arr = content;
-            if (committed) {
-              opos = rule_off[rk];
-              olen = (uint32_t)(rule_off[rk + 1] - opos);
-              arr = rule_rhs;
-            } else if (inflight) {
-              opos = pstart[ref];
-              olen = plen[ref];
-            }
-            ++cmps;
-            hit = olen == my_len && same_seq<Sym>(content + my_pos, arr + opos, my_len);
+      }
+      if (!hit) {
+        if (!is_long) {
+          hit = w == kk;
+        } else if ((w & kHiMask) == kk) {
+          const uint32_t rk = hint_load(&sl->rank);
+          const uint32_t ref = (uint32_t)w;
+          // a committed rule is compared with its stored right-hand side, a
+          // slot claimed in this pass with the claiming occurrence; anything
+          // else (a slot left by an interrupted call) cannot match
+          const bool committed = rk != kNone && rk < u_committed;
+          const bool inflight = rk == kNone && ref < d;
+          uint64_t opos = 0;
+          uint32_t olen = 0xFFFFFFFFu;
+          const Sym* arr = content;
+          if (committed) {
+            opos = rule_off[rk];
+            olen = (uint32_t)(rule_off[rk + 1] - opos);
+            arr = rule_rhs;
+          } else if (inflight) {
+            opos = pstart[ref];
+            olen = plen[ref];
           }
+          ++cmps;
+          hit = olen == my_len && same_seq<Sym>(content + my_pos, arr + opos, my_len);
         }
-        if (hit) result = (uint32_t)pos;
-        else pos = (pos + 1) & mask;
       }
-      if (result == kNone) {
-        ++fails;
-      } else {
-        Slot* sl = &table[result];
-        // (first occurrence, rank) in one load; a stale (larger) first
-        // occurrence only costs an unneeded atomicMin
-        const uint64_t mr = hint_load(reinterpret_cast<const uint64_t*>(&sl->minocc));
-        if ((uint32_t)(mr >> 32) == kNone && (uint32_t)mr > (uint32_t)o)
-          atomicMin(&sl->minocc, (uint32_t)o);
-      }
-      slot_idx[o] = result;
+      if (hit) result = (uint32_t)pos;
+      else pos = (pos + 1) & mask;
     }
+    if (result == kNone) {
+      ++fails;
+    } else {
+      Slot* sl = &table[result];
+      // (first occurrence, rank) in one load; a stale (larger) first
+      // occurrence only costs an unneeded atomicMin
+      const uint64_t mr = hint_load(reinterpret_cast<const uint64_t*>(&sl->minocc));
+      if ((uint32_t)(mr >> 32) == kNone && (uint32_t)mr > (uint32_t)o)
+        atomicMin(&sl->minocc, (uint32_t)o);
+    }
+    slot_idx[o] = result;
   }
   // one global atomic per block and counter
   won = wave_sum(won);
@@ -759,19 +862,201 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t d, const uint64_t* __re
   }
 }
 
+// Combining insert for rounds whose phrases repeat a few keys many times
+// (round 1 of DNA-like text: ~10^8 phrases, ~10^4 distinct).  Every block
+// takes a chunk of kCombChunk consecutive phrases and first builds a
+// dictionary of the chunk's exact keys in LDS, with each key's first
+// occurrence in the chunk; then one thread per distinct key probes the
+// global dictionary once and lowers the slot's first occurrence once; then
+// every phrase takes its slot from LDS.  Frequent keys thus cost one global
+// access per chunk instead of one per occurrence (which, for a handful of
+// keys, all land on the same few L2 lines).  Long keys and keys that find no
+// room in the LDS table are appended to `rest` for k_insert.
+constexpr int kCombLog2 = 11;
+constexpr int kComb = 1 << kCombLog2;   // LDS dictionary entries
+constexpr int kCombChunk = 4096;        // phrases per block and iteration
+constexpr int kCombProbe = 32;          // LDS probe budget
+constexpr int kCombItems = kCombChunk / 256;
+constexpr uint16_t kCombNone = 0xFFFF;
+
+__global__ __launch_bounds__(256) void k_insert_comb(uint64_t begin, uint64_t end,
+                                                     const uint64_t* __restrict__ key, Slot* table,
+                                                     uint64_t mask, uint32_t* __restrict__ slot_idx,
+                                                     uint32_t* __restrict__ rest,
+                                                     uint32_t* __restrict__ rest_len,
+                                                     Counters* __restrict__ ctr) {
+  __shared__ unsigned long long s_key[kComb];  // reused as the chunk's rest list
+  __shared__ uint32_t s_min[kComb];
+  __shared__ uint32_t s_slot[kComb];
+  __shared__ uint16_t s_loc[kCombChunk];
+  __shared__ unsigned long long s_sum[3];
+  __shared__ uint32_t s_nrest, s_rbase;
+  static_assert(kComb * sizeof(unsigned long long) >= kCombChunk * sizeof(uint32_t),
+                "the rest list reuses the key table");
+  if (threadIdx.x < 3) s_sum[threadIdx.x] = 0;
+  unsigned long long won = 0, probes = 0, fails = 0;
+  for (uint64_t c0 = begin + blockIdx.x * (uint64_t)kCombChunk; c0 < end;
+       c0 += (uint64_t)gridDim.x * kCombChunk) {
+    for (int i = threadIdx.x; i < kComb; i += blockDim.x) {
+      s_key[i] = kEmpty;
+      s_min[i] = kNone;
+    }
+    if (threadIdx.x == 0) s_nrest = 0;
+    __syncthreads();
+    // 1: the chunk's exact keys into the LDS dictionary (all keys loaded first,
+    // so that their loads overlap)
+    uint64_t kc[kCombItems];
+#pragma unroll
+    for (int x = 0; x < kCombItems; ++x) {
+      const uint64_t o = c0 + x * 256 + threadIdx.x;
+      kc[x] = o < end ? key[o] : kLongTag;
+    }
+#pragma unroll
+    for (int x = 0; x < kCombItems; ++x) {
+      const uint32_t li = x * 256 + threadIdx.x;
+      const uint64_t o = c0 + li;
+      uint32_t found = kNone;
+      {
+        const uint64_t kk = kc[x];
+        if (!(kk & kLongTag)) {
+          uint32_t lpos = (uint32_t)(mix64(kk) >> 40) & (kComb - 1);
+          for (int t = 0; t < kCombProbe && found == kNone; ++t) {
+            const unsigned long long w = s_key[lpos];
+            bool hit;
+            if (w == kEmpty) {
+              const unsigned long long prev =
+                  atomicCAS(&s_key[lpos], (unsigned long long)kEmpty, (unsigned long long)kk);
+              hit = prev == kEmpty || prev == kk;
+            } else {
+              hit = w == kk;
+            }
+            if (hit) found = lpos;
+            else lpos = (lpos + 1) & (kComb - 1);
+          }
+          if (found != kNone) atomicMin(&s_min[found], (uint32_t)o);
+        }
+      }
+      s_loc[li] = found == kNone ? kCombNone : (uint16_t)found;
+    }
+    __syncthreads();
+    // 2: one global insert per distinct key, with its first occurrence (the
+    // home words of the thread's entries are loaded first)
+    uint64_t hw[kComb / 256];
+#pragma unroll
+    for (int j = 0; j < kComb / 256; ++j) {
+      const uint64_t kk = s_key[j * 256 + threadIdx.x];
+      hw[j] = kk != kEmpty ? hint_load(&table[mix64(kk) & mask].w0) : kEmpty;
+    }
+#pragma unroll
+    for (int j = 0; j < kComb / 256; ++j) {
+      const int i = j * 256 + threadIdx.x;
+      const uint64_t kk = s_key[i];
+      uint32_t res = kNone;
+      if (kk != kEmpty) {
+        uint64_t pos = mix64(kk) & mask;
+        for (uint32_t probe = 0; probe < kMaxProbe && res == kNone; ++probe) {
+          Slot* sl = &table[pos];
+          ++probes;
+          uint64_t w = probe ? hint_load(&sl->w0) : hw[j];
+          bool hit = false;
+          if (w == kEmpty) {
+            const unsigned long long prev =
+                atomicCAS(reinterpret_cast<unsigned long long*>(&sl->w0),
+                          (unsigned long long)kEmpty, (unsigned long long)kk);
+            if (prev == kEmpty) {
+              hit = true;
+              ++won;
+            } else {
+              w = prev;
+            }
+          }
+          if (!hit) hit = w == kk;
+          if (hit) res = (uint32_t)pos;
+          else pos = (pos + 1) & mask;
+        }
+        if (res == kNone) {
+          ++fails;
+        } else {
+          const uint32_t m = s_min[i];
+          Slot* sl = &table[res];
+          const uint64_t mr = hint_load(reinterpret_cast<const uint64_t*>(&sl->minocc));
+          if ((uint32_t)(mr >> 32) == kNone && (uint32_t)mr > m) atomicMin(&sl->minocc, m);
+        }
+      }
+      s_slot[i] = res;
+    }
+    __syncthreads();
+    // 3: slots of the combined phrases; the others join the rest list
+    uint32_t* s_list = reinterpret_cast<uint32_t*>(s_key);
+    for (int x = 0; x < kCombItems; ++x) {
+      const uint32_t li = x * 256 + threadIdx.x;
+      const uint64_t o = c0 + li;
+      if (o < end) {
+        const uint16_t lr = s_loc[li];
+        if (lr != kCombNone) slot_idx[o] = s_slot[lr];
+        else s_list[atomicAdd(&s_nrest, 1u)] = (uint32_t)o;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_nrest) s_rbase = atomicAdd(rest_len, s_nrest);
+    __syncthreads();
+    const uint32_t nr = s_nrest;
+    for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x) rest[s_rbase + i] = s_list[i];
+    __syncthreads();
+  }
+  won = wave_sum(won);
+  probes = wave_sum(probes);
+  fails = wave_sum(fails);
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&s_sum[0], won);
+    atomicAdd(&s_sum[1], probes);
+    atomicAdd(&s_sum[2], fails);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_sum[0]) atomicAdd(&ctr->won, s_sum[0]);
+    if (s_sum[1]) atomicAdd(&ctr->probes, s_sum[1]);
+    if (s_sum[2]) atomicAdd(&ctr->overflow, (unsigned int)s_sum[2]);
+  }
+}
+
+// With `combine` the phrases go through k_insert_comb in launches over
+// growing ranges [0, 2^16), [2^16, 2^20), ...: a kernel boundary makes every
+// slot's first occurrence visible to all CUs, so the frequent keys, whose
+// first occurrences come early, find it settled in later ranges and skip the
+// atomicMin (within one launch a CU may keep reading a stale first
+// occurrence from its L1).  What k_insert_comb leaves (rest, count
+// *rest_len, zero on entry) then goes through k_insert.  Otherwise one
+// k_insert launch takes all d phrases.
 void launch_insert(bool bytes, uint64_t d, const uint64_t* key, const uint64_t* pstart,
                    const uint32_t* plen, const void* content, const uint64_t* rule_off,
                    const void* rule_rhs, uint32_t u_committed, Slot* table, uint64_t mask,
-                   uint32_t* slot_idx, Counters* ctr, hipStream_t s) {
+                   uint32_t* slot_idx, bool combine, uint32_t* rest, uint32_t* rest_len,
+                   Counters* ctr, hipStream_t s) {
   if (!d) return;
-  unsigned g = grid_for(d, 256 * kBatch);
+  const uint32_t* list = nullptr;
+  const uint32_t* list_len = nullptr;
+  unsigned g = grid_for(d, 256);
+  if (combine) {
+    const unsigned r = resident_blocks((const void*)k_insert_comb, 256);
+    for (uint64_t begin = 0, end = d < (1ull << 16) ? d : (1ull << 16); begin < d;
+         begin = end, end = end * 16 < d ? end * 16 : d) {
+      unsigned gc = grid_for(end - begin, kCombChunk);
+      if (gc > r) gc = r;
+      k_insert_comb<<<gc, 256, 0, s>>>(begin, end, key, table, mask, slot_idx, rest, rest_len, ctr);
+      LCG_LAUNCH_CHECK("insert_comb");
+    }
+    list = rest;  // at most d phrases; the count is on the device
+    list_len = rest_len;
+  }
   if (g > kPersistentBlocks) g = kPersistentBlocks;
   if (bytes)
-    k_insert<uint8_t><<<g, 256, 0, s>>>(d, key, pstart, plen, static_cast<const uint8_t*>(content),
-                                        rule_off, static_cast<const uint8_t*>(rule_rhs),
-                                        u_committed, table, mask, slot_idx, ctr);
+    k_insert<uint8_t><<<g, 256, 0, s>>>(0, d, d, list, list_len, key, pstart, plen,
+                                        static_cast<const uint8_t*>(content), rule_off,
+                                        static_cast<const uint8_t*>(rule_rhs), u_committed, table,
+                                        mask, slot_idx, ctr);
   else
-    k_insert<uint32_t><<<g, 256, 0, s>>>(d, key, pstart, plen,
+    k_insert<uint32_t><<<g, 256, 0, s>>>(0, d, d, list, list_len, key, pstart, plen,
                                          static_cast<const uint32_t*>(content), rule_off,
                                          static_cast<const uint32_t*>(rule_rhs), u_committed,
                                          table, mask, slot_idx, ctr);
@@ -880,9 +1165,13 @@ __device__ __forceinline__ unsigned long long wave_excl_scan(unsigned long long 
   return x - v;
 }
 
-// New rules: the first occurrence of every new phrase appends the rule.  The
-// wave of 64 consecutive phrases is exactly one flag word, so the offset of
-// its right-hand side is the word's scanned length plus a wave scan.
+// New rules: the first occurrence of every new phrase appends the rule.  One
+// wave per 64-phrase flag word (a word without a new phrase ends at once), so
+// the offset of a rule's right-hand side is the word's scanned length plus a
+// wave scan.  A rule with an exact key gets its fingerprint here (Eq. 4 over
+// the F values of its symbols, fprev), a long one brings it from emit (fnew).
+// The slot then holds the rank and F side by side: one 8-byte load gives a
+// later occurrence both.
 template <typename Sym>
 __global__ __launch_bounds__(256) void k_commit_new(uint64_t d, const uint32_t* __restrict__ slot_idx,
                                                     Slot* table, const uint64_t* __restrict__ newbits,
@@ -892,64 +1181,167 @@ __global__ __launch_bounds__(256) void k_commit_new(uint64_t d, const uint32_t* 
                                                     const uint64_t* __restrict__ pstart,
                                                     const uint32_t* __restrict__ plen,
                                                     const Sym* __restrict__ content,
-                                                    const uint32_t* __restrict__ fnew, uint32_t u_prev,
-                                                    uint64_t q_prev, uint64_t* __restrict__ rule_off,
+                                                    const uint32_t* __restrict__ fnew,
+                                                    const uint32_t* __restrict__ fprev, LevelHash h,
+                                                    uint32_t u_prev, uint64_t q_prev,
+                                                    uint64_t* __restrict__ rule_off,
                                                     Sym* __restrict__ rule_rhs,
                                                     uint32_t* __restrict__ rule_fp) {
   constexpr bool kBytes = sizeof(Sym) == 1;
-  const uint64_t o = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  const uint64_t w = o < d ? newbits[o >> 6] : 0;
-  const bool isnew = (w >> (o & 63)) & 1ULL;
-  const uint64_t kk = isnew ? key[o] : 0;
-  const uint32_t L = isnew ? key_len<kBytes>(kk, plen, o) : 0;
-  const unsigned long long excl = wave_excl_scan(L);
-  if (!isnew) return;
-  const uint32_t r = u_prev + (uint32_t)(wcnt_base[o >> 6] +
-                                         __builtin_popcountll(w & ((1ULL << (o & 63)) - 1ULL)));
-  const uint64_t q = q_prev + wlen_base[o >> 6] + excl;
-  if (kk & kLongTag) {
-    const Sym* src = content + pstart[o];
-    for (uint32_t i = 0; i < L; ++i) rule_rhs[q + i] = src[i];
-  } else {
-    for (uint32_t i = 0; i < L; ++i) rule_rhs[q + i] = (Sym)key_sym<kBytes>(kk, i);
+  const uint64_t W = (d + 63) / 64;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t wd = blockIdx.x * (uint64_t)(blockDim.x / 64) + (threadIdx.x >> 6);
+  if (wd >= W) return;  // uniform in the wave
+  {
+    const uint64_t fw = newbits[wd];
+    if (!fw) return;  // uniform in the wave
+    const uint64_t o = wd * 64 + lane;
+    const bool isnew = (fw >> lane) & 1ULL;
+    const uint64_t kk = isnew ? key[o] : 0;
+    const uint32_t L = isnew ? key_len<kBytes>(kk, plen, o) : 0;
+    const unsigned long long excl = wave_excl_scan(L);
+    if (!isnew) return;
+    const uint32_t r = u_prev + (uint32_t)(wcnt_base[wd] +
+                                           __builtin_popcountll(fw & ((1ULL << lane) - 1ULL)));
+    const uint64_t q = q_prev + wlen_base[wd] + excl;
+    uint32_t F;
+    if (kk & kLongTag) {
+      const Sym* src = content + pstart[o];
+      for (uint32_t i = 0; i < L; ++i) rule_rhs[q + i] = src[i];
+      F = fnew[o];
+    } else {
+      uint64_t S = 0;
+      for (uint32_t i = L; i-- > 0;) {
+        const uint32_t v = key_sym<kBytes>(kk, i);
+        rule_rhs[q + i] = (Sym)v;
+        S = addmod61(mulmod61(S, h.c), fprev[v]);
+      }
+      F = (uint32_t)(addmod61(mulmod61(h.a, S), h.b) & 0xFFFFFFFFULL);
+    }
+    rule_off[r + 1] = q + L;
+    rule_fp[r] = F;
+    Slot* sl = &table[slot_idx[o]];
+    *reinterpret_cast<uint64_t*>(&sl->minocc) = (uint64_t)F | ((uint64_t)r << 32);
+    const uint64_t w0 = sl->w0;
+    if (w0 & kLongTag) sl->w0 = (w0 & kHiMask) | r;
   }
-  rule_off[r + 1] = q + L;
-  rule_fp[r] = fnew[o];
-  Slot* sl = &table[slot_idx[o]];
-  sl->rank = r;
-  const uint64_t w0 = sl->w0;
-  if (w0 & kLongTag) sl->w0 = (w0 & kHiMask) | r;
 }
 
-// T^{i+1}: every phrase takes the (now committed) rank of its slot.
+// T^{i+1}: every phrase takes the (now committed) rank of its slot, and its
+// fingerprint when the next round needs it (fnext).
 __global__ __launch_bounds__(256) void k_rewrite(uint64_t d, const uint32_t* __restrict__ slot_idx,
                                                  const Slot* __restrict__ table,
-                                                 uint32_t* __restrict__ sym_next) {
+                                                 uint32_t* __restrict__ sym_next,
+                                                 uint32_t* __restrict__ fnext) {
   const uint64_t o = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (o >= d) return;
   const uint32_t sidx = slot_idx[o];
-  sym_next[o] = sidx == kNone ? 0u : table[sidx].rank;  // kNone only after an overflow (redone)
+  // kNone only after an overflow (the round is redone)
+  const uint64_t fr = sidx == kNone ? 0 : *reinterpret_cast<const uint64_t*>(&table[sidx].minocc);
+  sym_next[o] = (uint32_t)(fr >> 32);
+  if (fnext) fnext[o] = (uint32_t)fr;
+}
+
+// The same with one table read per distinct slot of a chunk of phrases (for
+// the rounds that use the combining insert: there a few slots take most of
+// the phrases).
+__global__ __launch_bounds__(256) void k_rewrite_comb(uint64_t d, const uint32_t* __restrict__ slot_idx,
+                                                      const Slot* __restrict__ table,
+                                                      uint32_t* __restrict__ sym_next,
+                                                      uint32_t* __restrict__ fnext) {
+  __shared__ uint32_t s_sk[kComb];
+  __shared__ unsigned long long s_fr[kComb];
+  __shared__ uint16_t s_loc[kCombChunk];
+  for (uint64_t c0 = blockIdx.x * (uint64_t)kCombChunk; c0 < d; c0 += (uint64_t)gridDim.x * kCombChunk) {
+    for (int i = threadIdx.x; i < kComb; i += blockDim.x) s_sk[i] = kNone;
+    uint32_t sc[kCombItems];
+#pragma unroll
+    for (int x = 0; x < kCombItems; ++x) {
+      const uint64_t o = c0 + x * 256 + threadIdx.x;
+      sc[x] = o < d ? slot_idx[o] : kNone;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int x = 0; x < kCombItems; ++x) {
+      const uint32_t li = x * 256 + threadIdx.x;
+      uint32_t found = kNone;
+      {
+        const uint32_t sidx = sc[x];
+        if (sidx != kNone) {
+          uint32_t lpos = (sidx * 0x9E3779B1u) >> (32 - kCombLog2);
+          for (int t = 0; t < kCombProbe && found == kNone; ++t) {
+            const uint32_t w = s_sk[lpos];
+            bool hit;
+            if (w == kNone) {
+              const uint32_t prev = atomicCAS(&s_sk[lpos], kNone, sidx);
+              hit = prev == kNone || prev == sidx;
+            } else {
+              hit = w == sidx;
+            }
+            if (hit) found = lpos;
+            else lpos = (lpos + 1) & (kComb - 1);
+          }
+        }
+      }
+      s_loc[li] = found == kNone ? kCombNone : (uint16_t)found;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kComb / 256; ++j) {
+      const uint32_t sidx = s_sk[j * 256 + threadIdx.x];
+      s_fr[j * 256 + threadIdx.x] =
+          sidx == kNone ? 0 : *reinterpret_cast<const uint64_t*>(&table[sidx].minocc);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int x = 0; x < kCombItems; ++x) {
+      const uint32_t li = x * 256 + threadIdx.x;
+      const uint64_t o = c0 + li;
+      if (o < d) {
+        const uint16_t lr = s_loc[li];
+        uint64_t fr;
+        if (lr != kCombNone) {
+          fr = s_fr[lr];
+        } else {
+          const uint32_t sidx = sc[x];
+          fr = sidx == kNone ? 0 : *reinterpret_cast<const uint64_t*>(&table[sidx].minocc);
+        }
+        sym_next[o] = (uint32_t)(fr >> 32);
+        if (fnext) fnext[o] = (uint32_t)fr;
+      }
+    }
+    __syncthreads();
+  }
 }
 
 void launch_commit(bool bytes, uint64_t d, const uint32_t* slot_idx, Slot* table,
                    const uint64_t* newbits, const uint64_t* wcnt_base, const uint64_t* wlen_base,
                    const uint64_t* key, const uint64_t* pstart, const uint32_t* plen,
-                   const void* content,
-                   const uint32_t* fnew, uint32_t u_prev, uint64_t q_prev, uint64_t* rule_off,
-                   void* rule_rhs, uint32_t* rule_fp, uint32_t* sym_next, hipStream_t s) {
+                   const void* content, const uint32_t* fnew, const uint32_t* fprev, LevelHash h,
+                   uint32_t u_prev, uint64_t q_prev, uint64_t* rule_off, void* rule_rhs,
+                   uint32_t* rule_fp, uint32_t* sym_next, uint32_t* fnext, bool combine,
+                   hipStream_t s) {
   if (!d) return;
+  const unsigned g = grid_for((d + 63) / 64, 4);  // one wave per flag word
   if (bytes)
-    k_commit_new<uint8_t><<<grid_for(d, 256), 256, 0, s>>>(
+    k_commit_new<uint8_t><<<g, 256, 0, s>>>(
         d, slot_idx, table, newbits, wcnt_base, wlen_base, key, pstart, plen,
-        static_cast<const uint8_t*>(content), fnew, u_prev, q_prev, rule_off,
+        static_cast<const uint8_t*>(content), fnew, fprev, h, u_prev, q_prev, rule_off,
         static_cast<uint8_t*>(rule_rhs), rule_fp);
   else
-    k_commit_new<uint32_t><<<grid_for(d, 256), 256, 0, s>>>(
+    k_commit_new<uint32_t><<<g, 256, 0, s>>>(
         d, slot_idx, table, newbits, wcnt_base, wlen_base, key, pstart, plen,
-        static_cast<const uint32_t*>(content), fnew, u_prev, q_prev, rule_off,
+        static_cast<const uint32_t*>(content), fnew, fprev, h, u_prev, q_prev, rule_off,
         static_cast<uint32_t*>(rule_rhs), rule_fp);
   LCG_LAUNCH_CHECK("commit_new");
-  k_rewrite<<<grid_for(d, 256), 256, 0, s>>>(d, slot_idx, table, sym_next);
+  if (combine) {
+    unsigned g = grid_for(d, kCombChunk);
+    const unsigned r = resident_blocks((const void*)k_rewrite_comb, 256);
+    if (g > r) g = r;
+    k_rewrite_comb<<<g, 256, 0, s>>>(d, slot_idx, table, sym_next, fnext);
+  } else {
+    k_rewrite<<<grid_for(d, 256), 256, 0, s>>>(d, slot_idx, table, sym_next, fnext);
+  }
   LCG_LAUNCH_CHECK("rewrite");
 }
 
@@ -966,7 +1358,10 @@ __global__ void k_rehash(const Slot* __restrict__ old_t, uint64_t old_cap, Slot*
       unsigned long long prev = atomicCAS(reinterpret_cast<unsigned long long*>(&new_t[pos].w0),
                                           (unsigned long long)kEmpty, (unsigned long long)sl.w0);
       done = prev == kEmpty;
-      if (done) new_t[pos].rank = sl.rank;
+      if (done) {
+        new_t[pos].minocc = sl.minocc;  // the committed rule's F
+        new_t[pos].rank = sl.rank;
+      }
       else pos = (pos + 1) & mask;
     }
     if (!done) atomicOr(&ctr->overflow, 1u);

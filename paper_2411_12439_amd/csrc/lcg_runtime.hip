@@ -283,8 +283,9 @@ static uint64_t next_pow2(uint64_t x) {
   return p;
 }
 
-// HyperLogLog estimate (Flajolet et al. 2007) with the linear-counting
-// correction for small cardinalities.
+// HyperLogLog estimate (Flajolet et al. 2007) over 32-bit key hashes, with
+// the linear-counting correction for small cardinalities and the
+// hash-collision correction for large ones.
 static double hll_estimate(const unsigned int* regs) {
   const double m = kHll;
   double sum = 0;
@@ -294,7 +295,9 @@ static double hll_estimate(const unsigned int* regs) {
     if (regs[i] == 0) ++zeros;
   }
   double e = (0.7213 / (1.0 + 1.079 / m)) * m * m / sum;
+  const double two32 = 4294967296.0;
   if (e <= 2.5 * m && zeros) e = m * std::log(m / zeros);
+  else if (e > two32 / 30.0) e = e < two32 ? -two32 * std::log(1.0 - e / two32) : two32;
   return e;
 }
 
@@ -318,12 +321,12 @@ struct Work {
   DBuf<Counters> ctr, fin;
   DBuf<uint8_t> content8, hll_part;
   DBuf<uint2> tile_seg;
-  DBuf<uint32_t> content32, remap[2];
+  DBuf<uint32_t> content32, remap[2], rest;
   void release_after(hipStream_t s) {
     DBuf<uint64_t>* b64[] = {&bits, &tile_cnt, &tile_base, &scan_tmp, &pstart, &key, &off[0],
                              &off[1], &newbits, &wcnt, &wlen, &wcnt_base, &wlen_base};
     DBuf<uint32_t>* b32[] = {&plen, &slot_idx, &sym[0], &sym[1], &fpv[0], &fpv[1], &lut,
-                             &content32, &remap[0], &remap[1]};
+                             &content32, &remap[0], &remap[1], &rest};
     for (auto* b : b64) b->reset_after(s);
     for (auto* b : b32) b->reset_after(s);
     ctr.reset_after(s);
@@ -399,7 +402,8 @@ static void ensure_table(Level& L, uint64_t need, uint32_t min_log2, Work& w, hi
   uint64_t want = std::max<uint64_t>(next_pow2(2 * std::max<uint64_t>(need, 1)), 1ull << min_log2);
   if (force_grow) want = std::max<uint64_t>(want, L.tcap * 4);
   if (L.tcap >= want && L.table.p) return;
-  if (want > (1ull << 34)) throw LcgError{LCG_ETABLE, "dictionary capacity limit reached"};
+  // slot indices are uint32 and kNone is never one
+  if (want > (1ull << 31)) throw LcgError{LCG_ETABLE, "dictionary capacity limit reached"};
   DBuf<Slot> nt;
   nt.need(want, s);
   launch_fill_slots(nt.p, want, s);
@@ -425,10 +429,15 @@ static void ensure_level(lcg_grammar* g, size_t i, hipStream_t s) {
   }
 }
 
+// A round whose estimated count of new keys is at most 1/kCombineRatio of its
+// phrases uses the combining insert and rewrite.
+constexpr uint64_t kCombineRatio = 32;
+
 struct DedupResult {
   uint32_t u_new;
   uint64_t q_new;
   uint64_t probes, compares;
+  bool combined;
 };
 
 // insert -> newflags -> scan -> commit for the d phrases of level `lv`
@@ -436,13 +445,17 @@ struct DedupResult {
 // 1); fnew holds their F values; ranks land in sym_next.  Regrows the
 // dictionary and retries if a probe sequence ran out of budget.
 static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const void* content,
-                                const uint32_t* fnew, uint32_t* sym_next, uint64_t est_new,
-                                const Opts& o, Work& w, hipStream_t s, PhaseEvents* pe = nullptr) {
+                                const uint32_t* fnew, uint32_t* sym_next, uint32_t* fnext,
+                                uint64_t est_new, const Opts& o, Work& w, hipStream_t s,
+                                PhaseEvents* pe = nullptr) {
   Level& L = g->levels[lv - 1];
   const bool bytes = lv == 1;
   ensure_table(L, (uint64_t)L.u + est_new, o.table_min_log2, w, s);
   const uint64_t W = (d + 63) / 64;
+  // few distinct keys for many phrases: combine equal keys per chunk first
+  const bool combine = est_new * kCombineRatio <= d;
   w.slot_idx.need(d, s);
+  if (combine) w.rest.need(d, s);
   w.newbits.need(W, s);
   w.wcnt.need(W, s);
   w.wlen.need(W, s);
@@ -457,7 +470,8 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
     const void* rule_rhs = bytes ? (const void*)L.rhs8.p : (const void*)L.rhs32.p;
     if (pe) pe->rec(3, s);
     launch_insert(bytes, d, w.key.p, w.pstart.p, w.plen.p, content, L.off.p, rule_rhs, L.u,
-                  L.table.p, L.tcap - 1, w.slot_idx.p, w.ctr.p, s);
+                  L.table.p, L.tcap - 1, w.slot_idx.p, combine, w.rest.p, &w.ctr.p->rest_len,
+                  w.ctr.p, s);
     if (pe) pe->rec(4, s);
     // first occurrences from the table side when the table is much smaller
     // than the phrase array (a scan of the table plus one atomic per new rule
@@ -497,13 +511,15 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
     L.rhs32.grow(L.q + q_new, L.q, s);
     rule_rhs = L.rhs32.p;
   }
+  // F of the level-(lv-1) symbols: h^0 of the bytes, else the previous level's rules
+  const uint32_t* fprev = bytes ? w.lut.p : g->levels[lv - 2].fp.p;
   launch_commit(bytes, d, w.slot_idx.p, L.table.p, w.newbits.p, w.wcnt_base.p, w.wlen_base.p,
-                w.key.p, w.pstart.p, w.plen.p, content, fnew, L.u, L.q, L.off.p, rule_rhs, L.fp.p,
-                sym_next, s);
+                w.key.p, w.pstart.p, w.plen.p, content, fnew, fprev, g->H.lv[lv], L.u, L.q,
+                L.off.p, rule_rhs, L.fp.p, sym_next, fnext, combine, s);
   if (pe) pe->rec(6, s);
   L.u += (uint32_t)u_new;
   L.q += q_new;
-  return DedupResult{(uint32_t)u_new, q_new, hc.probes, hc.compares};
+  return DedupResult{(uint32_t)u_new, q_new, hc.probes, hc.compares, combine};
 }
 
 // BuildGram of k strings into g (fresh or existing): the batched form.
@@ -616,7 +632,8 @@ static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_
     const uint64_t est =
         sketch ? std::min<uint64_t>(d, (uint64_t)(hll_estimate(mb->ctr.hll) * 1.25) + 64) : d;
     const void* content = bytes ? (const void*)d_text : (const void*)w.sym[cur ^ 1].p;
-    DedupResult r = dedup_commit(g, lv, d, content, w.fpv[cur].p, w.sym[cur].p, est, o, w, s, &pe);
+    DedupResult r = dedup_commit(g, lv, d, content, w.fpv[cur].p, w.sym[cur].p, w.fpv[cur].p, est,
+                                 o, w, s, &pe);
     zero_counters(w.fin.p, s);
     launch_segments(cur_off, k, w.bits.p, w.tile_base.p, d, w.off[cur].p, s);
     launch_finish(cur_off, w.off[cur].p, k, w.sym[cur].p, lv, g->c_level.p + c_base,
@@ -624,7 +641,8 @@ static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_
     pe.rec(7, s);
     const uint64_t t_insert = pe.ns(3, 4), t_rank = pe.ns(4, 5);
     prev = Stat{active_len, d, r.u_new, r.q_new, 0, r.probes, r.compares, g->levels[lv - 1].tcap,
-                t_classify + t_emit + t_insert + t_rank, t_classify, t_emit, t_insert, t_rank, 0, 0};
+                t_classify + t_emit + t_insert + t_rank, t_classify, t_emit, t_insert, t_rank, 0, 0,
+                r.combined ? 1u : 0u};
     pending = true;
     cur_off = w.off[cur].p;
     n_i = d;
@@ -668,7 +686,7 @@ static void merge_core(lcg_grammar* a, const lcg_grammar* b, Work& w, hipStream_
         launch_merge_prepare(false, ub, B.off.p, B.rhs32.p, remap_prev, f_prev, a->H.lv[lv], 0,
                              w.content32.p, w.pstart.p, w.plen.p, w.key.p, s);
       }
-      dedup_commit(a, (uint32_t)lv, ub, content, B.fp.p, w.remap[cur].p, ub, o, w, s);
+      dedup_commit(a, (uint32_t)lv, ub, content, B.fp.p, w.remap[cur].p, nullptr, ub, o, w, s);
       launch_c_merge(b->c_level.p, b->c_sym.p, kb, (uint32_t)lv, w.remap[cur].p,
                      a->c_level.p + ka, a->c_sym.p + ka, s);
     }

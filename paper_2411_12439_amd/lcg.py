@@ -12,10 +12,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblcg.so")
-STATS_FIELDS = 15
+STATS_FIELDS = 16
 STAT_NAMES = ("n", "phrases", "new_rules", "new_rhs", "active", "probes", "compares",
               "table_cap", "t_round_ns", "t_classify_ns", "t_emit_ns", "t_insert_ns", "t_rank_ns",
-              "t_commit_ns", "t_segments_ns")
+              "t_commit_ns", "t_segments_ns", "dict_mode")
 
 MODE_BATCHED = 0
 MODE_PLAIN = 1

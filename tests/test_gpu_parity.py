@@ -168,6 +168,16 @@ def test_errors(L):
     torch.cuda.synchronize()
 
 
+def test_combining_round_equals_oracle(L):
+    """4 MB of the tiny recipe: round 1 has ~10^6 phrases over a few thousand keys,
+    so it runs the combining insert and rewrite; exact equality with the oracle."""
+    text, off = D.make_config("tiny", scale=4.0)
+    g = _gpu(L, text, off)
+    st = g.stats()
+    assert st[0, 2] * 32 <= st[0, 1], "round 1 should have few distinct keys"
+    _assert_same(g.export(), _oracle(text, off).export())
+
+
 # ---------------------------------------------------------------- other configurations (scaled)
 @pytest.mark.parametrize("name,scale", [("repeats", 0.004), ("batched", 0.001), ("bacterial", 0.01)])
 def test_scaled_configs_equal_oracle(L, name, scale):
