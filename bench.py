@@ -51,7 +51,7 @@ WORKLOADS = {
 # per new rule, commit the new rule's rank, F and right-hand side, rewrite the
 # rank of every phrase.
 PHASES = ("classify", "emit", "insert", "rank", "commit", "segments")
-ROOFLINE_KERNEL = "k_insert<unsigned int>"
+ROOFLINE_KERNEL = "k_insert<unsigned int, false>"
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2411_12439_amd", "csrc", "lcg_kernels.hip")
 
@@ -70,8 +70,8 @@ def phase_alg_bytes(st):
 
 
 def insert_rounds(st):
-    """Rows whose insert phase is exactly one k_insert<unsigned int> launch:
-    rounds >= 2 with one insert per phrase (dict_mode 0)."""
+    """Rows whose insert phase is exactly one k_insert<unsigned int, false>
+    launch: rounds >= 2 with one insert per phrase and host reads (mode 0)."""
     return [r for i, r in enumerate(st, start=1) if i >= 2 and int(r[15]) == 0 and r[1] > 0]
 
 
@@ -85,7 +85,7 @@ def profile_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed PMC summary of the
     workload, or None when there is none or the kernel source has changed
     since its counters were taken."""
-    name = "%s_%s_traffic.txt" % (kernel.replace("<", "_").replace(">", "").replace(" ", "_"),
+    name = "%s_%s_traffic.txt" % ("".join(c if c.isalnum() else "_" for c in kernel).strip("_"),
                                   workload)
     path = os.path.join(PROFILE_DIR, name)
     if not os.path.exists(path):
@@ -219,7 +219,7 @@ def main():
     alg = path_alg_bytes(stats)
     alg_gbps = alg / step_s.mean() / 1e9
 
-    # The roofline of the dominant kernel, k_insert<unsigned int>: in the
+    # The roofline of the dominant kernel, k_insert<unsigned int, false>: in the
     # rounds listed by insert_rounds its phase events bracket exactly its one
     # launch, so the mean below is its mean launch duration.
     per_alg = phase_alg_bytes(stats)

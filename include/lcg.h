@@ -73,7 +73,11 @@ typedef struct {
                           fingerprint bits, so that dictionary lookups rely on the full
                           right-hand-side comparison; 0 = normal keys */
   uint32_t table_min_log2; /* smallest dictionary capacity, log2 (6..34; 0 = 12) */
-  uint32_t reserved[2];     /* must be zero */
+  uint32_t tail_log2;  /* rounds over at most 2^tail_log2 symbols are queued without reading
+                          sizes back to the host (each kernel reads its size from device
+                          memory, dictionaries are sized for the worst case); 1..40,
+                          0 = 22.  Results do not depend on it. */
+  uint32_t reserved;   /* must be zero */
 } lcg_opts;
 
 /* Fill *o with the defaults (seed 0, batched mode, unlimited budget). */
@@ -149,9 +153,10 @@ lcg_status lcg_c_copy(lcg_grammar_t g, uint8_t* h_level, uint32_t* h_sym);
  * capacity, then device nanoseconds (0 without LCG_FLAG_TIMING) of the round's
  * kernels (sum of the following), of classify + tile scan, of emit, of
  * insert, of rank (new flags + scans), of commit, and of the segment update;
- * last, the dictionary mode of the round (0: one insert per phrase, 1: equal
- * keys combined per chunk of phrases first, chosen when the round's key
- * sketch estimates few distinct keys per phrase).
+ * last, the mode of the round (0: one insert per phrase, 1: equal keys
+ * combined per chunk of phrases first, chosen when the round's key sketch
+ * estimates few distinct keys per phrase; 2: one insert per phrase, the round
+ * queued without host reads, see lcg_opts.tail_log2).
  * Rounds of later builds (lcg_build_into, the per-string builds of the plain
  * form) are appended.
  */

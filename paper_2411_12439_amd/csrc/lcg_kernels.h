@@ -36,7 +36,8 @@ struct RoundIn {
   const uint32_t* lut;      // h^0 of the 256 byte values (level 1)
   const uint64_t* off;      // k+1 segment offsets of T^i
   uint32_t k;
-  uint64_t n;               // length of T^i
+  uint64_t n;               // length of T^i (a bound of it when n_dev is set)
+  const uint64_t* n_dev;    // NULL, or the length of T^i in device memory
   bool bytes;               // symbols are bytes
 };
 
@@ -55,34 +56,43 @@ void launch_emit(const RoundIn& in, const uint64_t* bits, const uint64_t* tile_b
 // tmp must hold scan_tmp_words(n) uint64.
 size_t scan_tmp_words(uint64_t n);
 void scan_exclusive(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s);
+// One-block exclusive scan of count = ceil(*x_dev / 2^shift) values (count
+// itself without x_dev); out[count] and *total (if given) receive the sum.
+void scan_one(const uint64_t* in, uint64_t* out, uint64_t count, const uint64_t* x_dev, int shift,
+              uint64_t* total, hipStream_t s);
 
 // combine: the rounds where few keys take most phrases (rest: d uint32 of
 // scratch, its count in ctr->rest_len, zero on entry).
-void launch_insert(bool bytes, uint64_t d, const uint64_t* key, const uint64_t* pstart,
-                   const uint32_t* plen, const void* content, const uint64_t* rule_off,
-                   const void* rule_rhs, uint32_t u_committed, Slot* table, uint64_t mask,
-                   uint32_t* slot_idx, bool combine, uint32_t* rest, uint32_t* rest_len,
-                   Counters* ctr, hipStream_t s);
-void launch_newflags(bool bytes, uint64_t d, const uint32_t* slot_idx, const Slot* table,
-                     const uint64_t* key, const uint32_t* plen, uint64_t* newbits, uint64_t* wcnt,
-                     uint64_t* wlen, hipStream_t s);
+//
+// Kernels given a device count (d_dev, in.n_dev: the size sits in device
+// memory, the host passes a bound of it in d / in.n) are launched over the
+// bound and stop at the count: rounds can then be queued without reading
+// sizes back.
+void launch_insert(bool bytes, uint64_t d, const uint64_t* d_dev, const uint64_t* key,
+                   const uint64_t* pstart, const uint32_t* plen, const void* content,
+                   const uint64_t* rule_off, const void* rule_rhs, uint32_t u_committed,
+                   Slot* table, uint64_t mask, uint32_t* slot_idx, bool combine, uint32_t* rest,
+                   uint32_t* rest_len, Counters* ctr, hipStream_t s);
+void launch_newflags(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t* slot_idx,
+                     const Slot* table, const uint64_t* key, const uint32_t* plen,
+                     uint64_t* newbits, uint64_t* wcnt, uint64_t* wlen, hipStream_t s);
 void launch_newflags_table(bool bytes, const Slot* table, uint64_t cap, uint64_t d,
                            const uint64_t* key, const uint32_t* plen, uint64_t* newbits,
                            uint64_t* wcnt, uint64_t* wlen, hipStream_t s);
-void launch_commit(bool bytes, uint64_t d, const uint32_t* slot_idx, Slot* table,
+void launch_commit(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t* slot_idx, Slot* table,
                    const uint64_t* newbits, const uint64_t* wcnt_base, const uint64_t* wlen_base,
                    const uint64_t* key, const uint64_t* pstart, const uint32_t* plen,
                    const void* content, const uint32_t* fnew, const uint32_t* fprev, LevelHash h,
                    uint32_t u_prev, uint64_t q_prev, uint64_t* rule_off, void* rule_rhs,
-                   uint32_t* rule_fp, uint32_t* sym_next, uint32_t* fnext, bool combine,
-                   hipStream_t s);
+                   uint32_t* rule_fp, uint32_t* sym_next, uint32_t* fnext, hipStream_t s);
 void launch_rehash(const Slot* old_t, uint64_t old_cap, Slot* new_t, uint64_t new_mask,
                    Counters* ctr, hipStream_t s);
 
 void launch_c_init(const uint8_t* text, const uint64_t* off, uint32_t k, uint8_t* c_level,
                    uint32_t* c_sym, hipStream_t s);
 void launch_segments(const uint64_t* off, uint32_t k, const uint64_t* bits,
-                     const uint64_t* tile_base, uint64_t d, uint64_t* new_off, hipStream_t s);
+                     const uint64_t* tile_base, uint64_t d, const uint64_t* d_dev,
+                     uint64_t* new_off, hipStream_t s);
 void launch_finish(const uint64_t* off, const uint64_t* new_off, uint32_t k,
                    const uint32_t* sym_next, uint32_t level, uint8_t* c_level, uint32_t* c_sym,
                    Counters* ctr, hipStream_t s);

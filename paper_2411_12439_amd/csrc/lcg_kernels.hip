@@ -286,7 +286,9 @@ __device__ __forceinline__ void stage_fp(const RoundIn& in, const uint32_t* s_lu
 // binary searches over the offsets run side by side, not inside the tile's
 // block).
 __global__ void k_tile_seg(const uint64_t* __restrict__ off, uint32_t k, uint64_t n,
-                           uint64_t tiles, uint2* __restrict__ tile_seg) {
+                           const uint64_t* __restrict__ n_dev, uint2* __restrict__ tile_seg) {
+  if (n_dev) n = *n_dev;
+  const uint64_t tiles = (n + kTile - 1) / kTile;
   const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (t >= tiles) return;
   const uint64_t t0 = t * kTile;
@@ -297,9 +299,12 @@ __global__ void k_tile_seg(const uint64_t* __restrict__ off, uint32_t k, uint64_
 }
 
 template <bool BYTES>
-__global__ __launch_bounds__(kBlock) void k_classify(RoundIn in, uint64_t* __restrict__ bits,
+__global__ __launch_bounds__(kBlock) void k_classify(RoundIn in0, uint64_t* __restrict__ bits,
                                                      uint64_t* __restrict__ tile_cnt,
                                                      const uint2* __restrict__ tile_seg) {
+  RoundIn in = in0;
+  if (in0.n_dev) in.n = *in0.n_dev;  // launched over a bound; the size is on the device
+  if ((uint64_t)blockIdx.x * kTile >= in.n) return;
   __shared__ uint32_t s_lut[256];
   __shared__ uint32_t s_f[kCStagePadded];
   __shared__ uint32_t s_seg[2];
@@ -384,8 +389,8 @@ __global__ __launch_bounds__(kBlock) void k_classify(RoundIn in, uint64_t* __res
 void launch_classify(const RoundIn& in, uint64_t* bits, uint64_t* tile_cnt, uint2* tile_seg,
                      hipStream_t s) {
   static_assert(kItems == 16 && kBlock == 256, "bit packing assumes 16 positions per thread");
-  unsigned tiles = grid_for(in.n, kTile);
-  k_tile_seg<<<grid_for(tiles, 256), 256, 0, s>>>(in.off, in.k, in.n, tiles, tile_seg);
+  unsigned tiles = grid_for(in.n, kTile);  // in.n: the size, or its bound when in.n_dev is set
+  k_tile_seg<<<grid_for(tiles, 256), 256, 0, s>>>(in.off, in.k, in.n, in.n_dev, tile_seg);
   LCG_LAUNCH_CHECK("tile_seg");
   if (in.bytes) k_classify<true><<<tiles, kBlock, 0, s>>>(in, bits, tile_cnt, tile_seg);
   else k_classify<false><<<tiles, kBlock, 0, s>>>(in, bits, tile_cnt, tile_seg);
@@ -520,7 +525,7 @@ __device__ __forceinline__ uint64_t phrase_fp(const RoundIn& in, const uint32_t*
 constexpr uint32_t kLongList = 2048;  // long phrases deferred per tile; more are done inline
 
 template <bool BYTES>
-__global__ __launch_bounds__(kBlock) void k_emit(RoundIn in, const uint64_t* __restrict__ bits,
+__global__ __launch_bounds__(kBlock) void k_emit(RoundIn in0, const uint64_t* __restrict__ bits,
                                                  const uint64_t* __restrict__ tile_base,
                                                  const uint2* __restrict__ tile_seg, uint64_t tiles,
                                                  LevelHash h, uint32_t key_bits,
@@ -536,6 +541,11 @@ __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in, const uint64_t* __r
   __shared__ uint32_t s_nlong;
   __shared__ uint32_t s_hll[kHll];
   __shared__ EmitStage<BYTES> st;
+  RoundIn in = in0;
+  if (in0.n_dev) {  // launched over a bound; the size is on the device
+    in.n = *in0.n_dev;
+    tiles = (in.n + kTile - 1) / kTile;
+  }
   if constexpr (BYTES) s_lut[threadIdx.x] = in.lut[threadIdx.x];
   for (int i = threadIdx.x; i < kHll; i += kBlock) s_hll[i] = 0;
   for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
@@ -715,6 +725,56 @@ void scan_exclusive(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* tmp
   LCG_LAUNCH_CHECK("copy_word");
 }
 
+// Exclusive scan in one block, for short arrays whose length is on the
+// device: count = ceil(*x_dev / 2^shift) (or count_host without x_dev).
+// out[count] and, if given, *total receive the sum.
+constexpr int kScanOneThreads = 1024;
+__global__ __launch_bounds__(kScanOneThreads) void k_scan_one(const uint64_t* __restrict__ in,
+                                                              uint64_t* __restrict__ out,
+                                                              uint64_t count,
+                                                              const uint64_t* __restrict__ x_dev,
+                                                              int shift,
+                                                              uint64_t* __restrict__ total) {
+  __shared__ uint64_t s_wave[kScanOneThreads / 64];
+  __shared__ uint64_t s_carry;
+  if (x_dev) count = (*x_dev + (1ull << shift) - 1) >> shift;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (uint64_t c0 = 0; c0 < count; c0 += kScanOneThreads) {
+    const uint64_t i = c0 + threadIdx.x;
+    const uint64_t v = i < count ? in[i] : 0;
+    uint64_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint64_t y = __shfl_up(x, d, 64);
+      if (lane >= d) x += y;
+    }
+    if (lane == 63) s_wave[wid] = x;
+    __syncthreads();
+    uint64_t base = s_carry, tot = 0;
+    for (int w = 0; w < kScanOneThreads / 64; ++w) {
+      const uint64_t sw = s_wave[w];
+      if (w < wid) base += sw;
+      tot += sw;
+    }
+    if (i < count) out[i] = base + x - v;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[count] = s_carry;
+    if (total) *total = s_carry;
+  }
+}
+
+void scan_one(const uint64_t* in, uint64_t* out, uint64_t count, const uint64_t* x_dev, int shift,
+              uint64_t* total, hipStream_t s) {
+  k_scan_one<<<1, kScanOneThreads, 0, s>>>(in, out, count, x_dev, shift, total);
+  LCG_LAUNCH_CHECK("scan_one");
+}
+
 // ------------------------------------------------------------------ insert
 // Equality of two symbol sequences of length len, without an early exit and
 // without a call (both forms of the probe loop around it were compiled into
@@ -751,9 +811,12 @@ __device__ __forceinline__ bool same_seq(const Sym* a, const Sym* b, uint32_t le
 // reference lost its result.
 //
 // The phrases are o = begin .. end-1, or o = list[begin .. *list_len-1] when
-// a list is given; d is the round's phrase count.
-template <typename Sym>
+// a list is given; d is the round's phrase count (DEV_COUNT: d = end =
+// *d_dev; a separate instance, so that profiles tell the rounds queued without
+// host reads from the others).
+template <typename Sym, bool DEV_COUNT>
 __global__ __launch_bounds__(256) void k_insert(uint64_t begin, uint64_t end, uint64_t d,
+                                                const uint64_t* __restrict__ d_dev,
                                                 const uint32_t* __restrict__ list,
                                                 const uint32_t* __restrict__ list_len,
                                                 const uint64_t* __restrict__ key,
@@ -770,10 +833,11 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t begin, uint64_t end, ui
   __syncthreads();
   unsigned long long won = 0, probes = 0, cmps = 0, fails = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  if constexpr (DEV_COUNT) end = d = *d_dev;  // launched over a bound; the count is on the device
   const uint64_t lim = list ? (uint64_t)*list_len : end;
   for (uint64_t i = begin + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < lim; i += stride) {
     const uint64_t o = list ? (uint64_t)list[i] : i;
-    const uint64_t kk = key[o];
+    const uint64_t kk = __builtin_nontemporal_load(&key[o]);  // streams past L1
     uint64_t pos = mix64(kk) & mask;
     uint64_t w = hint_load(&table[pos].w0);
     const bool is_long = (kk & kLongTag) != 0;
@@ -840,7 +904,7 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t begin, uint64_t end, ui
       if ((uint32_t)(mr >> 32) == kNone && (uint32_t)mr > (uint32_t)o)
         atomicMin(&sl->minocc, (uint32_t)o);
     }
-    slot_idx[o] = result;
+    __builtin_nontemporal_store(result, &slot_idx[o]);
   }
   // one global atomic per block and counter
   won = wave_sum(won);
@@ -1028,12 +1092,13 @@ __global__ __launch_bounds__(256) void k_insert_comb(uint64_t begin, uint64_t en
 // occurrence from its L1).  What k_insert_comb leaves (rest, count
 // *rest_len, zero on entry) then goes through k_insert.  Otherwise one
 // k_insert launch takes all d phrases.
-void launch_insert(bool bytes, uint64_t d, const uint64_t* key, const uint64_t* pstart,
-                   const uint32_t* plen, const void* content, const uint64_t* rule_off,
-                   const void* rule_rhs, uint32_t u_committed, Slot* table, uint64_t mask,
-                   uint32_t* slot_idx, bool combine, uint32_t* rest, uint32_t* rest_len,
-                   Counters* ctr, hipStream_t s) {
+void launch_insert(bool bytes, uint64_t d, const uint64_t* d_dev, const uint64_t* key,
+                   const uint64_t* pstart, const uint32_t* plen, const void* content,
+                   const uint64_t* rule_off, const void* rule_rhs, uint32_t u_committed,
+                   Slot* table, uint64_t mask, uint32_t* slot_idx, bool combine, uint32_t* rest,
+                   uint32_t* rest_len, Counters* ctr, hipStream_t s) {
   if (!d) return;
+  if (d_dev && combine) throw std::runtime_error("insert: combining needs the count on the host");
   const uint32_t* list = nullptr;
   const uint32_t* list_len = nullptr;
   unsigned g = grid_for(d, 256);
@@ -1050,29 +1115,40 @@ void launch_insert(bool bytes, uint64_t d, const uint64_t* key, const uint64_t* 
     list_len = rest_len;
   }
   if (g > kPersistentBlocks) g = kPersistentBlocks;
-  if (bytes)
-    k_insert<uint8_t><<<g, 256, 0, s>>>(0, d, d, list, list_len, key, pstart, plen,
-                                        static_cast<const uint8_t*>(content), rule_off,
-                                        static_cast<const uint8_t*>(rule_rhs), u_committed, table,
-                                        mask, slot_idx, ctr);
+  const uint8_t* c8 = static_cast<const uint8_t*>(content);
+  const uint8_t* r8 = static_cast<const uint8_t*>(rule_rhs);
+  const uint32_t* c32 = static_cast<const uint32_t*>(content);
+  const uint32_t* r32 = static_cast<const uint32_t*>(rule_rhs);
+  if (bytes && d_dev)
+    k_insert<uint8_t, true><<<g, 256, 0, s>>>(0, d, d, d_dev, list, list_len, key, pstart, plen, c8,
+                                              rule_off, r8, u_committed, table, mask, slot_idx, ctr);
+  else if (bytes)
+    k_insert<uint8_t, false><<<g, 256, 0, s>>>(0, d, d, d_dev, list, list_len, key, pstart, plen, c8,
+                                               rule_off, r8, u_committed, table, mask, slot_idx, ctr);
+  else if (d_dev)
+    k_insert<uint32_t, true><<<g, 256, 0, s>>>(0, d, d, d_dev, list, list_len, key, pstart, plen,
+                                               c32, rule_off, r32, u_committed, table, mask,
+                                               slot_idx, ctr);
   else
-    k_insert<uint32_t><<<g, 256, 0, s>>>(0, d, d, list, list_len, key, pstart, plen,
-                                         static_cast<const uint32_t*>(content), rule_off,
-                                         static_cast<const uint32_t*>(rule_rhs), u_committed,
-                                         table, mask, slot_idx, ctr);
+    k_insert<uint32_t, false><<<g, 256, 0, s>>>(0, d, d, d_dev, list, list_len, key, pstart, plen,
+                                                c32, rule_off, r32, u_committed, table, mask,
+                                                slot_idx, ctr);
   LCG_LAUNCH_CHECK("insert");
 }
 
 // ------------------------------------------------------------------ newflags
 template <bool BYTES>
-__global__ __launch_bounds__(256) void k_newflags(uint64_t d, const uint32_t* __restrict__ slot_idx,
+__global__ __launch_bounds__(256) void k_newflags(uint64_t d, const uint64_t* __restrict__ d_dev,
+                                                  const uint32_t* __restrict__ slot_idx,
                                                   const Slot* __restrict__ table,
                                                   const uint64_t* __restrict__ key,
                                                   const uint32_t* __restrict__ plen,
                                                   uint64_t* __restrict__ newbits,
                                                   uint64_t* __restrict__ wcnt,
                                                   uint64_t* __restrict__ wlen) {
+  if (d_dev) d = *d_dev;
   const uint64_t o = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (((o >> 6) << 6) >= d) return;  // the whole wave is past the end
   bool f = false;
   unsigned long long len = 0;
   if (o < d) {
@@ -1093,16 +1169,16 @@ __global__ __launch_bounds__(256) void k_newflags(uint64_t d, const uint32_t* __
   }
 }
 
-void launch_newflags(bool bytes, uint64_t d, const uint32_t* slot_idx, const Slot* table,
-                     const uint64_t* key, const uint32_t* plen, uint64_t* newbits, uint64_t* wcnt,
-                     uint64_t* wlen, hipStream_t s) {
+void launch_newflags(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t* slot_idx,
+                     const Slot* table, const uint64_t* key, const uint32_t* plen,
+                     uint64_t* newbits, uint64_t* wcnt, uint64_t* wlen, hipStream_t s) {
   if (!d) return;
   if (bytes)
-    k_newflags<true><<<grid_for(d, 256), 256, 0, s>>>(d, slot_idx, table, key, plen, newbits, wcnt,
-                                                      wlen);
+    k_newflags<true><<<grid_for(d, 256), 256, 0, s>>>(d, d_dev, slot_idx, table, key, plen, newbits,
+                                                      wcnt, wlen);
   else
-    k_newflags<false><<<grid_for(d, 256), 256, 0, s>>>(d, slot_idx, table, key, plen, newbits,
-                                                       wcnt, wlen);
+    k_newflags<false><<<grid_for(d, 256), 256, 0, s>>>(d, d_dev, slot_idx, table, key, plen,
+                                                       newbits, wcnt, wlen);
   LCG_LAUNCH_CHECK("newflags");
 }
 
@@ -1173,7 +1249,8 @@ __device__ __forceinline__ unsigned long long wave_excl_scan(unsigned long long 
 // The slot then holds the rank and F side by side: one 8-byte load gives a
 // later occurrence both.
 template <typename Sym>
-__global__ __launch_bounds__(256) void k_commit_new(uint64_t d, const uint32_t* __restrict__ slot_idx,
+__global__ __launch_bounds__(256) void k_commit_new(uint64_t d, const uint64_t* __restrict__ d_dev,
+                                                    const uint32_t* __restrict__ slot_idx,
                                                     Slot* table, const uint64_t* __restrict__ newbits,
                                                     const uint64_t* __restrict__ wcnt_base,
                                                     const uint64_t* __restrict__ wlen_base,
@@ -1188,6 +1265,7 @@ __global__ __launch_bounds__(256) void k_commit_new(uint64_t d, const uint32_t* 
                                                     Sym* __restrict__ rule_rhs,
                                                     uint32_t* __restrict__ rule_fp) {
   constexpr bool kBytes = sizeof(Sym) == 1;
+  if (d_dev) d = *d_dev;
   const uint64_t W = (d + 63) / 64;
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t wd = blockIdx.x * (uint64_t)(blockDim.x / 64) + (threadIdx.x >> 6);
@@ -1204,144 +1282,86 @@ __global__ __launch_bounds__(256) void k_commit_new(uint64_t d, const uint32_t* 
     const uint32_t r = u_prev + (uint32_t)(wcnt_base[wd] +
                                            __builtin_popcountll(fw & ((1ULL << lane) - 1ULL)));
     const uint64_t q = q_prev + wlen_base[wd] + excl;
+    const uint32_t sidx = slot_idx[o];
     uint32_t F;
     if (kk & kLongTag) {
+      // eight symbols per step, so that their loads are in flight together
       const Sym* src = content + pstart[o];
-      for (uint32_t i = 0; i < L; ++i) rule_rhs[q + i] = src[i];
+      for (uint32_t i = 0; i < L; i += 8) {
+        Sym v[8];
+#pragma unroll
+        for (uint32_t x = 0; x < 8; ++x) v[x] = i + x < L ? src[i + x] : Sym(0);
+#pragma unroll
+        for (uint32_t x = 0; x < 8; ++x)
+          if (i + x < L) rule_rhs[q + i + x] = v[x];
+      }
       F = fnew[o];
     } else {
+      // at most 7 symbols (4 above level 1): gather their F first, then Horner
+      constexpr uint32_t kMaxExact = kBytes ? 7 : 4;
+      uint32_t v[kMaxExact], f[kMaxExact];
+#pragma unroll
+      for (uint32_t x = 0; x < kMaxExact; ++x) {
+        v[x] = x < L ? key_sym<kBytes>(kk, x) : 0u;
+        f[x] = x < L ? fprev[v[x]] : 0u;
+      }
       uint64_t S = 0;
-      for (uint32_t i = L; i-- > 0;) {
-        const uint32_t v = key_sym<kBytes>(kk, i);
-        rule_rhs[q + i] = (Sym)v;
-        S = addmod61(mulmod61(S, h.c), fprev[v]);
+#pragma unroll
+      for (int x = kMaxExact - 1; x >= 0; --x) {
+        if ((uint32_t)x < L) {
+          rule_rhs[q + x] = (Sym)v[x];
+          S = addmod61(mulmod61(S, h.c), f[x]);
+        }
       }
       F = (uint32_t)(addmod61(mulmod61(h.a, S), h.b) & 0xFFFFFFFFULL);
     }
     rule_off[r + 1] = q + L;
     rule_fp[r] = F;
-    Slot* sl = &table[slot_idx[o]];
+    Slot* sl = &table[sidx];
     *reinterpret_cast<uint64_t*>(&sl->minocc) = (uint64_t)F | ((uint64_t)r << 32);
-    const uint64_t w0 = sl->w0;
-    if (w0 & kLongTag) sl->w0 = (w0 & kHiMask) | r;
+    // a long key's slot word switches from the claiming occurrence to the rank
+    if (kk & kLongTag) sl->w0 = (kk & kHiMask) | r;
   }
 }
 
 // T^{i+1}: every phrase takes the (now committed) rank of its slot, and its
 // fingerprint when the next round needs it (fnext).
-__global__ __launch_bounds__(256) void k_rewrite(uint64_t d, const uint32_t* __restrict__ slot_idx,
+__global__ __launch_bounds__(256) void k_rewrite(uint64_t d, const uint64_t* __restrict__ d_dev,
+                                                 const uint32_t* __restrict__ slot_idx,
                                                  const Slot* __restrict__ table,
                                                  uint32_t* __restrict__ sym_next,
                                                  uint32_t* __restrict__ fnext) {
+  if (d_dev) d = *d_dev;
   const uint64_t o = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (o >= d) return;
-  const uint32_t sidx = slot_idx[o];
+  // the phrase arrays stream past (non-temporal), the table lines stay cached
+  const uint32_t sidx = __builtin_nontemporal_load(&slot_idx[o]);
   // kNone only after an overflow (the round is redone)
   const uint64_t fr = sidx == kNone ? 0 : *reinterpret_cast<const uint64_t*>(&table[sidx].minocc);
-  sym_next[o] = (uint32_t)(fr >> 32);
-  if (fnext) fnext[o] = (uint32_t)fr;
+  __builtin_nontemporal_store((uint32_t)(fr >> 32), &sym_next[o]);
+  if (fnext) __builtin_nontemporal_store((uint32_t)fr, &fnext[o]);
 }
 
-// The same with one table read per distinct slot of a chunk of phrases (for
-// the rounds that use the combining insert: there a few slots take most of
-// the phrases).
-__global__ __launch_bounds__(256) void k_rewrite_comb(uint64_t d, const uint32_t* __restrict__ slot_idx,
-                                                      const Slot* __restrict__ table,
-                                                      uint32_t* __restrict__ sym_next,
-                                                      uint32_t* __restrict__ fnext) {
-  __shared__ uint32_t s_sk[kComb];
-  __shared__ unsigned long long s_fr[kComb];
-  __shared__ uint16_t s_loc[kCombChunk];
-  for (uint64_t c0 = blockIdx.x * (uint64_t)kCombChunk; c0 < d; c0 += (uint64_t)gridDim.x * kCombChunk) {
-    for (int i = threadIdx.x; i < kComb; i += blockDim.x) s_sk[i] = kNone;
-    uint32_t sc[kCombItems];
-#pragma unroll
-    for (int x = 0; x < kCombItems; ++x) {
-      const uint64_t o = c0 + x * 256 + threadIdx.x;
-      sc[x] = o < d ? slot_idx[o] : kNone;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int x = 0; x < kCombItems; ++x) {
-      const uint32_t li = x * 256 + threadIdx.x;
-      uint32_t found = kNone;
-      {
-        const uint32_t sidx = sc[x];
-        if (sidx != kNone) {
-          uint32_t lpos = (sidx * 0x9E3779B1u) >> (32 - kCombLog2);
-          for (int t = 0; t < kCombProbe && found == kNone; ++t) {
-            const uint32_t w = s_sk[lpos];
-            bool hit;
-            if (w == kNone) {
-              const uint32_t prev = atomicCAS(&s_sk[lpos], kNone, sidx);
-              hit = prev == kNone || prev == sidx;
-            } else {
-              hit = w == sidx;
-            }
-            if (hit) found = lpos;
-            else lpos = (lpos + 1) & (kComb - 1);
-          }
-        }
-      }
-      s_loc[li] = found == kNone ? kCombNone : (uint16_t)found;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kComb / 256; ++j) {
-      const uint32_t sidx = s_sk[j * 256 + threadIdx.x];
-      s_fr[j * 256 + threadIdx.x] =
-          sidx == kNone ? 0 : *reinterpret_cast<const uint64_t*>(&table[sidx].minocc);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int x = 0; x < kCombItems; ++x) {
-      const uint32_t li = x * 256 + threadIdx.x;
-      const uint64_t o = c0 + li;
-      if (o < d) {
-        const uint16_t lr = s_loc[li];
-        uint64_t fr;
-        if (lr != kCombNone) {
-          fr = s_fr[lr];
-        } else {
-          const uint32_t sidx = sc[x];
-          fr = sidx == kNone ? 0 : *reinterpret_cast<const uint64_t*>(&table[sidx].minocc);
-        }
-        sym_next[o] = (uint32_t)(fr >> 32);
-        if (fnext) fnext[o] = (uint32_t)fr;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-void launch_commit(bool bytes, uint64_t d, const uint32_t* slot_idx, Slot* table,
+void launch_commit(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t* slot_idx, Slot* table,
                    const uint64_t* newbits, const uint64_t* wcnt_base, const uint64_t* wlen_base,
                    const uint64_t* key, const uint64_t* pstart, const uint32_t* plen,
                    const void* content, const uint32_t* fnew, const uint32_t* fprev, LevelHash h,
                    uint32_t u_prev, uint64_t q_prev, uint64_t* rule_off, void* rule_rhs,
-                   uint32_t* rule_fp, uint32_t* sym_next, uint32_t* fnext, bool combine,
-                   hipStream_t s) {
+                   uint32_t* rule_fp, uint32_t* sym_next, uint32_t* fnext, hipStream_t s) {
   if (!d) return;
   const unsigned g = grid_for((d + 63) / 64, 4);  // one wave per flag word
   if (bytes)
     k_commit_new<uint8_t><<<g, 256, 0, s>>>(
-        d, slot_idx, table, newbits, wcnt_base, wlen_base, key, pstart, plen,
+        d, d_dev, slot_idx, table, newbits, wcnt_base, wlen_base, key, pstart, plen,
         static_cast<const uint8_t*>(content), fnew, fprev, h, u_prev, q_prev, rule_off,
         static_cast<uint8_t*>(rule_rhs), rule_fp);
   else
     k_commit_new<uint32_t><<<g, 256, 0, s>>>(
-        d, slot_idx, table, newbits, wcnt_base, wlen_base, key, pstart, plen,
+        d, d_dev, slot_idx, table, newbits, wcnt_base, wlen_base, key, pstart, plen,
         static_cast<const uint32_t*>(content), fnew, fprev, h, u_prev, q_prev, rule_off,
         static_cast<uint32_t*>(rule_rhs), rule_fp);
   LCG_LAUNCH_CHECK("commit_new");
-  if (combine) {
-    unsigned g = grid_for(d, kCombChunk);
-    const unsigned r = resident_blocks((const void*)k_rewrite_comb, 256);
-    if (g > r) g = r;
-    k_rewrite_comb<<<g, 256, 0, s>>>(d, slot_idx, table, sym_next, fnext);
-  } else {
-    k_rewrite<<<grid_for(d, 256), 256, 0, s>>>(d, slot_idx, table, sym_next, fnext);
-  }
+  k_rewrite<<<grid_for(d, 256), 256, 0, s>>>(d, d_dev, slot_idx, table, sym_next, fnext);
   LCG_LAUNCH_CHECK("rewrite");
 }
 
@@ -1401,11 +1421,12 @@ void launch_c_init(const uint8_t* text, const uint64_t* off, uint32_t k, uint8_t
 // before its first position (tile prefix + popcount inside the tile).
 __global__ void k_segments(const uint64_t* __restrict__ off, uint32_t k,
                            const uint64_t* __restrict__ bits, const uint64_t* __restrict__ tile_base,
-                           uint64_t d, uint64_t* __restrict__ new_off) {
+                           uint64_t d, const uint64_t* __restrict__ d_dev,
+                           uint64_t* __restrict__ new_off) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j > k) return;
   if (j == k) {
-    new_off[k] = d;
+    new_off[k] = d_dev ? *d_dev : d;
     return;
   }
   const uint64_t x = off[j];
@@ -1417,8 +1438,10 @@ __global__ void k_segments(const uint64_t* __restrict__ off, uint32_t k,
 }
 
 void launch_segments(const uint64_t* off, uint32_t k, const uint64_t* bits,
-                     const uint64_t* tile_base, uint64_t d, uint64_t* new_off, hipStream_t s) {
-  k_segments<<<grid_for((uint64_t)k + 1, 256), 256, 0, s>>>(off, k, bits, tile_base, d, new_off);
+                     const uint64_t* tile_base, uint64_t d, const uint64_t* d_dev,
+                     uint64_t* new_off, hipStream_t s) {
+  k_segments<<<grid_for((uint64_t)k + 1, 256), 256, 0, s>>>(off, k, bits, tile_base, d, d_dev,
+                                                             new_off);
   LCG_LAUNCH_CHECK("segments");
 }
 

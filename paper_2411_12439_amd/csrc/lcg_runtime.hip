@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <stdexcept>
 #include <string>
@@ -245,6 +246,7 @@ struct Opts {
   uint64_t budget = 0;
   uint32_t key_bits = 0;
   uint32_t table_min_log2 = 12;
+  uint32_t tail_log2 = 22;
 };
 
 static Opts read_opts(const lcg_opts* o) {
@@ -256,6 +258,9 @@ static Opts read_opts(const lcg_opts* o) {
   r.budget = o->hbm_budget;
   r.key_bits = o->key_bits;
   if (o->table_min_log2) r.table_min_log2 = o->table_min_log2;
+  if (o->tail_log2) r.tail_log2 = o->tail_log2;
+  if (r.tail_log2 > 40) throw LcgError{LCG_EINVAL, "tail_log2 out of range"};
+  if (o->reserved) throw LcgError{LCG_EINVAL, "reserved option field must be zero"};
   if (r.mode != LCG_MODE_BATCHED && r.mode != LCG_MODE_PLAIN)
     throw LcgError{LCG_EINVAL, "unknown mode"};
   if (r.key_bits > 30) throw LcgError{LCG_EINVAL, "key_bits must be 0..30"};
@@ -309,6 +314,16 @@ static uint64_t build_bytes(uint64_t n, uint32_t k) {
   return 21 * n + 48ull * k + (64ull << 20);
 }
 
+// What the device records of one round run without host reads (tail mode).
+struct TailRec {
+  uint64_t d;    // phrases (the length of the next round's sequence)
+  uint64_t u;    // new rules
+  uint64_t q;    // new right-hand-side symbols
+  uint64_t pad;
+  Counters ctr;  // dictionary counters
+  Counters fin;  // strings still longer than one symbol after the round
+};
+
 // Reusable per-call scratch.
 struct Work {
   DBuf<uint64_t> bits, tile_cnt, tile_base, scan_tmp;
@@ -322,6 +337,7 @@ struct Work {
   DBuf<uint8_t> content8, hll_part;
   DBuf<uint2> tile_seg;
   DBuf<uint32_t> content32, remap[2], rest;
+  DBuf<struct TailRec> tail;
   void release_after(hipStream_t s) {
     DBuf<uint64_t>* b64[] = {&bits, &tile_cnt, &tile_base, &scan_tmp, &pstart, &key, &off[0],
                              &off[1], &newbits, &wcnt, &wlen, &wcnt_base, &wlen_base};
@@ -331,6 +347,7 @@ struct Work {
     for (auto* b : b32) b->reset_after(s);
     ctr.reset_after(s);
     fin.reset_after(s);
+    tail.reset_after(s);
     content8.reset_after(s);
     hll_part.reset_after(s);
     tile_seg.reset_after(s);
@@ -346,6 +363,7 @@ struct Mailbox {
   Counters ctr;
   Counters fin;
   uint64_t d, u_new, q_new;
+  uint32_t polled[HashFamily::kLevels];  // active counts of the tail rounds
 };
 
 static Mailbox* mailbox() {
@@ -469,7 +487,7 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
     zero_counters(w.ctr.p, s);
     const void* rule_rhs = bytes ? (const void*)L.rhs8.p : (const void*)L.rhs32.p;
     if (pe) pe->rec(3, s);
-    launch_insert(bytes, d, w.key.p, w.pstart.p, w.plen.p, content, L.off.p, rule_rhs, L.u,
+    launch_insert(bytes, d, nullptr, w.key.p, w.pstart.p, w.plen.p, content, L.off.p, rule_rhs, L.u,
                   L.table.p, L.tcap - 1, w.slot_idx.p, combine, w.rest.p, &w.ctr.p->rest_len,
                   w.ctr.p, s);
     if (pe) pe->rec(4, s);
@@ -480,7 +498,7 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
       launch_newflags_table(bytes, L.table.p, L.tcap, d, w.key.p, w.plen.p, w.newbits.p, w.wcnt.p,
                             w.wlen.p, s);
     else
-      launch_newflags(bytes, d, w.slot_idx.p, L.table.p, w.key.p, w.plen.p, w.newbits.p, w.wcnt.p,
+      launch_newflags(bytes, d, nullptr, w.slot_idx.p, L.table.p, w.key.p, w.plen.p, w.newbits.p, w.wcnt.p,
                       w.wlen.p, s);
     scan_exclusive(w.wcnt.p, w.wcnt_base.p, W, w.scan_tmp.p, s);
     scan_exclusive(w.wlen.p, w.wlen_base.p, W, w.scan_tmp.p, s);
@@ -513,13 +531,180 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
   }
   // F of the level-(lv-1) symbols: h^0 of the bytes, else the previous level's rules
   const uint32_t* fprev = bytes ? w.lut.p : g->levels[lv - 2].fp.p;
-  launch_commit(bytes, d, w.slot_idx.p, L.table.p, w.newbits.p, w.wcnt_base.p, w.wlen_base.p,
+  launch_commit(bytes, d, nullptr, w.slot_idx.p, L.table.p, w.newbits.p, w.wcnt_base.p, w.wlen_base.p,
                 w.key.p, w.pstart.p, w.plen.p, content, fnew, fprev, g->H.lv[lv], L.u, L.q,
-                L.off.p, rule_rhs, L.fp.p, sym_next, fnext, combine, s);
+                L.off.p, rule_rhs, L.fp.p, sym_next, fnext, s);
   if (pe) pe->rec(6, s);
   L.u += (uint32_t)u_new;
   L.q += q_new;
   return DedupResult{(uint32_t)u_new, q_new, hc.probes, hc.compares, combine};
+}
+
+// Tail mode.  Once the sequence is short (n_i <= 2^tail_log2) the rounds are
+// launch-bound, not memory-bound, and the two host reads per round would
+// dominate.  From there on every round is queued without reading anything
+// back: each kernel reads its size (n_i, d_i) from device memory and is
+// launched over the worst case (d_i <= n_i/2 + k, Theorem 1's halving), the
+// level's dictionary and rule arrays are sized for that worst case before
+// the round is queued, and the round's counts land in a device record.  The
+// host only waits, kTailLag rounds behind the queue, for a round's count of
+// strings still active, to stop queueing once it is zero; the rounds queued
+// after the last one find no phrase and change nothing.
+constexpr uint32_t kTailLag = 2;
+
+static hipEvent_t tail_event(uint32_t i) {
+  static thread_local std::vector<hipEvent_t> ev;
+  while (ev.size() <= i) {
+    hipEvent_t e;
+    HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ev.push_back(e);
+  }
+  return ev[i];
+}
+
+static void tail_rounds(lcg_grammar* g, uint32_t lv, uint64_t n_i, uint64_t active_len,
+                        const uint8_t* d_text, const uint64_t* cur_off, int cur, uint32_t k,
+                        uint32_t c_base, const Opts& o, Work& w, hipStream_t s) {
+  const uint32_t lv0 = lv;
+  const size_t levels_before = g->levels.size();
+  const uint32_t max_rounds = (uint32_t)HashFamily::kLevels - lv0;
+  w.tail.need(max_rounds, s);
+  launch_zero(w.tail.p, sizeof(TailRec) * max_rounds, s);
+  const bool timing = (o.flags & LCG_FLAG_TIMING) != 0;
+  std::vector<std::unique_ptr<PhaseEvents>> pev;
+  Mailbox* mb = mailbox();
+  uint64_t nb = n_i;                  // bound of the round's sequence length
+  const uint64_t* n_dev = nullptr;    // its exact value on the device (none for the first)
+  uint32_t r = 0;
+  bool done = false;
+  for (; r < max_rounds && !done; ++r, ++lv) {
+    const bool bytes = lv == 1;
+    TailRec* rec = w.tail.p + r;
+    RoundIn in;
+    in.sym = bytes ? (const void*)d_text : (const void*)w.sym[cur ^ 1].p;
+    in.fp = bytes ? nullptr : w.fpv[cur ^ 1].p;
+    in.lut = w.lut.p;
+    in.off = cur_off;
+    in.k = k;
+    in.n = nb;
+    in.n_dev = n_dev;
+    in.bytes = bytes;
+    const uint64_t tiles = (nb + kTile - 1) / kTile;
+    const uint64_t d_b = nb / 2 + k + 1;
+    const uint64_t W_b = (d_b + 63) / 64;
+    w.bits.need(tiles * kTileWords, s);
+    w.tile_cnt.need(tiles, s);
+    w.tile_base.need(tiles + 1, s);
+    w.tile_seg.need(tiles, s);
+    w.pstart.need(d_b, s);
+    w.plen.need(d_b, s);
+    w.key.need(d_b, s);
+    w.slot_idx.need(d_b, s);
+    w.sym[cur].need(d_b, s);
+    w.fpv[cur].need(d_b, s);
+    w.off[cur].need(k + 1, s);
+    w.newbits.need(W_b, s);
+    w.wcnt.need(W_b, s);
+    w.wlen.need(W_b, s);
+    w.wcnt_base.need(W_b + 1, s);
+    w.wlen_base.need(W_b + 1, s);
+    ensure_level(g, lv, s);
+    Level& L = g->levels[lv - 1];
+    ensure_table(L, (uint64_t)L.u + d_b, o.table_min_log2, w, s);
+    if ((uint64_t)L.u + d_b >= kNone) throw LcgError{LCG_EOVERFLOW, "level needs 2^32 ranks"};
+    L.off.grow(L.u + d_b + 1, L.u + 1, s);
+    L.fp.grow(L.u + d_b, L.u, s);
+    void* rule_rhs;
+    if (bytes) {
+      L.rhs8.grow(L.q + nb, L.q, s);
+      rule_rhs = L.rhs8.p;
+    } else {
+      L.rhs32.grow(L.q + nb, L.q, s);
+      rule_rhs = L.rhs32.p;
+    }
+    PhaseEvents* pe = nullptr;
+    if (timing) {
+      pev.emplace_back(new PhaseEvents(true));
+      pe = pev.back().get();
+    }
+    const void* content = in.sym;
+    if (pe) pe->rec(0, s);
+    launch_classify(in, w.bits.p, w.tile_cnt.p, w.tile_seg.p, s);
+    scan_one(w.tile_cnt.p, w.tile_base.p, tiles, n_dev, 12, &rec->d, s);  // kTile = 2^12
+    if (pe) pe->rec(1, s);
+    if (pe) pe->rec(2, s);
+    launch_emit(in, w.bits.p, w.tile_base.p, w.tile_seg.p, g->H.lv[lv], o.key_bits, w.pstart.p,
+                w.plen.p, w.key.p, w.fpv[cur].p, w.hll_part.p, nullptr, s);
+    if (pe) pe->rec(8, s);
+    if (pe) pe->rec(3, s);
+    launch_insert(bytes, d_b, &rec->d, w.key.p, w.pstart.p, w.plen.p, content, L.off.p, rule_rhs,
+                  L.u, L.table.p, L.tcap - 1, w.slot_idx.p, false, nullptr, nullptr, &rec->ctr, s);
+    if (pe) pe->rec(4, s);
+    launch_newflags(bytes, d_b, &rec->d, w.slot_idx.p, L.table.p, w.key.p, w.plen.p, w.newbits.p,
+                    w.wcnt.p, w.wlen.p, s);
+    scan_one(w.wcnt.p, w.wcnt_base.p, W_b, &rec->d, 6, &rec->u, s);
+    scan_one(w.wlen.p, w.wlen_base.p, W_b, &rec->d, 6, &rec->q, s);
+    if (pe) pe->rec(5, s);
+    const uint32_t* fprev = bytes ? w.lut.p : g->levels[lv - 2].fp.p;
+    launch_commit(bytes, d_b, &rec->d, w.slot_idx.p, L.table.p, w.newbits.p, w.wcnt_base.p,
+                  w.wlen_base.p, w.key.p, w.pstart.p, w.plen.p, content, w.fpv[cur].p, fprev,
+                  g->H.lv[lv], L.u, L.q, L.off.p, rule_rhs, L.fp.p, w.sym[cur].p, w.fpv[cur].p, s);
+    if (pe) pe->rec(6, s);
+    launch_segments(cur_off, k, w.bits.p, w.tile_base.p, d_b, &rec->d, w.off[cur].p, s);
+    launch_finish(cur_off, w.off[cur].p, k, w.sym[cur].p, lv, g->c_level.p + c_base,
+                  g->c_sym.p + c_base, &rec->fin, s);
+    if (pe) pe->rec(7, s);
+    HIP_CHECK(hipMemcpyAsync(&mb->polled[r], &rec->fin.active, sizeof(uint32_t),
+                             hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipEventRecord(tail_event(r), s));
+    if (r >= kTailLag) {
+      HIP_CHECK(hipEventSynchronize(tail_event(r - kTailLag)));
+      done = mb->polled[r - kTailLag] == 0;
+    }
+    n_dev = &rec->d;
+    nb = d_b;
+    cur_off = w.off[cur].p;
+    cur ^= 1;
+  }
+  std::vector<TailRec> rec(r);
+  HIP_CHECK(hipMemcpyAsync(rec.data(), w.tail.p, sizeof(TailRec) * r, hipMemcpyDeviceToHost, s));
+  sync(s);
+  uint32_t j = 0;
+  for (; j < r && rec[j].d; ++j) {
+    const TailRec& t = rec[j];
+    if (t.ctr.overflow) throw LcgError{LCG_ETABLE, "dictionary overflow in a tail round"};
+    Level& L = g->levels[lv0 - 1 + j];
+    if ((uint64_t)L.u + t.u >= kNone) throw LcgError{LCG_EOVERFLOW, "level needs 2^32 ranks"};
+    L.u += (uint32_t)t.u;
+    L.q += t.q;
+    Stat row{};
+    row[0] = j ? rec[j - 1].fin.active_len : active_len;
+    row[1] = t.d;
+    row[2] = t.u;
+    row[3] = t.q;
+    row[4] = t.fin.active;
+    row[5] = t.ctr.probes;
+    row[6] = t.ctr.compares;
+    row[7] = L.tcap;
+    if (timing) {
+      PhaseEvents& pe = *pev[j];
+      row[9] = pe.ns(0, 1);
+      row[10] = pe.ns(2, 8);
+      row[11] = pe.ns(3, 4);
+      row[12] = pe.ns(4, 5);
+      row[13] = pe.ns(5, 6);
+      row[14] = pe.ns(6, 7);
+      row[8] = row[9] + row[10] + row[11] + row[12] + row[13] + row[14];
+    }
+    row[15] = 2;  // queued without host reads
+    g->stats.push_back(row);
+  }
+  if (j == r && r == max_rounds && rec[r - 1].fin.active)
+    throw LcgError{LCG_EOVERFLOW, "more than 63 rounds"};
+  // levels opened for the rounds queued after the last one stay empty
+  while (g->levels.size() > levels_before && g->levels.size() > lv0 - 1 + j &&
+         g->levels.back().u == 0)
+    g->levels.pop_back();
 }
 
 // BuildGram of k strings into g (fresh or existing): the batched form.
@@ -571,6 +756,23 @@ static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_
       if (hf.active) throw LcgError{LCG_EOVERFLOW, "more than 63 rounds"};
       break;
     }
+    if (n_i <= (1ull << o.tail_log2)) {
+      // the rest of the rounds run in tail mode; first the previous round's row
+      if (pending) {
+        HIP_CHECK(hipMemcpyAsync(&hf, w.fin.p, offsetof(Counters, hll), hipMemcpyDeviceToHost, s));
+        sync(s);
+        prev[4] = hf.active;
+        prev[13] = pe.ns(5, 6);
+        prev[14] = pe.ns(6, 7);
+        prev[8] += prev[13] + prev[14];
+        g->stats.push_back(prev);
+        active = hf.active;
+        active_len = hf.active_len;
+        if (!active) break;
+      }
+      tail_rounds(g, lv, n_i, active_len, d_text, cur_off, cur, k, c_base, o, w, s);
+      break;
+    }
     const bool bytes = lv == 1;
     RoundIn in;
     in.sym = bytes ? (const void*)d_text : (const void*)w.sym[cur ^ 1].p;
@@ -579,6 +781,7 @@ static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_
     in.off = cur_off;
     in.k = k;
     in.n = n_i;
+    in.n_dev = nullptr;
     in.bytes = bytes;
     const uint64_t tiles = (n_i + kTile - 1) / kTile;
     const uint64_t d_cap = n_i / 2 + k + 1;  // phrases have length >= 2 but the first
@@ -635,7 +838,7 @@ static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_
     DedupResult r = dedup_commit(g, lv, d, content, w.fpv[cur].p, w.sym[cur].p, w.fpv[cur].p, est,
                                  o, w, s, &pe);
     zero_counters(w.fin.p, s);
-    launch_segments(cur_off, k, w.bits.p, w.tile_base.p, d, w.off[cur].p, s);
+    launch_segments(cur_off, k, w.bits.p, w.tile_base.p, d, nullptr, w.off[cur].p, s);
     launch_finish(cur_off, w.off[cur].p, k, w.sym[cur].p, lv, g->c_level.p + c_base,
                   g->c_sym.p + c_base, w.fin.p, s);
     pe.rec(7, s);

@@ -40,7 +40,8 @@ class LcgError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("mode", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("hbm_budget", ctypes.c_uint64), ("key_bits", ctypes.c_uint32),
-                ("table_min_log2", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
+                ("table_min_log2", ctypes.c_uint32), ("tail_log2", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 _lib = None
@@ -121,7 +122,8 @@ def _check_inputs(text, offsets):
         raise ValueError("need at least one string")
 
 
-def make_opts(seed=0, mode=MODE_BATCHED, flags=0, hbm_budget=0, key_bits=0, table_min_log2=0):
+def make_opts(seed=0, mode=MODE_BATCHED, flags=0, hbm_budget=0, key_bits=0, table_min_log2=0,
+              tail_log2=0):
     o = Opts()
     lib().lcg_opts_init(ctypes.byref(o))
     o.seed = seed
@@ -130,6 +132,7 @@ def make_opts(seed=0, mode=MODE_BATCHED, flags=0, hbm_budget=0, key_bits=0, tabl
     o.hbm_budget = hbm_budget
     o.key_bits = key_bits
     o.table_min_log2 = table_min_log2
+    o.tail_log2 = tail_log2
     return o
 
 
@@ -215,10 +218,10 @@ def new(seed):
 
 
 def build(text, offsets, seed=0, mode=MODE_BATCHED, flags=0, hbm_budget=0, key_bits=0,
-          table_min_log2=0, stream=None):
+          table_min_log2=0, tail_log2=0, stream=None):
     """BuildGram over the strings text[offsets[j]:offsets[j+1]] (device tensors)."""
     _check_inputs(text, offsets)
-    o = make_opts(seed, mode, flags, hbm_budget, key_bits, table_min_log2)
+    o = make_opts(seed, mode, flags, hbm_budget, key_bits, table_min_log2, tail_log2)
     h = ctypes.c_void_p()
     _check(lib().lcg_build(ctypes.c_void_p(text.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
                            offsets.numel() - 1, ctypes.byref(o), _stream(stream), ctypes.byref(h)))
@@ -226,12 +229,12 @@ def build(text, offsets, seed=0, mode=MODE_BATCHED, flags=0, hbm_budget=0, key_b
 
 
 def build_into(g, text, offsets, seed=None, flags=0, hbm_budget=0, key_bits=0, table_min_log2=0,
-               stream=None):
+               tail_log2=0, stream=None):
     """Compress a batch into an existing grammar; returns the C index of its first string."""
     _check_inputs(text, offsets)
     if seed is None:
         seed = g.info()[0]
-    o = make_opts(seed, MODE_BATCHED, flags, hbm_budget, key_bits, table_min_log2)
+    o = make_opts(seed, MODE_BATCHED, flags, hbm_budget, key_bits, table_min_log2, tail_log2)
     first = ctypes.c_uint32()
     _check(lib().lcg_build_into(g.h, ctypes.c_void_p(text.data_ptr()),
                                 ctypes.c_void_p(offsets.data_ptr()), offsets.numel() - 1,

@@ -47,12 +47,27 @@ def _oracle(text, off, seed=SEED):
     return O.build(text, off, seed)
 
 
+# Round paths: tail_log2=0 (default 2^22) queues every round of these small
+# inputs without host reads (tail mode); tail_log2=1 reads sizes back every
+# round (the path of large rounds).
+PATHS = pytest.mark.parametrize("tail", [0, 1], ids=["tail", "synced"])
+
+
 # ---------------------------------------------------------------- tiny config
+@PATHS
 @pytest.mark.parametrize("mode", [0, 1], ids=["batched", "plain"])
-def test_tiny_config_equals_oracle(L, mode):
+def test_tiny_config_equals_oracle(L, mode, tail):
     text, off = D.make_config("tiny")
-    g = _gpu(L, text, off, mode=mode)
+    g = _gpu(L, text, off, mode=mode, tail_log2=tail)
     _assert_same(g.export(), _oracle(text, off).export())
+
+
+def test_tail_and_synced_rounds_agree(L):
+    """The same grammar, rank for rank, whichever rounds run in tail mode."""
+    text, off = D.make_config("tiny", scale=2.0)
+    ref = _gpu(L, text, off, tail_log2=1).export()
+    for tail in (8, 14, 18, 30):
+        _assert_same(_gpu(L, text, off, tail_log2=tail).export(), ref)
 
 
 def test_tiny_config_round_statistics(L):
@@ -98,11 +113,12 @@ EDGE = {
 }
 
 
+@PATHS
 @pytest.mark.parametrize("case", sorted(EDGE))
 @pytest.mark.parametrize("mode", [0, 1], ids=["batched", "plain"])
-def test_edge_cases(L, case, mode):
+def test_edge_cases(L, case, mode, tail):
     text, off = _pack(EDGE[case])
-    g = _gpu(L, text, off, mode=mode)
+    g = _gpu(L, text, off, mode=mode, tail_log2=tail)
     _assert_same(g.export(), _oracle(text, off).export())
 
 
@@ -112,11 +128,12 @@ def test_exhaustive_short_dna(L):
     _assert_same(_gpu(L, text, off).export(), _oracle(text, off).export())
 
 
+@PATHS
 @pytest.mark.parametrize("key_bits", [3, 12])
-def test_truncated_keys_rely_on_full_comparison(L, key_bits):
+def test_truncated_keys_rely_on_full_comparison(L, key_bits, tail):
     """Keys cut to a few bits collide constantly; exact comparison must still dedup correctly."""
     text, off = D.make_config("tiny", scale=0.05)
-    g = _gpu(L, text, off, key_bits=key_bits)
+    g = _gpu(L, text, off, key_bits=key_bits, tail_log2=tail)
     _assert_same(g.export(), _oracle(text, off).export())
     assert g.stats()[:, 6].sum() > 0  # full comparisons happened
 
@@ -128,24 +145,26 @@ def test_small_tables_regrow(L):
 
 
 # ---------------------------------------------------------------- merge / build_into
+@PATHS
 @pytest.mark.parametrize("cut", [1, 3, 7])
-def test_merge_equals_build_of_concatenation(L, cut):
+def test_merge_equals_build_of_concatenation(L, cut, tail):
     text, off = D.make_config("tiny", scale=0.1)
     ta, oa = text[:off[cut]], off[:cut + 1]
     tb, ob = text[off[cut]:], off[cut:] - off[cut]
-    ga = _gpu(L, ta, oa)
-    gb = _gpu(L, tb, ob)
+    ga = _gpu(L, ta, oa, tail_log2=tail)
+    gb = _gpu(L, tb, ob, tail_log2=tail)
     ga.merge(gb)
     _assert_same(ga.export(), _oracle(text, off).export())
     _assert_same(gb.export(), _oracle(tb, ob).export())  # b unchanged
 
 
-def test_build_into_equals_oracle(L):
+@PATHS
+def test_build_into_equals_oracle(L, tail):
     text, off = D.make_config("tiny", scale=0.1)
     g = L.new(SEED)
     for lo, hi in ((0, 2), (2, 3), (3, 8)):
         t, o = L.to_device(text[off[lo]:off[hi]], off[lo:hi + 1] - off[lo])
-        first = L.build_into(g, t, o)
+        first = L.build_into(g, t, o, tail_log2=tail)
         assert first == lo
     _assert_same(g.export(), _oracle(text, off).export())
 
@@ -170,11 +189,12 @@ def test_errors(L):
 
 def test_combining_round_equals_oracle(L):
     """4 MB of the tiny recipe: round 1 has ~10^6 phrases over a few thousand keys,
-    so it runs the combining insert and rewrite; exact equality with the oracle."""
+    so (run with host reads) it combines equal keys per chunk; exact equality with
+    the oracle."""
     text, off = D.make_config("tiny", scale=4.0)
-    g = _gpu(L, text, off)
+    g = _gpu(L, text, off, tail_log2=21)
     st = g.stats()
-    assert st[0, 2] * 32 <= st[0, 1], "round 1 should have few distinct keys"
+    assert st[0, 15] == 1, "round 1 should combine equal keys"
     _assert_same(g.export(), _oracle(text, off).export())
 
 
