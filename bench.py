@@ -255,6 +255,27 @@ def main():
            "timed_wall_s": round(wall, 3),
            "roofline": roofline}
 
+    # decompression of the whole collection (the inverse path): all strings
+    # expanded together, top-down over the levels
+    g = lcg.build(t, o, seed=seed)
+    out_t, offs_t = g.expand_strings()
+    torch.cuda.synchronize()
+    if not torch.equal(out_t, t):
+        raise SystemExit("expand_strings does not give back the input")
+    xs = []
+    for i in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.expand_strings()
+        torch.cuda.synchronize()
+        xs.append(time.perf_counter() - t0)
+    g.free()
+    del out_t, offs_t
+    out["expand"] = {"what": "lcg_expand_strings of all strings (decompression), output bytes/s",
+                     "gbps": round(n / float(np.mean(xs)) / 1e9, 3),
+                     "ms": round(float(np.mean(xs)) * 1e3, 3)}
+    print("[bench] expand all strings: %.2f ms" % (np.mean(xs) * 1e3), file=sys.stderr, flush=True)
+
     if not args.no_plain:
         g = lcg.build(t, o, seed=seed, mode=lcg.MODE_PLAIN)
         g.free()

@@ -132,6 +132,17 @@ lcg_status lcg_merge(lcg_grammar_t a, lcg_grammar_t b, hipStream_t stream);
 lcg_status lcg_expand(lcg_grammar_t g, uint32_t j, uint8_t* d_out, uint64_t cap,
                       uint64_t* out_len, hipStream_t stream);
 
+/* Expansion of strings j0..j1-1 (j0 <= j1 <= k) one after the other into
+ * d_out (device, cap bytes), top-down over the levels for all of them at once
+ * (the inverse of lcg_build over that range).  d_offsets (device, j1-j0+1
+ * uint64, may be NULL) receives the strings' offsets in d_out; *total (host,
+ * may be NULL) the total length.  If the total exceeds cap, nothing is
+ * written to d_out, *total is set and LCG_EINVAL is returned (call with
+ * cap = 0 to learn the size).  The stream is synchronised before returning. */
+lcg_status lcg_expand_strings(lcg_grammar_t g, uint32_t j0, uint32_t j1, uint8_t* d_out,
+                              uint64_t cap, uint64_t* d_offsets, uint64_t* total,
+                              hipStream_t stream);
+
 /* An empty grammar with hash family `seed` (no levels, no strings). */
 lcg_status lcg_new(uint64_t seed, lcg_grammar_t* out);
 

@@ -111,4 +111,27 @@ void launch_expand_lens(const uint32_t* cur, uint64_t m, const uint64_t* rule_of
 void launch_expand_emit(bool bytes, const uint32_t* cur, uint64_t m, const uint64_t* rule_off,
                         const void* rule_rhs, const uint64_t* pos, void* next, hipStream_t s);
 
+// Expansion of a range of ks strings at once, top-down by byte positions.
+// E (per level, bytes of every rule's expansion): launch_explen, level 1 with
+// e_below = NULL, level L > 1 over rhs ranks of level L-1 with e_below = E of
+// level L-1.  e_levels is a device array of the per-level E pointers.
+void launch_explen(const uint64_t* rule_off, const uint32_t* rhs, const uint64_t* e_below,
+                   uint32_t u, uint64_t* e, hipStream_t s);
+void launch_xs_strlen(const uint8_t* c_level, const uint32_t* c_sym, uint32_t ks,
+                      const uint64_t* const* e_levels, uint64_t* len, hipStream_t s);
+// Strings whose C entry is at `level` join the items (sym, pos; count is the
+// device item counter) or, at level 0, write their byte into out.
+void launch_xs_enter(const uint8_t* c_level, const uint32_t* c_sym, uint32_t ks, uint32_t level,
+                     const uint64_t* str_off, uint32_t* sym, uint64_t* pos, uint64_t* count,
+                     uint8_t* out, hipStream_t s);
+// *total += children of the m items (must be zeroed by the caller)
+void launch_xs_count(const uint32_t* sym, uint64_t m, const uint64_t* rule_off, uint64_t* total,
+                     hipStream_t s);
+// Items -> children (or bytes); *gcount += grandchildren (the children's
+// right-hand-side lengths under rule_off_below, when given).
+void launch_xs_expand(bool to_bytes, const uint32_t* sym, const uint64_t* pos, uint64_t m,
+                      const uint64_t* rule_off, const void* rule_rhs, const uint64_t* e_below,
+                      const uint64_t* rule_off_below, uint32_t* nsym, uint64_t* npos,
+                      uint64_t* ncount, uint64_t* gcount, uint8_t* out, hipStream_t s);
+
 }  // namespace lcg

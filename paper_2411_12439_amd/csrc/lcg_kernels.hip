@@ -1576,4 +1576,193 @@ void launch_expand_emit(bool bytes, const uint32_t* cur, uint64_t m, const uint6
   LCG_LAUNCH_CHECK("expand_emit");
 }
 
+// ------------------------------------------------------------------ expand many strings
+// Expansion of a range of strings at once, top-down, by byte positions.
+// Every rule's expansion length in bytes (E, per level, bottom-up) lets each
+// symbol carry the byte position of its expansion; a level's symbols become
+// their right-hand sides (symbol, position) in any order, so no scan is
+// needed, and the level-1 symbols write their bytes at their positions.
+
+// E of the level's rules: E_1[r] = |rhs(r)|, E_L[r] = sum of E_{L-1} over rhs(r)
+__global__ void k_explen(const uint64_t* __restrict__ rule_off, const uint32_t* __restrict__ rhs,
+                         const uint64_t* __restrict__ e_below, uint32_t u,
+                         uint64_t* __restrict__ e) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= u) return;
+  const uint64_t p0 = rule_off[r], p1 = rule_off[r + 1];
+  if (!e_below) {
+    e[r] = p1 - p0;
+    return;
+  }
+  uint64_t sum = 0;
+  for (uint64_t t = p0; t < p1; ++t) sum += e_below[rhs[t]];
+  e[r] = sum;
+}
+
+void launch_explen(const uint64_t* rule_off, const uint32_t* rhs, const uint64_t* e_below,
+                   uint32_t u, uint64_t* e, hipStream_t s) {
+  if (!u) return;
+  k_explen<<<grid_for(u, 256), 256, 0, s>>>(rule_off, rhs, e_below, u, e);
+  LCG_LAUNCH_CHECK("explen");
+}
+
+// byte length of each string of the range (from its C entry)
+__global__ void k_xs_strlen(const uint8_t* __restrict__ c_level, const uint32_t* __restrict__ c_sym,
+                            uint32_t ks, const uint64_t* const* __restrict__ e_levels,
+                            uint64_t* __restrict__ len) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ks) return;
+  const uint32_t lv = c_level[s];
+  len[s] = lv == 0 ? 1 : e_levels[lv - 1][c_sym[s]];
+}
+
+// strings whose C entry is at `level` join the level's items (level >= 1),
+// or write their byte (level 0)
+__global__ void k_xs_enter(const uint8_t* __restrict__ c_level, const uint32_t* __restrict__ c_sym,
+                           uint32_t ks, uint32_t level, const uint64_t* __restrict__ str_off,
+                           uint32_t* __restrict__ sym, uint64_t* __restrict__ pos,
+                           unsigned long long* __restrict__ count, uint8_t* __restrict__ out) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ks || c_level[s] != level) return;
+  if (level == 0) {
+    out[str_off[s]] = (uint8_t)c_sym[s];
+    return;
+  }
+  const unsigned long long at = atomicAdd(count, 1ULL);
+  sym[at] = c_sym[s];
+  pos[at] = str_off[s];
+}
+
+// children count of the level's items (sum of right-hand-side lengths)
+__global__ __launch_bounds__(256) void k_xs_count(const uint32_t* __restrict__ sym, uint64_t m,
+                                                  const uint64_t* __restrict__ rule_off,
+                                                  unsigned long long* __restrict__ total) {
+  unsigned long long c = 0;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < m;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t r = sym[i];
+    c += rule_off[r + 1] - rule_off[r];
+  }
+  c = wave_sum(c);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(total, c);
+}
+
+// the level's items -> their children (TO_BYTES: level 1 -> bytes at their
+// positions).  A block takes kBlock items, scans their right-hand-side
+// lengths in LDS, reserves its children with one atomicAdd and then writes
+// them child-parallel (thread j: children j, j + kBlock, ...; the parent by
+// binary search over the block's scan), so that stores are coalesced.  The
+// grandchildren (children of the written children) are counted on the way
+// into *gcount, which sizes the next level (rule_off_below: the rules of the
+// children's level; NULL below level 2).
+template <bool TO_BYTES>
+__global__ __launch_bounds__(kBlock) void k_xs_expand(const uint32_t* __restrict__ sym,
+                                                      const uint64_t* __restrict__ pos, uint64_t m,
+                                                      const uint64_t* __restrict__ rule_off,
+                                                      const void* __restrict__ rule_rhs,
+                                                      const uint64_t* __restrict__ e_below,
+                                                      const uint64_t* __restrict__ rule_off_below,
+                                                      uint32_t* __restrict__ nsym,
+                                                      uint64_t* __restrict__ npos,
+                                                      unsigned long long* __restrict__ ncount,
+                                                      unsigned long long* __restrict__ gcount,
+                                                      uint8_t* __restrict__ out) {
+  __shared__ unsigned long long s_wave[kBlock / 64];
+  __shared__ unsigned long long s_excl[kBlock + 1];
+  __shared__ uint64_t s_a[kBlock];
+  __shared__ uint64_t s_p[kBlock];
+  __shared__ unsigned long long s_base;
+  unsigned long long gc = 0;
+  for (uint64_t b0 = blockIdx.x * (uint64_t)kBlock; b0 < m; b0 += (uint64_t)gridDim.x * kBlock) {
+    const uint64_t i = b0 + threadIdx.x;
+    uint64_t a = 0, q = 0, p = 0;
+    if (i < m) {
+      const uint32_t r = sym[i];
+      p = pos[i];
+      a = rule_off[r];
+      q = rule_off[r + 1] - a;
+    }
+    unsigned long long tot = 0;
+    const unsigned long long excl = block_excl_scan<unsigned long long>(q, s_wave, &tot);
+    s_excl[threadIdx.x] = excl;
+    s_a[threadIdx.x] = a;
+    s_p[threadIdx.x] = p;
+    if (threadIdx.x == 0) {
+      s_excl[kBlock] = tot;
+      if constexpr (!TO_BYTES) s_base = atomicAdd(ncount, tot);
+    }
+    __syncthreads();
+    for (unsigned long long c = threadIdx.x; c < tot; c += kBlock) {
+      // parent: the largest j with s_excl[j] <= c (items with q = 0 are skipped)
+      uint32_t lo = 0, hi = kBlock - 1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (s_excl[mid] <= c) lo = mid; else hi = mid - 1;
+      }
+      const uint64_t t = c - s_excl[lo];
+      if constexpr (TO_BYTES) {
+        out[s_p[lo] + t] = static_cast<const uint8_t*>(rule_rhs)[s_a[lo] + t];
+      } else {
+        const uint32_t* rhs = static_cast<const uint32_t*>(rule_rhs) + s_a[lo];
+        uint64_t pp = s_p[lo];
+        for (uint64_t x = 0; x < t; ++x) pp += e_below[rhs[x]];
+        const uint32_t ch = rhs[t];
+        nsym[s_base + c] = ch;
+        npos[s_base + c] = pp;
+        if (rule_off_below) gc += rule_off_below[ch + 1] - rule_off_below[ch];
+      }
+    }
+    __syncthreads();  // the LDS arrays are rewritten by the next iteration
+  }
+  if constexpr (!TO_BYTES) {
+    gc = wave_sum(gc);
+    if ((threadIdx.x & 63) == 0 && gc && gcount) atomicAdd(gcount, gc);
+  }
+}
+
+void launch_xs_strlen(const uint8_t* c_level, const uint32_t* c_sym, uint32_t ks,
+                      const uint64_t* const* e_levels, uint64_t* len, hipStream_t s) {
+  if (!ks) return;
+  k_xs_strlen<<<grid_for(ks, 256), 256, 0, s>>>(c_level, c_sym, ks, e_levels, len);
+  LCG_LAUNCH_CHECK("xs_strlen");
+}
+
+void launch_xs_enter(const uint8_t* c_level, const uint32_t* c_sym, uint32_t ks, uint32_t level,
+                     const uint64_t* str_off, uint32_t* sym, uint64_t* pos, uint64_t* count,
+                     uint8_t* out, hipStream_t s) {
+  if (!ks) return;
+  k_xs_enter<<<grid_for(ks, 256), 256, 0, s>>>(c_level, c_sym, ks, level, str_off, sym, pos,
+                                               reinterpret_cast<unsigned long long*>(count), out);
+  LCG_LAUNCH_CHECK("xs_enter");
+}
+
+void launch_xs_count(const uint32_t* sym, uint64_t m, const uint64_t* rule_off, uint64_t* total,
+                     hipStream_t s) {
+  if (!m) return;
+  unsigned g = grid_for(m, 256);
+  if (g > kPersistentBlocks) g = kPersistentBlocks;
+  k_xs_count<<<g, 256, 0, s>>>(sym, m, rule_off, reinterpret_cast<unsigned long long*>(total));
+  LCG_LAUNCH_CHECK("xs_count");
+}
+
+void launch_xs_expand(bool to_bytes, const uint32_t* sym, const uint64_t* pos, uint64_t m,
+                      const uint64_t* rule_off, const void* rule_rhs, const uint64_t* e_below,
+                      const uint64_t* rule_off_below, uint32_t* nsym, uint64_t* npos,
+                      uint64_t* ncount, uint64_t* gcount, uint8_t* out, hipStream_t s) {
+  if (!m) return;
+  unsigned g = grid_for(m, kBlock);
+  const unsigned r = resident_blocks(to_bytes ? (const void*)k_xs_expand<true>
+                                              : (const void*)k_xs_expand<false>, kBlock);
+  if (g > r) g = r;
+  auto nc = reinterpret_cast<unsigned long long*>(ncount);
+  auto gc = reinterpret_cast<unsigned long long*>(gcount);
+  if (to_bytes)
+    k_xs_expand<true><<<g, kBlock, 0, s>>>(sym, pos, m, rule_off, rule_rhs, e_below,
+                                           rule_off_below, nsym, npos, nc, gc, out);
+  else
+    k_xs_expand<false><<<g, kBlock, 0, s>>>(sym, pos, m, rule_off, rule_rhs, e_below,
+                                            rule_off_below, nsym, npos, nc, gc, out);
+  LCG_LAUNCH_CHECK("xs_expand");
+}
+
 }  // namespace lcg

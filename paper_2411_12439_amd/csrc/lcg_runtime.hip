@@ -234,6 +234,11 @@ struct lcg_grammar {
   lcg::DBuf<uint8_t> c_level;
   lcg::DBuf<uint32_t> c_sym;
   std::vector<lcg::Stat> stats;
+  uint64_t version = 0;  // changes whenever the grammar does
+  // expansion lengths in bytes of every rule, per level (for lcg_expand_strings)
+  std::vector<lcg::DBuf<uint64_t>> explen;
+  lcg::DBuf<const uint64_t*> explen_ptrs;
+  uint64_t explen_version = ~0ull;
   explicit lcg_grammar(uint64_t s) : seed(s), H(s) {}
 };
 
@@ -855,6 +860,7 @@ static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_
 
 // MergeGrams(a, b): a absorbs b level by level (Sec. 3.6).
 static void merge_core(lcg_grammar* a, const lcg_grammar* b, Work& w, hipStream_t s) {
+  ++a->version;
   if (a->seed != b->seed) throw LcgError{LCG_ESEED, "grammars use different hash families"};
   const uint32_t ka = a->k, kb = b->k;
   a->c_level.grow(ka + kb, ka, s);
@@ -920,6 +926,7 @@ static void check_budget(const Opts& o, uint64_t n, uint32_t k) {
 
 static void build_any(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_off, uint32_t k,
                       const Opts& o, hipStream_t s) {
+  ++g->version;
   std::vector<uint64_t> h_off = fetch_offsets(d_off, k, s);
   if (!d_text) throw LcgError{LCG_EINVAL, "text is NULL"};
   Work w;
@@ -997,6 +1004,122 @@ static void expand_core(lcg_grammar* g, uint32_t j, uint8_t* d_out, uint64_t cap
   }
 }
 
+// Expansion lengths (bytes) of every rule of g, per level, kept until g changes.
+static void ensure_explen(lcg_grammar* g, hipStream_t s) {
+  if (g->explen_version == g->version && g->explen.size() == g->levels.size()) return;
+  const size_t nl = g->levels.size();
+  g->explen.resize(nl);
+  std::vector<const uint64_t*> ptrs(std::max<size_t>(nl, 1), nullptr);
+  for (size_t i = 0; i < nl; ++i) {
+    const Level& L = g->levels[i];
+    g->explen[i].need(std::max<uint32_t>(L.u, 1), s);
+    launch_explen(L.off.p, i ? L.rhs32.p : nullptr, i ? g->explen[i - 1].p : nullptr, L.u,
+                  g->explen[i].p, s);
+    ptrs[i] = g->explen[i].p;
+  }
+  g->explen_ptrs.need(ptrs.size(), s);
+  HIP_CHECK(hipMemcpyAsync(g->explen_ptrs.p, ptrs.data(), ptrs.size() * sizeof(void*),
+                           hipMemcpyHostToDevice, s));
+  sync(s);  // ptrs is a host temporary
+  g->explen_version = g->version;
+}
+
+// Items of a level: the children written by the expansion first, then the
+// strings entering at that level.
+static inline uint64_t children_before(uint64_t m_next, uint64_t entering) {
+  return m_next - entering;
+}
+
+// Strings j0..j1-1 expanded together, top-down by byte positions (see
+// launch_xs_*): every symbol carries the position of its expansion, so a
+// level is one pass over its symbols, in any order.
+static void expand_strings_core(lcg_grammar* g, uint32_t j0, uint32_t j1, uint8_t* d_out,
+                                uint64_t cap, uint64_t* d_offsets, uint64_t* total_out,
+                                hipStream_t s) {
+  if (j0 > j1 || j1 > g->k) throw LcgError{LCG_EINVAL, "string range out of bounds"};
+  const uint32_t ks = j1 - j0;
+  std::vector<uint8_t> h_level(ks);
+  if (ks) {
+    HIP_CHECK(hipMemcpyAsync(h_level.data(), g->c_level.p + j0, ks, hipMemcpyDeviceToHost, s));
+    sync(s);
+  }
+  uint32_t top = 0;
+  for (uint8_t v : h_level) top = std::max<uint32_t>(top, v);
+  if (top > g->levels.size()) throw LcgError{LCG_EHIP, "internal: C entry above the top level"};
+  std::vector<uint64_t> entering(top + 1, 0);
+  for (uint8_t v : h_level) ++entering[v];
+  ensure_explen(g, s);
+  const uint8_t* cl = g->c_level.p + j0;
+  const uint32_t* cs = g->c_sym.p + j0;
+  DBuf<uint64_t> len, str_off, tmp, ctr;
+  len.need(std::max<uint32_t>(ks, 1), s);
+  str_off.need(ks + 1, s);
+  ctr.need(2, s);  // [0]: items of the next level, [1]: children count
+  uint64_t total = 0;
+  if (ks) {
+    launch_xs_strlen(cl, cs, ks, g->explen_ptrs.p, len.p, s);
+    tmp.need(std::max<size_t>(scan_tmp_words(ks), 1), s);
+    scan_exclusive(len.p, str_off.p, ks, tmp.p, s);
+    total = read_dev(str_off.p + ks, s);
+  } else {
+    launch_zero(str_off.p, sizeof(uint64_t), s);
+  }
+  if (total_out) *total_out = total;
+  if (total > cap) throw LcgError{LCG_EINVAL, "output buffer too small"};
+  if (d_offsets)
+    HIP_CHECK(hipMemcpyAsync(d_offsets, str_off.p, (ks + 1) * sizeof(uint64_t),
+                             hipMemcpyDeviceToDevice, s));
+  DBuf<uint32_t> sym[2];
+  DBuf<uint64_t> pos[2];
+  int cur = 0;
+  uint64_t m = entering[top];
+  uint64_t children = 0;  // children of the current level's items
+  launch_zero(ctr.p, 2 * sizeof(uint64_t), s);
+  if (top >= 1) {
+    sym[cur].need(std::max<uint64_t>(m, 1), s);
+    pos[cur].need(std::max<uint64_t>(m, 1), s);
+    launch_xs_enter(cl, cs, ks, top, str_off.p, sym[cur].p, pos[cur].p, ctr.p, d_out, s);
+    if (top >= 2) {
+      launch_xs_count(sym[cur].p, m, g->levels[top - 1].off.p, ctr.p + 1, s);
+      children = read_dev(ctr.p + 1, s);
+    }
+  }
+  for (uint32_t lv = top; lv >= 1; --lv) {
+    const Level& L = g->levels[lv - 1];
+    if (lv == 1) {
+      launch_xs_expand(true, sym[cur].p, pos[cur].p, m, L.off.p, L.rhs8.p, nullptr, nullptr,
+                       nullptr, nullptr, nullptr, nullptr, d_out, s);
+      break;
+    }
+    // the children are counted by the previous pass (or above, at the top);
+    // this pass counts the grandchildren, except those of entering strings
+    const uint64_t m_next = children + entering[lv - 1];
+    sym[cur ^ 1].need(std::max<uint64_t>(m_next, 1), s);
+    pos[cur ^ 1].need(std::max<uint64_t>(m_next, 1), s);
+    launch_zero(ctr.p, 2 * sizeof(uint64_t), s);
+    const uint64_t* off_below = lv >= 3 ? g->levels[lv - 2].off.p : nullptr;
+    launch_xs_expand(false, sym[cur].p, pos[cur].p, m, L.off.p, L.rhs32.p, g->explen[lv - 2].p,
+                     off_below, sym[cur ^ 1].p, pos[cur ^ 1].p, ctr.p, ctr.p + 1, nullptr, s);
+    launch_xs_enter(cl, cs, ks, lv - 1, str_off.p, sym[cur ^ 1].p, pos[cur ^ 1].p, ctr.p, d_out, s);
+    if (lv >= 3) {
+      children = read_dev(ctr.p + 1, s);
+      if (entering[lv - 1]) {
+        // the entering strings' own children
+        DBuf<uint64_t> extra;
+        extra.need(1, s);
+        launch_zero(extra.p, sizeof(uint64_t), s);
+        launch_xs_count(sym[cur ^ 1].p + children_before(m_next, entering[lv - 1]),
+                        entering[lv - 1], off_below, extra.p, s);
+        children += read_dev(extra.p, s);
+      }
+    }
+    cur ^= 1;
+    m = m_next;
+  }
+  if (entering[0]) launch_xs_enter(cl, cs, ks, 0, str_off.p, nullptr, nullptr, ctr.p, d_out, s);
+  sync(s);
+}
+
 template <typename F>
 static lcg_status guard(F&& f) {
   try {
@@ -1071,6 +1194,16 @@ lcg_status lcg_merge(lcg_grammar_t a, lcg_grammar_t b, hipStream_t stream) {
     if (a == b) throw LcgError{LCG_EINVAL, "cannot merge a grammar into itself"};
     Work w;
     merge_core(a, b, w, stream);
+  });
+}
+
+lcg_status lcg_expand_strings(lcg_grammar_t g, uint32_t j0, uint32_t j1, uint8_t* d_out,
+                              uint64_t cap, uint64_t* d_offsets, uint64_t* total,
+                              hipStream_t stream) {
+  return guard([&] {
+    if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    if (!d_out && cap) throw LcgError{LCG_EINVAL, "d_out is NULL"};
+    expand_strings_core(g, j0, j1, d_out, cap, d_offsets, total, stream);
   });
 }
 

@@ -25,7 +25,8 @@ _STATUS = {0: "LCG_OK", -1: "LCG_EINVAL", -2: "LCG_ENOMEM", -3: "LCG_ESEED",
            -4: "LCG_EOVERFLOW", -5: "LCG_ETABLE", -6: "LCG_EHIP"}
 
 # Every symbol include/lcg.h declares (checked by the CPU test suite).
-EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_expand", "lcg_new",
+EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_expand",
+           "lcg_expand_strings", "lcg_new",
            "lcg_info", "lcg_level_size", "lcg_level_copy", "lcg_c_copy", "lcg_stats",
            "lcg_stats_clear", "lcg_build_bytes", "lcg_free", "lcg_release_pool", "lcg_last_error")
 
@@ -69,6 +70,9 @@ def lib():
     L.lcg_merge.restype = st
     L.lcg_expand.argtypes = [vp, ctypes.c_uint32, vp, ctypes.c_uint64, u64p, vp]
     L.lcg_expand.restype = st
+    L.lcg_expand_strings.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, vp, ctypes.c_uint64, vp,
+                                     u64p, vp]
+    L.lcg_expand_strings.restype = st
     L.lcg_new.argtypes = [ctypes.c_uint64, ctypes.POINTER(vp)]
     L.lcg_new.restype = st
     L.lcg_info.argtypes = [vp, u64p, u32p, u32p]
@@ -209,6 +213,24 @@ class Grammar:
         _check(lib().lcg_expand(self.h, j, ctypes.c_void_p(out.data_ptr()), out.numel(),
                                 ctypes.byref(n), _stream(stream)))
         return out[:n.value]
+
+
+    def expand_strings(self, j0=0, j1=None, stream=None):
+        """Strings j0..j1-1 expanded together: (uint8 device tensor, int64 offsets tensor)."""
+        import torch
+        _, _, k = self.info()
+        j1 = k if j1 is None else j1
+        total = ctypes.c_uint64()
+        rc = lib().lcg_expand_strings(self.h, j0, j1, None, 0, None, ctypes.byref(total),
+                                      _stream(stream))
+        if rc not in (0, -1):
+            _check(rc)
+        out = torch.empty(max(total.value, 1), dtype=torch.uint8, device="cuda")
+        offs = torch.empty(max(j1 - j0, 0) + 1, dtype=torch.int64, device="cuda")
+        _check(lib().lcg_expand_strings(self.h, j0, j1, ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                        ctypes.c_void_p(offs.data_ptr()), ctypes.byref(total),
+                                        _stream(stream)))
+        return out[:total.value], offs
 
 
 def new(seed):

@@ -86,6 +86,23 @@ def test_round_trip_expand(L):
         assert np.array_equal(g.expand(j).cpu().numpy(), text[off[j]:off[j + 1]])
 
 
+def _check_expand_strings(g, text, off, j0, j1):
+    out, offs = g.expand_strings(j0, j1)
+    want = text[off[j0]:off[j1]]
+    assert np.array_equal(out.cpu().numpy(), want)
+    assert np.array_equal(offs.cpu().numpy(), (off[j0:j1 + 1] - off[j0]).astype(np.int64))
+
+
+@PATHS
+def test_expand_strings_round_trip(L, tail):
+    """All strings expanded together (and sub-ranges) give back the input."""
+    text, off = D.make_config("tiny", scale=0.3)
+    g = _gpu(L, text, off, tail_log2=tail)
+    k = len(off) - 1
+    for j0, j1 in ((0, k), (2, 5), (k - 1, k), (3, 3)):
+        _check_expand_strings(g, text, off, j0, j1)
+
+
 def test_deterministic(L):
     text, off = D.make_config("tiny", scale=0.5)
     a = _gpu(L, text, off).export()
@@ -120,6 +137,7 @@ def test_edge_cases(L, case, mode, tail):
     text, off = _pack(EDGE[case])
     g = _gpu(L, text, off, mode=mode, tail_log2=tail)
     _assert_same(g.export(), _oracle(text, off).export())
+    _check_expand_strings(g, text, off, 0, len(off) - 1)
 
 
 def test_exhaustive_short_dna(L):
@@ -223,6 +241,11 @@ def test_full_bacterial_sampled_strings(L, bacterial_full, j):
     alone = O.build(text[off[j]:off[j + 1]], np.array([0, off[j + 1] - off[j]], np.uint64), SEED)
     assert CN.canon(got) == CN.canon(alone.export())
     assert np.array_equal(g.expand(j).cpu().numpy(), text[off[j]:off[j + 1]])
+
+
+def test_full_bacterial_expand_strings(L, bacterial_full):
+    text, off, t, o, g = bacterial_full
+    _check_expand_strings(g, text, off, 0, len(off) - 1)
 
 
 def test_full_bacterial_plain_equals_batched(L, bacterial_full):
