@@ -145,6 +145,8 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=4.0,
                     help="seconds per offered load of the serving leg (0 = skip)")
     ap.add_argument("--serving-loads", default="0.5,2,8")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (lcg_tune) and time the default options")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 3 times (calibrates rocprof "
                          "FETCH_SIZE / WRITE_SIZE against a copy of known size) and exit")
@@ -178,8 +180,12 @@ def main():
     print("[bench] %s: %d strings, %d bytes on device" % (args.config, k, n), file=sys.stderr,
           flush=True)
 
+    # the autotuner picks the speed-only options for this workload (untimed)
+    tuned, tuned_ms = ({}, None) if args.no_tune else lcg.tune(t, o, seed=seed)
+    if tuned:
+        print("[bench] tuned %s (%.2f ms)" % (tuned, tuned_ms), file=sys.stderr, flush=True)
     for i in range(args.warmup):
-        g = lcg.build(t, o, seed=seed, flags=lcg.FLAG_TIMING)
+        g = lcg.build(t, o, seed=seed, flags=lcg.FLAG_TIMING, **tuned)
         g.free()
         print("[bench] warmup %d done" % i, file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -192,7 +198,7 @@ def main():
     for i in range(args.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        g = lcg.build(t, o, seed=seed, flags=lcg.FLAG_TIMING)
+        g = lcg.build(t, o, seed=seed, flags=lcg.FLAG_TIMING, **tuned)
         torch.cuda.synchronize()
         step_s.append(time.perf_counter() - t0)
         st = g.stats()
@@ -253,6 +259,7 @@ def main():
            "alg_gbps": round(alg_gbps, 2),
            "alg_frac_hbm": round(alg_gbps / HBM_PEAK_GBPS, 4),
            "timed_wall_s": round(wall, 3),
+           "tuned_options": tuned,
            "roofline": roofline}
 
     # decompression of the whole collection (the inverse path): all strings

@@ -77,6 +77,12 @@ typedef struct {
                           sizes back to the host (each kernel reads its size from device
                           memory, dictionaries are sized for the worst case); 1..40,
                           0 = 22.  Results do not depend on it. */
+  uint32_t table_load_log2; /* dictionaries are sized for a load of at most 2^-table_load_log2
+                               of their capacity; 1..3, 0 = 1.  Results do not depend on it. */
+  uint32_t combine_log2;    /* a round whose key sketch estimates at most d / 2^combine_log2
+                               new keys for its d phrases combines equal keys per chunk of
+                               phrases before the dictionary; 1..30, 0 = 5, 31 = never.
+                               Results do not depend on it. */
   uint32_t reserved;   /* must be zero */
 } lcg_opts;
 
@@ -142,6 +148,17 @@ lcg_status lcg_expand(lcg_grammar_t g, uint32_t j, uint8_t* d_out, uint64_t cap,
 lcg_status lcg_expand_strings(lcg_grammar_t g, uint32_t j0, uint32_t j1, uint8_t* d_out,
                               uint64_t cap, uint64_t* d_offsets, uint64_t* total,
                               hipStream_t stream);
+
+/* Autotuner: times complete builds of the given strings (which it builds,
+ * and frees, several times) under candidate values of the options that do not
+ * change results (tail_log2, table_load_log2, combine_log2), one option at a
+ * time starting from `base`, and writes the fastest setting found to *best
+ * (the other fields copied from base) and its build time in milliseconds to
+ * *best_ms (may be NULL).  Times are device times between HIP events on
+ * `stream`.  Arguments as for lcg_build; base->mode must be
+ * LCG_MODE_BATCHED. */
+lcg_status lcg_tune(const uint8_t* d_text, const uint64_t* d_offsets, uint32_t k,
+                    const lcg_opts* base, hipStream_t stream, lcg_opts* best, double* best_ms);
 
 /* An empty grammar with hash family `seed` (no levels, no strings). */
 lcg_status lcg_new(uint64_t seed, lcg_grammar_t* out);

@@ -252,6 +252,8 @@ struct Opts {
   uint32_t key_bits = 0;
   uint32_t table_min_log2 = 12;
   uint32_t tail_log2 = 22;
+  uint32_t table_load_log2 = 1;
+  uint32_t combine_log2 = 5;  // 31: never
 };
 
 static Opts read_opts(const lcg_opts* o) {
@@ -265,6 +267,10 @@ static Opts read_opts(const lcg_opts* o) {
   if (o->table_min_log2) r.table_min_log2 = o->table_min_log2;
   if (o->tail_log2) r.tail_log2 = o->tail_log2;
   if (r.tail_log2 > 40) throw LcgError{LCG_EINVAL, "tail_log2 out of range"};
+  if (o->table_load_log2) r.table_load_log2 = o->table_load_log2;
+  if (r.table_load_log2 > 3) throw LcgError{LCG_EINVAL, "table_load_log2 out of range"};
+  if (o->combine_log2) r.combine_log2 = o->combine_log2;
+  if (r.combine_log2 > 31) throw LcgError{LCG_EINVAL, "combine_log2 out of range"};
   if (o->reserved) throw LcgError{LCG_EINVAL, "reserved option field must be zero"};
   if (r.mode != LCG_MODE_BATCHED && r.mode != LCG_MODE_PLAIN)
     throw LcgError{LCG_EINVAL, "unknown mode"};
@@ -419,10 +425,12 @@ struct PhaseEvents {
   }
 };
 
-// Make room in level L's dictionary for `need` committed + new keys at load <= 1/2.
-static void ensure_table(Level& L, uint64_t need, uint32_t min_log2, Work& w, hipStream_t s,
+// Make room in level L's dictionary for `need` committed + new keys at load
+// <= 2^-table_load_log2.
+static void ensure_table(Level& L, uint64_t need, const Opts& o, Work& w, hipStream_t s,
                          bool force_grow = false) {
-  uint64_t want = std::max<uint64_t>(next_pow2(2 * std::max<uint64_t>(need, 1)), 1ull << min_log2);
+  uint64_t want = std::max<uint64_t>(next_pow2(std::max<uint64_t>(need, 1) << o.table_load_log2),
+                                     1ull << o.table_min_log2);
   if (force_grow) want = std::max<uint64_t>(want, L.tcap * 4);
   if (L.tcap >= want && L.table.p) return;
   // slot indices are uint32 and kNone is never one
@@ -452,9 +460,6 @@ static void ensure_level(lcg_grammar* g, size_t i, hipStream_t s) {
   }
 }
 
-// A round whose estimated count of new keys is at most 1/kCombineRatio of its
-// phrases uses the combining insert and rewrite.
-constexpr uint64_t kCombineRatio = 32;
 
 struct DedupResult {
   uint32_t u_new;
@@ -473,10 +478,10 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
                                 PhaseEvents* pe = nullptr) {
   Level& L = g->levels[lv - 1];
   const bool bytes = lv == 1;
-  ensure_table(L, (uint64_t)L.u + est_new, o.table_min_log2, w, s);
+  ensure_table(L, (uint64_t)L.u + est_new, o, w, s);
   const uint64_t W = (d + 63) / 64;
   // few distinct keys for many phrases: combine equal keys per chunk first
-  const bool combine = est_new * kCombineRatio <= d;
+  const bool combine = o.combine_log2 < 31 && (est_new << o.combine_log2) <= d;
   w.slot_idx.need(d, s);
   if (combine) w.rest.need(d, s);
   w.newbits.need(W, s);
@@ -520,7 +525,7 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
                    (unsigned long long)L.tcap, hc.won, hc.probes, hc.compares, hc.overflow);
     if (!hc.overflow) break;
     if (attempt >= 6) throw LcgError{LCG_ETABLE, "dictionary overflow persists after regrowth"};
-    ensure_table(L, (uint64_t)L.u + std::max<uint64_t>(est_new, hc.won), o.table_min_log2, w, s,
+    ensure_table(L, (uint64_t)L.u + std::max<uint64_t>(est_new, hc.won), o, w, s,
                  /*force_grow=*/true);
   }
   if ((uint64_t)L.u + u_new >= kNone) throw LcgError{LCG_EOVERFLOW, "level needs 2^32 ranks"};
@@ -615,7 +620,7 @@ static void tail_rounds(lcg_grammar* g, uint32_t lv, uint64_t n_i, uint64_t acti
     w.wlen_base.need(W_b + 1, s);
     ensure_level(g, lv, s);
     Level& L = g->levels[lv - 1];
-    ensure_table(L, (uint64_t)L.u + d_b, o.table_min_log2, w, s);
+    ensure_table(L, (uint64_t)L.u + d_b, o, w, s);
     if ((uint64_t)L.u + d_b >= kNone) throw LcgError{LCG_EOVERFLOW, "level needs 2^32 ranks"};
     L.off.grow(L.u + d_b + 1, L.u + 1, s);
     L.fp.grow(L.u + d_b, L.u, s);
@@ -1170,6 +1175,74 @@ lcg_status lcg_build(const uint8_t* d_text, const uint64_t* d_offsets, uint32_t 
       throw;
     }
     *out = g;
+  });
+}
+
+lcg_status lcg_tune(const uint8_t* d_text, const uint64_t* d_offsets, uint32_t k,
+                    const lcg_opts* base, hipStream_t stream, lcg_opts* best, double* best_ms) {
+  return guard([&] {
+    if (!best) throw LcgError{LCG_EINVAL, "best is NULL"};
+    const Opts o0 = read_opts(base);
+    if (o0.mode != LCG_MODE_BATCHED) throw LcgError{LCG_EINVAL, "tuning is for the batched form"};
+    lcg_opts cur;
+    if (base) cur = *base;
+    else lcg_opts_init(&cur);
+    // explicit values, so that candidates compare with the current setting
+    cur.tail_log2 = o0.tail_log2;
+    cur.table_load_log2 = o0.table_load_log2;
+    cur.combine_log2 = o0.combine_log2;
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    auto time_build = [&](const lcg_opts& c) {
+      const Opts o = read_opts(&c);
+      lcg_grammar* g = new lcg_grammar(o.seed);
+      float ms = 0;
+      try {
+        HIP_CHECK(hipEventRecord(e0, stream));
+        build_any(g, d_text, d_offsets, k, o, stream);
+        HIP_CHECK(hipEventRecord(e1, stream));
+        HIP_CHECK(hipEventSynchronize(e1));
+        HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+      } catch (...) {
+        (void)hipStreamSynchronize(stream);
+        delete g;
+        throw;
+      }
+      delete g;
+      return (double)ms;
+    };
+    struct Knob {
+      uint32_t lcg_opts::*field;
+      std::vector<uint32_t> values;
+    };
+    const Knob knobs[] = {{&lcg_opts::tail_log2, {16, 18, 20, 22, 24}},
+                          {&lcg_opts::table_load_log2, {1, 2}},
+                          {&lcg_opts::combine_log2, {4, 5, 6, 31}}};
+    try {
+      time_build(cur);  // warm-up: pool, code objects, caches
+      double best_t = time_build(cur);
+      for (const Knob& kn : knobs) {
+        for (uint32_t v : kn.values) {
+          if (cur.*(kn.field) == v) continue;
+          lcg_opts c = cur;
+          c.*(kn.field) = v;
+          const double t = time_build(c);
+          if (t < best_t * 0.98) {  // a clear gain, not noise
+            cur = c;
+            best_t = t;
+          }
+        }
+      }
+      *best = cur;
+      if (best_ms) *best_ms = best_t;
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
   });
 }
 

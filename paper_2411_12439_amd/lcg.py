@@ -26,7 +26,7 @@ _STATUS = {0: "LCG_OK", -1: "LCG_EINVAL", -2: "LCG_ENOMEM", -3: "LCG_ESEED",
 
 # Every symbol include/lcg.h declares (checked by the CPU test suite).
 EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_expand",
-           "lcg_expand_strings", "lcg_new",
+           "lcg_expand_strings", "lcg_tune", "lcg_new",
            "lcg_info", "lcg_level_size", "lcg_level_copy", "lcg_c_copy", "lcg_stats",
            "lcg_stats_clear", "lcg_build_bytes", "lcg_free", "lcg_release_pool", "lcg_last_error")
 
@@ -42,7 +42,11 @@ class Opts(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("mode", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("hbm_budget", ctypes.c_uint64), ("key_bits", ctypes.c_uint32),
                 ("table_min_log2", ctypes.c_uint32), ("tail_log2", ctypes.c_uint32),
+                ("table_load_log2", ctypes.c_uint32), ("combine_log2", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32)]
+
+# options that only change speed, never results (what the autotuner sets)
+TUNABLE = ("tail_log2", "table_load_log2", "combine_log2")
 
 
 _lib = None
@@ -73,6 +77,9 @@ def lib():
     L.lcg_expand_strings.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, vp, ctypes.c_uint64, vp,
                                      u64p, vp]
     L.lcg_expand_strings.restype = st
+    L.lcg_tune.argtypes = [vp, vp, ctypes.c_uint32, ctypes.POINTER(Opts), vp, ctypes.POINTER(Opts),
+                           ctypes.POINTER(ctypes.c_double)]
+    L.lcg_tune.restype = st
     L.lcg_new.argtypes = [ctypes.c_uint64, ctypes.POINTER(vp)]
     L.lcg_new.restype = st
     L.lcg_info.argtypes = [vp, u64p, u32p, u32p]
@@ -127,7 +134,7 @@ def _check_inputs(text, offsets):
 
 
 def make_opts(seed=0, mode=MODE_BATCHED, flags=0, hbm_budget=0, key_bits=0, table_min_log2=0,
-              tail_log2=0):
+              tail_log2=0, table_load_log2=0, combine_log2=0):
     o = Opts()
     lib().lcg_opts_init(ctypes.byref(o))
     o.seed = seed
@@ -137,6 +144,8 @@ def make_opts(seed=0, mode=MODE_BATCHED, flags=0, hbm_budget=0, key_bits=0, tabl
     o.key_bits = key_bits
     o.table_min_log2 = table_min_log2
     o.tail_log2 = tail_log2
+    o.table_load_log2 = table_load_log2
+    o.combine_log2 = combine_log2
     return o
 
 
@@ -240,10 +249,11 @@ def new(seed):
 
 
 def build(text, offsets, seed=0, mode=MODE_BATCHED, flags=0, hbm_budget=0, key_bits=0,
-          table_min_log2=0, tail_log2=0, stream=None):
+          table_min_log2=0, tail_log2=0, table_load_log2=0, combine_log2=0, stream=None):
     """BuildGram over the strings text[offsets[j]:offsets[j+1]] (device tensors)."""
     _check_inputs(text, offsets)
-    o = make_opts(seed, mode, flags, hbm_budget, key_bits, table_min_log2, tail_log2)
+    o = make_opts(seed, mode, flags, hbm_budget, key_bits, table_min_log2, tail_log2,
+                  table_load_log2, combine_log2)
     h = ctypes.c_void_p()
     _check(lib().lcg_build(ctypes.c_void_p(text.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
                            offsets.numel() - 1, ctypes.byref(o), _stream(stream), ctypes.byref(h)))
@@ -262,6 +272,19 @@ def build_into(g, text, offsets, seed=None, flags=0, hbm_budget=0, key_bits=0, t
                                 ctypes.c_void_p(offsets.data_ptr()), offsets.numel() - 1,
                                 ctypes.byref(o), _stream(stream), ctypes.byref(first)))
     return first.value
+
+
+def tune(text, offsets, seed=0, stream=None, **base):
+    """lcg_tune: the fastest setting of the TUNABLE options for these strings.
+    Returns ({option: value}, build milliseconds)."""
+    _check_inputs(text, offsets)
+    o = make_opts(seed, **base)
+    best = Opts()
+    ms = ctypes.c_double()
+    _check(lib().lcg_tune(ctypes.c_void_p(text.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
+                          offsets.numel() - 1, ctypes.byref(o), _stream(stream), ctypes.byref(best),
+                          ctypes.byref(ms)))
+    return {f: int(getattr(best, f)) for f in TUNABLE}, ms.value
 
 
 def build_bytes(n, k):

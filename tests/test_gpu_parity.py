@@ -103,6 +103,26 @@ def test_expand_strings_round_trip(L, tail):
         _check_expand_strings(g, text, off, j0, j1)
 
 
+def test_speed_options_do_not_change_results(L):
+    """Every setting of the options the autotuner may change gives the same grammar."""
+    text, off = D.make_config("bacterial", scale=0.02)
+    ref = _gpu(L, text, off).export()
+    for kw in ({"table_load_log2": 2}, {"table_load_log2": 3}, {"combine_log2": 31},
+               {"combine_log2": 1}, {"combine_log2": 8, "tail_log2": 16},
+               {"tail_log2": 30, "table_load_log2": 2}):
+        _assert_same(_gpu(L, text, off, **kw).export(), ref)
+
+
+def test_autotuner(L):
+    text, off = D.make_config("tiny", scale=2.0)
+    t, o = L.to_device(text, off)
+    best, ms = L.tune(t, o, seed=SEED)
+    assert ms > 0
+    assert set(best) == set(L.TUNABLE)
+    assert 1 <= best["table_load_log2"] <= 3 and 1 <= best["combine_log2"] <= 31
+    _assert_same(L.build(t, o, seed=SEED, **best).export(), _oracle(text, off).export())
+
+
 def test_deterministic(L):
     text, off = D.make_config("tiny", scale=0.5)
     a = _gpu(L, text, off).export()
