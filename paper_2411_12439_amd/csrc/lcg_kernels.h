@@ -29,6 +29,13 @@ struct Counters {
   unsigned int hll[kHll];       // HyperLogLog registers of the round's phrase keys
 };
 
+// Strings a tile of kTile positions overlaps (lo..hi) and the offsets of
+// string lo.
+struct TileSeg {
+  uint32_t lo, hi;
+  uint64_t start, end;
+};
+
 // Everything one round of the position kernels needs.
 struct RoundIn {
   const void* sym;          // uint8_t (level 1) or uint32_t symbols of T^i
@@ -45,10 +52,10 @@ void launch_f0_lut(uint32_t* lut, uint64_t a0, uint64_t b0, hipStream_t s);
 void launch_fill_slots(Slot* t, uint64_t cap, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 
-void launch_classify(const RoundIn& in, uint64_t* bits, uint64_t* tile_cnt, uint2* tile_seg,
+void launch_classify(const RoundIn& in, uint64_t* bits, uint64_t* tile_cnt, TileSeg* tile_seg,
                      hipStream_t s);
 void launch_emit(const RoundIn& in, const uint64_t* bits, const uint64_t* tile_base,
-                 const uint2* tile_seg, LevelHash h,
+                 const TileSeg* tile_seg, LevelHash h,
                  uint32_t key_bits, uint64_t* pstart, uint32_t* plen, uint64_t* key, uint32_t* fnew,
                  uint8_t* hll_part, Counters* ctr, hipStream_t s);
 

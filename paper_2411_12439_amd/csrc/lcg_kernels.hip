@@ -240,53 +240,11 @@ constexpr int kCStage = kTile + 1 + kRightHalo;  // staged position t0 - 1 + i .
 __device__ __forceinline__ uint32_t cpad(uint32_t i) { return i + (i >> 4); }
 constexpr int kCStagePadded = kCStage + kCStage / 16 + 1;
 
-template <bool BYTES>
-__device__ __forceinline__ void stage_fp(const RoundIn& in, const uint32_t* s_lut, uint64_t t0,
-                                         uint32_t* s_f) {
-  // main tile: positions t0 .. t0 + kTile - 1 -> s_f[1 .. kTile]
-  const uint64_t lim = in.n - t0 < (uint64_t)kTile ? in.n - t0 : (uint64_t)kTile;
-  if constexpr (BYTES) {
-    const uint8_t* src = static_cast<const uint8_t*>(in.sym) + t0;
-    const uint32_t i = threadIdx.x * 16;
-    if ((reinterpret_cast<uintptr_t>(src) & 15) == 0 && i + 16 <= lim) {
-      const uint4 v = *reinterpret_cast<const uint4*>(src + i);
-      const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int x = 0; x < 16; ++x) s_f[cpad(1 + i + x)] = s_lut[(wv[x >> 2] >> (8 * (x & 3))) & 0xFF];
-    } else {
-      for (uint32_t x = i; x < i + 16 && x < lim; ++x) s_f[cpad(1 + x)] = s_lut[src[x]];
-    }
-  } else {
-    const uint32_t* src = in.fp + t0;
-    if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
-      for (uint32_t i = threadIdx.x * 4; i < kTile; i += kBlock * 4) {
-        if (i + 4 <= lim) {
-          const uint4 v = *reinterpret_cast<const uint4*>(src + i);
-          s_f[cpad(1 + i)] = v.x;
-          s_f[cpad(2 + i)] = v.y;
-          s_f[cpad(3 + i)] = v.z;
-          s_f[cpad(4 + i)] = v.w;
-        } else {
-          for (uint32_t x = i; x < i + 4 && x < lim; ++x) s_f[cpad(1 + x)] = src[x];
-        }
-      }
-    } else {
-      for (uint32_t i = threadIdx.x; i < lim; i += kBlock) s_f[cpad(1 + i)] = src[i];
-    }
-  }
-  // left neighbour and right halo
-  if (threadIdx.x == 0) s_f[0] = t0 > 0 ? fval<BYTES>(in, s_lut, t0 - 1) : 0u;
-  if (threadIdx.x < kRightHalo) {
-    const uint64_t p = t0 + kTile + threadIdx.x;
-    s_f[cpad(1 + kTile + threadIdx.x)] = p < in.n ? fval<BYTES>(in, s_lut, p) : 0u;
-  }
-}
-
-// The first and last string each tile overlaps (one thread per tile, so the
-// binary searches over the offsets run side by side, not inside the tile's
-// block).
+// The first and last string each tile overlaps, and the offsets of the first
+// (one thread per tile, so the binary searches over the offsets run side by
+// side, not inside the tile's block).
 __global__ void k_tile_seg(const uint64_t* __restrict__ off, uint32_t k, uint64_t n,
-                           const uint64_t* __restrict__ n_dev, uint2* __restrict__ tile_seg) {
+                           const uint64_t* __restrict__ n_dev, TileSeg* __restrict__ tile_seg) {
   if (n_dev) n = *n_dev;
   const uint64_t tiles = (n + kTile - 1) / kTile;
   const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
@@ -295,98 +253,195 @@ __global__ void k_tile_seg(const uint64_t* __restrict__ off, uint32_t k, uint64_
   const uint64_t tl = (t0 + kTile < n ? t0 + kTile : n) - 1;
   const uint32_t lo = seg_search(off, 0, k - 1, t0);
   const uint32_t hi = seg_search(off, lo, k - 1, tl);
-  tile_seg[t] = make_uint2(lo, hi);
+  TileSeg ts;
+  ts.lo = lo;
+  ts.hi = hi;
+  ts.start = off[lo];
+  ts.end = off[lo + 1];
+  tile_seg[t] = ts;
+}
+
+// A tile's raw input, held in registers from its load to its staging: 16
+// bytes (level 1) or 16 fingerprints per thread, the left neighbour (thread
+// 0) and one right-halo value (threads < kRightHalo).
+template <bool BYTES>
+struct TileRegs;
+template <>
+struct TileRegs<true> {
+  uint4 v;
+  uint32_t left, right;
+};
+template <>
+struct TileRegs<false> {
+  uint4 v[4];
+  uint32_t left, right;
+};
+
+template <bool BYTES>
+__device__ __forceinline__ uint32_t raw_at(const RoundIn& in, uint64_t i) {
+  if constexpr (BYTES) return static_cast<const uint8_t*>(in.sym)[i];
+  else return in.fp[i];
 }
 
 template <bool BYTES>
+__device__ __forceinline__ void tile_load(const RoundIn& in, uint64_t t0, TileRegs<BYTES>& r) {
+  const uint64_t lim = in.n - t0 < (uint64_t)kTile ? in.n - t0 : (uint64_t)kTile;
+  if constexpr (BYTES) {
+    const uint8_t* src = static_cast<const uint8_t*>(in.sym) + t0;
+    const uint32_t i = threadIdx.x * 16;
+    if ((reinterpret_cast<uintptr_t>(src) & 15) == 0 && i + 16 <= lim) {
+      r.v = *reinterpret_cast<const uint4*>(src + i);
+    } else {
+      uint32_t w[4] = {0, 0, 0, 0};
+      for (uint32_t x = 0; x < 16; ++x)
+        if (i + x < lim) w[x >> 2] |= (uint32_t)src[i + x] << (8 * (x & 3));
+      r.v = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  } else {
+    const uint32_t* src = in.fp + t0;
+    const bool al = (reinterpret_cast<uintptr_t>(src) & 15) == 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t i = threadIdx.x * 4 + k * kBlock * 4;
+      if (al && i + 4 <= lim) {
+        r.v[k] = *reinterpret_cast<const uint4*>(src + i);
+      } else {
+        uint32_t w[4] = {0, 0, 0, 0};
+        for (uint32_t x = 0; x < 4; ++x)
+          if (i + x < lim) w[x] = src[i + x];
+        r.v[k] = make_uint4(w[0], w[1], w[2], w[3]);
+      }
+    }
+  }
+  r.left = threadIdx.x == 0 && t0 > 0 ? raw_at<BYTES>(in, t0 - 1) : 0u;
+  const uint64_t p = t0 + kTile + threadIdx.x;
+  r.right = threadIdx.x < kRightHalo && p < in.n ? raw_at<BYTES>(in, p) : 0u;
+}
+
+// registers -> s_f (fingerprints; bytes through the h^0 table).  Positions
+// past the end get a value no decision reads (every break needs its run to
+// end inside the string).
+template <bool BYTES>
+__device__ __forceinline__ void tile_store(const TileRegs<BYTES>& r, const uint32_t* s_lut,
+                                           uint32_t* s_f) {
+  if constexpr (BYTES) {
+    const uint32_t i = threadIdx.x * 16;
+    const uint32_t wv[4] = {r.v.x, r.v.y, r.v.z, r.v.w};
+#pragma unroll
+    for (int x = 0; x < 16; ++x) s_f[cpad(1 + i + x)] = s_lut[(wv[x >> 2] >> (8 * (x & 3))) & 0xFF];
+    if (threadIdx.x == 0) s_f[0] = s_lut[r.left & 0xFF];
+    if (threadIdx.x < kRightHalo) s_f[cpad(1 + kTile + threadIdx.x)] = s_lut[r.right & 0xFF];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t i = threadIdx.x * 4 + k * kBlock * 4;
+      s_f[cpad(1 + i)] = r.v[k].x;
+      s_f[cpad(2 + i)] = r.v[k].y;
+      s_f[cpad(3 + i)] = r.v[k].z;
+      s_f[cpad(4 + i)] = r.v[k].w;
+    }
+    if (threadIdx.x == 0) s_f[0] = r.left;
+    if (threadIdx.x < kRightHalo) s_f[cpad(1 + kTile + threadIdx.x)] = r.right;
+  }
+}
+
+// One tile per block.  The tile's input, its entry of the tile map and the
+// h^0 table are all requested before the first barrier, so the block waits
+// for memory once; the map brings the offsets of the tile's first string.
+// (A resident-sized grid looping over tiles measured slower: the loop form
+// needs 92-116 VGPRs, half the occupancy.)
+template <bool BYTES>
 __global__ __launch_bounds__(kBlock) void k_classify(RoundIn in0, uint64_t* __restrict__ bits,
                                                      uint64_t* __restrict__ tile_cnt,
-                                                     const uint2* __restrict__ tile_seg) {
+                                                     const TileSeg* __restrict__ tile_seg) {
   RoundIn in = in0;
   if (in0.n_dev) in.n = *in0.n_dev;  // launched over a bound; the size is on the device
-  if ((uint64_t)blockIdx.x * kTile >= in.n) return;
+  const uint64_t tile = blockIdx.x;
+  const uint64_t t0 = tile * kTile;
+  if (t0 >= in.n) return;
   __shared__ uint32_t s_lut[256];
   __shared__ uint32_t s_f[kCStagePadded];
-  __shared__ uint32_t s_seg[2];
   __shared__ uint32_t s_mask[kBlock];
   __shared__ uint32_t s_cnt;
-  const uint64_t t0 = (uint64_t)blockIdx.x * kTile;
-  if constexpr (BYTES) {
-    s_lut[threadIdx.x] = in.lut[threadIdx.x];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const uint2 r = tile_seg[blockIdx.x];
-    s_seg[0] = r.x;
-    s_seg[1] = r.y;
-    s_cnt = 0;
-  }
-  stage_fp<BYTES>(in, s_lut, t0, s_f);
+  TileRegs<BYTES> regs;
+  tile_load<BYTES>(in, t0, regs);
+  const TileSeg ts = tile_seg[tile];
+  if constexpr (BYTES) s_lut[threadIdx.x] = in.lut[threadIdx.x];
+  if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
-  const uint64_t b = t0 + (uint64_t)threadIdx.x * kItems;
-  uint32_t mask = 0;
-  if (b < in.n) {
-    uint32_t fw[kItems + 2];
+  tile_store<BYTES>(regs, s_lut, s_f);
+  __syncthreads();
+  {
+    const uint64_t b = t0 + (uint64_t)threadIdx.x * kItems;
+    uint32_t mask = 0;
+    if (b < in.n) {
+      uint32_t fw[kItems + 2];
 #pragma unroll
-    for (int x = 0; x < kItems + 2; ++x) fw[x] = s_f[cpad(threadIdx.x * kItems + x)];  // position b - 1 + x
-    uint32_t desc = 0, eq = 0, gt = 0;
+      for (int x = 0; x < kItems + 2; ++x) fw[x] = s_f[cpad(threadIdx.x * kItems + x)];  // position b - 1 + x
+      uint32_t desc = 0, eq = 0, gt = 0;
 #pragma unroll
-    for (int x = 0; x < kItems; ++x) {
-      desc |= (uint32_t)(fw[x] > fw[x + 1]) << x;       // F[l-1] > F[l]
-      eq |= (uint32_t)(fw[x + 1] == fw[x + 2]) << x;    // F[l] == F[l+1]
-      gt |= (uint32_t)(fw[x + 2] > fw[x + 1]) << x;     // F[l+1] > F[l]
-    }
-    uint32_t j = seg_search(in.off, s_seg[0], s_seg[1], b);
-    uint64_t s_start = in.off[j], s_end = in.off[j + 1];
-    const int xe = in.n - b < (uint64_t)kItems ? (int)(in.n - b) : kItems;
-    for (int x = 0; x < xe; ++x) {
-      const uint64_t l = b + x;
-      while (l >= s_end) {
-        ++j;
+      for (int x = 0; x < kItems; ++x) {
+        desc |= (uint32_t)(fw[x] > fw[x + 1]) << x;       // F[l-1] > F[l]
+        eq |= (uint32_t)(fw[x + 1] == fw[x + 2]) << x;    // F[l] == F[l+1]
+        gt |= (uint32_t)(fw[x + 2] > fw[x + 1]) << x;     // F[l+1] > F[l]
+      }
+      uint32_t j = ts.lo;
+      uint64_t s_start = ts.start, s_end = ts.end;
+      if (ts.hi != ts.lo) {
+        j = seg_search(in.off, ts.lo, ts.hi, b);
         s_start = in.off[j];
         s_end = in.off[j + 1];
       }
-      bool brk = false;
-      if (l == s_start) {
-        brk = s_end - s_start >= 2;
-      } else if ((desc >> x) & 1u) {
-        uint32_t ne = (~eq >> x) & ((1u << (kItems - x)) - 1u);
-        if (ne) {
-          uint32_t y = __builtin_ctz(ne);
-          uint64_t r = l + y + 1;
-          brk = r < s_end && ((gt >> (x + y)) & 1u);
-        } else {
-          // the run continues past the window: walk it (LDS, then memory)
-          // F[l] .. F[b + kItems] are all equal, the last one is fw[kItems + 1]
-          const uint32_t fl = fw[kItems + 1];
-          uint64_t r = b + kItems + 1;
-          uint32_t fr = 0;
-          bool more = true;
-          while (more && r < s_end) {
-            const uint64_t i = r - t0 + 1;
-            fr = i < (uint64_t)kCStage ? s_f[cpad((uint32_t)i)] : fval<BYTES>(in, s_lut, r);
-            more = fr == fl;
-            r += more ? 1 : 0;
-          }
-          brk = r < s_end && fr > fl;
+      const int xe = in.n - b < (uint64_t)kItems ? (int)(in.n - b) : kItems;
+      for (int x = 0; x < xe; ++x) {
+        const uint64_t l = b + x;
+        while (l >= s_end) {
+          ++j;
+          s_start = in.off[j];
+          s_end = in.off[j + 1];
         }
+        bool brk = false;
+        if (l == s_start) {
+          brk = s_end - s_start >= 2;
+        } else if ((desc >> x) & 1u) {
+          uint32_t ne = (~eq >> x) & ((1u << (kItems - x)) - 1u);
+          if (ne) {
+            uint32_t y = __builtin_ctz(ne);
+            uint64_t r = l + y + 1;
+            brk = r < s_end && ((gt >> (x + y)) & 1u);
+          } else {
+            // the run continues past the window: walk it (LDS, then memory)
+            // F[l] .. F[b + kItems] are all equal, the last one is fw[kItems + 1]
+            const uint32_t fl = fw[kItems + 1];
+            uint64_t r = b + kItems + 1;
+            uint32_t fr = 0;
+            bool more = true;
+            while (more && r < s_end) {
+              const uint64_t i = r - t0 + 1;
+              fr = i < (uint64_t)kCStage ? s_f[cpad((uint32_t)i)] : fval<BYTES>(in, s_lut, r);
+              more = fr == fl;
+              r += more ? 1 : 0;
+            }
+            brk = r < s_end && fr > fl;
+          }
+        }
+        mask |= (uint32_t)brk << x;
       }
-      mask |= (uint32_t)brk << x;
     }
+    s_mask[threadIdx.x] = mask;
+    atomicAdd(&s_cnt, (uint32_t)__builtin_popcount(mask));
   }
-  s_mask[threadIdx.x] = mask;
-  atomicAdd(&s_cnt, (uint32_t)__builtin_popcount(mask));
   __syncthreads();
   if (threadIdx.x < kTileWords) {
     const int t = threadIdx.x * 4;
     uint64_t w = (uint64_t)s_mask[t] | ((uint64_t)s_mask[t + 1] << 16) |
                  ((uint64_t)s_mask[t + 2] << 32) | ((uint64_t)s_mask[t + 3] << 48);
-    bits[(uint64_t)blockIdx.x * kTileWords + threadIdx.x] = w;
+    bits[tile * kTileWords + threadIdx.x] = w;
   }
-  if (threadIdx.x == 0) tile_cnt[blockIdx.x] = s_cnt;
+  if (threadIdx.x == 0) tile_cnt[tile] = s_cnt;
 }
 
-void launch_classify(const RoundIn& in, uint64_t* bits, uint64_t* tile_cnt, uint2* tile_seg,
+void launch_classify(const RoundIn& in, uint64_t* bits, uint64_t* tile_cnt, TileSeg* tile_seg,
                      hipStream_t s) {
   static_assert(kItems == 16 && kBlock == 256, "bit packing assumes 16 positions per thread");
   unsigned tiles = grid_for(in.n, kTile);  // in.n: the size, or its bound when in.n_dev is set
@@ -527,7 +582,7 @@ constexpr uint32_t kLongList = 2048;  // long phrases deferred per tile; more ar
 template <bool BYTES>
 __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in0, const uint64_t* __restrict__ bits,
                                                  const uint64_t* __restrict__ tile_base,
-                                                 const uint2* __restrict__ tile_seg, uint64_t tiles,
+                                                 const TileSeg* __restrict__ tile_seg, uint64_t tiles,
                                                  LevelHash h, uint32_t key_bits,
                                                  uint64_t* __restrict__ pstart, uint32_t* __restrict__ plen,
                                                  uint64_t* __restrict__ key, uint32_t* __restrict__ fnew,
@@ -552,11 +607,16 @@ __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in0, const uint64_t* __
     const uint64_t t0 = tile * kTile;
     __syncthreads();
     if (threadIdx.x == 0) {
-      const uint2 r = tile_seg[tile];
-      s_seg[0] = r.x;
-      s_seg[1] = r.y;
+      const TileSeg r = tile_seg[tile];
+      s_seg[0] = r.lo;
+      s_seg[1] = r.hi;
       s_nlong = 0;
+      if (r.lo == r.hi) {  // one string: its offsets come with the map
+        s_off[0] = r.start;
+        s_off[1] = r.end;
+      }
     }
+    const uint64_t base = tile_base[tile];  // requested with the tile, used after the scan
     stage_tile<BYTES>(in, t0, st);
     uint32_t mask = (uint32_t)(bits[tile * kTileWords + threadIdx.x / 4] >> ((threadIdx.x & 3) * 16)) &
                     0xFFFFu;
@@ -569,10 +629,9 @@ __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in0, const uint64_t* __
     }
     const uint32_t slo = s_seg[0], shi = s_seg[1];
     const bool cached = shi - slo + 2 <= kSegCache + 1;
-    if (cached)
+    if (cached && shi != slo)
       for (uint32_t i = threadIdx.x; i < shi - slo + 2; i += kBlock) s_off[i] = in.off[slo + i];
     __syncthreads();
-    const uint64_t base = tile_base[tile];
     // Short phrases: their key is their content, taken from the staged tile.
     // Their fingerprint is computed once per new rule when the rule is
     // stored, not once per occurrence.  Long phrases (compared in full, keyed
@@ -648,7 +707,7 @@ __global__ __launch_bounds__(256) void k_hll_reduce(const uint8_t* __restrict__ 
 }
 
 void launch_emit(const RoundIn& in, const uint64_t* bits, const uint64_t* tile_base,
-                 const uint2* tile_seg, LevelHash h,
+                 const TileSeg* tile_seg, LevelHash h,
                  uint32_t key_bits, uint64_t* pstart, uint32_t* plen, uint64_t* key, uint32_t* fnew,
                  uint8_t* hll_part, Counters* ctr, hipStream_t s) {
   uint64_t tiles = grid_for(in.n, kTile);

@@ -346,7 +346,7 @@ struct Work {
   DBuf<uint32_t> lut;
   DBuf<Counters> ctr, fin;
   DBuf<uint8_t> content8, hll_part;
-  DBuf<uint2> tile_seg;
+  DBuf<TileSeg> tile_seg;
   DBuf<uint32_t> content32, remap[2], rest;
   DBuf<struct TailRec> tail;
   void release_after(hipStream_t s) {
