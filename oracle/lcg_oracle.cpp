@@ -37,6 +37,7 @@
 #include <cstdio>
 #include <string>
 #include <vector>
+#include <map>
 #include <unordered_map>
 
 namespace {
@@ -378,5 +379,196 @@ void oracle_stats_copy(const OracleGrammar* g, uint64_t* out) {
   }
 }
 void oracle_free(OracleGrammar* g) { delete g; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------
+// Post-processing (Sec. 2.2, last paragraph; applied to the output of
+// PBuildGram in the order RL, then Simp, Sec. 4).
+//
+// The result is a straight-line grammar with one id space:
+//   * ids 0..255 are the terminals (byte values);
+//   * then, for level i = 1, 2, ...: first the run rules made from the runs
+//     in level i's right-hand sides (their symbols are level-(i-1) symbols),
+//     ordered by (symbol, run length), then level i's rules in rank order.
+// Every rule therefore refers only to smaller ids.  A rule is stored as a
+// right-hand side and a multiplicity: exp(X) = exp(rhs(X))^mult(X).  Rules
+// with mult = 1 are ordinary rules; a run rule X' -> (X, l) is stored as
+// rhs = [X], mult = l >= 2.
+//
+// RL: every maximal equal-symbol run X^l with l >= 2 in an ordinary rule's
+// right-hand side is replaced by the id of the run rule (X, l); each distinct
+// pair (X, l) of a level gets one run rule.
+//
+// Simp: an ordinary rule whose id occurs exactly once over all right-hand
+// sides and C, that one occurrence being in an ordinary rule, is removed and
+// its right-hand side takes the place of its occurrence (recursively).
+// Occurrences in run rules and in C keep a rule: a run rule holds a symbol,
+// not a sequence, and C holds one symbol per string.  Run rules themselves
+// are never removed.  The remaining rules are renumbered in id order from 256.
+//
+// Grammar size G counts |rhs| for ordinary rules and 2 for a run rule.
+
+struct OracleSlp {
+  std::vector<uint64_t> off{0};
+  std::vector<uint32_t> rhs;
+  std::vector<uint32_t> mult;
+  std::vector<uint32_t> c;
+  // g and G of the input, run rules made, g and G after RL, rules removed,
+  // g and G of the result
+  uint64_t stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+};
+
+namespace {
+
+uint64_t slp_size(const OracleSlp& s) {
+  uint64_t G = 0;
+  for (size_t r = 0; r + 1 < s.off.size(); ++r)
+    G += s.mult[r] >= 2 ? 2 : s.off[r + 1] - s.off[r];
+  return G;
+}
+
+// The level grammar in the global id space, with RL applied when rl is set.
+OracleSlp to_global(const OracleGrammar* g, bool rl) {
+  OracleSlp s;
+  std::vector<uint32_t> obase(g->levels.size() + 1, 0);  // first id of level i's rules
+  uint32_t next = 256;
+  for (size_t i = 1; i <= g->levels.size(); ++i) {
+    const Level& L = g->levels[i - 1];
+    auto gid = [&](uint32_t x) { return i == 1 ? x : obase[i - 1] + x; };
+    // the distinct runs (X, l >= 2) of the level, in (X, l) order
+    std::map<std::pair<uint32_t, uint32_t>, uint32_t> runs;
+    if (rl) {
+      for (uint32_t r = 0; r < L.size(); ++r) {
+        uint64_t a = L.rhs_off[r], b = L.rhs_off[r + 1];
+        for (uint64_t x = a; x < b;) {
+          uint64_t y = x + 1;
+          while (y < b && L.rhs[y] == L.rhs[x]) ++y;
+          if (y - x >= 2) runs[{L.rhs[x], (uint32_t)(y - x)}] = 0;
+          x = y;
+        }
+      }
+    }
+    for (auto& kv : runs) {
+      kv.second = next++;
+      s.rhs.push_back(gid(kv.first.first));
+      s.off.push_back(s.rhs.size());
+      s.mult.push_back(kv.first.second);
+    }
+    obase[i] = next;
+    next += L.size();
+    for (uint32_t r = 0; r < L.size(); ++r) {
+      uint64_t a = L.rhs_off[r], b = L.rhs_off[r + 1];
+      for (uint64_t x = a; x < b;) {
+        uint64_t y = x + 1;
+        if (rl)
+          while (y < b && L.rhs[y] == L.rhs[x]) ++y;
+        if (y - x >= 2)
+          s.rhs.push_back(runs.at({L.rhs[x], (uint32_t)(y - x)}));
+        else
+          s.rhs.push_back(gid(L.rhs[x]));
+        x = y;
+      }
+      s.off.push_back(s.rhs.size());
+      s.mult.push_back(1);
+    }
+  }
+  for (size_t j = 0; j < g->c_level.size(); ++j)
+    s.c.push_back(g->c_level[j] == 0 ? g->c_sym[j] : obase[g->c_level[j]] + g->c_sym[j]);
+  return s;
+}
+
+void simp_append(const OracleSlp& s, const std::vector<uint8_t>& removed,
+                 const std::vector<uint32_t>& newid, uint32_t y, std::vector<uint32_t>& out) {
+  if (y < 256 || !removed[y - 256]) {
+    out.push_back(y < 256 ? y : newid[y - 256]);
+    return;
+  }
+  for (uint64_t t = s.off[y - 256]; t < s.off[y - 255]; ++t)
+    simp_append(s, removed, newid, s.rhs[t], out);
+}
+
+OracleSlp simp(const OracleSlp& s) {
+  size_t g = s.mult.size();
+  std::vector<uint64_t> occ(g, 0);    // occurrences in ordinary right-hand sides
+  std::vector<uint8_t> pinned(g, 0);  // occurs in a run rule or in C
+  for (size_t r = 0; r < g; ++r)
+    for (uint64_t t = s.off[r]; t < s.off[r + 1]; ++t) {
+      uint32_t y = s.rhs[t];
+      if (y < 256) continue;
+      if (s.mult[r] >= 2) pinned[y - 256] = 1;
+      else ++occ[y - 256];
+    }
+  for (uint32_t y : s.c)
+    if (y >= 256) pinned[y - 256] = 1;
+  std::vector<uint8_t> removed(g, 0);
+  std::vector<uint32_t> newid(g, 0);
+  uint32_t next = 256;
+  for (size_t r = 0; r < g; ++r) {
+    removed[r] = s.mult[r] == 1 && occ[r] == 1 && !pinned[r];
+    if (!removed[r]) newid[r] = next++;
+  }
+  OracleSlp o;
+  for (size_t r = 0; r < g; ++r) {
+    if (removed[r]) continue;
+    for (uint64_t t = s.off[r]; t < s.off[r + 1]; ++t)
+      simp_append(s, removed, newid, s.rhs[t], o.rhs);
+    o.off.push_back(o.rhs.size());
+    o.mult.push_back(s.mult[r]);
+  }
+  for (uint32_t y : s.c) o.c.push_back(y < 256 ? y : newid[y - 256]);
+  return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+// flags: 1 = RL, 2 = Simp (both: RL first).
+OracleSlp* oracle_postprocess(const OracleGrammar* g, uint32_t flags) {
+  OracleSlp plain = to_global(g, false);
+  OracleSlp s = to_global(g, (flags & 1) != 0);
+  uint64_t st0 = plain.mult.size(), st1 = slp_size(plain);
+  uint64_t runs = s.mult.size() - plain.mult.size();
+  uint64_t g_rl = s.mult.size(), G_rl = slp_size(s);
+  if (flags & 2) s = simp(s);
+  OracleSlp* out = new OracleSlp(std::move(s));
+  uint64_t st[8] = {st0, st1, runs, g_rl, G_rl, g_rl - out->mult.size(), out->mult.size(),
+                    slp_size(*out)};
+  std::memcpy(out->stats, st, sizeof(st));
+  return out;
+}
+void oracle_slp_size(const OracleSlp* s, uint32_t* g, uint64_t* rhs_len, uint32_t* k) {
+  *g = (uint32_t)s->mult.size();
+  *rhs_len = s->rhs.size();
+  *k = (uint32_t)s->c.size();
+}
+void oracle_slp_copy(const OracleSlp* s, uint64_t* off, uint32_t* rhs, uint32_t* mult,
+                     uint32_t* c, uint64_t* stats) {
+  std::memcpy(off, s->off.data(), s->off.size() * sizeof(uint64_t));
+  std::memcpy(rhs, s->rhs.data(), s->rhs.size() * sizeof(uint32_t));
+  std::memcpy(mult, s->mult.data(), s->mult.size() * sizeof(uint32_t));
+  std::memcpy(c, s->c.data(), s->c.size() * sizeof(uint32_t));
+  std::memcpy(stats, s->stats, sizeof(s->stats));
+}
+// exp(C[j]) of the post-processed grammar; returns its length, writes at most cap bytes.
+uint64_t oracle_slp_expand(const OracleSlp* s, uint32_t j, uint8_t* out, uint64_t cap) {
+  uint64_t len = 0;
+  std::vector<uint32_t> stack{s->c[j]};
+  while (!stack.empty()) {
+    uint32_t y = stack.back();
+    stack.pop_back();
+    if (y < 256) {
+      if (len < cap) out[len] = (uint8_t)y;
+      ++len;
+      continue;
+    }
+    uint32_t r = y - 256;
+    for (uint32_t m = 0; m < s->mult[r]; ++m)
+      for (uint64_t t = s->off[r + 1]; t-- > s->off[r];) stack.push_back(s->rhs[t]);
+  }
+  return len;
+}
+void oracle_slp_free(OracleSlp* s) { delete s; }
 
 }  // extern "C"

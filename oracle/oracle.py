@@ -69,6 +69,13 @@ def lib():
         L.oracle_num_rounds.restype = ctypes.c_uint32
         L.oracle_stats_copy.argtypes = [vp, u64p]
         L.oracle_free.argtypes = [vp]
+        L.oracle_postprocess.argtypes = [vp, ctypes.c_uint32]
+        L.oracle_postprocess.restype = vp
+        L.oracle_slp_size.argtypes = [vp, u32p, u64p, u32p]
+        L.oracle_slp_copy.argtypes = [vp, u64p, u32p, u32p, u32p, u64p]
+        L.oracle_slp_expand.argtypes = [vp, ctypes.c_uint32, u8p, ctypes.c_uint64]
+        L.oracle_slp_expand.restype = ctypes.c_uint64
+        L.oracle_slp_free.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -145,6 +152,44 @@ class Grammar:
         out = np.zeros(max(n, 1), np.uint8)
         L.oracle_expand(self.h, j, _ptr(out, ctypes.c_uint8), n)
         return out[:n].tobytes()
+
+    def postprocess(self, rl=True, simp=True, expand=False):
+        """RL and/or Simp (Sec. 2.2): the straight-line grammar described in
+        ``lcg_oracle.cpp`` as a dictionary::
+
+            {"off": uint64[g+1], "rhs": uint32[Q], "mult": uint32[g], "c": uint32[k],
+             "stats": uint64[8]}
+
+        Rule ids are 256 + index; ids below 256 are terminals.  stats: g and G
+        of the input, run rules made, g and G after RL, rules removed, g and G
+        of the result.  With ``expand``, "expansions" lists exp(C[j]) of every
+        string, expanded from the post-processed grammar.
+        """
+        L = lib()
+        h = L.oracle_postprocess(self.h, (1 if rl else 0) | (2 if simp else 0))
+        try:
+            g = ctypes.c_uint32()
+            q = ctypes.c_uint64()
+            k = ctypes.c_uint32()
+            L.oracle_slp_size(h, ctypes.byref(g), ctypes.byref(q), ctypes.byref(k))
+            off = np.zeros(g.value + 1, np.uint64)
+            rhs = np.zeros(max(q.value, 1), np.uint32)
+            mult = np.zeros(max(g.value, 1), np.uint32)
+            c = np.zeros(max(k.value, 1), np.uint32)
+            st = np.zeros(8, np.uint64)
+            L.oracle_slp_copy(h, _ptr(off, ctypes.c_uint64), _ptr(rhs, ctypes.c_uint32),
+                              _ptr(mult, ctypes.c_uint32), _ptr(c, ctypes.c_uint32),
+                              _ptr(st, ctypes.c_uint64))
+            exps = []
+            for j in range(k.value if expand else 0):
+                n = L.oracle_slp_expand(h, j, None, 0)
+                buf = np.zeros(max(n, 1), np.uint8)
+                L.oracle_slp_expand(h, j, _ptr(buf, ctypes.c_uint8), n)
+                exps.append(buf[:n].tobytes())
+        finally:
+            L.oracle_slp_free(h)
+        return {"off": off, "rhs": rhs[:q.value], "mult": mult[:g.value], "c": c[:k.value],
+                "stats": st, "expansions": exps if expand else None}
 
     def merge(self, other):
         """MergeGrams(self, other): self absorbs other; other is unchanged."""
