@@ -199,6 +199,66 @@ lcg_status lcg_stats_clear(lcg_grammar_t g);
 uint64_t lcg_build_bytes(uint64_t n, uint32_t k);
 
 void lcg_free(lcg_grammar_t g);
+
+/* ---- post-processing: RL and Simp ------------------------------------------
+ *
+ * Run-length compression (RL) and grammar simplification (Simp), the two
+ * post-processing steps of Sec. 2.2 that the paper applies to the output of
+ * PBuildGram, RL first (Sec. 4).  The result is a straight-line grammar
+ * (lcg_slp_t) that owns its device memory, with one id space:
+ *   - ids 0..255 are the terminals (byte values);
+ *   - then, for every level i = 1, 2, ... of the input grammar: first the run
+ *     rules made from the runs in level i's right-hand sides, ordered by
+ *     (symbol, run length), then level i's rules in rank order.  Every rule
+ *     refers only to smaller ids.
+ * Rule 256 + r has right-hand side rhs[off[r] .. off[r+1]) and multiplicity
+ * mult[r]: exp = exp(rhs)^mult.  An ordinary rule has mult = 1; the run rule
+ * X' -> (X, l) of a maximal equal-symbol run X^l (l >= 2) is rhs = [X],
+ * mult = l.  C[j] is the id string j derives from.
+ *   RL:   every maximal run X^l, l >= 2, in an ordinary right-hand side is
+ *         replaced by the id of its run rule; each distinct (X, l) of a level
+ *         gets one run rule.
+ *   Simp: every ordinary rule whose id occurs exactly once over all
+ *         right-hand sides and C, that occurrence being in an ordinary rule,
+ *         is removed and its right-hand side spliced in place of the
+ *         occurrence (recursively).  Occurrences in run rules and in C keep a
+ *         rule; run rules are never removed.  Kept rules are renumbered in id
+ *         order from 256.
+ * Grammar size G counts |rhs| for ordinary rules and 2 for a run rule.
+ */
+typedef struct lcg_slp* lcg_slp_t;
+
+enum {
+  LCG_PP_RL = 1u,   /* run-length compression */
+  LCG_PP_SIMP = 2u  /* simplification (after RL when both are set) */
+};
+
+/* Statistics of a post-processing call, in this order: rules g and size G of
+ * the input, run rules made, g and G after RL, rules removed by Simp, g and G
+ * of the result. */
+#define LCG_SLP_STATS 8
+
+/*
+ * Post-process g (left unchanged) on `stream` into *out (free with
+ * lcg_slp_free).  flags: LCG_PP_RL and/or LCG_PP_SIMP; 0 gives g itself in the
+ * id layout above.  Synchronises the stream.  Errors: LCG_EINVAL (NULL
+ * argument, unknown flag, a grammar without strings), LCG_EOVERFLOW (2^32 -
+ * 256 rules or more, or more than 2^31 runs in a level), LCG_ENOMEM, LCG_EHIP.
+ */
+lcg_status lcg_postprocess(lcg_grammar_t g, uint32_t flags, hipStream_t stream, lcg_slp_t* out);
+/* g = rules (ids 256 .. 256+g-1), rhs_len = total right-hand-side length, k = strings. */
+lcg_status lcg_slp_size(lcg_slp_t p, uint32_t* g, uint64_t* rhs_len, uint32_t* k);
+/* h_stats: uint64[LCG_SLP_STATS]. */
+lcg_status lcg_slp_stats(lcg_slp_t p, uint64_t* h_stats);
+/* Device arrays owned by p (valid until lcg_slp_free): off uint64[g+1],
+ * rhs uint32[rhs_len], mult uint32[g], C uint32[k].  Any pointer may be NULL. */
+lcg_status lcg_slp_device(lcg_slp_t p, const uint64_t** d_off, const uint32_t** d_rhs,
+                          const uint32_t** d_mult, const uint32_t** d_c);
+/* Host copies of the same arrays (caller-sized; any pointer may be NULL). */
+lcg_status lcg_slp_copy(lcg_slp_t p, uint64_t* h_off, uint32_t* h_rhs, uint32_t* h_mult,
+                        uint32_t* h_c);
+void lcg_slp_free(lcg_slp_t p);
+
 /* Return the library's cached free device blocks to the driver. */
 void lcg_release_pool(void);
 /* Thread-local description of the last failure. */

@@ -1,0 +1,275 @@
+// Host-side internals shared by the library's translation units: errors,
+// the device block pool, device buffers, the grammar object and the guard
+// that turns exceptions into lcg_status at the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/lcg.h"
+#include "lcg_kernels.h"
+
+namespace lcg {
+
+// ------------------------------------------------------------------ errors
+struct LcgError {
+  lcg_status status;
+  std::string msg;
+};
+
+inline thread_local std::string g_last_error;
+
+#define HIP_CHECK(x)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess)                                                              \
+      throw LcgError{LCG_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)};        \
+  } while (0)
+
+// ------------------------------------------------------------------ hash family
+// Coefficients (a_i, b_i, c_i) of levels 0..63 in [1, p-1], drawn in that
+// order from SplitMix64 (Steele, Lea, Flood 2014; Vigna's constants) seeded
+// with the grammar seed, each output reduced mod 2^61-1, zeros redrawn.
+struct HashFamily {
+  static constexpr int kLevels = 64;
+  LevelHash lv[kLevels];
+  explicit HashFamily(uint64_t seed) {
+    uint64_t state = seed;
+    auto draw = [&state]() {
+      for (;;) {
+        state += 0x9E3779B97F4A7C15ULL;
+        uint64_t z = state;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        z ^= z >> 31;
+        uint64_t v = z % kP61;
+        if (v) return v;
+      }
+    };
+    for (int i = 0; i < kLevels; ++i) {
+      lv[i].a = draw();
+      lv[i].b = draw();
+      lv[i].c = draw();
+    }
+  }
+};
+
+// ------------------------------------------------------------------ device pool
+// Caching pool of device blocks: calls reuse blocks instead of paying for
+// hipMalloc/hipFree (which synchronise the device) every round.
+class Pool {
+ public:
+  void* alloc(size_t bytes) {
+    size_t sz = round_size(bytes);
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      auto it = free_.lower_bound(sz);
+      if (it != free_.end() && it->first <= sz + sz / 2) {
+        void* p = it->second;
+        size_t got = it->first;
+        free_.erase(it);
+        used_[p] = got;
+        return p;
+      }
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, sz);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      trim();
+      e = hipMalloc(&p, sz);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw LcgError{LCG_ENOMEM, "hipMalloc of " + std::to_string(sz) + " bytes failed"};
+      }
+    }
+    std::lock_guard<std::mutex> lk(mu_);
+    used_[p] = sz;
+    return p;
+  }
+  size_t size_of(void* p) {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = used_.find(p);
+    return it == used_.end() ? 0 : it->second;
+  }
+  void release(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = used_.find(p);
+    if (it == used_.end()) return;
+    free_.insert({it->second, p});
+    used_.erase(it);
+  }
+  // release once work already enqueued on `s` has finished (see flush)
+  void release_after(void* p, hipStream_t s) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    pending_.push_back({p, s});
+  }
+  // `s` has been synchronised: its pending blocks become reusable
+  void flush(hipStream_t s) {
+    std::vector<void*> done;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      for (size_t i = 0; i < pending_.size();) {
+        if (pending_[i].second == s) {
+          done.push_back(pending_[i].first);
+          pending_[i] = pending_.back();
+          pending_.pop_back();
+        } else {
+          ++i;
+        }
+      }
+    }
+    for (void* p : done) release(p);
+  }
+  void trim() {
+    std::lock_guard<std::mutex> lk(mu_);
+    for (auto& kv : free_) (void)hipFree(kv.second);
+    free_.clear();
+  }
+
+ private:
+  static size_t round_size(size_t b) {
+    if (b < 256) b = 256;
+    if (b <= (1u << 20)) {
+      size_t p = 256;
+      while (p < b) p <<= 1;
+      return p;
+    }
+    const size_t g = 2u << 20;
+    return (b + g - 1) / g * g;
+  }
+  std::mutex mu_;
+  std::vector<std::pair<void*, hipStream_t>> pending_;
+  std::multimap<size_t, void*> free_;
+  std::unordered_map<void*, size_t> used_;
+};
+
+inline Pool& pool() {
+  static Pool* p = new Pool();  // never destroyed: blocks may outlive static destructors
+  return *p;
+}
+
+template <typename T>
+struct DBuf {
+  T* p = nullptr;
+  size_t cap = 0;  // elements
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), cap(o.cap) { o.p = nullptr; o.cap = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { reset(); p = o.p; cap = o.cap; o.p = nullptr; o.cap = 0; }
+    return *this;
+  }
+  ~DBuf() { reset(); }
+  // release now (no work in flight may use the block)
+  void reset() {
+    if (p) pool().release(p);
+    p = nullptr;
+    cap = 0;
+  }
+  // release once the work already enqueued on s is done
+  void reset_after(hipStream_t s) {
+    if (p) pool().release_after(p, s);
+    p = nullptr;
+    cap = 0;
+  }
+  // capacity >= n, old contents discarded; the old block is released after
+  // the work enqueued on s
+  void need(size_t n, hipStream_t s) {
+    if (n <= cap && p) return;
+    reset_after(s);
+    size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    p = static_cast<T*>(pool().alloc(bytes));
+    cap = pool().size_of(p) / sizeof(T);
+  }
+  // capacity >= n, first `used` elements kept (copied on s)
+  void grow(size_t n, size_t used, hipStream_t s) {
+    if (n <= cap && p) return;
+    size_t want = std::max<size_t>(n, cap + cap / 2);
+    T* np = static_cast<T*>(pool().alloc(std::max<size_t>(want, 1) * sizeof(T)));
+    if (used) HIP_CHECK(hipMemcpyAsync(np, p, used * sizeof(T), hipMemcpyDeviceToDevice, s));
+    reset_after(s);
+    p = np;
+    cap = pool().size_of(np) / sizeof(T);
+  }
+};
+
+// ------------------------------------------------------------------ grammar
+struct Level {
+  uint32_t u = 0;      // rules
+  uint64_t q = 0;      // total rhs length
+  DBuf<uint64_t> off;  // u + 1 offsets
+  DBuf<uint8_t> rhs8;  // level 1: bytes
+  DBuf<uint32_t> rhs32;
+  DBuf<uint32_t> fp;   // F^i of each rule
+  DBuf<Slot> table;    // dictionary H^i: every committed rule holds one slot
+  uint64_t tcap = 0;
+};
+
+using Stat = std::array<uint64_t, LCG_STATS_FIELDS>;
+
+}  // namespace lcg
+
+struct lcg_grammar {
+  uint64_t seed;
+  lcg::HashFamily H;
+  std::vector<lcg::Level> levels;  // levels[i-1] = level i
+  uint32_t k = 0;
+  lcg::DBuf<uint8_t> c_level;
+  lcg::DBuf<uint32_t> c_sym;
+  std::vector<lcg::Stat> stats;
+  uint64_t version = 0;  // changes whenever the grammar does
+  // expansion lengths in bytes of every rule, per level (for lcg_expand_strings)
+  std::vector<lcg::DBuf<uint64_t>> explen;
+  lcg::DBuf<const uint64_t*> explen_ptrs;
+  uint64_t explen_version = ~0ull;
+  explicit lcg_grammar(uint64_t s) : seed(s), H(s) {}
+};
+
+namespace lcg {
+
+// Synchronise s; blocks whose release waited for it become reusable.
+inline void sync(hipStream_t s) {
+  HIP_CHECK(hipStreamSynchronize(s));
+  pool().flush(s);
+}
+
+template <typename T>
+inline T read_dev(const T* p, hipStream_t s) {
+  T v;
+  HIP_CHECK(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, s));
+  sync(s);
+  return v;
+}
+
+template <typename F>
+lcg_status guard(F&& f) {
+  try {
+    f();
+    return LCG_OK;
+  } catch (const LcgError& e) {
+    g_last_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return LCG_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return LCG_EHIP;
+  }
+}
+
+}  // namespace lcg

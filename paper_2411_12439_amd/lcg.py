@@ -28,7 +28,14 @@ _STATUS = {0: "LCG_OK", -1: "LCG_EINVAL", -2: "LCG_ENOMEM", -3: "LCG_ESEED",
 EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_expand",
            "lcg_expand_strings", "lcg_tune", "lcg_new",
            "lcg_info", "lcg_level_size", "lcg_level_copy", "lcg_c_copy", "lcg_stats",
-           "lcg_stats_clear", "lcg_build_bytes", "lcg_free", "lcg_release_pool", "lcg_last_error")
+           "lcg_stats_clear", "lcg_build_bytes", "lcg_free", "lcg_release_pool", "lcg_last_error",
+           "lcg_postprocess", "lcg_slp_size", "lcg_slp_stats", "lcg_slp_device", "lcg_slp_copy",
+           "lcg_slp_free")
+
+PP_RL = 1
+PP_SIMP = 2
+SLP_STATS = 8
+SLP_STAT_NAMES = ("g_in", "G_in", "run_rules", "g_rl", "G_rl", "removed", "g_out", "G_out")
 
 
 class LcgError(RuntimeError):
@@ -102,6 +109,19 @@ def lib():
     L.lcg_release_pool.restype = None
     L.lcg_last_error.argtypes = []
     L.lcg_last_error.restype = ctypes.c_char_p
+    L.lcg_postprocess.argtypes = [vp, ctypes.c_uint32, vp, ctypes.POINTER(vp)]
+    L.lcg_postprocess.restype = st
+    L.lcg_slp_size.argtypes = [vp, u32p, u64p, u32p]
+    L.lcg_slp_size.restype = st
+    L.lcg_slp_stats.argtypes = [vp, u64p]
+    L.lcg_slp_stats.restype = st
+    L.lcg_slp_device.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                 ctypes.POINTER(vp)]
+    L.lcg_slp_device.restype = st
+    L.lcg_slp_copy.argtypes = [vp, u64p, u32p, u32p, u32p]
+    L.lcg_slp_copy.restype = st
+    L.lcg_slp_free.argtypes = [vp]
+    L.lcg_slp_free.restype = None
     _lib = L
     return L
 
@@ -240,6 +260,53 @@ class Grammar:
                                         ctypes.c_void_p(offs.data_ptr()), ctypes.byref(total),
                                         _stream(stream)))
         return out[:total.value], offs
+
+
+    def postprocess(self, rl=True, simp=True, stream=None):
+        """RL and/or Simp (Sec. 2.2) on the device: a new Slp (this grammar is unchanged)."""
+        h = ctypes.c_void_p()
+        flags = (PP_RL if rl else 0) | (PP_SIMP if simp else 0)
+        _check(lib().lcg_postprocess(self.h, flags, _stream(stream), ctypes.byref(h)))
+        return Slp(h.value)
+
+
+class Slp:
+    """Owning handle of a post-processed straight-line grammar (lcg_slp_t)."""
+
+    def __init__(self, handle):
+        self.h = handle
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.lcg_slp_free(self.h)
+            self.h = None
+
+    def free(self):
+        if self.h:
+            lib().lcg_slp_free(self.h)
+            self.h = None
+
+    def size(self):
+        """(rules g, right-hand-side length, strings k)."""
+        g, q, k = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint32()
+        _check(lib().lcg_slp_size(self.h, ctypes.byref(g), ctypes.byref(q), ctypes.byref(k)))
+        return g.value, q.value, k.value
+
+    def stats(self):
+        out = np.zeros(SLP_STATS, np.uint64)
+        _check(lib().lcg_slp_stats(self.h, _ptr(out, ctypes.c_uint64)))
+        return out
+
+    def export(self):
+        """Host copy: {"off", "rhs", "mult", "c", "stats"} (arrays as declared in lcg.h)."""
+        g, q, k = self.size()
+        off = np.zeros(g + 1, np.uint64)
+        rhs = np.zeros(max(q, 1), np.uint32)
+        mult = np.zeros(max(g, 1), np.uint32)
+        c = np.zeros(max(k, 1), np.uint32)
+        _check(lib().lcg_slp_copy(self.h, _ptr(off, ctypes.c_uint64), _ptr(rhs, ctypes.c_uint32),
+                                  _ptr(mult, ctypes.c_uint32), _ptr(c, ctypes.c_uint32)))
+        return {"off": off, "rhs": rhs[:q], "mult": mult[:g], "c": c[:k], "stats": self.stats()}
 
 
 def new(seed):

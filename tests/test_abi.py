@@ -52,6 +52,11 @@ def test_host_only_entry_points(lcgmod):
     with pytest.raises(lcgmod.LcgError) as e:
         lcgmod._check(lcgmod.lib().lcg_level_size(g.h, 1, None, None))
     assert e.value.name == "LCG_EINVAL"
+    # post-processing a grammar without strings is refused before any device work
+    import ctypes
+    h = ctypes.c_void_p()
+    assert lcgmod.lib().lcg_postprocess(g.h, 3, None, ctypes.byref(h)) == -1 and not h.value
+    assert lcgmod.lib().lcg_postprocess(g.h, 8, None, ctypes.byref(h)) == -1
     g.free()
 
 

@@ -1,0 +1,143 @@
+"""Parity of the device post-processing (RL and Simp, Sec. 2.2) with the oracle.
+
+Both sides lay the result out the same way (one id space: terminals, then per
+level the run rules in (symbol, length) order and the level's rules in rank
+order; Simp renumbers the kept rules in that order), so every array is
+compared element by element: offsets, right-hand sides, multiplicities, C and
+the size statistics.  Zero tolerance: it is integer data.
+"""
+import numpy as np
+import pytest
+
+from paper_2411_12439_amd import datagen as D
+
+pytestmark = pytest.mark.gpu
+SEED = D.HASH_SEED
+FLAGS = [(False, False), (True, False), (False, True), (True, True)]
+FLAG_IDS = ["none", "rl", "simp", "rl_simp"]
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2411_12439_amd import lcg
+    lcg.lib()
+    return lcg
+
+
+def _assert_slp_equal(got, want):
+    for key in ("off", "rhs", "mult", "c"):
+        a, b = np.asarray(got[key]), np.asarray(want[key])
+        assert a.shape == b.shape, (key, a.shape, b.shape)
+        if not np.array_equal(a, b):
+            i = int(np.nonzero(a != b)[0][0])
+            raise AssertionError("%s differs first at %d: gpu %d, oracle %d" % (key, i, a[i], b[i]))
+    assert np.asarray(got["stats"]).tolist() == np.asarray(want["stats"]).tolist()
+
+
+def _both(L, text, off, rl, simp, **kw):
+    from oracle import oracle as O
+    t, o = L.to_device(text, off)
+    g = L.build(t, o, seed=SEED, **kw)
+    got = g.postprocess(rl=rl, simp=simp).export()
+    want = O.build(text, off, SEED).postprocess(rl=rl, simp=simp)
+    return got, want
+
+
+@pytest.mark.parametrize("flags", FLAGS, ids=FLAG_IDS)
+@pytest.mark.parametrize("config,scale", [("tiny", 1.0), ("bacterial", 0.01), ("repeats", 0.0005),
+                                          ("batched", 0.0005)])
+def test_configs_equal_oracle(L, config, scale, flags):
+    text, off = D.make_config(config, scale=scale)
+    print("postprocess parity: %s scale %g flags %s" % (config, scale, flags), flush=True)
+    got, want = _both(L, text, off, *flags)
+    _assert_slp_equal(got, want)
+
+
+def _odd_collections():
+    rng = np.random.default_rng(5)
+    dna = lambda n: D.BASES[rng.integers(0, 4, n)].tobytes()
+    base = dna(3000)
+    return {
+        "single_bytes": [b"A", b"C", b"A"],
+        "homopolymers": [b"G" * 2, b"G" * 3, b"T" * 5000, b"GGGG"],
+        "one_string": [dna(20000)],
+        "mixed": [b"A", dna(7), b"CC", base, base[100:2900], base[::-1], b"N" * 300 + base[:500]],
+        "binary_runs": [bytes(rng.choice([65, 67], int(rng.integers(100, 4000))).astype(np.uint8))
+                        for _ in range(12)],
+        "tandem": [b"ACG" * 2000, b"ACGT" * 1000 + b"A" * 700, b"AC" * 3000],
+    }
+
+
+@pytest.mark.parametrize("flags", FLAGS, ids=FLAG_IDS)
+@pytest.mark.parametrize("name", sorted(_odd_collections()))
+def test_edge_collections_equal_oracle(L, name, flags):
+    from oracle import oracle as O
+    text, off = O.pack(_odd_collections()[name])
+    print("postprocess edge case: %s flags %s" % (name, flags), flush=True)
+    got, want = _both(L, text, off, *flags)
+    _assert_slp_equal(got, want)
+
+
+@pytest.mark.parametrize("flags", FLAGS[1:], ids=FLAG_IDS[1:])
+def test_merged_and_plain_grammars(L, flags):
+    """Post-processing a merged grammar and a plain-form grammar equals the
+    oracle's post-processing of the merged oracle grammar."""
+    from oracle import oracle as O
+    text, off = D.make_config("bacterial", scale=0.004)
+    k = len(off) - 1
+    h = k // 2
+    want_g = O.build(text[:off[h]], off[:h + 1], SEED)
+    want_g.merge(O.build(text[off[h]:], off[h:] - off[h], SEED))
+    want = want_g.postprocess(*flags)
+    ta, oa = L.to_device(text[:off[h]], off[:h + 1])
+    tb, ob = L.to_device(text[off[h]:], off[h:] - off[h])
+    ga = L.build(ta, oa, seed=SEED)
+    ga.merge(L.build(tb, ob, seed=SEED))
+    _assert_slp_equal(ga.postprocess(*flags).export(), want)
+    t, o = L.to_device(text, off)
+    gp = L.build(t, o, seed=SEED, mode=L.MODE_PLAIN)
+    _assert_slp_equal(gp.postprocess(*flags).export(),
+                      O.build(text, off, SEED).postprocess(*flags))
+
+
+def test_postprocess_leaves_grammar_unchanged_and_repeats(L):
+    from paper_2411_12439_amd import canon as CN
+    text, off = D.make_config("tiny", scale=0.5)
+    t, o = L.to_device(text, off)
+    g = L.build(t, o, seed=SEED)
+    before = g.export()
+    a = g.postprocess().export()
+    b = g.postprocess().export()
+    _assert_slp_equal(a, b)
+    assert CN.exports_equal(g.export(), before)
+    assert np.array_equal(g.expand(0).cpu().numpy(), text[off[0]:off[1]])
+
+
+def test_rejects_bad_arguments(L):
+    import ctypes
+    text, off = D.make_config("tiny", scale=0.05)
+    t, o = L.to_device(text, off)
+    g = L.build(t, o, seed=SEED)
+    h = ctypes.c_void_p()
+    rc = L.lib().lcg_postprocess(g.h, 4, None, ctypes.byref(h))
+    assert rc == -1 and not h.value
+    rc = L.lib().lcg_postprocess(None, 3, None, ctypes.byref(h))
+    assert rc == -1
+    empty = L.new(SEED)
+    rc = L.lib().lcg_postprocess(empty.h, 3, None, ctypes.byref(h))
+    assert rc == -1
+
+
+def test_full_bacterial_equals_oracle(L):
+    """The benchmark collection (64 strings, ~322 MB): the oracle builds its own
+    grammar and post-processes it; every array must equal the device result."""
+    from oracle import oracle as O
+    text, off = D.make_config("bacterial")
+    print("postprocess parity: full bacterial (oracle build, ~30 s)", flush=True)
+    want = O.build(text, off, SEED).postprocess(rl=True, simp=True)
+    t, o = L.to_device(text, off)
+    g = L.build(t, o, seed=SEED)
+    got = g.postprocess(rl=True, simp=True).export()
+    _assert_slp_equal(got, want)
