@@ -23,6 +23,7 @@
 
 #include <hipcub/hipcub.hpp>
 
+#include <initializer_list>
 #include <memory>
 
 #include "lcg_host.h"
@@ -65,107 +66,282 @@ inline unsigned pgrid(uint64_t n) {
 
 __global__ void k_pp_set(uint64_t* p, uint64_t v) { *p = v; }
 
+// ---------------------------------------------------------------- rule groups
+// Kernels that visit right-hand-side positions take groups of kGrp
+// consecutive rules per block: the group's offsets go to LDS, the block reads
+// the group's positions kGrp at a time (consecutive threads, consecutive
+// positions) and each position finds its rule by binary search in LDS.
+constexpr uint32_t kGrp = 256;
+
+#define GROUP_LOOP(grp, ngroups) for (uint64_t grp = blockIdx.x; grp < (ngroups); grp += gridDim.x)
+
+__device__ __forceinline__ void load_offsets(const uint64_t* __restrict__ off, uint64_t r0, uint32_t n,
+                                             uint64_t* s_off) {
+  for (uint32_t j = threadIdx.x; j <= n; j += blockDim.x) s_off[j] = off[r0 + j];
+  __syncthreads();
+}
+
+// the rule j < n of the group whose positions hold t (s_off[0] <= t < s_off[n])
+__device__ __forceinline__ uint32_t owner_in(const uint64_t* s_off, uint32_t n, uint64_t t) {
+  uint32_t lo = 0;
+  for (uint32_t step = kGrp / 2; step; step >>= 1) {
+    const uint32_t mid = lo + step;
+    if (mid < n && s_off[mid] <= t) lo = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint64_t lower_bound_u64(const uint64_t* a, uint64_t n, uint64_t key) {
+  uint64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
 // ---------------------------------------------------------------- RL
-// head[off[r]] = 1 for every rule r of the level
-__global__ void k_pp_heads(const uint64_t* __restrict__ off, uint32_t u, uint8_t* __restrict__ head) {
-  PP_LOOP(r, u) head[off[r]] = 1;
+// One input level in the global position space (all levels' right-hand sides
+// one after the other).  The second half is filled once the runs are known.
+struct PLevel {
+  const void* rhs;       // uint8 (bytes) or uint32 symbols
+  const uint64_t* off;   // u + 1 offsets
+  uint64_t p0;           // global position of the level's first symbol
+  uint64_t q;
+  uint32_t u;
+  uint32_t gpre;         // first rule group of the level
+  uint32_t bytes;
+  uint32_t symbase;      // id of the level's symbol 0 (0: terminals)
+  uint64_t cpre;         // repeated positions in earlier levels
+  uint64_t out0;         // result position of the level's first ordinary symbol
+  uint32_t rlbase;       // id of its first run rule
+  uint32_t obase;        // id of its rule 0
+  uint32_t upre;         // its first entry in the distinct-run list
+  uint32_t v;            // its run rules
+};
+
+__device__ __forceinline__ uint32_t sym_at(const PLevel& L, uint64_t t) {
+  return L.bytes ? (uint32_t) static_cast<const uint8_t*>(L.rhs)[t]
+                 : static_cast<const uint32_t*>(L.rhs)[t];
 }
 
-// a run starts at a rule's first position and wherever the symbol changes
-template <typename Sym>
-__global__ void k_pp_runflag(const Sym* __restrict__ rhs, uint64_t q, const uint8_t* __restrict__ head,
-                             uint64_t* __restrict__ flag) {
-  PP_LOOP(x, q) flag[x] = (x == 0 || head[x] || rhs[x] != rhs[x - 1]) ? 1 : 0;
+__device__ __forceinline__ uint32_t level_of_group(const PLevel* tab, uint32_t h, uint64_t grp) {
+  uint32_t lv = 0;
+  while (lv + 1 < h && tab[lv + 1].gpre <= grp) ++lv;
+  return lv;
 }
 
-// start[j] = position of run j; start[m] = q
-__global__ void k_pp_runlist(const uint64_t* __restrict__ flag, const uint64_t* __restrict__ ns,
-                             uint64_t q, uint64_t* __restrict__ start) {
-  PP_LOOP(x, q) {
-    if (flag[x]) start[ns[x]] = x;
-    if (x == 0) start[ns[q]] = q;
+__device__ __forceinline__ uint32_t level_of_pos(const PLevel* tab, uint32_t h, uint64_t x) {
+  uint32_t lv = 0;
+  while (lv + 1 < h && tab[lv + 1].p0 <= x) ++lv;
+  return lv;
+}
+
+// A position repeats when it is not its rule's first and holds the same
+// symbol as the position before it; the repeated positions, in order, are the
+// list P that RL works from.
+
+// the block's repeat flags of one chunk of kGrp positions: *excl receives
+// the number of flagged threads before this one, the return value the
+// chunk's total (s_w: kGrp / 64 words of LDS)
+__device__ __forceinline__ uint32_t block_flag_scan(bool f, uint32_t* excl, uint32_t* s_w) {
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint64_t bal = __ballot(f);
+  if (lane == 0) s_w[wv] = (uint32_t)__builtin_popcountll(bal);
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+  for (uint32_t w = 0; w < kGrp / 64; ++w) {
+    const uint32_t c = s_w[w];
+    before += w < wv ? c : 0;
+    total += c;
+  }
+  *excl = before + (uint32_t)__builtin_popcountll(bal & ((1ull << lane) - 1));
+  __syncthreads();  // s_w is rewritten by the next chunk
+  return total;
+}
+
+__device__ __forceinline__ bool repeats_at(const PLevel& L, const uint64_t* s_off, uint32_t n,
+                                           uint64_t t, uint64_t b) {
+  if (t >= b) return false;
+  const uint32_t j = owner_in(s_off, n, t);
+  return t != s_off[j] && sym_at(L, t) == sym_at(L, t - 1);
+}
+
+// repeated positions of every rule group
+__global__ __launch_bounds__(kGrp) void k_pp_repcount(const PLevel* __restrict__ tab, uint32_t h,
+                                                      uint64_t ngroups, uint64_t* __restrict__ gcnt) {
+  __shared__ uint64_t s_off[kGrp + 1];
+  __shared__ uint32_t s_w[kGrp / 64];
+  GROUP_LOOP(grp, ngroups) {
+    const uint32_t lv = level_of_group(tab, h, grp);
+    const PLevel L = tab[lv];
+    const uint64_t r0 = (grp - L.gpre) * kGrp;
+    const uint32_t n = (uint32_t)min<uint64_t>(kGrp, L.u - r0);
+    load_offsets(L.off, r0, n, s_off);
+    const uint64_t a = s_off[0], b = s_off[n];
+    uint64_t total = 0;
+    for (uint64_t base = a; base < b; base += kGrp) {
+      uint32_t excl;
+      total += block_flag_scan(repeats_at(L, s_off, n, base + threadIdx.x, b), &excl, s_w);
+    }
+    if (threadIdx.x == 0) gcnt[grp] = total;
+    __syncthreads();
   }
 }
 
-__global__ void k_pp_longflag(const uint64_t* __restrict__ start, uint64_t m,
-                              uint64_t* __restrict__ lflag) {
-  PP_LOOP(j, m) lflag[j] = (start[j + 1] - start[j] >= 2) ? 1 : 0;
-}
-
-// key of a run of length >= 2: symbol << 32 | length
-template <typename Sym>
-__global__ void k_pp_longkeys(const Sym* __restrict__ rhs, const uint64_t* __restrict__ start,
-                              const uint64_t* __restrict__ lflag, const uint64_t* __restrict__ lpos,
-                              uint64_t m, uint64_t* __restrict__ keys) {
-  PP_LOOP(j, m) {
-    if (!lflag[j]) continue;
-    const uint64_t x = start[j];
-    keys[lpos[j]] = ((uint64_t)(uint32_t)rhs[x] << 32) | (start[j + 1] - x);
+// P[gpos[grp] + ...] = the group's repeated positions (global), in order
+__global__ __launch_bounds__(kGrp) void k_pp_repwrite(const PLevel* __restrict__ tab, uint32_t h,
+                                                      uint64_t ngroups, const uint64_t* __restrict__ gpos,
+                                                      uint64_t* __restrict__ P) {
+  __shared__ uint64_t s_off[kGrp + 1];
+  __shared__ uint32_t s_w[kGrp / 64];
+  GROUP_LOOP(grp, ngroups) {
+    const uint64_t g0 = gpos[grp];
+    if (gpos[grp + 1] == g0) continue;  // no repeats in the group (uniform)
+    const uint32_t lv = level_of_group(tab, h, grp);
+    const PLevel L = tab[lv];
+    const uint64_t r0 = (grp - L.gpre) * kGrp;
+    const uint32_t n = (uint32_t)min<uint64_t>(kGrp, L.u - r0);
+    load_offsets(L.off, r0, n, s_off);
+    const uint64_t a = s_off[0], b = s_off[n];
+    uint64_t done = g0;
+    for (uint64_t base = a; base < b; base += kGrp) {
+      const uint64_t t = base + threadIdx.x;
+      const bool rep = repeats_at(L, s_off, n, t, b);
+      uint32_t excl;
+      const uint32_t tot = block_flag_scan(rep, &excl, s_w);
+      if (rep) P[done + excl] = L.p0 + t;
+      done += tot;
+    }
+    __syncthreads();
   }
 }
 
-__global__ void k_pp_uniqflag(const uint64_t* __restrict__ sorted, uint64_t c,
-                              uint64_t* __restrict__ uflag) {
-  PP_LOOP(j, c) uflag[j] = (j == 0 || sorted[j] != sorted[j - 1]) ? 1 : 0;
+// gpos at the first group of every level, and the total (for the host)
+__global__ void k_pp_level_reps(const PLevel* __restrict__ tab, uint32_t h, uint64_t ngroups,
+                                const uint64_t* __restrict__ gpos, uint64_t* __restrict__ out) {
+  PP_LOOP(i, h + 1) out[i] = gpos[i < h ? tab[i].gpre : ngroups];
 }
 
-__global__ void k_pp_uniqlist(const uint64_t* __restrict__ sorted, const uint64_t* __restrict__ uflag,
-                              const uint64_t* __restrict__ upos, uint64_t c,
-                              uint64_t* __restrict__ uniq) {
-  PP_LOOP(j, c) if (uflag[j]) uniq[upos[j]] = sorted[j];
-}
-
-// the level's right-hand sides after RL: one symbol per run
-template <typename Sym>
-__global__ void k_pp_rl_rhs(const Sym* __restrict__ rhs, const uint64_t* __restrict__ start, uint64_t m,
-                            const uint64_t* __restrict__ uniq, uint64_t v, uint32_t symbase,
-                            uint32_t rlbase, uint32_t* __restrict__ out) {
-  PP_LOOP(j, m) {
-    const uint64_t x = start[j];
-    const uint64_t l = start[j + 1] - x;
-    const uint32_t s = (uint32_t)rhs[x];
-    if (l < 2) {
-      out[j] = symbase + s;
+// Runs from the sorted repeated positions P: a run X^l (l >= 2) starting at s
+// is the group of consecutive entries s+1 .. s+l-1.  At each group's first
+// entry i: rlen[i] = l, and (level, key = X << 32 | l) is appended to the run
+// list; rlen is 0 at the other entries.
+__global__ void k_pp_runs(const PLevel* __restrict__ tab, uint32_t h, const uint64_t* __restrict__ P,
+                          uint64_t c, uint32_t* __restrict__ rlen, uint64_t* __restrict__ rkey,
+                          uint32_t* __restrict__ rlvl, unsigned long long* __restrict__ rcount) {
+  PP_LOOP(i, c) {
+    const uint64_t x = P[i];
+    if (i > 0 && P[i - 1] == x - 1) {
+      rlen[i] = 0;
       continue;
     }
-    const uint64_t key = ((uint64_t)s << 32) | l;
-    uint64_t lo = 0, hi = v;  // first uniq[] >= key (present by construction)
+    // last e >= i with P[e] - x == e - i (P strictly increases, so this holds
+    // exactly on a prefix)
+    uint64_t lo = i, hi = c - 1;
     while (lo < hi) {
-      const uint64_t mid = (lo + hi) >> 1;
-      if (uniq[mid] < key) lo = mid + 1; else hi = mid;
+      const uint64_t mid = (lo + hi + 1) >> 1;
+      if (P[mid] - x == mid - i) lo = mid; else hi = mid - 1;
     }
-    out[j] = rlbase + (uint32_t)lo;
+    const uint64_t l = lo - i + 2;  // < 2^32: a run lies inside one rule
+    rlen[i] = (uint32_t)l;
+    const uint64_t s = x - 1;
+    const uint32_t lv = level_of_pos(tab, h, s);
+    const uint32_t X = sym_at(tab[lv], s - tab[lv].p0);
+    const unsigned long long at = atomicAdd(rcount, 1ull);
+    rkey[at] = ((uint64_t)X << 32) | l;
+    rlvl[at] = lv;
   }
 }
 
-// run rules of the level: rhs = [symbol], mult = length
-__global__ void k_pp_rl_rules(const uint64_t* __restrict__ uniq, uint64_t v, uint32_t symbase,
-                              uint64_t pos0, uint32_t rule0, uint32_t* __restrict__ rhs1,
-                              uint64_t* __restrict__ off1, uint32_t* __restrict__ mult1) {
-  PP_LOOP(j, v) {
-    const uint64_t key = uniq[j];
-    rhs1[pos0 + j] = symbase + (uint32_t)(key >> 32);
-    off1[rule0 + j] = pos0 + j;
-    mult1[rule0 + j] = (uint32_t)key;
+// distinct (level, key) pairs of the sorted run list
+__global__ void k_pp_uniqflag(const uint32_t* __restrict__ lvl, const uint64_t* __restrict__ key,
+                              uint64_t R, uint64_t* __restrict__ flag) {
+  PP_LOOP(j, R) flag[j] = (j == 0 || lvl[j] != lvl[j - 1] || key[j] != key[j - 1]) ? 1 : 0;
+}
+
+__global__ void k_pp_uniqlist(const uint32_t* __restrict__ lvl, const uint64_t* __restrict__ key,
+                              const uint64_t* __restrict__ flag, const uint64_t* __restrict__ pos,
+                              uint64_t R, uint32_t* __restrict__ ulvl, uint64_t* __restrict__ ukey,
+                              unsigned long long* __restrict__ vcnt) {
+  PP_LOOP(j, R) {
+    if (!flag[j]) continue;
+    ulvl[pos[j]] = lvl[j];
+    ukey[pos[j]] = key[j];
+    atomicAdd(&vcnt[lvl[j]], 1ull);
   }
 }
 
-// offsets of the level's ordinary rules (ns: run index of each position, or
-// NULL when runs are kept as they are)
-__global__ void k_pp_ord_off(const uint64_t* __restrict__ off, const uint64_t* __restrict__ ns,
-                             uint32_t u, uint64_t pos0, uint32_t rule0, uint64_t* __restrict__ off1,
-                             uint32_t* __restrict__ mult1) {
-  PP_LOOP(r, u) {
-    const uint64_t x = off[r];
-    off1[rule0 + r] = pos0 + (ns ? ns[x] : x);
-    mult1[rule0 + r] = 1;
+// Every level's ordinary rules after RL: one symbol per maximal run (the run
+// rule's id for a run of length >= 2), the rules' offsets and multiplicities.
+// A group's repeated positions before a position come from gpos and the
+// block's flag prefix; only the first position of a run of length >= 2 looks
+// its length up in P.
+__global__ __launch_bounds__(kGrp) void k_pp_rl_write(const PLevel* __restrict__ tab, uint32_t h,
+                                                      uint64_t ngroups, const uint64_t* __restrict__ gpos,
+                                                      const uint64_t* __restrict__ P, uint64_t c,
+                                                      const uint32_t* __restrict__ rlen,
+                                                      const uint64_t* __restrict__ ukey,
+                                                      uint32_t* __restrict__ rhs1,
+                                                      uint64_t* __restrict__ off1,
+                                                      uint32_t* __restrict__ mult1) {
+  __shared__ uint64_t s_off[kGrp + 1];
+  __shared__ uint32_t s_w[kGrp / 64];
+  GROUP_LOOP(grp, ngroups) {
+    const uint32_t lv = level_of_group(tab, h, grp);
+    const PLevel L = tab[lv];
+    const uint64_t r0 = (grp - L.gpre) * kGrp;
+    const uint32_t n = (uint32_t)min<uint64_t>(kGrp, L.u - r0);
+    load_offsets(L.off, r0, n, s_off);
+    const uint64_t a = s_off[0], b = s_off[n];
+    const bool any = gpos[grp + 1] != gpos[grp];  // uniform
+    uint64_t done = gpos[grp] - L.cpre;           // the level's repeats before the chunk
+    for (uint64_t base = a; base < b; base += kGrp) {
+      const uint64_t t = base + threadIdx.x;
+      const bool valid = t < b;
+      const uint32_t j = valid ? owner_in(s_off, n, t) : 0;
+      bool rep = false;
+      uint32_t excl = 0, tot = 0;
+      if (any) {
+        rep = valid && t != s_off[j] && sym_at(L, t) == sym_at(L, t - 1);
+        tot = block_flag_scan(rep, &excl, s_w);
+      }
+      if (valid && !rep) {
+        const uint64_t out = L.out0 + t - (done + excl);
+        const uint32_t X = sym_at(L, t);
+        uint32_t id = L.symbase + X;
+        // the next position repeats: x starts a run of length >= 2
+        if (c && t + 1 < s_off[j + 1] && sym_at(L, t + 1) == X) {
+          const uint64_t lb = lower_bound_u64(P, c, L.p0 + t + 1);
+          const uint64_t key = ((uint64_t)X << 32) | rlen[lb];
+          id = L.rlbase + (uint32_t)lower_bound_u64(ukey + L.upre, L.v, key);
+        }
+        rhs1[out] = id;
+        if (t == s_off[j]) {
+          off1[L.obase - 256 + r0 + j] = out;
+          mult1[L.obase - 256 + r0 + j] = 1;
+        }
+      }
+      done += tot;
+    }
+    __syncthreads();
   }
 }
 
-template <typename Sym>
-__global__ void k_pp_copy_rhs(const Sym* __restrict__ rhs, uint64_t q, uint32_t symbase,
-                              uint32_t* __restrict__ out) {
-  PP_LOOP(x, q) out[x] = symbase + (uint32_t)rhs[x];
+// the run rules: rhs = [X], mult = l, ahead of their level's ordinary rules
+__global__ void k_pp_rl_rules(const PLevel* __restrict__ tab, const uint32_t* __restrict__ ulvl,
+                              const uint64_t* __restrict__ ukey, uint64_t vt,
+                              uint32_t* __restrict__ rhs1, uint64_t* __restrict__ off1,
+                              uint32_t* __restrict__ mult1) {
+  PP_LOOP(j, vt) {
+    const PLevel& L = tab[ulvl[j]];
+    const uint32_t jl = (uint32_t)j - L.upre;
+    const uint64_t key = ukey[j];
+    const uint64_t pos = L.out0 - L.v + jl;
+    rhs1[pos] = L.symbase + (uint32_t)(key >> 32);
+    off1[L.rlbase - 256 + jl] = pos;
+    mult1[L.rlbase - 256 + jl] = (uint32_t)key;
+  }
 }
 
 // C in global ids (obase[lv]: id of rule 0 of level lv)
@@ -179,33 +355,40 @@ __global__ void k_pp_c_global(const uint8_t* __restrict__ cl, const uint32_t* __
 }
 
 // ---------------------------------------------------------------- Simp
-__device__ __forceinline__ bool pp_removed(const uint32_t* mult1, const uint32_t* occ, uint32_t z) {
-  return mult1[z] == 1 && occ[z] == 1;
-}
+constexpr uint64_t kRemoved = 1ull << 63;
 
-// Occurrences: +1 in an ordinary rule, +2 in a run rule (which pins the
-// symbol).  The first ordinary occurrence records its rule and position; it
-// is the only one when the count ends at 1.
-__global__ void k_pp_occ(const uint64_t* __restrict__ off1, const uint32_t* __restrict__ rhs1,
-                         const uint32_t* __restrict__ mult1, uint32_t g1, uint32_t* occ,
-                         uint32_t* __restrict__ par, uint64_t* __restrict__ at) {
-  PP_LOOP(r, g1) {
-    const bool run = mult1[r] >= 2;
-    const uint64_t b = off1[r + 1];
-    for (uint64_t t = off1[r]; t < b; ++t) {
+// Occurrences over the right-hand sides: +1 in an ordinary rule, +2 in a run
+// rule (which pins the symbol).  Counts stop mattering at 2.  The first
+// ordinary occurrence records its rule and position; it is the only one when
+// the count ends at 1.
+__global__ __launch_bounds__(kGrp) void k_pp_occ(const uint64_t* __restrict__ off1,
+                                                 const uint32_t* __restrict__ rhs1,
+                                                 const uint32_t* __restrict__ mult1, uint32_t g1,
+                                                 uint32_t* occ, uint32_t* __restrict__ par,
+                                                 uint64_t* __restrict__ at) {
+  __shared__ uint64_t s_off[kGrp + 1];
+  __shared__ uint8_t s_run[kGrp];
+  const uint64_t ngroups = (g1 + kGrp - 1) / kGrp;
+  GROUP_LOOP(grp, ngroups) {
+    const uint64_t r0 = grp * kGrp;
+    const uint32_t n = (uint32_t)min<uint64_t>(kGrp, g1 - r0);
+    if (threadIdx.x < n) s_run[threadIdx.x] = mult1[r0 + threadIdx.x] >= 2;
+    load_offsets(off1, r0, n, s_off);
+    const uint64_t a = s_off[0], b = s_off[n];
+    for (uint64_t t = a + threadIdx.x; t < b; t += kGrp) {
       const uint32_t y = rhs1[t];
       if (y < 256) continue;
       const uint32_t z = y - 256;
-      if (run) {
-        atomicAdd(&occ[z], 2u);
-        continue;
-      }
       if (__hip_atomic_load(&occ[z], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= 2) continue;
-      if (atomicAdd(&occ[z], 1u) == 0) {
-        par[z] = (uint32_t)r;
+      const uint32_t j = owner_in(s_off, n, t);
+      if (s_run[j]) {
+        atomicAdd(&occ[z], 2u);
+      } else if (atomicAdd(&occ[z], 1u) == 0) {
+        par[z] = (uint32_t)(r0 + j);
         at[z] = t;
       }
     }
+    __syncthreads();
   }
 }
 
@@ -213,19 +396,34 @@ __global__ void k_pp_occ_c(const uint32_t* __restrict__ c1, uint32_t k, uint32_t
   PP_LOOP(j, k) if (c1[j] >= 256) atomicAdd(&occ[c1[j] - 256], 2u);
 }
 
-// flattened length of the ordinary rules [r0, r1) (lower levels done)
-__global__ void k_pp_flat(const uint64_t* __restrict__ off1, const uint32_t* __restrict__ rhs1,
-                          const uint32_t* __restrict__ mult1, const uint32_t* __restrict__ occ,
-                          uint32_t r0, uint32_t r1, uint64_t* W) {
-  PP_LOOP(i, r1 - r0) {
-    const uint32_t r = r0 + (uint32_t)i;
-    uint64_t w = 0;
-    const uint64_t b = off1[r + 1];
-    for (uint64_t t = off1[r]; t < b; ++t) {
+__device__ __forceinline__ bool pp_removed(const uint32_t* mult1, const uint32_t* occ, uint32_t z) {
+  return mult1[z] == 1 && occ[z] == 1;
+}
+
+// flattened length W of the ordinary rules [rb, re) (one level; the levels
+// below are done): a kept symbol counts 1, a removed one its W
+__global__ __launch_bounds__(kGrp) void k_pp_flat(const uint64_t* __restrict__ off1,
+                                                  const uint32_t* __restrict__ rhs1,
+                                                  const uint32_t* __restrict__ mult1,
+                                                  const uint32_t* __restrict__ occ, uint32_t rb,
+                                                  uint32_t re, uint64_t* W) {
+  __shared__ uint64_t s_off[kGrp + 1];
+  __shared__ unsigned long long s_acc[kGrp];
+  const uint64_t ngroups = (re - rb + kGrp - 1) / kGrp;
+  GROUP_LOOP(grp, ngroups) {
+    const uint64_t r0 = rb + grp * kGrp;
+    const uint32_t n = (uint32_t)min<uint64_t>(kGrp, re - r0);
+    s_acc[threadIdx.x] = 0;
+    load_offsets(off1, r0, n, s_off);
+    const uint64_t a = s_off[0], b = s_off[n];
+    for (uint64_t t = a + threadIdx.x; t < b; t += kGrp) {
       const uint32_t y = rhs1[t];
-      w += (y >= 256 && pp_removed(mult1, occ, y - 256)) ? W[y - 256] : 1;
+      const uint64_t w = (y >= 256 && pp_removed(mult1, occ, y - 256)) ? W[y - 256] : 1;
+      atomicAdd(&s_acc[owner_in(s_off, n, t)], (unsigned long long)w);
     }
-    W[r] = w;
+    __syncthreads();
+    if (threadIdx.x < n) W[r0 + threadIdx.x] = s_acc[threadIdx.x];
+    __syncthreads();
   }
 }
 
@@ -235,83 +433,108 @@ __global__ void k_pp_keep(const uint32_t* __restrict__ mult1, const uint32_t* __
                           uint64_t* __restrict__ len) {
   PP_LOOP(r, g1) {
     const bool run = mult1[r] >= 2;
-    const bool keep = !pp_removed(mult1, occ, (uint32_t)r);
+    const bool keep = run || occ[r] != 1;
     kf[r] = keep ? 1 : 0;
     len[r] = keep ? (run ? 1 : W[r]) : 0;
   }
 }
 
+// per rule: its new id (kept) or kRemoved | W (removed)
+__global__ void k_pp_nw(const uint64_t* __restrict__ kf, const uint64_t* __restrict__ nidx,
+                        const uint64_t* __restrict__ W, uint32_t g1, uint64_t* __restrict__ nw) {
+  PP_LOOP(r, g1) nw[r] = kf[r] ? 256 + nidx[r] : (kRemoved | W[r]);
+}
+
 // weight of every position: 1 for a kept symbol, the flattened length of a removed one
 __global__ void k_pp_weights(const uint32_t* __restrict__ rhs1, uint64_t q1,
-                             const uint32_t* __restrict__ mult1, const uint32_t* __restrict__ occ,
-                             const uint64_t* __restrict__ W, uint64_t* __restrict__ wg) {
+                             const uint64_t* __restrict__ nw, uint64_t* __restrict__ wg) {
   PP_LOOP(t, q1) {
     const uint32_t y = rhs1[t];
-    wg[t] = (y >= 256 && pp_removed(mult1, occ, y - 256)) ? W[y - 256] : 1;
+    uint64_t w = 1;
+    if (y >= 256) {
+      const uint64_t v = nw[y - 256];
+      if (v & kRemoved) w = v & ~kRemoved;
+    }
+    wg[t] = w;
   }
 }
 
-// where the removed rules of [r0, r1) land in the output (upper levels done)
-__global__ void k_pp_base(const uint64_t* __restrict__ off1, const uint32_t* __restrict__ mult1,
-                          const uint32_t* __restrict__ occ, const uint32_t* __restrict__ par,
-                          const uint64_t* __restrict__ at, const uint64_t* __restrict__ sw,
-                          const uint64_t* __restrict__ so, uint32_t r0, uint32_t r1, uint64_t* base) {
-  PP_LOOP(i, r1 - r0) {
-    const uint32_t r = r0 + (uint32_t)i;
-    if (!pp_removed(mult1, occ, r)) continue;
+// where the removed rules of [rb, re) land in the output (upper levels done):
+// the output position of the holder plus the weights before the occurrence
+__global__ void k_pp_base(const uint64_t* __restrict__ off1, const uint64_t* __restrict__ nw,
+                          const uint32_t* __restrict__ par, const uint64_t* __restrict__ at,
+                          const uint64_t* __restrict__ sw, const uint64_t* __restrict__ so,
+                          uint32_t rb, uint32_t re, uint64_t* base) {
+  PP_LOOP(i, re - rb) {
+    const uint32_t r = rb + (uint32_t)i;
+    if (!(nw[r] & kRemoved)) continue;
     const uint32_t p = par[r];
-    const uint64_t dp = pp_removed(mult1, occ, p) ? base[p] : so[p];
+    const uint64_t dp = (nw[p] & kRemoved) ? base[p] : so[p];
     base[r] = dp + sw[at[r]] - sw[off1[p]];
   }
 }
 
-// every kept symbol of every rule at its output position; kept rules' offsets
-// and multiplicities
-__global__ void k_pp_write(const uint64_t* __restrict__ off1, const uint32_t* __restrict__ rhs1,
-                           const uint32_t* __restrict__ mult1, const uint32_t* __restrict__ occ,
-                           const uint64_t* __restrict__ nidx, const uint64_t* __restrict__ so,
-                           const uint64_t* __restrict__ base, const uint64_t* __restrict__ sw,
-                           uint32_t g1, uint32_t* __restrict__ rhs2, uint64_t* __restrict__ off2,
-                           uint32_t* __restrict__ mult2) {
-  PP_LOOP(r, g1) {
-    const bool keep = !pp_removed(mult1, occ, (uint32_t)r);
-    const uint64_t dest = keep ? so[r] : base[r];
-    const uint64_t a = off1[r], b = off1[r + 1];
-    const uint64_t s0 = sw[a];
-    for (uint64_t t = a; t < b; ++t) {
-      const uint32_t y = rhs1[t];
-      if (y < 256) {
-        rhs2[dest + sw[t] - s0] = y;
-      } else if (!pp_removed(mult1, occ, y - 256)) {
-        rhs2[dest + sw[t] - s0] = 256 + (uint32_t)nidx[y - 256];
+// every kept symbol of every rule at its output position; kept rules'
+// offsets and multiplicities
+__global__ __launch_bounds__(kGrp) void k_pp_write(const uint64_t* __restrict__ off1,
+                                                   const uint32_t* __restrict__ rhs1,
+                                                   const uint32_t* __restrict__ mult1,
+                                                   const uint64_t* __restrict__ nw,
+                                                   const uint64_t* __restrict__ so,
+                                                   const uint64_t* __restrict__ base,
+                                                   const uint64_t* __restrict__ sw, uint32_t g1,
+                                                   uint32_t* __restrict__ rhs2,
+                                                   uint64_t* __restrict__ off2,
+                                                   uint32_t* __restrict__ mult2) {
+  __shared__ uint64_t s_off[kGrp + 1];
+  __shared__ uint64_t s_dest[kGrp];  // output position of the rule's first symbol, minus its sw
+  const uint64_t ngroups = (g1 + kGrp - 1) / kGrp;
+  GROUP_LOOP(grp, ngroups) {
+    const uint64_t r0 = grp * kGrp;
+    const uint32_t n = (uint32_t)min<uint64_t>(kGrp, g1 - r0);
+    if (threadIdx.x < n) {
+      const uint64_t r = r0 + threadIdx.x;
+      const uint64_t v = nw[r];
+      const bool keep = !(v & kRemoved);
+      s_dest[threadIdx.x] = (keep ? so[r] : base[r]) - sw[off1[r]];
+      if (keep) {
+        off2[v - 256] = so[r];
+        mult2[v - 256] = mult1[r];
       }
     }
-    if (keep) {
-      off2[nidx[r]] = so[r];
-      mult2[nidx[r]] = mult1[r];
+    load_offsets(off1, r0, n, s_off);
+    const uint64_t a = s_off[0], b = s_off[n];
+    for (uint64_t t = a + threadIdx.x; t < b; t += kGrp) {
+      const uint32_t y = rhs1[t];
+      uint32_t id = y;
+      if (y >= 256) {
+        const uint64_t v = nw[y - 256];
+        if (v & kRemoved) continue;
+        id = (uint32_t)v;
+      }
+      rhs2[s_dest[owner_in(s_off, n, t)] + sw[t]] = id;
     }
-    if (r == 0) off2[nidx[g1]] = so[g1];
+    __syncthreads();
   }
 }
 
 __global__ void k_pp_c_out(const uint32_t* __restrict__ c1, uint32_t k,
-                           const uint64_t* __restrict__ nidx, uint32_t* __restrict__ c2) {
-  PP_LOOP(j, k) c2[j] = c1[j] < 256 ? c1[j] : 256 + (uint32_t)nidx[c1[j] - 256];
+                           const uint64_t* __restrict__ nw, uint32_t* __restrict__ c2) {
+  PP_LOOP(j, k) c2[j] = c1[j] < 256 ? c1[j] : (uint32_t)nw[c1[j] - 256];
 }
 
 // ---------------------------------------------------------------- host
 struct Scan {
   DBuf<uint64_t> tmp;
-  // out[0..n] = exclusive prefix sums of in[0..n); returns the total
-  uint64_t run(const uint64_t* in, uint64_t* out, uint64_t n, hipStream_t s, bool read = true) {
+  // out[0..n] = exclusive prefix sums of in[0..n) (out[n]: the total)
+  void run(const uint64_t* in, uint64_t* out, uint64_t n, hipStream_t s) {
     if (n == 0) {
       k_pp_set<<<1, 1, 0, s>>>(out, 0);
       PP_CHECK("pp_set");
-      return 0;
+      return;
     }
     tmp.need(scan_tmp_words(n), s);
     scan_exclusive(in, out, n, tmp.p, s);
-    return read ? read_dev(out + n, s) : 0;
   }
 };
 
@@ -319,137 +542,156 @@ void zero(void* p, size_t bytes, hipStream_t s) {
   if (bytes) launch_zero(p, (bytes + 3) & ~size_t(3), s);
 }
 
-}  // namespace
-
-// RL of one level into the global arrays.  Returns (runs m, run rules v).
-template <typename Sym>
-static std::pair<uint64_t, uint64_t> rl_level(const Level& L, const Sym* rhs, uint32_t symbase,
-                                              uint64_t pos0, uint32_t rlbase0, Scan& sc,
-                                              DBuf<uint32_t>& rhs1, DBuf<uint64_t>& off1,
-                                              DBuf<uint32_t>& mult1, hipStream_t s) {
-  const uint64_t q = L.q;
-  const uint32_t u = L.u;
-  DBuf<uint8_t> head;
-  DBuf<uint64_t> flag, ns, start;
-  head.need((q + 3) & ~uint64_t(3), s);
-  zero(head.p, q, s);
-  k_pp_heads<<<pgrid(u), kPB, 0, s>>>(L.off.p, u, head.p);
-  PP_CHECK("pp_heads");
-  flag.need(q, s);
-  ns.need(q + 1, s);
-  k_pp_runflag<Sym><<<pgrid(q), kPB, 0, s>>>(rhs, q, head.p, flag.p);
-  PP_CHECK("pp_runflag");
-  const uint64_t m = sc.run(flag.p, ns.p, q, s);
-  start.need(m + 1, s);
-  k_pp_runlist<<<pgrid(q), kPB, 0, s>>>(flag.p, ns.p, q, start.p);
-  PP_CHECK("pp_runlist");
-  // the distinct runs of length >= 2, sorted
-  DBuf<uint64_t> lflag, lpos;
-  lflag.need(m, s);
-  lpos.need(m + 1, s);
-  k_pp_longflag<<<pgrid(m), kPB, 0, s>>>(start.p, m, lflag.p);
-  PP_CHECK("pp_longflag");
-  const uint64_t c = sc.run(lflag.p, lpos.p, m, s);
-  uint64_t v = 0;
-  DBuf<uint64_t> uniq;
-  if (c > 0x7fffffffull) throw LcgError{LCG_EOVERFLOW, "more than 2^31 runs in one level"};
-  if (c) {
-    DBuf<uint64_t> keys, sorted, uflag, upos;
-    keys.need(c, s);
-    sorted.need(c, s);
-    k_pp_longkeys<Sym><<<pgrid(m), kPB, 0, s>>>(rhs, start.p, lflag.p, lpos.p, m, keys.p);
-    PP_CHECK("pp_longkeys");
-    size_t tbytes = 0;
-    HIP_CHECK(hipcub::DeviceRadixSort::SortKeys(nullptr, tbytes, keys.p, sorted.p, (int)c, 0, 64, s));
-    DBuf<uint8_t> tmp;
-    tmp.need(std::max<size_t>(tbytes, 4), s);
-    HIP_CHECK(hipcub::DeviceRadixSort::SortKeys(tmp.p, tbytes, keys.p, sorted.p, (int)c, 0, 64, s));
-    uflag.need(c, s);
-    upos.need(c + 1, s);
-    k_pp_uniqflag<<<pgrid(c), kPB, 0, s>>>(sorted.p, c, uflag.p);
-    PP_CHECK("pp_uniqflag");
-    v = sc.run(uflag.p, upos.p, c, s);
-    uniq.need(v, s);
-    k_pp_uniqlist<<<pgrid(c), kPB, 0, s>>>(sorted.p, uflag.p, upos.p, c, uniq.p);
-    PP_CHECK("pp_uniqlist");
-    k_pp_rl_rules<<<pgrid(v), kPB, 0, s>>>(uniq.p, v, symbase, pos0, rlbase0 - 256, rhs1.p, off1.p,
-                                           mult1.p);
-    PP_CHECK("pp_rl_rules");
-    keys.reset_after(s);
-    sorted.reset_after(s);
-    uflag.reset_after(s);
-    upos.reset_after(s);
-    tmp.reset_after(s);
-  }
-  const uint32_t obase = rlbase0 + (uint32_t)v;
-  k_pp_rl_rhs<Sym><<<pgrid(m), kPB, 0, s>>>(rhs, start.p, m, uniq.p, v, symbase, rlbase0,
-                                            rhs1.p + pos0 + v);
-  PP_CHECK("pp_rl_rhs");
-  k_pp_ord_off<<<pgrid(u), kPB, 0, s>>>(L.off.p, ns.p, u, pos0 + v, obase - 256, off1.p, mult1.p);
-  PP_CHECK("pp_ord_off");
-  head.reset_after(s);
-  flag.reset_after(s);
-  ns.reset_after(s);
-  start.reset_after(s);
-  lflag.reset_after(s);
-  lpos.reset_after(s);
-  uniq.reset_after(s);
-  return {m, v};
+template <typename T>
+void read_many(std::initializer_list<std::pair<const T*, T*>> items, hipStream_t s) {
+  for (auto& it : items)
+    HIP_CHECK(hipMemcpyAsync(it.second, it.first, sizeof(T), hipMemcpyDeviceToHost, s));
+  sync(s);
 }
+
+unsigned groups_grid(uint64_t ngroups) {
+  return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ngroups, 8192));
+}
+
+}  // namespace
 
 static lcg_slp* postprocess_core(lcg_grammar* g, uint32_t flags, hipStream_t s) {
   const bool rl = flags & LCG_PP_RL;
   const bool simp = flags & LCG_PP_SIMP;
-  const size_t h = g->levels.size();
-  uint64_t g0 = 0, q0 = 0;
-  for (const Level& L : g->levels) {
+  const uint32_t h = (uint32_t)g->levels.size();
+  if (h > 63) throw LcgError{LCG_EOVERFLOW, "more than 63 levels"};
+  uint64_t g0 = 0, q0 = 0, ngroups = 0;
+  std::vector<PLevel> tab(std::max<uint32_t>(h, 1));
+  for (uint32_t i = 0; i < h; ++i) {
+    const Level& L = g->levels[i];
+    PLevel& P = tab[i];
+    std::memset(&P, 0, sizeof(P));
+    P.rhs = i == 0 ? (const void*)L.rhs8.p : (const void*)L.rhs32.p;
+    P.off = L.off.p;
+    P.p0 = q0;
+    P.q = L.q;
+    P.u = L.u;
+    P.gpre = (uint32_t)ngroups;
+    P.bytes = i == 0;
+    ngroups += (L.u + kGrp - 1) / kGrp;
     g0 += L.u;
     q0 += L.q;
   }
-  // capacities: RL never adds positions (m + v <= q per level) and adds at
-  // most q/2 run rules per level
+  // capacities: RL never adds positions (runs + run rules <= q per level) and
+  // makes at most q/2 run rules per level
   const uint64_t gcap = g0 + (rl ? q0 / 2 : 0);
   if (256 + gcap >= (1ull << 32)) throw LcgError{LCG_EOVERFLOW, "more than 2^32 - 256 rules"};
-  DBuf<uint32_t> rhs1, mult1, c1;
-  DBuf<uint64_t> off1;
-  rhs1.need(std::max<uint64_t>(q0, 1), s);
-  off1.need(gcap + 1, s);
-  mult1.need(std::max<uint64_t>(gcap, 1), s);
-  Scan sc;
+  DBuf<PLevel> tab_d;
+  tab_d.need(tab.size(), s);
+  HIP_CHECK(hipMemcpyAsync(tab_d.p, tab.data(), tab.size() * sizeof(PLevel), hipMemcpyHostToDevice, s));
+  // repeated positions: per rule group, scanned, then written in order (P)
+  DBuf<uint64_t> gpos, P, ukey;
+  DBuf<uint32_t> rlen, ulvl;
+  gpos.need(ngroups + 1, s);
+  std::vector<uint64_t> hreps(h + 1, 0), hv(64, 0);
+  uint64_t c = 0, vt = 0;
+  if (rl && h) {
+    DBuf<uint64_t> gcnt, lvreps;
+    gcnt.need(std::max<uint64_t>(ngroups, 1), s);
+    k_pp_repcount<<<groups_grid(ngroups), kGrp, 0, s>>>(tab_d.p, h, ngroups, gcnt.p);
+    PP_CHECK("pp_repcount");
+    Scan sc;
+    sc.run(gcnt.p, gpos.p, ngroups, s);
+    lvreps.need(h + 1, s);
+    k_pp_level_reps<<<pgrid(h + 1), kPB, 0, s>>>(tab_d.p, h, ngroups, gpos.p, lvreps.p);
+    PP_CHECK("pp_level_reps");
+    HIP_CHECK(hipMemcpyAsync(hreps.data(), lvreps.p, (h + 1) * 8, hipMemcpyDeviceToHost, s));
+    sync(s);
+    c = hreps[h];
+    if (c) {
+      P.need(c, s);
+      k_pp_repwrite<<<groups_grid(ngroups), kGrp, 0, s>>>(tab_d.p, h, ngroups, gpos.p, P.p);
+      PP_CHECK("pp_repwrite");
+      // cnt: [0] runs of length >= 2, [1 + i] distinct ones of level i
+      DBuf<unsigned long long> cnt;
+      cnt.need(65, s);
+      zero(cnt.p, 65 * 8, s);
+      rlen.need(c, s);
+      DBuf<uint64_t> rkey, k1, k2, uflag, upos;
+      DBuf<uint32_t> rlvl, l1, l2;
+      rkey.need(c, s);
+      rlvl.need(c, s);
+      k_pp_runs<<<pgrid(c), kPB, 0, s>>>(tab_d.p, h, P.p, c, rlen.p, rkey.p, rlvl.p, cnt.p);
+      PP_CHECK("pp_runs");
+      const uint64_t R = read_dev(cnt.p, s);
+      if (R > 0x7fffffffull) throw LcgError{LCG_EOVERFLOW, "more than 2^31 runs"};
+      // sort the runs by (level, key): by key, then stably by level
+      k1.need(R, s);
+      l1.need(R, s);
+      k2.need(R, s);
+      l2.need(R, s);
+      size_t tb = 0, tb2 = 0;
+      HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, rkey.p, k1.p, rlvl.p, l1.p, (int)R,
+                                                   0, 64, s));
+      HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb2, l1.p, l2.p, k1.p, k2.p, (int)R, 0,
+                                                   8, s));
+      tb = std::max(tb, tb2);
+      DBuf<uint8_t> tmp;
+      tmp.need(std::max<size_t>(tb, 4), s);
+      HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(tmp.p, tb, rkey.p, k1.p, rlvl.p, l1.p, (int)R, 0,
+                                                   64, s));
+      HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(tmp.p, tb, l1.p, l2.p, k1.p, k2.p, (int)R, 0, 8,
+                                                   s));
+      uflag.need(R, s);
+      upos.need(R + 1, s);
+      k_pp_uniqflag<<<pgrid(R), kPB, 0, s>>>(l2.p, k2.p, R, uflag.p);
+      PP_CHECK("pp_uniqflag");
+      sc.run(uflag.p, upos.p, R, s);
+      vt = read_dev(upos.p + R, s);
+      ukey.need(vt, s);
+      ulvl.need(vt, s);
+      k_pp_uniqlist<<<pgrid(R), kPB, 0, s>>>(l2.p, k2.p, uflag.p, upos.p, R, ulvl.p, ukey.p,
+                                             cnt.p + 1);
+      PP_CHECK("pp_uniqlist");
+      HIP_CHECK(hipMemcpyAsync(hv.data(), cnt.p + 1, 64 * 8, hipMemcpyDeviceToHost, s));
+      sync(s);
+    }
+  } else {
+    zero(gpos.p, (ngroups + 1) * 8, s);
+  }
+  // id and position bases of every level
   std::vector<uint32_t> obase(h + 1, 0);
-  uint64_t pos = 0;
   uint32_t next = 256;
-  uint64_t runs = 0;
-  for (size_t i = 1; i <= h; ++i) {
-    const Level& L = g->levels[i - 1];
-    const uint32_t symbase = i == 1 ? 0 : obase[i - 1];
-    if (L.u == 0) {
-      obase[i] = next;
-      continue;
-    }
-    uint64_t m = L.q, v = 0;
-    if (rl) {
-      auto mv = i == 1 ? rl_level<uint8_t>(L, L.rhs8.p, symbase, pos, next, sc, rhs1, off1, mult1, s)
-                       : rl_level<uint32_t>(L, L.rhs32.p, symbase, pos, next, sc, rhs1, off1, mult1, s);
-      m = mv.first;
-      v = mv.second;
-    } else {
-      if (i == 1)
-        k_pp_copy_rhs<uint8_t><<<pgrid(L.q), kPB, 0, s>>>(L.rhs8.p, L.q, symbase, rhs1.p + pos);
-      else
-        k_pp_copy_rhs<uint32_t><<<pgrid(L.q), kPB, 0, s>>>(L.rhs32.p, L.q, symbase, rhs1.p + pos);
-      PP_CHECK("pp_copy_rhs");
-      k_pp_ord_off<<<pgrid(L.u), kPB, 0, s>>>(L.off.p, nullptr, L.u, pos, next - 256, off1.p,
-                                               mult1.p);
-      PP_CHECK("pp_ord_off");
-    }
-    obase[i] = next + (uint32_t)v;
-    next = obase[i] + L.u;
-    pos += m + v;
+  uint64_t pos = 0, cpre = 0, upre = 0, runs = 0;
+  for (uint32_t i = 0; i < h; ++i) {
+    PLevel& L = tab[i];
+    const uint64_t reps = hreps[i + 1] - hreps[i], v = hv[i];
+    L.symbase = i == 0 ? 0 : obase[i];
+    L.cpre = cpre;
+    L.upre = (uint32_t)upre;
+    L.v = (uint32_t)v;
+    L.rlbase = next;
+    L.obase = next + (uint32_t)v;
+    L.out0 = pos + v;
+    obase[i + 1] = L.obase;
+    next = L.obase + L.u;
+    pos += v + (L.q - reps);
+    cpre += reps;
+    upre += v;
     runs += v;
   }
   const uint32_t g1 = next - 256;
   const uint64_t q1 = pos;
+  DBuf<uint32_t> rhs1, mult1, c1;
+  DBuf<uint64_t> off1;
+  rhs1.need(std::max<uint64_t>(q1, 1), s);
+  off1.need(g1 + 1, s);
+  mult1.need(std::max<uint32_t>(g1, 1), s);
+  HIP_CHECK(hipMemcpyAsync(tab_d.p, tab.data(), tab.size() * sizeof(PLevel), hipMemcpyHostToDevice, s));
+  if (h) {
+    k_pp_rl_write<<<groups_grid(ngroups), kGrp, 0, s>>>(tab_d.p, h, ngroups, gpos.p, P.p, c,
+                                                        rlen.p, ukey.p, rhs1.p, off1.p, mult1.p);
+    PP_CHECK("pp_rl_write");
+  }
+  if (vt) {
+    k_pp_rl_rules<<<pgrid(vt), kPB, 0, s>>>(tab_d.p, ulvl.p, ukey.p, vt, rhs1.p, off1.p, mult1.p);
+    PP_CHECK("pp_rl_rules");
+  }
   k_pp_set<<<1, 1, 0, s>>>(off1.p + g1, q1);
   PP_CHECK("pp_set");
   DBuf<uint32_t> obase_d;
@@ -485,55 +727,69 @@ static lcg_slp* postprocess_core(lcg_grammar* g, uint32_t flags, hipStream_t s) 
 
   // ---- Simp
   DBuf<uint32_t> occ, par;
-  DBuf<uint64_t> at, W, kf, nidx, len, so, wg, sw, base;
-  occ.need(std::max<uint32_t>(g1, 1), s);
+  DBuf<uint64_t> at, W, kf, nidx, len, so, nw, wg, sw, base;
+  const uint32_t g1c = std::max<uint32_t>(g1, 1);
+  occ.need(g1c, s);
   zero(occ.p, (size_t)g1 * 4, s);
-  par.need(std::max<uint32_t>(g1, 1), s);
-  at.need(std::max<uint32_t>(g1, 1), s);
-  k_pp_occ<<<pgrid(g1), kPB, 0, s>>>(off1.p, rhs1.p, mult1.p, g1, occ.p, par.p, at.p);
-  PP_CHECK("pp_occ");
+  par.need(g1c, s);
+  at.need(g1c, s);
+  const uint64_t ng1 = (g1 + kGrp - 1) / kGrp;
+  if (g1) {
+    k_pp_occ<<<groups_grid(ng1), kGrp, 0, s>>>(off1.p, rhs1.p, mult1.p, g1, occ.p, par.p, at.p);
+    PP_CHECK("pp_occ");
+  }
   k_pp_occ_c<<<pgrid(g->k), kPB, 0, s>>>(c1.p, g->k, occ.p);
   PP_CHECK("pp_occ_c");
-  W.need(std::max<uint32_t>(g1, 1), s);
-  for (size_t i = 1; i <= h; ++i) {
-    const uint32_t u = g->levels[i - 1].u;
+  W.need(g1c, s);
+  for (uint32_t i = 0; i < h; ++i) {
+    const uint32_t u = tab[i].u;
     if (!u) continue;
-    k_pp_flat<<<pgrid(u), kPB, 0, s>>>(off1.p, rhs1.p, mult1.p, occ.p, obase[i] - 256,
-                                        obase[i] - 256 + u, W.p);
+    const uint32_t rb = tab[i].obase - 256;
+    k_pp_flat<<<groups_grid((u + kGrp - 1) / kGrp), kGrp, 0, s>>>(off1.p, rhs1.p, mult1.p, occ.p,
+                                                                    rb, rb + u, W.p);
     PP_CHECK("pp_flat");
   }
-  kf.need(std::max<uint32_t>(g1, 1), s);
-  len.need(std::max<uint32_t>(g1, 1), s);
+  kf.need(g1c, s);
+  len.need(g1c, s);
   nidx.need(g1 + 1, s);
   so.need(g1 + 1, s);
   k_pp_keep<<<pgrid(g1), kPB, 0, s>>>(mult1.p, occ.p, W.p, g1, kf.p, len.p);
   PP_CHECK("pp_keep");
-  const uint32_t g2 = (uint32_t)sc.run(kf.p, nidx.p, g1, s);
-  const uint64_t q2 = sc.run(len.p, so.p, g1, s);
+  Scan sc;
+  sc.run(kf.p, nidx.p, g1, s);
+  sc.run(len.p, so.p, g1, s);
+  nw.need(g1c, s);
+  k_pp_nw<<<pgrid(g1), kPB, 0, s>>>(kf.p, nidx.p, W.p, g1, nw.p);
+  PP_CHECK("pp_nw");
   wg.need(std::max<uint64_t>(q1, 1), s);
   sw.need(q1 + 1, s);
-  k_pp_weights<<<pgrid(q1), kPB, 0, s>>>(rhs1.p, q1, mult1.p, occ.p, W.p, wg.p);
+  k_pp_weights<<<pgrid(q1), kPB, 0, s>>>(rhs1.p, q1, nw.p, wg.p);
   PP_CHECK("pp_weights");
-  sc.run(wg.p, sw.p, q1, s, false);
-  base.need(std::max<uint32_t>(g1, 1), s);
-  for (size_t i = h; i >= 1; --i) {
-    const uint32_t u = g->levels[i - 1].u;
+  sc.run(wg.p, sw.p, q1, s);
+  base.need(g1c, s);
+  for (uint32_t i = h; i-- > 0;) {
+    const uint32_t u = tab[i].u;
     if (!u) continue;
-    k_pp_base<<<pgrid(u), kPB, 0, s>>>(off1.p, mult1.p, occ.p, par.p, at.p, sw.p, so.p,
-                                        obase[i] - 256, obase[i] - 256 + u, base.p);
+    const uint32_t rb = tab[i].obase - 256;
+    k_pp_base<<<pgrid(u), kPB, 0, s>>>(off1.p, nw.p, par.p, at.p, sw.p, so.p, rb, rb + u, base.p);
     PP_CHECK("pp_base");
   }
-  out->g = g2;
+  uint64_t g2 = 0, q2 = 0;
+  read_many<uint64_t>({{nidx.p + g1, &g2}, {so.p + g1, &q2}}, s);
+  out->g = (uint32_t)g2;
   out->q = q2;
   out->off.need(g2 + 1, s);
   out->rhs.need(std::max<uint64_t>(q2, 1), s);
-  out->mult.need(std::max<uint32_t>(g2, 1), s);
+  out->mult.need(std::max<uint64_t>(g2, 1), s);
   out->c.need(std::max<uint32_t>(g->k, 1), s);
-  k_pp_write<<<pgrid(g1), kPB, 0, s>>>(off1.p, rhs1.p, mult1.p, occ.p, nidx.p, so.p, base.p, sw.p,
-                                        g1, out->rhs.p, out->off.p, out->mult.p);
-  PP_CHECK("pp_write");
-  if (g1 == 0) k_pp_set<<<1, 1, 0, s>>>(out->off.p, 0);
-  k_pp_c_out<<<pgrid(g->k), kPB, 0, s>>>(c1.p, g->k, nidx.p, out->c.p);
+  if (g1) {
+    k_pp_write<<<groups_grid(ng1), kGrp, 0, s>>>(off1.p, rhs1.p, mult1.p, nw.p, so.p, base.p, sw.p,
+                                                 g1, out->rhs.p, out->off.p, out->mult.p);
+    PP_CHECK("pp_write");
+  }
+  k_pp_set<<<1, 1, 0, s>>>(out->off.p + g2, q2);
+  PP_CHECK("pp_set");
+  k_pp_c_out<<<pgrid(g->k), kPB, 0, s>>>(c1.p, g->k, nw.p, out->c.p);
   PP_CHECK("pp_c_out");
   st[5] = g1 - g2;
   st[6] = g2;
