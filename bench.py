@@ -276,6 +276,36 @@ def main():
         g.expand_strings()
         torch.cuda.synchronize()
         xs.append(time.perf_counter() - t0)
+    # post-processing of the same grammar: RL, then Simp (Sec. 2.2, Sec. 4),
+    # with the size statistics of the paper's Table 2
+    sizes = g.level_sizes()
+    g.postprocess().free()
+    pps = []
+    for i in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = g.postprocess()
+        torch.cuda.synchronize()
+        pps.append(time.perf_counter() - t0)
+        st = [int(x) for x in p.stats()]
+        g_out, q_out, k_out = p.size()
+        p.free()
+    pp_in = sum(q * (1 if i == 0 else 4) + (u + 1) * 8 for i, (u, q) in enumerate(sizes)) + 5 * k
+    pp_out = q_out * 4 + (g_out + 1) * 8 + g_out * 4 + k_out * 4
+    pp_s = float(np.mean(pps))
+    out["postprocess"] = {
+        "what": "lcg_postprocess (RL, then Simp) of the collection's grammar on the device",
+        "ms": round(pp_s * 1e3, 3),
+        "alg_bytes": pp_in + pp_out,
+        "alg_gbps": round((pp_in + pp_out) / pp_s / 1e9, 2),
+        "rules_in": st[0], "size_in": st[1], "run_rules": st[2], "rules_out": st[6],
+        "size_out": st[7],
+        "rl_nonterminal_increase_pct": round(100.0 * st[2] / st[0], 4),
+        "rl_size_reduction_pct": round(100.0 * (st[1] - st[4]) / st[1], 3),
+        "simp_deleted_rules_pct": round(100.0 * st[5] / st[3], 3),
+        "simp_size_reduction_pct": round(100.0 * (st[4] - st[7]) / st[4], 3)}
+    print("[bench] postprocess (RL + Simp): %.2f ms, %s" % (pp_s * 1e3, st), file=sys.stderr,
+          flush=True)
     g.free()
     del out_t, offs_t
     out["expand"] = {"what": "lcg_expand_strings of all strings (decompression), output bytes/s",
