@@ -290,6 +290,21 @@ def main():
         st = [int(x) for x in p.stats()]
         g_out, q_out, k_out = p.size()
         p.free()
+    # decompression of the post-processed grammar (the stored form)
+    p = g.postprocess()
+    sout, _ = p.expand_strings()
+    torch.cuda.synchronize()
+    if not torch.equal(sout, t):
+        raise SystemExit("the post-processed grammar does not decompress to the input")
+    del sout
+    sxs = []
+    for i in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.expand_strings()
+        torch.cuda.synchronize()
+        sxs.append(time.perf_counter() - t0)
+    p.free()
     pp_in = sum(q * (1 if i == 0 else 4) + (u + 1) * 8 for i, (u, q) in enumerate(sizes)) + 5 * k
     pp_out = q_out * 4 + (g_out + 1) * 8 + g_out * 4 + k_out * 4
     pp_s = float(np.mean(pps))
@@ -303,7 +318,9 @@ def main():
         "rl_nonterminal_increase_pct": round(100.0 * st[2] / st[0], 4),
         "rl_size_reduction_pct": round(100.0 * (st[1] - st[4]) / st[1], 3),
         "simp_deleted_rules_pct": round(100.0 * st[5] / st[3], 3),
-        "simp_size_reduction_pct": round(100.0 * (st[4] - st[7]) / st[4], 3)}
+        "simp_size_reduction_pct": round(100.0 * (st[4] - st[7]) / st[4], 3),
+        "expand_ms": round(float(np.mean(sxs)) * 1e3, 3),
+        "expand_gbps": round(n / float(np.mean(sxs)) / 1e9, 3)}
     print("[bench] postprocess (RL + Simp): %.2f ms, %s" % (pp_s * 1e3, st), file=sys.stderr,
           flush=True)
     g.free()

@@ -257,6 +257,18 @@ lcg_status lcg_slp_device(lcg_slp_t p, const uint64_t** d_off, const uint32_t** 
 /* Host copies of the same arrays (caller-sized; any pointer may be NULL). */
 lcg_status lcg_slp_copy(lcg_slp_t p, uint64_t* h_off, uint32_t* h_rhs, uint32_t* h_mult,
                         uint32_t* h_c);
+/*
+ * Decompression of the post-processed grammar: exp(C[j]) for j0 <= j < j1,
+ * one after the other in d_out (device, cap bytes); d_offsets (device
+ * uint64[j1-j0+1], may be NULL) receives where each string starts and the
+ * total; *total the number of bytes.  With cap smaller than the total the
+ * call returns LCG_EINVAL after setting *total (query with d_out = NULL,
+ * cap = 0).  The rules' expansion lengths are computed on the first call and
+ * kept with p.  Synchronises the stream.
+ */
+lcg_status lcg_slp_expand_strings(lcg_slp_t p, uint32_t j0, uint32_t j1, uint8_t* d_out,
+                                  uint64_t cap, uint64_t* d_offsets, uint64_t* total,
+                                  hipStream_t stream);
 void lcg_slp_free(lcg_slp_t p);
 
 /* Return the library's cached free device blocks to the driver. */

@@ -234,6 +234,8 @@ struct lcg_grammar {
   uint64_t version = 0;  // changes whenever the grammar does
   // expansion lengths in bytes of every rule, per level (for lcg_expand_strings)
   std::vector<lcg::DBuf<uint64_t>> explen;
+  // per rule of levels >= 3: the summed right-hand-side lengths of its children
+  std::vector<lcg::DBuf<uint64_t>> gc;
   lcg::DBuf<const uint64_t*> explen_ptrs;
   uint64_t explen_version = ~0ull;
   explicit lcg_grammar(uint64_t s) : seed(s), H(s) {}

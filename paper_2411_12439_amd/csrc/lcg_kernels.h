@@ -134,11 +134,18 @@ void launch_xs_enter(const uint8_t* c_level, const uint32_t* c_sym, uint32_t ks,
 // *total += children of the m items (must be zeroed by the caller)
 void launch_xs_count(const uint32_t* sym, uint64_t m, const uint64_t* rule_off, uint64_t* total,
                      hipStream_t s);
-// Items -> children (or bytes); *gcount += grandchildren (the children's
-// right-hand-side lengths under rule_off_below, when given).
+// Items -> children (or bytes); *gcount += grandchildren (gc_rule[r] per
+// item, when given).
 void launch_xs_expand(bool to_bytes, const uint32_t* sym, const uint64_t* pos, uint64_t m,
                       const uint64_t* rule_off, const void* rule_rhs, const uint64_t* e_below,
-                      const uint64_t* rule_off_below, uint32_t* nsym, uint64_t* npos,
+                      const uint64_t* gc_rule, uint32_t* nsym, uint64_t* npos,
                       uint64_t* ncount, uint64_t* gcount, uint8_t* out, hipStream_t s);
+// Level-2 items -> the bytes of their level-1 children, in place.
+void launch_xs_bytes2(const uint32_t* sym, const uint64_t* pos, uint64_t m, const uint64_t* off2,
+                      const uint32_t* rhs2, const uint64_t* off1, const uint8_t* rhs1, uint8_t* out,
+                      hipStream_t s);
+// per rule of a level >= 2: the summed right-hand-side lengths of its children
+void launch_gc(const uint64_t* rule_off, const uint32_t* rhs, const uint64_t* off_below, uint32_t u,
+               uint64_t* gc, hipStream_t s);
 
 }  // namespace lcg

@@ -1707,76 +1707,116 @@ __global__ __launch_bounds__(256) void k_xs_count(const uint32_t* __restrict__ s
 }
 
 // the level's items -> their children (TO_BYTES: level 1 -> bytes at their
-// positions).  A block takes kBlock items, scans their right-hand-side
-// lengths in LDS, reserves its children with one atomicAdd and then writes
-// them child-parallel (thread j: children j, j + kBlock, ...; the parent by
-// binary search over the block's scan), so that stores are coalesced.  The
-// grandchildren (children of the written children) are counted on the way
-// into *gcount, which sizes the next level (rule_off_below: the rules of the
-// children's level; NULL below level 2).
+// positions).  One thread per item: a block scan of the items' right-hand-side
+// lengths and one atomicAdd per block reserve the children, which each thread
+// then writes in order with their positions (the item's position plus the
+// expansion lengths of the siblings before).  The grandchildren are counted
+// on the way into *gcount from gc_rule (per rule: the right-hand-side lengths
+// of its children summed; NULL when the children are level-1 rules).
 template <bool TO_BYTES>
 __global__ __launch_bounds__(kBlock) void k_xs_expand(const uint32_t* __restrict__ sym,
                                                       const uint64_t* __restrict__ pos, uint64_t m,
                                                       const uint64_t* __restrict__ rule_off,
                                                       const void* __restrict__ rule_rhs,
                                                       const uint64_t* __restrict__ e_below,
-                                                      const uint64_t* __restrict__ rule_off_below,
+                                                      const uint64_t* __restrict__ gc_rule,
                                                       uint32_t* __restrict__ nsym,
                                                       uint64_t* __restrict__ npos,
                                                       unsigned long long* __restrict__ ncount,
                                                       unsigned long long* __restrict__ gcount,
                                                       uint8_t* __restrict__ out) {
   __shared__ unsigned long long s_wave[kBlock / 64];
-  __shared__ unsigned long long s_excl[kBlock + 1];
-  __shared__ uint64_t s_a[kBlock];
-  __shared__ uint64_t s_p[kBlock];
   __shared__ unsigned long long s_base;
   unsigned long long gc = 0;
   for (uint64_t b0 = blockIdx.x * (uint64_t)kBlock; b0 < m; b0 += (uint64_t)gridDim.x * kBlock) {
     const uint64_t i = b0 + threadIdx.x;
     uint64_t a = 0, q = 0, p = 0;
+    uint32_t r = 0;
     if (i < m) {
-      const uint32_t r = sym[i];
+      r = sym[i];
       p = pos[i];
       a = rule_off[r];
       q = rule_off[r + 1] - a;
     }
-    unsigned long long tot = 0;
-    const unsigned long long excl = block_excl_scan<unsigned long long>(q, s_wave, &tot);
-    s_excl[threadIdx.x] = excl;
-    s_a[threadIdx.x] = a;
-    s_p[threadIdx.x] = p;
-    if (threadIdx.x == 0) {
-      s_excl[kBlock] = tot;
-      if constexpr (!TO_BYTES) s_base = atomicAdd(ncount, tot);
-    }
-    __syncthreads();
-    for (unsigned long long c = threadIdx.x; c < tot; c += kBlock) {
-      // parent: the largest j with s_excl[j] <= c (items with q = 0 are skipped)
-      uint32_t lo = 0, hi = kBlock - 1;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (s_excl[mid] <= c) lo = mid; else hi = mid - 1;
+    if constexpr (TO_BYTES) {
+      const uint8_t* rhs = static_cast<const uint8_t*>(rule_rhs) + a;
+      for (uint64_t k = 0; k < q; ++k) out[p + k] = rhs[k];
+    } else {
+      if (i < m && gc_rule) gc += gc_rule[r];
+      unsigned long long tot = 0;
+      const unsigned long long excl = block_excl_scan<unsigned long long>(q, s_wave, &tot);
+      if (threadIdx.x == 0) s_base = atomicAdd(ncount, tot);
+      __syncthreads();
+      const uint64_t o = s_base + excl;
+      const uint32_t* rhs = static_cast<const uint32_t*>(rule_rhs) + a;
+      uint64_t pp = p;
+      for (uint64_t k = 0; k < q; ++k) {
+        const uint32_t ch = rhs[k];
+        nsym[o + k] = ch;
+        npos[o + k] = pp;
+        pp += e_below[ch];
       }
-      const uint64_t t = c - s_excl[lo];
-      if constexpr (TO_BYTES) {
-        out[s_p[lo] + t] = static_cast<const uint8_t*>(rule_rhs)[s_a[lo] + t];
-      } else {
-        const uint32_t* rhs = static_cast<const uint32_t*>(rule_rhs) + s_a[lo];
-        uint64_t pp = s_p[lo];
-        for (uint64_t x = 0; x < t; ++x) pp += e_below[rhs[x]];
-        const uint32_t ch = rhs[t];
-        nsym[s_base + c] = ch;
-        npos[s_base + c] = pp;
-        if (rule_off_below) gc += rule_off_below[ch + 1] - rule_off_below[ch];
-      }
+      __syncthreads();  // s_base is rewritten by the next iteration
     }
-    __syncthreads();  // the LDS arrays are rewritten by the next iteration
   }
   if constexpr (!TO_BYTES) {
     gc = wave_sum(gc);
     if ((threadIdx.x & 63) == 0 && gc && gcount) atomicAdd(gcount, gc);
   }
+}
+
+// level-2 items -> bytes: each child (a level-1 rule) has its bytes copied in
+// place, so the level-1 occurrences are never materialised as items
+__global__ __launch_bounds__(kBlock) void k_xs_bytes2(const uint32_t* __restrict__ sym,
+                                                      const uint64_t* __restrict__ pos, uint64_t m,
+                                                      const uint64_t* __restrict__ off2,
+                                                      const uint32_t* __restrict__ rhs2,
+                                                      const uint64_t* __restrict__ off1,
+                                                      const uint8_t* __restrict__ rhs1,
+                                                      uint8_t* __restrict__ out) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < m;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t r = sym[i];
+    uint64_t p = pos[i];
+    const uint64_t b = off2[r + 1];
+    for (uint64_t t = off2[r]; t < b; ++t) {
+      const uint32_t c = rhs2[t];
+      const uint64_t b1 = off1[c + 1];
+      for (uint64_t x = off1[c]; x < b1; ++x) out[p++] = rhs1[x];
+    }
+  }
+}
+
+void launch_xs_bytes2(const uint32_t* sym, const uint64_t* pos, uint64_t m, const uint64_t* off2,
+                      const uint32_t* rhs2, const uint64_t* off1, const uint8_t* rhs1, uint8_t* out,
+                      hipStream_t s) {
+  if (!m) return;
+  unsigned g = grid_for(m, kBlock);
+  const unsigned r = resident_blocks((const void*)k_xs_bytes2, kBlock);
+  if (g > r) g = r;
+  k_xs_bytes2<<<g, kBlock, 0, s>>>(sym, pos, m, off2, rhs2, off1, rhs1, out);
+  LCG_LAUNCH_CHECK("xs_bytes2");
+}
+
+// per rule of a level L >= 2: the summed right-hand-side lengths of its
+// children (rules of level L-1, offsets off_below)
+__global__ void k_gc(const uint64_t* __restrict__ rule_off, const uint32_t* __restrict__ rhs,
+                     const uint64_t* __restrict__ off_below, uint32_t u, uint64_t* __restrict__ gc) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= u) return;
+  uint64_t sum = 0;
+  for (uint64_t t = rule_off[r]; t < rule_off[r + 1]; ++t) {
+    const uint32_t c = rhs[t];
+    sum += off_below[c + 1] - off_below[c];
+  }
+  gc[r] = sum;
+}
+
+void launch_gc(const uint64_t* rule_off, const uint32_t* rhs, const uint64_t* off_below, uint32_t u,
+               uint64_t* gc, hipStream_t s) {
+  if (!u) return;
+  k_gc<<<grid_for(u, 256), 256, 0, s>>>(rule_off, rhs, off_below, u, gc);
+  LCG_LAUNCH_CHECK("gc");
 }
 
 void launch_xs_strlen(const uint8_t* c_level, const uint32_t* c_sym, uint32_t ks,
@@ -1806,7 +1846,7 @@ void launch_xs_count(const uint32_t* sym, uint64_t m, const uint64_t* rule_off, 
 
 void launch_xs_expand(bool to_bytes, const uint32_t* sym, const uint64_t* pos, uint64_t m,
                       const uint64_t* rule_off, const void* rule_rhs, const uint64_t* e_below,
-                      const uint64_t* rule_off_below, uint32_t* nsym, uint64_t* npos,
+                      const uint64_t* gc_rule, uint32_t* nsym, uint64_t* npos,
                       uint64_t* ncount, uint64_t* gcount, uint8_t* out, hipStream_t s) {
   if (!m) return;
   unsigned g = grid_for(m, kBlock);
@@ -1817,10 +1857,10 @@ void launch_xs_expand(bool to_bytes, const uint32_t* sym, const uint64_t* pos, u
   auto gc = reinterpret_cast<unsigned long long*>(gcount);
   if (to_bytes)
     k_xs_expand<true><<<g, kBlock, 0, s>>>(sym, pos, m, rule_off, rule_rhs, e_below,
-                                           rule_off_below, nsym, npos, nc, gc, out);
+                                           gc_rule, nsym, npos, nc, gc, out);
   else
     k_xs_expand<false><<<g, kBlock, 0, s>>>(sym, pos, m, rule_off, rule_rhs, e_below,
-                                            rule_off_below, nsym, npos, nc, gc, out);
+                                            gc_rule, nsym, npos, nc, gc, out);
   LCG_LAUNCH_CHECK("xs_expand");
 }
 

@@ -38,6 +38,19 @@ struct lcg_slp {
   lcg::DBuf<uint32_t> mult;  // g
   lcg::DBuf<uint32_t> c;     // k
   uint64_t stats[LCG_SLP_STATS] = {};
+  // id blocks in dependency order (per input level: its run rules, then its
+  // ordinary rules): rules of a block refer only to earlier blocks
+  std::vector<uint32_t> bounds;
+  // for the expansion, computed on first use: expansion length E and number of
+  // nonterminals NT of every rule's right-hand side
+  lcg::DBuf<uint64_t> E;
+  lcg::DBuf<uint32_t> nt;
+  // per right-hand-side position t of rule r (prefix sums over all positions;
+  // subtract the value at off[r]): S = expansion bytes before t, N = item
+  // children (nonterminals that are not leaves) before t
+  lcg::DBuf<uint64_t> S, N;
+  lcg::DBuf<uint8_t> meta;  // RuleMeta per rule
+  bool lens_ready = false;
 };
 
 namespace lcg {
@@ -523,6 +536,206 @@ __global__ void k_pp_c_out(const uint32_t* __restrict__ c1, uint32_t k,
   PP_LOOP(j, k) c2[j] = c1[j] < 256 ? c1[j] : (uint32_t)nw[c1[j] - 256];
 }
 
+// out[i] = a[ids[i] - 256]
+__global__ void k_pp_gather(const uint64_t* __restrict__ a, const uint32_t* __restrict__ ids,
+                            uint32_t n, uint64_t* __restrict__ out) {
+  PP_LOOP(i, n) out[i] = a[ids[i] - 256];
+}
+
+// ---------------------------------------------------------------- expansion
+// E and NT of the rules [r0, r1) (earlier blocks done)
+__global__ void k_slp_lens(const uint64_t* __restrict__ off, const uint32_t* __restrict__ rhs,
+                           const uint32_t* __restrict__ mult, uint32_t r0, uint32_t r1,
+                           uint64_t* E, uint32_t* nt) {
+  PP_LOOP(i, r1 - r0) {
+    const uint32_t r = r0 + (uint32_t)i;
+    uint64_t e = 0;
+    uint32_t c = 0;
+    const uint64_t b = off[r + 1];
+    for (uint64_t t = off[r]; t < b; ++t) {
+      const uint32_t y = rhs[t];
+      if (y < 256) {
+        e += 1;
+      } else {
+        e += E[y - 256];
+        ++c;
+      }
+    }
+    E[r] = e * mult[r];
+    nt[r] = c;
+  }
+}
+
+__global__ void k_slp_strlen(const uint32_t* __restrict__ c, uint32_t ks,
+                             const uint64_t* __restrict__ E, uint64_t* __restrict__ len) {
+  PP_LOOP(j, ks) len[j] = c[j] < 256 ? 1 : E[c[j] - 256];
+}
+
+// strings whose C entry is a rule become items; a terminal is written at once
+__global__ void k_slp_enter(const uint32_t* __restrict__ c, uint32_t ks,
+                            const uint64_t* __restrict__ str_off, uint32_t* __restrict__ sym,
+                            uint64_t* __restrict__ pos, unsigned long long* __restrict__ count,
+                            uint8_t* __restrict__ out) {
+  PP_LOOP(j, ks) {
+    const uint32_t y = c[j];
+    if (y < 256) {
+      out[str_off[j]] = (uint8_t)y;
+      continue;
+    }
+    const unsigned long long at = atomicAdd(count, 1ull);
+    sym[at] = y;
+    pos[at] = str_off[j];
+  }
+}
+
+// A leaf is a rule whose right-hand side is all terminals and whose expansion
+// is at most kLeaf bytes: its parent writes those bytes itself instead of
+// making it an item of the next step.
+constexpr uint64_t kLeaf = 64;
+
+struct RuleMeta {
+  uint64_t a;       // first right-hand-side position
+  uint64_t period;  // E / mult
+  uint64_t sa, na;  // S[a], N[a]
+  uint32_t q, mult;
+  uint32_t ntx;     // item children per repetition
+  uint32_t leaf;
+};
+
+// per position: its expansion bytes and whether it is an item child
+__global__ void k_slp_posw(const uint32_t* __restrict__ rhs, uint64_t q,
+                           const uint64_t* __restrict__ E, const uint32_t* __restrict__ nt,
+                           uint64_t* __restrict__ we, uint64_t* __restrict__ wn) {
+  PP_LOOP(t, q) {
+    const uint32_t y = rhs[t];
+    if (y < 256) {
+      we[t] = 1;
+      wn[t] = 0;
+    } else {
+      const uint64_t e = E[y - 256];
+      we[t] = e;
+      wn[t] = (nt[y - 256] == 0 && e <= kLeaf) ? 0 : 1;
+    }
+  }
+}
+
+__global__ void k_slp_meta(const uint64_t* __restrict__ off, const uint32_t* __restrict__ mult,
+                           const uint32_t* __restrict__ nt, const uint64_t* __restrict__ E,
+                           const uint64_t* __restrict__ S, const uint64_t* __restrict__ N, uint32_t g,
+                           RuleMeta* __restrict__ meta) {
+  PP_LOOP(r, g) {
+    RuleMeta mt;
+    mt.a = off[r];
+    const uint64_t b = off[r + 1];
+    mt.q = (uint32_t)(b - mt.a);
+    mt.mult = mult[r];
+    mt.period = E[r] / mt.mult;
+    mt.sa = S[mt.a];
+    mt.na = N[mt.a];
+    mt.ntx = (uint32_t)(N[b] - mt.na);
+    mt.leaf = nt[r] == 0 && E[r] <= kLeaf;
+    meta[r] = mt;
+  }
+}
+
+// Per item, once: its child counts (all: mult * |rhs|; items: mult * ntx) and
+// what its children need: the rule's first position, |rhs|, ntx, the period,
+// the item's position minus S[a] and N[a].
+struct SlpItem {
+  uint64_t a, period, pos_s, na;
+  uint32_t q, nt;
+};
+
+__global__ void k_slp_count(const uint32_t* __restrict__ sym, const uint64_t* __restrict__ pos,
+                            uint64_t m, const RuleMeta* __restrict__ meta,
+                            uint64_t* __restrict__ cnt, uint64_t* __restrict__ ntc,
+                            SlpItem* __restrict__ items) {
+  PP_LOOP(i, m) {
+    const RuleMeta mt = meta[sym[i] - 256];
+    cnt[i] = (uint64_t)mt.mult * mt.q;
+    ntc[i] = (uint64_t)mt.mult * mt.ntx;
+    SlpItem it;
+    it.a = mt.a;
+    it.period = mt.period;
+    it.pos_s = pos[i] - mt.sa;
+    it.na = mt.na;
+    it.q = mt.q;
+    it.nt = mt.ntx;
+    items[i] = it;
+  }
+}
+
+// One step, balanced over children: block b takes children [b*kChunk,
+// (b+1)*kChunk) of the items' concatenated child lists (cbase: exclusive scan
+// of the per-item child counts), finds each child's item by binary search over
+// the chunk's item bounds in LDS, and computes the child from S and N:
+// repetition rep = v / q and position k = v % q inside the item's rule give its
+// byte position (item position + rep * period + S - S[a]) and, for an item
+// child, its slot among the next step's items (nbase + rep * ntx + N - N[a]).
+// Terminals and leaves are written to out.
+constexpr uint32_t kChunk = 2048;
+__global__ __launch_bounds__(kPB) void k_slp_children(
+    const SlpItem* __restrict__ items, uint64_t m, const uint64_t* __restrict__ cbase,
+    const uint64_t* __restrict__ nbase, uint64_t total, const uint32_t* __restrict__ rhs,
+    const uint64_t* __restrict__ S, const uint64_t* __restrict__ N,
+    const RuleMeta* __restrict__ meta, uint32_t* __restrict__ nsym, uint64_t* __restrict__ npos,
+    uint8_t* __restrict__ out) {
+  __shared__ uint64_t s_cb[kChunk + 1];
+  __shared__ uint64_t s_i0, s_n;
+  const uint64_t nchunks = (total + kChunk - 1) / kChunk;
+  for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const uint64_t c0 = ch * kChunk;
+    const uint64_t c1 = min<uint64_t>(c0 + kChunk, total);
+    if (threadIdx.x == 0) {
+      // items holding children c0 and c1 - 1: the last i with cbase[i] <= c
+      uint64_t lo = 0, hi = m - 1;
+      while (lo < hi) {
+        const uint64_t mid = (lo + hi + 1) >> 1;
+        if (cbase[mid] <= c0) lo = mid; else hi = mid - 1;
+      }
+      const uint64_t i0 = lo;
+      hi = m - 1;
+      while (lo < hi) {
+        const uint64_t mid = (lo + hi + 1) >> 1;
+        if (cbase[mid] <= c1 - 1) lo = mid; else hi = mid - 1;
+      }
+      s_i0 = i0;
+      s_n = lo - i0 + 1;  // <= kChunk: every item has at least one child
+    }
+    __syncthreads();
+    const uint64_t i0 = s_i0, ni = s_n;
+    for (uint64_t j = threadIdx.x; j < ni; j += blockDim.x) s_cb[j] = cbase[i0 + j];
+    __syncthreads();
+    for (uint64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+      uint32_t lo = 0, hi = (uint32_t)ni - 1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (s_cb[mid] <= c) lo = mid; else hi = mid - 1;
+      }
+      const uint64_t i = i0 + lo;
+      const SlpItem it = items[i];
+      const uint64_t v = c - s_cb[lo];
+      const uint64_t rep = v / it.q, k = v - rep * it.q;
+      const uint64_t t = it.a + k;
+      const uint32_t y = rhs[t];
+      const uint64_t p = it.pos_s + rep * it.period + S[t];
+      if (y < 256) {
+        out[p] = (uint8_t)y;
+      } else if (N[t + 1] == N[t]) {  // a leaf: its bytes, mult times
+        const RuleMeta lf = meta[y - 256];
+        uint64_t w = p;
+        for (uint32_t rr = 0; rr < lf.mult; ++rr)
+          for (uint32_t kk = 0; kk < lf.q; ++kk) out[w++] = (uint8_t)rhs[lf.a + kk];
+      } else {
+        const uint64_t slot = nbase[i] + rep * it.nt + (N[t] - it.na);
+        nsym[slot] = y;
+        npos[slot] = p;
+      }
+    }
+    __syncthreads();  // s_cb is rewritten by the next chunk
+  }
+}
+
 // ---------------------------------------------------------------- host
 struct Scan {
   DBuf<uint64_t> tmp;
@@ -711,7 +924,14 @@ static lcg_slp* postprocess_core(lcg_grammar* g, uint32_t flags, hipStream_t s) 
   st[2] = runs;
   st[3] = g1;
   st[4] = q1 + runs;
+  std::vector<uint32_t> bounds1;  // block bounds in the ids after RL
+  bounds1.push_back(256);
+  for (uint32_t i = 0; i < h; ++i) {
+    bounds1.push_back(tab[i].obase);
+    bounds1.push_back(tab[i].obase + tab[i].u);
+  }
   if (!simp) {
+    out->bounds = bounds1;
     out->g = g1;
     out->q = q1;
     out->off = std::move(off1);
@@ -776,6 +996,19 @@ static lcg_slp* postprocess_core(lcg_grammar* g, uint32_t flags, hipStream_t s) 
   }
   uint64_t g2 = 0, q2 = 0;
   read_many<uint64_t>({{nidx.p + g1, &g2}, {so.p + g1, &q2}}, s);
+  {  // block bounds after renumbering: the kept rules before each bound
+    DBuf<uint32_t> bq;
+    DBuf<uint64_t> bv;
+    bq.need(bounds1.size(), s);
+    bv.need(bounds1.size(), s);
+    HIP_CHECK(hipMemcpyAsync(bq.p, bounds1.data(), bounds1.size() * 4, hipMemcpyHostToDevice, s));
+    k_pp_gather<<<pgrid(bounds1.size()), kPB, 0, s>>>(nidx.p, bq.p, (uint32_t)bounds1.size(), bv.p);
+    PP_CHECK("pp_gather");
+    std::vector<uint64_t> hb(bounds1.size());
+    HIP_CHECK(hipMemcpyAsync(hb.data(), bv.p, hb.size() * 8, hipMemcpyDeviceToHost, s));
+    sync(s);
+    for (uint64_t v : hb) out->bounds.push_back(256 + (uint32_t)v);
+  }
   out->g = (uint32_t)g2;
   out->q = q2;
   out->off.need(g2 + 1, s);
@@ -796,6 +1029,98 @@ static lcg_slp* postprocess_core(lcg_grammar* g, uint32_t flags, hipStream_t s) 
   st[7] = q2 + runs;
   sync(s);
   return out.release();
+}
+
+static void slp_lens(lcg_slp* p, hipStream_t s) {
+  if (p->lens_ready) return;
+  const uint32_t gc = std::max<uint32_t>(p->g, 1);
+  p->E.need(gc, s);
+  p->nt.need(gc, s);
+  for (size_t b = 0; b + 1 < p->bounds.size(); ++b) {
+    const uint32_t r0 = p->bounds[b] - 256, r1 = p->bounds[b + 1] - 256;
+    if (r1 <= r0) continue;
+    k_slp_lens<<<pgrid(r1 - r0), kPB, 0, s>>>(p->off.p, p->rhs.p, p->mult.p, r0, r1, p->E.p,
+                                              p->nt.p);
+    PP_CHECK("slp_lens");
+  }
+  p->S.need(p->q + 1, s);
+  p->N.need(p->q + 1, s);
+  {
+    DBuf<uint64_t> we, wn;
+    we.need(std::max<uint64_t>(p->q, 1), s);
+    wn.need(std::max<uint64_t>(p->q, 1), s);
+    k_slp_posw<<<pgrid(p->q), kPB, 0, s>>>(p->rhs.p, p->q, p->E.p, p->nt.p, we.p, wn.p);
+    PP_CHECK("slp_posw");
+    Scan sc;
+    sc.run(we.p, p->S.p, p->q, s);
+    sc.run(wn.p, p->N.p, p->q, s);
+    p->meta.need(std::max<uint64_t>(p->g, 1) * sizeof(RuleMeta), s);
+    k_slp_meta<<<pgrid(p->g), kPB, 0, s>>>(p->off.p, p->mult.p, p->nt.p, p->E.p, p->S.p, p->N.p,
+                                           p->g, reinterpret_cast<RuleMeta*>(p->meta.p));
+    PP_CHECK("slp_meta");
+    sync(s);
+  }
+  p->lens_ready = true;
+}
+
+// exp(C[j]) for j0 <= j < j1, one after the other in d_out (see lcg.h)
+static void slp_expand_core(lcg_slp* p, uint32_t j0, uint32_t j1, uint8_t* d_out, uint64_t cap,
+                            uint64_t* d_offsets, uint64_t* total_out, hipStream_t s) {
+  if (j0 > j1 || j1 > p->k) throw LcgError{LCG_EINVAL, "string range out of bounds"};
+  const uint32_t ks = j1 - j0;
+  slp_lens(p, s);
+  DBuf<uint64_t> len, str_off, ctr;
+  Scan sc;
+  len.need(std::max<uint32_t>(ks, 1), s);
+  str_off.need(ks + 1, s);
+  k_slp_strlen<<<pgrid(ks), kPB, 0, s>>>(p->c.p + j0, ks, p->E.p, len.p);
+  PP_CHECK("slp_strlen");
+  sc.run(len.p, str_off.p, ks, s);
+  const uint64_t total = read_dev(str_off.p + ks, s);
+  if (total_out) *total_out = total;
+  if (total > cap) throw LcgError{LCG_EINVAL, "output buffer too small"};
+  if (d_offsets)
+    HIP_CHECK(hipMemcpyAsync(d_offsets, str_off.p, (ks + 1) * sizeof(uint64_t),
+                             hipMemcpyDeviceToDevice, s));
+  // the strings whose C entry is a rule are the first step's items
+  ctr.need(1, s);
+  zero(ctr.p, 8, s);
+  DBuf<uint32_t> sym[2];
+  DBuf<uint64_t> pos[2];
+  int cur = 0;
+  sym[0].need(std::max<uint32_t>(ks, 1), s);
+  pos[0].need(std::max<uint32_t>(ks, 1), s);
+  auto* uctr = reinterpret_cast<unsigned long long*>(ctr.p);
+  k_slp_enter<<<pgrid(ks), kPB, 0, s>>>(p->c.p + j0, ks, str_off.p, sym[0].p, pos[0].p, uctr,
+                                        d_out);
+  PP_CHECK("slp_enter");
+  uint64_t m = read_dev(ctr.p, s);
+  DBuf<uint64_t> cnt, ntc, cbase, nbase;
+  DBuf<SlpItem> items;
+  while (m) {
+    cnt.need(m, s);
+    ntc.need(m, s);
+    cbase.need(m + 1, s);
+    nbase.need(m + 1, s);
+    items.need(m, s);
+    const RuleMeta* meta = reinterpret_cast<const RuleMeta*>(p->meta.p);
+    k_slp_count<<<pgrid(m), kPB, 0, s>>>(sym[cur].p, pos[cur].p, m, meta, cnt.p, ntc.p, items.p);
+    PP_CHECK("slp_count");
+    sc.run(cnt.p, cbase.p, m, s);
+    sc.run(ntc.p, nbase.p, m, s);
+    uint64_t total = 0, m_next = 0;
+    read_many<uint64_t>({{cbase.p + m, &total}, {nbase.p + m, &m_next}}, s);
+    sym[cur ^ 1].need(std::max<uint64_t>(m_next, 1), s);
+    pos[cur ^ 1].need(std::max<uint64_t>(m_next, 1), s);
+    const uint64_t nchunks = (total + kChunk - 1) / kChunk;
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(nchunks, 8192));
+    k_slp_children<<<grid, kPB, 0, s>>>(items.p, m, cbase.p, nbase.p, total, p->rhs.p, p->S.p,
+                                        p->N.p, meta, sym[cur ^ 1].p, pos[cur ^ 1].p, d_out);
+    PP_CHECK("slp_children");
+    cur ^= 1;
+    m = m_next;
+  }
+  sync(s);
 }
 
 }  // namespace lcg
@@ -848,6 +1173,16 @@ lcg_status lcg_slp_copy(lcg_slp_t p, uint64_t* h_off, uint32_t* h_rhs, uint32_t*
     if (h_rhs && p->q) HIP_CHECK(hipMemcpy(h_rhs, p->rhs.p, p->q * 4, hipMemcpyDeviceToHost));
     if (h_mult && p->g) HIP_CHECK(hipMemcpy(h_mult, p->mult.p, p->g * 4ull, hipMemcpyDeviceToHost));
     if (h_c && p->k) HIP_CHECK(hipMemcpy(h_c, p->c.p, p->k * 4ull, hipMemcpyDeviceToHost));
+  });
+}
+
+lcg_status lcg_slp_expand_strings(lcg_slp_t p, uint32_t j0, uint32_t j1, uint8_t* d_out,
+                                  uint64_t cap, uint64_t* d_offsets, uint64_t* total,
+                                  hipStream_t stream) {
+  return guard([&] {
+    if (!p) throw LcgError{LCG_EINVAL, "slp is NULL"};
+    if (cap && !d_out) throw LcgError{LCG_EINVAL, "d_out is NULL"};
+    slp_expand_core(p, j0, j1, d_out, cap, d_offsets, total, stream);
   });
 }
 

@@ -783,6 +783,7 @@ static void ensure_explen(lcg_grammar* g, hipStream_t s) {
   if (g->explen_version == g->version && g->explen.size() == g->levels.size()) return;
   const size_t nl = g->levels.size();
   g->explen.resize(nl);
+  g->gc.resize(nl);
   std::vector<const uint64_t*> ptrs(std::max<size_t>(nl, 1), nullptr);
   for (size_t i = 0; i < nl; ++i) {
     const Level& L = g->levels[i];
@@ -790,6 +791,10 @@ static void ensure_explen(lcg_grammar* g, hipStream_t s) {
     launch_explen(L.off.p, i ? L.rhs32.p : nullptr, i ? g->explen[i - 1].p : nullptr, L.u,
                   g->explen[i].p, s);
     ptrs[i] = g->explen[i].p;
+    if (i >= 3) {  // levels >= 4: grandchildren counts for the expansion
+      g->gc[i].need(std::max<uint32_t>(L.u, 1), s);
+      launch_gc(L.off.p, L.rhs32.p, g->levels[i - 1].off.p, L.u, g->gc[i].p, s);
+    }
   }
   g->explen_ptrs.need(ptrs.size(), s);
   HIP_CHECK(hipMemcpyAsync(g->explen_ptrs.p, ptrs.data(), ptrs.size() * sizeof(void*),
@@ -853,7 +858,7 @@ static void expand_strings_core(lcg_grammar* g, uint32_t j0, uint32_t j1, uint8_
     sym[cur].need(std::max<uint64_t>(m, 1), s);
     pos[cur].need(std::max<uint64_t>(m, 1), s);
     launch_xs_enter(cl, cs, ks, top, str_off.p, sym[cur].p, pos[cur].p, ctr.p, d_out, s);
-    if (top >= 2) {
+    if (top >= 3) {
       launch_xs_count(sym[cur].p, m, g->levels[top - 1].off.p, ctr.p + 1, s);
       children = read_dev(ctr.p + 1, s);
     }
@@ -865,17 +870,33 @@ static void expand_strings_core(lcg_grammar* g, uint32_t j0, uint32_t j1, uint8_
                        nullptr, nullptr, nullptr, nullptr, d_out, s);
       break;
     }
+    if (lv == 2) {
+      // level-2 items write the bytes of their level-1 children in place; the
+      // level-1 items left are the strings entering there
+      const Level& L1 = g->levels[0];
+      launch_xs_bytes2(sym[cur].p, pos[cur].p, m, L.off.p, L.rhs32.p, L1.off.p, L1.rhs8.p, d_out, s);
+      const uint64_t m1 = entering[1];
+      sym[cur ^ 1].need(std::max<uint64_t>(m1, 1), s);
+      pos[cur ^ 1].need(std::max<uint64_t>(m1, 1), s);
+      launch_zero(ctr.p, 2 * sizeof(uint64_t), s);
+      launch_xs_enter(cl, cs, ks, 1, str_off.p, sym[cur ^ 1].p, pos[cur ^ 1].p, ctr.p, d_out, s);
+      cur ^= 1;
+      m = m1;
+      continue;
+    }
     // the children are counted by the previous pass (or above, at the top);
     // this pass counts the grandchildren, except those of entering strings
     const uint64_t m_next = children + entering[lv - 1];
     sym[cur ^ 1].need(std::max<uint64_t>(m_next, 1), s);
     pos[cur ^ 1].need(std::max<uint64_t>(m_next, 1), s);
     launch_zero(ctr.p, 2 * sizeof(uint64_t), s);
-    const uint64_t* off_below = lv >= 3 ? g->levels[lv - 2].off.p : nullptr;
+    // grandchildren are counted while they will be items (level >= 2)
+    const uint64_t* off_below = lv >= 4 ? g->levels[lv - 2].off.p : nullptr;
     launch_xs_expand(false, sym[cur].p, pos[cur].p, m, L.off.p, L.rhs32.p, g->explen[lv - 2].p,
-                     off_below, sym[cur ^ 1].p, pos[cur ^ 1].p, ctr.p, ctr.p + 1, nullptr, s);
+                     lv >= 4 ? g->gc[lv - 1].p : nullptr, sym[cur ^ 1].p, pos[cur ^ 1].p, ctr.p,
+                     ctr.p + 1, nullptr, s);
     launch_xs_enter(cl, cs, ks, lv - 1, str_off.p, sym[cur ^ 1].p, pos[cur ^ 1].p, ctr.p, d_out, s);
-    if (lv >= 3) {
+    if (lv >= 4) {
       children = read_dev(ctr.p + 1, s);
       if (entering[lv - 1]) {
         // the entering strings' own children

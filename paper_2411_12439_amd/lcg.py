@@ -30,7 +30,7 @@ EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_exp
            "lcg_info", "lcg_level_size", "lcg_level_copy", "lcg_c_copy", "lcg_stats",
            "lcg_stats_clear", "lcg_build_bytes", "lcg_free", "lcg_release_pool", "lcg_last_error",
            "lcg_postprocess", "lcg_slp_size", "lcg_slp_stats", "lcg_slp_device", "lcg_slp_copy",
-           "lcg_slp_free")
+           "lcg_slp_expand_strings", "lcg_slp_free")
 
 PP_RL = 1
 PP_SIMP = 2
@@ -120,6 +120,9 @@ def lib():
     L.lcg_slp_device.restype = st
     L.lcg_slp_copy.argtypes = [vp, u64p, u32p, u32p, u32p]
     L.lcg_slp_copy.restype = st
+    L.lcg_slp_expand_strings.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, vp,
+                                         ctypes.c_uint64, vp, u64p, vp]
+    L.lcg_slp_expand_strings.restype = st
     L.lcg_slp_free.argtypes = [vp]
     L.lcg_slp_free.restype = None
     _lib = L
@@ -307,6 +310,22 @@ class Slp:
         _check(lib().lcg_slp_copy(self.h, _ptr(off, ctypes.c_uint64), _ptr(rhs, ctypes.c_uint32),
                                   _ptr(mult, ctypes.c_uint32), _ptr(c, ctypes.c_uint32)))
         return {"off": off, "rhs": rhs[:q], "mult": mult[:g], "c": c[:k], "stats": self.stats()}
+
+    def expand_strings(self, j0=0, j1=None, stream=None):
+        """Strings j0..j1-1 decompressed together: (uint8 device tensor, int64 offsets tensor)."""
+        import torch
+        j1 = self.size()[2] if j1 is None else j1
+        total = ctypes.c_uint64()
+        rc = lib().lcg_slp_expand_strings(self.h, j0, j1, None, 0, None, ctypes.byref(total),
+                                          _stream(stream))
+        if rc not in (0, -1):
+            _check(rc)
+        out = torch.empty(max(total.value, 1), dtype=torch.uint8, device="cuda")
+        offs = torch.empty(max(j1 - j0, 0) + 1, dtype=torch.int64, device="cuda")
+        _check(lib().lcg_slp_expand_strings(self.h, j0, j1, ctypes.c_void_p(out.data_ptr()),
+                                            out.numel(), ctypes.c_void_p(offs.data_ptr()),
+                                            ctypes.byref(total), _stream(stream)))
+        return out[:total.value], offs
 
 
 def new(seed):

@@ -36,11 +36,27 @@ def _assert_slp_equal(got, want):
     assert np.asarray(got["stats"]).tolist() == np.asarray(want["stats"]).tolist()
 
 
+def _check_slp_expand(slp, text, off):
+    """The post-processed grammar decompresses to the input: all strings, and a sub-range."""
+    import torch
+    out, offs = slp.expand_strings()
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), np.asarray(text, np.uint8))
+    assert np.array_equal(offs.cpu().numpy().astype(np.uint64), np.asarray(off, np.uint64))
+    k = len(off) - 1
+    j0, j1 = k // 3, max(k // 3, (2 * k) // 3)
+    out, offs = slp.expand_strings(j0, j1)
+    want = np.asarray(text[int(off[j0]):int(off[j1])], np.uint8)
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
 def _both(L, text, off, rl, simp, **kw):
     from oracle import oracle as O
     t, o = L.to_device(text, off)
     g = L.build(t, o, seed=SEED, **kw)
-    got = g.postprocess(rl=rl, simp=simp).export()
+    slp = g.postprocess(rl=rl, simp=simp)
+    got = slp.export()
+    _check_slp_expand(slp, text, off)
     want = O.build(text, off, SEED).postprocess(rl=rl, simp=simp)
     return got, want
 
@@ -139,5 +155,6 @@ def test_full_bacterial_equals_oracle(L):
     want = O.build(text, off, SEED).postprocess(rl=True, simp=True)
     t, o = L.to_device(text, off)
     g = L.build(t, o, seed=SEED)
-    got = g.postprocess(rl=True, simp=True).export()
-    _assert_slp_equal(got, want)
+    slp = g.postprocess(rl=True, simp=True)
+    _assert_slp_equal(slp.export(), want)
+    _check_slp_expand(slp, text, off)
