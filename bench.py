@@ -323,6 +323,32 @@ def main():
         "expand_gbps": round(n / float(np.mean(sxs)) / 1e9, 3)}
     print("[bench] postprocess (RL + Simp): %.2f ms, %s" % (pp_s * 1e3, st), file=sys.stderr,
           flush=True)
+
+    # random access: 100,000 substrings of 256 bytes at seeded random places
+    rng = np.random.default_rng(7)
+    nq, qlen = 100000, 256
+    lens_s = np.diff(off.astype(np.int64))
+    qj = rng.integers(0, k, nq)
+    qs = (rng.random(nq) * (lens_s[qj] - qlen + 1)).astype(np.int64)
+    dj = torch.tensor(qj, dtype=torch.int32, device="cuda")
+    ds = torch.tensor(qs, dtype=torch.int64, device="cuda")
+    dl = torch.full((nq,), qlen, dtype=torch.int32, device="cuda")
+    xo, _ = g.extract(dj, ds, dl)
+    want = text[(off.astype(np.int64)[qj] + qs)[:, None] + np.arange(qlen)[None, :]]
+    if not np.array_equal(xo.cpu().numpy().reshape(nq, qlen), want):
+        raise SystemExit("lcg_extract does not give back the input")
+    xts = []
+    for i in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.extract(dj, ds, dl)
+        torch.cuda.synchronize()
+        xts.append(time.perf_counter() - t0)
+    x_s = float(np.mean(xts))
+    out["extract"] = {"what": "lcg_extract: 100,000 random 256-byte substrings of the collection",
+                      "ms": round(x_s * 1e3, 3), "queries_per_s": round(nq / x_s),
+                      "gbps": round(nq * qlen / x_s / 1e9, 3)}
+    print("[bench] extract: %.2f ms for %d queries" % (x_s * 1e3, nq), file=sys.stderr, flush=True)
     g.free()
     del out_t, offs_t
     out["expand"] = {"what": "lcg_expand_strings of all strings (decompression), output bytes/s",

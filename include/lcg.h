@@ -160,6 +160,22 @@ lcg_status lcg_expand_strings(lcg_grammar_t g, uint32_t j0, uint32_t j1, uint8_t
 lcg_status lcg_tune(const uint8_t* d_text, const uint64_t* d_offsets, uint32_t k,
                     const lcg_opts* base, hipStream_t stream, lcg_opts* best, double* best_ms);
 
+/*
+ * Random access (the inverse path without expanding whole strings): for every
+ * query q < nq, bytes [d_start[q], d_start[q] + d_len[q]) of string d_j[q]
+ * are written to d_out + d_out_off[q].  Query arrays are device memory
+ * (uint32 j, uint64 start, uint32 len, uint64 output offset); 1 <= len <=
+ * LCG_EXTRACT_MAX.  One block per query descends from C[j] keeping only the
+ * symbols whose expansion overlaps the range (at most len of them per level).
+ * Synchronises the stream.  Errors: LCG_EINVAL for NULL arrays, a grammar
+ * without strings, or any query out of range (its output is not written;
+ * the other queries are).
+ */
+#define LCG_EXTRACT_MAX 2048
+lcg_status lcg_extract(lcg_grammar_t g, uint32_t nq, const uint32_t* d_j, const uint64_t* d_start,
+                       const uint32_t* d_len, const uint64_t* d_out_off, uint8_t* d_out,
+                       hipStream_t stream);
+
 /* An empty grammar with hash family `seed` (no levels, no strings). */
 lcg_status lcg_new(uint64_t seed, lcg_grammar_t* out);
 

@@ -221,6 +221,13 @@ struct Level {
 
 using Stat = std::array<uint64_t, LCG_STATS_FIELDS>;
 
+// device view of one level: its rule offsets and right-hand sides (uint8 at
+// level 1, uint32 above)
+struct LevelPtrs {
+  const uint64_t* off;
+  const void* rhs;
+};
+
 }  // namespace lcg
 
 struct lcg_grammar {
@@ -237,6 +244,7 @@ struct lcg_grammar {
   // per rule of levels >= 3: the summed right-hand-side lengths of its children
   std::vector<lcg::DBuf<uint64_t>> gc;
   lcg::DBuf<const uint64_t*> explen_ptrs;
+  lcg::DBuf<lcg::LevelPtrs> level_ptrs;  // per level: offsets and right-hand sides
   uint64_t explen_version = ~0ull;
   explicit lcg_grammar(uint64_t s) : seed(s), H(s) {}
 };
@@ -256,6 +264,10 @@ inline T read_dev(const T* p, hipStream_t s) {
   sync(s);
   return v;
 }
+
+// expansion lengths (and the per-level device tables) of g, computed once
+// per version of the grammar
+void ensure_explen(lcg_grammar* g, hipStream_t s);
 
 template <typename F>
 lcg_status guard(F&& f) {

@@ -779,12 +779,17 @@ static void expand_core(lcg_grammar* g, uint32_t j, uint8_t* d_out, uint64_t cap
 }
 
 // Expansion lengths (bytes) of every rule of g, per level, kept until g changes.
-static void ensure_explen(lcg_grammar* g, hipStream_t s) {
+void ensure_explen(lcg_grammar* g, hipStream_t s) {
   if (g->explen_version == g->version && g->explen.size() == g->levels.size()) return;
   const size_t nl = g->levels.size();
   g->explen.resize(nl);
   g->gc.resize(nl);
   std::vector<const uint64_t*> ptrs(std::max<size_t>(nl, 1), nullptr);
+  std::vector<LevelPtrs> lp(std::max<size_t>(nl, 1));
+  for (size_t i = 0; i < nl; ++i) {
+    lp[i].off = g->levels[i].off.p;
+    lp[i].rhs = i ? (const void*)g->levels[i].rhs32.p : (const void*)g->levels[i].rhs8.p;
+  }
   for (size_t i = 0; i < nl; ++i) {
     const Level& L = g->levels[i];
     g->explen[i].need(std::max<uint32_t>(L.u, 1), s);
@@ -798,6 +803,9 @@ static void ensure_explen(lcg_grammar* g, hipStream_t s) {
   }
   g->explen_ptrs.need(ptrs.size(), s);
   HIP_CHECK(hipMemcpyAsync(g->explen_ptrs.p, ptrs.data(), ptrs.size() * sizeof(void*),
+                           hipMemcpyHostToDevice, s));
+  g->level_ptrs.need(lp.size(), s);
+  HIP_CHECK(hipMemcpyAsync(g->level_ptrs.p, lp.data(), lp.size() * sizeof(LevelPtrs),
                            hipMemcpyHostToDevice, s));
   sync(s);  // ptrs is a host temporary
   g->explen_version = g->version;

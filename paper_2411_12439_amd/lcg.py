@@ -30,7 +30,9 @@ EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_exp
            "lcg_info", "lcg_level_size", "lcg_level_copy", "lcg_c_copy", "lcg_stats",
            "lcg_stats_clear", "lcg_build_bytes", "lcg_free", "lcg_release_pool", "lcg_last_error",
            "lcg_postprocess", "lcg_slp_size", "lcg_slp_stats", "lcg_slp_device", "lcg_slp_copy",
-           "lcg_slp_expand_strings", "lcg_slp_free")
+           "lcg_slp_expand_strings", "lcg_slp_free", "lcg_extract")
+
+EXTRACT_MAX = 2048
 
 PP_RL = 1
 PP_SIMP = 2
@@ -123,6 +125,8 @@ def lib():
     L.lcg_slp_expand_strings.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, vp,
                                          ctypes.c_uint64, vp, u64p, vp]
     L.lcg_slp_expand_strings.restype = st
+    L.lcg_extract.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, vp, vp, vp]
+    L.lcg_extract.restype = st
     L.lcg_slp_free.argtypes = [vp]
     L.lcg_slp_free.restype = None
     _lib = L
@@ -264,6 +268,27 @@ class Grammar:
                                         _stream(stream)))
         return out[:total.value], offs
 
+
+    def extract(self, j, start, length, stream=None):
+        """Random access: bytes [start[q], start[q] + length[q]) of string j[q] for every
+        query (device tensors or array-likes; 1 <= length <= EXTRACT_MAX).
+        Returns (uint8 device tensor of all answers, int64 offsets tensor)."""
+        import torch
+        dev = "cuda"
+        j = torch.as_tensor(j, dtype=torch.int32, device=dev).contiguous()
+        start = torch.as_tensor(start, dtype=torch.int64, device=dev).contiguous()
+        length = torch.as_tensor(length, dtype=torch.int32, device=dev).contiguous()
+        nq = j.numel()
+        offs = torch.zeros(nq + 1, dtype=torch.int64, device=dev)
+        if nq:
+            offs[1:] = torch.cumsum(length.to(torch.int64), 0)
+        out = torch.empty(max(int(offs[-1].item()) if nq else 0, 1), dtype=torch.uint8, device=dev)
+        _check(lib().lcg_extract(self.h, nq, ctypes.c_void_p(j.data_ptr()),
+                                 ctypes.c_void_p(start.data_ptr()),
+                                 ctypes.c_void_p(length.data_ptr()),
+                                 ctypes.c_void_p(offs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                 _stream(stream)))
+        return out[:int(offs[-1].item()) if nq else 0], offs
 
     def postprocess(self, rl=True, simp=True, stream=None):
         """RL and/or Simp (Sec. 2.2) on the device: a new Slp (this grammar is unchanged)."""

@@ -1,0 +1,112 @@
+"""Random access (lcg_extract) against slices of the input.
+
+The expected bytes are the input itself (the grammar derives it exactly), so
+every query is compared byte for byte.  Queries hit string starts and ends,
+single bytes, the maximum length, strings of length one (C at level 0) and
+long level-1 rules (homopolymers).
+"""
+import numpy as np
+import pytest
+
+from paper_2411_12439_amd import datagen as D
+
+pytestmark = pytest.mark.gpu
+SEED = D.HASH_SEED
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2411_12439_amd import lcg
+    lcg.lib()
+    return lcg
+
+
+def _queries(rng, off, nq, maxlen):
+    lens_s = np.diff(off.astype(np.int64))
+    j = rng.integers(0, len(lens_s), nq)
+    ln = np.minimum(rng.integers(1, maxlen + 1, nq), lens_s[j])
+    st = (rng.random(nq) * (lens_s[j] - ln + 1)).astype(np.int64)
+    # boundaries: string starts, string ends, single bytes, whole short strings
+    k = len(lens_s)
+    j = np.concatenate([j, np.arange(k), np.arange(k), np.arange(k)])
+    st = np.concatenate([st, np.zeros(k, np.int64), lens_s - np.minimum(lens_s, maxlen),
+                         lens_s - 1])
+    ln = np.concatenate([ln, np.minimum(lens_s, maxlen), np.minimum(lens_s, maxlen),
+                         np.ones(k, np.int64)])
+    return j, st, ln
+
+
+def _check(L, g, text, off, j, st, ln):
+    out, offs = g.extract(j, st, ln)
+    got = out.cpu().numpy()
+    o = offs.cpu().numpy()
+    base = off.astype(np.int64)
+    for q in range(len(j)):
+        a = int(base[j[q]] + st[q])
+        want = text[a:a + int(ln[q])]
+        assert np.array_equal(got[o[q]:o[q + 1]], want), (q, int(j[q]), int(st[q]), int(ln[q]))
+
+
+@pytest.mark.parametrize("config,scale", [("tiny", 1.0), ("bacterial", 0.01), ("repeats", 0.0005)])
+def test_random_queries(L, config, scale):
+    text, off = D.make_config(config, scale=scale)
+    t, o = L.to_device(text, off)
+    g = L.build(t, o, seed=SEED)
+    rng = np.random.default_rng(3)
+    print("extract: %s scale %g" % (config, scale), flush=True)
+    _check(L, g, text, off, *_queries(rng, off, 3000, L.EXTRACT_MAX))
+
+
+def test_edge_strings(L):
+    from oracle import oracle as O
+    rng = np.random.default_rng(4)
+    dna = D.BASES[rng.integers(0, 4, 9000)].tobytes()
+    strings = [b"A", b"C", b"GG", b"T" * 7000, dna, b"N" * 100 + dna[:300], b"AC" * 2000, b"x"]
+    text, off = O.pack(strings)
+    t, o = L.to_device(text, off)
+    g = L.build(t, o, seed=SEED)
+    _check(L, g, text, off, *_queries(rng, off, 2000, L.EXTRACT_MAX))
+    # after a merge, and on a plain-form grammar
+    half = len(strings) // 2
+    ta, oa = L.to_device(*O.pack(strings[:half]))
+    tb, ob = L.to_device(*O.pack(strings[half:]))
+    ga = L.build(ta, oa, seed=SEED)
+    ga.merge(L.build(tb, ob, seed=SEED))
+    _check(L, ga, text, off, *_queries(rng, off, 500, 300))
+    gp = L.build(t, o, seed=SEED, mode=L.MODE_PLAIN)
+    _check(L, gp, text, off, *_queries(rng, off, 500, 64))
+
+
+def test_out_of_range_queries_are_rejected(L):
+    text, off = D.make_config("tiny", scale=0.05)
+    t, o = L.to_device(text, off)
+    g = L.build(t, o, seed=SEED)
+    n0 = int(off[1] - off[0])
+    for j, st, ln in ((0, n0, 1), (0, n0 - 2, 3), (len(off) - 1, 0, 1), (0, 0, 0),
+                      (0, 0, L.EXTRACT_MAX + 1)):
+        with pytest.raises(L.LcgError) as e:
+            g.extract([j], [st], [ln])
+        assert e.value.name == "LCG_EINVAL"
+    # a bad query does not stop the good ones
+    import torch
+    j = torch.tensor([0, 0], dtype=torch.int32, device="cuda")
+    st = torch.tensor([5, n0], dtype=torch.int64, device="cuda")
+    ln = torch.tensor([10, 1], dtype=torch.int32, device="cuda")
+    offs = torch.tensor([0, 10, 11], dtype=torch.int64, device="cuda")
+    out = torch.zeros(11, dtype=torch.uint8, device="cuda")
+    import ctypes
+    rc = L.lib().lcg_extract(g.h, 2, ctypes.c_void_p(j.data_ptr()), ctypes.c_void_p(st.data_ptr()),
+                             ctypes.c_void_p(ln.data_ptr()), ctypes.c_void_p(offs.data_ptr()),
+                             ctypes.c_void_p(out.data_ptr()), None)
+    assert rc == -1
+    assert np.array_equal(out.cpu().numpy()[:10], text[5:15])
+
+
+def test_full_bacterial_random_access(L):
+    text, off = D.make_config("bacterial")
+    t, o = L.to_device(text, off)
+    g = L.build(t, o, seed=SEED)
+    rng = np.random.default_rng(9)
+    _check(L, g, text, off, *_queries(rng, off, 4000, L.EXTRACT_MAX))
