@@ -161,6 +161,25 @@ lcg_status lcg_tune(const uint8_t* d_text, const uint64_t* d_offsets, uint32_t k
                     const lcg_opts* base, hipStream_t stream, lcg_opts* best, double* best_ms);
 
 /*
+ * Streaming build from a file (App. A.3's buffered BuildGram on one device):
+ * the file holds one non-empty string per line ('\n'-terminated; the last
+ * line may lack it).  It is read in chunks of whole lines of at most
+ * chunk_bytes (4 KiB .. 64 GiB; a longer line is LCG_EINVAL) by host threads
+ * into pinned buffers, uploaded on a copy stream while the previous chunk is
+ * compressed, split into strings on the device and compressed into g with
+ * lcg_build_into, so device memory is bounded by the chunk size and the
+ * grammar, not by the file.  The strings are appended to C in file order;
+ * the result equals lcg_build_into of the whole file at once.
+ *   opts    as for lcg_build_into (NULL: defaults); its seed is taken from g
+ *   h_info  NULL or uint64[6]: string bytes, strings, chunks, wall ns, ns the
+ *           builder waited for the reader, ns in lcg_build_into
+ * Errors: LCG_EINVAL (NULL arguments, unreadable file, empty line, line
+ * longer than a chunk), and those of lcg_build_into.
+ */
+lcg_status lcg_build_file(lcg_grammar_t g, const char* path, uint64_t chunk_bytes,
+                          const lcg_opts* opts, hipStream_t stream, uint64_t* h_info);
+
+/*
  * Random access (the inverse path without expanding whole strings): for every
  * query q < nq, bytes [d_start[q], d_start[q] + d_len[q]) of string d_j[q]
  * are written to d_out + d_out_off[q].  Query arrays are device memory

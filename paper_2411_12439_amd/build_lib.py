@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblcg.so")
-SOURCES = ["lcg_kernels.hip", "lcg_runtime.hip", "lcg_post.hip", "lcg_access.hip"]
+SOURCES = ["lcg_kernels.hip", "lcg_runtime.hip", "lcg_post.hip", "lcg_access.hip",
+           "lcg_stream.hip"]
 ARCH = os.environ.get("LCG_OFFLOAD_ARCH", "gfx950")
 
 

@@ -30,7 +30,7 @@ EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_exp
            "lcg_info", "lcg_level_size", "lcg_level_copy", "lcg_c_copy", "lcg_stats",
            "lcg_stats_clear", "lcg_build_bytes", "lcg_free", "lcg_release_pool", "lcg_last_error",
            "lcg_postprocess", "lcg_slp_size", "lcg_slp_stats", "lcg_slp_device", "lcg_slp_copy",
-           "lcg_slp_expand_strings", "lcg_slp_free", "lcg_extract")
+           "lcg_slp_expand_strings", "lcg_slp_free", "lcg_extract", "lcg_build_file")
 
 EXTRACT_MAX = 2048
 
@@ -125,6 +125,9 @@ def lib():
     L.lcg_slp_expand_strings.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, vp,
                                          ctypes.c_uint64, vp, u64p, vp]
     L.lcg_slp_expand_strings.restype = st
+    L.lcg_build_file.argtypes = [vp, ctypes.c_char_p, ctypes.c_uint64, ctypes.POINTER(Opts), vp,
+                                 u64p]
+    L.lcg_build_file.restype = st
     L.lcg_extract.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, vp, vp, vp]
     L.lcg_extract.restype = st
     L.lcg_slp_free.argtypes = [vp]
@@ -383,6 +386,17 @@ def build_into(g, text, offsets, seed=None, flags=0, hbm_budget=0, key_bits=0, t
                                 ctypes.c_void_p(offsets.data_ptr()), offsets.numel() - 1,
                                 ctypes.byref(o), _stream(stream), ctypes.byref(first)))
     return first.value
+
+
+def build_file(g, path, chunk_bytes=64 << 20, stream=None, **opts):
+    """Stream a file of newline-separated strings into grammar g (lcg_build_file).
+    Returns {"bytes", "strings", "chunks", "wall_s", "read_wait_s", "build_s"}."""
+    o = make_opts(g.info()[0], **opts)
+    info = np.zeros(6, np.uint64)
+    _check(lib().lcg_build_file(g.h, os.fsencode(path), chunk_bytes, ctypes.byref(o),
+                                _stream(stream), _ptr(info, ctypes.c_uint64)))
+    return {"bytes": int(info[0]), "strings": int(info[1]), "chunks": int(info[2]),
+            "wall_s": info[3] / 1e9, "read_wait_s": info[4] / 1e9, "build_s": info[5] / 1e9}
 
 
 def tune(text, offsets, seed=0, stream=None, **base):

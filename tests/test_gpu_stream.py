@@ -1,0 +1,117 @@
+"""Streaming builds from a file (lcg_build_file) against one build of the same strings.
+
+Ranks are numbered by first occurrence (string order, then position), so
+compressing the file chunk by chunk into a running grammar must give the same
+grammar as one build over all of its lines, rank for rank.
+"""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2411_12439_amd import datagen as D
+
+pytestmark = pytest.mark.gpu
+SEED = D.HASH_SEED
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2411_12439_amd import lcg
+    lcg.lib()
+    return lcg
+
+
+def _strings(text, off):
+    o = off.astype(np.int64)
+    return [text[o[j]:o[j + 1]].tobytes() for j in range(len(o) - 1)]
+
+
+def _write(strings, trailing_newline=True):
+    fd, path = tempfile.mkstemp(suffix=".txt")
+    with os.fdopen(fd, "wb") as f:
+        f.write(b"\n".join(strings))
+        if trailing_newline:
+            f.write(b"\n")
+    return path
+
+
+def _assert_same(a, b):
+    assert len(a["levels"]) == len(b["levels"])
+    for la, lb in zip(a["levels"], b["levels"]):
+        assert np.array_equal(la["rhs_off"], lb["rhs_off"])
+        assert np.array_equal(la["rhs"], lb["rhs"])
+        assert np.array_equal(la["fp"], lb["fp"])
+    assert np.array_equal(a["c_level"], b["c_level"])
+    assert np.array_equal(a["c_sym"], b["c_sym"])
+
+
+@pytest.mark.parametrize("chunk,trailing", [(300 << 10, True), (1 << 20, False), (64 << 20, True)])
+def test_file_equals_one_build(L, chunk, trailing):
+    from oracle import oracle as O
+    text, off = D.make_config("tiny")
+    strings = _strings(text, off) + [b"A", b"ACGT" * 100, b"T" * 5000]
+    path = _write(strings, trailing)
+    try:
+        g = L.new(SEED)
+        info = L.build_file(g, path, chunk_bytes=chunk)
+        t, o = L.to_device(*O.pack(strings))
+        want = L.build(t, o, seed=SEED).export()
+        _assert_same(g.export(), want)
+        assert info["strings"] == len(strings)
+        assert info["bytes"] == sum(len(s) for s in strings)
+        if chunk == 300 << 10:
+            assert info["chunks"] > 3
+    finally:
+        os.unlink(path)
+
+
+def test_file_into_existing_grammar(L):
+    from oracle import oracle as O
+    text, off = D.make_config("bacterial", scale=0.01)
+    strings = _strings(text, off)
+    half = len(strings) // 2
+    path = _write(strings[half:])
+    try:
+        ta, oa = L.to_device(*O.pack(strings[:half]))
+        g = L.build(ta, oa, seed=SEED)
+        L.build_file(g, path, chunk_bytes=200 << 10)
+        t, o = L.to_device(*O.pack(strings))
+        _assert_same(g.export(), L.build(t, o, seed=SEED).export())
+        # and the whole collection expands back from the streamed grammar
+        out, offs = g.expand_strings()
+        assert np.array_equal(out.cpu().numpy(), O.pack(strings)[0])
+    finally:
+        os.unlink(path)
+
+
+def test_file_errors(L):
+    g = L.new(SEED)
+    with pytest.raises(L.LcgError) as e:
+        L.build_file(g, "/nonexistent/collection.txt")
+    assert e.value.name == "LCG_EINVAL"
+    path = _write([b"ACGT", b"", b"GG"])
+    try:
+        with pytest.raises(L.LcgError) as e:
+            L.build_file(L.new(SEED), path, chunk_bytes=4096)
+        assert e.value.name == "LCG_EINVAL"
+    finally:
+        os.unlink(path)
+    path = _write([b"A" * 10000, b"C"])
+    try:
+        with pytest.raises(L.LcgError) as e:
+            L.build_file(L.new(SEED), path, chunk_bytes=4096)
+        assert e.value.name == "LCG_EINVAL"
+    finally:
+        os.unlink(path)
+    fd, path = tempfile.mkstemp()
+    os.close(fd)
+    try:
+        g = L.new(SEED)
+        info = L.build_file(g, path, chunk_bytes=4096)
+        assert info["strings"] == 0 and g.info()[2] == 0
+    finally:
+        os.unlink(path)
