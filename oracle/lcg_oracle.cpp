@@ -571,4 +571,25 @@ uint64_t oracle_slp_expand(const OracleSlp* s, uint32_t j, uint8_t* out, uint64_
 }
 void oracle_slp_free(OracleSlp* s) { delete s; }
 
+// Longest common extension of two positions of a collection (the lcp / lcs
+// of the match-completion step sketched in App. B), by comparing bytes:
+// forward (dir 0): the longest common prefix of T_j1[p1..] and T_j2[p2..];
+// backward (dir 1): the longest common suffix of T_j1[..p1) and T_j2[..p2).
+void oracle_lce(const uint8_t* text, const uint64_t* off, uint32_t nq, const uint32_t* j1,
+                const uint64_t* p1, const uint32_t* j2, const uint64_t* p2, uint32_t dir,
+                uint64_t* out) {
+  for (uint32_t q = 0; q < nq; ++q) {
+    const uint8_t* a = text + off[j1[q]];
+    const uint8_t* b = text + off[j2[q]];
+    const uint64_t na = off[j1[q] + 1] - off[j1[q]], nb = off[j2[q] + 1] - off[j2[q]];
+    uint64_t l = 0;
+    if (dir == 0) {
+      while (p1[q] + l < na && p2[q] + l < nb && a[p1[q] + l] == b[p2[q] + l]) ++l;
+    } else {
+      while (l < p1[q] && l < p2[q] && a[p1[q] - 1 - l] == b[p2[q] - 1 - l]) ++l;
+    }
+    out[q] = l;
+  }
+}
+
 }  // extern "C"

@@ -76,6 +76,8 @@ def lib():
         L.oracle_slp_expand.argtypes = [vp, ctypes.c_uint32, u8p, ctypes.c_uint64]
         L.oracle_slp_expand.restype = ctypes.c_uint64
         L.oracle_slp_free.argtypes = [vp]
+        L.oracle_lce.argtypes = [u8p, u64p, ctypes.c_uint32, u32p, u64p, u32p, u64p,
+                                 ctypes.c_uint32, u64p]
         _lib = L
     return _lib
 
@@ -223,6 +225,22 @@ def pack(strings):
     offsets[1:] = np.cumsum([len(b) for b in bs]) if bs else []
     text = np.frombuffer(b"".join(bs), np.uint8) if bs else np.zeros(0, np.uint8)
     return text, offsets
+
+
+def lce(text, offsets, j1, p1, j2, p2, backward=False):
+    """Longest common extensions of position pairs (see oracle_lce): uint64[nq]."""
+    text = np.ascontiguousarray(text, np.uint8)
+    offsets = np.ascontiguousarray(offsets, np.uint64)
+    j1 = np.ascontiguousarray(j1, np.uint32)
+    j2 = np.ascontiguousarray(j2, np.uint32)
+    p1 = np.ascontiguousarray(p1, np.uint64)
+    p2 = np.ascontiguousarray(p2, np.uint64)
+    out = np.zeros(len(j1), np.uint64)
+    lib().oracle_lce(_ptr(text, ctypes.c_uint8), _ptr(offsets, ctypes.c_uint64), len(j1),
+                     _ptr(j1, ctypes.c_uint32), _ptr(p1, ctypes.c_uint64),
+                     _ptr(j2, ctypes.c_uint32), _ptr(p2, ctypes.c_uint64), 1 if backward else 0,
+                     _ptr(out, ctypes.c_uint64))
+    return out
 
 
 def from_arrays(seed, levels, c_level, c_sym):

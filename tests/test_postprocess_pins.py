@@ -129,3 +129,4 @@ def test_round_trip_tiny_and_repeats(oracle_mod):
         rules = BP.rules_of(got)
         assert all(z < 256 + r for r, (rhs, _) in enumerate(rules) for z in rhs)
         assert st[7] == BP.grammar_size(rules)
+
