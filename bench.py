@@ -349,6 +349,59 @@ def main():
                       "ms": round(x_s * 1e3, 3), "queries_per_s": round(nq / x_s),
                       "gbps": round(nq * qlen / x_s / 1e9, 3)}
     print("[bench] extract: %.2f ms for %d queries" % (x_s * 1e3, nq), file=sys.stderr, flush=True)
+
+    # longest common extensions (the match-extension query of App. B): anchors
+    # are 24-mers of one copy of a base genome found in another copy of the
+    # same base; each is extended forward and backward.  1,000 anchors, each
+    # queried 100 times (100,000 queries per direction).
+    na, rep = 1000, 100
+    strs = {}
+    anc = []
+    while len(anc) < na:
+        a = int(rng.integers(0, k))
+        b = (a + 4 * int(rng.integers(1, max(2, k // 4)))) % k
+        pa = int(rng.integers(0, lens_s[a] - 24))
+        for x in (a, b):
+            if x not in strs:
+                strs[x] = text[off[x]:off[x + 1]].tobytes()
+        pb = strs[b].find(strs[a][pa:pa + 24])
+        if pb >= 0:
+            anc.append((a, pa, b, pb))
+    anc = np.array(anc * rep, dtype=np.int64)
+    lj1 = torch.tensor(anc[:, 0], dtype=torch.int32, device="cuda")
+    lp1 = torch.tensor(anc[:, 1], dtype=torch.int64, device="cuda")
+    lj2 = torch.tensor(anc[:, 2], dtype=torch.int32, device="cuda")
+    lp2 = torch.tensor(anc[:, 3], dtype=torch.int64, device="cuda")
+    fwd = g.lce(lj1, lp1, lj2, lp2).cpu().numpy()
+    bwd = g.lce(lj1, lp1, lj2, lp2, backward=True).cpu().numpy()
+    oo = off.astype(np.int64)
+    for q in range(na):  # each answer L: L equal bytes, then a difference or a string end
+        a, pa, b, pb = (int(x) for x in anc[q])
+        lf, lb = int(fwd[q]), int(bwd[q])
+        sa, sb = strs[a], strs[b]
+        ok_f = sa[pa:pa + lf] == sb[pb:pb + lf] and (
+            pa + lf in (len(sa),) or pb + lf == len(sb) or sa[pa + lf] != sb[pb + lf])
+        ok_b = sa[pa - lb:pa] == sb[pb - lb:pb] and (
+            lb == pa or lb == pb or sa[pa - lb - 1] != sb[pb - lb - 1])
+        if not (ok_f and ok_b and lf >= 24):
+            raise SystemExit("lcg_lce answer %d is not the longest common extension" % q)
+    lts = []
+    for i in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.lce(lj1, lp1, lj2, lp2)
+        g.lce(lj1, lp1, lj2, lp2, backward=True)
+        torch.cuda.synchronize()
+        lts.append(time.perf_counter() - t0)
+    l_s = float(np.mean(lts))
+    out["lce"] = {"what": "lcg_lce: 100,000 forward and 100,000 backward longest common "
+                          "extensions from 24-mer anchors shared by two copies of a base",
+                  "ms": round(l_s * 1e3, 3), "queries_per_s": round(2 * len(anc) / l_s),
+                  "mean_forward_bytes": round(float(fwd.mean()), 1),
+                  "mean_backward_bytes": round(float(bwd.mean()), 1),
+                  "compared_gbps": round(float(fwd.sum() + bwd.sum()) / l_s / 1e9, 3)}
+    print("[bench] lce: %.2f ms for %d queries (mean %.1f + %.1f bytes)" %
+          (l_s * 1e3, 2 * len(anc), fwd.mean(), bwd.mean()), file=sys.stderr, flush=True)
     g.free()
     del out_t, offs_t
     out["expand"] = {"what": "lcg_expand_strings of all strings (decompression), output bytes/s",

@@ -195,6 +195,25 @@ lcg_status lcg_extract(lcg_grammar_t g, uint32_t nq, const uint32_t* d_j, const 
                        const uint32_t* d_len, const uint64_t* d_out_off, uint8_t* d_out,
                        hipStream_t stream);
 
+/*
+ * Longest common extension through the grammar: the lcp / lcs queries with
+ * which the match-completion step sketched in App. B extends a match found
+ * among right-hand sides.  For every query q (device arrays: uint32 j1, j2,
+ * uint64 p1, p2; positions 0 <= p <= |T_j|):
+ *   backward = 0: d_out[q] = length of the longest common prefix of
+ *                 T_j1[p1..] and T_j2[p2..];
+ *   backward = 1: length of the longest common suffix of T_j1[..p1) and
+ *                 T_j2[..p2).
+ * Two cursors (the symbol covering the position at every level) walk the
+ * strings; whenever both sit at the same offset of the same symbol, the rest
+ * of that symbol is skipped at once.  Synchronises the stream.  Errors:
+ * LCG_EINVAL (NULL arrays, backward > 1, a grammar without strings, a query
+ * out of range: its output is not written, the others are).
+ */
+lcg_status lcg_lce(lcg_grammar_t g, uint32_t nq, const uint32_t* d_j1, const uint64_t* d_p1,
+                   const uint32_t* d_j2, const uint64_t* d_p2, uint32_t backward,
+                   uint64_t* d_out, hipStream_t stream);
+
 /* An empty grammar with hash family `seed` (no levels, no strings). */
 lcg_status lcg_new(uint64_t seed, lcg_grammar_t* out);
 

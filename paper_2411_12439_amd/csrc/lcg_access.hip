@@ -96,6 +96,154 @@ __global__ __launch_bounds__(kXBlock) void k_extract(
   }
 }
 
+// ---------------------------------------------------------------- LCE
+// A position of a string seen through the grammar: for every level from the
+// string's top symbol down to 1, the symbol covering the position and the
+// position's offset inside that symbol's expansion.
+constexpr int kMaxLv = 64;
+
+struct Cursor {
+  int top;                // level of C[j] (0: a one-byte string)
+  uint32_t sym[kMaxLv];   // sym[l]: level-l symbol covering the position
+  uint64_t off[kMaxLv];   // offset inside exp(sym[l])
+};
+
+__device__ __forceinline__ uint64_t sym_len(const uint64_t* const* explen, int l, uint32_t y) {
+  return explen[l - 1][y];
+}
+
+// recompute the levels below l from sym[l], off[l]
+__device__ void cursor_descend(Cursor& c, int l, const LevelPtrs* lv_ptr,
+                               const uint64_t* const* explen) {
+  for (; l >= 2; --l) {
+    const LevelPtrs L = lv_ptr[l - 1];
+    const uint32_t* rhs = static_cast<const uint32_t*>(L.rhs);
+    const uint64_t* eb = explen[l - 2];
+    uint64_t o = c.off[l];
+    const uint64_t tb = L.off[c.sym[l] + 1];
+    // the child holding offset o (o < exp length of sym[l]: the scan ends in the rule)
+    for (uint64_t t = L.off[c.sym[l]]; t < tb; ++t) {
+      const uint32_t ch = rhs[t];
+      const uint64_t e = eb[ch];
+      c.sym[l - 1] = ch;
+      c.off[l - 1] = o;
+      if (o < e) break;
+      o -= e;
+    }
+  }
+}
+
+__device__ void cursor_init(Cursor& c, int top, uint32_t y, uint64_t x, const LevelPtrs* lv_ptr,
+                            const uint64_t* const* explen) {
+  c.top = top;
+  c.sym[top] = y;
+  c.off[top] = x;
+  if (top >= 1) cursor_descend(c, top, lv_ptr, explen);
+}
+
+// move by s bytes (forward, or backward with BACK), staying inside the string
+template <bool BACK>
+__device__ void cursor_move(Cursor& c, uint64_t s, const LevelPtrs* lv_ptr,
+                            const uint64_t* const* explen) {
+  int l = 1;
+  for (; l < c.top; ++l) {
+    if (BACK ? c.off[l] >= s : c.off[l] + s < sym_len(explen, l, c.sym[l])) break;
+  }
+  for (int m = l; m <= c.top; ++m) c.off[m] = BACK ? c.off[m] - s : c.off[m] + s;
+  cursor_descend(c, l, lv_ptr, explen);
+}
+
+__device__ __forceinline__ uint8_t level1_byte(const LevelPtrs* lv_ptr, uint32_t r, uint64_t o) {
+  const LevelPtrs L = lv_ptr[0];
+  return static_cast<const uint8_t*>(L.rhs)[L.off[r] + o];
+}
+
+// One thread per query: two cursors walk the strings together.  When both sit
+// at the same offset of the same symbol at some level, the rest of that
+// symbol (its expansion is the same) is skipped in one step -- the highest
+// such level first; otherwise the bytes of the two level-1 symbols are
+// compared up to a mismatch or the end of either symbol.
+template <bool BACK>
+__global__ __launch_bounds__(64) void k_lce(const LevelPtrs* __restrict__ lv_ptr,
+                                            const uint64_t* const* __restrict__ explen,
+                                            const uint8_t* __restrict__ c_level,
+                                            const uint32_t* __restrict__ c_sym, uint32_t k,
+                                            uint32_t nq, const uint32_t* __restrict__ qj1,
+                                            const uint64_t* __restrict__ qp1,
+                                            const uint32_t* __restrict__ qj2,
+                                            const uint64_t* __restrict__ qp2,
+                                            uint64_t* __restrict__ out, unsigned int* bad) {
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+    const uint32_t j1 = qj1[q], j2 = qj2[q];
+    if (j1 >= k || j2 >= k) {
+      atomicAdd(bad, 1u);
+      continue;
+    }
+    const int t1 = c_level[j1], t2 = c_level[j2];
+    const uint64_t n1 = t1 ? sym_len(explen, t1, c_sym[j1]) : 1;
+    const uint64_t n2 = t2 ? sym_len(explen, t2, c_sym[j2]) : 1;
+    const uint64_t p1 = qp1[q], p2 = qp2[q];
+    if (p1 > n1 || p2 > n2) {
+      atomicAdd(bad, 1u);
+      continue;
+    }
+    // bytes available in the walking direction
+    uint64_t room1 = BACK ? p1 : n1 - p1, room2 = BACK ? p2 : n2 - p2;
+    if (!room1 || !room2) {
+      out[q] = 0;
+      continue;
+    }
+    Cursor a, b;
+    cursor_init(a, t1, c_sym[j1], BACK ? p1 - 1 : p1, lv_ptr, explen);
+    cursor_init(b, t2, c_sym[j2], BACK ? p2 - 1 : p2, lv_ptr, explen);
+    uint64_t len = 0;
+    for (;;) {
+      uint64_t s = 0;
+      for (int l = min(a.top, b.top); l >= 1; --l) {
+        if (a.sym[l] == b.sym[l] && a.off[l] == b.off[l]) {
+          s = BACK ? a.off[l] + 1 : sym_len(explen, l, a.sym[l]) - a.off[l];
+          break;
+        }
+      }
+      if (!s) {
+        // byte by byte inside the two level-1 symbols (or the one-byte strings)
+        uint64_t oa = a.top ? a.off[1] : 0, ob = b.top ? b.off[1] : 0;
+        const uint64_t ea = a.top ? sym_len(explen, 1, a.sym[1]) : 1;
+        const uint64_t eb = b.top ? sym_len(explen, 1, b.sym[1]) : 1;
+        bool mismatch = false;
+        for (;;) {
+          const uint8_t xa = a.top ? level1_byte(lv_ptr, a.sym[1], oa) : (uint8_t)a.sym[0];
+          const uint8_t xb = b.top ? level1_byte(lv_ptr, b.sym[1], ob) : (uint8_t)b.sym[0];
+          if (xa != xb) {
+            mismatch = true;
+            break;
+          }
+          ++s;
+          if (BACK ? (oa == 0 || ob == 0) : (oa + 1 == ea || ob + 1 == eb)) break;
+          if (BACK) {
+            --oa;
+            --ob;
+          } else {
+            ++oa;
+            ++ob;
+          }
+        }
+        if (mismatch) {
+          len += s;
+          break;
+        }
+      }
+      len += s;
+      if (s >= room1 || s >= room2) break;  // a string ends
+      room1 -= s;
+      room2 -= s;
+      cursor_move<BACK>(a, s, lv_ptr, explen);
+      cursor_move<BACK>(b, s, lv_ptr, explen);
+    }
+    out[q] = len;
+  }
+}
+
 }  // namespace
 }  // namespace lcg
 
@@ -127,6 +275,39 @@ lcg_status lcg_extract(lcg_grammar_t g, uint32_t nq, const uint32_t* d_j, const 
                                      " out of range (string index, or start + len beyond the "
                                      "string, or len not in 1.." +
                                      std::to_string(LCG_EXTRACT_MAX) + ")"};
+  });
+}
+
+lcg_status lcg_lce(lcg_grammar_t g, uint32_t nq, const uint32_t* d_j1, const uint64_t* d_p1,
+                   const uint32_t* d_j2, const uint64_t* d_p2, uint32_t backward,
+                   uint64_t* d_out, hipStream_t stream) {
+  return guard([&] {
+    if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    if (backward > 1) throw LcgError{LCG_EINVAL, "backward must be 0 or 1"};
+    if (!nq) return;
+    if (!d_j1 || !d_p1 || !d_j2 || !d_p2 || !d_out)
+      throw LcgError{LCG_EINVAL, "NULL query or output array"};
+    if (!g->k) throw LcgError{LCG_EINVAL, "the grammar holds no string"};
+    if (g->levels.size() >= (size_t)kMaxLv) throw LcgError{LCG_EOVERFLOW, "too many levels"};
+    ensure_explen(g, stream);
+    DBuf<unsigned int> bad;
+    bad.need(1, stream);
+    launch_zero(bad.p, sizeof(unsigned int), stream);
+    const unsigned grid = std::min<uint32_t>((nq + 63) / 64, 16384u);
+    if (backward)
+      k_lce<true><<<grid, 64, 0, stream>>>(g->level_ptrs.p, g->explen_ptrs.p, g->c_level.p,
+                                          g->c_sym.p, g->k, nq, d_j1, d_p1, d_j2, d_p2, d_out,
+                                          bad.p);
+    else
+      k_lce<false><<<grid, 64, 0, stream>>>(g->level_ptrs.p, g->explen_ptrs.p, g->c_level.p,
+                                           g->c_sym.p, g->k, nq, d_j1, d_p1, d_j2, d_p2, d_out,
+                                           bad.p);
+    HIP_CHECK(hipGetLastError());
+    const unsigned int nbad = read_dev(bad.p, stream);
+    if (nbad)
+      throw LcgError{LCG_EINVAL, std::to_string(nbad) + " quer" + (nbad == 1 ? "y" : "ies") +
+                                     " out of range (string index, or position beyond the "
+                                     "string's end)"};
   });
 }
 

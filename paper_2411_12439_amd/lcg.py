@@ -30,7 +30,7 @@ EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_exp
            "lcg_info", "lcg_level_size", "lcg_level_copy", "lcg_c_copy", "lcg_stats",
            "lcg_stats_clear", "lcg_build_bytes", "lcg_free", "lcg_release_pool", "lcg_last_error",
            "lcg_postprocess", "lcg_slp_size", "lcg_slp_stats", "lcg_slp_device", "lcg_slp_copy",
-           "lcg_slp_expand_strings", "lcg_slp_free", "lcg_extract", "lcg_build_file")
+           "lcg_slp_expand_strings", "lcg_slp_free", "lcg_extract", "lcg_build_file", "lcg_lce")
 
 EXTRACT_MAX = 2048
 
@@ -129,6 +129,8 @@ def lib():
                                  u64p]
     L.lcg_build_file.restype = st
     L.lcg_extract.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, vp, vp, vp]
+    L.lcg_lce.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, vp, ctypes.c_uint32, vp, vp]
+    L.lcg_lce.restype = st
     L.lcg_extract.restype = st
     L.lcg_slp_free.argtypes = [vp]
     L.lcg_slp_free.restype = None
@@ -292,6 +294,21 @@ class Grammar:
                                  ctypes.c_void_p(offs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                  _stream(stream)))
         return out[:int(offs[-1].item()) if nq else 0], offs
+
+    def lce(self, j1, p1, j2, p2, backward=False, stream=None):
+        """Longest common extension of position pairs (lcg_lce): int64 device tensor."""
+        import torch
+        dev = "cuda"
+        j1 = torch.as_tensor(j1, dtype=torch.int32, device=dev).contiguous()
+        j2 = torch.as_tensor(j2, dtype=torch.int32, device=dev).contiguous()
+        p1 = torch.as_tensor(p1, dtype=torch.int64, device=dev).contiguous()
+        p2 = torch.as_tensor(p2, dtype=torch.int64, device=dev).contiguous()
+        out = torch.zeros(max(j1.numel(), 1), dtype=torch.int64, device=dev)
+        _check(lib().lcg_lce(self.h, j1.numel(), ctypes.c_void_p(j1.data_ptr()),
+                             ctypes.c_void_p(p1.data_ptr()), ctypes.c_void_p(j2.data_ptr()),
+                             ctypes.c_void_p(p2.data_ptr()), 1 if backward else 0,
+                             ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+        return out[:j1.numel()]
 
     def postprocess(self, rl=True, simp=True, stream=None):
         """RL and/or Simp (Sec. 2.2) on the device: a new Slp (this grammar is unchanged)."""

@@ -1,9 +1,11 @@
-"""Random access (lcg_extract) against slices of the input.
+"""Random access (lcg_extract) and longest common extensions (lcg_lce).
 
-The expected bytes are the input itself (the grammar derives it exactly), so
-every query is compared byte for byte.  Queries hit string starts and ends,
-single bytes, the maximum length, strings of length one (C at level 0) and
-long level-1 rules (homopolymers).
+Extraction is checked against slices of the input (the grammar derives it
+exactly), byte for byte: queries hit string starts and ends, single bytes,
+the maximum length, strings of length one (C at level 0) and long level-1
+rules (homopolymers).  LCE answers are checked against the oracle's plain
+byte comparison, in both directions, on random pairs and on pairs at the same
+offset of copies of one base (long matches), including string ends.
 """
 import numpy as np
 import pytest
@@ -110,3 +112,69 @@ def test_full_bacterial_random_access(L):
     g = L.build(t, o, seed=SEED)
     rng = np.random.default_rng(9)
     _check(L, g, text, off, *_queries(rng, off, 4000, L.EXTRACT_MAX))
+
+
+# ------------------------------------------------ longest common extension
+def _lce_queries(rng, off, nq, base_of=None):
+    """Half random pairs, half pairs at the same offset of copies of the same base
+    (long matches), plus string ends."""
+    lens_s = np.diff(off.astype(np.int64))
+    k = len(lens_s)
+    j1 = rng.integers(0, k, nq)
+    j2 = rng.integers(0, k, nq)
+    if base_of is not None:
+        same = np.nonzero(np.arange(nq) % 2 == 0)[0]
+        for q in same:
+            cands = np.nonzero(base_of == base_of[j1[q]])[0]
+            j2[q] = cands[rng.integers(0, len(cands))]
+    p1 = (rng.random(nq) * (lens_s[j1] + 1)).astype(np.int64)
+    p2 = (rng.random(nq) * (lens_s[j2] + 1)).astype(np.int64)
+    if base_of is not None:
+        p2[::2] = np.minimum(p1[::2], lens_s[j2[::2]])
+    j1 = np.concatenate([j1, np.arange(k), np.arange(k)])
+    j2 = np.concatenate([j2, np.arange(k), (np.arange(k) + 1) % k])
+    p1 = np.concatenate([p1, lens_s, np.zeros(k, np.int64)])
+    p2 = np.concatenate([p2, np.zeros(k, np.int64), np.zeros(k, np.int64)])
+    return j1, p1, j2, p2
+
+
+@pytest.mark.parametrize("backward", [False, True])
+@pytest.mark.parametrize("config,scale", [("tiny", 1.0), ("bacterial", 0.01), ("repeats", 0.0005)])
+def test_lce_equals_oracle(L, config, scale, backward):
+    from oracle import oracle as O
+    text, off = D.make_config(config, scale=scale)
+    t, o = L.to_device(text, off)
+    g = L.build(t, o, seed=SEED)
+    rng = np.random.default_rng(21)
+    base_of = np.arange(len(off) - 1) % (4 if config == "bacterial" else 1)
+    q = _lce_queries(rng, off, 4000, base_of)
+    got = g.lce(*q, backward=backward).cpu().numpy()
+    want = O.lce(text, off, q[0], q[1], q[2], q[3], backward).astype(np.int64)
+    assert np.array_equal(got, want), int(np.nonzero(got != want)[0][0])
+
+
+@pytest.mark.parametrize("backward", [False, True])
+def test_lce_edge_strings(L, backward):
+    from oracle import oracle as O
+    rng = np.random.default_rng(22)
+    dna = D.BASES[rng.integers(0, 4, 5000)].tobytes()
+    strings = [b"A", b"A", b"AA", b"T" * 3000, b"T" * 2999 + b"G", dna, dna[:2500] + b"N" + dna[2501:],
+               dna[7:], b"ACG" * 1000, b"ACG" * 999 + b"ACC", b"C"]
+    text, off = O.pack(strings)
+    t, o = L.to_device(text, off)
+    for g in (L.build(t, o, seed=SEED), L.build(t, o, seed=SEED, mode=L.MODE_PLAIN)):
+        q = _lce_queries(rng, off, 3000)
+        got = g.lce(*q, backward=backward).cpu().numpy()
+        want = O.lce(text, off, q[0], q[1], q[2], q[3], backward).astype(np.int64)
+        assert np.array_equal(got, want), int(np.nonzero(got != want)[0][0])
+
+
+def test_lce_rejects_out_of_range(L):
+    text, off = D.make_config("tiny", scale=0.05)
+    t, o = L.to_device(text, off)
+    g = L.build(t, o, seed=SEED)
+    n0 = int(off[1] - off[0])
+    for args in (([0], [n0 + 1], [0], [0]), ([len(off) - 1], [0], [0], [0])):
+        with pytest.raises(L.LcgError) as e:
+            g.lce(*args)
+        assert e.value.name == "LCG_EINVAL"
