@@ -142,6 +142,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--rounds", action="store_true", help="per-round phase table on stderr")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the timed builds: no decompression, post-processing, random "
+                         "access, LCE or streaming legs (for profiling the build alone)")
     ap.add_argument("--serving-seconds", type=float, default=4.0,
                     help="seconds per offered load of the serving leg (0 = skip)")
     ap.add_argument("--serving-loads", default="0.5,2,8")
@@ -262,6 +265,15 @@ def main():
            "tuned_options": tuned,
            "roofline": roofline}
 
+    if not args.no_extra:
+        extra_legs(args, out, text, off, t, o, n, k, seed)
+    plain_and_rest(args, out, text, off, t, o, n, seed, value)
+
+
+def extra_legs(args, out, text, off, t, o, n, k, seed):
+    """Decompression, post-processing, random access, LCE and streaming legs."""
+    import torch
+    from paper_2411_12439_amd import lcg
     # decompression of the whole collection (the inverse path): all strings
     # expanded together, top-down over the levels
     g = lcg.build(t, o, seed=seed)
@@ -443,6 +455,12 @@ def main():
     finally:
         os.unlink(path)
 
+
+
+def plain_and_rest(args, out, text, off, t, o, n, seed, value):
+    """Plain form, serving and the CPU baseline; prints the JSON line."""
+    import torch
+    from paper_2411_12439_amd import datagen, lcg
     if not args.no_plain:
         g = lcg.build(t, o, seed=seed, mode=lcg.MODE_PLAIN)
         g.free()
