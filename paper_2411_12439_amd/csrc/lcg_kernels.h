@@ -91,7 +91,12 @@ void launch_commit(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t
                    const uint64_t* key, const uint64_t* pstart, const uint32_t* plen,
                    const void* content, const uint32_t* fnew, const uint32_t* fprev, LevelHash h,
                    uint32_t u_prev, uint64_t q_prev, uint64_t* rule_off, void* rule_rhs,
-                   uint32_t* rule_fp, uint32_t* sym_next, uint32_t* fnext, hipStream_t s);
+                   uint32_t* rule_fp, uint32_t* sym_next, uint32_t* fnext, uint64_t u_new,
+                   uint32_t* nlist, uint64_t* nqoff, hipStream_t s);
+// commit: when the new rules (u_new, known on the host) are fewer than
+// d / kCommitListRatio, the new phrases are listed first and committed one
+// thread per rule (nlist: u_new uint32, nqoff: u_new uint64 of scratch)
+constexpr uint64_t kCommitListRatio = 4;
 void launch_rehash(const Slot* old_t, uint64_t old_cap, Slot* new_t, uint64_t new_mask,
                    Counters* ctr, hipStream_t s);
 

@@ -1307,6 +1307,64 @@ __device__ __forceinline__ unsigned long long wave_excl_scan(unsigned long long 
 // the F values of its symbols, fprev), a long one brings it from emit (fnew).
 // The slot then holds the rank and F side by side: one 8-byte load gives a
 // later occurrence both.
+// Commit the new phrase o as rule r (right-hand side at q): its content
+// (from the phrase for a long key, from the key itself for an exact one),
+// its F (Eq. 4 from the symbols' F, once per rule, for exact keys) and
+// (F, rank) into its slot.
+template <typename Sym>
+__device__ __forceinline__ void commit_one(uint64_t o, uint32_t r, uint64_t q, uint64_t kk,
+                                           uint32_t L, uint32_t sidx, Slot* table,
+                                           const uint64_t* __restrict__ pstart,
+                                           const Sym* __restrict__ content,
+                                           const uint32_t* __restrict__ fnew,
+                                           const uint32_t* __restrict__ fprev, LevelHash h,
+                                           uint64_t* __restrict__ rule_off,
+                                           Sym* __restrict__ rule_rhs,
+                                           uint32_t* __restrict__ rule_fp) {
+  constexpr bool kBytes = sizeof(Sym) == 1;
+  uint32_t F;
+  if (kk & kLongTag) {
+    // eight symbols per step, so that their loads are in flight together
+    const Sym* src = content + pstart[o];
+    for (uint32_t i = 0; i < L; i += 8) {
+      Sym v[8];
+#pragma unroll
+      for (uint32_t x = 0; x < 8; ++x) v[x] = i + x < L ? src[i + x] : Sym(0);
+#pragma unroll
+      for (uint32_t x = 0; x < 8; ++x)
+        if (i + x < L) rule_rhs[q + i + x] = v[x];
+    }
+    F = fnew[o];
+  } else {
+    // at most 7 symbols (4 above level 1): gather their F first, then Horner
+    constexpr uint32_t kMaxExact = kBytes ? 7 : 4;
+    uint32_t v[kMaxExact], f[kMaxExact];
+#pragma unroll
+    for (uint32_t x = 0; x < kMaxExact; ++x) {
+      v[x] = x < L ? key_sym<kBytes>(kk, x) : 0u;
+      f[x] = x < L ? fprev[v[x]] : 0u;
+    }
+    uint64_t S = 0;
+#pragma unroll
+    for (int x = kMaxExact - 1; x >= 0; --x) {
+      if ((uint32_t)x < L) {
+        rule_rhs[q + x] = (Sym)v[x];
+        S = addmod61(mulmod61(S, h.c), f[x]);
+      }
+    }
+    F = (uint32_t)(addmod61(mulmod61(h.a, S), h.b) & 0xFFFFFFFFULL);
+  }
+  rule_off[r + 1] = q + L;
+  rule_fp[r] = F;
+  Slot* sl = &table[sidx];
+  *reinterpret_cast<uint64_t*>(&sl->minocc) = (uint64_t)F | ((uint64_t)r << 32);
+  // a long key's slot word switches from the claiming occurrence to the rank
+  if (kk & kLongTag) sl->w0 = (kk & kHiMask) | r;
+}
+
+// one wave per flag word of 64 phrases: ranks from the word's count base and
+// the wave's ballot prefix, right-hand-side offsets from the word's length
+// base and a wave scan
 template <typename Sym>
 __global__ __launch_bounds__(256) void k_commit_new(uint64_t d, const uint64_t* __restrict__ d_dev,
                                                     const uint32_t* __restrict__ slot_idx,
@@ -1329,57 +1387,69 @@ __global__ __launch_bounds__(256) void k_commit_new(uint64_t d, const uint64_t* 
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t wd = blockIdx.x * (uint64_t)(blockDim.x / 64) + (threadIdx.x >> 6);
   if (wd >= W) return;  // uniform in the wave
-  {
-    const uint64_t fw = newbits[wd];
-    if (!fw) return;  // uniform in the wave
-    const uint64_t o = wd * 64 + lane;
-    const bool isnew = (fw >> lane) & 1ULL;
-    const uint64_t kk = isnew ? key[o] : 0;
-    const uint32_t L = isnew ? key_len<kBytes>(kk, plen, o) : 0;
-    const unsigned long long excl = wave_excl_scan(L);
-    if (!isnew) return;
-    const uint32_t r = u_prev + (uint32_t)(wcnt_base[wd] +
-                                           __builtin_popcountll(fw & ((1ULL << lane) - 1ULL)));
-    const uint64_t q = q_prev + wlen_base[wd] + excl;
-    const uint32_t sidx = slot_idx[o];
-    uint32_t F;
-    if (kk & kLongTag) {
-      // eight symbols per step, so that their loads are in flight together
-      const Sym* src = content + pstart[o];
-      for (uint32_t i = 0; i < L; i += 8) {
-        Sym v[8];
-#pragma unroll
-        for (uint32_t x = 0; x < 8; ++x) v[x] = i + x < L ? src[i + x] : Sym(0);
-#pragma unroll
-        for (uint32_t x = 0; x < 8; ++x)
-          if (i + x < L) rule_rhs[q + i + x] = v[x];
-      }
-      F = fnew[o];
-    } else {
-      // at most 7 symbols (4 above level 1): gather their F first, then Horner
-      constexpr uint32_t kMaxExact = kBytes ? 7 : 4;
-      uint32_t v[kMaxExact], f[kMaxExact];
-#pragma unroll
-      for (uint32_t x = 0; x < kMaxExact; ++x) {
-        v[x] = x < L ? key_sym<kBytes>(kk, x) : 0u;
-        f[x] = x < L ? fprev[v[x]] : 0u;
-      }
-      uint64_t S = 0;
-#pragma unroll
-      for (int x = kMaxExact - 1; x >= 0; --x) {
-        if ((uint32_t)x < L) {
-          rule_rhs[q + x] = (Sym)v[x];
-          S = addmod61(mulmod61(S, h.c), f[x]);
-        }
-      }
-      F = (uint32_t)(addmod61(mulmod61(h.a, S), h.b) & 0xFFFFFFFFULL);
+  const uint64_t fw = newbits[wd];
+  if (!fw) return;  // uniform in the wave
+  const uint64_t o = wd * 64 + lane;
+  const bool isnew = (fw >> lane) & 1ULL;
+  const uint64_t kk = isnew ? key[o] : 0;
+  const uint32_t L = isnew ? key_len<kBytes>(kk, plen, o) : 0;
+  const unsigned long long excl = wave_excl_scan(L);
+  if (!isnew) return;
+  const uint32_t r = u_prev + (uint32_t)(wcnt_base[wd] +
+                                         __builtin_popcountll(fw & ((1ULL << lane) - 1ULL)));
+  const uint64_t q = q_prev + wlen_base[wd] + excl;
+  commit_one<Sym>(o, r, q, kk, L, slot_idx[o], table, pstart, content, fnew, fprev, h, rule_off,
+                  rule_rhs, rule_fp);
+}
+
+// When few phrases are new, one wave per word leaves most lanes idle: the new
+// phrases are first listed in rank order (one thread per word walks its set
+// bits, keeping a running right-hand-side offset) and then committed one
+// thread per rule.
+template <bool BYTES>
+__global__ void k_new_list(uint64_t W, const uint64_t* __restrict__ newbits,
+                           const uint64_t* __restrict__ wcnt_base,
+                           const uint64_t* __restrict__ wlen_base, const uint64_t* __restrict__ key,
+                           const uint32_t* __restrict__ plen, uint32_t* __restrict__ list,
+                           uint64_t* __restrict__ qoff) {
+  for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < W;
+       w += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t bits = newbits[w];
+    if (!bits) continue;
+    uint64_t idx = wcnt_base[w], run = wlen_base[w];
+    while (bits) {
+      const uint64_t o = w * 64 + __builtin_ctzll(bits);
+      bits &= bits - 1;
+      list[idx] = (uint32_t)o;
+      qoff[idx] = run;
+      run += key_len<BYTES>(key[o], plen, o);
+      ++idx;
     }
-    rule_off[r + 1] = q + L;
-    rule_fp[r] = F;
-    Slot* sl = &table[sidx];
-    *reinterpret_cast<uint64_t*>(&sl->minocc) = (uint64_t)F | ((uint64_t)r << 32);
-    // a long key's slot word switches from the claiming occurrence to the rank
-    if (kk & kLongTag) sl->w0 = (kk & kHiMask) | r;
+  }
+}
+
+template <typename Sym>
+__global__ __launch_bounds__(256) void k_commit_list(uint64_t u_new, const uint32_t* __restrict__ list,
+                                                     const uint64_t* __restrict__ qoff,
+                                                     const uint32_t* __restrict__ slot_idx,
+                                                     Slot* table, const uint64_t* __restrict__ key,
+                                                     const uint64_t* __restrict__ pstart,
+                                                     const uint32_t* __restrict__ plen,
+                                                     const Sym* __restrict__ content,
+                                                     const uint32_t* __restrict__ fnew,
+                                                     const uint32_t* __restrict__ fprev, LevelHash h,
+                                                     uint32_t u_prev, uint64_t q_prev,
+                                                     uint64_t* __restrict__ rule_off,
+                                                     Sym* __restrict__ rule_rhs,
+                                                     uint32_t* __restrict__ rule_fp) {
+  constexpr bool kBytes = sizeof(Sym) == 1;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < u_new;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t o = list[i];
+    const uint64_t kk = key[o];
+    commit_one<Sym>(o, u_prev + (uint32_t)i, q_prev + qoff[i], kk, key_len<kBytes>(kk, plen, o),
+                    slot_idx[o], table, pstart, content, fnew, fprev, h, rule_off, rule_rhs,
+                    rule_fp);
   }
 }
 
@@ -1406,10 +1476,34 @@ void launch_commit(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t
                    const uint64_t* key, const uint64_t* pstart, const uint32_t* plen,
                    const void* content, const uint32_t* fnew, const uint32_t* fprev, LevelHash h,
                    uint32_t u_prev, uint64_t q_prev, uint64_t* rule_off, void* rule_rhs,
-                   uint32_t* rule_fp, uint32_t* sym_next, uint32_t* fnext, hipStream_t s) {
+                   uint32_t* rule_fp, uint32_t* sym_next, uint32_t* fnext, uint64_t u_new,
+                   uint32_t* nlist, uint64_t* nqoff, hipStream_t s) {
   if (!d) return;
   const unsigned g = grid_for((d + 63) / 64, 4);  // one wave per flag word
-  if (bytes)
+  if (!d_dev && nlist && nqoff && u_new * kCommitListRatio < d) {
+    const uint64_t W = (d + 63) / 64;
+    unsigned gw = grid_for(W, 256);
+    if (gw > kPersistentBlocks) gw = kPersistentBlocks;
+    unsigned gu = grid_for(u_new, 256);
+    if (gu > kPersistentBlocks * 4) gu = kPersistentBlocks * 4;
+    if (bytes) {
+      k_new_list<true><<<gw, 256, 0, s>>>(W, newbits, wcnt_base, wlen_base, key, plen, nlist, nqoff);
+      if (u_new)
+        k_commit_list<uint8_t><<<gu, 256, 0, s>>>(
+            u_new, nlist, nqoff, slot_idx, table, key, pstart, plen,
+            static_cast<const uint8_t*>(content), fnew, fprev, h, u_prev, q_prev, rule_off,
+            static_cast<uint8_t*>(rule_rhs), rule_fp);
+    } else {
+      k_new_list<false><<<gw, 256, 0, s>>>(W, newbits, wcnt_base, wlen_base, key, plen, nlist,
+                                           nqoff);
+      if (u_new)
+        k_commit_list<uint32_t><<<gu, 256, 0, s>>>(
+            u_new, nlist, nqoff, slot_idx, table, key, pstart, plen,
+            static_cast<const uint32_t*>(content), fnew, fprev, h, u_prev, q_prev, rule_off,
+            static_cast<uint32_t*>(rule_rhs), rule_fp);
+    }
+    LCG_LAUNCH_CHECK("commit_list");
+  } else if (bytes)
     k_commit_new<uint8_t><<<g, 256, 0, s>>>(
         d, d_dev, slot_idx, table, newbits, wcnt_base, wlen_base, key, pstart, plen,
         static_cast<const uint8_t*>(content), fnew, fprev, h, u_prev, q_prev, rule_off,

@@ -111,8 +111,8 @@ struct Work {
   DBuf<uint32_t> plen, slot_idx;
   DBuf<uint32_t> sym[2], fpv[2];
   DBuf<uint64_t> off[2];
-  DBuf<uint64_t> newbits, wcnt, wlen, wcnt_base, wlen_base;
-  DBuf<uint32_t> lut;
+  DBuf<uint64_t> newbits, wcnt, wlen, wcnt_base, wlen_base, nqoff;
+  DBuf<uint32_t> lut, nlist;
   DBuf<Counters> ctr, fin;
   DBuf<uint8_t> content8, hll_part;
   DBuf<TileSeg> tile_seg;
@@ -120,9 +120,9 @@ struct Work {
   DBuf<struct TailRec> tail;
   void release_after(hipStream_t s) {
     DBuf<uint64_t>* b64[] = {&bits, &tile_cnt, &tile_base, &scan_tmp, &pstart, &key, &off[0],
-                             &off[1], &newbits, &wcnt, &wlen, &wcnt_base, &wlen_base};
+                             &off[1], &newbits, &wcnt, &wlen, &wcnt_base, &wlen_base, &nqoff};
     DBuf<uint32_t>* b32[] = {&plen, &slot_idx, &sym[0], &sym[1], &fpv[0], &fpv[1], &lut,
-                             &content32, &remap[0], &remap[1], &rest};
+                             &content32, &remap[0], &remap[1], &rest, &nlist};
     for (auto* b : b64) b->reset_after(s);
     for (auto* b : b32) b->reset_after(s);
     ctr.reset_after(s);
@@ -310,9 +310,13 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
   }
   // F of the level-(lv-1) symbols: h^0 of the bytes, else the previous level's rules
   const uint32_t* fprev = bytes ? w.lut.p : g->levels[lv - 2].fp.p;
+  if (u_new * kCommitListRatio < d) {
+    w.nlist.need(std::max<uint64_t>(u_new, 1), s);
+    w.nqoff.need(std::max<uint64_t>(u_new, 1), s);
+  }
   launch_commit(bytes, d, nullptr, w.slot_idx.p, L.table.p, w.newbits.p, w.wcnt_base.p, w.wlen_base.p,
                 w.key.p, w.pstart.p, w.plen.p, content, fnew, fprev, g->H.lv[lv], L.u, L.q,
-                L.off.p, rule_rhs, L.fp.p, sym_next, fnext, s);
+                L.off.p, rule_rhs, L.fp.p, sym_next, fnext, u_new, w.nlist.p, w.nqoff.p, s);
   if (pe) pe->rec(6, s);
   L.u += (uint32_t)u_new;
   L.q += q_new;
@@ -427,7 +431,8 @@ static void tail_rounds(lcg_grammar* g, uint32_t lv, uint64_t n_i, uint64_t acti
     const uint32_t* fprev = bytes ? w.lut.p : g->levels[lv - 2].fp.p;
     launch_commit(bytes, d_b, &rec->d, w.slot_idx.p, L.table.p, w.newbits.p, w.wcnt_base.p,
                   w.wlen_base.p, w.key.p, w.pstart.p, w.plen.p, content, w.fpv[cur].p, fprev,
-                  g->H.lv[lv], L.u, L.q, L.off.p, rule_rhs, L.fp.p, w.sym[cur].p, w.fpv[cur].p, s);
+                  g->H.lv[lv], L.u, L.q, L.off.p, rule_rhs, L.fp.p, w.sym[cur].p, w.fpv[cur].p,
+                  0, nullptr, nullptr, s);
     if (pe) pe->rec(6, s);
     launch_segments(cur_off, k, w.bits.p, w.tile_base.p, d_b, &rec->d, w.off[cur].p, s);
     launch_finish(cur_off, w.off[cur].p, k, w.sym[cur].p, lv, g->c_level.p + c_base,
