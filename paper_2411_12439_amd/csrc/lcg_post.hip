@@ -50,6 +50,10 @@ struct lcg_slp {
   // children (nonterminals that are not leaves) before t
   lcg::DBuf<uint64_t> S, N;
   lcg::DBuf<uint8_t> meta;  // RuleMeta per rule
+  // item children of the item children (the step after next), per rule
+  lcg::DBuf<uint64_t> gnt;
+  // per rule: E, with the top bit set for a leaf
+  lcg::DBuf<uint64_t> el;
   bool lens_ready = false;
 };
 
@@ -638,101 +642,186 @@ __global__ void k_slp_meta(const uint64_t* __restrict__ off, const uint32_t* __r
   }
 }
 
-// Per item, once: its child counts (all: mult * |rhs|; items: mult * ntx) and
-// what its children need: the rule's first position, |rhs|, ntx, the period,
-// the item's position minus S[a] and N[a].
-struct SlpItem {
-  uint64_t a, period, pos_s, na;
-  uint32_t q, nt;
-};
-
-__global__ void k_slp_count(const uint32_t* __restrict__ sym, const uint64_t* __restrict__ pos,
-                            uint64_t m, const RuleMeta* __restrict__ meta,
-                            uint64_t* __restrict__ cnt, uint64_t* __restrict__ ntc,
-                            SlpItem* __restrict__ items) {
-  PP_LOOP(i, m) {
-    const RuleMeta mt = meta[sym[i] - 256];
-    cnt[i] = (uint64_t)mt.mult * mt.q;
-    ntc[i] = (uint64_t)mt.mult * mt.ntx;
-    SlpItem it;
-    it.a = mt.a;
-    it.period = mt.period;
-    it.pos_s = pos[i] - mt.sa;
-    it.na = mt.na;
-    it.q = mt.q;
-    it.nt = mt.ntx;
-    items[i] = it;
+// per rule: the item children of its item children, over all repetitions
+// (sizes the step after next)
+__global__ void k_slp_gnt(const uint64_t* __restrict__ off, const uint32_t* __restrict__ rhs,
+                          const uint64_t* __restrict__ N, const RuleMeta* __restrict__ meta,
+                          uint32_t g, uint64_t* __restrict__ gnt) {
+  PP_LOOP(r, g) {
+    const uint64_t a = off[r], b = off[r + 1];
+    uint64_t sum = 0;
+    for (uint64_t t = a; t < b; ++t) {
+      if (N[t + 1] == N[t]) continue;  // a terminal or a leaf
+      const RuleMeta c = meta[rhs[t] - 256];
+      sum += (uint64_t)c.mult * c.ntx;
+    }
+    gnt[r] = sum * meta[r].mult;
   }
 }
 
-// One step, balanced over children: block b takes children [b*kChunk,
-// (b+1)*kChunk) of the items' concatenated child lists (cbase: exclusive scan
-// of the per-item child counts), finds each child's item by binary search over
-// the chunk's item bounds in LDS, and computes the child from S and N:
-// repetition rep = v / q and position k = v % q inside the item's rule give its
-// byte position (item position + rep * period + S - S[a]) and, for an item
-// child, its slot among the next step's items (nbase + rep * ntx + N - N[a]).
-// Terminals and leaves are written to out.
-constexpr uint32_t kChunk = 2048;
-__global__ __launch_bounds__(kPB) void k_slp_children(
-    const SlpItem* __restrict__ items, uint64_t m, const uint64_t* __restrict__ cbase,
-    const uint64_t* __restrict__ nbase, uint64_t total, const uint32_t* __restrict__ rhs,
-    const uint64_t* __restrict__ S, const uint64_t* __restrict__ N,
-    const RuleMeta* __restrict__ meta, uint32_t* __restrict__ nsym, uint64_t* __restrict__ npos,
-    uint8_t* __restrict__ out) {
-  __shared__ uint64_t s_cb[kChunk + 1];
-  __shared__ uint64_t s_i0, s_n;
-  const uint64_t nchunks = (total + kChunk - 1) / kChunk;
-  for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-    const uint64_t c0 = ch * kChunk;
-    const uint64_t c1 = min<uint64_t>(c0 + kChunk, total);
-    if (threadIdx.x == 0) {
-      // items holding children c0 and c1 - 1: the last i with cbase[i] <= c
-      uint64_t lo = 0, hi = m - 1;
-      while (lo < hi) {
-        const uint64_t mid = (lo + hi + 1) >> 1;
-        if (cbase[mid] <= c0) lo = mid; else hi = mid - 1;
-      }
-      const uint64_t i0 = lo;
-      hi = m - 1;
-      while (lo < hi) {
-        const uint64_t mid = (lo + hi + 1) >> 1;
-        if (cbase[mid] <= c1 - 1) lo = mid; else hi = mid - 1;
-      }
-      s_i0 = i0;
-      s_n = lo - i0 + 1;  // <= kChunk: every item has at least one child
-    }
-    __syncthreads();
-    const uint64_t i0 = s_i0, ni = s_n;
-    for (uint64_t j = threadIdx.x; j < ni; j += blockDim.x) s_cb[j] = cbase[i0 + j];
-    __syncthreads();
-    for (uint64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
-      uint32_t lo = 0, hi = (uint32_t)ni - 1;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (s_cb[mid] <= c) lo = mid; else hi = mid - 1;
-      }
-      const uint64_t i = i0 + lo;
-      const SlpItem it = items[i];
-      const uint64_t v = c - s_cb[lo];
-      const uint64_t rep = v / it.q, k = v - rep * it.q;
-      const uint64_t t = it.a + k;
-      const uint32_t y = rhs[t];
-      const uint64_t p = it.pos_s + rep * it.period + S[t];
-      if (y < 256) {
-        out[p] = (uint8_t)y;
-      } else if (N[t + 1] == N[t]) {  // a leaf: its bytes, mult times
+constexpr uint64_t kLeafBit = 1ull << 63;
+
+// An item's children [v0, v1) (v = rep * q + k): terminals and leaves are
+// written to out, item children go to slots o, o+1, ... of the next step.
+// The first child's position comes from S; the others follow by adding the
+// children's expansion lengths.
+__device__ __forceinline__ void slp_item_children(const RuleMeta& mt, uint64_t pos, uint64_t v0,
+                                                  uint64_t v1, uint64_t o,
+                                                  const uint32_t* __restrict__ rhs,
+                                                  const uint64_t* __restrict__ S,
+                                                  const uint64_t* __restrict__ el,
+                                                  const RuleMeta* __restrict__ meta,
+                                                  uint32_t* __restrict__ nsym,
+                                                  uint64_t* __restrict__ npos,
+                                                  uint8_t* __restrict__ out) {
+  uint64_t rep = v0 / mt.q, k = v0 - rep * mt.q;
+  uint64_t p = pos + rep * mt.period + (k ? S[mt.a + k] - mt.sa : 0);
+  for (uint64_t v = v0; v < v1; ++v) {
+    const uint32_t y = rhs[mt.a + k];
+    if (y < 256) {
+      out[p] = (uint8_t)y;
+      p += 1;
+    } else {
+      const uint64_t e = el[y - 256];
+      if (e & kLeafBit) {  // a leaf: its bytes, mult times
         const RuleMeta lf = meta[y - 256];
         uint64_t w = p;
         for (uint32_t rr = 0; rr < lf.mult; ++rr)
           for (uint32_t kk = 0; kk < lf.q; ++kk) out[w++] = (uint8_t)rhs[lf.a + kk];
       } else {
-        const uint64_t slot = nbase[i] + rep * it.nt + (N[t] - it.na);
-        nsym[slot] = y;
-        npos[slot] = p;
+        nsym[o] = y;
+        npos[o] = p;
+        ++o;
+      }
+      p += e & ~kLeafBit;
+    }
+    if (++k == mt.q) k = 0, ++rep;
+  }
+}
+
+__global__ void k_slp_el(const uint64_t* __restrict__ E, const uint32_t* __restrict__ nt,
+                         uint32_t g, uint64_t* __restrict__ el) {
+  PP_LOOP(r, g) el[r] = E[r] | ((nt[r] == 0 && E[r] <= kLeaf) ? kLeafBit : 0);
+}
+
+// block-wide exclusive scan of v (s_w: kPB / 64 words); *tot gets the sum
+__device__ __forceinline__ unsigned long long block_scan_u64(unsigned long long v,
+                                                             unsigned long long* s_w,
+                                                             unsigned long long* tot) {
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  unsigned long long incl = v;
+  for (int d = 1; d < 64; d <<= 1) {
+    const unsigned long long o = __shfl_up(incl, d);
+    if ((int)lane >= d) incl += o;
+  }
+  if (lane == 63) s_w[wv] = incl;
+  __syncthreads();
+  unsigned long long before = 0, t = 0;
+  for (uint32_t w = 0; w < kPB / 64; ++w) {
+    before += w < wv ? s_w[w] : 0;
+    t += s_w[w];
+  }
+  __syncthreads();
+  *tot = t;
+  return before + incl - v;
+}
+
+// One step over items (sym, pos) or over pieces of big items (vi: item
+// index, v0: first child; NULL for whole items).  An item with at most kSmall
+// children is handled whole by one thread; a bigger one is listed in big[]
+// (whole-item pass only) and handled later in pieces of kSmall children.  Item
+// children are reserved per block (scan + one atomicAdd); the step after
+// next is sized on the way from GNT.
+constexpr uint64_t kSmall = 64;
+__global__ __launch_bounds__(kPB) void k_slp_step(
+    const uint32_t* __restrict__ sym, const uint64_t* __restrict__ pos, uint64_t m,
+    const uint32_t* __restrict__ vi, const uint64_t* __restrict__ v0s,
+    const RuleMeta* __restrict__ meta, const uint64_t* __restrict__ gnt,
+    const uint32_t* __restrict__ rhs, const uint64_t* __restrict__ S, const uint64_t* __restrict__ N,
+    const uint64_t* __restrict__ el, uint32_t* __restrict__ nsym, uint64_t* __restrict__ npos, unsigned long long* ncount,
+    unsigned long long* gcount, uint32_t* __restrict__ big, unsigned long long* nbig,
+    uint8_t* __restrict__ out) {
+  __shared__ unsigned long long s_w[kPB / 64];
+  __shared__ unsigned long long s_base;
+  unsigned long long gsum = 0;
+  for (uint64_t b0 = blockIdx.x * (uint64_t)kPB; b0 < m; b0 += (uint64_t)gridDim.x * kPB) {
+    const uint64_t j = b0 + threadIdx.x;
+    RuleMeta mt{};
+    uint64_t p = 0, v0 = 0, v1 = 0;
+    unsigned long long ntc = 0;
+    if (j < m) {
+      const uint64_t i = vi ? vi[j] : j;
+      mt = meta[sym[i] - 256];
+      p = pos[i];
+      const uint64_t cnt = (uint64_t)mt.mult * mt.q;
+      if (vi) {  // a piece of a big item
+        v0 = v0s[j];
+        v1 = min(cnt, v0 + kSmall);
+      } else if (cnt <= kSmall) {
+        v1 = cnt;
+        gsum += gnt[sym[i] - 256];
+      } else {  // big: listed for the pieces pass
+        big[atomicAdd(nbig, 1ull)] = (uint32_t)i;
+      }
+      // item children among [v0, v1): whole repetitions plus the partial ones
+      if (v1 > v0) {
+        const uint64_t q = mt.q, ntx = mt.ntx;
+        const uint64_t r0 = v0 / q, r1 = v1 / q, k0 = v0 - r0 * q, k1 = v1 - r1 * q;
+        // N prefixes inside the rule: items before position k
+        const uint64_t n0 = N[mt.a + k0] - mt.na, n1 = N[mt.a + k1] - mt.na;
+        ntc = (r1 - r0) * ntx + n1 - n0;
       }
     }
-    __syncthreads();  // s_cb is rewritten by the next chunk
+    unsigned long long tot;
+    const unsigned long long excl = block_scan_u64(ntc, s_w, &tot);
+    if (threadIdx.x == 0) s_base = tot ? atomicAdd(ncount, tot) : 0;
+    __syncthreads();
+    if (v1 > v0)
+      slp_item_children(mt, p, v0, v1, s_base + excl, rhs, S, el, meta, nsym, npos, out);
+    __syncthreads();  // s_base is rewritten by the next iteration
+  }
+  for (int d = 32; d; d >>= 1) gsum += __shfl_xor(gsum, d);
+  if ((threadIdx.x & 63) == 0 && gsum) atomicAdd(gcount, gsum);
+}
+
+// the pieces of the big items: (item, first child) for every kSmall children;
+// their GNT joins the step after next
+__global__ void k_slp_pieces(const uint32_t* __restrict__ big, uint64_t nb,
+                             const uint32_t* __restrict__ sym, const RuleMeta* __restrict__ meta,
+                             const uint64_t* __restrict__ gnt, uint32_t* __restrict__ vi,
+                             uint64_t* __restrict__ v0s, unsigned long long* npieces,
+                             unsigned long long* gcount) {
+  PP_LOOP(j, nb) {
+    const uint32_t i = big[j];
+    const uint32_t r = sym[i] - 256;
+    const RuleMeta mt = meta[r];
+    const uint64_t cnt = (uint64_t)mt.mult * mt.q;
+    const uint64_t np = (cnt + kSmall - 1) / kSmall;
+    const unsigned long long at = atomicAdd(npieces, (unsigned long long)np);
+    for (uint64_t x = 0; x < np; ++x) {
+      vi[at + x] = i;
+      v0s[at + x] = x * kSmall;
+    }
+    atomicAdd(gcount, (unsigned long long)gnt[r]);
+  }
+}
+
+// item children of the first step's items (*m_dev of them)
+__global__ void k_slp_first(const uint64_t* __restrict__ m_dev, const uint32_t* __restrict__ sym,
+                            const RuleMeta* __restrict__ meta, unsigned long long* total) {
+  PP_LOOP(i, *m_dev) {
+    const RuleMeta mt = meta[sym[i] - 256];
+    atomicAdd(total, (unsigned long long)mt.mult * mt.ntx);
+  }
+}
+
+// pieces of the big items of a step (at most this many per step)
+__global__ void k_slp_npieces(const uint32_t* __restrict__ big, uint64_t nb,
+                              const uint32_t* __restrict__ sym, const RuleMeta* __restrict__ meta,
+                              unsigned long long* npieces) {
+  PP_LOOP(j, nb) {
+    const RuleMeta mt = meta[sym[big[j]] - 256];
+    atomicAdd(npieces, ((uint64_t)mt.mult * mt.q + kSmall - 1) / kSmall);
   }
 }
 
@@ -1058,6 +1147,14 @@ static void slp_lens(lcg_slp* p, hipStream_t s) {
     k_slp_meta<<<pgrid(p->g), kPB, 0, s>>>(p->off.p, p->mult.p, p->nt.p, p->E.p, p->S.p, p->N.p,
                                            p->g, reinterpret_cast<RuleMeta*>(p->meta.p));
     PP_CHECK("slp_meta");
+    p->gnt.need(std::max<uint64_t>(p->g, 1), s);
+    k_slp_gnt<<<pgrid(p->g), kPB, 0, s>>>(p->off.p, p->rhs.p, p->N.p,
+                                          reinterpret_cast<const RuleMeta*>(p->meta.p), p->g,
+                                          p->gnt.p);
+    PP_CHECK("slp_gnt");
+    p->el.need(std::max<uint64_t>(p->g, 1), s);
+    k_slp_el<<<pgrid(p->g), kPB, 0, s>>>(p->E.p, p->nt.p, p->g, p->el.p);
+    PP_CHECK("slp_el");
     sync(s);
   }
   p->lens_ready = true;
@@ -1083,42 +1180,54 @@ static void slp_expand_core(lcg_slp* p, uint32_t j0, uint32_t j1, uint8_t* d_out
     HIP_CHECK(hipMemcpyAsync(d_offsets, str_off.p, (ks + 1) * sizeof(uint64_t),
                              hipMemcpyDeviceToDevice, s));
   // the strings whose C entry is a rule are the first step's items
-  ctr.need(1, s);
-  zero(ctr.p, 8, s);
-  DBuf<uint32_t> sym[2];
-  DBuf<uint64_t> pos[2];
+  ctr.need(4, s);  // [0] items written, [1] items of the step after next, [2] big items, [3] pieces
+  zero(ctr.p, 32, s);
+  auto* uctr = reinterpret_cast<unsigned long long*>(ctr.p);
+  const RuleMeta* meta = reinterpret_cast<const RuleMeta*>(p->meta.p);
+  DBuf<uint32_t> sym[2], big, vi;
+  DBuf<uint64_t> pos[2], v0s;
   int cur = 0;
   sym[0].need(std::max<uint32_t>(ks, 1), s);
   pos[0].need(std::max<uint32_t>(ks, 1), s);
-  auto* uctr = reinterpret_cast<unsigned long long*>(ctr.p);
   k_slp_enter<<<pgrid(ks), kPB, 0, s>>>(p->c.p + j0, ks, str_off.p, sym[0].p, pos[0].p, uctr,
                                         d_out);
   PP_CHECK("slp_enter");
-  uint64_t m = read_dev(ctr.p, s);
-  DBuf<uint64_t> cnt, ntc, cbase, nbase;
-  DBuf<SlpItem> items;
+  // the first step's items and, from their rules, the item children they make
+  k_slp_first<<<pgrid(ks), kPB, 0, s>>>(ctr.p, sym[0].p, meta, uctr + 1);
+  PP_CHECK("slp_first");
+  uint64_t counts[2];
+  read_many<uint64_t>({{ctr.p, &counts[0]}, {ctr.p + 1, &counts[1]}}, s);
+  uint64_t m = counts[0], m_next = counts[1];
   while (m) {
-    cnt.need(m, s);
-    ntc.need(m, s);
-    cbase.need(m + 1, s);
-    nbase.need(m + 1, s);
-    items.need(m, s);
-    const RuleMeta* meta = reinterpret_cast<const RuleMeta*>(p->meta.p);
-    k_slp_count<<<pgrid(m), kPB, 0, s>>>(sym[cur].p, pos[cur].p, m, meta, cnt.p, ntc.p, items.p);
-    PP_CHECK("slp_count");
-    sc.run(cnt.p, cbase.p, m, s);
-    sc.run(ntc.p, nbase.p, m, s);
-    uint64_t total = 0, m_next = 0;
-    read_many<uint64_t>({{cbase.p + m, &total}, {nbase.p + m, &m_next}}, s);
     sym[cur ^ 1].need(std::max<uint64_t>(m_next, 1), s);
     pos[cur ^ 1].need(std::max<uint64_t>(m_next, 1), s);
-    const uint64_t nchunks = (total + kChunk - 1) / kChunk;
-    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(nchunks, 8192));
-    k_slp_children<<<grid, kPB, 0, s>>>(items.p, m, cbase.p, nbase.p, total, p->rhs.p, p->S.p,
-                                        p->N.p, meta, sym[cur ^ 1].p, pos[cur ^ 1].p, d_out);
-    PP_CHECK("slp_children");
+    big.need(std::max<uint64_t>(m, 1), s);
+    zero(ctr.p, 32, s);
+    const unsigned grid = std::min(pgrid(m), 4096u);
+    k_slp_step<<<grid, kPB, 0, s>>>(sym[cur].p, pos[cur].p, m, nullptr, nullptr, meta, p->gnt.p,
+                                    p->rhs.p, p->S.p, p->N.p, p->el.p, sym[cur ^ 1].p,
+                                    pos[cur ^ 1].p, uctr, uctr + 1, big.p, uctr + 2, d_out);
+    PP_CHECK("slp_step");
+    const uint64_t nb = read_dev(ctr.p + 2, s);
+    if (nb) {  // the big items, in pieces of kSmall children
+      k_slp_npieces<<<pgrid(nb), kPB, 0, s>>>(big.p, nb, sym[cur].p, meta, uctr + 3);
+      PP_CHECK("slp_npieces");
+      const uint64_t np = read_dev(ctr.p + 3, s);
+      vi.need(np, s);
+      v0s.need(np, s);
+      zero(ctr.p + 3, 8, s);
+      k_slp_pieces<<<pgrid(nb), kPB, 0, s>>>(big.p, nb, sym[cur].p, meta, p->gnt.p, vi.p, v0s.p,
+                                             uctr + 3, uctr + 1);
+      PP_CHECK("slp_pieces");
+      k_slp_step<<<std::min(pgrid(np), 4096u), kPB, 0, s>>>(
+          sym[cur].p, pos[cur].p, np, vi.p, v0s.p, meta, p->gnt.p, p->rhs.p, p->S.p, p->N.p,
+          p->el.p, sym[cur ^ 1].p, pos[cur ^ 1].p, uctr, uctr + 1, big.p, uctr + 2, d_out);
+      PP_CHECK("slp_step");
+    }
+    const uint64_t after = read_dev(ctr.p + 1, s);
     cur ^= 1;
     m = m_next;
+    m_next = after;
   }
   sync(s);
 }
