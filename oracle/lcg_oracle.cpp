@@ -1,8 +1,9 @@
 // LCG reference oracle -- TEST INFRASTRUCTURE ONLY.
 //
 // A plain, slow, single-threaded CPU implementation of the stable locally
-// consistent grammar construction (BuildGram), of MergeGrams and of grammar
-// expansion, written from the paper "Efficient terabyte-scale text
+// consistent grammar construction (BuildGram), of MergeGrams, of grammar
+// expansion, of the RL and Simp post-processing and of the stored file of its
+// result, written from the paper "Efficient terabyte-scale text
 // compression via stable local consistency and parallel grammar processing"
 // (Diaz-Dominguez, arXiv 2411.12439).  Only the test suite, the smoke check
 // and the CPU-baseline leg of the benchmark load it.  It shares no code,
@@ -32,12 +33,14 @@
 //   * Merge is Sec. 3.6 in rank form (App. A.1): the offsets L_a, L_b only
 //     convert ranks to global ids and are not materialised.
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <cstdio>
 #include <string>
 #include <vector>
 #include <map>
+#include <memory>
 #include <unordered_map>
 
 namespace {
@@ -414,6 +417,10 @@ struct OracleSlp {
   std::vector<uint32_t> rhs;
   std::vector<uint32_t> mult;
   std::vector<uint32_t> c;
+  // The level structure: rule ids [bounds[b], bounds[b+1]) form block b (per
+  // input level, its run rules, then its ordinary rules; blocks may be
+  // empty), and the rules of a block refer only to ids below bounds[b].
+  std::vector<uint32_t> bounds{256};
   // g and G of the input, run rules made, g and G after RL, rules removed,
   // g and G of the result
   uint64_t stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -456,7 +463,9 @@ OracleSlp to_global(const OracleGrammar* g, bool rl) {
       s.mult.push_back(kv.first.second);
     }
     obase[i] = next;
+    s.bounds.push_back(next);
     next += L.size();
+    s.bounds.push_back(next);
     for (uint32_t r = 0; r < L.size(); ++r) {
       uint64_t a = L.rhs_off[r], b = L.rhs_off[r + 1];
       for (uint64_t x = a; x < b;) {
@@ -509,6 +518,10 @@ OracleSlp simp(const OracleSlp& s) {
     if (!removed[r]) newid[r] = next++;
   }
   OracleSlp o;
+  o.bounds.clear();
+  std::vector<uint32_t> kept_below(g + 1, 0);
+  for (size_t r = 0; r < g; ++r) kept_below[r + 1] = kept_below[r] + !removed[r];
+  for (uint32_t b : s.bounds) o.bounds.push_back(256 + kept_below[b - 256]);  // kept rules below b
   for (size_t r = 0; r < g; ++r) {
     if (removed[r]) continue;
     for (uint64_t t = s.off[r]; t < s.off[r + 1]; ++t)
@@ -570,6 +583,209 @@ uint64_t oracle_slp_expand(const OracleSlp* s, uint32_t j, uint8_t* out, uint64_
   return len;
 }
 void oracle_slp_free(OracleSlp* s) { delete s; }
+// The block bounds (see OracleSlp); returns their number, writes them if out.
+uint32_t oracle_slp_bounds(const OracleSlp* s, uint32_t* out) {
+  if (out) std::memcpy(out, s->bounds.data(), s->bounds.size() * sizeof(uint32_t));
+  return (uint32_t)s->bounds.size();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The stored file of a post-processed grammar.  App. A (storing the final
+// grammar) budgets G log g bits for the right-hand sides, g log G bits for
+// the pointers to them and one entry per string for C.  The file is:
+//
+//   header, eight 64-bit words: magic "LCGSLP01", r (rules), G (cells), k
+//     (strings), runs (run rules), nb (block bounds), the widths
+//     b_sym | b_cell << 8 | b_ptr << 16, the file's size in bytes;
+//   R: the right-hand sides of rules 256, 257, ... one after the other, G
+//     cells of b_cell bits; a run rule X' -> (X, l) takes two cells, X then l;
+//   P: the first cell of every rule in R, r cells of b_ptr bits;
+//   M: one bit per rule, set for the run rules;
+//   C: k cells of b_sym bits;
+//   B: the nb block bounds, 32-bit cells.
+//
+// Every section starts on a 64-bit word (padding bits are zero); in a section
+// of width b, cell i occupies the bits i*b .. i*b+b-1, bit t being bit t mod
+// 64 of the little-endian word t / 64.  Widths: b_sym = bits(255 + r), the
+// largest id; b_cell = max(b_sym, bits(longest run)); b_ptr = bits(G - 1),
+// 1 without rules; bits(x) = the binary digits of x, at least 1.
+//
+// The decoder accepts exactly what the encoder can write: the header's
+// counts, widths and size agree; the bounds rise from 256 to 256 + r; the
+// pointers start at 0 and rise, run rules spanning two cells; every cell of a
+// rule in block b names an id below bounds[b] (so rules refer only to smaller
+// ids); run lengths are at least 2; C names ids below 256 + r; and no rule
+// and no sum of the strings' lengths reaches 2^61 bytes.
+namespace {
+
+uint32_t nbits(uint64_t x) {
+  uint32_t b = 1;
+  while (b < 64 && (x >> b) != 0) ++b;
+  return b;
+}
+
+uint64_t words_for(uint64_t cells, uint32_t width) { return (cells * width + 63) / 64; }
+
+// one bit at a time, the slow and obvious way
+void put_bits(std::vector<uint64_t>& w, uint64_t base_word, uint64_t cell, uint32_t width,
+              uint64_t v) {
+  for (uint32_t t = 0; t < width; ++t) {
+    const uint64_t bit = cell * width + t;
+    if ((v >> t) & 1) w[base_word + bit / 64] |= 1ull << (bit % 64);
+  }
+}
+
+uint64_t get_bits(const std::vector<uint64_t>& w, uint64_t base_word, uint64_t cell,
+                  uint32_t width) {
+  uint64_t v = 0;
+  for (uint32_t t = 0; t < width; ++t) {
+    const uint64_t bit = cell * width + t;
+    v |= ((w[base_word + bit / 64] >> (bit % 64)) & 1) << t;
+  }
+  return v;
+}
+
+constexpr uint64_t kStoreMagic = 0x3130504C5347434Cull;  // the bytes "LCGSLP01"
+constexpr uint64_t kLenLimit = 1ull << 61;
+
+}  // namespace
+
+extern "C" {
+
+// The stored file of s: returns its size in bytes and writes it to out when
+// cap is at least that size.
+uint64_t oracle_slp_encode(const OracleSlp* s, uint8_t* out, uint64_t cap) {
+  const uint64_t r = s->mult.size(), k = s->c.size(), nb = s->bounds.size();
+  uint64_t runs = 0, longest = 0;
+  for (uint32_t m : s->mult)
+    if (m >= 2) {
+      ++runs;
+      if (m > longest) longest = m;
+    }
+  const uint64_t G = slp_size(*s);
+  const uint32_t b_sym = nbits(255 + r);
+  const uint32_t b_cell = std::max(b_sym, runs ? nbits(longest) : 1u);
+  const uint32_t b_ptr = r ? nbits(G - 1) : 1;
+  const uint64_t wR = words_for(G, b_cell), wP = words_for(r, b_ptr), wM = words_for(r, 1),
+                 wC = words_for(k, b_sym), wB = words_for(nb, 32);
+  const uint64_t nwords = 8 + wR + wP + wM + wC + wB;
+  if (!out || cap < nwords * 8) return nwords * 8;
+  std::vector<uint64_t> w(nwords, 0);
+  w[0] = kStoreMagic;
+  w[1] = r;
+  w[2] = G;
+  w[3] = k;
+  w[4] = runs;
+  w[5] = nb;
+  w[6] = b_sym | (uint64_t)b_cell << 8 | (uint64_t)b_ptr << 16;
+  w[7] = nwords * 8;
+  const uint64_t oR = 8, oP = oR + wR, oM = oP + wP, oC = oM + wM, oB = oC + wC;
+  uint64_t cell = 0;
+  for (uint64_t x = 0; x < r; ++x) {
+    put_bits(w, oP, x, b_ptr, cell);
+    if (s->mult[x] >= 2) {
+      put_bits(w, oR, cell++, b_cell, s->rhs[s->off[x]]);
+      put_bits(w, oR, cell++, b_cell, s->mult[x]);
+      put_bits(w, oM, x, 1, 1);
+    } else {
+      for (uint64_t t = s->off[x]; t < s->off[x + 1]; ++t) put_bits(w, oR, cell++, b_cell, s->rhs[t]);
+    }
+  }
+  for (uint64_t j = 0; j < k; ++j) put_bits(w, oC, j, b_sym, s->c[j]);
+  for (uint64_t b = 0; b < nb; ++b) put_bits(w, oB, b, 32, s->bounds[b]);
+  for (uint64_t i = 0; i < nwords; ++i)
+    for (int t = 0; t < 8; ++t) out[i * 8 + t] = (uint8_t)(w[i] >> (8 * t));
+  return nwords * 8;
+}
+
+// The grammar of a stored file, or NULL (oracle_last_error says why).
+OracleSlp* oracle_slp_decode(const uint8_t* in, uint64_t n) {
+  auto fail = [](const char* why) -> OracleSlp* {
+    g_err = why;
+    return nullptr;
+  };
+  if (n < 64 || n % 8) return fail("size is not a whole header plus words");
+  std::vector<uint64_t> w(n / 8, 0);
+  for (uint64_t i = 0; i < n / 8; ++i)
+    for (int t = 0; t < 8; ++t) w[i] |= (uint64_t)in[i * 8 + t] << (8 * t);
+  if (w[0] != kStoreMagic) return fail("bad magic");
+  const uint64_t r = w[1], G = w[2], k = w[3], runs = w[4], nb = w[5];
+  const uint32_t b_sym = w[6] & 0xFF, b_cell = (w[6] >> 8) & 0xFF, b_ptr = (w[6] >> 16) & 0xFF;
+  if (w[6] >> 24) return fail("bad widths word");
+  if (w[7] != n) return fail("size differs from the header");
+  if (r > 0xFFFFFFFFull - 256 || k == 0 || k > 0xFFFFFFFFull || runs > r || G >= (1ull << 58) ||
+      G < r + runs || nb < 2 || nb > 1024)
+    return fail("counts out of range");
+  if (b_sym != nbits(255 + r) || b_cell < b_sym || b_cell > 32 || b_ptr != (r ? nbits(G - 1) : 1u))
+    return fail("widths do not match the counts");
+  const uint64_t wR = words_for(G, b_cell), wP = words_for(r, b_ptr), wM = words_for(r, 1),
+                 wC = words_for(k, b_sym), wB = words_for(nb, 32);
+  if ((8 + wR + wP + wM + wC + wB) * 8 != n) return fail("sections do not fill the size");
+  const uint64_t oR = 8, oP = oR + wR, oM = oP + wP, oC = oM + wM, oB = oC + wC;
+  std::unique_ptr<OracleSlp> s(new OracleSlp());
+  s->bounds.clear();
+  for (uint64_t b = 0; b < nb; ++b) s->bounds.push_back((uint32_t)get_bits(w, oB, b, 32));
+  if (s->bounds[0] != 256 || s->bounds[nb - 1] != 256 + r) return fail("bad block bounds");
+  for (uint64_t b = 1; b < nb; ++b)
+    if (s->bounds[b] < s->bounds[b - 1]) return fail("bad block bounds");
+  std::vector<uint64_t> start(r + 1, G);
+  uint64_t nrun = 0;
+  for (uint64_t x = 0; x < r; ++x) {
+    start[x] = get_bits(w, oP, x, b_ptr);
+    nrun += get_bits(w, oM, x, 1);
+  }
+  if (nrun != runs) return fail("run count differs from the header");
+  if (r && start[0] != 0) return fail("bad rule pointers");
+  uint32_t blk = 0;
+  for (uint64_t x = 0; x < r; ++x) {
+    const bool run = get_bits(w, oM, x, 1) != 0;
+    if (start[x + 1] <= start[x] || start[x + 1] - start[x] > 0xFFFFFFFFull ||
+        (run && start[x + 1] - start[x] != 2))
+      return fail("bad rule pointers");
+    while (blk + 1 < nb && s->bounds[blk + 1] <= 256 + x) ++blk;  // the block of rule x
+    const uint64_t below = s->bounds[blk];
+    const uint64_t a = get_bits(w, oR, start[x], b_cell);
+    if (a >= below) return fail("a rule names an id of its own block or above");
+    s->rhs.push_back((uint32_t)a);
+    if (run) {
+      const uint64_t l = get_bits(w, oR, start[x] + 1, b_cell);
+      if (l < 2) return fail("a run shorter than 2");
+      s->mult.push_back((uint32_t)l);
+    } else {
+      for (uint64_t i = start[x] + 1; i < start[x + 1]; ++i) {
+        const uint64_t y = get_bits(w, oR, i, b_cell);
+        if (y >= below) return fail("a rule names an id of its own block or above");
+        s->rhs.push_back((uint32_t)y);
+      }
+      s->mult.push_back(1);
+    }
+    s->off.push_back(s->rhs.size());
+  }
+  for (uint64_t j = 0; j < k; ++j) {
+    const uint64_t y = get_bits(w, oC, j, b_sym);
+    if (y >= 256 + r) return fail("C names an id beyond the rules");
+    s->c.push_back((uint32_t)y);
+  }
+  // expansion lengths in id order (every rule refers to smaller ids only)
+  std::vector<uint64_t> len(r, 0);
+  auto len_of = [&](uint32_t y) -> uint64_t { return y < 256 ? 1 : len[y - 256]; };
+  for (uint64_t x = 0; x < r; ++x) {
+    uint64_t e = 0;
+    for (uint64_t t = s->off[x]; t < s->off[x + 1]; ++t) e = std::min(e + len_of(s->rhs[t]), kLenLimit);
+    e = e > kLenLimit / s->mult[x] ? kLenLimit : e * s->mult[x];
+    if (e >= kLenLimit) return fail("an expansion reaches 2^61 bytes");
+    len[x] = e;
+  }
+  uint64_t total = 0;
+  for (uint32_t y : s->c) total = std::min(total + len_of(y), kLenLimit);
+  if (total >= kLenLimit) return fail("the strings reach 2^61 bytes");
+  const uint64_t G2 = slp_size(*s);
+  s->stats[6] = r;
+  s->stats[7] = G2;
+  return s.release();
+}
 
 // Longest common extension of two positions of a collection (the lcp / lcs
 // of the match-completion step sketched in App. B), by comparing bytes:

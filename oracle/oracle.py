@@ -76,6 +76,12 @@ def lib():
         L.oracle_slp_expand.argtypes = [vp, ctypes.c_uint32, u8p, ctypes.c_uint64]
         L.oracle_slp_expand.restype = ctypes.c_uint64
         L.oracle_slp_free.argtypes = [vp]
+        L.oracle_slp_bounds.argtypes = [vp, u32p]
+        L.oracle_slp_bounds.restype = ctypes.c_uint32
+        L.oracle_slp_encode.argtypes = [vp, u8p, ctypes.c_uint64]
+        L.oracle_slp_encode.restype = ctypes.c_uint64
+        L.oracle_slp_decode.argtypes = [u8p, ctypes.c_uint64]
+        L.oracle_slp_decode.restype = vp
         L.oracle_lce.argtypes = [u8p, u64p, ctypes.c_uint32, u32p, u64p, u32p, u64p,
                                  ctypes.c_uint32, u64p]
         _lib = L
@@ -160,38 +166,34 @@ class Grammar:
         ``lcg_oracle.cpp`` as a dictionary::
 
             {"off": uint64[g+1], "rhs": uint32[Q], "mult": uint32[g], "c": uint32[k],
-             "stats": uint64[8]}
+             "stats": uint64[8], "bounds": uint32[nb]}
 
         Rule ids are 256 + index; ids below 256 are terminals.  stats: g and G
         of the input, run rules made, g and G after RL, rules removed, g and G
-        of the result.  With ``expand``, "expansions" lists exp(C[j]) of every
-        string, expanded from the post-processed grammar.
+        of the result.  bounds: the level blocks of rule ids (rules of block b,
+        ids [bounds[b], bounds[b+1]), refer only to ids below bounds[b]).  With
+        ``expand``, "expansions" lists exp(C[j]) of every string, expanded
+        from the post-processed grammar.
         """
         L = lib()
         h = L.oracle_postprocess(self.h, (1 if rl else 0) | (2 if simp else 0))
         try:
-            g = ctypes.c_uint32()
-            q = ctypes.c_uint64()
-            k = ctypes.c_uint32()
-            L.oracle_slp_size(h, ctypes.byref(g), ctypes.byref(q), ctypes.byref(k))
-            off = np.zeros(g.value + 1, np.uint64)
-            rhs = np.zeros(max(q.value, 1), np.uint32)
-            mult = np.zeros(max(g.value, 1), np.uint32)
-            c = np.zeros(max(k.value, 1), np.uint32)
-            st = np.zeros(8, np.uint64)
-            L.oracle_slp_copy(h, _ptr(off, ctypes.c_uint64), _ptr(rhs, ctypes.c_uint32),
-                              _ptr(mult, ctypes.c_uint32), _ptr(c, ctypes.c_uint32),
-                              _ptr(st, ctypes.c_uint64))
-            exps = []
-            for j in range(k.value if expand else 0):
-                n = L.oracle_slp_expand(h, j, None, 0)
-                buf = np.zeros(max(n, 1), np.uint8)
-                L.oracle_slp_expand(h, j, _ptr(buf, ctypes.c_uint8), n)
-                exps.append(buf[:n].tobytes())
+            return _slp_dict(h, expand)
         finally:
             L.oracle_slp_free(h)
-        return {"off": off, "rhs": rhs[:q.value], "mult": mult[:g.value], "c": c[:k.value],
-                "stats": st, "expansions": exps if expand else None}
+
+    def stored(self, rl=True, simp=True):
+        """The stored file (bytes) of the post-processed grammar; the layout is
+        described above ``oracle_slp_encode`` in ``lcg_oracle.cpp``."""
+        L = lib()
+        h = L.oracle_postprocess(self.h, (1 if rl else 0) | (2 if simp else 0))
+        try:
+            n = L.oracle_slp_encode(h, None, 0)
+            buf = np.zeros(n, np.uint8)
+            L.oracle_slp_encode(h, _ptr(buf, ctypes.c_uint8), n)
+        finally:
+            L.oracle_slp_free(h)
+        return buf.tobytes()
 
     def merge(self, other):
         """MergeGrams(self, other): self absorbs other; other is unchanged."""
@@ -199,6 +201,48 @@ class Grammar:
         if rc != 0:
             raise ValueError(lib().oracle_last_error().decode())
         return self
+
+
+def decode_stored(data, expand=False):
+    """The grammar of a stored file as ``Grammar.postprocess`` returns it (stats
+    hold only g and G of the result); ValueError names what is malformed."""
+    L = lib()
+    buf = np.frombuffer(bytes(data), np.uint8).copy()
+    h = L.oracle_slp_decode(_ptr(buf, ctypes.c_uint8) if len(buf) else None, len(buf))
+    if not h:
+        raise ValueError(L.oracle_last_error().decode())
+    try:
+        return _slp_dict(h, expand)
+    finally:
+        L.oracle_slp_free(h)
+
+
+def _slp_dict(h, expand):
+    """The arrays of an oracle straight-line grammar handle."""
+    L = lib()
+    g = ctypes.c_uint32()
+    q = ctypes.c_uint64()
+    k = ctypes.c_uint32()
+    L.oracle_slp_size(h, ctypes.byref(g), ctypes.byref(q), ctypes.byref(k))
+    off = np.zeros(g.value + 1, np.uint64)
+    rhs = np.zeros(max(q.value, 1), np.uint32)
+    mult = np.zeros(max(g.value, 1), np.uint32)
+    c = np.zeros(max(k.value, 1), np.uint32)
+    st = np.zeros(8, np.uint64)
+    L.oracle_slp_copy(h, _ptr(off, ctypes.c_uint64), _ptr(rhs, ctypes.c_uint32),
+                      _ptr(mult, ctypes.c_uint32), _ptr(c, ctypes.c_uint32),
+                      _ptr(st, ctypes.c_uint64))
+    exps = []
+    for j in range(k.value if expand else 0):
+        n = L.oracle_slp_expand(h, j, None, 0)
+        buf = np.zeros(max(n, 1), np.uint8)
+        L.oracle_slp_expand(h, j, _ptr(buf, ctypes.c_uint8), n)
+        exps.append(buf[:n].tobytes())
+    nb = L.oracle_slp_bounds(h, None)
+    bounds = np.zeros(nb, np.uint32)
+    L.oracle_slp_bounds(h, _ptr(bounds, ctypes.c_uint32))
+    return {"off": off, "rhs": rhs[:q.value], "mult": mult[:g.value], "c": c[:k.value],
+            "stats": st, "bounds": bounds, "expansions": exps if expand else None}
 
 
 def build(text, offsets, seed):

@@ -1,0 +1,100 @@
+"""An independent reader and writer of the stored file of a post-processed
+grammar, for the tests (the format: App. A, storing the final grammar, in the
+layout described above ``oracle_slp_encode``).
+
+It shares nothing with the oracle's bit loops: every section is read or
+written as one Python integer (cell i of width b is bits i*b .. i*b+b-1 of
+the section's little-endian value).
+"""
+MAGIC = b"LCGSLP01"
+
+
+def nbits(x):
+    """binary digits of x, at least 1"""
+    return max(1, int(x).bit_length())
+
+
+def _words(cells, width):
+    return (cells * width + 63) // 64
+
+
+def _unpack(section, n, width):
+    v = int.from_bytes(section, "little")
+    mask = (1 << width) - 1
+    return [(v >> (i * width)) & mask for i in range(n)]
+
+
+def _pack(cells, width, nwords):
+    v = 0
+    for i, x in enumerate(cells):
+        assert 0 <= x < (1 << width)
+        v |= int(x) << (i * width)
+    return v.to_bytes(nwords * 8, "little")
+
+
+def read(data):
+    """dict with the header fields and the decoded rules [(rhs, mult)], c, bounds."""
+    data = bytes(data)
+    h = [int.from_bytes(data[8 * i:8 * i + 8], "little") for i in range(8)]
+    assert data[:8] == MAGIC
+    r, G, k, runs, nb, widths, size = h[1:]
+    b_sym, b_cell, b_ptr = widths & 0xFF, (widths >> 8) & 0xFF, (widths >> 16) & 0xFF
+    sizes = [_words(G, b_cell), _words(r, b_ptr), _words(r, 1), _words(k, b_sym), _words(nb, 32)]
+    at, secs = 64, []
+    for w in sizes:
+        secs.append(data[at:at + 8 * w])
+        at += 8 * w
+    R = _unpack(secs[0], G, b_cell)
+    P = _unpack(secs[1], r, b_ptr) + [G]
+    M = _unpack(secs[2], r, 1)
+    C = _unpack(secs[3], k, b_sym)
+    B = _unpack(secs[4], nb, 32)
+    rules = []
+    for x in range(r):
+        cells = R[P[x]:P[x + 1]]
+        rules.append(([cells[0]], cells[1]) if M[x] else (cells, 1))
+    return {"r": r, "G": G, "k": k, "runs": runs, "nb": nb, "b_sym": b_sym, "b_cell": b_cell,
+            "b_ptr": b_ptr, "size": size, "total": at, "section_words": sizes,
+            "rules": rules, "c": C, "bounds": B}
+
+
+def write(rules, c, bounds, b_cell=None):
+    """The file of rules [(rhs, mult)] (mult >= 2: a run rule, rhs = [X]), c and bounds."""
+    r, k, nb = len(rules), len(c), len(bounds)
+    cells, starts, marks = [], [], []
+    for rhs, mult in rules:
+        starts.append(len(cells))
+        if mult >= 2:
+            cells += [rhs[0], mult]
+        else:
+            cells += list(rhs)
+        marks.append(1 if mult >= 2 else 0)
+    G = len(cells)
+    runs = sum(marks)
+    b_sym = nbits(255 + r)
+    longest = max([m for _, m in rules if m >= 2], default=1)
+    if b_cell is None:
+        b_cell = max(b_sym, nbits(longest))
+    b_ptr = nbits(G - 1) if r else 1
+    sizes = [_words(G, b_cell), _words(r, b_ptr), _words(r, 1), _words(k, b_sym), _words(nb, 32)]
+    total = 64 + 8 * sum(sizes)
+    head = MAGIC + b"".join(int(v).to_bytes(8, "little") for v in
+                            (r, G, k, runs, nb, b_sym | b_cell << 8 | b_ptr << 16, total))
+    body = (_pack(cells, b_cell, sizes[0]) + _pack(starts, b_ptr, sizes[1]) +
+            _pack(marks, 1, sizes[2]) + _pack(c, b_sym, sizes[3]) + _pack(bounds, 32, sizes[4]))
+    return head + body
+
+
+def rules_of(pp):
+    """[(rhs list, mult)] of a post-processed grammar dictionary."""
+    off = [int(x) for x in pp["off"]]
+    rhs = [int(x) for x in pp["rhs"]]
+    return [(rhs[off[r]:off[r + 1]], int(pp["mult"][r])) for r in range(len(pp["mult"]))]
+
+
+def doubling_chain(levels):
+    """Rules X_0 -> AA, X_i -> X_{i-1} X_{i-1}: exp(X_i) has 2^(i+1) bytes; one
+    rule per block."""
+    rules = [([65, 65], 1)] + [([256 + i - 1, 256 + i - 1], 1) for i in range(1, levels)]
+    bounds = list(range(256, 256 + levels + 1))
+    return rules, [256 + levels - 1], bounds
