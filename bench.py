@@ -316,6 +316,33 @@ def extra_legs(args, out, text, off, t, o, n, k, seed):
         p.expand_strings()
         torch.cuda.synchronize()
         sxs.append(time.perf_counter() - t0)
+    # the stored file of the post-processed grammar (App. A's bit budget):
+    # encoded, decoded (with every check and the expansion lengths) and
+    # decompressed from the decoded grammar
+    enc, dec = [], []
+    for i in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = p.encode()
+        torch.cuda.synchronize()
+        enc.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        d = lcg.decode(f)
+        torch.cuda.synchronize()
+        dec.append(time.perf_counter() - t0)
+        if i + 1 < max(1, args.steps):
+            d.free()
+    dout, _ = d.expand_strings()
+    torch.cuda.synchronize()
+    if not torch.equal(dout, t):
+        raise SystemExit("the decoded stored grammar does not decompress to the input")
+    del dout
+    d.free()
+    fbytes = int(f.numel())
+    g_sym = 256 + g_out
+    budget_bits = (st[7] * int(np.ceil(np.log2(g_sym))) + g_out * int(np.ceil(np.log2(st[7])))
+                   + k_out * int(np.ceil(np.log2(g_sym))))
+    del f
     p.free()
     pp_in = sum(q * (1 if i == 0 else 4) + (u + 1) * 8 for i, (u, q) in enumerate(sizes)) + 5 * k
     pp_out = q_out * 4 + (g_out + 1) * 8 + g_out * 4 + k_out * 4
@@ -332,7 +359,12 @@ def extra_legs(args, out, text, off, t, o, n, k, seed):
         "simp_deleted_rules_pct": round(100.0 * st[5] / st[3], 3),
         "simp_size_reduction_pct": round(100.0 * (st[4] - st[7]) / st[4], 3),
         "expand_ms": round(float(np.mean(sxs)) * 1e3, 3),
-        "expand_gbps": round(n / float(np.mean(sxs)) / 1e9, 3)}
+        "expand_gbps": round(n / float(np.mean(sxs)) / 1e9, 3),
+        "stored_bytes": fbytes,
+        "stored_bits_per_input_byte": round(8.0 * fbytes / n, 4),
+        "stored_vs_paper_budget": round(8.0 * fbytes / budget_bits, 5),
+        "encode_ms": round(float(np.mean(enc)) * 1e3, 3),
+        "decode_ms": round(float(np.mean(dec)) * 1e3, 3)}
     print("[bench] postprocess (RL + Simp): %.2f ms, %s" % (pp_s * 1e3, st), file=sys.stderr,
           flush=True)
 

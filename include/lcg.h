@@ -325,6 +325,50 @@ lcg_status lcg_slp_expand_strings(lcg_slp_t p, uint32_t j0, uint32_t j1, uint8_t
                                   hipStream_t stream);
 void lcg_slp_free(lcg_slp_t p);
 
+/* ---- the stored file of a post-processed grammar ----------------------------
+ *
+ * App. A (storing the final grammar) budgets G log g bits for the
+ * right-hand sides, g log G bits for the pointers to them and one entry per
+ * string for C.  The file (little-endian) is:
+ *   header, eight 64-bit words: the bytes "LCGSLP01", r (rules), G (cells),
+ *     k (strings), runs (run rules), nb (block bounds), the widths
+ *     b_sym | b_cell << 8 | b_ptr << 16, the file's size in bytes;
+ *   R: the right-hand sides of rules 256, 257, ... one after the other, G
+ *     cells of b_cell bits; a run rule X' -> (X, l) takes two cells, X and l;
+ *   P: the first cell of every rule in R, r cells of b_ptr bits;
+ *   M: one bit per rule, set for run rules;
+ *   C: k cells of b_sym bits;
+ *   B: the nb block bounds, 32-bit cells: ids [B[b], B[b+1]) form block b
+ *     (per level of the input, its run rules, then its ordinary rules), whose
+ *     rules name only ids below B[b].
+ * Each section starts on a 64-bit word, padding bits are zero; cell i of a
+ * section of width b holds the bits i*b .. i*b+b-1, bit t being bit t % 64 of
+ * word t / 64.  b_sym = bits(255 + r) (the largest id, i.e. ceil(log2 g) for
+ * g = 256 + r symbols), b_cell = max(b_sym, bits(longest run)), b_ptr =
+ * bits(G - 1) (1 without rules), bits(x) = the binary digits of x, at least 1.
+ */
+/*
+ * Write p's stored file to d_out (device, 8-byte aligned, cap bytes) on
+ * `stream`; *bytes receives its size.  With cap smaller than the size the
+ * call returns LCG_EINVAL after setting *bytes (query with d_out = NULL,
+ * cap = 0).  Synchronises the stream.  Errors: LCG_EINVAL, LCG_ENOMEM, LCG_EHIP.
+ */
+lcg_status lcg_slp_encode(lcg_slp_t p, uint8_t* d_out, uint64_t cap, uint64_t* bytes,
+                          hipStream_t stream);
+/*
+ * The grammar of the stored file d_in (device, 8-byte aligned, `bytes` long)
+ * into *out (free with lcg_slp_free).  The caller keeps d_in.  Everything is
+ * checked before anything is expanded; LCG_EINVAL (with lcg_last_error
+ * naming the fault) unless: the header's counts, widths and size agree; the
+ * bounds rise from 256 to 256 + r (1 to 1024 of them); the pointers start
+ * at 0 and rise, a run rule spanning two cells; every cell of a rule of block
+ * b names an id below B[b]; run lengths are at least 2; C names ids below
+ * 256 + r; no rule and no sum of the strings' lengths reaches 2^61 bytes.
+ * The result's statistics hold only its g and G (entries 6 and 7).
+ * Synchronises the stream.  Errors: LCG_EINVAL, LCG_ENOMEM, LCG_EHIP.
+ */
+lcg_status lcg_slp_decode(const uint8_t* d_in, uint64_t bytes, hipStream_t stream, lcg_slp_t* out);
+
 /* Return the library's cached free device blocks to the driver. */
 void lcg_release_pool(void);
 /* Thread-local description of the last failure. */

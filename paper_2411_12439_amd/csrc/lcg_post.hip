@@ -23,6 +23,7 @@
 
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
 #include <initializer_list>
 #include <memory>
 
@@ -547,26 +548,50 @@ __global__ void k_pp_gather(const uint64_t* __restrict__ a, const uint32_t* __re
 }
 
 // ---------------------------------------------------------------- expansion
-// E and NT of the rules [r0, r1) (earlier blocks done)
+// Expansion lengths stop at kLenLimit: a rule that reaches it (possible only
+// in a decoded file) sets *err, and the grammar is refused.
+constexpr uint64_t kLenLimit = 1ull << 61;
+
+// Right-hand sides longer than kLongRule symbols (after Simp, each string's
+// root rule holds ~10^5 of them) are not summed by one thread: their
+// positions go in pieces of kPiece to whole blocks, and a thread per long
+// rule adds up its pieces.
+constexpr uint64_t kLongRule = 1024;
+constexpr uint64_t kPiece = 4096;
+
+// E and NT of the rules [r0, r1) whose right-hand sides are not long
+// (earlier blocks done)
 __global__ void k_slp_lens(const uint64_t* __restrict__ off, const uint32_t* __restrict__ rhs,
                            const uint32_t* __restrict__ mult, uint32_t r0, uint32_t r1,
-                           uint64_t* E, uint32_t* nt) {
+                           uint64_t* E, uint32_t* nt, uint32_t* __restrict__ err) {
   PP_LOOP(i, r1 - r0) {
     const uint32_t r = r0 + (uint32_t)i;
     uint64_t e = 0;
     uint32_t c = 0;
     const uint64_t b = off[r + 1];
+    if (b - off[r] > kLongRule) continue;
     for (uint64_t t = off[r]; t < b; ++t) {
       const uint32_t y = rhs[t];
       if (y < 256) {
         e += 1;
       } else {
-        e += E[y - 256];
+        e = min(e + E[y - 256], kLenLimit);  // both terms are at most kLenLimit
         ++c;
       }
     }
-    E[r] = e * mult[r];
+    const uint64_t m = mult[r];
+    const uint64_t tot = (e >= kLenLimit || e > (kLenLimit - 1) / m) ? kLenLimit : e * m;
+    if (tot >= kLenLimit) atomicOr(err, 1u);
+    E[r] = tot;
     nt[r] = c;
+  }
+}
+
+// the long rules (any order)
+__global__ void k_slp_longlist(const uint64_t* __restrict__ off, uint32_t g,
+                               uint32_t* __restrict__ ids, unsigned long long* __restrict__ cnt) {
+  PP_LOOP(r, g) {
+    if (off[r + 1] - off[r] > kLongRule) ids[atomicAdd(cnt, 1ull)] = (uint32_t)r;
   }
 }
 
@@ -642,13 +667,132 @@ __global__ void k_slp_meta(const uint64_t* __restrict__ off, const uint32_t* __r
   }
 }
 
-// per rule: the item children of its item children, over all repetitions
-// (sizes the step after next)
+// block-wide sums of a (saturating at kLenLimit) and c
+__device__ __forceinline__ void block_sums(uint64_t& a, uint64_t& c, uint64_t* s_a, uint64_t* s_c) {
+  for (int d = 32; d; d >>= 1) {
+    a = min(a + (uint64_t)__shfl_down(a, d), kLenLimit);
+    c += (uint64_t)__shfl_down(c, d);
+  }
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    s_a[wv] = a;
+    s_c[wv] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (uint32_t w = 1; w < kPB / 64; ++w) {
+      a = min(a + s_a[w], kLenLimit);
+      c += s_c[w];
+    }
+  }
+  __syncthreads();
+}
+
+// Per piece [pa, pb) of a long rule: mode 0, the expansion bytes (saturating)
+// and the nonterminals of its positions; mode 1, the item children of its item
+// children (the grandchild count).  Four positions per thread and step, their
+// loads issued together.
+template <int MODE>
+__global__ __launch_bounds__(kPB) void k_slp_pieces_sum(const uint64_t* __restrict__ pa,
+                                                        const uint64_t* __restrict__ pb,
+                                                        uint64_t p0, uint64_t p1,
+                                                        const uint32_t* __restrict__ rhs,
+                                                        const uint64_t* __restrict__ E,
+                                                        const uint64_t* __restrict__ N,
+                                                        const RuleMeta* __restrict__ meta,
+                                                        uint64_t* __restrict__ part_a,
+                                                        uint64_t* __restrict__ part_c) {
+  __shared__ uint64_t s_a[kPB / 64], s_c[kPB / 64];
+  for (uint64_t pc = p0 + blockIdx.x; pc < p1; pc += gridDim.x) {
+    const uint64_t a = pa[pc], b = pb[pc];
+    uint64_t sa = 0, sc = 0;
+    for (uint64_t t0 = a + threadIdx.x; t0 < b; t0 += 4 * kPB) {
+      uint32_t y[4];
+      bool in[4], child[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint64_t t = t0 + (uint64_t)k * kPB;
+        in[k] = t < b;
+        y[k] = in[k] ? rhs[t] : 0;
+        if constexpr (MODE == 1) child[k] = in[k] && N[t + 1] != N[t];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if constexpr (MODE == 0) {
+          if (!in[k]) continue;
+          if (y[k] < 256) {
+            sa = min(sa + 1, kLenLimit);
+          } else {
+            sa = min(sa + E[y[k] - 256], kLenLimit);
+            ++sc;
+          }
+        } else {
+          if (!child[k]) continue;
+          const RuleMeta c = meta[y[k] - 256];
+          sa += (uint64_t)c.mult * c.ntx;
+        }
+      }
+    }
+    block_sums(sa, sc, s_a, s_c);
+    if (threadIdx.x == 0) {
+      part_a[pc] = sa;
+      part_c[pc] = sc;
+    }
+  }
+}
+
+// per long rule i of [i0, i1) (pieces lp0[i] .. lp0[i+1]): E and NT from
+// its pieces' sums
+__global__ void k_slp_long_lens(const uint32_t* __restrict__ ids, const uint64_t* __restrict__ lp0,
+                                uint32_t i0, uint32_t i1, const uint64_t* __restrict__ part_a,
+                                const uint64_t* __restrict__ part_c,
+                                const uint32_t* __restrict__ mult, uint64_t* __restrict__ E,
+                                uint32_t* __restrict__ nt, uint32_t* __restrict__ err) {
+  PP_LOOP(j, i1 - i0) {
+    const uint32_t i = i0 + (uint32_t)j, r = ids[i];
+    uint64_t e = 0, c = 0;
+    for (uint64_t pc = lp0[i]; pc < lp0[i + 1]; ++pc) {
+      e = min(e + part_a[pc], kLenLimit);
+      c += part_c[pc];
+    }
+    const uint64_t m = mult[r];
+    const uint64_t tot = (e >= kLenLimit || e > (kLenLimit - 1) / m) ? kLenLimit : e * m;
+    if (tot >= kLenLimit) atomicOr(err, 1u);
+    E[r] = tot;
+    nt[r] = (uint32_t)c;
+  }
+}
+
+// per long rule: its grandchild count from its pieces' sums
+__global__ void k_slp_long_gnt(const uint32_t* __restrict__ ids, const uint64_t* __restrict__ lp0,
+                               uint32_t n, const uint64_t* __restrict__ part_a,
+                               const RuleMeta* __restrict__ meta, uint64_t* __restrict__ gnt) {
+  PP_LOOP(i, n) {
+    const uint32_t r = ids[i];
+    uint64_t sum = 0;
+    for (uint64_t pc = lp0[i]; pc < lp0[i + 1]; ++pc) sum += part_a[pc];
+    gnt[r] = sum * meta[r].mult;
+  }
+}
+
+// first and end position of each listed rule
+__global__ void k_slp_longoff(const uint32_t* __restrict__ ids, uint32_t n,
+                              const uint64_t* __restrict__ off, uint64_t* __restrict__ a,
+                              uint64_t* __restrict__ b) {
+  PP_LOOP(i, n) {
+    a[i] = off[ids[i]];
+    b[i] = off[ids[i] + 1];
+  }
+}
+
+// per rule whose right-hand side is not long: the item children of its item
+// children, over all repetitions (sizes the step after next)
 __global__ void k_slp_gnt(const uint64_t* __restrict__ off, const uint32_t* __restrict__ rhs,
                           const uint64_t* __restrict__ N, const RuleMeta* __restrict__ meta,
                           uint32_t g, uint64_t* __restrict__ gnt) {
   PP_LOOP(r, g) {
     const uint64_t a = off[r], b = off[r + 1];
+    if (b - a > kLongRule) continue;
     uint64_t sum = 0;
     for (uint64_t t = a; t < b; ++t) {
       if (N[t + 1] == N[t]) continue;  // a terminal or a leaf
@@ -1120,18 +1264,95 @@ static lcg_slp* postprocess_core(lcg_grammar* g, uint32_t flags, hipStream_t s) 
   return out.release();
 }
 
+// The long rules of p in id order and their pieces of kPiece positions: rule
+// ids[i] owns the pieces lp0[i] .. lp0[i+1] (host copy in h_ids / h_lp0).
+struct LongPieces {
+  std::vector<uint32_t> h_ids;
+  std::vector<uint64_t> h_lp0;
+  DBuf<uint32_t> ids;
+  DBuf<uint64_t> lp0, pa, pb, part_a, part_c;
+  uint64_t pieces = 0;
+};
+
+static void long_pieces(lcg_slp* p, LongPieces& L, hipStream_t s) {
+  const uint64_t cap = p->q / (kLongRule + 1) + 1;
+  DBuf<unsigned long long> cnt;
+  cnt.need(1, s);
+  zero(cnt.p, 8, s);
+  L.ids.need(cap, s);
+  if (p->g) {
+    k_slp_longlist<<<pgrid(p->g), kPB, 0, s>>>(p->off.p, p->g, L.ids.p, cnt.p);
+    PP_CHECK("slp_longlist");
+  }
+  const uint64_t n = read_dev(cnt.p, s);
+  if (!n) return;
+  L.h_ids.resize(n);
+  HIP_CHECK(hipMemcpyAsync(L.h_ids.data(), L.ids.p, n * 4, hipMemcpyDeviceToHost, s));
+  sync(s);
+  std::sort(L.h_ids.begin(), L.h_ids.end());
+  HIP_CHECK(hipMemcpyAsync(L.ids.p, L.h_ids.data(), n * 4, hipMemcpyHostToDevice, s));
+  DBuf<uint64_t> a, b;
+  a.need(n, s);
+  b.need(n, s);
+  k_slp_longoff<<<pgrid(n), kPB, 0, s>>>(L.ids.p, (uint32_t)n, p->off.p, a.p, b.p);
+  PP_CHECK("slp_longoff");
+  std::vector<uint64_t> ha(n), hb(n);
+  HIP_CHECK(hipMemcpyAsync(ha.data(), a.p, n * 8, hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(hb.data(), b.p, n * 8, hipMemcpyDeviceToHost, s));
+  sync(s);
+  std::vector<uint64_t> hpa, hpb;
+  L.h_lp0.assign(1, 0);
+  for (uint64_t i = 0; i < n; ++i) {
+    for (uint64_t x = ha[i]; x < hb[i]; x += kPiece) {
+      hpa.push_back(x);
+      hpb.push_back(std::min(hb[i], x + kPiece));
+    }
+    L.h_lp0.push_back(hpa.size());
+  }
+  L.pieces = hpa.size();
+  L.lp0.need(n + 1, s);
+  L.pa.need(L.pieces, s);
+  L.pb.need(L.pieces, s);
+  L.part_a.need(L.pieces, s);
+  L.part_c.need(L.pieces, s);
+  HIP_CHECK(hipMemcpyAsync(L.lp0.p, L.h_lp0.data(), (n + 1) * 8, hipMemcpyHostToDevice, s));
+  HIP_CHECK(hipMemcpyAsync(L.pa.p, hpa.data(), L.pieces * 8, hipMemcpyHostToDevice, s));
+  HIP_CHECK(hipMemcpyAsync(L.pb.p, hpb.data(), L.pieces * 8, hipMemcpyHostToDevice, s));
+  sync(s);  // the host vectors go out of scope
+}
+
 static void slp_lens(lcg_slp* p, hipStream_t s) {
   if (p->lens_ready) return;
   const uint32_t gc = std::max<uint32_t>(p->g, 1);
   p->E.need(gc, s);
   p->nt.need(gc, s);
+  DBuf<uint32_t> err;
+  err.need(1, s);
+  zero(err.p, 4, s);
+  LongPieces lp;
+  long_pieces(p, lp, s);
   for (size_t b = 0; b + 1 < p->bounds.size(); ++b) {
     const uint32_t r0 = p->bounds[b] - 256, r1 = p->bounds[b + 1] - 256;
     if (r1 <= r0) continue;
     k_slp_lens<<<pgrid(r1 - r0), kPB, 0, s>>>(p->off.p, p->rhs.p, p->mult.p, r0, r1, p->E.p,
-                                              p->nt.p);
+                                              p->nt.p, err.p);
     PP_CHECK("slp_lens");
+    const uint32_t i0 = (uint32_t)(std::lower_bound(lp.h_ids.begin(), lp.h_ids.end(), r0) -
+                                   lp.h_ids.begin());
+    const uint32_t i1 = (uint32_t)(std::lower_bound(lp.h_ids.begin(), lp.h_ids.end(), r1) -
+                                   lp.h_ids.begin());
+    if (i1 > i0) {  // the block's long rules, after its short ones
+      const uint64_t p0 = lp.h_lp0[i0], p1 = lp.h_lp0[i1];
+      k_slp_pieces_sum<0><<<(unsigned)std::min<uint64_t>(p1 - p0, 16384), kPB, 0, s>>>(
+          lp.pa.p, lp.pb.p, p0, p1, p->rhs.p, p->E.p, nullptr, nullptr, lp.part_a.p, lp.part_c.p);
+      PP_CHECK("slp_pieces_sum");
+      k_slp_long_lens<<<pgrid(i1 - i0), kPB, 0, s>>>(lp.ids.p, lp.lp0.p, i0, i1, lp.part_a.p,
+                                                     lp.part_c.p, p->mult.p, p->E.p, p->nt.p,
+                                                     err.p);
+      PP_CHECK("slp_long_lens");
+    }
   }
+  if (read_dev(err.p, s)) throw LcgError{LCG_EINVAL, "an expansion reaches 2^61 bytes"};
   p->S.need(p->q + 1, s);
   p->N.need(p->q + 1, s);
   {
@@ -1152,6 +1373,16 @@ static void slp_lens(lcg_slp* p, hipStream_t s) {
                                           reinterpret_cast<const RuleMeta*>(p->meta.p), p->g,
                                           p->gnt.p);
     PP_CHECK("slp_gnt");
+    if (lp.pieces) {
+      k_slp_pieces_sum<1><<<(unsigned)std::min<uint64_t>(lp.pieces, 16384), kPB, 0, s>>>(
+          lp.pa.p, lp.pb.p, 0, lp.pieces, p->rhs.p, nullptr, p->N.p,
+          reinterpret_cast<const RuleMeta*>(p->meta.p), lp.part_a.p, lp.part_c.p);
+      PP_CHECK("slp_pieces_sum");
+      k_slp_long_gnt<<<pgrid(lp.h_ids.size()), kPB, 0, s>>>(
+          lp.ids.p, lp.lp0.p, (uint32_t)lp.h_ids.size(), lp.part_a.p,
+          reinterpret_cast<const RuleMeta*>(p->meta.p), p->gnt.p);
+      PP_CHECK("slp_long_gnt");
+    }
     p->el.need(std::max<uint64_t>(p->g, 1), s);
     k_slp_el<<<pgrid(p->g), kPB, 0, s>>>(p->E.p, p->nt.p, p->g, p->el.p);
     PP_CHECK("slp_el");
@@ -1232,6 +1463,459 @@ static void slp_expand_core(lcg_slp* p, uint32_t j0, uint32_t j1, uint8_t* d_out
   sync(s);
 }
 
+// ---------------------------------------------------------------- stored file
+// The file of a post-processed grammar, with the bit budget of App. A
+// (storing the final grammar): right-hand-side cells of ceil(log g) bits,
+// one pointer of ceil(log G) bits per rule, one cell per string for C, plus a
+// run-rule bit per rule and the level block bounds.  Layout in include/lcg.h.
+// Fixed-width cells make both directions data-parallel: a 64-bit word of a
+// section holds known cells, so the encoder gives each output word a thread
+// and the decoder each run of cells.
+namespace {
+
+constexpr uint64_t kStoreMagic = 0x3130504C5347434Cull;  // the bytes "LCGSLP01"
+constexpr uint64_t kStoreMaxBounds = 1024;
+constexpr uint32_t kCellsPerThread = 16;
+
+uint32_t store_bits(uint64_t x) {  // binary digits of x, at least 1
+  uint32_t b = 1;
+  while (b < 64 && (x >> b)) ++b;
+  return b;
+}
+
+uint64_t store_words(uint64_t cells, uint32_t width) { return (cells * width + 63) / 64; }
+
+struct StoreLayout {
+  uint64_t r = 0, G = 0, k = 0, runs = 0, nb = 0;
+  uint32_t b_sym = 0, b_cell = 0, b_ptr = 0;
+  uint64_t wR = 0, wP = 0, wM = 0, wC = 0, wB = 0;  // section words
+  uint64_t oR = 0, oP = 0, oM = 0, oC = 0, oB = 0;  // section starts (words)
+  uint64_t bytes = 0;
+  void place() {
+    wR = store_words(G, b_cell);
+    wP = store_words(r, b_ptr);
+    wM = store_words(r, 1);
+    wC = store_words(k, b_sym);
+    wB = store_words(nb, 32);
+    oR = 8;
+    oP = oR + wR;
+    oM = oP + wP;
+    oC = oM + wM;
+    oB = oC + wC;
+    bytes = (oB + wB) * 8;
+  }
+};
+
+// cell i of width b (1..64) of a section
+__device__ __forceinline__ uint64_t cell_get(const uint64_t* __restrict__ w, uint64_t i, uint32_t b) {
+  const uint64_t bit = i * b;
+  const uint64_t q = bit >> 6;
+  const uint32_t o = (uint32_t)(bit & 63);
+  uint64_t v = w[q] >> o;
+  if (o + b > 64) v |= w[q + 1] << (64 - o);
+  return b == 64 ? v : v & ((1ull << b) - 1);
+}
+
+// number of entries of the ascending a[0..n) below key
+__device__ __forceinline__ uint64_t count_below(const uint64_t* __restrict__ a, uint64_t n,
+                                                uint64_t key) {
+  uint64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Word wi of a section of n cells of width b, from the cells' values get(i),
+// asked in increasing i.
+template <typename Get>
+__device__ __forceinline__ uint64_t pack_word(uint64_t wi, uint64_t n, uint32_t b, Get& get) {
+  const uint64_t lo = wi * 64;
+  const uint64_t end = min(n, (lo + 64 + b - 1) / b);
+  uint64_t word = 0;
+  for (uint64_t i = lo / b; i < end; ++i) {
+    const uint64_t v = get(i);
+    const uint64_t at = i * b;
+    word |= at >= lo ? v << (at - lo) : v >> (lo - at);
+  }
+  return word;
+}
+
+// run rules: flag per rule, the longest run
+__global__ void k_st_runflags(const uint32_t* __restrict__ mult, uint64_t r,
+                              uint64_t* __restrict__ fl, uint32_t* __restrict__ longest) {
+  PP_LOOP(x, r) {
+    const uint32_t m = mult[x];
+    fl[x] = m >= 2;
+    if (m >= 2) atomicMax(longest, m);
+  }
+}
+
+// the run rules in id order and the cell of R that holds each one's length
+__global__ void k_st_runlist(const uint32_t* __restrict__ mult, const uint64_t* __restrict__ off,
+                             const uint64_t* __restrict__ rb, uint64_t r,
+                             uint32_t* __restrict__ rr, uint64_t* __restrict__ lcell) {
+  PP_LOOP(x, r) {
+    if (mult[x] < 2) continue;
+    const uint64_t j = rb[x];
+    rr[j] = (uint32_t)x;
+    lcell[j] = off[x] + j + 1;  // the rule's symbol cell is off[x] + j
+  }
+}
+
+// R: the cells of the right-hand sides, a length cell after each run rule's symbol
+struct RCells {
+  const uint32_t* rhs;
+  const uint32_t* mult;
+  const uint32_t* rr;
+  const uint64_t* lcell;
+  uint64_t runs;
+  uint64_t nl;  // length cells before the cell asked next
+  bool started = false;
+  __device__ uint64_t operator()(uint64_t i) {
+    if (!started) {
+      nl = count_below(lcell, runs, i);
+      started = true;
+    }
+    if (nl < runs && lcell[nl] == i) return mult[rr[nl++]];
+    return rhs[i - nl];
+  }
+};
+
+__global__ void k_st_pack_r(const uint32_t* __restrict__ rhs, const uint32_t* __restrict__ mult,
+                            const uint32_t* __restrict__ rr, const uint64_t* __restrict__ lcell,
+                            uint64_t runs, uint64_t G, uint32_t b, uint64_t nw,
+                            uint64_t* __restrict__ out) {
+  PP_LOOP(wi, nw) {
+    RCells get{rhs, mult, rr, lcell, runs, 0};
+    out[wi] = pack_word(wi, G, b, get);
+  }
+}
+
+// P: the first cell of rule x is off[x] plus the run rules before x
+__global__ void k_st_pack_p(const uint64_t* __restrict__ off, const uint64_t* __restrict__ rb,
+                            uint64_t r, uint32_t b, uint64_t nw, uint64_t* __restrict__ out) {
+  PP_LOOP(wi, nw) {
+    auto get = [&](uint64_t x) { return off[x] + rb[x]; };
+    out[wi] = pack_word(wi, r, b, get);
+  }
+}
+
+// M: one wave per 64 rules, one ballot per word
+__global__ void k_st_pack_m(const uint32_t* __restrict__ mult, uint64_t r, uint64_t nw,
+                            uint64_t* __restrict__ out) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
+  for (uint64_t wi = blockIdx.x * (uint64_t)(blockDim.x / 64) + (threadIdx.x >> 6); wi < nw;
+       wi += waves) {
+    const uint64_t x = wi * 64 + lane;
+    const uint64_t bits = __ballot(x < r && mult[x] >= 2);
+    if (lane == 0) out[wi] = bits;
+  }
+}
+
+__global__ void k_st_pack_c(const uint32_t* __restrict__ c, uint64_t k, uint32_t b, uint64_t nw,
+                            uint64_t* __restrict__ out) {
+  PP_LOOP(wi, nw) {
+    auto get = [&](uint64_t j) { return (uint64_t)c[j]; };
+    out[wi] = pack_word(wi, k, b, get);
+  }
+}
+
+// decode: pointers and run marks
+__global__ void k_st_unpack_pm(const uint64_t* __restrict__ P, const uint64_t* __restrict__ M,
+                               uint64_t r, uint32_t b_ptr, uint64_t* __restrict__ S,
+                               uint64_t* __restrict__ fl) {
+  PP_LOOP(x, r) {
+    S[x] = cell_get(P, x, b_ptr);
+    fl[x] = (M[x >> 6] >> (x & 63)) & 1;
+  }
+}
+
+// decode: the pointers start at 0 and rise, a rule spans at most 2^32 - 1
+// cells, a run rule exactly 2 (S[r] = G)
+__global__ void k_st_check_ptr(const uint64_t* __restrict__ S, const uint64_t* __restrict__ fl,
+                               uint64_t r, uint32_t* __restrict__ err) {
+  PP_LOOP(x, r) {
+    const uint64_t a = S[x], b = S[x + 1];
+    const bool bad = (x == 0 && a != 0) || b <= a || b - a > 0xFFFFFFFFull || (fl[x] && b - a != 2);
+    if (bad) atomicOr(err, 1u);
+  }
+}
+
+// decode: offsets, run list, placeholder multiplicities
+__global__ void k_st_rules(const uint64_t* __restrict__ S, const uint64_t* __restrict__ fl,
+                           const uint64_t* __restrict__ rb, uint64_t r,
+                           uint64_t* __restrict__ off, uint32_t* __restrict__ mult,
+                           uint32_t* __restrict__ rr, uint64_t* __restrict__ lcell) {
+  PP_LOOP(x, r) {
+    const uint64_t j = rb[x];
+    off[x] = S[x] - j;
+    mult[x] = fl[x] ? 0 : 1;
+    if (fl[x]) {
+      rr[j] = (uint32_t)x;
+      lcell[j] = S[x] + 1;
+    }
+  }
+}
+
+// decode: the first cell of each block (cb[b] = S[bounds[b] - 256]; S[r] = G)
+__global__ void k_st_blockcells(const uint64_t* __restrict__ S, const uint32_t* __restrict__ bounds,
+                                uint32_t nb, uint64_t* __restrict__ cb) {
+  PP_LOOP(b, nb) cb[b] = S[bounds[b] - 256];
+}
+
+// decode: kCellsPerThread consecutive cells of R per thread.  A length cell
+// gives its run rule's multiplicity (at least 2); any other cell is the next
+// right-hand-side symbol and must name an id below its block's first id.
+__global__ __launch_bounds__(kPB) void k_st_cells(const uint64_t* __restrict__ R, uint64_t G,
+                                                  uint32_t b, const uint64_t* __restrict__ lcell,
+                                                  const uint32_t* __restrict__ rr, uint64_t runs,
+                                                  const uint64_t* __restrict__ cb,
+                                                  const uint32_t* __restrict__ bounds, uint32_t nb,
+                                                  uint32_t* __restrict__ rhs,
+                                                  uint32_t* __restrict__ mult,
+                                                  uint32_t* __restrict__ err) {
+  __shared__ uint64_t s_cb[kStoreMaxBounds];
+  __shared__ uint32_t s_bd[kStoreMaxBounds];
+  for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) {
+    s_cb[i] = cb[i];
+    s_bd[i] = bounds[i];
+  }
+  __syncthreads();
+  const uint64_t chunks = (G + kCellsPerThread - 1) / kCellsPerThread;
+  PP_LOOP(t, chunks) {
+    const uint64_t i0 = t * kCellsPerThread;
+    const uint64_t i1 = min(G, i0 + kCellsPerThread);
+    uint64_t nl = count_below(lcell, runs, i0);
+    uint32_t blk = 0;  // the last block whose first cell is at most i0
+    for (uint32_t step = kStoreMaxBounds / 2; step; step >>= 1)
+      if (blk + step < nb && s_cb[blk + step] <= i0) blk += step;
+    bool bad = false;
+    for (uint64_t i = i0; i < i1; ++i) {
+      while (blk + 1 < nb && s_cb[blk + 1] <= i) ++blk;
+      const uint64_t v = cell_get(R, i, b);
+      if (nl < runs && lcell[nl] == i) {
+        bad |= v < 2;
+        mult[rr[nl]] = (uint32_t)v;
+        ++nl;
+      } else {
+        bad |= v >= s_bd[blk];
+        rhs[i - nl] = (uint32_t)v;
+      }
+    }
+    if (bad) atomicOr(err, 2u);
+  }
+}
+
+__global__ void k_st_unpack_c(const uint64_t* __restrict__ C, uint64_t k, uint32_t b, uint64_t ids,
+                              uint32_t* __restrict__ c, uint32_t* __restrict__ err) {
+  PP_LOOP(j, k) {
+    const uint64_t y = cell_get(C, j, b);
+    if (y >= ids) atomicOr(err, 4u);
+    c[j] = (uint32_t)y;
+  }
+}
+
+// the strings' total expansion, stopping at kLenLimit
+__global__ void k_st_total(const uint32_t* __restrict__ c, uint64_t k, const uint64_t* __restrict__ E,
+                           unsigned long long* __restrict__ total) {
+  uint64_t sum = 0;
+  PP_LOOP(j, k) {
+    const uint32_t y = c[j];
+    sum = min(sum + (y < 256 ? 1 : E[y - 256]), kLenLimit);
+  }
+  for (int d = 32; d; d >>= 1) sum = min(sum + (uint64_t)__shfl_down(sum, d), kLenLimit);
+  if ((threadIdx.x & 63) == 0 && sum) {
+    unsigned long long old = *total, seen;
+    do {
+      seen = old;
+      old = atomicCAS(total, seen, (unsigned long long)min((uint64_t)seen + sum, kLenLimit));
+    } while (old != seen);
+  }
+}
+
+}  // namespace
+
+// Size of p's stored file; with d_out (cap bytes at least that size) the
+// file is written there.
+static uint64_t store_encode(lcg_slp* p, uint8_t* d_out, uint64_t cap, hipStream_t s) {
+  StoreLayout L;
+  L.r = p->g;
+  L.k = p->k;
+  L.nb = p->bounds.size();
+  const uint64_t r = L.r;
+  DBuf<uint64_t> fl, rb, lcell;
+  DBuf<uint32_t> rr, longest;
+  fl.need(std::max<uint64_t>(r, 1), s);
+  rb.need(r + 1, s);
+  longest.need(1, s);
+  zero(longest.p, 4, s);
+  if (r) {
+    k_st_runflags<<<pgrid(r), kPB, 0, s>>>(p->mult.p, r, fl.p, longest.p);
+    PP_CHECK("st_runflags");
+  }
+  Scan sc;
+  sc.run(fl.p, rb.p, r, s);
+  uint64_t runs = 0;
+  uint32_t lg = 0;
+  HIP_CHECK(hipMemcpyAsync(&runs, rb.p + r, 8, hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(&lg, longest.p, 4, hipMemcpyDeviceToHost, s));
+  sync(s);
+  L.runs = runs;
+  L.G = p->q + runs;
+  L.b_sym = store_bits(255 + r);
+  L.b_cell = std::max(L.b_sym, runs ? store_bits(lg) : 1u);
+  L.b_ptr = r ? store_bits(L.G - 1) : 1;
+  L.place();
+  if (!d_out || cap < L.bytes) return L.bytes;
+  if (reinterpret_cast<uintptr_t>(d_out) % 8) throw LcgError{LCG_EINVAL, "d_out is not 8-byte aligned"};
+  uint64_t* w = reinterpret_cast<uint64_t*>(d_out);
+  std::vector<uint64_t> head = {kStoreMagic, r, L.G, L.k, runs, L.nb,
+                                L.b_sym | (uint64_t)L.b_cell << 8 | (uint64_t)L.b_ptr << 16,
+                                L.bytes};
+  std::vector<uint32_t> bnd(L.wB * 2, 0);
+  std::copy(p->bounds.begin(), p->bounds.end(), bnd.begin());
+  HIP_CHECK(hipMemcpyAsync(w, head.data(), 64, hipMemcpyHostToDevice, s));
+  HIP_CHECK(hipMemcpyAsync(w + L.oB, bnd.data(), L.wB * 8, hipMemcpyHostToDevice, s));
+  rr.need(std::max<uint64_t>(runs, 1), s);
+  lcell.need(std::max<uint64_t>(runs, 1), s);
+  if (runs) {
+    k_st_runlist<<<pgrid(r), kPB, 0, s>>>(p->mult.p, p->off.p, rb.p, r, rr.p, lcell.p);
+    PP_CHECK("st_runlist");
+  }
+  if (L.wR) {
+    k_st_pack_r<<<pgrid(L.wR), kPB, 0, s>>>(p->rhs.p, p->mult.p, rr.p, lcell.p, runs, L.G, L.b_cell,
+                                            L.wR, w + L.oR);
+    PP_CHECK("st_pack_r");
+  }
+  if (L.wP) {
+    k_st_pack_p<<<pgrid(L.wP), kPB, 0, s>>>(p->off.p, rb.p, r, L.b_ptr, L.wP, w + L.oP);
+    PP_CHECK("st_pack_p");
+    k_st_pack_m<<<pgrid(L.wM * 64), kPB, 0, s>>>(p->mult.p, r, L.wM, w + L.oM);
+    PP_CHECK("st_pack_m");
+  }
+  k_st_pack_c<<<pgrid(L.wC), kPB, 0, s>>>(p->c.p, L.k, L.b_sym, L.wC, w + L.oC);
+  PP_CHECK("st_pack_c");
+  sync(s);
+  return L.bytes;
+}
+
+// The grammar of a stored file (see include/lcg.h for what is checked).
+static lcg_slp* store_decode(const uint8_t* d_in, uint64_t n, hipStream_t s) {
+  auto bad = [](const char* why) { return LcgError{LCG_EINVAL, std::string("stored grammar: ") + why}; };
+  if (n < 64 || n % 8) throw bad("size is not a whole header plus words");
+  if (reinterpret_cast<uintptr_t>(d_in) % 8) throw LcgError{LCG_EINVAL, "d_in is not 8-byte aligned"};
+  const uint64_t* w = reinterpret_cast<const uint64_t*>(d_in);
+  uint64_t h[8];
+  HIP_CHECK(hipMemcpyAsync(h, w, 64, hipMemcpyDeviceToHost, s));
+  sync(s);
+  if (h[0] != kStoreMagic) throw bad("bad magic");
+  StoreLayout L;
+  L.r = h[1];
+  L.G = h[2];
+  L.k = h[3];
+  L.runs = h[4];
+  L.nb = h[5];
+  L.b_sym = h[6] & 0xFF;
+  L.b_cell = (h[6] >> 8) & 0xFF;
+  L.b_ptr = (h[6] >> 16) & 0xFF;
+  if (h[6] >> 24) throw bad("bad widths word");
+  if (h[7] != n) throw bad("size differs from the header");
+  const uint64_t r = L.r, G = L.G, k = L.k, runs = L.runs;
+  if (r > 0xFFFFFFFFull - 256 || k == 0 || k > 0xFFFFFFFFull || runs > r || G >= (1ull << 58) ||
+      G < r + runs || (r == 0 && G != 0) || L.nb < 1 || L.nb > kStoreMaxBounds)
+    throw bad("counts out of range");
+  if (L.b_sym != store_bits(255 + r) || L.b_cell < L.b_sym || L.b_cell > 32 ||
+      L.b_ptr != (r ? store_bits(G - 1) : 1u))
+    throw bad("widths do not match the counts");
+  L.place();
+  if (L.bytes != n) throw bad("sections do not fill the size");
+  std::vector<uint32_t> bnd(L.wB * 2);
+  HIP_CHECK(hipMemcpyAsync(bnd.data(), w + L.oB, L.wB * 8, hipMemcpyDeviceToHost, s));
+  sync(s);
+  bnd.resize(L.nb);
+  if (bnd[0] != 256 || bnd[L.nb - 1] != 256 + r) throw bad("bad block bounds");
+  for (uint64_t b = 1; b < L.nb; ++b)
+    if (bnd[b] < bnd[b - 1]) throw bad("bad block bounds");
+
+  std::unique_ptr<lcg_slp> out(new lcg_slp());
+  out->g = (uint32_t)r;
+  out->q = G - runs;
+  out->k = (uint32_t)k;
+  out->bounds = bnd;
+  out->off.need(r + 1, s);
+  out->rhs.need(std::max<uint64_t>(out->q, 1), s);
+  out->mult.need(std::max<uint64_t>(r, 1), s);
+  out->c.need(k, s);
+  DBuf<uint64_t> S, fl, rb, lcell, cb;
+  DBuf<uint32_t> rr, err, bd;
+  S.need(r + 1, s);
+  fl.need(std::max<uint64_t>(r, 1), s);
+  rb.need(r + 1, s);
+  err.need(1, s);
+  zero(err.p, 4, s);
+  if (r) {
+    k_st_unpack_pm<<<pgrid(r), kPB, 0, s>>>(w + L.oP, w + L.oM, r, L.b_ptr, S.p, fl.p);
+    PP_CHECK("st_unpack_pm");
+  }
+  k_pp_set<<<1, 1, 0, s>>>(S.p + r, G);
+  PP_CHECK("pp_set");
+  if (r) {
+    k_st_check_ptr<<<pgrid(r), kPB, 0, s>>>(S.p, fl.p, r, err.p);
+    PP_CHECK("st_check_ptr");
+  }
+  Scan sc;
+  sc.run(fl.p, rb.p, r, s);
+  uint64_t nruns = 0;
+  uint32_t e = 0;
+  HIP_CHECK(hipMemcpyAsync(&nruns, rb.p + r, 8, hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(&e, err.p, 4, hipMemcpyDeviceToHost, s));
+  sync(s);
+  if (nruns != runs) throw bad("run count differs from the header");
+  if (e) throw bad("bad rule pointers");
+  // the pointers are sound: every length cell lies inside R and the cells
+  // before cell i hold at most i of them
+  rr.need(std::max<uint64_t>(runs, 1), s);
+  lcell.need(std::max<uint64_t>(runs, 1), s);
+  if (r) {
+    k_st_rules<<<pgrid(r), kPB, 0, s>>>(S.p, fl.p, rb.p, r, out->off.p, out->mult.p, rr.p, lcell.p);
+    PP_CHECK("st_rules");
+  }
+  k_pp_set<<<1, 1, 0, s>>>(out->off.p + r, G - runs);
+  PP_CHECK("pp_set");
+  bd.need(L.nb, s);
+  cb.need(L.nb, s);
+  HIP_CHECK(hipMemcpyAsync(bd.p, bnd.data(), L.nb * 4, hipMemcpyHostToDevice, s));
+  k_st_blockcells<<<1, kPB, 0, s>>>(S.p, bd.p, (uint32_t)L.nb, cb.p);
+  PP_CHECK("st_blockcells");
+  if (G) {
+    const uint64_t chunks = (G + kCellsPerThread - 1) / kCellsPerThread;
+    k_st_cells<<<pgrid(chunks), kPB, 0, s>>>(w + L.oR, G, L.b_cell, lcell.p, rr.p, runs, cb.p, bd.p,
+                                             (uint32_t)L.nb, out->rhs.p, out->mult.p, err.p);
+    PP_CHECK("st_cells");
+  }
+  k_st_unpack_c<<<pgrid(k), kPB, 0, s>>>(w + L.oC, k, L.b_sym, 256 + r, out->c.p, err.p);
+  PP_CHECK("st_unpack_c");
+  e = read_dev(err.p, s);
+  if (e & 2) throw bad("a rule names an id of its own block or above, or a run is shorter than 2");
+  if (e & 4) throw bad("C names an id beyond the rules");
+  out->stats[6] = r;
+  out->stats[7] = G;
+  slp_lens(out.get(), s);
+  {
+    DBuf<uint64_t> tot;
+    tot.need(1, s);
+    zero(tot.p, 8, s);
+    k_st_total<<<std::min(pgrid(k), 1024u), kPB, 0, s>>>(out->c.p, k, out->E.p,
+                                                         reinterpret_cast<unsigned long long*>(tot.p));
+    PP_CHECK("st_total");
+    if (read_dev(tot.p, s) >= kLenLimit) throw bad("the strings reach 2^61 bytes");
+  }
+  return out.release();
+}
+
 }  // namespace lcg
 
 using namespace lcg;
@@ -1292,6 +1976,23 @@ lcg_status lcg_slp_expand_strings(lcg_slp_t p, uint32_t j0, uint32_t j1, uint8_t
     if (!p) throw LcgError{LCG_EINVAL, "slp is NULL"};
     if (cap && !d_out) throw LcgError{LCG_EINVAL, "d_out is NULL"};
     slp_expand_core(p, j0, j1, d_out, cap, d_offsets, total, stream);
+  });
+}
+
+lcg_status lcg_slp_encode(lcg_slp_t p, uint8_t* d_out, uint64_t cap, uint64_t* bytes,
+                          hipStream_t stream) {
+  return guard([&] {
+    if (!p || !bytes) throw LcgError{LCG_EINVAL, "slp or bytes is NULL"};
+    if (cap && !d_out) throw LcgError{LCG_EINVAL, "d_out is NULL"};
+    *bytes = store_encode(p, d_out, cap, stream);
+    if (d_out && cap < *bytes) throw LcgError{LCG_EINVAL, "output buffer too small"};
+  });
+}
+
+lcg_status lcg_slp_decode(const uint8_t* d_in, uint64_t bytes, hipStream_t stream, lcg_slp_t* out) {
+  return guard([&] {
+    if (!d_in || !out) throw LcgError{LCG_EINVAL, "d_in or out is NULL"};
+    *out = store_decode(d_in, bytes, stream);
   });
 }
 

@@ -30,7 +30,8 @@ EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_exp
            "lcg_info", "lcg_level_size", "lcg_level_copy", "lcg_c_copy", "lcg_stats",
            "lcg_stats_clear", "lcg_build_bytes", "lcg_free", "lcg_release_pool", "lcg_last_error",
            "lcg_postprocess", "lcg_slp_size", "lcg_slp_stats", "lcg_slp_device", "lcg_slp_copy",
-           "lcg_slp_expand_strings", "lcg_slp_free", "lcg_extract", "lcg_build_file", "lcg_lce")
+           "lcg_slp_expand_strings", "lcg_slp_free", "lcg_extract", "lcg_build_file", "lcg_lce",
+           "lcg_slp_encode", "lcg_slp_decode")
 
 EXTRACT_MAX = 2048
 
@@ -125,6 +126,10 @@ def lib():
     L.lcg_slp_expand_strings.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, vp,
                                          ctypes.c_uint64, vp, u64p, vp]
     L.lcg_slp_expand_strings.restype = st
+    L.lcg_slp_encode.argtypes = [vp, vp, ctypes.c_uint64, u64p, vp]
+    L.lcg_slp_encode.restype = st
+    L.lcg_slp_decode.argtypes = [vp, ctypes.c_uint64, vp, ctypes.POINTER(vp)]
+    L.lcg_slp_decode.restype = st
     L.lcg_build_file.argtypes = [vp, ctypes.c_char_p, ctypes.c_uint64, ctypes.POINTER(Opts), vp,
                                  u64p]
     L.lcg_build_file.restype = st
@@ -371,6 +376,24 @@ class Slp:
                                             out.numel(), ctypes.c_void_p(offs.data_ptr()),
                                             ctypes.byref(total), _stream(stream)))
         return out[:total.value], offs
+
+    def encode(self, stream=None):
+        """The stored file (layout in include/lcg.h) as a uint8 device tensor."""
+        import torch
+        n = ctypes.c_uint64()
+        _check(lib().lcg_slp_encode(self.h, None, 0, ctypes.byref(n), _stream(stream)))
+        out = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        _check(lib().lcg_slp_encode(self.h, ctypes.c_void_p(out.data_ptr()), n.value,
+                                    ctypes.byref(n), _stream(stream)))
+        return out
+
+
+def decode(data, stream=None):
+    """The post-processed grammar of a stored file (a uint8 device tensor)."""
+    h = ctypes.c_void_p()
+    _check(lib().lcg_slp_decode(ctypes.c_void_p(data.data_ptr()), data.numel(), _stream(stream),
+                                ctypes.byref(h)))
+    return Slp(h.value)
 
 
 def new(seed):

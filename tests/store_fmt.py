@@ -98,3 +98,41 @@ def doubling_chain(levels):
     rules = [([65, 65], 1)] + [([256 + i - 1, 256 + i - 1], 1) for i in range(1, levels)]
     bounds = list(range(256, 256 + levels + 1))
     return rules, [256 + levels - 1], bounds
+
+
+def run_of_one(rules, c, bounds, x):
+    """The file with run rule x's length cell set to 1 (still marked a run rule)."""
+    data = write(rules, c, bounds)
+    f = read(data)
+    cells = []
+    for rhs, m in rules:
+        cells += [rhs[0], m] if m >= 2 else list(rhs)
+    start = sum(2 if m >= 2 else len(rhs) for rhs, m in rules[:x])
+    cells[start + 1] = 1
+    sec = _pack(cells, f["b_cell"], f["section_words"][0])
+    return data[:64] + sec + data[64 + len(sec):]
+
+
+def bad_files(oracle_mod, seed):
+    """(name, bytes, fragment of the refusal's message) of malformed files,
+    each made from a good file of a small grammar with run rules."""
+    g = oracle_mod.build_strings([b"ACGTTTTTACGA" * 3, b"GGGACGT"], seed)
+    good = g.stored()
+    f = read(good)
+    rules, c, B = f["rules"], f["c"], f["bounds"]
+    out = [("magic", b"X" + good[1:], "magic"),
+           ("truncated", good[:-8], "size"),
+           ("short", good[:40], "size"),
+           ("wide cells", write(rules, c, B, b_cell=33), "widths")]
+    # the last rule naming its own id: a cycle would be possible
+    last = len(rules) - 1
+    bad = list(rules)
+    bad[last] = ([256 + last] + bad[last][0][1:], bad[last][1])
+    out.append(("own block", write(bad, c, B), "own block"))
+    runs = [x for x, (_, m) in enumerate(rules) if m >= 2]
+    out.append(("run of one", run_of_one(rules, c, B, runs[0]), "run"))
+    out.append(("C beyond", write(rules, [256 + len(rules)] + c[1:], B), "C names"))
+    out.append(("bounds", write(rules, c, [257] + B[1:]), "bounds"))
+    ch_rules, ch_c, ch_b = doubling_chain(61)
+    out.append(("lengths", write(ch_rules, ch_c, ch_b), "2^61"))
+    return out

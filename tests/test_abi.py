@@ -57,6 +57,15 @@ def test_host_only_entry_points(lcgmod):
     h = ctypes.c_void_p()
     assert lcgmod.lib().lcg_postprocess(g.h, 3, None, ctypes.byref(h)) == -1 and not h.value
     assert lcgmod.lib().lcg_postprocess(g.h, 8, None, ctypes.byref(h)) == -1
+    # stored files: missing arguments, sizes that cannot hold a header, misalignment
+    L = lcgmod.lib()
+    n = ctypes.c_uint64()
+    assert L.lcg_slp_encode(None, None, 0, ctypes.byref(n), None) == -1
+    assert L.lcg_slp_decode(None, 64, None, ctypes.byref(h)) == -1
+    for ptr, size in ((8, 40), (8, 70), (9, 64)):
+        assert L.lcg_slp_decode(ctypes.c_void_p(ptr), size, None, ctypes.byref(h)) == -1
+        assert not h.value
+    assert b"stored grammar" in L.lcg_last_error() or b"aligned" in L.lcg_last_error()
     g.free()
 
 

@@ -8,7 +8,7 @@ halving holds in every round and every string ends; sampled strings'
 sub-grammars equal the oracle's grammar of each string alone (stability,
 Def. 1); random substrings and longest common extensions match the input;
 and for the repeat-heavy collection the RL + Simp grammar decompresses to the
-input and keeps Simp's size identity.
+input, also through its stored file, and keeps Simp's size identity.
 """
 import numpy as np
 import pytest
@@ -89,6 +89,12 @@ def test_full_repeats(L):
     out, _ = slp.expand_strings()
     assert torch.equal(out, t)
     del out
+    # through the stored file and back
+    dec = L.decode(slp.encode())
+    out, _ = dec.expand_strings()
+    assert torch.equal(out, t)
+    del out
+    dec.free()
     # longest common extensions between the copies, against the bytes
     rng = np.random.default_rng(6)
     lens = np.diff(off.astype(np.int64))

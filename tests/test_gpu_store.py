@@ -1,0 +1,115 @@
+"""The stored file of a post-processed grammar on the GPU (lcg_slp_encode,
+lcg_slp_decode) against the oracle.
+
+The GPU grammar equals the oracle's rank for rank, so its file must equal the
+oracle's byte for byte, for every combination of RL and Simp.  Decoding the
+oracle's file on the GPU gives the oracle's decoded arrays, decompresses to
+the input and encodes back to the same bytes.  Every malformed file the
+oracle refuses is refused by the GPU decoder too, before anything is
+expanded.
+"""
+import numpy as np
+import pytest
+
+import store_fmt as SF
+from paper_2411_12439_amd import datagen as D
+
+pytestmark = pytest.mark.gpu
+SEED = D.HASH_SEED
+FLAGS = {"none": (False, False), "rl": (True, False), "simp": (False, True),
+         "rl_simp": (True, True)}
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2411_12439_amd import lcg
+    lcg.lib()
+    return lcg
+
+
+def _dev(data):
+    import torch
+    return torch.from_numpy(np.frombuffer(bytes(data), np.uint8).copy()).to("cuda")
+
+
+def _check_case(L, O, text, off, which):
+    rl, simp = FLAGS[which]
+    t, o = L.to_device(text, off)
+    g = L.build(t, o, seed=SEED)
+    slp = g.postprocess(rl=rl, simp=simp)
+    got = bytes(slp.encode().cpu().numpy())
+    og = O.build(text, off, SEED)
+    want = og.stored(rl=rl, simp=simp)
+    assert len(got) == len(want)
+    if got != want:
+        a = np.frombuffer(got, np.uint64)
+        b = np.frombuffer(want, np.uint64)
+        raise AssertionError("first differing word %d" % int(np.nonzero(a != b)[0][0]))
+    # decode the oracle's file on the GPU
+    dec = L.decode(_dev(want))
+    e = dec.export()
+    od = O.decode_stored(want)
+    for key in ("off", "rhs", "mult", "c"):
+        assert np.array_equal(e[key], od[key]), key
+    assert e["stats"].tolist()[6:] == od["stats"].tolist()[6:]
+    out, _ = dec.expand_strings()
+    assert np.array_equal(out.cpu().numpy(), text)
+    assert bytes(dec.encode().cpu().numpy()) == want
+
+
+@pytest.mark.parametrize("which", sorted(FLAGS))
+@pytest.mark.parametrize("config,scale", [("tiny", 1.0), ("bacterial", 0.01), ("repeats", 0.0005)])
+def test_file_equals_oracle(L, config, scale, which):
+    from oracle import oracle as O
+    print("stored: %s %g %s" % (config, scale, which), flush=True)
+    text, off = D.make_config(config, scale=scale)
+    _check_case(L, O, text, off, which)
+
+
+@pytest.mark.parametrize("which", ["none", "rl_simp"])
+def test_edge_collections(L, which):
+    from oracle import oracle as O
+    rng = np.random.default_rng(31)
+    dna = D.BASES[rng.integers(0, 4, 3000)].tobytes()
+    cases = [
+        [b"A", b"C", b"A"],                       # no rules at all
+        [b"T" * 5000],                            # a run longer than 2^b_sym
+        [b"A", dna, b"G" * 3, dna[:1000] + b"N" + dna[1001:], b"AC" * 800, b"x"],
+    ]
+    for strings in cases:
+        text, off = O.pack(strings)
+        _check_case(L, O, text, off, which)
+
+
+def test_malformed_files_are_refused(L):
+    from oracle import oracle as O
+    for name, data, frag in SF.bad_files(O, SEED):
+        print("malformed:", name, flush=True)
+        with pytest.raises(ValueError):
+            O.decode_stored(data)
+        with pytest.raises(L.LcgError) as e:
+            L.decode(_dev(data))
+        assert e.value.name == "LCG_EINVAL", name
+        assert frag in str(e.value), (name, str(e.value))
+
+
+def test_long_doubling_chain_decodes_without_expansion(L):
+    """2^60 bytes from 60 rules: accepted; lengths are kept, nothing expanded."""
+    rules, c, b = SF.doubling_chain(60)
+    dec = L.decode(_dev(SF.write(rules, c, b)))
+    assert dec.size() == (60, 120, 1)
+    assert dec.stats().tolist()[6:] == [60, 120]
+
+
+def test_small_buffer_and_query(L):
+    import ctypes
+    text, off = D.make_config("tiny", scale=0.1)
+    t, o = L.to_device(text, off)
+    slp = L.build(t, o, seed=SEED).postprocess()
+    full = slp.encode()
+    n = ctypes.c_uint64()
+    small = full[:64].clone()
+    rc = L.lib().lcg_slp_encode(slp.h, ctypes.c_void_p(small.data_ptr()), 64, ctypes.byref(n), None)
+    assert rc == -1 and n.value == full.numel()

@@ -108,48 +108,8 @@ def test_paper_budget_on_genome_like(oracle_mod):
     assert f["section_words"][1] == -(-r * math.ceil(math.log2(G)) // 64)
 
 
-def _bad_files(oracle_mod):
-    """(name, bytes, message fragment) of malformed files."""
-    g = oracle_mod.build_strings([b"ACGTTTTTACGA" * 3, b"GGGACGT"], SEED)
-    good = g.stored()
-    f = SF.read(good)
-    rules, c, B = f["rules"], f["c"], f["bounds"]
-    out = []
-    out.append(("magic", b"X" + good[1:], "magic"))
-    out.append(("truncated", good[:-8], "size"))
-    out.append(("short", good[:40], "size"))
-    out.append(("wide cells", SF.write(rules, c, B, b_cell=33), "widths"))
-    # a rule naming an id of its own block: a cycle would be possible
-    last = len(rules) - 1
-    bad = list(rules)
-    bad[last] = ([256 + last] + bad[last][0][1:], bad[last][1])
-    out.append(("own block", SF.write(bad, c, B), "own block"))
-    # a run of length 1
-    runs = [x for x, (_, m) in enumerate(rules) if m >= 2]
-    out.append(("run of one", _run_of_one(rules, c, B, runs[0]), "run"))
-    out.append(("C beyond", SF.write(rules, [256 + len(rules)] + c[1:], B), "C names"))
-    out.append(("bounds", SF.write(rules, c, [257] + B[1:]), "bounds"))
-    ch_rules, ch_c, ch_b = SF.doubling_chain(61)
-    out.append(("lengths", SF.write(ch_rules, ch_c, ch_b), "2^61"))
-    return out
-
-
-def _run_of_one(rules, c, B, x):
-    """The file with run rule x's length cell set to 1 (still a run rule)."""
-    data = SF.write(rules, c, B)
-    f = SF.read(data)
-    cells = []
-    for rhs, m in rules:
-        cells += [rhs[0], m] if m >= 2 else list(rhs)
-    start = sum(2 if m >= 2 else len(rhs) for rhs, m in rules[:x])
-    cells[start + 1] = 1
-    b = f["b_cell"]
-    sec = SF._pack(cells, b, f["section_words"][0])
-    return data[:64] + sec + data[64 + len(sec):]
-
-
 def test_decoder_rejects_malformed(oracle_mod):
-    for name, data, frag in _bad_files(oracle_mod):
+    for name, data, frag in SF.bad_files(oracle_mod, SEED):
         with pytest.raises(ValueError) as e:
             oracle_mod.decode_stored(data)
         assert frag in str(e.value), (name, str(e.value))
@@ -160,3 +120,14 @@ def test_doubling_chain_below_limit(oracle_mod):
     rules, c, b = SF.doubling_chain(60)
     d = oracle_mod.decode_stored(SF.write(rules, c, b))
     assert len(d["mult"]) == 60 and d["stats"].tolist()[6:] == [60, 120]
+
+
+def test_grammar_without_rules(oracle_mod):
+    """Strings of one byte each: no rules, C holds terminals (8-bit cells), one bound."""
+    g = oracle_mod.build_strings([b"A", b"C", b"A"], SEED)
+    data = g.stored()
+    f = SF.read(data)
+    assert (f["r"], f["G"], f["k"], f["nb"], f["b_sym"]) == (0, 0, 3, 1, 8)
+    assert f["c"] == [65, 67, 65] and f["bounds"] == [256]
+    assert len(data) == 64 + 8 + 8
+    assert oracle_mod.decode_stored(data, expand=True)["expansions"] == [b"A", b"C", b"A"]
