@@ -331,10 +331,20 @@ int oracle_merge(OracleGrammar* a, const OracleGrammar* b) {
 
 // exp(C[j]) by recursive substitution of right-hand sides down to level 0.
 // Returns the expansion length; writes at most cap bytes.
+uint64_t oracle_expand_symbol(const OracleGrammar* g, uint32_t level, uint32_t sym, uint8_t* out,
+                              uint64_t cap);
+
 uint64_t oracle_expand(const OracleGrammar* g, uint32_t j, uint8_t* out, uint64_t cap) {
+  return oracle_expand_symbol(g, g->c_level[j], g->c_sym[j], out, cap);
+}
+
+// exp(X) of the level-`level` symbol X = sym (level 0: the byte sym); returns
+// its length, writes at most cap bytes.
+uint64_t oracle_expand_symbol(const OracleGrammar* g, uint32_t level, uint32_t sym, uint8_t* out,
+                              uint64_t cap) {
   uint64_t len = 0;
   std::vector<std::pair<int, uint32_t>> stack;
-  stack.push_back({g->c_level[j], g->c_sym[j]});
+  stack.push_back({(int)level, sym});
   while (!stack.empty()) {
     std::pair<int, uint32_t> t = stack.back();
     stack.pop_back();
@@ -716,7 +726,7 @@ OracleSlp* oracle_slp_decode(const uint8_t* in, uint64_t n) {
   if (w[6] >> 24) return fail("bad widths word");
   if (w[7] != n) return fail("size differs from the header");
   if (r > 0xFFFFFFFFull - 256 || k == 0 || k > 0xFFFFFFFFull || runs > r || G >= (1ull << 58) ||
-      G < r + runs || nb < 2 || nb > 1024)
+      G < r + runs || (r == 0 && G != 0) || nb < 1 || nb > 1024)
     return fail("counts out of range");
   if (b_sym != nbits(255 + r) || b_cell < b_sym || b_cell > 32 || b_ptr != (r ? nbits(G - 1) : 1u))
     return fail("widths do not match the counts");
@@ -791,6 +801,37 @@ OracleSlp* oracle_slp_decode(const uint8_t* in, uint64_t n) {
 // of the match-completion step sketched in App. B), by comparing bytes:
 // forward (dir 0): the longest common prefix of T_j1[p1..] and T_j2[p2..];
 // backward (dir 1): the longest common suffix of T_j1[..p1) and T_j2[..p2).
+// lcp (dir 0) or lcs (dir 1) of exp(X) and exp(Y), X and Y grammar symbols
+// given as (level, rank) -- the quantities App. B's MEM sketch completes
+// matches with -- by expanding both and comparing bytes.  Returns 0, or -1
+// (oracle_last_error) for a symbol that does not exist.
+int oracle_symbol_lce(const OracleGrammar* g, uint32_t nq, const uint8_t* lv1, const uint32_t* s1,
+                      const uint8_t* lv2, const uint32_t* s2, uint32_t dir, uint64_t* out) {
+  auto exists = [&](uint32_t lv, uint32_t x) {
+    if (lv == 0) return x < 256;
+    return lv <= g->levels.size() && x < g->levels[lv - 1].size();
+  };
+  for (uint32_t q = 0; q < nq; ++q) {
+    if (!exists(lv1[q], s1[q]) || !exists(lv2[q], s2[q])) {
+      g_err = "no such symbol";
+      return -1;
+    }
+    std::vector<uint8_t> a(oracle_expand_symbol(g, lv1[q], s1[q], nullptr, 0));
+    std::vector<uint8_t> b(oracle_expand_symbol(g, lv2[q], s2[q], nullptr, 0));
+    oracle_expand_symbol(g, lv1[q], s1[q], a.data(), a.size());
+    oracle_expand_symbol(g, lv2[q], s2[q], b.data(), b.size());
+    uint64_t l = 0;
+    const uint64_t na = a.size(), nb = b.size();
+    if (dir == 0) {
+      while (l < na && l < nb && a[l] == b[l]) ++l;
+    } else {
+      while (l < na && l < nb && a[na - 1 - l] == b[nb - 1 - l]) ++l;
+    }
+    out[q] = l;
+  }
+  return 0;
+}
+
 void oracle_lce(const uint8_t* text, const uint64_t* off, uint32_t nq, const uint32_t* j1,
                 const uint64_t* p1, const uint32_t* j2, const uint64_t* p2, uint32_t dir,
                 uint64_t* out) {

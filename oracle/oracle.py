@@ -76,6 +76,12 @@ def lib():
         L.oracle_slp_expand.argtypes = [vp, ctypes.c_uint32, u8p, ctypes.c_uint64]
         L.oracle_slp_expand.restype = ctypes.c_uint64
         L.oracle_slp_free.argtypes = [vp]
+        L.oracle_symbol_lce.argtypes = [vp, ctypes.c_uint32, u8p, u32p, u8p, u32p,
+                                        ctypes.c_uint32, u64p]
+        L.oracle_symbol_lce.restype = ctypes.c_int
+        L.oracle_expand_symbol.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, u8p,
+                                           ctypes.c_uint64]
+        L.oracle_expand_symbol.restype = ctypes.c_uint64
         L.oracle_slp_bounds.argtypes = [vp, u32p]
         L.oracle_slp_bounds.restype = ctypes.c_uint32
         L.oracle_slp_encode.argtypes = [vp, u8p, ctypes.c_uint64]
@@ -159,6 +165,30 @@ class Grammar:
         n = L.oracle_expand(self.h, j, None, 0)
         out = np.zeros(max(n, 1), np.uint8)
         L.oracle_expand(self.h, j, _ptr(out, ctypes.c_uint8), n)
+        return out[:n].tobytes()
+
+    def symbol_lce(self, lv1, s1, lv2, s2, backward=False):
+        """lcp (or lcs with ``backward``) of exp(X), exp(Y) for symbol pairs
+        given as (level, rank); level 0 is a byte.  uint64[nq]."""
+        lv1 = np.ascontiguousarray(lv1, np.uint8)
+        lv2 = np.ascontiguousarray(lv2, np.uint8)
+        s1 = np.ascontiguousarray(s1, np.uint32)
+        s2 = np.ascontiguousarray(s2, np.uint32)
+        out = np.zeros(max(len(s1), 1), np.uint64)
+        rc = lib().oracle_symbol_lce(self.h, len(s1), _ptr(lv1, ctypes.c_uint8),
+                                     _ptr(s1, ctypes.c_uint32), _ptr(lv2, ctypes.c_uint8),
+                                     _ptr(s2, ctypes.c_uint32), 1 if backward else 0,
+                                     _ptr(out, ctypes.c_uint64))
+        if rc != 0:
+            raise ValueError(lib().oracle_last_error().decode())
+        return out[:len(s1)]
+
+    def expand_symbol(self, level, sym):
+        """exp(X) of the symbol (level, rank) as bytes."""
+        L = lib()
+        n = L.oracle_expand_symbol(self.h, level, sym, None, 0)
+        out = np.zeros(max(n, 1), np.uint8)
+        L.oracle_expand_symbol(self.h, level, sym, _ptr(out, ctypes.c_uint8), n)
         return out[:n].tobytes()
 
     def postprocess(self, rl=True, simp=True, expand=False):
