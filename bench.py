@@ -446,6 +446,49 @@ def extra_legs(args, out, text, off, t, o, n, k, seed):
                   "compared_gbps": round(float(fwd.sum() + bwd.sum()) / l_s / 1e9, 3)}
     print("[bench] lce: %.2f ms for %d queries (mean %.1f + %.1f bytes)" %
           (l_s * 1e3, 2 * len(anc), fwd.mean(), bwd.mean()), file=sys.stderr, flush=True)
+    # App. B's lcp(X, Y) / lcs(X, Y) of grammar symbols: the C entries of string
+    # pairs (whole strings, so every answer can be checked against the bytes)
+    import ctypes
+    cl = np.zeros(k, np.uint8)
+    cs = np.zeros(k, np.uint32)
+    lcg._check(lcg.lib().lcg_c_copy(g.h, cl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                    cs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+    ns = 100000
+    sj1 = rng.integers(0, k, ns)
+    sj2 = rng.integers(0, k, ns)
+    q = (torch.tensor(cl[sj1], device="cuda"), torch.tensor(cs[sj1].astype(np.int32), device="cuda"),
+         torch.tensor(cl[sj2], device="cuda"), torch.tensor(cs[sj2].astype(np.int32), device="cuda"))
+    sf = g.symbol_lce(*q).cpu().numpy()
+    sbk = g.symbol_lce(*q, backward=True).cpu().numpy()
+    def string(j):
+        if j not in strs:
+            strs[j] = text[off[j]:off[j + 1]].tobytes()
+        return strs[j]
+
+    for i in range(2000):
+        a, b = string(int(sj1[i])), string(int(sj2[i]))
+        lf, lb = int(sf[i]), int(sbk[i])
+        ok_f = a[:lf] == b[:lf] and (lf == min(len(a), len(b)) or a[lf] != b[lf])
+        ok_b = a[len(a) - lb:] == b[len(b) - lb:] and (
+            lb == min(len(a), len(b)) or a[len(a) - lb - 1] != b[len(b) - lb - 1])
+        if not (ok_f and ok_b):
+            raise SystemExit("lcg_symbol_lce answer %d is not the lcp / lcs" % i)
+    sts = []
+    for i in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.symbol_lce(*q)
+        g.symbol_lce(*q, backward=True)
+        torch.cuda.synchronize()
+        sts.append(time.perf_counter() - t0)
+    s_s = float(np.mean(sts))
+    out["symbol_lce"] = {"what": "lcg_symbol_lce: lcp and lcs of the C entries of 100,000 random "
+                                 "string pairs (exp(C[j]) = T_j; 2,000 answers checked on the bytes)",
+                         "ms": round(s_s * 1e3, 3), "queries_per_s": round(2 * ns / s_s),
+                         "mean_lcp_bytes": round(float(sf.mean()), 1),
+                         "mean_lcs_bytes": round(float(sbk.mean()), 1)}
+    print("[bench] symbol lce: %.2f ms for %d queries" % (s_s * 1e3, 2 * ns), file=sys.stderr,
+          flush=True)
     g.free()
     del out_t, offs_t
     out["expand"] = {"what": "lcg_expand_strings of all strings (decompression), output bytes/s",

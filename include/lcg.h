@@ -213,6 +213,21 @@ lcg_status lcg_extract(lcg_grammar_t g, uint32_t nq, const uint32_t* d_j, const 
 lcg_status lcg_lce(lcg_grammar_t g, uint32_t nq, const uint32_t* d_j1, const uint64_t* d_p1,
                    const uint32_t* d_j2, const uint64_t* d_p2, uint32_t backward,
                    uint64_t* d_out, hipStream_t stream);
+/*
+ * App. B's lcp(X, Y) and lcs(X, Y): the longest common prefix (backward = 0)
+ * or suffix (backward = 1) of exp(X) and exp(Y) for grammar symbols X and Y,
+ * the quantities that complete a match found among right-hand sides.  Query
+ * q names X = (d_lv1[q], d_s1[q]) and Y = (d_lv2[q], d_s2[q]) (device arrays:
+ * uint8 levels, uint32 ranks); level 0 is a terminal (the byte s), level
+ * i >= 1 the rank-s rule of level i.  d_out (uint64[nq]) receives the
+ * lengths.  The same cursor walk as lcg_lce, started at the symbols' first or
+ * last byte.  Synchronises the stream.  Errors: LCG_EINVAL (NULL arrays,
+ * backward > 1, a query naming no symbol: its output is not written, the
+ * others are), LCG_EOVERFLOW (64 levels or more).
+ */
+lcg_status lcg_symbol_lce(lcg_grammar_t g, uint32_t nq, const uint8_t* d_lv1, const uint32_t* d_s1,
+                          const uint8_t* d_lv2, const uint32_t* d_s2, uint32_t backward,
+                          uint64_t* d_out, hipStream_t stream);
 
 /* An empty grammar with hash family `seed` (no levels, no strings). */
 lcg_status lcg_new(uint64_t seed, lcg_grammar_t* out);

@@ -158,11 +158,69 @@ __device__ __forceinline__ uint8_t level1_byte(const LevelPtrs* lv_ptr, uint32_t
   return static_cast<const uint8_t*>(L.rhs)[L.off[r] + o];
 }
 
-// One thread per query: two cursors walk the strings together.  When both sit
-// at the same offset of the same symbol at some level, the rest of that
-// symbol (its expansion is the same) is skipped in one step -- the highest
-// such level first; otherwise the bytes of the two level-1 symbols are
-// compared up to a mismatch or the end of either symbol.
+// The common extension of exp(y1) from offset p1 and exp(y2) from offset p2
+// (level t1 and t2 symbols of expansion lengths n1, n2; level 0: a byte),
+// forward or, with BACK, backward from just before p1, p2.  Two cursors walk
+// the expansions together.  When both sit at the same offset of the same
+// symbol at some level, the rest of that symbol (its expansion is the same)
+// is skipped in one step -- the highest such level first; otherwise the bytes
+// of the two level-1 symbols are compared up to a mismatch or the end of
+// either symbol.
+template <bool BACK>
+__device__ uint64_t lce_walk(const LevelPtrs* __restrict__ lv_ptr,
+                             const uint64_t* const* __restrict__ explen, int t1, uint32_t y1,
+                             uint64_t p1, uint64_t n1, int t2, uint32_t y2, uint64_t p2,
+                             uint64_t n2) {
+  // bytes available in the walking direction
+  uint64_t room1 = BACK ? p1 : n1 - p1, room2 = BACK ? p2 : n2 - p2;
+  if (!room1 || !room2) return 0;
+  Cursor a, b;
+  cursor_init(a, t1, y1, BACK ? p1 - 1 : p1, lv_ptr, explen);
+  cursor_init(b, t2, y2, BACK ? p2 - 1 : p2, lv_ptr, explen);
+  uint64_t len = 0;
+  for (;;) {
+    uint64_t s = 0;
+    for (int l = min(a.top, b.top); l >= 1; --l) {
+      if (a.sym[l] == b.sym[l] && a.off[l] == b.off[l]) {
+        s = BACK ? a.off[l] + 1 : sym_len(explen, l, a.sym[l]) - a.off[l];
+        break;
+      }
+    }
+    if (!s) {
+      // byte by byte inside the two level-1 symbols (or the single bytes)
+      uint64_t oa = a.top ? a.off[1] : 0, ob = b.top ? b.off[1] : 0;
+      const uint64_t ea = a.top ? sym_len(explen, 1, a.sym[1]) : 1;
+      const uint64_t eb = b.top ? sym_len(explen, 1, b.sym[1]) : 1;
+      bool mismatch = false;
+      for (;;) {
+        const uint8_t xa = a.top ? level1_byte(lv_ptr, a.sym[1], oa) : (uint8_t)a.sym[0];
+        const uint8_t xb = b.top ? level1_byte(lv_ptr, b.sym[1], ob) : (uint8_t)b.sym[0];
+        if (xa != xb) {
+          mismatch = true;
+          break;
+        }
+        ++s;
+        if (BACK ? (oa == 0 || ob == 0) : (oa + 1 == ea || ob + 1 == eb)) break;
+        if (BACK) {
+          --oa;
+          --ob;
+        } else {
+          ++oa;
+          ++ob;
+        }
+      }
+      if (mismatch) return len + s;
+    }
+    len += s;
+    if (s >= room1 || s >= room2) return len;  // an expansion ends
+    room1 -= s;
+    room2 -= s;
+    cursor_move<BACK>(a, s, lv_ptr, explen);
+    cursor_move<BACK>(b, s, lv_ptr, explen);
+  }
+}
+
+// One thread per query: positions p1 of string j1 and p2 of string j2.
 template <bool BACK>
 __global__ __launch_bounds__(64) void k_lce(const LevelPtrs* __restrict__ lv_ptr,
                                             const uint64_t* const* __restrict__ explen,
@@ -187,60 +245,33 @@ __global__ __launch_bounds__(64) void k_lce(const LevelPtrs* __restrict__ lv_ptr
       atomicAdd(bad, 1u);
       continue;
     }
-    // bytes available in the walking direction
-    uint64_t room1 = BACK ? p1 : n1 - p1, room2 = BACK ? p2 : n2 - p2;
-    if (!room1 || !room2) {
-      out[q] = 0;
+    out[q] = lce_walk<BACK>(lv_ptr, explen, t1, c_sym[j1], p1, n1, t2, c_sym[j2], p2, n2);
+  }
+}
+
+// One thread per query: the whole expansions of the symbols (lv1, s1) and
+// (lv2, s2), from their first (or, with BACK, last) byte.  lv_size[l] is the
+// number of level-l symbols (256 at level 0).
+template <bool BACK>
+__global__ __launch_bounds__(64) void k_symbol_lce(const LevelPtrs* __restrict__ lv_ptr,
+                                                   const uint64_t* const* __restrict__ explen,
+                                                   const uint32_t* __restrict__ lv_size,
+                                                   uint32_t levels, uint32_t nq,
+                                                   const uint8_t* __restrict__ qlv1,
+                                                   const uint32_t* __restrict__ qs1,
+                                                   const uint8_t* __restrict__ qlv2,
+                                                   const uint32_t* __restrict__ qs2,
+                                                   uint64_t* __restrict__ out, unsigned int* bad) {
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+    const uint32_t t1 = qlv1[q], t2 = qlv2[q], y1 = qs1[q], y2 = qs2[q];
+    if (t1 > levels || t2 > levels || y1 >= lv_size[t1] || y2 >= lv_size[t2]) {
+      atomicAdd(bad, 1u);
       continue;
     }
-    Cursor a, b;
-    cursor_init(a, t1, c_sym[j1], BACK ? p1 - 1 : p1, lv_ptr, explen);
-    cursor_init(b, t2, c_sym[j2], BACK ? p2 - 1 : p2, lv_ptr, explen);
-    uint64_t len = 0;
-    for (;;) {
-      uint64_t s = 0;
-      for (int l = min(a.top, b.top); l >= 1; --l) {
-        if (a.sym[l] == b.sym[l] && a.off[l] == b.off[l]) {
-          s = BACK ? a.off[l] + 1 : sym_len(explen, l, a.sym[l]) - a.off[l];
-          break;
-        }
-      }
-      if (!s) {
-        // byte by byte inside the two level-1 symbols (or the one-byte strings)
-        uint64_t oa = a.top ? a.off[1] : 0, ob = b.top ? b.off[1] : 0;
-        const uint64_t ea = a.top ? sym_len(explen, 1, a.sym[1]) : 1;
-        const uint64_t eb = b.top ? sym_len(explen, 1, b.sym[1]) : 1;
-        bool mismatch = false;
-        for (;;) {
-          const uint8_t xa = a.top ? level1_byte(lv_ptr, a.sym[1], oa) : (uint8_t)a.sym[0];
-          const uint8_t xb = b.top ? level1_byte(lv_ptr, b.sym[1], ob) : (uint8_t)b.sym[0];
-          if (xa != xb) {
-            mismatch = true;
-            break;
-          }
-          ++s;
-          if (BACK ? (oa == 0 || ob == 0) : (oa + 1 == ea || ob + 1 == eb)) break;
-          if (BACK) {
-            --oa;
-            --ob;
-          } else {
-            ++oa;
-            ++ob;
-          }
-        }
-        if (mismatch) {
-          len += s;
-          break;
-        }
-      }
-      len += s;
-      if (s >= room1 || s >= room2) break;  // a string ends
-      room1 -= s;
-      room2 -= s;
-      cursor_move<BACK>(a, s, lv_ptr, explen);
-      cursor_move<BACK>(b, s, lv_ptr, explen);
-    }
-    out[q] = len;
+    const uint64_t n1 = t1 ? sym_len(explen, t1, y1) : 1;
+    const uint64_t n2 = t2 ? sym_len(explen, t2, y2) : 1;
+    out[q] = lce_walk<BACK>(lv_ptr, explen, (int)t1, y1, BACK ? n1 : 0, n1, (int)t2, y2,
+                            BACK ? n2 : 0, n2);
   }
 }
 
@@ -308,6 +339,42 @@ lcg_status lcg_lce(lcg_grammar_t g, uint32_t nq, const uint32_t* d_j1, const uin
       throw LcgError{LCG_EINVAL, std::to_string(nbad) + " quer" + (nbad == 1 ? "y" : "ies") +
                                      " out of range (string index, or position beyond the "
                                      "string's end)"};
+  });
+}
+
+lcg_status lcg_symbol_lce(lcg_grammar_t g, uint32_t nq, const uint8_t* d_lv1, const uint32_t* d_s1,
+                          const uint8_t* d_lv2, const uint32_t* d_s2, uint32_t backward,
+                          uint64_t* d_out, hipStream_t stream) {
+  return guard([&] {
+    if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    if (backward > 1) throw LcgError{LCG_EINVAL, "backward must be 0 or 1"};
+    if (!nq) return;
+    if (!d_lv1 || !d_s1 || !d_lv2 || !d_s2 || !d_out)
+      throw LcgError{LCG_EINVAL, "NULL query or output array"};
+    if (g->levels.size() >= (size_t)kMaxLv) throw LcgError{LCG_EOVERFLOW, "too many levels"};
+    ensure_explen(g, stream);
+    const uint32_t h = (uint32_t)g->levels.size();
+    std::vector<uint32_t> sizes(h + 1, 256);
+    for (uint32_t l = 1; l <= h; ++l) sizes[l] = g->levels[l - 1].u;
+    DBuf<uint32_t> lv_size;
+    lv_size.need(h + 1, stream);
+    HIP_CHECK(hipMemcpyAsync(lv_size.p, sizes.data(), (h + 1) * 4, hipMemcpyHostToDevice, stream));
+    DBuf<unsigned int> bad;
+    bad.need(1, stream);
+    launch_zero(bad.p, sizeof(unsigned int), stream);
+    const unsigned grid = std::min<uint32_t>((nq + 63) / 64, 16384u);
+    if (backward)
+      k_symbol_lce<true><<<grid, 64, 0, stream>>>(g->level_ptrs.p, g->explen_ptrs.p, lv_size.p, h,
+                                                 nq, d_lv1, d_s1, d_lv2, d_s2, d_out, bad.p);
+    else
+      k_symbol_lce<false><<<grid, 64, 0, stream>>>(g->level_ptrs.p, g->explen_ptrs.p, lv_size.p, h,
+                                                  nq, d_lv1, d_s1, d_lv2, d_s2, d_out, bad.p);
+    HIP_CHECK(hipGetLastError());
+    const unsigned int nbad = read_dev(bad.p, stream);  // also keeps `sizes` alive until the copy is done
+    if (nbad)
+      throw LcgError{LCG_EINVAL, std::to_string(nbad) + " quer" + (nbad == 1 ? "y names" : "ies name") +
+                                     " no symbol (level beyond the grammar's, or rank beyond "
+                                     "the level's rules)"};
   });
 }
 

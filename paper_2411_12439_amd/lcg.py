@@ -31,7 +31,7 @@ EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_exp
            "lcg_stats_clear", "lcg_build_bytes", "lcg_free", "lcg_release_pool", "lcg_last_error",
            "lcg_postprocess", "lcg_slp_size", "lcg_slp_stats", "lcg_slp_device", "lcg_slp_copy",
            "lcg_slp_expand_strings", "lcg_slp_free", "lcg_extract", "lcg_build_file", "lcg_lce",
-           "lcg_slp_encode", "lcg_slp_decode")
+           "lcg_slp_encode", "lcg_slp_decode", "lcg_symbol_lce")
 
 EXTRACT_MAX = 2048
 
@@ -136,6 +136,8 @@ def lib():
     L.lcg_extract.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, vp, vp, vp]
     L.lcg_lce.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, vp, ctypes.c_uint32, vp, vp]
     L.lcg_lce.restype = st
+    L.lcg_symbol_lce.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, vp, ctypes.c_uint32, vp, vp]
+    L.lcg_symbol_lce.restype = st
     L.lcg_extract.restype = st
     L.lcg_slp_free.argtypes = [vp]
     L.lcg_slp_free.restype = None
@@ -314,6 +316,22 @@ class Grammar:
                              ctypes.c_void_p(p2.data_ptr()), 1 if backward else 0,
                              ctypes.c_void_p(out.data_ptr()), _stream(stream)))
         return out[:j1.numel()]
+
+    def symbol_lce(self, lv1, s1, lv2, s2, backward=False, stream=None):
+        """lcp (or lcs) of the expansions of symbol pairs (level, rank) (lcg_symbol_lce):
+        int64 device tensor."""
+        import torch
+        dev = "cuda"
+        lv1 = torch.as_tensor(lv1, dtype=torch.uint8, device=dev).contiguous()
+        lv2 = torch.as_tensor(lv2, dtype=torch.uint8, device=dev).contiguous()
+        s1 = torch.as_tensor(s1, dtype=torch.int32, device=dev).contiguous()
+        s2 = torch.as_tensor(s2, dtype=torch.int32, device=dev).contiguous()
+        out = torch.zeros(max(s1.numel(), 1), dtype=torch.int64, device=dev)
+        _check(lib().lcg_symbol_lce(self.h, s1.numel(), ctypes.c_void_p(lv1.data_ptr()),
+                                    ctypes.c_void_p(s1.data_ptr()), ctypes.c_void_p(lv2.data_ptr()),
+                                    ctypes.c_void_p(s2.data_ptr()), 1 if backward else 0,
+                                    ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+        return out[:s1.numel()]
 
     def postprocess(self, rl=True, simp=True, stream=None):
         """RL and/or Simp (Sec. 2.2) on the device: a new Slp (this grammar is unchanged)."""

@@ -1,11 +1,15 @@
-"""Random access (lcg_extract) and longest common extensions (lcg_lce).
+"""Random access (lcg_extract), longest common extensions (lcg_lce) and the
+lcp / lcs of symbol pairs (lcg_symbol_lce).
 
 Extraction is checked against slices of the input (the grammar derives it
 exactly), byte for byte: queries hit string starts and ends, single bytes,
 the maximum length, strings of length one (C at level 0) and long level-1
 rules (homopolymers).  LCE answers are checked against the oracle's plain
 byte comparison, in both directions, on random pairs and on pairs at the same
-offset of copies of one base (long matches), including string ends.
+offset of copies of one base (long matches), including string ends.  Symbol
+pairs (App. B's lcp(X, Y), lcs(X, Y)) are checked against the oracle's
+expand-and-compare on random pairs within and across levels, C entries
+(whole strings of copies: long common parts) and symbols against themselves.
 """
 import numpy as np
 import pytest
@@ -178,3 +182,65 @@ def test_lce_rejects_out_of_range(L):
         with pytest.raises(L.LcgError) as e:
             g.lce(*args)
         assert e.value.name == "LCG_EINVAL"
+
+
+# --------------------------------------------- symbol pairs: lcp(X, Y), lcs(X, Y)
+def _symbol_queries(rng, e, nq):
+    """Pairs within a level (half) and across levels, then C entries of random
+    string pairs (whole strings) and each C entry against itself."""
+    levels = e["levels"]
+    h = len(levels)
+    size = lambda lv: 256 if lv == 0 else len(levels[lv - 1]["fp"])
+    lv1 = rng.integers(0, h + 1, nq)
+    lv2 = np.where(rng.random(nq) < 0.5, lv1, rng.integers(0, h + 1, nq))
+    s1 = np.array([rng.integers(0, size(v)) for v in lv1])
+    s2 = np.array([rng.integers(0, size(v)) for v in lv2])
+    # the C entries against each other: whole strings
+    k = len(e["c_sym"])
+    j1 = rng.integers(0, k, nq // 4)
+    j2 = rng.integers(0, k, nq // 4)
+    lv1 = np.concatenate([lv1, e["c_level"][j1], e["c_level"][j1]])
+    s1 = np.concatenate([s1, e["c_sym"][j1], e["c_sym"][j1]])
+    lv2 = np.concatenate([lv2, e["c_level"][j2], e["c_level"][j1]])
+    s2 = np.concatenate([s2, e["c_sym"][j2], e["c_sym"][j1]])
+    return lv1, s1, lv2, s2
+
+
+@pytest.mark.parametrize("backward", [False, True])
+@pytest.mark.parametrize("config,scale", [("tiny", 0.25), ("bacterial", 0.01), ("repeats", 0.0005)])
+def test_symbol_lce_equals_oracle(L, config, scale, backward):
+    from oracle import oracle as O
+    text, off = D.make_config(config, scale=scale)
+    t, o = L.to_device(text, off)
+    g = L.build(t, o, seed=SEED)
+    og = O.build(text, off, SEED)
+    rng = np.random.default_rng(23)
+    q = _symbol_queries(rng, og.export(), 600)
+    got = g.symbol_lce(*q, backward=backward).cpu().numpy()
+    want = og.symbol_lce(*q, backward).astype(np.int64)
+    assert np.array_equal(got, want), int(np.nonzero(got != want)[0][0])
+
+
+def test_symbol_lce_edges_and_errors(L):
+    from oracle import oracle as O
+    strings = [b"A", b"C", b"T" * 3000, b"T" * 2999 + b"G", b"ACG" * 500, b"ACG" * 499 + b"ACC"]
+    text, off = O.pack(strings)
+    t, o = L.to_device(text, off)
+    g = L.build(t, o, seed=SEED)
+    og = O.build(text, off, SEED)
+    e = og.export()
+    rng = np.random.default_rng(24)
+    for backward in (False, True):
+        q = _symbol_queries(rng, e, 300)
+        got = g.symbol_lce(*q, backward=backward).cpu().numpy()
+        assert np.array_equal(got, og.symbol_lce(*q, backward).astype(np.int64))
+    h = len(e["levels"])
+    for args in (([h + 1], [0], [1], [0]), ([1], [len(e["levels"][0]["fp"])], [1], [0]),
+                 ([0], [256], [0], [0])):
+        with pytest.raises(L.LcgError) as ex:
+            g.symbol_lce(*args)
+        assert ex.value.name == "LCG_EINVAL"
+    # a grammar of one-byte strings: only bytes exist
+    ta, oa = L.to_device(*O.pack([b"A", b"C"]))
+    g1 = L.build(ta, oa, seed=SEED)
+    assert g1.symbol_lce([0, 0], [65, 65], [0, 0], [65, 67]).cpu().tolist() == [1, 0]
