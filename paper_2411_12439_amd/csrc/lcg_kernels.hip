@@ -393,6 +393,40 @@ __global__ __launch_bounds__(kBlock) void k_classify(RoundIn in0, uint64_t* __re
         s_end = in.off[j + 1];
       }
       const int xe = in.n - b < (uint64_t)kItems ? (int)(in.n - b) : kItems;
+      if (s_start < b && b + kItems < s_end) {
+        // The window b-1 .. b+16 lies inside one string and holds no string
+        // start: all 16 positions at once.  S(x), the direction of the first
+        // change at or after x (F[r] > F[l] at the first r > l with F[r] !=
+        // F[l]), obeys S(x) = G(x) | (E(x) & S(x+1)) with G = change to a
+        // larger value, E = equal neighbour: a carry chain running from high
+        // x to low x, i.e. the carries of an addition on the bit-reversed
+        // masks.  The run reaching past the window takes the value found by
+        // walking it.
+        const uint32_t full = (1u << kItems) - 1u;
+        const uint32_t ne = ~eq & full;
+        const uint32_t G = ne & gt;
+        const uint32_t gr = __builtin_bitreverse32(G) >> (32 - kItems);
+        const uint32_t pr = __builtin_bitreverse32(eq & full) >> (32 - kItems);
+        const uint32_t A = gr | pr, B = gr;
+        const uint32_t carries = ((A + B) ^ A ^ B) >> 1;  // carry out of reversed bit i
+        uint32_t S = __builtin_bitreverse32(carries & full) >> (32 - kItems);
+        // positions whose equal run reaches the end of the window
+        const uint32_t tail = ne ? ~((2u << (31 - __builtin_clz(ne))) - 1u) & full : full;
+        if (desc & tail) {
+          const uint32_t fl = fw[kItems + 1];
+          uint64_t r = b + kItems + 1;
+          uint32_t fr = 0;
+          bool more = true;
+          while (more && r < s_end) {
+            const uint64_t i = r - t0 + 1;
+            fr = i < (uint64_t)kCStage ? s_f[cpad((uint32_t)i)] : fval<BYTES>(in, s_lut, r);
+            more = fr == fl;
+            r += more ? 1 : 0;
+          }
+          if (r < s_end && fr > fl) S |= tail;
+        }
+        mask = desc & S;
+      } else {
       for (int x = 0; x < xe; ++x) {
         const uint64_t l = b + x;
         while (l >= s_end) {
@@ -426,6 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(RoundIn in0, uint64_t* __re
           }
         }
         mask |= (uint32_t)brk << x;
+      }
       }
     }
     s_mask[threadIdx.x] = mask;
