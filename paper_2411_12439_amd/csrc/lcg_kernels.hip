@@ -502,7 +502,7 @@ template <bool BYTES>
 struct EmitStage;
 template <>
 struct EmitStage<true> {
-  uint8_t sym[kStage];
+  alignas(16) uint8_t sym[kStage + 16];  // 16 spare bytes: word reads past the last phrase
 };
 template <>
 struct EmitStage<false> {
@@ -548,6 +548,19 @@ __device__ __forceinline__ void stage_tile(const RoundIn& in, uint64_t t0, EmitS
       }
     }
   }
+}
+
+// exact_key of a staged byte phrase (q <= 7 at tile offset p) from three
+// aligned LDS words instead of q byte reads: the same key.
+__device__ __forceinline__ bool exact_key_staged(const uint8_t* sym, uint32_t p, uint64_t q,
+                                                 uint64_t& k) {
+  if (q > 7) return false;
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(sym) + (p >> 2);
+  const uint64_t lo = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+  const uint32_t sh = (p & 3u) * 8u;
+  uint64_t v = sh ? (lo >> sh) | ((uint64_t)w[2] << (64 - sh)) : lo;
+  k = (v & ((1ull << (8 * q)) - 1ull)) | (q << 56);
+  return true;
 }
 
 // End of the phrase starting at tile offset s_start[jj]: the next break in
@@ -679,8 +692,12 @@ __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in0, const uint64_t* __
       uint64_t kk = 0;
       bool exact = false;
       if (key_bits == 0) {
-        if (e <= t0 + kStage) exact = exact_key<BYTES>(st.sym, l - t0, q, kk);
-        else exact = exact_key<BYTES>(in.sym, l, q, kk);
+        if (e <= t0 + kStage) {
+          if constexpr (BYTES) exact = exact_key_staged(st.sym, (uint32_t)(l - t0), q, kk);
+          else exact = exact_key<BYTES>(st.sym, l - t0, q, kk);
+        } else {
+          exact = exact_key<BYTES>(in.sym, l, q, kk);
+        }
       }
       if (exact) {
         key[base + jj] = kk;
