@@ -1506,21 +1506,43 @@ __global__ __launch_bounds__(256) void k_commit_list(uint64_t u_new, const uint3
 }
 
 // T^{i+1}: every phrase takes the (now committed) rank of its slot, and its
-// fingerprint when the next round needs it (fnext).
+// fingerprint when the next round needs it (fnext).  Four consecutive phrases
+// per thread: 16-byte loads and stores, four table reads in flight.
+constexpr int kRewriteItems = 4;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint64_t rank_and_fp(const Slot* __restrict__ table, uint32_t sidx) {
+  // kNone only after an overflow (the round is redone)
+  return sidx == kNone ? 0 : *reinterpret_cast<const uint64_t*>(&table[sidx].minocc);
+}
+
 __global__ __launch_bounds__(256) void k_rewrite(uint64_t d, const uint64_t* __restrict__ d_dev,
                                                  const uint32_t* __restrict__ slot_idx,
                                                  const Slot* __restrict__ table,
                                                  uint32_t* __restrict__ sym_next,
                                                  uint32_t* __restrict__ fnext) {
   if (d_dev) d = *d_dev;
-  const uint64_t o = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t o = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) * kRewriteItems;
   if (o >= d) return;
-  // the phrase arrays stream past (non-temporal), the table lines stay cached
-  const uint32_t sidx = __builtin_nontemporal_load(&slot_idx[o]);
-  // kNone only after an overflow (the round is redone)
-  const uint64_t fr = sidx == kNone ? 0 : *reinterpret_cast<const uint64_t*>(&table[sidx].minocc);
-  __builtin_nontemporal_store((uint32_t)(fr >> 32), &sym_next[o]);
-  if (fnext) __builtin_nontemporal_store((uint32_t)fr, &fnext[o]);
+  if (o + kRewriteItems <= d) {
+    // the phrase arrays stream past (non-temporal), the table lines stay cached
+    const u32x4 si = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(slot_idx + o));
+    const uint64_t f0 = rank_and_fp(table, si.x), f1 = rank_and_fp(table, si.y),
+                   f2 = rank_and_fp(table, si.z), f3 = rank_and_fp(table, si.w);
+    const u32x4 sv = {(uint32_t)(f0 >> 32), (uint32_t)(f1 >> 32), (uint32_t)(f2 >> 32),
+                      (uint32_t)(f3 >> 32)};
+    __builtin_nontemporal_store(sv, reinterpret_cast<u32x4*>(sym_next + o));
+    if (fnext) {
+      const u32x4 fv = {(uint32_t)f0, (uint32_t)f1, (uint32_t)f2, (uint32_t)f3};
+      __builtin_nontemporal_store(fv, reinterpret_cast<u32x4*>(fnext + o));
+    }
+  } else {
+    for (uint64_t x = o; x < d; ++x) {
+      const uint64_t fr = rank_and_fp(table, slot_idx[x]);
+      sym_next[x] = (uint32_t)(fr >> 32);
+      if (fnext) fnext[x] = (uint32_t)fr;
+    }
+  }
 }
 
 void launch_commit(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t* slot_idx, Slot* table,
@@ -1566,7 +1588,11 @@ void launch_commit(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t
         static_cast<const uint32_t*>(content), fnew, fprev, h, u_prev, q_prev, rule_off,
         static_cast<uint32_t*>(rule_rhs), rule_fp);
   LCG_LAUNCH_CHECK("commit_new");
-  k_rewrite<<<grid_for(d, 256), 256, 0, s>>>(d, d_dev, slot_idx, table, sym_next, fnext);
+  if ((reinterpret_cast<uintptr_t>(slot_idx) | reinterpret_cast<uintptr_t>(sym_next) |
+       reinterpret_cast<uintptr_t>(fnext)) & 15)
+    throw std::runtime_error("rewrite arrays are not 16-byte aligned");
+  k_rewrite<<<grid_for((d + kRewriteItems - 1) / kRewriteItems, 256), 256, 0, s>>>(
+      d, d_dev, slot_idx, table, sym_next, fnext);
   LCG_LAUNCH_CHECK("rewrite");
 }
 
