@@ -506,7 +506,7 @@ struct EmitStage<true> {
 };
 template <>
 struct EmitStage<false> {
-  uint32_t sym[kStage];
+  uint32_t sym[kStage + 4];  // 4 spare words: fixed-length reads past the last phrase
   uint32_t fp[kStage];
 };
 
@@ -561,6 +561,25 @@ __device__ __forceinline__ bool exact_key_staged(const uint8_t* sym, uint32_t p,
   uint64_t v = sh ? (lo >> sh) | ((uint64_t)w[2] << (64 - sh)) : lo;
   k = (v & ((1ull << (8 * q)) - 1ull)) | (q << 56);
   return true;
+}
+
+// exact_key of a staged phrase of ranks (q <= 4 at tile offset p): four
+// reads and a fold predicated on q instead of a loop of q steps; the same key.
+__device__ __forceinline__ bool exact_key_staged(const uint32_t* sym, uint32_t p, uint64_t q,
+                                                 uint64_t& k) {
+  if (q > 4) return false;
+  const int rb = rank_bits_for((uint32_t)q);
+  uint64_t kk = 0;
+  bool fits = true;
+#pragma unroll
+  for (uint32_t x = 0; x < 4; ++x) {
+    const uint64_t r = sym[p + x];
+    const bool take = x < q;
+    fits = fits && (!take || rb >= 32 || (r >> rb) == 0);
+    kk = take ? ((kk << rb) | r) : kk;
+  }
+  k = (q << 58) | kk;
+  return fits;
 }
 
 // End of the phrase starting at tile offset s_start[jj]: the next break in
@@ -693,8 +712,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in0, const uint64_t* __
       bool exact = false;
       if (key_bits == 0) {
         if (e <= t0 + kStage) {
-          if constexpr (BYTES) exact = exact_key_staged(st.sym, (uint32_t)(l - t0), q, kk);
-          else exact = exact_key<BYTES>(st.sym, l - t0, q, kk);
+          exact = exact_key_staged(st.sym, (uint32_t)(l - t0), q, kk);
         } else {
           exact = exact_key<BYTES>(in.sym, l, q, kk);
         }
