@@ -242,6 +242,10 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                 "traffic": None if traffic is None else round(traffic, 1),
+                # the HBM bytes the counters saw per launch over its mean duration:
+                # how close the kernel runs to the bandwidth it actually uses
+                "traffic_gbps": None if traffic is None or not ins_ns else
+                round(traffic / (ins_ns / max(launches, 1) * 1e-9) / 1e9, 1),
                 "kernel": ROOFLINE_KERNEL, "launches_per_step": launches,
                 "mean_launch_us": round(ins_ns / max(launches, 1) / 1e3, 2),
                 "alg_bytes_per_launch": round(ins_alg / max(launches, 1), 1),
