@@ -374,11 +374,13 @@ lcg_status lcg_slp_encode(lcg_slp_t p, uint8_t* d_out, uint64_t cap, uint64_t* b
  * The grammar of the stored file d_in (device, 8-byte aligned, `bytes` long)
  * into *out (free with lcg_slp_free).  The caller keeps d_in.  Everything is
  * checked before anything is expanded; LCG_EINVAL (with lcg_last_error
- * naming the fault) unless: the header's counts, widths and size agree; the
- * bounds rise from 256 to 256 + r (1 to 1024 of them); the pointers start
- * at 0 and rise, a run rule spanning two cells; every cell of a rule of block
- * b names an id below B[b]; run lengths are at least 2; C names ids below
- * 256 + r; no rule and no sum of the strings' lengths reaches 2^61 bytes.
+ * naming the fault) unless: the header's counts, widths (b_cell that of the
+ * longest run) and size agree; padding bits are zero; the bounds rise from
+ * 256 to 256 + r (1 to 1024 of them); the pointers start at 0 and rise, a run
+ * rule spanning two cells; every cell of a rule of block b names an id below
+ * B[b]; run lengths are at least 2; C names ids below 256 + r; no rule and no
+ * sum of the strings' lengths reaches 2^61 bytes.  So every accepted file is
+ * the one lcg_slp_encode writes for the decoded grammar.
  * The result's statistics hold only its g and G (entries 6 and 7).
  * Synchronises the stream.  Errors: LCG_EINVAL, LCG_ENOMEM, LCG_EHIP.
  */

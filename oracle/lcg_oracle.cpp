@@ -623,7 +623,8 @@ uint32_t oracle_slp_bounds(const OracleSlp* s, uint32_t* out) {
 // 1 without rules; bits(x) = the binary digits of x, at least 1.
 //
 // The decoder accepts exactly what the encoder can write: the header's
-// counts, widths and size agree; the bounds rise from 256 to 256 + r; the
+// counts, widths (b_cell for the longest run included) and size agree;
+// padding bits are zero; the bounds rise from 256 to 256 + r; the
 // pointers start at 0 and rise, run rules spanning two cells; every cell of a
 // rule in block b names an id below bounds[b] (so rules refer only to smaller
 // ids); run lengths are at least 2; C names ids below 256 + r; and no rule
@@ -734,6 +735,13 @@ OracleSlp* oracle_slp_decode(const uint8_t* in, uint64_t n) {
                  wC = words_for(k, b_sym), wB = words_for(nb, 32);
   if ((8 + wR + wP + wM + wC + wB) * 8 != n) return fail("sections do not fill the size");
   const uint64_t oR = 8, oP = oR + wR, oM = oP + wP, oC = oM + wM, oB = oC + wC;
+  // padding: the bits after a section's last cell are zero
+  const uint64_t sec_cells[5][3] = {{oR, G, b_cell}, {oP, r, b_ptr}, {oM, r, 1}, {oC, k, b_sym},
+                                    {oB, nb, 32}};
+  for (const auto& sc : sec_cells) {
+    const uint64_t bits = sc[1] * sc[2];
+    if (bits % 64 && (w[sc[0] + bits / 64] >> (bits % 64)) != 0) return fail("nonzero padding");
+  }
   std::unique_ptr<OracleSlp> s(new OracleSlp());
   s->bounds.clear();
   for (uint64_t b = 0; b < nb; ++b) s->bounds.push_back((uint32_t)get_bits(w, oB, b, 32));
@@ -773,6 +781,10 @@ OracleSlp* oracle_slp_decode(const uint8_t* in, uint64_t n) {
     }
     s->off.push_back(s->rhs.size());
   }
+  uint64_t longest = 0;
+  for (uint32_t m : s->mult) longest = std::max<uint64_t>(longest, m >= 2 ? m : 0);
+  if (b_cell != std::max(b_sym, longest ? nbits(longest) : 1u))
+    return fail("widths do not match the longest run");
   for (uint64_t j = 0; j < k; ++j) {
     const uint64_t y = get_bits(w, oC, j, b_sym);
     if (y >= 256 + r) return fail("C names an id beyond the rules");

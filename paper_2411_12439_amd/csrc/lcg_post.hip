@@ -1676,6 +1676,7 @@ __global__ __launch_bounds__(kPB) void k_st_cells(const uint64_t* __restrict__ R
                                                   const uint32_t* __restrict__ bounds, uint32_t nb,
                                                   uint32_t* __restrict__ rhs,
                                                   uint32_t* __restrict__ mult,
+                                                  uint32_t* __restrict__ longest,
                                                   uint32_t* __restrict__ err) {
   __shared__ uint64_t s_cb[kStoreMaxBounds];
   __shared__ uint32_t s_bd[kStoreMaxBounds];
@@ -1693,12 +1694,14 @@ __global__ __launch_bounds__(kPB) void k_st_cells(const uint64_t* __restrict__ R
     for (uint32_t step = kStoreMaxBounds / 2; step; step >>= 1)
       if (blk + step < nb && s_cb[blk + step] <= i0) blk += step;
     bool bad = false;
+    uint32_t lg = 0;
     for (uint64_t i = i0; i < i1; ++i) {
       while (blk + 1 < nb && s_cb[blk + 1] <= i) ++blk;
       const uint64_t v = cell_get(R, i, b);
       if (nl < runs && lcell[nl] == i) {
         bad |= v < 2;
         mult[rr[nl]] = (uint32_t)v;
+        lg = max(lg, (uint32_t)v);
         ++nl;
       } else {
         bad |= v >= s_bd[blk];
@@ -1706,6 +1709,7 @@ __global__ __launch_bounds__(kPB) void k_st_cells(const uint64_t* __restrict__ R
       }
     }
     if (bad) atomicOr(err, 2u);
+    if (lg) atomicMax(longest, lg);
   }
 }
 
@@ -1832,6 +1836,21 @@ static lcg_slp* store_decode(const uint8_t* d_in, uint64_t n, hipStream_t s) {
     throw bad("widths do not match the counts");
   L.place();
   if (L.bytes != n) throw bad("sections do not fill the size");
+  {  // padding: the bits after a section's last cell are zero
+    const uint64_t sec[5][3] = {{L.oR, G, L.b_cell}, {L.oP, r, L.b_ptr}, {L.oM, r, 1},
+                                {L.oC, k, L.b_sym}, {L.oB, L.nb, 32}};
+    uint64_t last[5] = {0, 0, 0, 0, 0};
+    for (int i = 0; i < 5; ++i) {
+      const uint64_t bits = sec[i][1] * sec[i][2];
+      if (bits % 64)
+        HIP_CHECK(hipMemcpyAsync(&last[i], w + sec[i][0] + bits / 64, 8, hipMemcpyDeviceToHost, s));
+    }
+    sync(s);
+    for (int i = 0; i < 5; ++i) {
+      const uint64_t bits = sec[i][1] * sec[i][2];
+      if (bits % 64 && (last[i] >> (bits % 64)) != 0) throw bad("nonzero padding");
+    }
+  }
   std::vector<uint32_t> bnd(L.wB * 2);
   HIP_CHECK(hipMemcpyAsync(bnd.data(), w + L.oB, L.wB * 8, hipMemcpyDeviceToHost, s));
   sync(s);
@@ -1850,12 +1869,14 @@ static lcg_slp* store_decode(const uint8_t* d_in, uint64_t n, hipStream_t s) {
   out->mult.need(std::max<uint64_t>(r, 1), s);
   out->c.need(k, s);
   DBuf<uint64_t> S, fl, rb, lcell, cb;
-  DBuf<uint32_t> rr, err, bd;
+  DBuf<uint32_t> rr, err, bd, longest;
   S.need(r + 1, s);
   fl.need(std::max<uint64_t>(r, 1), s);
   rb.need(r + 1, s);
   err.need(1, s);
   zero(err.p, 4, s);
+  longest.need(1, s);
+  zero(longest.p, 4, s);
   if (r) {
     k_st_unpack_pm<<<pgrid(r), kPB, 0, s>>>(w + L.oP, w + L.oM, r, L.b_ptr, S.p, fl.p);
     PP_CHECK("st_unpack_pm");
@@ -1893,14 +1914,19 @@ static lcg_slp* store_decode(const uint8_t* d_in, uint64_t n, hipStream_t s) {
   if (G) {
     const uint64_t chunks = (G + kCellsPerThread - 1) / kCellsPerThread;
     k_st_cells<<<pgrid(chunks), kPB, 0, s>>>(w + L.oR, G, L.b_cell, lcell.p, rr.p, runs, cb.p, bd.p,
-                                             (uint32_t)L.nb, out->rhs.p, out->mult.p, err.p);
+                                             (uint32_t)L.nb, out->rhs.p, out->mult.p, longest.p,
+                                             err.p);
     PP_CHECK("st_cells");
   }
   k_st_unpack_c<<<pgrid(k), kPB, 0, s>>>(w + L.oC, k, L.b_sym, 256 + r, out->c.p, err.p);
   PP_CHECK("st_unpack_c");
+  uint32_t lg = 0;
+  HIP_CHECK(hipMemcpyAsync(&lg, longest.p, 4, hipMemcpyDeviceToHost, s));
   e = read_dev(err.p, s);
   if (e & 2) throw bad("a rule names an id of its own block or above, or a run is shorter than 2");
   if (e & 4) throw bad("C names an id beyond the rules");
+  if (L.b_cell != std::max(L.b_sym, runs ? store_bits(lg) : 1u))
+    throw bad("widths do not match the longest run");
   out->stats[6] = r;
   out->stats[7] = G;
   slp_lens(out.get(), s);

@@ -136,3 +136,25 @@ def bad_files(oracle_mod, seed):
     ch_rules, ch_c, ch_b = doubling_chain(61)
     out.append(("lengths", write(ch_rules, ch_c, ch_b), "2^61"))
     return out
+
+
+def corrupted(good, seed, count):
+    """`count` seeded corruptions of a good file: one to three bit flips (header
+    words included), a truncation, or a 64-bit word of random bytes."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        b = bytearray(good)
+        kind = int(rng.integers(0, 4))
+        if kind < 2:
+            for _ in range(int(rng.integers(1, 4))):
+                bit = int(rng.integers(0, 8 * len(b)))
+                b[bit // 8] ^= 1 << (bit % 8)
+        elif kind == 2:
+            b = b[:8 * int(rng.integers(0, len(b) // 8))]
+        else:
+            w = int(rng.integers(0, len(b) // 8))
+            b[8 * w:8 * w + 8] = rng.integers(0, 256, 8).astype(np.uint8).tobytes()
+        out.append(bytes(b))
+    return out

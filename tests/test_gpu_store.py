@@ -113,3 +113,34 @@ def test_small_buffer_and_query(L):
     small = full[:64].clone()
     rc = L.lib().lcg_slp_encode(slp.h, ctypes.c_void_p(small.data_ptr()), 64, ctypes.byref(n), None)
     assert rc == -1 and n.value == full.numel()
+
+
+def test_corrupted_files_same_decision_as_oracle(L):
+    """Seeded random corruptions of a good file: the GPU decoder refuses exactly
+    the files the oracle refuses, and decodes the others to the oracle's arrays
+    (nothing is expanded: an accepted file may derive a huge text)."""
+    from oracle import oracle as O
+    rng = np.random.default_rng(41)
+    base = D.BASES[rng.integers(0, 4, 400)]
+    strings = [base.tobytes(), base[:200].tobytes() + b"T" * 40, b"A", b"GG" * 30]
+    good = O.build_strings(strings, SEED).stored()
+    accepted = 0
+    for i, data in enumerate(SF.corrupted(good, 78, 300)):
+        print("corrupted file", i, flush=True)
+        try:
+            want = O.decode_stored(data)
+        except ValueError:
+            want = None
+        if len(data) == 0:
+            assert want is None
+            continue
+        if want is None:
+            with pytest.raises(L.LcgError) as e:
+                L.decode(_dev(data))
+            assert e.value.name == "LCG_EINVAL"
+            continue
+        accepted += 1
+        e = L.decode(_dev(data)).export()
+        for key in ("off", "rhs", "mult", "c"):
+            assert np.array_equal(e[key], want[key]), (i, key)
+    assert accepted > 0

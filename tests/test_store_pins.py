@@ -131,3 +131,18 @@ def test_grammar_without_rules(oracle_mod):
     assert f["c"] == [65, 67, 65] and f["bounds"] == [256]
     assert len(data) == 64 + 8 + 8
     assert oracle_mod.decode_stored(data, expand=True)["expansions"] == [b"A", b"C", b"A"]
+
+
+def test_decoder_on_corrupted_files(oracle_mod):
+    """Random corruptions: every file is refused with ValueError or decodes to a
+    grammar whose file is the same bytes (the checks leave nothing in between)."""
+    g = oracle_mod.build_strings(_collections()[0], SEED)
+    accepted = 0
+    for data in SF.corrupted(g.stored(), 77, 400):
+        try:
+            d = oracle_mod.decode_stored(data)
+        except ValueError:
+            continue
+        accepted += 1
+        assert SF.write(SF.rules_of(d), d["c"].tolist(), d["bounds"].tolist()) == data
+    assert 0 < accepted < 400
