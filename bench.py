@@ -19,6 +19,8 @@ Prints one JSON line (see the keys below).  Extra fields:
   roofline               the dominant kernel, its algorithmic bytes per launch
                          over its mean launch time (HIP events recorded by the
                          library on the stream its kernels run on)
+  hbm_copy_gbps          read + write GB/s of a 1 GiB device-to-device copy: the
+                         streaming ceiling measured on this GPU
   cpu_baseline           the CPU oracle (single-threaded) on a bounded sample
 """
 import argparse
@@ -115,6 +117,26 @@ def path_alg_bytes(st):
     return tot
 
 
+def copy_ceiling(nbytes=1 << 30, reps=5):
+    """Read + write GB/s of a device-to-device copy of 1 GiB on this GPU: the
+    streaming ceiling measured beside the published 8 TB/s."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    gbps = 2.0 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(gbps, 1)
+
+
 def cpu_baseline(text, off, seed, n_strings):
     from oracle import oracle as O
     k = min(n_strings, len(off) - 1)
@@ -133,8 +155,8 @@ def cpu_baseline(text, off, seed, n_strings):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="bacterial", choices=sorted(WORKLOADS))
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--plain-steps", type=int, default=1)
@@ -268,6 +290,7 @@ def main():
            "timed_wall_s": round(wall, 3),
            "tuned_options": tuned,
            "roofline": roofline}
+    out["hbm_copy_gbps"] = copy_ceiling()
 
     if not args.no_extra:
         extra_legs(args, out, text, off, t, o, n, k, seed)
