@@ -1,7 +1,8 @@
 // Random access into a level grammar: bytes [start, start + len) of string j
 // without expanding the rest of the string (the grammar's expansion lengths
-// locate every symbol, Sec. 2.2's exp(X) per rule).  One block answers one
-// query: starting from C[j] it keeps, level by level, only the symbols whose
+// locate every symbol, Sec. 2.2's exp(X) per rule).  One wave (one block for
+// queries longer than 256 bytes) answers one query: starting from C[j] it
+// keeps, level by level, only the symbols whose
 // expansion overlaps the range -- they cover disjoint pieces of at least one
 // byte each, so there are never more than len of them -- and the level-1
 // symbols finally write their bytes.
@@ -13,6 +14,108 @@ namespace lcg {
 namespace {
 
 constexpr int kXBlock = 256;
+
+// Queries of at most kXWaveMax bytes are answered by one wave each (k_extract
+// below skips them): a 256-entry frontier per wave keeps eight times more
+// queries in flight per CU than a block with the full frontier, and each
+// query is a chain of dependent reads, one level after another.
+constexpr uint32_t kXWaveMax = 256;
+constexpr int kXWaves = kXBlock / 64;
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(kXBlock) void k_extract_wave(
+    const LevelPtrs* __restrict__ lv_ptr, const uint64_t* const* __restrict__ explen,
+    const uint8_t* __restrict__ c_level, const uint32_t* __restrict__ c_sym, uint32_t k,
+    uint32_t nq, const uint32_t* __restrict__ qj, const uint64_t* __restrict__ qstart,
+    const uint32_t* __restrict__ qlen, const uint64_t* __restrict__ qout, uint8_t* __restrict__ out,
+    unsigned int* __restrict__ bad) {
+  __shared__ uint32_t s_sym[kXWaves][2][kXWaveMax];
+  __shared__ int64_t s_pos[kXWaves][2][kXWaveMax];
+  __shared__ uint32_t s_n[kXWaves][2];
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t(*sym)[kXWaveMax] = s_sym[wv];
+  int64_t(*pos)[kXWaveMax] = s_pos[wv];
+  uint32_t* cnt = s_n[wv];
+  for (uint32_t q = blockIdx.x * kXWaves + wv; q < nq; q += gridDim.x * kXWaves) {
+    const uint64_t len = qlen[q];
+    if (len < 1 || len > kXWaveMax) continue;  // the block kernel's
+    uint8_t* dst = out + qout[q];
+    int level = -1;
+    const uint32_t j = qj[q];
+    const uint64_t start = qstart[q];
+    uint32_t y = 0;
+    if (j < k) {
+      const uint32_t lv = c_level[j];
+      y = c_sym[j];
+      const uint64_t e = lv == 0 ? 1 : explen[lv - 1][y];
+      if (start <= e && len <= e - start) level = (int)lv;
+    }
+    if (level < 0) {
+      if (lane == 0) atomicAdd(bad, 1u);
+      continue;
+    }
+    if (level == 0) {
+      if (lane == 0) dst[0] = (uint8_t)y;
+      continue;
+    }
+    if (lane == 0) {
+      sym[0][0] = y;
+      pos[0][0] = -(int64_t)start;
+      cnt[0] = 1;
+    }
+    wave_sync();
+    int cur = 0;
+    while (level >= 2) {  // keep the children overlapping [0, len)
+      if (lane == 0) cnt[cur ^ 1] = 0;
+      wave_sync();
+      const LevelPtrs L = lv_ptr[level - 1];
+      const uint64_t* e_below = explen[level - 2];
+      const uint32_t* rhs = static_cast<const uint32_t*>(L.rhs);
+      const uint32_t n = cnt[cur];
+      for (uint32_t i = lane; i < n; i += 64) {
+        const uint32_t r = sym[cur][i];
+        int64_t p = pos[cur][i];
+        const uint64_t b = L.off[r + 1];
+        for (uint64_t t = L.off[r]; t < b && p < (int64_t)len; ++t) {
+          const uint32_t c = rhs[t];
+          const int64_t e = (int64_t)e_below[c];
+          if (p + e > 0) {
+            const uint32_t slot = atomicAdd(&cnt[cur ^ 1], 1u);
+            if (slot < kXWaveMax) {  // always: the overlapping symbols are at most len
+              sym[cur ^ 1][slot] = c;
+              pos[cur ^ 1][slot] = p;
+            }
+          }
+          p += e;
+        }
+      }
+      wave_sync();
+      cur ^= 1;
+      --level;
+      if (lane == 0 && cnt[cur] > kXWaveMax) cnt[cur] = kXWaveMax;
+      wave_sync();
+    }
+    {  // level 1: the bytes
+      const LevelPtrs L = lv_ptr[0];
+      const uint8_t* rhs = static_cast<const uint8_t*>(L.rhs);
+      const uint32_t n = cnt[cur];
+      for (uint32_t i = lane; i < n; i += 64) {
+        const uint32_t r = sym[cur][i];
+        int64_t p = pos[cur][i];
+        const uint64_t a = L.off[r], b = L.off[r + 1];
+        uint64_t t = a + (p < 0 ? (uint64_t)(-p) : 0);
+        p = p < 0 ? 0 : p;
+        for (; t < b && p < (int64_t)len; ++t, ++p) dst[p] = rhs[t];
+      }
+    }
+    wave_sync();  // the frontier is rewritten by the wave's next query
+  }
+}
 
 __global__ __launch_bounds__(kXBlock) void k_extract(
     const LevelPtrs* __restrict__ lv_ptr, const uint64_t* const* __restrict__ explen,
@@ -26,6 +129,7 @@ __global__ __launch_bounds__(kXBlock) void k_extract(
   __shared__ int s_level;
   for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
     const uint64_t len = qlen[q];
+    if (len >= 1 && len <= kXWaveMax) continue;  // answered by k_extract_wave
     uint8_t* dst = out + qout[q];
     if (threadIdx.x == 0) {
       int level = -1;
@@ -295,6 +399,11 @@ lcg_status lcg_extract(lcg_grammar_t g, uint32_t nq, const uint32_t* d_j, const 
     DBuf<unsigned int> bad;
     bad.need(1, stream);
     launch_zero(bad.p, sizeof(unsigned int), stream);
+    const unsigned wgrid = std::min<uint32_t>((nq + kXWaves - 1) / kXWaves, 8192u);
+    k_extract_wave<<<wgrid, kXBlock, 0, stream>>>(g->level_ptrs.p, g->explen_ptrs.p, g->c_level.p,
+                                                 g->c_sym.p, g->k, nq, d_j, d_start, d_len,
+                                                 d_out_off, d_out, bad.p);
+    HIP_CHECK(hipGetLastError());
     const unsigned grid = std::min<uint32_t>(nq, 4096u);
     k_extract<<<grid, kXBlock, 0, stream>>>(g->level_ptrs.p, g->explen_ptrs.p, g->c_level.p,
                                            g->c_sym.p, g->k, nq, d_j, d_start, d_len, d_out_off,
