@@ -22,6 +22,8 @@ Prints one JSON line (see the keys below).  Extra fields:
   hbm_copy_gbps          read + write GB/s of a 1 GiB device-to-device copy: the
                          streaming ceiling measured on this GPU
   cpu_baseline           the CPU oracle (single-threaded) on a bounded sample
+  cpu_baseline_parallel  the same oracle on up to 16 host cores: disjoint runs of
+                         strings built concurrently, then merged (MergeGrams)
 """
 import argparse
 import json
@@ -150,6 +152,44 @@ def cpu_baseline(text, off, seed, n_strings):
     return {"value": nb / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": "first %d of %d strings (%d bytes), one thread, build of the sample; "
                       "%.1f s" % (k, len(off) - 1, nb, dt)}
+
+
+def cpu_baseline_parallel(text, off, seed, per_thread):
+    """The unchanged oracle on all host cores (at most 16, the GPU's share of the
+    host): disjoint runs of strings built by concurrent threads (the oracle is a
+    C library; ctypes releases the GIL during its calls), then merged pairwise
+    in string order with the oracle's MergeGrams, the pairs of each step
+    concurrently.  Valid by stability: the merge gives the grammar of the whole
+    sample."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import oracle as O
+    P = max(1, min(16, os.cpu_count() or 1))
+    k = min(P * per_thread, len(off) - 1)
+    P = min(P, k)
+    cuts = [k * i // P for i in range(P + 1)]
+
+    def part(i):
+        a, b = cuts[i], cuts[i + 1]
+        o = off[a:b + 1] - off[a]
+        return O.build(text[off[a]:off[b]], o, seed)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(P) as ex:
+        parts = list(ex.map(part, range(P)))
+        t1 = time.perf_counter()
+        # merge-sort fashion (App. A.3): pairs (i, i + step) merged concurrently,
+        # the left grammar absorbing the right one, so string order is kept
+        step = 1
+        while step < P:
+            list(ex.map(lambda i: parts[i].merge(parts[i + step]),
+                        range(0, P - step, 2 * step)))
+            step *= 2
+    dt = time.perf_counter() - t0
+    nb = int(off[k])
+    return {"value": nb / dt / 1e9, "unit": "GB/s", "cores": P, "kind": "oracle",
+            "sample": "first %d of %d strings (%d bytes) in %d runs built by %d threads, "
+                      "then merged pairwise in order; %.1f s (builds %.1f s, merges %.1f s)" % (
+                          k, len(off) - 1, nb, P, P, dt, t1 - t0, dt - (t1 - t0))}
 
 
 def main():
@@ -597,6 +637,7 @@ def plain_and_rest(args, out, text, off, t, o, n, seed, value):
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(text, off, seed, args.cpu_strings)
+        out["cpu_baseline_parallel"] = cpu_baseline_parallel(text, off, seed, args.cpu_strings)
     print(json.dumps(out), flush=True)
 
 
