@@ -386,8 +386,29 @@ lcg_status lcg_slp_encode(lcg_slp_t p, uint8_t* d_out, uint64_t cap, uint64_t* b
  */
 lcg_status lcg_slp_decode(const uint8_t* d_in, uint64_t bytes, hipStream_t stream, lcg_slp_t* out);
 
-/* Return the library's cached free device blocks to the driver. */
+/* Return the library's cached free device blocks to where they came from
+ * (hipFree, or the allocator that made them). */
 void lcg_release_pool(void);
+
+/*
+ * Device memory from the caller's allocator, e.g. PyTorch's caching
+ * allocator, so that the library and the caller share one pool.  alloc
+ * returns `bytes` of device memory, 256-byte aligned, or NULL when it has
+ * none; free takes back a block alloc returned.  Both may be called from any
+ * library call made after this one, on the calling thread, and must not call
+ * into the library.  Process-wide: every block the library allocates from
+ * now on comes from *a (a is copied; NULL returns to hipMalloc).  Blocks
+ * already held keep their origin and go back to it when released by
+ * lcg_release_pool.  Call it while no other library call is running.
+ * Errors: LCG_EINVAL (alloc or free missing); an allocation failure in a
+ * later call gives LCG_ENOMEM.
+ */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* block, void* ctx);
+  void* ctx;
+} lcg_allocator;
+lcg_status lcg_set_allocator(const lcg_allocator* a);
 /* Thread-local description of the last failure. */
 const char* lcg_last_error(void);
 

@@ -66,48 +66,58 @@ struct HashFamily {
 
 // ------------------------------------------------------------------ device pool
 // Caching pool of device blocks: calls reuse blocks instead of paying for
-// hipMalloc/hipFree (which synchronise the device) every round.
+// hipMalloc/hipFree (which synchronise the device) every round.  New blocks
+// come from hipMalloc, or from the caller's allocator once lcg_set_allocator
+// installed one; every block remembers where it came from and goes back
+// there when the pool is trimmed.
 class Pool {
  public:
+  Pool() { sources_.push_back(lcg_allocator{nullptr, nullptr, nullptr}); }  // 0: hipMalloc
+  void set_allocator(const lcg_allocator* a) {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (!a) {
+      current_ = 0;
+      return;
+    }
+    sources_.push_back(*a);
+    current_ = sources_.size() - 1;
+  }
   void* alloc(size_t bytes) {
     size_t sz = round_size(bytes);
+    size_t src = 0;
     {
       std::lock_guard<std::mutex> lk(mu_);
       auto it = free_.lower_bound(sz);
       if (it != free_.end() && it->first <= sz + sz / 2) {
-        void* p = it->second;
-        size_t got = it->first;
+        const Block b = it->second;
         free_.erase(it);
-        used_[p] = got;
-        return p;
+        used_[b.p] = b;
+        return b.p;
       }
+      src = current_;
     }
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, sz);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
+    void* p = fresh(src, sz);
+    if (!p) {
       trim();
-      e = hipMalloc(&p, sz);
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        throw LcgError{LCG_ENOMEM, "hipMalloc of " + std::to_string(sz) + " bytes failed"};
-      }
+      p = fresh(src, sz);
+      if (!p)
+        throw LcgError{LCG_ENOMEM, "device allocation of " + std::to_string(sz) + " bytes failed"};
     }
     std::lock_guard<std::mutex> lk(mu_);
-    used_[p] = sz;
+    used_[p] = Block{p, sz, src};
     return p;
   }
   size_t size_of(void* p) {
     std::lock_guard<std::mutex> lk(mu_);
     auto it = used_.find(p);
-    return it == used_.end() ? 0 : it->second;
+    return it == used_.end() ? 0 : it->second.size;
   }
   void release(void* p) {
     if (!p) return;
     std::lock_guard<std::mutex> lk(mu_);
     auto it = used_.find(p);
     if (it == used_.end()) return;
-    free_.insert({it->second, p});
+    free_.insert({it->second.size, it->second});
     used_.erase(it);
   }
   // release once work already enqueued on `s` has finished (see flush)
@@ -133,13 +143,44 @@ class Pool {
     }
     for (void* p : done) release(p);
   }
+  // the idle blocks go back to where they came from
   void trim() {
     std::lock_guard<std::mutex> lk(mu_);
-    for (auto& kv : free_) (void)hipFree(kv.second);
+    for (auto& kv : free_) {
+      const Block& b = kv.second;
+      if (b.src == 0) (void)hipFree(b.p);
+      else sources_[b.src].free(b.p, sources_[b.src].ctx);
+    }
     free_.clear();
   }
 
  private:
+  struct Block {
+    void* p;
+    size_t size;
+    size_t src;  // index into sources_
+  };
+  void* fresh(size_t src, size_t sz) {
+    void* p = nullptr;
+    if (src == 0) {
+      if (hipMalloc(&p, sz) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+      return p;
+    }
+    lcg_allocator a;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      a = sources_[src];
+    }
+    p = a.alloc(sz, a.ctx);
+    if (p && (reinterpret_cast<uintptr_t>(p) & 255)) {  // the kernels rely on 256-byte blocks
+      a.free(p, a.ctx);
+      throw LcgError{LCG_EINVAL, "the installed allocator returned a block not 256-byte aligned"};
+    }
+    return p;
+  }
   static size_t round_size(size_t b) {
     if (b < 256) b = 256;
     if (b <= (1u << 20)) {
@@ -151,9 +192,11 @@ class Pool {
     return (b + g - 1) / g * g;
   }
   std::mutex mu_;
+  std::vector<lcg_allocator> sources_;  // never shrinks: blocks keep their index
+  size_t current_ = 0;
   std::vector<std::pair<void*, hipStream_t>> pending_;
-  std::multimap<size_t, void*> free_;
-  std::unordered_map<void*, size_t> used_;
+  std::multimap<size_t, Block> free_;
+  std::unordered_map<void*, Block> used_;
 };
 
 inline Pool& pool() {

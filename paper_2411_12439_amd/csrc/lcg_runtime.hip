@@ -1142,6 +1142,13 @@ void lcg_free(lcg_grammar_t g) { delete g; }
 
 void lcg_release_pool(void) { pool().trim(); }
 
+lcg_status lcg_set_allocator(const lcg_allocator* a) {
+  return guard([&] {
+    if (a && (!a->alloc || !a->free)) throw LcgError{LCG_EINVAL, "allocator without alloc or free"};
+    pool().set_allocator(a);
+  });
+}
+
 const char* lcg_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"

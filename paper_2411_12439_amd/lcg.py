@@ -31,7 +31,7 @@ EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_exp
            "lcg_stats_clear", "lcg_build_bytes", "lcg_free", "lcg_release_pool", "lcg_last_error",
            "lcg_postprocess", "lcg_slp_size", "lcg_slp_stats", "lcg_slp_device", "lcg_slp_copy",
            "lcg_slp_expand_strings", "lcg_slp_free", "lcg_extract", "lcg_build_file", "lcg_lce",
-           "lcg_slp_encode", "lcg_slp_decode", "lcg_symbol_lce")
+           "lcg_slp_encode", "lcg_slp_decode", "lcg_symbol_lce", "lcg_set_allocator")
 
 EXTRACT_MAX = 2048
 
@@ -39,6 +39,14 @@ PP_RL = 1
 PP_SIMP = 2
 SLP_STATS = 8
 SLP_STAT_NAMES = ("g_in", "G_in", "run_rules", "g_rl", "G_rl", "removed", "g_out", "G_out")
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p)]
 
 
 class LcgError(RuntimeError):
@@ -138,6 +146,8 @@ def lib():
     L.lcg_lce.restype = st
     L.lcg_symbol_lce.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, vp, ctypes.c_uint32, vp, vp]
     L.lcg_symbol_lce.restype = st
+    L.lcg_set_allocator.argtypes = [ctypes.POINTER(Allocator)]
+    L.lcg_set_allocator.restype = st
     L.lcg_extract.restype = st
     L.lcg_slp_free.argtypes = [vp]
     L.lcg_slp_free.restype = None
@@ -412,6 +422,32 @@ def decode(data, stream=None):
     _check(lib().lcg_slp_decode(ctypes.c_void_p(data.data_ptr()), data.numel(), _stream(stream),
                                 ctypes.byref(h)))
     return Slp(h.value)
+
+
+_torch_allocator = None  # kept alive: blocks it made may be returned at any later time
+
+
+def use_torch_allocator(enable=True):
+    """Take the library's device memory from PyTorch's caching allocator
+    (lcg_set_allocator), or from hipMalloc again with enable=False.
+    Process-wide."""
+    global _torch_allocator
+    if not enable:
+        _check(lib().lcg_set_allocator(None))
+        return
+    import torch
+    if _torch_allocator is None:
+        def _alloc(nbytes, ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes))
+            except RuntimeError:  # out of memory: the library reports LCG_ENOMEM
+                return None
+
+        def _free(block, ctx):
+            torch.cuda.caching_allocator_delete(block)
+
+        _torch_allocator = Allocator(_ALLOC_FN(_alloc), _FREE_FN(_free), None)
+    _check(lib().lcg_set_allocator(ctypes.byref(_torch_allocator)))
 
 
 def new(seed):

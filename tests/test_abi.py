@@ -66,6 +66,10 @@ def test_host_only_entry_points(lcgmod):
         assert L.lcg_slp_decode(ctypes.c_void_p(ptr), size, None, ctypes.byref(h)) == -1
         assert not h.value
     assert b"stored grammar" in L.lcg_last_error() or b"aligned" in L.lcg_last_error()
+    # an allocator needs both functions; NULL restores hipMalloc
+    half = lcgmod.Allocator(lcgmod._ALLOC_FN(lambda n, c: None), lcgmod._FREE_FN(), None)
+    assert L.lcg_set_allocator(ctypes.byref(half)) == -1
+    assert L.lcg_set_allocator(None) == 0
     g.free()
 
 
