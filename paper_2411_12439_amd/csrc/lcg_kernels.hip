@@ -1313,27 +1313,36 @@ void launch_newflags(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32
 
 // The same flags from the table side, for tables smaller than the phrase
 // array: every slot claimed in this pass marks its first occurrence.
-// newbits and wlen must be zero on entry.
-template <bool BYTES>
+// newbits must be zero on entry; k_word_counts then takes each word's counts.
 __global__ __launch_bounds__(256) void k_newflags_table(const Slot* __restrict__ table, uint64_t cap,
-                                                        uint64_t d, const uint64_t* __restrict__ key,
-                                                        const uint32_t* __restrict__ plen,
-                                                        unsigned long long* __restrict__ newbits,
-                                                        unsigned long long* __restrict__ wlen) {
+                                                        uint64_t d,
+                                                        unsigned long long* __restrict__ newbits) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap;
        i += (uint64_t)gridDim.x * blockDim.x) {
     const Slot sl = table[i];
     if (sl.w0 == kEmpty || sl.rank != kNone || sl.minocc >= d) continue;
     const uint64_t m = sl.minocc;
     atomicOr(&newbits[m >> 6], 1ULL << (m & 63));
-    atomicAdd(&wlen[m >> 6], (unsigned long long)key_len<BYTES>(key[m], plen, m));
   }
 }
 
+// Per flag word: its new rules and their right-hand-side lengths (the keys of
+// one word's phrases lie side by side).
+template <bool BYTES>
 __global__ void k_word_counts(const uint64_t* __restrict__ newbits, uint64_t W,
-                              uint64_t* __restrict__ wcnt) {
+                              const uint64_t* __restrict__ key, const uint32_t* __restrict__ plen,
+                              uint64_t* __restrict__ wcnt, uint64_t* __restrict__ wlen) {
   const uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (w < W) wcnt[w] = __builtin_popcountll(newbits[w]);
+  if (w >= W) return;
+  uint64_t bits = newbits[w];
+  wcnt[w] = __builtin_popcountll(bits);
+  uint64_t len = 0;
+  while (bits) {
+    const uint64_t m = w * 64 + (uint64_t)__builtin_ctzll(bits);
+    bits &= bits - 1;
+    len += key_len<BYTES>(key[m], plen, m);
+  }
+  wlen[w] = len;
 }
 
 void launch_newflags_table(bool bytes, const Slot* table, uint64_t cap, uint64_t d,
@@ -1342,19 +1351,14 @@ void launch_newflags_table(bool bytes, const Slot* table, uint64_t cap, uint64_t
   if (!d) return;
   const uint64_t W = (d + 63) / 64;
   launch_zero(newbits, W * 8, s);
-  launch_zero(wlen, W * 8, s);
   unsigned g = grid_for(cap, 256);
   if (g > 8192) g = 8192;
-  if (bytes)
-    k_newflags_table<true><<<g, 256, 0, s>>>(table, cap, d, key, plen,
-                                            reinterpret_cast<unsigned long long*>(newbits),
-                                            reinterpret_cast<unsigned long long*>(wlen));
-  else
-    k_newflags_table<false><<<g, 256, 0, s>>>(table, cap, d, key, plen,
-                                             reinterpret_cast<unsigned long long*>(newbits),
-                                             reinterpret_cast<unsigned long long*>(wlen));
+  k_newflags_table<<<g, 256, 0, s>>>(table, cap, d, reinterpret_cast<unsigned long long*>(newbits));
   LCG_LAUNCH_CHECK("newflags_table");
-  k_word_counts<<<grid_for(W, 256), 256, 0, s>>>(newbits, W, wcnt);
+  if (bytes)
+    k_word_counts<true><<<grid_for(W, 256), 256, 0, s>>>(newbits, W, key, plen, wcnt, wlen);
+  else
+    k_word_counts<false><<<grid_for(W, 256), 256, 0, s>>>(newbits, W, key, plen, wcnt, wlen);
   LCG_LAUNCH_CHECK("word_counts");
 }
 
