@@ -25,16 +25,25 @@ def L():
     lcg.release_pool()
 
 
+def _allocated():
+    """torch's allocated bytes once earlier tests' garbage is gone (the suite
+    shares one process)."""
+    import gc
+    import torch
+    gc.collect()
+    torch.cuda.synchronize()
+    return torch.cuda.memory_allocated()
+
+
 def test_torch_allocator_serves_the_library(L):
     import torch
     from oracle import oracle as O
     from paper_2411_12439_amd import canon as CN
     text, off = D.make_config("tiny")
     t, o = L.to_device(text, off)
-    torch.cuda.synchronize()
     L.release_pool()
     L.use_torch_allocator(True)
-    base = torch.cuda.memory_allocated()
+    base = _allocated()
     g = L.build(t, o, seed=SEED)
     held = torch.cuda.memory_allocated() - base
     assert held > 0  # the grammar's levels and the pool's blocks are torch's
@@ -44,11 +53,11 @@ def test_torch_allocator_serves_the_library(L):
     del out, offs  # torch tensors of the binding, not library blocks
     g.free()
     L.release_pool()
-    torch.cuda.synchronize()
-    assert torch.cuda.memory_allocated() == base  # every block went back to torch
+    assert _allocated() <= base  # every block went back to torch
     # back to hipMalloc: torch sees nothing of the next build
     L.use_torch_allocator(False)
+    base2 = _allocated()
     g2 = L.build(t, o, seed=SEED)
-    assert torch.cuda.memory_allocated() == base
+    assert _allocated() <= base2
     assert CN.canon(g2.export()) == CN.canon(O.build(text, off, SEED).export())
     g2.free()
