@@ -217,9 +217,9 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE against a copy of known size) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: there is no multi-GPU path "
               "(the collection would be split across GPUs by whole strings and the per-GPU "
-              "grammars merged; see DESIGN.md).", file=sys.stderr)
+              "grammars merged).", file=sys.stderr)
         sys.exit(2)
 
     import torch
