@@ -460,6 +460,26 @@ def extra_legs(args, out, text, off, t, o, n, k, seed):
                       "ms": round(x_s * 1e3, 3), "queries_per_s": round(nq / x_s),
                       "gbps": round(nq * qlen / x_s / 1e9, 3)}
     print("[bench] extract: %.2f ms for %d queries" % (x_s * 1e3, nq), file=sys.stderr, flush=True)
+    # the same queries on the post-processed grammar (RL + Simp)
+    pg = g.postprocess()
+    xo, _ = pg.extract(dj, ds, dl)  # the first call also computes the expansion lengths
+    if not np.array_equal(xo.cpu().numpy().reshape(nq, qlen), want):
+        raise SystemExit("lcg_slp_extract does not give back the input")
+    xts = []
+    for i in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pg.extract(dj, ds, dl)
+        torch.cuda.synchronize()
+        xts.append(time.perf_counter() - t0)
+    pg.free()
+    x_s = float(np.mean(xts))
+    out["slp_extract"] = {"what": "lcg_slp_extract: the same 100,000 substrings from the RL + Simp "
+                                  "grammar, every answer checked",
+                          "ms": round(x_s * 1e3, 3), "queries_per_s": round(nq / x_s),
+                          "gbps": round(nq * qlen / x_s / 1e9, 3)}
+    print("[bench] slp extract: %.2f ms for %d queries" % (x_s * 1e3, nq), file=sys.stderr,
+          flush=True)
 
     # longest common extensions (the match-extension query of App. B): anchors
     # are 24-mers of one copy of a base genome found in another copy of the

@@ -338,6 +338,21 @@ lcg_status lcg_slp_copy(lcg_slp_t p, uint64_t* h_off, uint32_t* h_rhs, uint32_t*
 lcg_status lcg_slp_expand_strings(lcg_slp_t p, uint32_t j0, uint32_t j1, uint8_t* d_out,
                                   uint64_t cap, uint64_t* d_offsets, uint64_t* total,
                                   hipStream_t stream);
+/*
+ * Random access into the post-processed grammar, with the contract of
+ * lcg_extract: query q writes bytes [start[q], start[q] + len[q]) of string
+ * j[q] (1 <= len <= LCG_EXTRACT_MAX) to d_out + out_off[q].  One block per
+ * query replaces, step by step from C[j], each rule by its children that
+ * overlap the range (whole repetitions of a run rule skipped at once, the
+ * first overlapping child found by binary search over the rule's prefix sums
+ * of expansion lengths).  The first call computes and keeps the expansion
+ * lengths, like lcg_slp_expand_strings.  Synchronises the stream.  Errors:
+ * LCG_EINVAL (NULL arrays; queries out of range: their output is not
+ * written, the others are).
+ */
+lcg_status lcg_slp_extract(lcg_slp_t p, uint32_t nq, const uint32_t* d_j, const uint64_t* d_start,
+                           const uint32_t* d_len, const uint64_t* d_out_off, uint8_t* d_out,
+                           hipStream_t stream);
 void lcg_slp_free(lcg_slp_t p);
 
 /* ---- the stored file of a post-processed grammar ----------------------------

@@ -1463,6 +1463,123 @@ static void slp_expand_core(lcg_slp* p, uint32_t j0, uint32_t j1, uint8_t* d_out
   sync(s);
 }
 
+// ---------------------------------------------------------------- random access
+// Bytes [start, start + len) of string j of a post-processed grammar, one
+// block per query.  The frontier holds (symbol, offset of its expansion
+// relative to the query start); each step replaces every rule by its
+// children that overlap [0, len): whole repetitions of a run rule are
+// skipped arithmetically, and the first overlapping child of a right-hand
+// side is found by binary search over the per-position prefix sums S (a
+// Simp root rule has ~10^5 children).  Terminals are written as they
+// appear.  The overlapping pieces are disjoint and non-empty, so a frontier
+// never holds more than len entries.
+namespace {
+
+__global__ __launch_bounds__(kPB) void k_slp_extract(
+    const uint64_t* __restrict__ off, const uint32_t* __restrict__ rhs,
+    const uint32_t* __restrict__ mult, const uint64_t* __restrict__ E,
+    const uint64_t* __restrict__ S, const uint32_t* __restrict__ c, uint32_t k, uint32_t nq,
+    const uint32_t* __restrict__ qj, const uint64_t* __restrict__ qstart,
+    const uint32_t* __restrict__ qlen, const uint64_t* __restrict__ qout, uint8_t* __restrict__ out,
+    unsigned int* __restrict__ bad) {
+  __shared__ uint32_t s_sym[2][LCG_EXTRACT_MAX];
+  __shared__ int64_t s_pos[2][LCG_EXTRACT_MAX];
+  __shared__ uint32_t s_n[2];
+  for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
+    const uint64_t len = qlen[q];
+    const uint32_t j = qj[q];
+    const uint64_t start = qstart[q];
+    bool ok = j < k && len >= 1 && len <= LCG_EXTRACT_MAX;
+    uint32_t y = 0;
+    if (ok) {
+      y = c[j];
+      const uint64_t e = y < 256 ? 1 : E[y - 256];
+      ok = start <= e && len <= e - start;
+    }
+    if (!ok) {  // uniform over the block
+      if (threadIdx.x == 0) atomicAdd(bad, 1u);
+      continue;
+    }
+    uint8_t* dst = out + qout[q];
+    if (threadIdx.x == 0) {
+      if (y < 256) dst[0] = (uint8_t)y;
+      s_sym[0][0] = y;
+      s_pos[0][0] = -(int64_t)start;
+      s_n[0] = y < 256 ? 0 : 1;
+    }
+    __syncthreads();
+    int cur = 0;
+    while (s_n[cur]) {
+      if (threadIdx.x == 0) s_n[cur ^ 1] = 0;
+      __syncthreads();
+      const uint32_t n = s_n[cur];
+      for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint32_t r = s_sym[cur][i] - 256;
+        const int64_t base = s_pos[cur][i];
+        const uint64_t a = off[r], b = off[r + 1];
+        const uint64_t m = mult[r];
+        const int64_t period = (int64_t)(E[r] / m);
+        const uint64_t sa = S[a];
+        uint64_t rep = base < 0 ? (uint64_t)(-base) / (uint64_t)period : 0;
+        for (; rep < m; ++rep) {
+          const int64_t rb = base + (int64_t)rep * period;
+          if (rb >= (int64_t)len) break;
+          // first child whose expansion ends after offset -rb (or the first child)
+          uint64_t t = a;
+          if (rb < 0) {
+            uint64_t lo = a, hi = b - 1;  // largest t with S[t] - S[a] <= -rb
+            while (lo < hi) {
+              const uint64_t mid = (lo + hi + 1) >> 1;
+              if (S[mid] - sa <= (uint64_t)(-rb)) lo = mid; else hi = mid - 1;
+            }
+            t = lo;
+          }
+          for (; t < b; ++t) {
+            const int64_t cb = rb + (int64_t)(S[t] - sa);
+            if (cb >= (int64_t)len) break;
+            const uint32_t ch = rhs[t];
+            if (ch < 256) {
+              if (cb >= 0) dst[cb] = (uint8_t)ch;
+            } else if (cb + (int64_t)E[ch - 256] > 0) {
+              const uint32_t slot = atomicAdd(&s_n[cur ^ 1], 1u);
+              if (slot < LCG_EXTRACT_MAX) {  // always: the overlapping pieces are at most len
+                s_sym[cur ^ 1][slot] = ch;
+                s_pos[cur ^ 1][slot] = cb;
+              }
+            }
+          }
+        }
+      }
+      __syncthreads();
+      cur ^= 1;
+      if (threadIdx.x == 0 && s_n[cur] > LCG_EXTRACT_MAX) s_n[cur] = LCG_EXTRACT_MAX;
+      __syncthreads();
+    }
+    __syncthreads();  // the frontier is rewritten by the next query
+  }
+}
+
+}  // namespace
+
+static void slp_extract_core(lcg_slp* p, uint32_t nq, const uint32_t* d_j, const uint64_t* d_start,
+                             const uint32_t* d_len, const uint64_t* d_out_off, uint8_t* d_out,
+                             hipStream_t s) {
+  slp_lens(p, s);
+  DBuf<unsigned int> bad;
+  bad.need(1, s);
+  zero(bad.p, 4, s);
+  k_slp_extract<<<std::min<uint32_t>(nq, 8192u), kPB, 0, s>>>(
+      p->off.p, p->rhs.p, p->mult.p, p->E.p, p->S.p, p->c.p, p->k, nq, d_j, d_start, d_len,
+      d_out_off, d_out, bad.p);
+  PP_CHECK("slp_extract");
+  const unsigned int nbad = read_dev(bad.p, s);
+  if (nbad)
+    throw LcgError{LCG_EINVAL, std::to_string(nbad) + " quer" + (nbad == 1 ? "y" : "ies") +
+                                   " out of range (string index, or start + len beyond the "
+                                   "string, or len not in 1.." +
+                                   std::to_string(LCG_EXTRACT_MAX) + ")"};
+}
+
 // ---------------------------------------------------------------- stored file
 // The file of a post-processed grammar, with the bit budget of App. A
 // (storing the final grammar): right-hand-side cells of ceil(log g) bits,
@@ -1992,6 +2109,18 @@ lcg_status lcg_slp_copy(lcg_slp_t p, uint64_t* h_off, uint32_t* h_rhs, uint32_t*
     if (h_rhs && p->q) HIP_CHECK(hipMemcpy(h_rhs, p->rhs.p, p->q * 4, hipMemcpyDeviceToHost));
     if (h_mult && p->g) HIP_CHECK(hipMemcpy(h_mult, p->mult.p, p->g * 4ull, hipMemcpyDeviceToHost));
     if (h_c && p->k) HIP_CHECK(hipMemcpy(h_c, p->c.p, p->k * 4ull, hipMemcpyDeviceToHost));
+  });
+}
+
+lcg_status lcg_slp_extract(lcg_slp_t p, uint32_t nq, const uint32_t* d_j, const uint64_t* d_start,
+                           const uint32_t* d_len, const uint64_t* d_out_off, uint8_t* d_out,
+                           hipStream_t stream) {
+  return guard([&] {
+    if (!p) throw LcgError{LCG_EINVAL, "slp is NULL"};
+    if (!nq) return;
+    if (!d_j || !d_start || !d_len || !d_out_off || !d_out)
+      throw LcgError{LCG_EINVAL, "NULL query or output array"};
+    slp_extract_core(p, nq, d_j, d_start, d_len, d_out_off, d_out, stream);
   });
 }
 

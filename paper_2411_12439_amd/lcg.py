@@ -31,7 +31,8 @@ EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_exp
            "lcg_stats_clear", "lcg_build_bytes", "lcg_free", "lcg_release_pool", "lcg_last_error",
            "lcg_postprocess", "lcg_slp_size", "lcg_slp_stats", "lcg_slp_device", "lcg_slp_copy",
            "lcg_slp_expand_strings", "lcg_slp_free", "lcg_extract", "lcg_build_file", "lcg_lce",
-           "lcg_slp_encode", "lcg_slp_decode", "lcg_symbol_lce", "lcg_set_allocator")
+           "lcg_slp_encode", "lcg_slp_decode", "lcg_symbol_lce", "lcg_set_allocator",
+           "lcg_slp_extract")
 
 EXTRACT_MAX = 2048
 
@@ -146,6 +147,8 @@ def lib():
     L.lcg_lce.restype = st
     L.lcg_symbol_lce.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, vp, ctypes.c_uint32, vp, vp]
     L.lcg_symbol_lce.restype = st
+    L.lcg_slp_extract.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, vp, vp, vp]
+    L.lcg_slp_extract.restype = st
     L.lcg_set_allocator.argtypes = [ctypes.POINTER(Allocator)]
     L.lcg_set_allocator.restype = st
     L.lcg_extract.restype = st
@@ -295,22 +298,7 @@ class Grammar:
         """Random access: bytes [start[q], start[q] + length[q]) of string j[q] for every
         query (device tensors or array-likes; 1 <= length <= EXTRACT_MAX).
         Returns (uint8 device tensor of all answers, int64 offsets tensor)."""
-        import torch
-        dev = "cuda"
-        j = torch.as_tensor(j, dtype=torch.int32, device=dev).contiguous()
-        start = torch.as_tensor(start, dtype=torch.int64, device=dev).contiguous()
-        length = torch.as_tensor(length, dtype=torch.int32, device=dev).contiguous()
-        nq = j.numel()
-        offs = torch.zeros(nq + 1, dtype=torch.int64, device=dev)
-        if nq:
-            offs[1:] = torch.cumsum(length.to(torch.int64), 0)
-        out = torch.empty(max(int(offs[-1].item()) if nq else 0, 1), dtype=torch.uint8, device=dev)
-        _check(lib().lcg_extract(self.h, nq, ctypes.c_void_p(j.data_ptr()),
-                                 ctypes.c_void_p(start.data_ptr()),
-                                 ctypes.c_void_p(length.data_ptr()),
-                                 ctypes.c_void_p(offs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                                 _stream(stream)))
-        return out[:int(offs[-1].item()) if nq else 0], offs
+        return _extract(lib().lcg_extract, self.h, j, start, length, stream)
 
     def lce(self, j1, p1, j2, p2, backward=False, stream=None):
         """Longest common extension of position pairs (lcg_lce): int64 device tensor."""
@@ -405,6 +393,11 @@ class Slp:
                                             ctypes.byref(total), _stream(stream)))
         return out[:total.value], offs
 
+    def extract(self, j, start, length, stream=None):
+        """Random access into the post-processed grammar (lcg_slp_extract), with
+        the arguments and result of Grammar.extract."""
+        return _extract(lib().lcg_slp_extract, self.h, j, start, length, stream)
+
     def encode(self, stream=None):
         """The stored file (layout in include/lcg.h) as a uint8 device tensor."""
         import torch
@@ -422,6 +415,26 @@ def decode(data, stream=None):
     _check(lib().lcg_slp_decode(ctypes.c_void_p(data.data_ptr()), data.numel(), _stream(stream),
                                 ctypes.byref(h)))
     return Slp(h.value)
+
+
+def _extract(fn, h, j, start, length, stream):
+    """Marshal a batch of substring queries for lcg_extract / lcg_slp_extract:
+    answers laid out one after the other (offsets = prefix sums of the lengths)."""
+    import torch
+    dev = "cuda"
+    j = torch.as_tensor(j, dtype=torch.int32, device=dev).contiguous()
+    start = torch.as_tensor(start, dtype=torch.int64, device=dev).contiguous()
+    length = torch.as_tensor(length, dtype=torch.int32, device=dev).contiguous()
+    nq = j.numel()
+    offs = torch.zeros(nq + 1, dtype=torch.int64, device=dev)
+    if nq:
+        offs[1:] = torch.cumsum(length.to(torch.int64), 0)
+    total = int(offs[-1].item()) if nq else 0
+    out = torch.empty(max(total, 1), dtype=torch.uint8, device=dev)
+    _check(fn(h, nq, ctypes.c_void_p(j.data_ptr()), ctypes.c_void_p(start.data_ptr()),
+              ctypes.c_void_p(length.data_ptr()), ctypes.c_void_p(offs.data_ptr()),
+              ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out[:total], offs
 
 
 _torch_allocator = None  # kept alive: blocks it made may be returned at any later time

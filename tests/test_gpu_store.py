@@ -6,7 +6,8 @@ oracle's byte for byte, for every combination of RL and Simp.  Decoding the
 oracle's file on the GPU gives the oracle's decoded arrays, decompresses to
 the input and encodes back to the same bytes.  Every malformed file the
 oracle refuses is refused by the GPU decoder too, before anything is
-expanded.
+expanded.  Random access into the post-processed grammar (lcg_slp_extract)
+gives the input's substrings, before and after the stored file.
 """
 import numpy as np
 import pytest
@@ -144,3 +145,60 @@ def test_corrupted_files_same_decision_as_oracle(L):
         for key in ("off", "rhs", "mult", "c"):
             assert np.array_equal(e[key], want[key]), (i, key)
     assert accepted > 0
+
+
+# ------------------------------------------ random access to the post-processed grammar
+def _slp_queries(rng, off, nq, maxlen):
+    lens_s = np.diff(off.astype(np.int64))
+    k = len(lens_s)
+    j = rng.integers(0, k, nq)
+    ln = np.minimum(rng.integers(1, maxlen + 1, nq), lens_s[j])
+    st = (rng.random(nq) * (lens_s[j] - ln + 1)).astype(np.int64)
+    # string starts and ends, single bytes
+    j = np.concatenate([j, np.arange(k), np.arange(k), np.arange(k)])
+    st = np.concatenate([st, np.zeros(k, np.int64), lens_s - np.minimum(lens_s, maxlen), lens_s - 1])
+    ln = np.concatenate([ln, np.minimum(lens_s, maxlen), np.minimum(lens_s, maxlen),
+                         np.ones(k, np.int64)])
+    return j, st, ln
+
+
+def _check_slp_extract(slp, text, off, q):
+    out, offs = slp.extract(*q)
+    got = out.cpu().numpy()
+    o = offs.cpu().numpy()
+    base = off.astype(np.int64)
+    j, st, ln = q
+    for i in range(len(j)):
+        a = int(base[j[i]] + st[i])
+        assert np.array_equal(got[o[i]:o[i + 1]], text[a:a + int(ln[i])]), (i, int(j[i]), int(st[i]))
+
+
+@pytest.mark.parametrize("which", sorted(FLAGS))
+@pytest.mark.parametrize("config,scale", [("tiny", 1.0), ("bacterial", 0.01), ("repeats", 0.0005)])
+def test_slp_extract(L, config, scale, which):
+    """Substrings of the post-processed grammar (run rules included) equal the
+    input's, also after the grammar went through its stored file."""
+    rl, simp = FLAGS[which]
+    text, off = D.make_config(config, scale=scale)
+    t, o = L.to_device(text, off)
+    slp = L.build(t, o, seed=SEED).postprocess(rl=rl, simp=simp)
+    rng = np.random.default_rng(51)
+    q = _slp_queries(rng, off, 1500, L.EXTRACT_MAX)
+    _check_slp_extract(slp, text, off, q)
+    _check_slp_extract(L.decode(slp.encode()), text, off, q)
+
+
+def test_slp_extract_edges_and_errors(L):
+    from oracle import oracle as O
+    rng = np.random.default_rng(52)
+    dna = D.BASES[rng.integers(0, 4, 4000)].tobytes()
+    strings = [b"A", b"T" * 7000, b"AC" * 3000, dna, b"G" * 3 + dna[:500], b"C"]
+    text, off = O.pack(strings)
+    t, o = L.to_device(text, off)
+    slp = L.build(t, o, seed=SEED).postprocess()
+    _check_slp_extract(slp, text, off, _slp_queries(rng, off, 800, L.EXTRACT_MAX))
+    n0 = int(off[1] - off[0])
+    for j, st, ln in ((0, n0, 1), (1, 0, L.EXTRACT_MAX + 1), (len(strings), 0, 1), (2, 0, 0)):
+        with pytest.raises(L.LcgError) as e:
+            slp.extract([j], [st], [ln])
+        assert e.value.name == "LCG_EINVAL"
