@@ -341,8 +341,9 @@ lcg_status lcg_slp_expand_strings(lcg_slp_t p, uint32_t j0, uint32_t j1, uint8_t
 /*
  * Random access into the post-processed grammar, with the contract of
  * lcg_extract: query q writes bytes [start[q], start[q] + len[q]) of string
- * j[q] (1 <= len <= LCG_EXTRACT_MAX) to d_out + out_off[q].  One block per
- * query replaces, step by step from C[j], each rule by its children that
+ * j[q] (1 <= len <= LCG_EXTRACT_MAX) to d_out + out_off[q].  One wave per
+ * query (one block above 256 bytes) replaces, step by step from C[j], each
+ * rule by its children that
  * overlap the range (whole repetitions of a run rule skipped at once, the
  * first overlapping child found by binary search over the rule's prefix sums
  * of expansion lengths).  The first call computes and keeps the expansion

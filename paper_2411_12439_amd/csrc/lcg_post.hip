@@ -1465,7 +1465,7 @@ static void slp_expand_core(lcg_slp* p, uint32_t j0, uint32_t j1, uint8_t* d_out
 
 // ---------------------------------------------------------------- random access
 // Bytes [start, start + len) of string j of a post-processed grammar, one
-// block per query.  The frontier holds (symbol, offset of its expansion
+// wave per query (one block for queries longer than 256 bytes).  The frontier holds (symbol, offset of its expansion
 // relative to the query start); each step replaces every rule by its
 // children that overlap [0, len): whole repetitions of a run rule are
 // skipped arithmetically, and the first overlapping child of a right-hand
@@ -1474,6 +1474,123 @@ static void slp_expand_core(lcg_slp* p, uint32_t j0, uint32_t j1, uint8_t* d_out
 // appear.  The overlapping pieces are disjoint and non-empty, so a frontier
 // never holds more than len entries.
 namespace {
+
+// The children of rule r (expansion starting at `base` relative to the query
+// start) that overlap [0, len): terminals are written to dst, rules pushed.
+template <typename Push>
+__device__ __forceinline__ void slp_overlap_children(uint32_t r, int64_t base, uint64_t len,
+                                                     const uint64_t* __restrict__ off,
+                                                     const uint32_t* __restrict__ rhs,
+                                                     const uint32_t* __restrict__ mult,
+                                                     const uint64_t* __restrict__ E,
+                                                     const uint64_t* __restrict__ S,
+                                                     uint8_t* __restrict__ dst, Push push) {
+  const uint64_t a = off[r], b = off[r + 1];
+  const uint64_t m = mult[r];
+  const int64_t period = (int64_t)(E[r] / m);
+  const uint64_t sa = S[a];
+  uint64_t rep = base < 0 ? (uint64_t)(-base) / (uint64_t)period : 0;
+  for (; rep < m; ++rep) {
+    const int64_t rb = base + (int64_t)rep * period;
+    if (rb >= (int64_t)len) break;
+    // the child holding offset -rb (or the first child)
+    uint64_t t = a;
+    if (rb < 0) {
+      uint64_t lo = a, hi = b - 1;  // largest t with S[t] - S[a] <= -rb
+      while (lo < hi) {
+        const uint64_t mid = (lo + hi + 1) >> 1;
+        if (S[mid] - sa <= (uint64_t)(-rb)) lo = mid; else hi = mid - 1;
+      }
+      t = lo;
+    }
+    for (; t < b; ++t) {
+      const int64_t cb = rb + (int64_t)(S[t] - sa);
+      if (cb >= (int64_t)len) break;
+      const uint32_t ch = rhs[t];
+      if (ch < 256) {
+        if (cb >= 0) dst[cb] = (uint8_t)ch;
+      } else if (cb + (int64_t)E[ch - 256] > 0) {
+        push(ch, cb);
+      }
+    }
+  }
+}
+
+// C[j]'s symbol if the query is valid, else -1
+__device__ __forceinline__ int64_t slp_query_root(const uint32_t* __restrict__ c, uint32_t k,
+                                                  const uint64_t* __restrict__ E, uint32_t j,
+                                                  uint64_t start, uint64_t len) {
+  if (j >= k || len < 1 || len > LCG_EXTRACT_MAX) return -1;
+  const uint32_t y = c[j];
+  const uint64_t e = y < 256 ? 1 : E[y - 256];
+  return start <= e && len <= e - start ? (int64_t)y : -1;
+}
+
+// Queries of at most kSXWave bytes, one wave each (the block kernel below skips them).
+constexpr uint32_t kSXWave = 256;
+constexpr int kSXWaves = kPB / 64;
+
+__device__ __forceinline__ void slp_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(kPB) void k_slp_extract_wave(
+    const uint64_t* __restrict__ off, const uint32_t* __restrict__ rhs,
+    const uint32_t* __restrict__ mult, const uint64_t* __restrict__ E,
+    const uint64_t* __restrict__ S, const uint32_t* __restrict__ c, uint32_t k, uint32_t nq,
+    const uint32_t* __restrict__ qj, const uint64_t* __restrict__ qstart,
+    const uint32_t* __restrict__ qlen, const uint64_t* __restrict__ qout, uint8_t* __restrict__ out,
+    unsigned int* __restrict__ bad) {
+  __shared__ uint32_t s_sym[kSXWaves][2][kSXWave];
+  __shared__ int64_t s_pos[kSXWaves][2][kSXWave];
+  __shared__ uint32_t s_n[kSXWaves][2];
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t(*sym)[kSXWave] = s_sym[wv];
+  int64_t(*pos)[kSXWave] = s_pos[wv];
+  uint32_t* cnt = s_n[wv];
+  for (uint32_t q = blockIdx.x * kSXWaves + wv; q < nq; q += gridDim.x * kSXWaves) {
+    const uint64_t len = qlen[q];
+    if (len < 1 || len > kSXWave) continue;  // the block kernel's
+    const int64_t root = slp_query_root(c, k, E, qj[q], qstart[q], len);
+    if (root < 0) {
+      if (lane == 0) atomicAdd(bad, 1u);
+      continue;
+    }
+    uint8_t* dst = out + qout[q];
+    if (root < 256) {
+      if (lane == 0) dst[0] = (uint8_t)root;
+      continue;
+    }
+    if (lane == 0) {
+      sym[0][0] = (uint32_t)root;
+      pos[0][0] = -(int64_t)qstart[q];
+      cnt[0] = 1;
+    }
+    slp_wave_sync();
+    int cur = 0;
+    while (cnt[cur]) {
+      if (lane == 0) cnt[cur ^ 1] = 0;
+      slp_wave_sync();
+      const uint32_t n = cnt[cur];
+      auto push = [&](uint32_t ch, int64_t cb) {
+        const uint32_t slot = atomicAdd(&cnt[cur ^ 1], 1u);
+        if (slot < kSXWave) {  // always: the overlapping pieces are at most len
+          sym[cur ^ 1][slot] = ch;
+          pos[cur ^ 1][slot] = cb;
+        }
+      };
+      for (uint32_t i = lane; i < n; i += 64)
+        slp_overlap_children(sym[cur][i] - 256, pos[cur][i], len, off, rhs, mult, E, S, dst, push);
+      slp_wave_sync();
+      cur ^= 1;
+      if (lane == 0 && cnt[cur] > kSXWave) cnt[cur] = kSXWave;
+      slp_wave_sync();
+    }
+    slp_wave_sync();  // the frontier is rewritten by the wave's next query
+  }
+}
 
 __global__ __launch_bounds__(kPB) void k_slp_extract(
     const uint64_t* __restrict__ off, const uint32_t* __restrict__ rhs,
@@ -1487,25 +1604,18 @@ __global__ __launch_bounds__(kPB) void k_slp_extract(
   __shared__ uint32_t s_n[2];
   for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
     const uint64_t len = qlen[q];
-    const uint32_t j = qj[q];
-    const uint64_t start = qstart[q];
-    bool ok = j < k && len >= 1 && len <= LCG_EXTRACT_MAX;
-    uint32_t y = 0;
-    if (ok) {
-      y = c[j];
-      const uint64_t e = y < 256 ? 1 : E[y - 256];
-      ok = start <= e && len <= e - start;
-    }
-    if (!ok) {  // uniform over the block
+    if (len >= 1 && len <= kSXWave) continue;  // answered by k_slp_extract_wave
+    const int64_t root = slp_query_root(c, k, E, qj[q], qstart[q], len);
+    if (root < 0) {  // uniform over the block
       if (threadIdx.x == 0) atomicAdd(bad, 1u);
       continue;
     }
     uint8_t* dst = out + qout[q];
     if (threadIdx.x == 0) {
-      if (y < 256) dst[0] = (uint8_t)y;
-      s_sym[0][0] = y;
-      s_pos[0][0] = -(int64_t)start;
-      s_n[0] = y < 256 ? 0 : 1;
+      if (root < 256) dst[0] = (uint8_t)root;
+      s_sym[0][0] = (uint32_t)root;
+      s_pos[0][0] = -(int64_t)qstart[q];
+      s_n[0] = root < 256 ? 0 : 1;
     }
     __syncthreads();
     int cur = 0;
@@ -1513,43 +1623,16 @@ __global__ __launch_bounds__(kPB) void k_slp_extract(
       if (threadIdx.x == 0) s_n[cur ^ 1] = 0;
       __syncthreads();
       const uint32_t n = s_n[cur];
-      for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const uint32_t r = s_sym[cur][i] - 256;
-        const int64_t base = s_pos[cur][i];
-        const uint64_t a = off[r], b = off[r + 1];
-        const uint64_t m = mult[r];
-        const int64_t period = (int64_t)(E[r] / m);
-        const uint64_t sa = S[a];
-        uint64_t rep = base < 0 ? (uint64_t)(-base) / (uint64_t)period : 0;
-        for (; rep < m; ++rep) {
-          const int64_t rb = base + (int64_t)rep * period;
-          if (rb >= (int64_t)len) break;
-          // first child whose expansion ends after offset -rb (or the first child)
-          uint64_t t = a;
-          if (rb < 0) {
-            uint64_t lo = a, hi = b - 1;  // largest t with S[t] - S[a] <= -rb
-            while (lo < hi) {
-              const uint64_t mid = (lo + hi + 1) >> 1;
-              if (S[mid] - sa <= (uint64_t)(-rb)) lo = mid; else hi = mid - 1;
-            }
-            t = lo;
-          }
-          for (; t < b; ++t) {
-            const int64_t cb = rb + (int64_t)(S[t] - sa);
-            if (cb >= (int64_t)len) break;
-            const uint32_t ch = rhs[t];
-            if (ch < 256) {
-              if (cb >= 0) dst[cb] = (uint8_t)ch;
-            } else if (cb + (int64_t)E[ch - 256] > 0) {
-              const uint32_t slot = atomicAdd(&s_n[cur ^ 1], 1u);
-              if (slot < LCG_EXTRACT_MAX) {  // always: the overlapping pieces are at most len
-                s_sym[cur ^ 1][slot] = ch;
-                s_pos[cur ^ 1][slot] = cb;
-              }
-            }
-          }
+      auto push = [&](uint32_t ch, int64_t cb) {
+        const uint32_t slot = atomicAdd(&s_n[cur ^ 1], 1u);
+        if (slot < LCG_EXTRACT_MAX) {  // always: the overlapping pieces are at most len
+          s_sym[cur ^ 1][slot] = ch;
+          s_pos[cur ^ 1][slot] = cb;
         }
-      }
+      };
+      for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
+        slp_overlap_children(s_sym[cur][i] - 256, s_pos[cur][i], len, off, rhs, mult, E, S, dst,
+                             push);
       __syncthreads();
       cur ^= 1;
       if (threadIdx.x == 0 && s_n[cur] > LCG_EXTRACT_MAX) s_n[cur] = LCG_EXTRACT_MAX;
@@ -1568,6 +1651,10 @@ static void slp_extract_core(lcg_slp* p, uint32_t nq, const uint32_t* d_j, const
   DBuf<unsigned int> bad;
   bad.need(1, s);
   zero(bad.p, 4, s);
+  k_slp_extract_wave<<<std::min<uint32_t>((nq + kSXWaves - 1) / kSXWaves, 8192u), kPB, 0, s>>>(
+      p->off.p, p->rhs.p, p->mult.p, p->E.p, p->S.p, p->c.p, p->k, nq, d_j, d_start, d_len,
+      d_out_off, d_out, bad.p);
+  PP_CHECK("slp_extract_wave");
   k_slp_extract<<<std::min<uint32_t>(nq, 8192u), kPB, 0, s>>>(
       p->off.p, p->rhs.p, p->mult.p, p->E.p, p->S.p, p->c.p, p->k, nq, d_j, d_start, d_len,
       d_out_off, d_out, bad.p);
