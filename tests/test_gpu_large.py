@@ -8,7 +8,8 @@ halving holds in every round and every string ends; sampled strings'
 sub-grammars equal the oracle's grammar of each string alone (stability,
 Def. 1); random substrings and longest common extensions match the input;
 and for the repeat-heavy collection the RL + Simp grammar decompresses to the
-input, also through its stored file, and keeps Simp's size identity.
+input, also through its stored file, gives random substrings of the input
+from the decoded grammar, and keeps Simp's size identity.
 """
 import numpy as np
 import pytest
@@ -94,6 +95,19 @@ def test_full_repeats(L):
     out, _ = dec.expand_strings()
     assert torch.equal(out, t)
     del out
+    # random substrings of the decoded grammar (run rules of long homopolymers)
+    rng = np.random.default_rng(7)
+    lens = np.diff(off.astype(np.int64))
+    jq = rng.integers(0, len(lens), 2000)
+    ln = rng.integers(1, L.EXTRACT_MAX + 1, 2000)
+    sq = (rng.random(2000) * (lens[jq] - ln + 1)).astype(np.int64)
+    xo, xoff = dec.extract(jq, sq, ln)
+    xo = xo.cpu().numpy()
+    xoff = xoff.cpu().numpy()
+    base = off.astype(np.int64)
+    for q in range(2000):
+        a = int(base[jq[q]] + sq[q])
+        assert np.array_equal(xo[xoff[q]:xoff[q + 1]], text[a:a + int(ln[q])]), q
     dec.free()
     # longest common extensions between the copies, against the bytes
     rng = np.random.default_rng(6)
