@@ -398,6 +398,12 @@ class Slp:
         the arguments and result of Grammar.extract."""
         return _extract(lib().lcg_slp_extract, self.h, j, start, length, stream)
 
+    def save(self, path, stream=None):
+        """Write the stored file (encode) to `path`; returns its size in bytes."""
+        data = self.encode(stream).cpu().numpy()
+        data.tofile(path)
+        return int(data.size)
+
     def encode(self, stream=None):
         """The stored file (layout in include/lcg.h) as a uint8 device tensor."""
         import torch
@@ -407,6 +413,13 @@ class Slp:
         _check(lib().lcg_slp_encode(self.h, ctypes.c_void_p(out.data_ptr()), n.value,
                                     ctypes.byref(n), _stream(stream)))
         return out
+
+
+def load_slp(path, stream=None):
+    """The post-processed grammar stored in the file `path` (written by Slp.save)."""
+    import torch
+    data = np.fromfile(path, dtype=np.uint8)
+    return decode(torch.from_numpy(data).to("cuda"), stream)
 
 
 def decode(data, stream=None):

@@ -202,3 +202,19 @@ def test_slp_extract_edges_and_errors(L):
         with pytest.raises(L.LcgError) as e:
             slp.extract([j], [st], [ln])
         assert e.value.name == "LCG_EINVAL"
+
+
+def test_save_and_load_a_file(L, tmp_path):
+    """Slp.save writes the stored file to disk and load_slp reads it back: the
+    same bytes as the oracle's file, the same strings."""
+    from oracle import oracle as O
+    text, off = D.make_config("tiny", scale=0.5)
+    t, o = L.to_device(text, off)
+    slp = L.build(t, o, seed=SEED).postprocess()
+    path = str(tmp_path / "collection.lcgs")
+    n = slp.save(path)
+    raw = open(path, "rb").read()
+    assert len(raw) == n and raw == O.build(text, off, SEED).stored()
+    back = L.load_slp(path)
+    out, _ = back.expand_strings()
+    assert np.array_equal(out.cpu().numpy(), text)
