@@ -55,6 +55,8 @@ struct lcg_slp {
   lcg::DBuf<uint64_t> gnt;
   // per rule: E, with the top bit set for a leaf
   lcg::DBuf<uint64_t> el;
+  // every leaf's expansion (mult copies of its terminals), one after the other
+  lcg::DBuf<uint8_t> lbytes;
   bool lens_ready = false;
 };
 
@@ -803,7 +805,10 @@ __global__ void k_slp_gnt(const uint64_t* __restrict__ off, const uint32_t* __re
   }
 }
 
+// el[r]: a rule's expansion length E; for a leaf, the leaf bit, E (at most
+// kLeaf, the low 7 bits) and the offset of its bytes in lbytes (bits 7..62).
 constexpr uint64_t kLeafBit = 1ull << 63;
+constexpr uint64_t kLeafLenMask = 127;
 
 // An item's children [v0, v1) (v = rep * q + k): terminals and leaves are
 // written to out, item children go to slots o, o+1, ... of the next step.
@@ -814,7 +819,7 @@ __device__ __forceinline__ void slp_item_children(const RuleMeta& mt, uint64_t p
                                                   const uint32_t* __restrict__ rhs,
                                                   const uint64_t* __restrict__ S,
                                                   const uint64_t* __restrict__ el,
-                                                  const RuleMeta* __restrict__ meta,
+                                                  const uint8_t* __restrict__ lbytes,
                                                   uint32_t* __restrict__ nsym,
                                                   uint64_t* __restrict__ npos,
                                                   uint8_t* __restrict__ out) {
@@ -827,25 +832,49 @@ __device__ __forceinline__ void slp_item_children(const RuleMeta& mt, uint64_t p
       p += 1;
     } else {
       const uint64_t e = el[y - 256];
-      if (e & kLeafBit) {  // a leaf: its bytes, mult times
-        const RuleMeta lf = meta[y - 256];
-        uint64_t w = p;
-        for (uint32_t rr = 0; rr < lf.mult; ++rr)
-          for (uint32_t kk = 0; kk < lf.q; ++kk) out[w++] = (uint8_t)rhs[lf.a + kk];
+      if (e & kLeafBit) {  // a leaf: its stored bytes
+        const uint64_t len = e & kLeafLenMask;
+        const uint8_t* src = lbytes + ((e & ~kLeafBit) >> 7);
+        for (uint64_t x = 0; x < len; ++x) out[p + x] = src[x];
+        p += len;
       } else {
         nsym[o] = y;
         npos[o] = p;
         ++o;
+        p += e;
       }
-      p += e & ~kLeafBit;
     }
     if (++k == mt.q) k = 0, ++rep;
   }
 }
 
+// per rule: its bytes if it is a leaf, else 0
+__global__ void k_slp_leaflen(const uint64_t* __restrict__ E, const uint32_t* __restrict__ nt,
+                              uint32_t g, uint64_t* __restrict__ w) {
+  PP_LOOP(r, g) w[r] = (nt[r] == 0 && E[r] <= kLeaf) ? E[r] : 0;
+}
+
+// the leaves' expansions into lbytes at their offsets
+__global__ void k_slp_leafbytes(const uint64_t* __restrict__ off, const uint32_t* __restrict__ rhs,
+                                const uint32_t* __restrict__ mult, const uint64_t* __restrict__ w,
+                                const uint64_t* __restrict__ lboff, uint32_t g,
+                                uint8_t* __restrict__ lbytes) {
+  PP_LOOP(r, g) {
+    if (!w[r]) continue;
+    const uint64_t a = off[r], q = off[r + 1] - a;
+    uint8_t* dst = lbytes + lboff[r];
+    for (uint32_t rr = 0; rr < mult[r]; ++rr)
+      for (uint64_t kk = 0; kk < q; ++kk) *dst++ = (uint8_t)rhs[a + kk];
+  }
+}
+
 __global__ void k_slp_el(const uint64_t* __restrict__ E, const uint32_t* __restrict__ nt,
-                         uint32_t g, uint64_t* __restrict__ el) {
-  PP_LOOP(r, g) el[r] = E[r] | ((nt[r] == 0 && E[r] <= kLeaf) ? kLeafBit : 0);
+                         const uint64_t* __restrict__ lboff, uint32_t g,
+                         uint64_t* __restrict__ el) {
+  PP_LOOP(r, g) {
+    const bool leaf = nt[r] == 0 && E[r] <= kLeaf;
+    el[r] = leaf ? kLeafBit | (lboff[r] << 7) | E[r] : E[r];
+  }
 }
 
 // block-wide exclusive scan of v (s_w: kPB / 64 words); *tot gets the sum
@@ -882,7 +911,8 @@ __global__ __launch_bounds__(kPB) void k_slp_step(
     const uint32_t* __restrict__ vi, const uint64_t* __restrict__ v0s,
     const RuleMeta* __restrict__ meta, const uint64_t* __restrict__ gnt,
     const uint32_t* __restrict__ rhs, const uint64_t* __restrict__ S, const uint64_t* __restrict__ N,
-    const uint64_t* __restrict__ el, uint32_t* __restrict__ nsym, uint64_t* __restrict__ npos, unsigned long long* ncount,
+    const uint64_t* __restrict__ el, const uint8_t* __restrict__ lbytes,
+    uint32_t* __restrict__ nsym, uint64_t* __restrict__ npos, unsigned long long* ncount,
     unsigned long long* gcount, uint32_t* __restrict__ big, unsigned long long* nbig,
     uint8_t* __restrict__ out) {
   __shared__ unsigned long long s_w[kPB / 64];
@@ -921,7 +951,7 @@ __global__ __launch_bounds__(kPB) void k_slp_step(
     if (threadIdx.x == 0) s_base = tot ? atomicAdd(ncount, tot) : 0;
     __syncthreads();
     if (v1 > v0)
-      slp_item_children(mt, p, v0, v1, s_base + excl, rhs, S, el, meta, nsym, npos, out);
+      slp_item_children(mt, p, v0, v1, s_base + excl, rhs, S, el, lbytes, nsym, npos, out);
     __syncthreads();  // s_base is rewritten by the next iteration
   }
   for (int d = 32; d; d >>= 1) gsum += __shfl_xor(gsum, d);
@@ -1383,9 +1413,23 @@ static void slp_lens(lcg_slp* p, hipStream_t s) {
           reinterpret_cast<const RuleMeta*>(p->meta.p), p->gnt.p);
       PP_CHECK("slp_long_gnt");
     }
-    p->el.need(std::max<uint64_t>(p->g, 1), s);
-    k_slp_el<<<pgrid(p->g), kPB, 0, s>>>(p->E.p, p->nt.p, p->g, p->el.p);
-    PP_CHECK("slp_el");
+    {  // the leaves' bytes, stored once
+      DBuf<uint64_t> wl, lboff;
+      wl.need(std::max<uint64_t>(p->g, 1), s);
+      lboff.need((uint64_t)p->g + 1, s);
+      k_slp_leaflen<<<pgrid(p->g), kPB, 0, s>>>(p->E.p, p->nt.p, p->g, wl.p);
+      PP_CHECK("slp_leaflen");
+      sc.run(wl.p, lboff.p, p->g, s);
+      const uint64_t nbytes = read_dev(lboff.p + p->g, s);
+      p->lbytes.need(std::max<uint64_t>(nbytes, 1), s);
+      k_slp_leafbytes<<<pgrid(p->g), kPB, 0, s>>>(p->off.p, p->rhs.p, p->mult.p, wl.p, lboff.p,
+                                                  p->g, p->lbytes.p);
+      PP_CHECK("slp_leafbytes");
+      p->el.need(std::max<uint64_t>(p->g, 1), s);
+      k_slp_el<<<pgrid(p->g), kPB, 0, s>>>(p->E.p, p->nt.p, lboff.p, p->g, p->el.p);
+      PP_CHECK("slp_el");
+      sync(s);  // wl and lboff are released below
+    }
     sync(s);
   }
   p->lens_ready = true;
@@ -1436,7 +1480,7 @@ static void slp_expand_core(lcg_slp* p, uint32_t j0, uint32_t j1, uint8_t* d_out
     zero(ctr.p, 32, s);
     const unsigned grid = std::min(pgrid(m), 4096u);
     k_slp_step<<<grid, kPB, 0, s>>>(sym[cur].p, pos[cur].p, m, nullptr, nullptr, meta, p->gnt.p,
-                                    p->rhs.p, p->S.p, p->N.p, p->el.p, sym[cur ^ 1].p,
+                                    p->rhs.p, p->S.p, p->N.p, p->el.p, p->lbytes.p, sym[cur ^ 1].p,
                                     pos[cur ^ 1].p, uctr, uctr + 1, big.p, uctr + 2, d_out);
     PP_CHECK("slp_step");
     const uint64_t nb = read_dev(ctr.p + 2, s);
@@ -1452,7 +1496,8 @@ static void slp_expand_core(lcg_slp* p, uint32_t j0, uint32_t j1, uint8_t* d_out
       PP_CHECK("slp_pieces");
       k_slp_step<<<std::min(pgrid(np), 4096u), kPB, 0, s>>>(
           sym[cur].p, pos[cur].p, np, vi.p, v0s.p, meta, p->gnt.p, p->rhs.p, p->S.p, p->N.p,
-          p->el.p, sym[cur ^ 1].p, pos[cur ^ 1].p, uctr, uctr + 1, big.p, uctr + 2, d_out);
+          p->el.p, p->lbytes.p, sym[cur ^ 1].p, pos[cur ^ 1].p, uctr, uctr + 1, big.p, uctr + 2,
+          d_out);
       PP_CHECK("slp_step");
     }
     const uint64_t after = read_dev(ctr.p + 1, s);
