@@ -544,6 +544,11 @@ def release_pool():
 def to_device(text, offsets, device="cuda"):
     """numpy (text uint8, offsets uint64) -> device tensors (int64 offsets)."""
     import torch
-    t = torch.from_numpy(np.ascontiguousarray(text, np.uint8)).to(device)
-    o = torch.from_numpy(np.ascontiguousarray(offsets, np.uint64).view(np.int64)).to(device)
+
+    def host(a, dtype):
+        a = np.ascontiguousarray(a, dtype)
+        return a if a.flags.writeable else a.copy()  # torch wraps only writable arrays
+
+    t = torch.from_numpy(host(text, np.uint8)).to(device)
+    o = torch.from_numpy(host(offsets, np.uint64).view(np.int64)).to(device)
     return t, o
