@@ -218,3 +218,28 @@ def test_save_and_load_a_file(L, tmp_path):
     back = L.load_slp(path)
     out, _ = back.expand_strings()
     assert np.array_equal(out.cpu().numpy(), text)
+
+
+def test_merged_and_plain_grammars_store_the_same_file(L):
+    """A grammar built in two halves and merged (MergeGrams), and one built in
+    the plain form, equal the oracle's grammar of all the strings rank for
+    rank, so their stored files are the oracle's bytes; random access works
+    on them."""
+    from oracle import oracle as O
+    text, off = D.make_config("bacterial", scale=0.01)
+    o64 = off.astype(np.int64)
+    strings = [text[o64[j]:o64[j + 1]].tobytes() for j in range(len(o64) - 1)]
+    half = len(strings) // 2
+    want = O.build(text, off, SEED).stored()
+    ta, oa = L.to_device(*O.pack(strings[:half]))
+    tb, ob = L.to_device(*O.pack(strings[half:]))
+    merged = L.build(ta, oa, seed=SEED)
+    merged.merge(L.build(tb, ob, seed=SEED))
+    t, o = L.to_device(text, off)
+    plain = L.build(t, o, seed=SEED, mode=L.MODE_PLAIN)
+    rng = np.random.default_rng(61)
+    q = _slp_queries(rng, off, 500, 300)
+    for g in (merged, plain):
+        slp = g.postprocess()
+        assert bytes(slp.encode().cpu().numpy()) == want
+        _check_slp_extract(slp, text, off, q)
