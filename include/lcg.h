@@ -242,6 +242,32 @@ lcg_status lcg_level_copy(lcg_grammar_t g, uint32_t level, uint64_t* h_rhs_off, 
 /* h_level: uint8[k] level of C[j]; h_sym: uint32[k] rank (byte value at level 0). */
 lcg_status lcg_c_copy(lcg_grammar_t g, uint8_t* h_level, uint32_t* h_sym);
 
+/* The whole grammar in host memory (the encoding of App. A.1: per level the
+ * rules' right-hand sides as ranks of the level below and their
+ * fingerprints F^i; C as (level, rank) pairs). */
+typedef struct {
+  uint32_t u;         /* rules of the level */
+  uint64_t rhs_len;   /* total right-hand-side length */
+  uint64_t* rhs_off;  /* u + 1 offsets into rhs */
+  uint32_t* rhs;      /* rhs_len symbols: bytes at level 1 (widened), ranks above */
+  uint32_t* fp;       /* u fingerprints */
+} lcg_host_level;
+typedef struct {
+  uint64_t seed;
+  uint32_t n_levels;
+  uint32_t k;
+  lcg_host_level* levels; /* n_levels entries, level 1 first */
+  uint8_t* c_level;       /* k: level of C[j] (0 = a byte) */
+  uint32_t* c_sym;        /* k: rank (the byte at level 0) */
+} lcg_host_grammar;
+/* Host copies of every level and of C into *out (arrays allocated by the
+ * library; release them with lcg_host_free).  Synchronises the device.
+ * Errors: LCG_EINVAL (NULL argument), LCG_ENOMEM (host allocation), LCG_EHIP;
+ * on error *out is left empty. */
+lcg_status lcg_export(lcg_grammar_t g, lcg_host_grammar* out);
+/* Frees the arrays of an exported grammar and empties *h (NULL is ignored). */
+void lcg_host_free(lcg_host_grammar* h);
+
 /*
  * Per-round statistics of the builds that produced g, LCG_STATS_FIELDS
  * uint64 per round, in this order: total active length n_i, phrases d_i, new

@@ -1120,6 +1120,53 @@ lcg_status lcg_c_copy(lcg_grammar_t g, uint8_t* h_level, uint32_t* h_sym) {
   });
 }
 
+void lcg_host_free(lcg_host_grammar* h) {
+  if (!h) return;
+  for (uint32_t i = 0; h->levels && i < h->n_levels; ++i) {
+    std::free(h->levels[i].rhs_off);
+    std::free(h->levels[i].rhs);
+    std::free(h->levels[i].fp);
+  }
+  std::free(h->levels);
+  std::free(h->c_level);
+  std::free(h->c_sym);
+  std::memset(h, 0, sizeof(*h));
+}
+
+lcg_status lcg_export(lcg_grammar_t g, lcg_host_grammar* out) {
+  if (out) std::memset(out, 0, sizeof(*out));
+  const lcg_status st = guard([&] {
+    if (!g || !out) throw LcgError{LCG_EINVAL, "grammar or out is NULL"};
+    auto grab = [](size_t bytes) {
+      void* p = std::malloc(bytes ? bytes : 1);
+      if (!p) throw LcgError{LCG_ENOMEM, "host allocation failed"};
+      return p;
+    };
+    const uint32_t nl = (uint32_t)g->levels.size();
+    out->seed = g->seed;
+    out->k = g->k;
+    out->levels = static_cast<lcg_host_level*>(grab(sizeof(lcg_host_level) * nl));
+    std::memset(out->levels, 0, sizeof(lcg_host_level) * (nl ? nl : 1));
+    out->n_levels = nl;
+    for (uint32_t i = 0; i < nl; ++i) {
+      lcg_host_level& H = out->levels[i];
+      H.u = g->levels[i].u;
+      H.rhs_len = g->levels[i].q;
+      H.rhs_off = static_cast<uint64_t*>(grab(sizeof(uint64_t) * (H.u + 1ull)));
+      H.rhs = static_cast<uint32_t*>(grab(sizeof(uint32_t) * H.rhs_len));
+      H.fp = static_cast<uint32_t*>(grab(sizeof(uint32_t) * H.u));
+      const lcg_status s = lcg_level_copy(g, i + 1, H.rhs_off, H.rhs, H.fp);
+      if (s != LCG_OK) throw LcgError{s, g_last_error};
+    }
+    out->c_level = static_cast<uint8_t*>(grab(g->k));
+    out->c_sym = static_cast<uint32_t*>(grab(sizeof(uint32_t) * g->k));
+    const lcg_status s = lcg_c_copy(g, out->c_level, out->c_sym);
+    if (s != LCG_OK) throw LcgError{s, g_last_error};
+  });
+  if (st != LCG_OK && out) lcg_host_free(out);
+  return st;
+}
+
 lcg_status lcg_stats(lcg_grammar_t g, uint64_t* h_out, uint32_t cap_rounds, uint32_t* n_rounds) {
   return guard([&] {
     if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};

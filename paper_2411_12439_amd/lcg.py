@@ -32,7 +32,7 @@ EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_exp
            "lcg_postprocess", "lcg_slp_size", "lcg_slp_stats", "lcg_slp_device", "lcg_slp_copy",
            "lcg_slp_expand_strings", "lcg_slp_free", "lcg_extract", "lcg_build_file", "lcg_lce",
            "lcg_slp_encode", "lcg_slp_decode", "lcg_symbol_lce", "lcg_set_allocator",
-           "lcg_slp_extract")
+           "lcg_slp_extract", "lcg_export", "lcg_host_free")
 
 EXTRACT_MAX = 2048
 
@@ -44,6 +44,18 @@ SLP_STAT_NAMES = ("g_in", "G_in", "run_rules", "g_rl", "G_rl", "removed", "g_out
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class HostLevel(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_uint32), ("rhs_len", ctypes.c_uint64),
+                ("rhs_off", ctypes.POINTER(ctypes.c_uint64)),
+                ("rhs", ctypes.POINTER(ctypes.c_uint32)), ("fp", ctypes.POINTER(ctypes.c_uint32))]
+
+
+class HostGrammar(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("n_levels", ctypes.c_uint32), ("k", ctypes.c_uint32),
+                ("levels", ctypes.POINTER(HostLevel)), ("c_level", ctypes.POINTER(ctypes.c_uint8)),
+                ("c_sym", ctypes.POINTER(ctypes.c_uint32))]
 
 
 class Allocator(ctypes.Structure):
@@ -147,6 +159,10 @@ def lib():
     L.lcg_lce.restype = st
     L.lcg_symbol_lce.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, vp, ctypes.c_uint32, vp, vp]
     L.lcg_symbol_lce.restype = st
+    L.lcg_export.argtypes = [vp, ctypes.POINTER(HostGrammar)]
+    L.lcg_export.restype = st
+    L.lcg_host_free.argtypes = [ctypes.POINTER(HostGrammar)]
+    L.lcg_host_free.restype = None
     L.lcg_slp_extract.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, vp, vp, vp]
     L.lcg_slp_extract.restype = st
     L.lcg_set_allocator.argtypes = [ctypes.POINTER(Allocator)]
@@ -246,6 +262,25 @@ class Grammar:
         cs = np.zeros(max(k, 1), np.uint32)
         _check(lib().lcg_c_copy(self.h, _ptr(cl, ctypes.c_uint8), _ptr(cs, ctypes.c_uint32)))
         return {"seed": seed, "levels": levels, "c_level": cl[:k], "c_sym": cs[:k]}
+
+    def export_host(self):
+        """The grammar through lcg_export, in the layout of export()."""
+        h = HostGrammar()
+        _check(lib().lcg_export(self.h, ctypes.byref(h)))
+        try:
+            levels = []
+            for i in range(h.n_levels):
+                lv = h.levels[i]
+                levels.append({
+                    "rhs_off": np.ctypeslib.as_array(lv.rhs_off, (lv.u + 1,)).copy(),
+                    "rhs": np.ctypeslib.as_array(lv.rhs, (max(lv.rhs_len, 1),))[:lv.rhs_len].copy(),
+                    "fp": np.ctypeslib.as_array(lv.fp, (max(lv.u, 1),))[:lv.u].copy()})
+            k = h.k
+            return {"seed": h.seed, "levels": levels,
+                    "c_level": np.ctypeslib.as_array(h.c_level, (max(k, 1),))[:k].copy(),
+                    "c_sym": np.ctypeslib.as_array(h.c_sym, (max(k, 1),))[:k].copy()}
+        finally:
+            lib().lcg_host_free(ctypes.byref(h))
 
     def stats(self):
         n = ctypes.c_uint32()

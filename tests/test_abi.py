@@ -70,6 +70,11 @@ def test_host_only_entry_points(lcgmod):
     half = lcgmod.Allocator(lcgmod._ALLOC_FN(lambda n, c: None), lcgmod._FREE_FN(), None)
     assert L.lcg_set_allocator(ctypes.byref(half)) == -1
     assert L.lcg_set_allocator(None) == 0
+    # host export: a NULL grammar is refused and leaves the result empty
+    hg = lcgmod.HostGrammar()
+    assert L.lcg_export(None, ctypes.byref(hg)) == -1 and hg.n_levels == 0 and not hg.levels
+    L.lcg_host_free(None)
+    L.lcg_host_free(ctypes.byref(hg))
     g.free()
 
 
