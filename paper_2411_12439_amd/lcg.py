@@ -554,9 +554,35 @@ def build_file(g, path, chunk_bytes=64 << 20, stream=None, **opts):
             "wall_s": info[3] / 1e9, "read_wait_s": info[4] / 1e9, "build_s": info[5] / 1e9}
 
 
-def tune(text, offsets, seed=0, stream=None, **base):
+def tune(text, offsets, seed=0, stream=None, cache=None, **base):
     """lcg_tune: the fastest setting of the TUNABLE options for these strings.
-    Returns ({option: value}, build milliseconds)."""
+    Returns ({option: value}, build milliseconds).  With `cache` (a JSON file
+    path) a result is kept per device and collection shape (bytes, strings),
+    and a later call for the same shape returns it without measuring."""
+    key = None
+    if cache is not None:
+        import json
+        import torch
+        key = "%s|%d|%d" % (torch.cuda.get_device_name(text.device), text.numel(),
+                            offsets.numel() - 1)
+        entries = {}
+        if os.path.exists(cache):
+            with open(cache) as f:
+                entries = json.load(f)
+        if key in entries:
+            e = entries[key]
+            return {f: int(e["options"][f]) for f in TUNABLE}, float(e["ms"])
+    opts, ms = _tune_measured(text, offsets, seed, stream, **base)
+    if cache is not None:
+        entries[key] = {"options": opts, "ms": ms}
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(entries, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return opts, ms
+
+
+def _tune_measured(text, offsets, seed, stream, **base):
     _check_inputs(text, offsets)
     o = make_opts(seed, **base)
     best = Opts()

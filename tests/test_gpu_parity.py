@@ -123,6 +123,24 @@ def test_autotuner(L):
     _assert_same(L.build(t, o, seed=SEED, **best).export(), _oracle(text, off).export())
 
 
+def test_autotuner_cache(L, tmp_path, monkeypatch):
+    """A cached result is returned for the same device and shape without
+    measuring again; another shape is measured."""
+    text, off = D.make_config("tiny", scale=0.5)
+    t, o = L.to_device(text, off)
+    cache = str(tmp_path / "tune.json")
+    first = L.tune(t, o, seed=SEED, cache=cache)
+
+    def no_measuring(*a, **k):
+        raise AssertionError("measured again")
+
+    monkeypatch.setattr(L, "_tune_measured", no_measuring)
+    assert L.tune(t, o, seed=SEED, cache=cache) == first
+    t2, o2 = L.to_device(*D.make_config("tiny", scale=0.25))
+    with pytest.raises(AssertionError):
+        L.tune(t2, o2, seed=SEED, cache=cache)
+
+
 def test_deterministic(L):
     text, off = D.make_config("tiny", scale=0.5)
     a = _gpu(L, text, off).export()
