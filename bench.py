@@ -139,6 +139,21 @@ def copy_ceiling(nbytes=1 << 30, reps=5):
     return round(gbps, 1)
 
 
+def host_cpu():
+    """The host's CPU model (from /proc/cpuinfo) and the logical CPUs this
+    process sees, recorded beside the oracle's timings."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return "%s, %d logical CPUs visible" % (model, os.cpu_count() or 0)
+
+
 def cpu_baseline(text, off, seed, n_strings):
     from oracle import oracle as O
     k = min(n_strings, len(off) - 1)
@@ -150,6 +165,7 @@ def cpu_baseline(text, off, seed, n_strings):
     del g
     nb = int(o_sub[-1])
     return {"value": nb / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "host_cpu": host_cpu(),
             "sample": "first %d of %d strings (%d bytes), one thread, build of the sample; "
                       "%.1f s" % (k, len(off) - 1, nb, dt)}
 
@@ -187,6 +203,7 @@ def cpu_baseline_parallel(text, off, seed, per_thread):
     dt = time.perf_counter() - t0
     nb = int(off[k])
     return {"value": nb / dt / 1e9, "unit": "GB/s", "cores": P, "kind": "oracle",
+            "host_cpu": host_cpu(),
             "sample": "first %d of %d strings (%d bytes) in %d runs built by %d threads, "
                       "then merged pairwise in order; %.1f s (builds %.1f s, merges %.1f s)" % (
                           k, len(off) - 1, nb, P, P, dt, t1 - t0, dt - (t1 - t0))}

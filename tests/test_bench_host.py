@@ -53,3 +53,16 @@ def test_traffic_needs_the_measured_source(tmp_path, monkeypatch):
     f.write_text("kernel_source_sha256: 00\ntraffic_bytes_per_launch: 123\n")
     assert B.profile_traffic("k_insert<unsigned int, false>", "demo") is None
     assert B.profile_traffic("k_insert<unsigned int, false>", "absent") is None
+
+
+def test_cpu_baselines_name_the_host():
+    """Both oracle timings record the host CPU beside their core count."""
+    from oracle import oracle as O
+    from paper_2411_12439_amd import datagen as D
+    text, off = O.pack([b"ACGTACGGTACA" * 20, b"ACGTTCGGTACA" * 20, b"GATTACA" * 30])
+    one = B.cpu_baseline(text, off, D.HASH_SEED, 2)
+    par = B.cpu_baseline_parallel(text, off, D.HASH_SEED, 1)
+    for r in (one, par):
+        assert r["kind"] == "oracle" and r["value"] > 0
+        assert "logical CPUs visible" in r["host_cpu"] and r["host_cpu"].split(",")[0]
+    assert one["cores"] == 1 and 1 <= par["cores"] <= 3
