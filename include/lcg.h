@@ -61,13 +61,18 @@ enum {
 };
 
 enum {
-  LCG_FLAG_TIMING = 1u  /* record per-round device time in the round statistics */
+  LCG_FLAG_TIMING = 1u,        /* record per-round device time in the round statistics */
+  LCG_FLAG_TIMING_INSERT = 2u  /* record only the dictionary insert's device time, and only
+                                  in rounds that read their sizes back (not in rounds queued
+                                  without host reads, see tail_log2); every other time field
+                                  is 0.  Two events per such round instead of about nine per
+                                  round: timing every phase slows a build by a few percent */
 };
 
 typedef struct {
   uint64_t seed;       /* selects the hash family H = {h^0..h^63}; grammars merge only if equal */
   uint32_t mode;       /* LCG_MODE_BATCHED or LCG_MODE_PLAIN */
-  uint32_t flags;      /* LCG_FLAG_* */
+  uint32_t flags;      /* LCG_FLAG_* (other bits: LCG_EINVAL) */
   uint64_t hbm_budget; /* bytes of device working memory a call may hold; 0 = unlimited */
   uint32_t key_bits;   /* test hook: if 1..30, every phrase is keyed by only this many
                           fingerprint bits, so that dictionary lookups rely on the full
@@ -273,7 +278,8 @@ void lcg_host_free(lcg_host_grammar* h);
  * uint64 per round, in this order: total active length n_i, phrases d_i, new
  * rules u_i, new right-hand-side symbols Q_i, strings still active after the
  * round, dictionary probes, full right-hand-side comparisons, dictionary
- * capacity, then device nanoseconds (0 without LCG_FLAG_TIMING) of the round's
+ * capacity, then device nanoseconds (0 without LCG_FLAG_TIMING; with
+ * LCG_FLAG_TIMING_INSERT only the insert's, in rounds with host reads) of the round's
  * kernels (sum of the following), of classify + tile scan, of emit, of
  * insert, of rank (new flags + scans), of commit, and of the segment update;
  * last, the mode of the round (0: one insert per phrase, 1: equal keys

@@ -20,6 +20,7 @@ STAT_NAMES = ("n", "phrases", "new_rules", "new_rhs", "active", "probes", "compa
 MODE_BATCHED = 0
 MODE_PLAIN = 1
 FLAG_TIMING = 1
+FLAG_TIMING_INSERT = 2
 
 _STATUS = {0: "LCG_OK", -1: "LCG_EINVAL", -2: "LCG_ENOMEM", -3: "LCG_ESEED",
            -4: "LCG_EOVERFLOW", -5: "LCG_ETABLE", -6: "LCG_EHIP"}
@@ -557,14 +558,17 @@ def build_file(g, path, chunk_bytes=64 << 20, stream=None, **opts):
 def tune(text, offsets, seed=0, stream=None, cache=None, **base):
     """lcg_tune: the fastest setting of the TUNABLE options for these strings.
     Returns ({option: value}, build milliseconds).  With `cache` (a JSON file
-    path) a result is kept per device and collection shape (bytes, strings),
-    and a later call for the same shape returns it without measuring."""
+    path) a result is kept per device, collection shape (bytes, strings) and
+    setting of the fixed options in `base`, and a later call for the same
+    ones returns it without measuring."""
     key = None
     if cache is not None:
         import json
         import torch
         key = "%s|%d|%d" % (torch.cuda.get_device_name(text.device), text.numel(),
                             offsets.numel() - 1)
+        if base:
+            key += "|" + ",".join("%s=%s" % kv for kv in sorted(base.items()))
         entries = {}
         if os.path.exists(cache):
             with open(cache) as f:

@@ -28,3 +28,23 @@ def test_export_equals_level_copies_and_oracle(config, scale):
         assert np.array_equal(got["c_level"], b["c_level"])
         assert np.array_equal(got["c_sym"], b["c_sym"])
     assert a["seed"] == b["seed"] == SEED
+
+
+def test_export_without_levels():
+    """A new grammar (no strings) and a grammar of one-byte strings have no
+    levels; lcg_export still returns them whole."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from oracle import oracle as O
+    from paper_2411_12439_amd import lcg
+    h = lcg.new(SEED).export_host()
+    assert h["seed"] == SEED and h["levels"] == []
+    assert h["c_level"].size == 0 and h["c_sym"].size == 0
+    strings = [b"A", b"C", b"A", b"T"]
+    t, o = lcg.to_device(*O.pack(strings))
+    g = lcg.build(t, o, seed=SEED)
+    a, want = g.export_host(), O.build(*O.pack(strings), SEED).export()
+    assert a["levels"] == [] and len(want["levels"]) == 0
+    assert np.array_equal(a["c_level"], want["c_level"])
+    assert np.array_equal(a["c_sym"], want["c_sym"])
+    assert a["c_sym"].tolist() == [ord(x) for x in "ACAT"]

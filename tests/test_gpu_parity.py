@@ -124,8 +124,9 @@ def test_autotuner(L):
 
 
 def test_autotuner_cache(L, tmp_path, monkeypatch):
-    """A cached result is returned for the same device and shape without
-    measuring again; another shape is measured."""
+    """A cached result is returned for the same device, shape and fixed
+    options without measuring again; another shape, or another setting of a
+    fixed option, is measured."""
     text, off = D.make_config("tiny", scale=0.5)
     t, o = L.to_device(text, off)
     cache = str(tmp_path / "tune.json")
@@ -139,7 +140,39 @@ def test_autotuner_cache(L, tmp_path, monkeypatch):
     t2, o2 = L.to_device(*D.make_config("tiny", scale=0.25))
     with pytest.raises(AssertionError):
         L.tune(t2, o2, seed=SEED, cache=cache)
+    with pytest.raises(AssertionError):
+        L.tune(t, o, seed=SEED, cache=cache, table_min_log2=20)
 
+
+
+def test_timing_flags(L):
+    """LCG_FLAG_TIMING_INSERT records the insert's device time in the rounds
+    with host reads and nothing else; neither timing flag changes the grammar
+    or the counts; an unknown flag bit is refused."""
+    text, off = D.make_config("tiny")
+    t, o = L.to_device(text, off)
+    kw = dict(seed=SEED, tail_log2=14)  # rounds above 2^14 symbols read their sizes back
+    sp = L.build(t, o, **kw)
+    si = L.build(t, o, flags=L.FLAG_TIMING_INSERT, **kw)
+    sf = L.build(t, o, flags=L.FLAG_TIMING, **kw)
+    want = _oracle(text, off).export()
+    for g in (sp, si, sf):
+        _assert_same(g.export(), want)
+    p, i, f = sp.stats(), si.stats(), sf.stats()
+    # n, d, u, Q, active strings, capacity and mode; the probe and comparison
+    # counts depend on which thread claims a slot first
+    det = [0, 1, 2, 3, 4, 7, 15]
+    for st in (i, f):
+        assert np.array_equal(st[:, det], p[:, det])
+    assert (p[:, 8:15] == 0).all()
+    host = i[:, 15] != 2
+    assert host.any() and (~host).any()
+    assert (i[host, 11] > 0).all() and np.array_equal(i[host, 8], i[host, 11])
+    assert (i[:, [9, 10, 12, 13, 14]] == 0).all() and (i[~host, 8:15] == 0).all()
+    assert (f[:, 8] > 0).all() and np.array_equal(f[:, 8], f[:, 9:15].sum(axis=1))
+    with pytest.raises(L.LcgError) as e:
+        L.build(t, o, flags=4, **kw)
+    assert e.value.name == "LCG_EINVAL"
 
 def test_deterministic(L):
     text, off = D.make_config("tiny", scale=0.5)
