@@ -823,12 +823,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_block(const uint64_t* __restric
   if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
 }
 
-__global__ void k_scan_add(uint64_t* __restrict__ out, uint64_t n, const uint64_t* __restrict__ offs) {
+// Adds each block's offset; thread n also stores the total, offs[nb], in
+// out[n].
+__global__ void k_scan_add(uint64_t* __restrict__ out, uint64_t n, const uint64_t* __restrict__ offs,
+                           uint64_t nb) {
   const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   if (i < n) out[i] += offs[i / kScanPer];
+  else if (i == n) out[n] = offs[nb];
 }
-
-__global__ void k_copy_word(uint64_t* dst, const uint64_t* src) { *dst = *src; }
 
 size_t scan_tmp_words(uint64_t n) {
   if (n <= (uint64_t)kScanPer) return 0;
@@ -848,10 +850,8 @@ void scan_exclusive(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* tmp
   k_scan_block<<<grid_for(nb * kScanPer, kScanPer), kBlock, 0, s>>>(in, out, n, sums);
   LCG_LAUNCH_CHECK("scan_block");
   scan_exclusive(sums, offs, nb, tmp + nb + nb + 1, s);
-  k_scan_add<<<grid_for(n, 256), 256, 0, s>>>(out, n, offs);
+  k_scan_add<<<grid_for(n + 1, 256), 256, 0, s>>>(out, n, offs, nb);
   LCG_LAUNCH_CHECK("scan_add");
-  k_copy_word<<<1, 1, 0, s>>>(out + n, offs + nb);
-  LCG_LAUNCH_CHECK("copy_word");
 }
 
 // Exclusive scan in one block, for short arrays whose length is on the
