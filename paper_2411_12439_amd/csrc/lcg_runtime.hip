@@ -235,11 +235,14 @@ static void ensure_table(Level& L, uint64_t need, const Opts& o, Work& w, hipStr
   L.tcap = want;
 }
 
-static void ensure_level(lcg_grammar* g, size_t i, hipStream_t s) {
+// Levels up to i exist; a level created here gets room for off_cap offsets
+// if it is level i (a caller that knows the level's size saves the copy of
+// the first offset when the array is grown to it), else for one.
+static void ensure_level(lcg_grammar* g, size_t i, hipStream_t s, size_t off_cap = 1) {
   while (g->levels.size() < i) {
     g->levels.emplace_back();
     Level& L = g->levels.back();
-    L.off.need(1, s);
+    L.off.need(g->levels.size() == i ? std::max<size_t>(off_cap, 1) : 1, s);
     HIP_CHECK(hipMemsetAsync(L.off.p, 0, sizeof(uint64_t), s));
   }
 }
@@ -406,7 +409,7 @@ static void tail_rounds(lcg_grammar* g, uint32_t lv, uint64_t n_i, uint64_t acti
     w.wlen.need(W_b, s);
     w.wcnt_base.need(W_b + 1, s);
     w.wlen_base.need(W_b + 1, s);
-    ensure_level(g, lv, s);
+    ensure_level(g, lv, s, d_b + 1);
     Level& L = g->levels[lv - 1];
     ensure_table(L, (uint64_t)L.u + d_b, o, w, s);
     if ((uint64_t)L.u + d_b >= kNone) throw LcgError{LCG_EOVERFLOW, "level needs 2^32 ranks"};
