@@ -7,6 +7,7 @@ import subprocess
 import sys
 
 import numpy as np
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -25,6 +26,14 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 2 and "one GPU only" in r.stderr
+
+
+@pytest.mark.parametrize("args", [["--steps", "0"], ["--phase-builds", "0"]])
+def test_no_timed_or_phase_builds_is_refused(args):
+    """The roofline needs timed builds and the phase table an untimed one."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + args,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2 and "must be at least 1" in r.stderr
 
 
 def test_algorithmic_bytes_of_two_rounds():
