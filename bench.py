@@ -68,8 +68,11 @@ def phase_alg_bytes(st):
     for i, row in enumerate(st, start=1):
         n, d, u, q = (float(x) for x in row[:4])
         s = 1.0 if i == 1 else 4.0
-        out["classify"] += n * (1.0 if i == 1 else 4.0)
-        out["emit"] += n * s
+        # round 1 reads its byte stream once in the model (classify takes it
+        # through the h^0 table; emit's second pass over it is not charged);
+        # later rounds read the fingerprints (classify) and the ranks (emit)
+        out["classify"] += n * s
+        out["emit"] += 0.0 if i == 1 else n * s
         out["insert"] += d * 8.0 + u * 8.0
         out["commit"] += u * 8.0 + q * s + d * 4.0
     return out
@@ -211,6 +214,65 @@ def cpu_baseline_parallel(text, off, seed, per_thread):
                           k, len(off) - 1, nb, P, P, dt, t1 - t0, dt - (t1 - t0))}
 
 
+def time_builds(lcg, t, o, seed, steps, warmup, phase_builds, tuned):
+    """Warm-up, timed and phase-timed batched builds of one resident collection.
+
+    Returns (step seconds, [(insert launches, insert ns)] per timed build, the
+    stats of the last phase-timed build, the summed per-phase ns, timed wall s)."""
+    import torch
+    # Timed builds record only the dictionary insert's events, in the rounds
+    # that read their sizes back (the roofline's launches): timing every phase
+    # costs about nine events per round.  The phase breakdown comes from the
+    # untimed builds after.
+    for i in range(warmup):
+        g = lcg.build(t, o, seed=seed, flags=lcg.FLAG_TIMING_INSERT, **tuned)
+        g.free()
+        print("[bench] warmup %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    step_s = []
+    ins_ns_steps = []
+    t_all = time.perf_counter()
+    for i in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = lcg.build(t, o, seed=seed, flags=lcg.FLAG_TIMING_INSERT, **tuned)
+        torch.cuda.synchronize()
+        step_s.append(time.perf_counter() - t0)
+        rows = insert_rounds(g.stats())
+        ins_ns_steps.append((len(rows), float(sum(r[11] for r in rows))))
+        g.free()
+        print("[bench] step %d: %.2f ms" % (i, step_s[-1] * 1e3), file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t_all
+    torch.cuda.synchronize()
+    phase_ns = {p: 0.0 for p in PHASES}
+    stats = None
+    for i in range(phase_builds):
+        g = lcg.build(t, o, seed=seed, flags=lcg.FLAG_TIMING, **tuned)
+        stats = g.stats()
+        for j, p in enumerate(PHASES):
+            phase_ns[p] += float(stats[:, 9 + j].sum())
+        g.free()
+    torch.cuda.synchronize()
+    return np.array(step_s), ins_ns_steps, stats, phase_ns, wall
+
+
+def time_plain(lcg, t, o, seed, steps):
+    """Seconds of `steps` plain-form builds (after one untimed one)."""
+    import torch
+    g = lcg.build(t, o, seed=seed, mode=lcg.MODE_PLAIN)
+    g.free()
+    ps = []
+    for i in range(max(1, steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = lcg.build(t, o, seed=seed, mode=lcg.MODE_PLAIN)
+        torch.cuda.synchronize()
+        ps.append(time.perf_counter() - t0)
+        g.free()
+        print("[bench] plain step %d: %.2f ms" % (i, ps[-1] * 1e3), file=sys.stderr, flush=True)
+    return np.array(ps)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,16 +280,21 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--phase-builds", type=int, default=3,
                     help="untimed builds after the timed ones, with every phase timed")
-    ap.add_argument("--config", default="bacterial", choices=sorted(WORKLOADS))
+    ap.add_argument("--config", default="batched", choices=sorted(WORKLOADS),
+                    help="the collection the headline is measured on (default: the batched one)")
+    ap.add_argument("--extra-config", default="bacterial", choices=sorted(WORKLOADS),
+                    help="the collection of the secondary legs (its own batched and plain builds, "
+                         "decompression, post-processing, random access, LCE, streaming)")
     ap.add_argument("--scale", type=float, default=1.0)
-    ap.add_argument("--plain-steps", type=int, default=1)
-    ap.add_argument("--cpu-strings", type=int, default=4, help="strings in the oracle sample")
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--cpu-bytes", type=float, default=150e6,
+                    help="bytes of the oracle's sample (whole strings from the first)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--rounds", action="store_true", help="per-round phase table on stderr")
     ap.add_argument("--no-extra", action="store_true",
-                    help="only the timed builds: no decompression, post-processing, random "
-                         "access, LCE or streaming legs (for profiling the build alone)")
+                    help="only the headline builds: no secondary collection, decompression, "
+                         "post-processing, random access, LCE or streaming legs")
     ap.add_argument("--serving-seconds", type=float, default=4.0,
                     help="seconds per offered load of the serving leg (0 = skip)")
     ap.add_argument("--serving-loads", default="0.5,2,8")
@@ -260,54 +327,21 @@ def main():
         return
 
     seed = datagen.HASH_SEED
+    t_gen = time.perf_counter()
     text, off = datagen.make_config(args.config, scale=args.scale)
     n = int(off[-1])
     k = len(off) - 1
     t, o = lcg.to_device(text, off)
     torch.cuda.synchronize()
-    print("[bench] %s: %d strings, %d bytes on device" % (args.config, k, n), file=sys.stderr,
-          flush=True)
+    print("[bench] %s: %d strings, %d bytes on device (%.1f s)" % (
+        args.config, k, n, time.perf_counter() - t_gen), file=sys.stderr, flush=True)
 
     # the autotuner picks the speed-only options for this workload (untimed)
     tuned, tuned_ms = ({}, None) if args.no_tune else lcg.tune(t, o, seed=seed)
     if tuned:
         print("[bench] tuned %s (%.2f ms)" % (tuned, tuned_ms), file=sys.stderr, flush=True)
-    # Timed builds record only the dictionary insert's events, in the rounds
-    # that read their sizes back (the roofline's launches): timing every phase
-    # costs about nine events per round, some 0.7 ms per build on this
-    # collection.  The phase breakdown comes from the untimed builds after.
-    for i in range(args.warmup):
-        g = lcg.build(t, o, seed=seed, flags=lcg.FLAG_TIMING_INSERT, **tuned)
-        g.free()
-        print("[bench] warmup %d done" % i, file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-
-    step_s = []
-    ins_ns_steps = []
-    t_all = time.perf_counter()
-    for i in range(args.steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g = lcg.build(t, o, seed=seed, flags=lcg.FLAG_TIMING_INSERT, **tuned)
-        torch.cuda.synchronize()
-        step_s.append(time.perf_counter() - t0)
-        rows = insert_rounds(g.stats())
-        ins_ns_steps.append((len(rows), float(sum(r[11] for r in rows))))
-        g.free()
-        print("[bench] step %d: %.2f ms" % (i, step_s[-1] * 1e3), file=sys.stderr, flush=True)
-    wall = time.perf_counter() - t_all
-    torch.cuda.synchronize()
-
-    # untimed builds with every phase timed: the per-phase device times
-    phase_ns = {p: 0.0 for p in PHASES}
-    stats = None
-    for i in range(args.phase_builds):
-        g = lcg.build(t, o, seed=seed, flags=lcg.FLAG_TIMING, **tuned)
-        stats = g.stats()
-        for j, p in enumerate(PHASES):
-            phase_ns[p] += float(stats[:, 9 + j].sum())
-        g.free()
-    torch.cuda.synchronize()
+    step_s, ins_ns_steps, stats, phase_ns, wall = time_builds(
+        lcg, t, o, seed, args.steps, args.warmup, args.phase_builds, tuned)
     if args.rounds:
         print("[bench] round      n        d        u     probes  cmp  ms: " + " ".join(PHASES),
               file=sys.stderr)
@@ -317,7 +351,6 @@ def main():
                 " ".join("%7.3f" % (row[9 + j] / 1e6) for j in range(len(PHASES)))),
                 file=sys.stderr)
 
-    step_s = np.array(step_s)
     gbps = n / step_s / 1e9
     value = n * args.steps / step_s.sum() / 1e9
     alg = path_alg_bytes(stats)
@@ -371,9 +404,35 @@ def main():
            "roofline": roofline}
     out["hbm_copy_gbps"] = copy_ceiling()
 
+    if not args.no_plain:
+        ps = time_plain(lcg, t, o, seed, args.plain_steps)
+        plain = n / float(np.median(ps)) / 1e9
+        out["plain_gbps"] = round(plain, 4)
+        out["plain_steps_gbps"] = [round(n / x / 1e9, 4) for x in ps]
+        out["batched_vs_plain"] = round(value / plain, 2)
+    del t, o
+    torch.cuda.empty_cache()
+
     if not args.no_extra:
-        extra_legs(args, out, text, off, t, o, n, k, seed)
-    plain_and_rest(args, out, text, off, t, o, n, seed, value)
+        extra = args.extra_config
+        xt, xoff = datagen.make_config(extra, scale=args.scale)
+        xn, xk = int(xoff[-1]), len(xoff) - 1
+        xdt, xdo = lcg.to_device(xt, xoff)
+        xs_s, _, _, _, _ = time_builds(lcg, xdt, xdo, seed, args.steps, 1, 1, tuned)
+        xv = xn * len(xs_s) / xs_s.sum() / 1e9
+        sec = {"workload": WORKLOADS[extra], "name": extra, "strings": xk, "bytes": xn,
+               "batched_gbps": round(xv, 4),
+               "batched_ms": round(float(xs_s.mean()) * 1e3, 3)}
+        if not args.no_plain:
+            xps = time_plain(lcg, xdt, xdo, seed, args.plain_steps)
+            sec["plain_gbps"] = round(xn / float(np.median(xps)) / 1e9, 4)
+            sec["batched_vs_plain"] = round(xv / sec["plain_gbps"], 2)
+        out["secondary"] = sec
+        print("[bench] secondary %s" % json.dumps(sec), file=sys.stderr, flush=True)
+        extra_legs(args, out, xt, xoff, xdt, xdo, xn, xk, seed)
+        del xdt, xdo
+        torch.cuda.empty_cache()
+    serving_and_cpu(args, out, text, off, seed)
 
 
 def extra_legs(args, out, text, off, t, o, n, k, seed):
@@ -658,45 +717,35 @@ def extra_legs(args, out, text, off, t, o, n, k, seed):
 
 
 
-def plain_and_rest(args, out, text, off, t, o, n, seed, value):
-    """Plain form, serving and the CPU baseline; prints the JSON line."""
-    import torch
-    from paper_2411_12439_amd import datagen, lcg
-    if not args.no_plain:
-        g = lcg.build(t, o, seed=seed, mode=lcg.MODE_PLAIN)
-        g.free()
-        ps = []
-        for i in range(max(1, args.plain_steps)):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            g = lcg.build(t, o, seed=seed, mode=lcg.MODE_PLAIN)
-            torch.cuda.synchronize()
-            ps.append(time.perf_counter() - t0)
-            g.free()
-            print("[bench] plain step %d: %.2f ms" % (i, ps[-1] * 1e3), file=sys.stderr, flush=True)
-        plain = n / float(np.mean(ps)) / 1e9
-        out["plain_gbps"] = round(plain, 4)
-        out["batched_vs_plain"] = round(value / plain, 2)
+def cpu_sample_strings(off, nbytes):
+    """Whole strings from the first until the sample holds at least nbytes."""
+    o = off.astype(np.int64)
+    return max(1, min(len(o) - 1, int(np.searchsorted(o, nbytes, side="left"))))
 
+
+def serving_and_cpu(args, out, text, off, seed):
+    """Serving leg and the CPU baselines; prints the JSON line."""
+    from paper_2411_12439_amd import datagen
     if args.serving_seconds > 0:
         from paper_2411_12439_amd import serve
-        del t, o
         src = datagen.ServingSource()
-        pool = serve.PinnedPool(src)
         rows = []
         for load in (float(x) for x in args.serving_loads.split(",")):
-            summary, srv, reqs = serve.run_load(pool, load, args.serving_seconds)
+            summary, srv, reqs = serve.run_load(src, load, args.serving_seconds)
             rng = np.random.default_rng(0)
             sample = rng.choice(len(reqs), size=min(4, len(reqs)), replace=False)
-            summary["alone_vs_mix_checked"] = serve.check_alone_vs_mix(srv, pool, reqs, sample)
+            summary["alone_vs_mix_checked"] = serve.check_alone_vs_mix(srv, src, reqs, sample)
             rows.append(summary)
             print("[bench] serving %s" % json.dumps(summary), file=sys.stderr, flush=True)
+            srv.close()
             del srv
         out["serving"] = rows
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(text, off, seed, args.cpu_strings)
-        out["cpu_baseline_parallel"] = cpu_baseline_parallel(text, off, seed, args.cpu_strings)
+        ks = cpu_sample_strings(off, args.cpu_bytes)
+        out["cpu_baseline"] = cpu_baseline(text, off, seed, ks)
+        out["cpu_baseline_parallel"] = cpu_baseline_parallel(
+            text, off, seed, max(1, ks // max(1, min(16, os.cpu_count() or 1))))
     print(json.dumps(out), flush=True)
 
 

@@ -88,7 +88,10 @@ typedef struct {
                                new keys for its d phrases combines equal keys per chunk of
                                phrases before the dictionary; 1..30, 0 = 5, 31 = never.
                                Results do not depend on it. */
-  uint32_t reserved;   /* must be zero */
+  uint32_t fail_round; /* test hook: if nonzero, the call fails with LCG_ETABLE when it
+                          reaches parsing round fail_round (after the earlier rounds have
+                          changed the grammar), to exercise the recovery described at
+                          lcg_build_into; 0 = off */
 } lcg_opts;
 
 /* Fill *o with the defaults (seed 0, batched mode, unlimited budget). */
@@ -120,6 +123,12 @@ lcg_status lcg_build(const uint8_t* d_text, const uint64_t* d_offsets, uint32_t 
  *   first_index  receives the index in C of the batch's first string (may be NULL)
  * Same input conventions and errors as lcg_build, plus LCG_ESEED if
  * opts->seed differs from g's seed.
+ * On any error g is restored to its state before the call (its string count,
+ * every level's rules, and dictionaries rebuilt from the rules kept, so that
+ * no entry of the failed call can be found later) and stays usable.  If the
+ * restoration itself fails (for instance after an asynchronous HIP fault), g
+ * is marked unusable: every later call on it except lcg_free and lcg_info
+ * returns LCG_EINVAL.
  */
 lcg_status lcg_build_into(lcg_grammar_t g, const uint8_t* d_text, const uint64_t* d_offsets,
                           uint32_t k, const lcg_opts* opts, hipStream_t stream,
@@ -131,7 +140,8 @@ lcg_status lcg_build_into(lcg_grammar_t g, const uint8_t* d_text, const uint64_t
  * the level below) is looked up in a's dictionary of that level; a hit reuses
  * a's rank, a miss appends the rule to a.  C_a becomes C_a . C_b.  a is
  * modified in place, b is left unchanged.  Errors: LCG_ESEED, LCG_ENOMEM,
- * LCG_EOVERFLOW, LCG_EHIP.
+ * LCG_EOVERFLOW, LCG_EHIP; on error a is restored as after a failed
+ * lcg_build_into.
  */
 lcg_status lcg_merge(lcg_grammar_t a, lcg_grammar_t b, hipStream_t stream);
 

@@ -107,6 +107,67 @@ def subgrammar(g, js):
             "c_sym": np.array(new_cs, np.uint32)}
 
 
+def _gather(off, rhs, syms):
+    """Concatenated right-hand sides of the rules `syms` (int64 ranks)."""
+    a = off[syms]
+    lens = off[syms + 1] - a
+    tot = int(lens.sum())
+    if tot == 0:
+        return rhs[:0].astype(np.int64), lens
+    starts = np.concatenate(([0], np.cumsum(lens)[:-1]))
+    idx = np.repeat(a - starts, lens) + np.arange(tot, dtype=np.int64)
+    return rhs[idx].astype(np.int64), lens
+
+
+def _as_i64(a):
+    """int64 view (or copy) of an offsets array."""
+    a = np.asarray(a)
+    return a.view(np.int64) if a.dtype == np.uint64 else a.astype(np.int64)
+
+
+def own_order_subgrammar(g, j):
+    """String j's grammar as found inside g, in the rank order a build of that
+    string alone gives.
+
+    The rules reachable from C[j] are kept and each level is renumbered in
+    order of first occurrence in the string's own sequence of that level's
+    symbols (T^{i+1}_j, rebuilt top-down from C[j]); that is the order in which
+    a build of T_j alone numbers its rules (first occurrence, Sec. 3.3), so
+    by stability (Def. 1) the result must equal that build exactly.  Works on
+    whole-genome strings: every step is a vectorised pass over one level."""
+    lv = int(np.asarray(g["c_level"], np.uint8)[j])
+    sym = int(np.asarray(g["c_sym"], np.uint32)[j])
+    if lv == 0:
+        return {"seed": g["seed"], "levels": [], "c_level": np.array([0], np.uint8),
+                "c_sym": np.array([sym], np.uint32)}
+    cur = np.array([sym], np.int64)      # T^{lv+1}_j
+    kept = [None] * lv
+    for i in range(lv, 0, -1):
+        L = g["levels"][i - 1]
+        off = _as_i64(L["rhs_off"])
+        rhs = np.asarray(L["rhs"])
+        uniq, first = np.unique(cur, return_index=True)
+        order = uniq[np.argsort(first, kind="stable")]
+        body, lens = _gather(off, rhs, order)
+        new_off = np.zeros(len(order) + 1, np.uint64)
+        new_off[1:] = np.cumsum(lens)
+        kept[i - 1] = (order, new_off, body, np.asarray(L["fp"], np.uint32)[order])
+        if i > 1:
+            cur, _ = _gather(off, rhs, cur)
+    levels = []
+    prev_map = None
+    for i in range(1, lv + 1):
+        order, new_off, body, fp = kept[i - 1]
+        if prev_map is not None:
+            body = prev_map[body]
+        levels.append({"rhs_off": new_off, "rhs": body.astype(np.uint32), "fp": fp})
+        u_old = len(g["levels"][i - 1]["rhs_off"]) - 1
+        prev_map = np.full(u_old, -1, np.int64)
+        prev_map[order] = np.arange(len(order), dtype=np.int64)
+    return {"seed": g["seed"], "levels": levels, "c_level": np.array([lv], np.uint8),
+            "c_sym": np.array([prev_map[sym]], np.uint32)}
+
+
 def exports_equal(x, y):
     """Exact (rank-for-rank) equality of two exported grammars."""
     if int(x["seed"]) != int(y["seed"]) or len(x["levels"]) != len(y["levels"]):

@@ -390,7 +390,7 @@ lcg_status lcg_extract(lcg_grammar_t g, uint32_t nq, const uint32_t* d_j, const 
                        const uint32_t* d_len, const uint64_t* d_out_off, uint8_t* d_out,
                        hipStream_t stream) {
   return guard([&] {
-    if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    live(g);
     if (!nq) return;
     if (!d_j || !d_start || !d_len || !d_out_off || !d_out)
       throw LcgError{LCG_EINVAL, "NULL query or output array"};
@@ -422,7 +422,7 @@ lcg_status lcg_lce(lcg_grammar_t g, uint32_t nq, const uint32_t* d_j1, const uin
                    const uint32_t* d_j2, const uint64_t* d_p2, uint32_t backward,
                    uint64_t* d_out, hipStream_t stream) {
   return guard([&] {
-    if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    live(g);
     if (backward > 1) throw LcgError{LCG_EINVAL, "backward must be 0 or 1"};
     if (!nq) return;
     if (!d_j1 || !d_p1 || !d_j2 || !d_p2 || !d_out)
@@ -455,7 +455,7 @@ lcg_status lcg_symbol_lce(lcg_grammar_t g, uint32_t nq, const uint8_t* d_lv1, co
                           const uint8_t* d_lv2, const uint32_t* d_s2, uint32_t backward,
                           uint64_t* d_out, hipStream_t stream) {
   return guard([&] {
-    if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    live(g);
     if (backward > 1) throw LcgError{LCG_EINVAL, "backward must be 0 or 1"};
     if (!nq) return;
     if (!d_lv1 || !d_s1 || !d_lv2 || !d_s2 || !d_out)

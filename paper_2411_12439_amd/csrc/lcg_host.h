@@ -289,10 +289,20 @@ struct lcg_grammar {
   lcg::DBuf<const uint64_t*> explen_ptrs;
   lcg::DBuf<lcg::LevelPtrs> level_ptrs;  // per level: offsets and right-hand sides
   uint64_t explen_version = ~0ull;
+  // set when a failed call could not restore the grammar: later calls refuse it
+  bool poisoned = false;
   explicit lcg_grammar(uint64_t s) : seed(s), H(s) {}
 };
 
 namespace lcg {
+
+// g, checked: not NULL and not left unusable by a failed call.
+inline lcg_grammar* live(lcg_grammar* g) {
+  if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+  if (g->poisoned)
+    throw LcgError{LCG_EINVAL, "grammar is unusable: an earlier call failed and could not restore it"};
+  return g;
+}
 
 // Synchronise s; blocks whose release waited for it become reusable.
 inline void sync(hipStream_t s) {

@@ -97,8 +97,9 @@ void launch_commit(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t
 // d / kCommitListRatio, the new phrases are listed first and committed one
 // thread per rule (nlist: u_new uint32, nqoff: u_new uint64 of scratch)
 constexpr uint64_t kCommitListRatio = 4;
+// Rules with rank < rank_limit (kNone: every committed rule) into new_t.
 void launch_rehash(const Slot* old_t, uint64_t old_cap, Slot* new_t, uint64_t new_mask,
-                   Counters* ctr, hipStream_t s);
+                   uint32_t rank_limit, Counters* ctr, hipStream_t s);
 
 void launch_c_init(const uint8_t* text, const uint64_t* off, uint32_t k, uint8_t* c_level,
                    uint32_t* c_sym, hipStream_t s);

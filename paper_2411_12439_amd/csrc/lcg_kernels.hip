@@ -61,13 +61,16 @@ static inline unsigned grid_for(uint64_t n, int block) {
 }
 
 // ------------------------------------------------------------------ helpers
-// A plain load, served by the CU's L1 and allowed to return a stale value.
-// Used where a stale value only costs extra work (an empty slot word leads to
-// the compare-and-swap, an uncommitted rank to the first-occurrence count, a
-// larger first occurrence to an atomicMin).
+// A relaxed atomic load of a word other threads update with atomics in the
+// same kernel.  Workgroup scope: the load may be served by the CU's L1 and
+// return an older value of the word, which only costs extra work where it is
+// used (an empty slot word leads to the compare-and-swap, which returns the
+// current word; a larger first occurrence to an atomicMin).  Being atomic,
+// the load is never torn, merged with another or assumed unchanged by the
+// compiler, which a plain load of a concurrently written word would allow.
 template <typename T>
 __device__ __forceinline__ T hint_load(const T* p) {
-  return *p;
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 #pragma unroll
@@ -1114,7 +1117,8 @@ __global__ __launch_bounds__(256) void k_insert_comb(uint64_t begin, uint64_t en
         if (!(kk & kLongTag)) {
           uint32_t lpos = (uint32_t)(mix64(kk) >> 40) & (kComb - 1);
           for (int t = 0; t < kCombProbe && found == kNone; ++t) {
-            const unsigned long long w = s_key[lpos];
+            const unsigned long long w =
+                __hip_atomic_load(&s_key[lpos], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             bool hit;
             if (w == kEmpty) {
               const unsigned long long prev =
@@ -1619,12 +1623,15 @@ void launch_commit(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t
 }
 
 // ------------------------------------------------------------------ rehash
+// Committed rules with rank < rank_limit move to the new table; claims that
+// were never committed (rank kNone) and rules at or above the limit are
+// dropped.
 __global__ void k_rehash(const Slot* __restrict__ old_t, uint64_t old_cap, Slot* new_t,
-                         uint64_t mask, Counters* ctr) {
+                         uint64_t mask, uint32_t rank_limit, Counters* ctr) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < old_cap;
        i += (uint64_t)gridDim.x * blockDim.x) {
     const Slot sl = old_t[i];
-    if (sl.w0 == kEmpty || sl.rank == kNone) continue;
+    if (sl.w0 == kEmpty || sl.rank == kNone || sl.rank >= rank_limit) continue;
     uint64_t pos = mix64(probe_key(sl.w0)) & mask;
     bool done = false;
     for (uint64_t t = 0; t <= mask && !done; ++t) {
@@ -1642,11 +1649,11 @@ __global__ void k_rehash(const Slot* __restrict__ old_t, uint64_t old_cap, Slot*
 }
 
 void launch_rehash(const Slot* old_t, uint64_t old_cap, Slot* new_t, uint64_t new_mask,
-                   Counters* ctr, hipStream_t s) {
+                   uint32_t rank_limit, Counters* ctr, hipStream_t s) {
   if (!old_cap) return;
   unsigned g = grid_for(old_cap, 256);
   if (g > 8192) g = 8192;
-  k_rehash<<<g, 256, 0, s>>>(old_t, old_cap, new_t, new_mask, ctr);
+  k_rehash<<<g, 256, 0, s>>>(old_t, old_cap, new_t, new_mask, rank_limit, ctr);
   LCG_LAUNCH_CHECK("rehash");
 }
 

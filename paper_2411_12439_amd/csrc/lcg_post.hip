@@ -2199,7 +2199,8 @@ extern "C" {
 
 lcg_status lcg_postprocess(lcg_grammar_t g, uint32_t flags, hipStream_t stream, lcg_slp_t* out) {
   return guard([&] {
-    if (!g || !out) throw LcgError{LCG_EINVAL, "grammar or out is NULL"};
+    live(g);
+    if (!out) throw LcgError{LCG_EINVAL, "out is NULL"};
     if (flags & ~uint32_t(LCG_PP_RL | LCG_PP_SIMP)) throw LcgError{LCG_EINVAL, "unknown flags"};
     if (g->k == 0) throw LcgError{LCG_EINVAL, "the grammar holds no string"};
     *out = postprocess_core(g, flags, stream);

@@ -37,6 +37,7 @@ struct Opts {
   uint32_t tail_log2 = 22;
   uint32_t table_load_log2 = 1;
   uint32_t combine_log2 = 5;  // 31: never
+  uint32_t fail_round = 0;    // test hook: fail on reaching this round (0 = off)
 };
 
 static Opts read_opts(const lcg_opts* o) {
@@ -54,7 +55,7 @@ static Opts read_opts(const lcg_opts* o) {
   if (r.table_load_log2 > 3) throw LcgError{LCG_EINVAL, "table_load_log2 out of range"};
   if (o->combine_log2) r.combine_log2 = o->combine_log2;
   if (r.combine_log2 > 31) throw LcgError{LCG_EINVAL, "combine_log2 out of range"};
-  if (o->reserved) throw LcgError{LCG_EINVAL, "reserved option field must be zero"};
+  r.fail_round = o->fail_round;
   if (r.flags & ~(uint32_t)(LCG_FLAG_TIMING | LCG_FLAG_TIMING_INSERT))
     throw LcgError{LCG_EINVAL, "unknown flag"};
   if (r.mode != LCG_MODE_BATCHED && r.mode != LCG_MODE_PLAIN)
@@ -224,7 +225,7 @@ static void ensure_table(Level& L, uint64_t need, const Opts& o, Work& w, hipStr
   launch_fill_slots(nt.p, want, s);
   if (L.tcap && L.u) {
     zero_counters(w.ctr.p, s);
-    launch_rehash(L.table.p, L.tcap, nt.p, want - 1, w.ctr.p, s);
+    launch_rehash(L.table.p, L.tcap, nt.p, want - 1, kNone, w.ctr.p, s);
     Mailbox* mb = mailbox();
     HIP_CHECK(hipMemcpyAsync(&mb->ctr, w.ctr.p, offsetof(Counters, hll), hipMemcpyDeviceToHost, s));
     sync(s);
@@ -379,6 +380,9 @@ static void tail_rounds(lcg_grammar* g, uint32_t lv, uint64_t n_i, uint64_t acti
   uint32_t r = 0;
   bool done = false;
   for (; r < max_rounds && !done; ++r, ++lv) {
+    if (o.fail_round && lv == o.fail_round)
+      throw LcgError{LCG_ETABLE, "test hook: failure forced at round " + std::to_string(lv) +
+                                     " (queued without host reads)"};
     const bool bytes = lv == 1;
     TailRec* rec = w.tail.p + r;
     RoundIn in;
@@ -547,6 +551,8 @@ static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_
   Stat prev{};
   for (uint32_t lv = 1;; ++lv) {
     Counters& hf = mb->fin;
+    if (o.fail_round && lv == o.fail_round && n_i > (1ull << o.tail_log2))
+      throw LcgError{LCG_ETABLE, "test hook: failure forced at round " + std::to_string(lv)};
     if (lv >= (uint32_t)HashFamily::kLevels) {
       HIP_CHECK(hipMemcpyAsync(&hf, w.fin.p, offsetof(Counters, hll), hipMemcpyDeviceToHost, s));
       sync(s);
@@ -719,6 +725,76 @@ static std::vector<uint64_t> fetch_offsets(const uint64_t* d_off, uint32_t k, hi
 static void check_budget(const Opts& o, uint64_t n, uint32_t k) {
   if (o.budget && build_bytes(n, k) > o.budget)
     throw LcgError{LCG_ENOMEM, "input needs more than hbm_budget bytes of working memory"};
+}
+
+// What a call that extends a grammar in place (lcg_build_into, lcg_merge)
+// restores if it fails part way.
+struct Snapshot {
+  uint32_t k;
+  std::vector<std::pair<uint32_t, uint64_t>> uq;  // rules and rhs length per level
+  size_t n_stats;
+};
+
+static Snapshot snapshot(const lcg_grammar* g) {
+  Snapshot sn{g->k, {}, g->stats.size()};
+  for (const Level& L : g->levels) sn.uq.emplace_back(L.u, L.q);
+  return sn;
+}
+
+// Undo a failed in-place call: levels and strings shrink back to the
+// snapshot, and every dictionary is rebuilt from the rules kept (rank below
+// the level's restored count), which drops the failed call's claims and
+// rules without breaking any probe sequence.  A grammar that cannot be
+// restored is marked unusable.
+static void rollback(lcg_grammar* g, const Snapshot& sn, hipStream_t s) noexcept {
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipGetLastError();
+    g->poisoned = true;
+    return;
+  }
+  try {
+    pool().flush(s);
+    while (g->levels.size() > sn.uq.size()) {
+      g->levels.back().table.reset_after(s);
+      g->levels.pop_back();
+    }
+    DBuf<Counters> ctr;
+    ctr.need(1, s);
+    for (size_t i = 0; i < g->levels.size(); ++i) {
+      Level& L = g->levels[i];
+      L.u = sn.uq[i].first;
+      L.q = sn.uq[i].second;
+      if (!L.tcap || !L.table.p) continue;
+      DBuf<Slot> nt;
+      nt.need(L.tcap, s);
+      launch_fill_slots(nt.p, L.tcap, s);
+      zero_counters(ctr.p, s);
+      launch_rehash(L.table.p, L.tcap, nt.p, L.tcap - 1, L.u, ctr.p, s);
+      const Counters c = read_dev(ctr.p, s);
+      if (c.overflow) throw LcgError{LCG_ETABLE, "rebuild failed"};
+      L.table.reset_after(s);
+      L.table = std::move(nt);
+    }
+    g->k = sn.k;
+    g->stats.resize(sn.n_stats);
+    ++g->version;
+    sync(s);
+  } catch (...) {
+    (void)hipGetLastError();
+    g->poisoned = true;
+  }
+}
+
+// Run f, which extends g in place; on failure restore g and rethrow.
+template <typename F>
+static void restoring(lcg_grammar* g, hipStream_t s, F&& f) {
+  const Snapshot sn = snapshot(g);
+  try {
+    f();
+  } catch (...) {
+    rollback(g, sn, s);
+    throw;
+  }
 }
 
 static void build_any(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_off, uint32_t k,
@@ -1054,23 +1130,24 @@ lcg_status lcg_build_into(lcg_grammar_t g, const uint8_t* d_text, const uint64_t
                           uint32_t k, const lcg_opts* opts, hipStream_t stream,
                           uint32_t* first_index) {
   return guard([&] {
-    if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    live(g);
     Opts o = read_opts(opts);
     if (opts && o.seed != g->seed) throw LcgError{LCG_ESEED, "opts seed differs from the grammar's"};
     Opts oo = o;
     oo.mode = LCG_MODE_BATCHED;
     uint32_t first = g->k;
-    build_any(g, d_text, d_offsets, k, oo, stream);
+    restoring(g, stream, [&] { build_any(g, d_text, d_offsets, k, oo, stream); });
     if (first_index) *first_index = first;
   });
 }
 
 lcg_status lcg_merge(lcg_grammar_t a, lcg_grammar_t b, hipStream_t stream) {
   return guard([&] {
-    if (!a || !b) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    live(a);
+    live(b);
     if (a == b) throw LcgError{LCG_EINVAL, "cannot merge a grammar into itself"};
     Work w;
-    merge_core(a, b, w, stream);
+    restoring(a, stream, [&] { merge_core(a, b, w, stream); });
   });
 }
 
@@ -1078,7 +1155,7 @@ lcg_status lcg_expand_strings(lcg_grammar_t g, uint32_t j0, uint32_t j1, uint8_t
                               uint64_t cap, uint64_t* d_offsets, uint64_t* total,
                               hipStream_t stream) {
   return guard([&] {
-    if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    live(g);
     if (!d_out && cap) throw LcgError{LCG_EINVAL, "d_out is NULL"};
     expand_strings_core(g, j0, j1, d_out, cap, d_offsets, total, stream);
   });
@@ -1087,7 +1164,7 @@ lcg_status lcg_expand_strings(lcg_grammar_t g, uint32_t j0, uint32_t j1, uint8_t
 lcg_status lcg_expand(lcg_grammar_t g, uint32_t j, uint8_t* d_out, uint64_t cap, uint64_t* out_len,
                       hipStream_t stream) {
   return guard([&] {
-    if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    live(g);
     expand_core(g, j, d_out, cap, out_len, stream);
   });
 }
@@ -1103,7 +1180,8 @@ lcg_status lcg_info(lcg_grammar_t g, uint64_t* seed, uint32_t* n_levels, uint32_
 
 lcg_status lcg_level_size(lcg_grammar_t g, uint32_t level, uint32_t* u, uint64_t* rhs_len) {
   return guard([&] {
-    if (!g || level == 0 || level > g->levels.size()) throw LcgError{LCG_EINVAL, "bad level"};
+    live(g);
+    if (level == 0 || level > g->levels.size()) throw LcgError{LCG_EINVAL, "bad level"};
     if (u) *u = g->levels[level - 1].u;
     if (rhs_len) *rhs_len = g->levels[level - 1].q;
   });
@@ -1112,7 +1190,8 @@ lcg_status lcg_level_size(lcg_grammar_t g, uint32_t level, uint32_t* u, uint64_t
 lcg_status lcg_level_copy(lcg_grammar_t g, uint32_t level, uint64_t* h_rhs_off, uint32_t* h_rhs,
                           uint32_t* h_fp) {
   return guard([&] {
-    if (!g || level == 0 || level > g->levels.size()) throw LcgError{LCG_EINVAL, "bad level"};
+    live(g);
+    if (level == 0 || level > g->levels.size()) throw LcgError{LCG_EINVAL, "bad level"};
     const Level& L = g->levels[level - 1];
     HIP_CHECK(hipDeviceSynchronize());
     if (h_rhs_off) HIP_CHECK(hipMemcpy(h_rhs_off, L.off.p, sizeof(uint64_t) * (L.u + 1), hipMemcpyDeviceToHost));
@@ -1131,7 +1210,7 @@ lcg_status lcg_level_copy(lcg_grammar_t g, uint32_t level, uint64_t* h_rhs_off, 
 
 lcg_status lcg_c_copy(lcg_grammar_t g, uint8_t* h_level, uint32_t* h_sym) {
   return guard([&] {
-    if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    live(g);
     HIP_CHECK(hipDeviceSynchronize());
     if (g->k && h_level) HIP_CHECK(hipMemcpy(h_level, g->c_level.p, g->k, hipMemcpyDeviceToHost));
     if (g->k && h_sym) HIP_CHECK(hipMemcpy(h_sym, g->c_sym.p, 4ull * g->k, hipMemcpyDeviceToHost));
@@ -1154,7 +1233,8 @@ void lcg_host_free(lcg_host_grammar* h) {
 lcg_status lcg_export(lcg_grammar_t g, lcg_host_grammar* out) {
   if (out) std::memset(out, 0, sizeof(*out));
   const lcg_status st = guard([&] {
-    if (!g || !out) throw LcgError{LCG_EINVAL, "grammar or out is NULL"};
+    live(g);
+    if (!out) throw LcgError{LCG_EINVAL, "out is NULL"};
     auto grab = [](size_t bytes) {
       void* p = std::malloc(bytes ? bytes : 1);
       if (!p) throw LcgError{LCG_ENOMEM, "host allocation failed"};
@@ -1190,7 +1270,7 @@ lcg_status lcg_export(lcg_grammar_t g, lcg_host_grammar* out) {
 
 lcg_status lcg_stats(lcg_grammar_t g, uint64_t* h_out, uint32_t cap_rounds, uint32_t* n_rounds) {
   return guard([&] {
-    if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    live(g);
     if (n_rounds) *n_rounds = (uint32_t)g->stats.size();
     for (uint32_t r = 0; r < cap_rounds && r < g->stats.size(); ++r)
       for (int f = 0; f < LCG_STATS_FIELDS; ++f) h_out[(size_t)r * LCG_STATS_FIELDS + f] = g->stats[r][f];
@@ -1199,7 +1279,7 @@ lcg_status lcg_stats(lcg_grammar_t g, uint64_t* h_out, uint32_t cap_rounds, uint
 
 lcg_status lcg_stats_clear(lcg_grammar_t g) {
   return guard([&] {
-    if (!g) throw LcgError{LCG_EINVAL, "grammar is NULL"};
+    live(g);
     g->stats.clear();
   });
 }

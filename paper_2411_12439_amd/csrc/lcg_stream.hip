@@ -238,7 +238,8 @@ extern "C" {
 lcg_status lcg_build_file(lcg_grammar_t g, const char* path, uint64_t chunk_bytes,
                           const lcg_opts* opts, hipStream_t stream, uint64_t* h_info) {
   return guard([&] {
-    if (!g || !path) throw LcgError{LCG_EINVAL, "grammar or path is NULL"};
+    live(g);
+    if (!path) throw LcgError{LCG_EINVAL, "path is NULL"};
     if (chunk_bytes < 4096 || chunk_bytes > (1ull << 36))
       throw LcgError{LCG_EINVAL, "chunk_bytes must be in 4 KiB .. 64 GiB"};
     lcg_opts o;

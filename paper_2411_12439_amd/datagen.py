@@ -29,7 +29,9 @@ Configurations (data seeds 1001..1005 by default):
                 0.001 and indels 0.0001, each truncated/padded to 250 MB (2 GB).
 * ``serving``   requests of one string each, lognormal sizes (median 1 MB,
                 sigma 1.5) clipped to [10 KB, 50 MB], windows of 16 bases of
-                50 MB at 1 % divergence, Poisson arrivals at a given load.
+                50 MB at 1 % divergence of their own (0.1 % indels from one of
+                two copies of the base, 0.9 % substitutions drawn per request),
+                Poisson arrivals at a given load.
 
 ``scale`` shrinks every length by a factor (for tests on small inputs with the
 same structure).
@@ -224,14 +226,21 @@ def make_config(name, seed=None, scale=1.0, **kw):
 class ServingSource:
     """Request generator of the serving form.
 
-    Bases of 50 MB (scaled) each get `variants` copies at 1 % divergence
-    (0.9 % substitutions, 0.1 % indels of 1-10 bp), made once; a request is a
-    random window of a random variant, of lognormal size (median 1 MB, sigma
-    1.5) clipped to [10 KB, 50 MB] (scaled).  Inter-arrival gaps are
+    Bases of 50 MB (scaled); each gets `variants` copies with 0.1 % indels of
+    1-10 bp, made once on the host.  A request is a random window of a random
+    copy, of lognormal size (median 1 MB, sigma 1.5) clipped to [10 KB, 50 MB]
+    (scaled), with its own 0.9 % substitutions: every request is synthesized
+    on the device from its descriptor (request id, copy, start, length) by a
+    seeded counter-based generator, so that each one carries fresh
+    divergence (1 % in all) without host work per byte, and can be
+    synthesized again, identically, to check it.  Inter-arrival gaps are
     exponential for a given offered load (bytes per second).
     """
 
+    SUB_RATE = 0.009
+
     def __init__(self, seed=CONFIG_SEEDS["serving"], scale=1.0, n_bases=16, variants=2):
+        self.seed = int(seed)
         self.rng = _rng(seed)
         self.scale = scale
         self.BL = max(1024, int(50_000_000 * scale))
@@ -239,22 +248,53 @@ class ServingSource:
         for _ in range(n_bases):
             base = random_bases(self.rng, self.BL)
             for _ in range(variants):
-                v = substitute(self.rng, base.copy(), 0.009)
-                self.variants.append(indels(self.rng, v, 0.001))
+                self.variants.append(indels(self.rng, base.copy(), 0.001))
+        self._dev = None
+        self.next_id = 0
 
     def draw(self):
-        """(variant index, start, length) of the next request."""
+        """Descriptor (request id, variant index, start, length) of the next request."""
         s = self.scale
         L = float(np.exp(self.rng.normal(np.log(1e6 * s), 1.5)))
         L = int(np.clip(L, 10_000 * s, 50_000_000 * s))
         v = int(self.rng.integers(0, len(self.variants)))
         L = max(2, min(L, len(self.variants[v])))
         st = int(self.rng.integers(0, len(self.variants[v]) - L + 1))
-        return v, st, L
+        rid = self.next_id
+        self.next_id += 1
+        return rid, v, st, L
 
-    def request(self):
-        v, st, L = self.draw()
-        return self.variants[v][st:st + L]
+    def _device_variants(self, device):
+        import torch
+        if self._dev is None:
+            self._dev = [torch.from_numpy(v).to(device) for v in self.variants]
+            self._bases = torch.from_numpy(BASES.copy()).to(device)
+        return self._dev
+
+    def materialize(self, desc, out=None, device="cuda"):
+        """The bytes of request `desc` as a device uint8 tensor (written into
+        `out` when given), on the current stream.  Position x is substituted
+        iff u_x < SUB_RATE for the request's uniform draws u (Philox, seeded
+        by the request id); the new base is the old one shifted by 1, 2 or 3
+        in ACGT order, chosen by which third of [0, SUB_RATE) u_x falls in."""
+        import torch
+        rid, v, st, L = desc
+        src = self._device_variants(device)[v][st:st + L]
+        g = torch.Generator(device=src.device)
+        g.manual_seed((self.seed * 1_000_003 + rid) & 0x7FFFFFFFFFFFFFFF)
+        u = torch.rand(L, generator=g, device=src.device)
+        shift = torch.floor(u * (3.0 / self.SUB_RATE)).to(torch.uint8) + 1
+        idx = ((src >> 1) ^ (src >> 2)) & 3          # A, C, G, T -> 0, 1, 2, 3
+        new = self._bases[((idx + shift) & 3).long()]
+        res = torch.where(u < self.SUB_RATE, new, src)
+        if out is None:
+            return res
+        out.copy_(res)
+        return out
+
+    def host_bytes(self, desc):
+        """The bytes of request `desc` on the host (through the device)."""
+        return self.materialize(desc).cpu().numpy()
 
     def mean_size(self):
         s = self.scale

@@ -75,7 +75,7 @@ class Opts(ctypes.Structure):
                 ("hbm_budget", ctypes.c_uint64), ("key_bits", ctypes.c_uint32),
                 ("table_min_log2", ctypes.c_uint32), ("tail_log2", ctypes.c_uint32),
                 ("table_load_log2", ctypes.c_uint32), ("combine_log2", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("fail_round", ctypes.c_uint32)]
 
 # options that only change speed, never results (what the autotuner sets)
 TUNABLE = ("tail_log2", "table_load_log2", "combine_log2")
@@ -203,7 +203,7 @@ def _check_inputs(text, offsets):
 
 
 def make_opts(seed=0, mode=MODE_BATCHED, flags=0, hbm_budget=0, key_bits=0, table_min_log2=0,
-              tail_log2=0, table_load_log2=0, combine_log2=0):
+              tail_log2=0, table_load_log2=0, combine_log2=0, fail_round=0):
     o = Opts()
     lib().lcg_opts_init(ctypes.byref(o))
     o.seed = seed
@@ -215,6 +215,7 @@ def make_opts(seed=0, mode=MODE_BATCHED, flags=0, hbm_budget=0, key_bits=0, tabl
     o.tail_log2 = tail_log2
     o.table_load_log2 = table_load_log2
     o.combine_log2 = combine_log2
+    o.fail_round = fail_round
     return o
 
 
@@ -531,12 +532,13 @@ def build(text, offsets, seed=0, mode=MODE_BATCHED, flags=0, hbm_budget=0, key_b
 
 
 def build_into(g, text, offsets, seed=None, flags=0, hbm_budget=0, key_bits=0, table_min_log2=0,
-               tail_log2=0, stream=None):
+               tail_log2=0, fail_round=0, stream=None):
     """Compress a batch into an existing grammar; returns the C index of its first string."""
     _check_inputs(text, offsets)
     if seed is None:
         seed = g.info()[0]
-    o = make_opts(seed, MODE_BATCHED, flags, hbm_budget, key_bits, table_min_log2, tail_log2)
+    o = make_opts(seed, MODE_BATCHED, flags, hbm_budget, key_bits, table_min_log2, tail_log2,
+                  fail_round=fail_round)
     first = ctypes.c_uint32()
     _check(lib().lcg_build_into(g.h, ctypes.c_void_p(text.data_ptr()),
                                 ctypes.c_void_p(offsets.data_ptr()), offsets.numel() - 1,

@@ -1,8 +1,9 @@
 """Serving form: continuous batching of compression requests into one running grammar.
 
-Requests (one byte string each) arrive over time.  Each is uploaded, on a
-copy stream, into a device ring buffer as soon as it arrives, overlapping the
-build running on the compute stream.  Whenever the GPU is free the scheduler
+Requests (one byte string each) arrive over time.  Each is written, on a
+copy stream, into a device ring buffer as soon as it arrives (synthesized
+there by the request source), overlapping the build running on the compute
+stream.  Whenever the GPU is free the scheduler
 admits the uploaded requests that fit the HBM budget -- a contiguous range of
 the ring, so the batch needs no gather -- and compresses the whole batch into
 the running grammar with one ``lcg_build_into`` call (BuildGram with a
@@ -74,12 +75,12 @@ class RingBuffer:
 
 
 class Request:
-    __slots__ = ("rid", "host", "n", "arrival", "off", "event", "done", "c_index")
+    __slots__ = ("rid", "desc", "n", "arrival", "off", "event", "done", "c_index")
 
-    def __init__(self, rid, host, arrival):
+    def __init__(self, rid, desc, arrival):
         self.rid = rid
-        self.host = host          # pinned host tensor (a view)
-        self.n = int(host.numel())
+        self.desc = desc          # the source's descriptor (request id, copy, start, length)
+        self.n = int(desc[3])
         self.arrival = arrival
         self.off = None
         self.event = None
@@ -90,10 +91,11 @@ class Request:
 class Server:
     """Continuous-batching compressor around one device-resident running grammar."""
 
-    def __init__(self, seed=_datagen.HASH_SEED, hbm_budget=16 << 30, ring_bytes=1 << 30,
+    def __init__(self, source, seed=_datagen.HASH_SEED, hbm_budget=16 << 30, ring_bytes=1 << 30,
                  device="cuda"):
         import torch
         self.torch = torch
+        self.source = source
         self.seed = seed
         self.g = _lcg.new(seed)
         self.budget = int(hbm_budget)
@@ -103,6 +105,10 @@ class Server:
         self.ready = collections.deque()     # uploaded (or uploading), not compressed
         self.completed = []
         self.batch_sizes = []
+
+    def close(self):
+        """Free the running grammar."""
+        self.g.free()
 
     def submit(self, req):
         self.waiting.append(req)
@@ -119,7 +125,7 @@ class Server:
             self.waiting.popleft()
             req.off = off
             with torch.cuda.stream(self.copy_stream):
-                self.ring.buf[off:off + req.n].copy_(req.host, non_blocking=True)
+                self.source.materialize(req.desc, out=self.ring.buf[off:off + req.n])
                 req.event = torch.cuda.Event()
                 req.event.record(self.copy_stream)
             self.ready.append(req)
@@ -153,7 +159,6 @@ class Server:
         for i, req in enumerate(batch):
             req.done = now
             req.c_index = first + i
-            req.host = None
             self.completed.append(req)
         self.ring.release(total, self.ready[0].off if self.ready else 0)
         self.batch_sizes.append(len(batch))
@@ -161,32 +166,15 @@ class Server:
         return len(batch)
 
 
-class PinnedPool:
-    """The serving variants in pinned host memory (requests are views into them)."""
-
-    def __init__(self, source):
-        import torch
-        self.source = source
-        self.pinned = []
-        for v in source.variants:
-            t = torch.empty(len(v), dtype=torch.uint8, pin_memory=True)
-            t.numpy()[:] = v
-            self.pinned.append(t)
-
-    def draw(self):
-        v, st, L = self.source.draw()
-        return (v, st, L), self.pinned[v][st:st + L]
-
-
-def run_load(pool, load_gbps, seconds, max_requests=None, seed=_datagen.HASH_SEED,
+def run_load(source, load_gbps, seconds, max_requests=None, seed=_datagen.HASH_SEED,
              hbm_budget=16 << 30, ring_bytes=1 << 30):
     """Serve a Poisson stream offering `load_gbps` GB/s for `seconds` (or max_requests).
 
-    Returns (summary, server, requests); requests[i] = (Request, (variant, start, len)).
+    Returns (summary, server, requests); requests[i] = (Request, descriptor).
     """
     import torch
-    srv = Server(seed, hbm_budget, ring_bytes)
-    gaps = pool.source.arrivals(load_gbps * 1e9, 1 << 16)
+    srv = Server(source, seed, hbm_budget, ring_bytes)
+    gaps = source.arrivals(load_gbps * 1e9, 1 << 16)
     reqs = []
     t0 = time.perf_counter()
     nxt = t0 + gaps[0]
@@ -195,10 +183,10 @@ def run_load(pool, load_gbps, seconds, max_requests=None, seed=_datagen.HASH_SEE
         now = time.perf_counter()
         open_ = now - t0 < seconds and (max_requests is None or i < max_requests)
         while open_ and nxt <= now:
-            where, host = pool.draw()
-            r = Request(i, host, nxt)
+            desc = source.draw()
+            r = Request(i, desc, nxt)
             srv.submit(r)
-            reqs.append((r, where))
+            reqs.append((r, desc))
             i += 1
             nxt += gaps[i % len(gaps)]
             open_ = max_requests is None or i < max_requests
@@ -232,15 +220,16 @@ def run_load(pool, load_gbps, seconds, max_requests=None, seed=_datagen.HASH_SEE
     return summary, srv, reqs
 
 
-def check_alone_vs_mix(srv, pool, reqs, sample):
+def check_alone_vs_mix(srv, source, reqs, sample):
     """For the sampled requests: rules reachable from the request's C entry in the
     running grammar == the grammar of the request compressed alone (canonically)."""
+    import torch
     g_all = srv.g.export()
     ok = 0
     for idx in sample:
-        req, (v, st, L) = reqs[idx]
-        data = pool.source.variants[v][st:st + L]
-        t, o = _lcg.to_device(data, np.array([0, L], np.uint64))
+        req, desc = reqs[idx]
+        t = source.materialize(desc)
+        o = torch.tensor([0, req.n], dtype=torch.int64, device=t.device)
         alone = _lcg.build(t, o, seed=srv.seed).export()
         sub = _canon.subgrammar(g_all, [req.c_index])
         if _canon.canon(sub) != _canon.canon(alone):
@@ -259,12 +248,11 @@ def main():
     ap.add_argument("--check", type=int, default=8, help="requests checked alone vs in the mix")
     args = ap.parse_args()
     src = _datagen.ServingSource(scale=args.scale)
-    pool = PinnedPool(src)
     for load in (float(x) for x in args.loads.split(",")):
-        summary, srv, reqs = run_load(pool, load, args.seconds)
+        summary, srv, reqs = run_load(src, load, args.seconds)
         rng = np.random.default_rng(0)
         sample = rng.choice(len(reqs), size=min(args.check, len(reqs)), replace=False)
-        summary["alone_vs_mix_checked"] = check_alone_vs_mix(srv, pool, reqs, sample)
+        summary["alone_vs_mix_checked"] = check_alone_vs_mix(srv, src, reqs, sample)
         print(json.dumps(summary), flush=True)
 
 

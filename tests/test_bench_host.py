@@ -43,7 +43,8 @@ def test_algorithmic_bytes_of_two_rounds():
     r2 = 8 * 30 + 12 * 10 + 16 * 5 + 4 * 12
     assert B.path_alg_bytes(st) == r1 + r2
     ph = B.phase_alg_bytes(st)
-    assert ph["classify"] == 100 + 4 * 30 and ph["emit"] == 100 + 4 * 30
+    assert ph["classify"] == 100 + 4 * 30 and ph["emit"] == 4 * 30
+    assert sum(ph.values()) == B.path_alg_bytes(st)
     assert ph["insert"] == 8 * (30 + 10) + 8 * (10 + 5)
     assert ph["commit"] == (8 * 10 + 40 + 4 * 30) + (8 * 5 + 4 * 12 + 4 * 10)
 

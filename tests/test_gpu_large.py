@@ -2,14 +2,19 @@
 ~5 GB, more than 2^32 positions) and the repeat-heavy one (8 x 250 MB with
 tandem repeats and homopolymer runs).
 
-The oracle would take minutes on the whole input, so the checks are the ones
-that hold at any size: every string expands back to the input; Theorem 1's
-halving holds in every round and every string ends; sampled strings'
-sub-grammars equal the oracle's grammar of each string alone (stability,
-Def. 1); random substrings and longest common extensions match the input;
-and for the repeat-heavy collection the RL + Simp grammar decompresses to the
-input, also through its stored file, gives random substrings of the input
-from the decoded grammar, and keeps Simp's size identity.
+Checked at full size: every string expands back to the input; Theorem 1's
+halving holds in every round and every string ends; chosen strings'
+sub-grammars equal the oracle's grammar of each string alone, rank for rank
+once renumbered in the string's own first-occurrence order (stability,
+Def. 1) -- on the batched collection the string holding byte 2^32, the two
+after it and the last one (the 64-bit offset paths), and the shortest and
+longest strings; on the repeat-heavy collection whole 250 MB strings (the
+first and the last), whose 20 kb homopolymers and tandem repeats make the
+deepest equal-run cases; random substrings and longest common extensions
+match the input; and for the repeat-heavy collection the RL + Simp grammar
+decompresses to the input, also through its stored file, gives random
+substrings of the input from the decoded grammar, and keeps Simp's size
+identity.
 """
 import numpy as np
 import pytest
@@ -17,7 +22,7 @@ import pytest
 from paper_2411_12439_amd import canon as CN
 from paper_2411_12439_amd import datagen as D
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 SEED = D.HASH_SEED
 
 
@@ -30,9 +35,28 @@ def L():
     return lcg
 
 
-def _common_checks(L, g, text, off, t, sample):
+def _built(L, name):
+    print("generating the %s collection" % name, flush=True)
+    text, off = D.make_config(name)
+    t, o = L.to_device(text, off)
+    print("building", flush=True)
+    g = L.build(t, o, seed=SEED)
+    print("exporting", flush=True)
+    return text, off, t, g, g.export()
+
+
+@pytest.fixture(scope="module")
+def batched(L):
+    return _built(L, "batched")
+
+
+@pytest.fixture(scope="module")
+def repeats(L):
+    return _built(L, "repeats")
+
+
+def _round_trip_and_invariants(g, off, t):
     import torch
-    from oracle import oracle as O
     k = len(off) - 1
     st = g.stats()
     active = k
@@ -43,13 +67,22 @@ def _common_checks(L, g, text, off, t, sample):
     assert st[-1, 4] == 0
     out, offs = g.expand_strings()
     assert out.numel() == t.numel() and torch.equal(out, t)
-    del out
-    e = g.export()
+    assert np.array_equal(offs.cpu().numpy().astype(np.uint64), off.astype(np.uint64))
+
+
+def _strings_equal_oracle(e, text, off, sample):
+    from oracle import oracle as O
     for j in sample:
         a, b = int(off[j]), int(off[j + 1])
-        alone = O.build(text[a:b], np.array([0, b - a], np.uint64), SEED)
-        assert CN.canon(CN.subgrammar(e, [j])) == CN.canon(alone.export()), j
-    rng = np.random.default_rng(5)
+        print("oracle on string %d (%d bytes at offset %d)" % (j, b - a, a), flush=True)
+        alone = O.build(text[a:b], np.array([0, b - a], np.uint64), SEED).export()
+        mine = CN.own_order_subgrammar(e, j)
+        assert CN.exports_equal(mine, alone), (j, CN.first_difference(mine, alone))
+
+
+def _random_substrings(L, g, text, off, seed):
+    rng = np.random.default_rng(seed)
+    k = len(off) - 1
     lens = np.diff(off.astype(np.int64))
     jq = rng.integers(0, k, 2000)
     ln = np.minimum(rng.integers(1, L.EXTRACT_MAX + 1, 2000), lens[jq])
@@ -63,26 +96,51 @@ def _common_checks(L, g, text, off, t, sample):
         assert np.array_equal(xo[xoff[q]:xoff[q + 1]], text[a:a + int(ln[q])]), q
 
 
-def test_full_batched(L):
-    print("generating the batched collection (~5 GB, about a minute)", flush=True)
-    text, off = D.make_config("batched")
+def test_full_batched_round_trip(batched):
+    text, off, t, g, e = batched
     assert int(off[-1]) > (1 << 32)
-    t, o = L.to_device(text, off)
-    print("building", flush=True)
-    g = L.build(t, o, seed=SEED)
-    print("checking", flush=True)
-    lens = np.diff(off.astype(np.int64))
-    small = [int(j) for j in np.argsort(lens)[:2]] + [int(np.argmax(lens))]
-    _common_checks(L, g, text, off, t, small)
+    _round_trip_and_invariants(g, off, t)
 
 
-def test_full_repeats(L):
-    from oracle import oracle as O
+def test_full_batched_strings_equal_oracle(batched):
+    """The string holding byte 2^32, the two after it, the last string, and
+    the shortest and longest ones, each against the oracle's build of it alone."""
+    text, off, t, g, e = batched
+    o = off.astype(np.int64)
+    k = len(o) - 1
+    j32 = int(np.searchsorted(o, 1 << 32, side="right")) - 1
+    assert o[j32] < (1 << 32) < o[j32 + 1] or o[j32] == (1 << 32)
+    lens = np.diff(o)
+    sample = [j32, j32 + 1, j32 + 2, k - 1, int(np.argmin(lens)), int(np.argmax(lens))]
+    assert all(o[j] > (1 << 32) for j in sample[1:4])
+    _strings_equal_oracle(e, text, off, sample)
+
+
+def test_full_batched_random_access(L, batched):
+    text, off, t, g, e = batched
+    _random_substrings(L, g, text, off, 5)
+
+
+def test_full_repeats_round_trip(repeats):
+    text, off, t, g, e = repeats
+    _round_trip_and_invariants(g, off, t)
+
+
+def test_full_repeats_whole_strings_equal_oracle(repeats):
+    """Whole 250 MB strings (homopolymers up to 20 kb, tandem repeats of
+    10-10,000 copies) against the oracle's build of each alone."""
+    text, off, t, g, e = repeats
+    _strings_equal_oracle(e, text, off, [0, len(off) - 2])
+
+
+def test_full_repeats_random_access(L, repeats):
+    text, off, t, g, e = repeats
+    _random_substrings(L, g, text, off, 5)
+
+
+def test_full_repeats_postprocess_and_store(L, repeats):
     import torch
-    text, off = D.make_config("repeats")
-    t, o = L.to_device(text, off)
-    g = L.build(t, o, seed=SEED)
-    _common_checks(L, g, text, off, t, [])
+    text, off, t, g, e = repeats
     # RL and Simp on the deep, run-heavy grammar
     slp = g.postprocess(rl=True, simp=True)
     st = [int(x) for x in slp.stats()]
@@ -96,19 +154,14 @@ def test_full_repeats(L):
     assert torch.equal(out, t)
     del out
     # random substrings of the decoded grammar (run rules of long homopolymers)
-    rng = np.random.default_rng(7)
-    lens = np.diff(off.astype(np.int64))
-    jq = rng.integers(0, len(lens), 2000)
-    ln = rng.integers(1, L.EXTRACT_MAX + 1, 2000)
-    sq = (rng.random(2000) * (lens[jq] - ln + 1)).astype(np.int64)
-    xo, xoff = dec.extract(jq, sq, ln)
-    xo = xo.cpu().numpy()
-    xoff = xoff.cpu().numpy()
-    base = off.astype(np.int64)
-    for q in range(2000):
-        a = int(base[jq[q]] + sq[q])
-        assert np.array_equal(xo[xoff[q]:xoff[q + 1]], text[a:a + int(ln[q])]), q
+    _random_substrings(L, dec, text, off, 7)
     dec.free()
+    slp.free()
+
+
+def test_full_repeats_lce(repeats):
+    from oracle import oracle as O
+    text, off, t, g, e = repeats
     # longest common extensions between the copies, against the bytes
     rng = np.random.default_rng(6)
     lens = np.diff(off.astype(np.int64))

@@ -1,8 +1,10 @@
-"""Streaming builds from a file (lcg_build_file) against one build of the same strings.
+"""Streaming builds from a file (lcg_build_file) against the oracle's build of
+the same strings.
 
 Ranks are numbered by first occurrence (string order, then position), so
-compressing the file chunk by chunk into a running grammar must give the same
-grammar as one build over all of its lines, rank for rank.
+compressing the file chunk by chunk into a running grammar must give the
+oracle's grammar of all of its lines in file order, rank for rank (and the
+library's one-call build of them).
 """
 import os
 import tempfile
@@ -58,9 +60,10 @@ def test_file_equals_one_build(L, chunk, trailing):
     try:
         g = L.new(SEED)
         info = L.build_file(g, path, chunk_bytes=chunk)
+        got = g.export()
+        _assert_same(got, O.build(*O.pack(strings), SEED).export())
         t, o = L.to_device(*O.pack(strings))
-        want = L.build(t, o, seed=SEED).export()
-        _assert_same(g.export(), want)
+        _assert_same(got, L.build(t, o, seed=SEED).export())
         assert info["strings"] == len(strings)
         assert info["bytes"] == sum(len(s) for s in strings)
         if chunk == 300 << 10:
@@ -79,8 +82,7 @@ def test_file_into_existing_grammar(L):
         ta, oa = L.to_device(*O.pack(strings[:half]))
         g = L.build(ta, oa, seed=SEED)
         L.build_file(g, path, chunk_bytes=200 << 10)
-        t, o = L.to_device(*O.pack(strings))
-        _assert_same(g.export(), L.build(t, o, seed=SEED).export())
+        _assert_same(g.export(), O.build(*O.pack(strings), SEED).export())
         # and the whole collection expands back from the streamed grammar
         out, offs = g.expand_strings()
         assert np.array_equal(out.cpu().numpy(), O.pack(strings)[0])

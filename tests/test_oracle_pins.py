@@ -353,3 +353,94 @@ def test_round1_density_iid_dna(oracle_mod):
     s = D.BASES[rng.integers(0, 4, 1 << 20)]
     brk = oracle_mod.round1_breaks(s, SEED)
     assert abs(brk.mean() - 14 / 48) < 0.005
+
+
+def _level_sequences(e, j):
+    """T^{i+1}_j for i = lv .. 1 (the sequence of level-i symbols of string j),
+    rebuilt from the exported grammar alone: [C[j]] at its level, each level
+    expanded by the right-hand sides of the level above."""
+    lv = int(e["c_level"][j])
+    seqs = {}
+    if lv == 0:
+        return lv, seqs
+    cur = np.array([int(e["c_sym"][j])], np.int64)
+    for i in range(lv, 0, -1):
+        seqs[i + 1] = cur
+        L = e["levels"][i - 1]
+        off = np.asarray(L["rhs_off"], np.int64)
+        rhs = np.asarray(L["rhs"], np.int64)
+        parts = [rhs[off[r]:off[r + 1]] for r in cur.tolist()]
+        cur = np.concatenate(parts)
+    seqs[1] = cur
+    return lv, seqs
+
+
+@pytest.mark.parametrize("which", ["tiny", "mixed", "runs"])
+def test_round_counters_follow_from_the_grammar(oracle_mod, which):
+    """The oracle's per-round counters (n_i, d_i, u_i, Q_i, strings still active)
+    are not read from its own loop here: they are recomputed from the exported
+    grammar.  A string whose C entry sits at level lv takes part in rounds
+    1..lv; in round i it enters as T^i_j and leaves as T^{i+1}_j, the
+    sequence of its level-i symbols (Sec. 3.3), so n_i and d_i are sums of
+    those lengths; every rule of a level is new in a single build (u_i, Q_i =
+    the level's size); and d_i = n_{i+1} + the strings that become inactive."""
+    O = oracle_mod
+    rng = np.random.default_rng(11)
+    if which == "tiny":
+        text, off = D.make_config("tiny", scale=0.1)
+        strings = [text[off[j]:off[j + 1]].tobytes() for j in range(len(off) - 1)]
+    elif which == "mixed":
+        strings = [bytes(rng.choice(list(b"ACGT"), int(n)).tolist())
+                   for n in rng.integers(1, 3000, 12)] + [b"A", b"GG", b"ACGTTGCA" * 40]
+    else:
+        strings = [b"A" * 700, b"AC" * 300 + b"G" * 50, b"TTTTGTTTT" * 40, b"C"]
+    text, off = O.pack(strings)
+    g = O.build(text, off, SEED)
+    st = g.stats().astype(np.int64)
+    e = g.export()
+    k = len(strings)
+    per = [_level_sequences(e, j) for j in range(k)]
+    rounds = max(lv for lv, _ in per)
+    assert st.shape[0] == rounds
+    for i in range(1, rounds + 1):
+        part = [seqs for lv, seqs in per if lv >= i]
+        n_i = sum(len(s[i]) for s in part)
+        d_i = sum(len(s[i + 1]) for s in part)
+        still = sum(1 for lv, _ in per if lv > i)
+        L = e["levels"][i - 1]
+        assert st[i - 1, 0] == n_i, (i, "n")
+        assert st[i - 1, 1] == d_i, (i, "d")
+        assert st[i - 1, 2] == len(L["fp"]), (i, "u")
+        assert st[i - 1, 3] == len(L["rhs"]), (i, "Q")
+        assert st[i - 1, 4] == still, (i, "active")
+        if i < rounds:
+            became_one = sum(1 for lv, _ in per if lv == i)
+            assert st[i - 1, 1] == st[i, 0] + became_one
+    # the input level: T^1_j is the string itself
+    for j, (lv, seqs) in enumerate(per):
+        if lv:
+            assert bytes(seqs[1].astype(np.uint8).tolist()) == strings[j]
+
+
+def test_own_order_subgrammar_equals_the_string_built_alone(oracle_mod):
+    """The renaming used for whole-genome comparisons: a string's rules inside
+    a collection, renumbered in its own first-occurrence order, equal the
+    oracle's grammar of that string alone, rank for rank (stability, Def. 1),
+    and agree with the canonical comparison."""
+    O = oracle_mod
+    rng = np.random.default_rng(3)
+    text, off = D.make_config("bacterial", scale=0.004)
+    strings = [text[off[j]:off[j + 1]].tobytes() for j in range(len(off) - 1)]
+    strings += [b"A", b"ACGT" * 50, b"G" * 300]
+    t, o = O.pack(strings)
+    e = O.build(t, o, SEED).export()
+    for j in list(range(len(strings))):
+        alone = O.build(*O.pack([strings[j]]), SEED).export()
+        mine = CN.own_order_subgrammar(e, j)
+        assert CN.exports_equal(mine, alone), (j, CN.first_difference(mine, alone))
+        assert CN.canon(CN.subgrammar(e, [j])) == CN.canon(alone)
+    # a wrong order (the collection's own ranks kept) is not accepted
+    j = len(strings) - 4
+    sub = CN.subgrammar(e, [j])
+    alone = O.build(*O.pack([strings[j]]), SEED).export()
+    assert not CN.exports_equal(sub, alone)

@@ -48,17 +48,16 @@ def served():
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     from paper_2411_12439_amd import serve
     src = D.ServingSource(scale=0.02, n_bases=4)
-    pool = serve.PinnedPool(src)
     # a high offered load so that requests queue up and batches form; a small
     # ring so that it wraps
-    summary, srv, reqs = serve.run_load(pool, load_gbps=5.0, seconds=30.0, max_requests=60,
+    summary, srv, reqs = serve.run_load(src, load_gbps=5.0, seconds=30.0, max_requests=60,
                                         ring_bytes=4 << 20)
-    return serve, pool, summary, srv, reqs
+    return serve, src, summary, srv, reqs
 
 
 @pytest.mark.gpu
 def test_serving_completes_every_request(served):
-    serve, pool, summary, srv, reqs = served
+    serve, src, summary, srv, reqs = served
     assert summary["requests"] == 60 == len(srv.completed)
     assert sum(srv.batch_sizes) == 60
     assert summary["max_batch"] >= 2, "no batch formed under load"
@@ -69,16 +68,16 @@ def test_serving_completes_every_request(served):
 @pytest.mark.gpu
 def test_serving_alone_equals_in_the_mix(served):
     """Def. 1: each request's rules inside the running grammar == the request built alone."""
-    serve, pool, summary, srv, reqs = served
-    assert serve.check_alone_vs_mix(srv, pool, reqs, range(len(reqs))) == len(reqs)
+    serve, src, summary, srv, reqs = served
+    assert serve.check_alone_vs_mix(srv, src, reqs, range(len(reqs))) == len(reqs)
 
 
 @pytest.mark.gpu
 def test_serving_round_trip(served):
-    serve, pool, summary, srv, reqs = served
-    for req, (v, st, L) in reqs[::7]:
+    serve, src, summary, srv, reqs = served
+    for req, desc in reqs[::7]:
         got = srv.g.expand(req.c_index).cpu().numpy()
-        assert np.array_equal(got, pool.source.variants[v][st:st + L])
+        assert np.array_equal(got, src.host_bytes(desc))
 
 
 @pytest.mark.gpu
@@ -87,10 +86,32 @@ def test_serving_grammar_equals_oracle_of_the_stream(served):
     in completion order: incremental merging loses nothing and adds nothing."""
     from oracle import oracle as O
     from paper_2411_12439_amd import canon as CN
-    serve, pool, summary, srv, reqs = served
+    serve, src, summary, srv, reqs = served
     order = sorted(reqs, key=lambda x: x[0].c_index)
-    strings = [pool.source.variants[v][st:st + L] for _, (v, st, L) in order]
+    strings = [src.host_bytes(desc) for _, desc in order]
     text, off = D.pack(strings)
     want = O.build(text, off, D.HASH_SEED).export()
     got = srv.g.export()
     assert CN.canon(got) == CN.canon(want)
+
+
+def test_requests_carry_their_own_divergence():
+    """Each request is a window of a base copy with fresh substitutions
+    (~0.9 %, every one a different base), drawn from the request id alone:
+    the same descriptor gives the same bytes, two requests over the same
+    window differ.  Checked on the CPU (the device uses the same recipe)."""
+    src = D.ServingSource(scale=0.002, n_bases=2)
+    rid, v, _, _ = src.draw()
+    st = 1000
+    desc = (rid, v, st, 60000)
+    win = src.variants[v][st:st + 60000]
+    a = src.materialize(desc, device="cpu").numpy()
+    b = src.materialize(desc, device="cpu").numpy()
+    c = src.materialize((rid + 1, v, st, 60000), device="cpu").numpy()
+    assert np.array_equal(a, b)
+    diff = a != win
+    rate = diff.mean()
+    assert 0.0075 < rate < 0.0105, rate
+    assert set(np.unique(a[diff]).tolist()) <= set(b"ACGT")
+    assert (a != c).mean() > 0.015          # fresh substitutions on both
+    assert np.array_equal(a[~diff], win[~diff])
