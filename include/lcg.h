@@ -135,6 +135,54 @@ lcg_status lcg_build_into(lcg_grammar_t g, const uint8_t* d_text, const uint64_t
                           uint32_t* first_index);
 
 /*
+ * Serving session (continuous batching into one running grammar, the serving
+ * form of BuildGram against a grammar being extended, App. A.2): batches of
+ * strings are admitted at any time and compressed into g round by round.
+ * Each lcg_session_step advances every admitted batch by one parsing round
+ * (a batch whose sequence has become short, at most 2^tail_log2 symbols, runs
+ * all its remaining rounds in that step), so a batch admitted while others
+ * are deep in their rounds starts at round 1 at the next step instead of
+ * waiting for them.  Batches share g's per-level dictionaries (a phrase is
+ * looked up and added if absent), so every string's rules inside g are those
+ * of the string compressed alone (stability, Def. 1), and g equals, up to a
+ * renaming of each level's ranks, the grammar of all admitted strings built
+ * in C order; for a given sequence of calls the ranks are always the same.
+ * One thread at a time may use a session.
+ */
+typedef struct lcg_session* lcg_session_t;
+
+/* A session over g (which it does not own; g must outlive it).  opts as for
+ * lcg_build_into (NULL: defaults; hbm_budget bounds the working memory the
+ * active batches may hold together, 0 = unlimited).  Errors: LCG_EINVAL,
+ * LCG_ESEED. */
+lcg_status lcg_session_new(lcg_grammar_t g, const lcg_opts* opts, lcg_session_t* out);
+
+/* Admit k strings (the input conventions of lcg_build) as one batch.  Their
+ * C indices are *first_index .. *first_index + k - 1 at once; their entries
+ * are final once *ticket has been reported done by lcg_session_step.  d_text
+ * and d_offsets must stay valid and unchanged until then.  Errors: LCG_EINVAL
+ * (bad input, or a failed session), LCG_ENOMEM (the batch's working-memory
+ * bound, lcg_build_bytes, does not fit hbm_budget beside the active batches:
+ * nothing is admitted, retry after a step), LCG_EHIP. */
+lcg_status lcg_session_admit(lcg_session_t s, const uint8_t* d_text, const uint64_t* d_offsets,
+                             uint32_t k, hipStream_t stream, uint32_t* first_index,
+                             uint64_t* ticket);
+
+/* One round of every active batch, in admission order; synchronises the
+ * stream.  h_done (host, cap entries, cap >= the number of active batches)
+ * receives the tickets of the batches that finished, *n_done their number
+ * and *n_active (may be NULL) the batches still active.  Errors: LCG_EINVAL
+ * (cap too small, a failed session); any failure of a round (LCG_ENOMEM,
+ * LCG_ETABLE, LCG_EOVERFLOW, LCG_EHIP) fails the session and leaves g unusable,
+ * since the active batches share its dictionaries. */
+lcg_status lcg_session_step(lcg_session_t s, hipStream_t stream, uint64_t* h_done, uint32_t cap,
+                            uint32_t* n_done, uint32_t* n_active);
+
+/* Free the session (not g).  Freeing it while batches are active leaves
+ * their strings unfinished and g unusable. */
+void lcg_session_free(lcg_session_t s);
+
+/*
  * MergeGrams(G_a, G_b) (Sec. 3.5-3.6), in the rank encoding of App. A.1:
  * level by level, every rule of b (right-hand side renamed into a's ranks of
  * the level below) is looked up in a's dictionary of that level; a hit reuses
@@ -163,6 +211,28 @@ lcg_status lcg_expand(lcg_grammar_t g, uint32_t j, uint8_t* d_out, uint64_t cap,
 lcg_status lcg_expand_strings(lcg_grammar_t g, uint32_t j0, uint32_t j1, uint8_t* d_out,
                               uint64_t cap, uint64_t* d_offsets, uint64_t* total,
                               hipStream_t stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * expansion as lcg_expand_strings (same arguments, results and errors), with
+ * every device buffer of the call taken from a fixed scratch region of
+ * 64 MiB that the library reserves once per device when it is loaded there
+ * and keeps until the process ends.  It calls no hipMalloc, hipFree or other
+ * allocating routine.  Limits and conditions:
+ *   - the expansion lengths of g must be current: computed by an earlier
+ *     lcg_expand_strings (or lcg_extract, lcg_lce, lcg_symbol_lce) call after
+ *     g last changed; otherwise LCG_EINVAL;
+ *   - a range whose per-level working set (16 bytes per symbol of a level
+ *     being expanded, two levels at a time, plus 40 bytes per string) does not
+ *     fit the 64 MiB is refused with LCG_EINVAL before anything is written to
+ *     d_out (lcg_expand_strings handles it);
+ *   - every call on one GPU shares that GPU's scratch: calls that overlap on
+ *     one device (on different streams or threads) race and must not be made.
+ */
+lcg_status lcg_expand_strings_noalloc(lcg_grammar_t g, uint32_t j0, uint32_t j1, uint8_t* d_out,
+                                      uint64_t cap, uint64_t* d_offsets, uint64_t* total,
+                                      hipStream_t stream);
 
 /* Autotuner: times complete builds of the given strings (which it builds,
  * and frees, several times) under candidate values of the options that do not

@@ -25,7 +25,7 @@ struct Counters {
   unsigned int active;          // strings still longer than one symbol
   unsigned long long active_len;  // their total length
   unsigned int rest_len;        // phrases left to the plain insert by the combining one
-  unsigned int pad;
+  unsigned int won_len;         // slots claimed in the running insert (entries of its won list)
   unsigned int hll[kHll];       // HyperLogLog registers of the round's phrase keys
 };
 
@@ -75,11 +75,20 @@ void scan_one(const uint64_t* in, uint64_t* out, uint64_t count, const uint64_t*
 // memory, the host passes a bound of it in d / in.n) are launched over the
 // bound and stop at the count: rounds can then be queued without reading
 // sizes back.
+// won: room for d slot indices; every slot the insert claims is listed there
+// (count in ctr->won_len, zero on entry).
 void launch_insert(bool bytes, uint64_t d, const uint64_t* d_dev, const uint64_t* key,
                    const uint64_t* pstart, const uint32_t* plen, const void* content,
                    const uint64_t* rule_off, const void* rule_rhs, uint32_t u_committed,
                    Slot* table, uint64_t mask, uint32_t* slot_idx, bool combine, uint32_t* rest,
-                   uint32_t* rest_len, Counters* ctr, hipStream_t s);
+                   uint32_t* rest_len, uint32_t* won, Counters* ctr, hipStream_t s);
+// First-occurrence flags of the new phrases from the insert's won list (the
+// first occurrence of every slot claimed in the round is new), then per flag
+// word the new rules and their right-hand-side lengths.  W: flag words to
+// fill (a bound of ceil(d / 64) when the count is on the device).
+void launch_newflags_won(bool bytes, const uint32_t* won, const Counters* ctr, const Slot* table,
+                         uint64_t W, const uint64_t* key, const uint32_t* plen, uint64_t* newbits,
+                         uint64_t* wcnt, uint64_t* wlen, hipStream_t s);
 void launch_newflags(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t* slot_idx,
                      const Slot* table, const uint64_t* key, const uint32_t* plen,
                      uint64_t* newbits, uint64_t* wcnt, uint64_t* wlen, hipStream_t s);

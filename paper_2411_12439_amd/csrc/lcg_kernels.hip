@@ -908,6 +908,21 @@ void scan_one(const uint64_t* in, uint64_t* out, uint64_t count, const uint64_t*
 }
 
 // ------------------------------------------------------------------ insert
+// Append the slots the active lanes won (mine != kNone) to the won list: one
+// atomic per wave, the lanes' entries in lane order.
+__device__ __forceinline__ void push_won(bool mine, uint32_t pos, uint32_t* won,
+                                         unsigned int* won_len) {
+  const uint64_t bal = __ballot(mine);
+  if (!bal) return;
+  const uint64_t act = __ballot(1);
+  const int leader = __builtin_ctzll(act);
+  const int lane = threadIdx.x & 63;
+  unsigned int base = 0;
+  if (lane == leader) base = atomicAdd(won_len, (unsigned int)__builtin_popcountll(bal));
+  base = __shfl(base, leader, 64);
+  if (mine) won[base + __builtin_popcountll(bal & ((1ull << lane) - 1ull))] = pos;
+}
+
 // Equality of two symbol sequences of length len, without an early exit and
 // without a call (both forms of the probe loop around it were compiled into
 // code that lost the probe result).  Eight symbols of each side per step, so
@@ -959,6 +974,7 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t begin, uint64_t end, ui
                                                 const Sym* __restrict__ rule_rhs, uint32_t u_committed,
                                                 Slot* table, uint64_t mask,
                                                 uint32_t* __restrict__ slot_idx,
+                                                uint32_t* __restrict__ won_list,
                                                 Counters* __restrict__ ctr) {
   __shared__ unsigned long long s_sum[4];
   if (threadIdx.x < 4) s_sum[threadIdx.x] = 0;
@@ -981,6 +997,7 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t begin, uint64_t end, ui
       my_len = plen[o];
     }
     uint32_t result = kNone;
+    bool claimed = false;
     for (uint32_t probe = 0; probe < kMaxProbe && result == kNone; ++probe) {
       Slot* sl = &table[pos];
       ++probes;
@@ -992,6 +1009,7 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t begin, uint64_t end, ui
                       (unsigned long long)want);
         if (prev == kEmpty) {
           hit = true;
+          claimed = true;
           ++won;
         } else {
           w = prev;
@@ -1037,6 +1055,7 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t begin, uint64_t end, ui
         atomicMin(&sl->minocc, (uint32_t)o);
     }
     __builtin_nontemporal_store(result, &slot_idx[o]);
+    push_won(claimed, result, won_list, &ctr->won_len);
   }
   // one global atomic per block and counter
   won = wave_sum(won);
@@ -1080,6 +1099,7 @@ __global__ __launch_bounds__(256) void k_insert_comb(uint64_t begin, uint64_t en
                                                      uint64_t mask, uint32_t* __restrict__ slot_idx,
                                                      uint32_t* __restrict__ rest,
                                                      uint32_t* __restrict__ rest_len,
+                                                     uint32_t* __restrict__ won_list,
                                                      Counters* __restrict__ ctr) {
   __shared__ unsigned long long s_key[kComb];  // reused as the chunk's rest list
   __shared__ uint32_t s_min[kComb];
@@ -1149,6 +1169,7 @@ __global__ __launch_bounds__(256) void k_insert_comb(uint64_t begin, uint64_t en
       const int i = j * 256 + threadIdx.x;
       const uint64_t kk = s_key[i];
       uint32_t res = kNone;
+      bool claimed = false;
       if (kk != kEmpty) {
         uint64_t pos = mix64(kk) & mask;
         for (uint32_t probe = 0; probe < kMaxProbe && res == kNone; ++probe) {
@@ -1162,6 +1183,7 @@ __global__ __launch_bounds__(256) void k_insert_comb(uint64_t begin, uint64_t en
                           (unsigned long long)kEmpty, (unsigned long long)kk);
             if (prev == kEmpty) {
               hit = true;
+              claimed = true;
               ++won;
             } else {
               w = prev;
@@ -1181,6 +1203,7 @@ __global__ __launch_bounds__(256) void k_insert_comb(uint64_t begin, uint64_t en
         }
       }
       s_slot[i] = res;
+      push_won(claimed, res, won_list, &ctr->won_len);
     }
     __syncthreads();
     // 3: slots of the combined phrases; the others join the rest list
@@ -1229,7 +1252,7 @@ void launch_insert(bool bytes, uint64_t d, const uint64_t* d_dev, const uint64_t
                    const uint64_t* pstart, const uint32_t* plen, const void* content,
                    const uint64_t* rule_off, const void* rule_rhs, uint32_t u_committed,
                    Slot* table, uint64_t mask, uint32_t* slot_idx, bool combine, uint32_t* rest,
-                   uint32_t* rest_len, Counters* ctr, hipStream_t s) {
+                   uint32_t* rest_len, uint32_t* won, Counters* ctr, hipStream_t s) {
   if (!d) return;
   if (d_dev && combine) throw std::runtime_error("insert: combining needs the count on the host");
   const uint32_t* list = nullptr;
@@ -1241,7 +1264,8 @@ void launch_insert(bool bytes, uint64_t d, const uint64_t* d_dev, const uint64_t
          begin = end, end = end * 16 < d ? end * 16 : d) {
       unsigned gc = grid_for(end - begin, kCombChunk);
       if (gc > r) gc = r;
-      k_insert_comb<<<gc, 256, 0, s>>>(begin, end, key, table, mask, slot_idx, rest, rest_len, ctr);
+      k_insert_comb<<<gc, 256, 0, s>>>(begin, end, key, table, mask, slot_idx, rest, rest_len, won,
+                                       ctr);
       LCG_LAUNCH_CHECK("insert_comb");
     }
     list = rest;  // at most d phrases; the count is on the device
@@ -1254,18 +1278,18 @@ void launch_insert(bool bytes, uint64_t d, const uint64_t* d_dev, const uint64_t
   const uint32_t* r32 = static_cast<const uint32_t*>(rule_rhs);
   if (bytes && d_dev)
     k_insert<uint8_t, true><<<g, 256, 0, s>>>(0, d, d, d_dev, list, list_len, key, pstart, plen, c8,
-                                              rule_off, r8, u_committed, table, mask, slot_idx, ctr);
+                                              rule_off, r8, u_committed, table, mask, slot_idx, won, ctr);
   else if (bytes)
     k_insert<uint8_t, false><<<g, 256, 0, s>>>(0, d, d, d_dev, list, list_len, key, pstart, plen, c8,
-                                               rule_off, r8, u_committed, table, mask, slot_idx, ctr);
+                                               rule_off, r8, u_committed, table, mask, slot_idx, won, ctr);
   else if (d_dev)
     k_insert<uint32_t, true><<<g, 256, 0, s>>>(0, d, d, d_dev, list, list_len, key, pstart, plen,
                                                c32, rule_off, r32, u_committed, table, mask,
-                                               slot_idx, ctr);
+                                               slot_idx, won, ctr);
   else
     k_insert<uint32_t, false><<<g, 256, 0, s>>>(0, d, d, d_dev, list, list_len, key, pstart, plen,
                                                 c32, rule_off, r32, u_committed, table, mask,
-                                                slot_idx, ctr);
+                                                slot_idx, won, ctr);
   LCG_LAUNCH_CHECK("insert");
 }
 
@@ -1359,6 +1383,35 @@ void launch_newflags_table(bool bytes, const Slot* table, uint64_t cap, uint64_t
   if (g > 8192) g = 8192;
   k_newflags_table<<<g, 256, 0, s>>>(table, cap, d, reinterpret_cast<unsigned long long*>(newbits));
   LCG_LAUNCH_CHECK("newflags_table");
+  if (bytes)
+    k_word_counts<true><<<grid_for(W, 256), 256, 0, s>>>(newbits, W, key, plen, wcnt, wlen);
+  else
+    k_word_counts<false><<<grid_for(W, 256), 256, 0, s>>>(newbits, W, key, plen, wcnt, wlen);
+  LCG_LAUNCH_CHECK("word_counts");
+}
+
+// The first occurrence of every slot claimed in the round marks its phrase
+// new (newbits zero on entry).
+__global__ __launch_bounds__(256) void k_newflags_won(const uint32_t* __restrict__ won,
+                                                      const Counters* __restrict__ ctr,
+                                                      const Slot* __restrict__ table,
+                                                      unsigned long long* __restrict__ newbits) {
+  const uint32_t n = ctr->won_len;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint64_t m = table[won[i]].minocc;
+    atomicOr(&newbits[m >> 6], 1ULL << (m & 63));
+  }
+}
+
+void launch_newflags_won(bool bytes, const uint32_t* won, const Counters* ctr, const Slot* table,
+                         uint64_t W, const uint64_t* key, const uint32_t* plen, uint64_t* newbits,
+                         uint64_t* wcnt, uint64_t* wlen, hipStream_t s) {
+  if (!W) return;
+  launch_zero(newbits, W * 8, s);
+  unsigned g = grid_for(W * 64, 256);
+  if (g > 4096) g = 4096;
+  k_newflags_won<<<g, 256, 0, s>>>(won, ctr, table, reinterpret_cast<unsigned long long*>(newbits));
+  LCG_LAUNCH_CHECK("newflags_won");
   if (bytes)
     k_word_counts<true><<<grid_for(W, 256), 256, 0, s>>>(newbits, W, key, plen, wcnt, wlen);
   else

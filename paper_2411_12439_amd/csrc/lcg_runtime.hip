@@ -119,13 +119,13 @@ struct Work {
   DBuf<Counters> ctr, fin;
   DBuf<uint8_t> content8, hll_part;
   DBuf<TileSeg> tile_seg;
-  DBuf<uint32_t> content32, remap[2], rest;
+  DBuf<uint32_t> content32, remap[2], rest, won;
   DBuf<struct TailRec> tail;
   void release_after(hipStream_t s) {
     DBuf<uint64_t>* b64[] = {&bits, &tile_cnt, &tile_base, &scan_tmp, &pstart, &key, &off[0],
                              &off[1], &newbits, &wcnt, &wlen, &wcnt_base, &wlen_base, &nqoff};
     DBuf<uint32_t>* b32[] = {&plen, &slot_idx, &sym[0], &sym[1], &fpv[0], &fpv[1], &lut,
-                             &content32, &remap[0], &remap[1], &rest, &nlist};
+                             &content32, &remap[0], &remap[1], &rest, &nlist, &won};
     for (auto* b : b64) b->reset_after(s);
     for (auto* b : b32) b->reset_after(s);
     ctr.reset_after(s);
@@ -271,6 +271,7 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
   // few distinct keys for many phrases: combine equal keys per chunk first
   const bool combine = o.combine_log2 < 31 && (est_new << o.combine_log2) <= d;
   w.slot_idx.need(d, s);
+  w.won.need(d, s);
   if (combine) w.rest.need(d, s);
   w.newbits.need(W, s);
   w.wcnt.need(W, s);
@@ -287,17 +288,12 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
     if (pe) pe->rec(3, s);
     launch_insert(bytes, d, nullptr, w.key.p, w.pstart.p, w.plen.p, content, L.off.p, rule_rhs, L.u,
                   L.table.p, L.tcap - 1, w.slot_idx.p, combine, w.rest.p, &w.ctr.p->rest_len,
-                  w.ctr.p, s);
+                  w.won.p, w.ctr.p, s);
     if (pe) pe->rec(4, s);
-    // first occurrences from the table side when the table is much smaller
-    // than the phrase array (a scan of the table plus one atomic per new rule
-    // against one random slot read per phrase)
-    if (2 * L.tcap <= d)
-      launch_newflags_table(bytes, L.table.p, L.tcap, d, w.key.p, w.plen.p, w.newbits.p, w.wcnt.p,
-                            w.wlen.p, s);
-    else
-      launch_newflags(bytes, d, nullptr, w.slot_idx.p, L.table.p, w.key.p, w.plen.p, w.newbits.p, w.wcnt.p,
-                      w.wlen.p, s);
+    // first occurrences from the slots the insert claimed: one slot read and
+    // one flag per new rule, not per phrase
+    launch_newflags_won(bytes, w.won.p, w.ctr.p, L.table.p, W, w.key.p, w.plen.p, w.newbits.p,
+                        w.wcnt.p, w.wlen.p, s);
     scan_exclusive(w.wcnt.p, w.wcnt_base.p, W, w.scan_tmp.p, s);
     scan_exclusive(w.wlen.p, w.wlen_base.p, W, w.scan_tmp.p, s);
     if (pe) pe->rec(5, s);
@@ -405,6 +401,7 @@ static void tail_rounds(lcg_grammar* g, uint32_t lv, uint64_t n_i, uint64_t acti
     w.plen.need(d_b, s);
     w.key.need(d_b, s);
     w.slot_idx.need(d_b, s);
+    w.won.need(d_b, s);
     w.sym[cur].need(d_b, s);
     w.fpv[cur].need(d_b, s);
     w.off[cur].need(k + 1, s);
@@ -443,10 +440,11 @@ static void tail_rounds(lcg_grammar* g, uint32_t lv, uint64_t n_i, uint64_t acti
     if (pe) pe->rec(8, s);
     if (pe) pe->rec(3, s);
     launch_insert(bytes, d_b, &rec->d, w.key.p, w.pstart.p, w.plen.p, content, L.off.p, rule_rhs,
-                  L.u, L.table.p, L.tcap - 1, w.slot_idx.p, false, nullptr, nullptr, &rec->ctr, s);
+                  L.u, L.table.p, L.tcap - 1, w.slot_idx.p, false, nullptr, nullptr, w.won.p,
+                  &rec->ctr, s);
     if (pe) pe->rec(4, s);
-    launch_newflags(bytes, d_b, &rec->d, w.slot_idx.p, L.table.p, w.key.p, w.plen.p, w.newbits.p,
-                    w.wcnt.p, w.wlen.p, s);
+    launch_newflags_won(bytes, w.won.p, &rec->ctr, L.table.p, W_b, w.key.p, w.plen.p, w.newbits.p,
+                        w.wcnt.p, w.wlen.p, s);
     scan_one(w.wcnt.p, w.wcnt_base.p, W_b, &rec->d, 6, &rec->u, s);
     scan_one(w.wlen.p, w.wlen_base.p, W_b, &rec->d, 6, &rec->q, s);
     if (pe) pe->rec(5, s);
@@ -513,73 +511,103 @@ static void tail_rounds(lcg_grammar* g, uint32_t lv, uint64_t n_i, uint64_t acti
     g->levels.pop_back();
 }
 
-// BuildGram of k strings into g (fresh or existing): the batched form.
-// Two host synchronisations per round: the phrase count and key sketch
-// (sizes the dictionary; also returns the previous round's count of strings
-// still active), and the new-rule counts (sizes the level).  The round after
-// the last one runs classify/emit on strings of length <= 1 and finds no
-// phrase; that is how the loop learns that every string is done.
-static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_off, uint32_t k,
-                       const std::vector<uint64_t>& h_off, const Opts& o, Work& w, hipStream_t s) {
-  const uint32_t c_base = g->k;
-  g->c_level.grow(c_base + k, c_base, s);
-  g->c_sym.grow(c_base + k, c_base, s);
-  launch_c_init(d_text, d_off, k, g->c_level.p + c_base, g->c_sym.p + c_base, s);
-  g->k += k;
-  uint32_t active = 0;
-  uint64_t active_len = 0;  // total length of the strings longer than one symbol
-  for (uint32_t j = 0; j < k; ++j) {
-    const uint64_t len = h_off[j + 1] - h_off[j];
-    active += len >= 2;
-    active_len += len >= 2 ? len : 0;
-  }
-  if (!active) {
-    sync(s);
-    return;
-  }
-  w.lut.need(256, s);
-  w.ctr.need(1, s);
-  w.fin.need(1, s);
-  w.hll_part.need((size_t)kEmitBlocks * kHll, s);
-  launch_f0_lut(w.lut.p, g->H.lv[0].a, g->H.lv[0].b, s);
-  const uint64_t* cur_off = d_off;
-  uint64_t n_i = h_off[k];
-  int cur = 0;  // ping-pong index of T^{i+1}
-  PhaseEvents pe(phase_mask(o.flags));
-  Mailbox* mb = mailbox();
-  bool pending = false;  // the previous round's row waits for its active count
+// BuildGram of k strings into g (fresh or existing), the batched form, kept
+// as the state of a build between its rounds, so that several builds into
+// one grammar can advance in turns (the serving session) as well as one
+// build to its end (build_core).
+//
+// A round with host reads synchronises twice: the phrase count and key
+// sketch (sizes the dictionary; also returns the previous round's count of
+// strings still active), and the new-rule counts (sizes the level).  The
+// round after the last one runs classify/emit on strings of length <= 1 and
+// finds no phrase; that is how the build learns that every string is done.
+// Once the sequence is short, one step queues all remaining rounds without
+// host reads (tail_rounds).
+struct Cohort {
+  lcg_grammar* g;
+  const uint8_t* d_text;
+  uint32_t k;
+  uint32_t c_base;  // index in C of the first string
+  Opts o;
+  Work& w;
+  PhaseEvents pe;
+  const uint64_t* cur_off;  // segment offsets of T^lv
+  uint64_t n_i;             // length of T^lv
+  uint32_t lv = 1;
+  int cur = 0;              // ping-pong index of T^{lv+1}
+  uint32_t active = 0;      // strings longer than one symbol
+  uint64_t active_len = 0;  // their total length
+  bool pending = false;     // the previous round's row waits for its active count
   Stat prev{};
-  for (uint32_t lv = 1;; ++lv) {
+  bool done = false;
+
+  Cohort(lcg_grammar* g_, const uint8_t* text, const uint64_t* d_off, uint32_t k_,
+         const std::vector<uint64_t>& h_off, const Opts& o_, Work& w_, hipStream_t s)
+      : g(g_), d_text(text), k(k_), c_base(g_->k), o(o_), w(w_), pe(phase_mask(o_.flags)),
+        cur_off(d_off), n_i(h_off[k_]) {
+    g->c_level.grow(c_base + k, c_base, s);
+    g->c_sym.grow(c_base + k, c_base, s);
+    launch_c_init(d_text, d_off, k, g->c_level.p + c_base, g->c_sym.p + c_base, s);
+    g->k += k;
+    for (uint32_t j = 0; j < k; ++j) {
+      const uint64_t len = h_off[j + 1] - h_off[j];
+      active += len >= 2;
+      active_len += len >= 2 ? len : 0;
+    }
+    if (!active) {
+      sync(s);
+      done = true;
+      return;
+    }
+    w.lut.need(256, s);
+    w.ctr.need(1, s);
+    w.fin.need(1, s);
+    w.hll_part.need((size_t)kEmitBlocks * kHll, s);
+    launch_f0_lut(w.lut.p, g->H.lv[0].a, g->H.lv[0].b, s);
+  }
+
+  // The previous round's row, completed with its count of strings still
+  // active (read into the mailbox by the caller).
+  void close_prev(const Counters& hf) {
+    prev[4] = hf.active;
+    prev[13] = pe.ns(5, 6);
+    prev[14] = pe.ns(6, 7);
+    prev[8] += prev[13] + prev[14];
+    g->stats.push_back(prev);
+    active = hf.active;
+    active_len = hf.active_len;
+  }
+
+  // One round with host reads, or all remaining rounds queued without them.
+  void step(hipStream_t s) {
+    if (done) return;
+    Mailbox* mb = mailbox();
     Counters& hf = mb->fin;
     if (o.fail_round && lv == o.fail_round && n_i > (1ull << o.tail_log2))
       throw LcgError{LCG_ETABLE, "test hook: failure forced at round " + std::to_string(lv)};
     if (lv >= (uint32_t)HashFamily::kLevels) {
       HIP_CHECK(hipMemcpyAsync(&hf, w.fin.p, offsetof(Counters, hll), hipMemcpyDeviceToHost, s));
       sync(s);
-      prev[4] = hf.active;
-      prev[13] = pe.ns(5, 6);
-      prev[14] = pe.ns(6, 7);
-      prev[8] += prev[13] + prev[14];
-      g->stats.push_back(prev);
+      close_prev(hf);
       if (hf.active) throw LcgError{LCG_EOVERFLOW, "more than 63 rounds"};
-      break;
+      done = true;
+      return;
     }
     if (n_i <= (1ull << o.tail_log2)) {
       // the rest of the rounds run in tail mode; first the previous round's row
       if (pending) {
         HIP_CHECK(hipMemcpyAsync(&hf, w.fin.p, offsetof(Counters, hll), hipMemcpyDeviceToHost, s));
         sync(s);
-        prev[4] = hf.active;
-        prev[13] = pe.ns(5, 6);
-        prev[14] = pe.ns(6, 7);
-        prev[8] += prev[13] + prev[14];
-        g->stats.push_back(prev);
-        active = hf.active;
-        active_len = hf.active_len;
-        if (!active) break;
+        close_prev(hf);
+        pending = false;
+        if (!active) {
+          done = true;
+          return;
+        }
       }
       tail_rounds(g, lv, n_i, active_len, d_text, cur_off, cur, k, c_base, o, w, s);
-      break;
+      done = true;
+      return;
     }
     const bool bytes = lv == 1;
     RoundIn in;
@@ -613,8 +641,8 @@ static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_
     pe.rec(2, s);
     // small rounds size the dictionary by the phrase count itself
     const bool sketch = n_i > (1u << 20);
-    launch_emit(in, w.bits.p, w.tile_base.p, w.tile_seg.p, g->H.lv[lv], o.key_bits, w.pstart.p, w.plen.p,
-                w.key.p, w.fpv[cur].p, w.hll_part.p, sketch ? w.ctr.p : nullptr, s);
+    launch_emit(in, w.bits.p, w.tile_base.p, w.tile_seg.p, g->H.lv[lv], o.key_bits, w.pstart.p,
+                w.plen.p, w.key.p, w.fpv[cur].p, w.hll_part.p, sketch ? w.ctr.p : nullptr, s);
     pe.rec(8, s);
     HIP_CHECK(hipMemcpyAsync(&mb->d, w.tile_base.p + tiles, 8, hipMemcpyDeviceToHost, s));
     if (sketch)
@@ -625,16 +653,12 @@ static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_
     sync(s);
     const uint64_t d = mb->d;
     if (pending) {
-      prev[4] = hf.active;
-      prev[13] = pe.ns(5, 6);
-      prev[14] = pe.ns(6, 7);
-      prev[8] += prev[13] + prev[14];
-      g->stats.push_back(prev);
-      active = hf.active;
-      active_len = hf.active_len;
+      close_prev(hf);
+      pending = false;
       if (!active) {
         if (d) throw LcgError{LCG_EHIP, "internal: phrases after the last round"};
-        break;
+        done = true;
+        return;
       }
     }
     if (d == 0 || d >= d_cap) throw LcgError{LCG_EHIP, "internal: phrase count out of range"};
@@ -658,7 +682,14 @@ static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_
     cur_off = w.off[cur].p;
     n_i = d;
     cur ^= 1;
+    ++lv;
   }
+};
+
+static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_off, uint32_t k,
+                       const std::vector<uint64_t>& h_off, const Opts& o, Work& w, hipStream_t s) {
+  Cohort c(g, d_text, d_off, k, h_off, o, w, s);
+  while (!c.done) c.step(s);
 }
 
 // MergeGrams(a, b): a absorbs b level by level (Sec. 3.6).
@@ -916,12 +947,80 @@ static inline uint64_t children_before(uint64_t m_next, uint64_t entering) {
   return m_next - entering;
 }
 
+// Device scratch of expand_strings_core: `fixed` regions live for the whole
+// call; `side(w, ...)` returns side w's region, replacing what that side held
+// before (the items of one level live on one side while the next level's are
+// written to the other).
+class XsScratch {
+ public:
+  virtual ~XsScratch() = default;
+  virtual void* fixed(size_t bytes, hipStream_t s) = 0;
+  virtual void* side(int w, size_t bytes, hipStream_t s) = 0;
+};
+
+// From the library's caching pool.
+class PoolXs final : public XsScratch {
+ public:
+  void* fixed(size_t bytes, hipStream_t s) override {
+    fixed_.emplace_back();
+    fixed_.back().need(std::max<size_t>(bytes, 1), s);
+    return fixed_.back().p;
+  }
+  void* side(int w, size_t bytes, hipStream_t s) override {
+    side_[w].need(std::max<size_t>(bytes, 1), s);
+    return side_[w].p;
+  }
+
+ private:
+  std::vector<DBuf<uint8_t>> fixed_;
+  DBuf<uint8_t> side_[2];
+};
+
+// From a fixed device region (no allocation): fixed regions from the bottom
+// up, side 0 above them, side 1 down from the top.  A request that does not
+// fit is refused before the region is written.
+class ArenaXs final : public XsScratch {
+ public:
+  ArenaXs(uint8_t* base, size_t cap) : base_(base), cap_(cap), lo_(0), top0_(0), bot1_(cap) {}
+  void* fixed(size_t bytes, hipStream_t) override {
+    if (top0_ != lo_) throw LcgError{LCG_EHIP, "internal: fixed scratch after a side region"};
+    const size_t b = round(bytes);
+    if (lo_ + b > bot1_) too_big();
+    void* p = base_ + lo_;
+    lo_ += b;
+    top0_ = lo_;
+    return p;
+  }
+  void* side(int w, size_t bytes, hipStream_t) override {
+    const size_t b = round(bytes);
+    if (w == 0) {
+      if (lo_ + b > bot1_) too_big();
+      top0_ = lo_ + b;
+      return base_ + lo_;
+    }
+    if (b > cap_ || cap_ - b < top0_) too_big();
+    bot1_ = cap_ - b;
+    return base_ + bot1_;
+  }
+
+ private:
+  static size_t round(size_t b) { return (std::max<size_t>(b, 1) + 255) & ~size_t(255); }
+  [[noreturn]] void too_big() const {
+    throw LcgError{LCG_EINVAL, "the expansion needs more than the " +
+                                   std::to_string(cap_ >> 20) +
+                                   " MiB of fixed scratch of lcg_expand_strings_noalloc"};
+  }
+  uint8_t* base_;
+  size_t cap_, lo_, top0_, bot1_;
+};
+
 // Strings j0..j1-1 expanded together, top-down by byte positions (see
 // launch_xs_*): every symbol carries the position of its expansion, so a
-// level is one pass over its symbols, in any order.
+// level is one pass over its symbols, in any order.  With `prepared` the
+// expansion lengths must already be current (nothing is allocated for them).
 static void expand_strings_core(lcg_grammar* g, uint32_t j0, uint32_t j1, uint8_t* d_out,
                                 uint64_t cap, uint64_t* d_offsets, uint64_t* total_out,
-                                hipStream_t s) {
+                                hipStream_t s, XsScratch& sc, bool prepared = false) {
   if (j0 > j1 || j1 > g->k) throw LcgError{LCG_EINVAL, "string range out of bounds"};
   const uint32_t ks = j1 - j0;
   std::vector<uint8_t> h_level(ks);
@@ -934,59 +1033,69 @@ static void expand_strings_core(lcg_grammar* g, uint32_t j0, uint32_t j1, uint8_
   if (top > g->levels.size()) throw LcgError{LCG_EHIP, "internal: C entry above the top level"};
   std::vector<uint64_t> entering(top + 1, 0);
   for (uint8_t v : h_level) ++entering[v];
-  ensure_explen(g, s);
+  if (prepared) {
+    if (g->explen_version != g->version || g->explen.size() != g->levels.size())
+      throw LcgError{LCG_EINVAL, "the grammar's expansion lengths are not prepared (call "
+                                 "lcg_expand_strings once after the grammar changes)"};
+  } else {
+    ensure_explen(g, s);
+  }
   const uint8_t* cl = g->c_level.p + j0;
   const uint32_t* cs = g->c_sym.p + j0;
-  DBuf<uint64_t> len, str_off, tmp, ctr;
-  len.need(std::max<uint32_t>(ks, 1), s);
-  str_off.need(ks + 1, s);
-  ctr.need(2, s);  // [0]: items of the next level, [1]: children count
+  auto fixed64 = [&](size_t n) { return static_cast<uint64_t*>(sc.fixed(n * 8, s)); };
+  uint64_t* len = fixed64(std::max<uint32_t>(ks, 1));
+  uint64_t* str_off = fixed64(ks + 1);
+  uint64_t* ctr = fixed64(2);  // [0]: items of the next level, [1]: children count
+  uint64_t* extra = fixed64(1);
+  uint64_t* tmp = fixed64(std::max<size_t>(scan_tmp_words(std::max<uint32_t>(ks, 1)), 1));
   uint64_t total = 0;
   if (ks) {
-    launch_xs_strlen(cl, cs, ks, g->explen_ptrs.p, len.p, s);
-    tmp.need(std::max<size_t>(scan_tmp_words(ks), 1), s);
-    scan_exclusive(len.p, str_off.p, ks, tmp.p, s);
-    total = read_dev(str_off.p + ks, s);
+    launch_xs_strlen(cl, cs, ks, g->explen_ptrs.p, len, s);
+    scan_exclusive(len, str_off, ks, tmp, s);
+    total = read_dev(str_off + ks, s);
   } else {
-    launch_zero(str_off.p, sizeof(uint64_t), s);
+    launch_zero(str_off, sizeof(uint64_t), s);
   }
   if (total_out) *total_out = total;
   if (total > cap) throw LcgError{LCG_EINVAL, "output buffer too small"};
-  if (d_offsets)
-    HIP_CHECK(hipMemcpyAsync(d_offsets, str_off.p, (ks + 1) * sizeof(uint64_t),
-                             hipMemcpyDeviceToDevice, s));
-  DBuf<uint32_t> sym[2];
-  DBuf<uint64_t> pos[2];
+  // the items of a level on one side: m symbols, then their m positions
+  uint32_t* sym[2] = {nullptr, nullptr};
+  uint64_t* pos[2] = {nullptr, nullptr};
+  auto items = [&](int w, uint64_t m) {
+    const size_t n = std::max<uint64_t>(m, 1);
+    uint8_t* p = static_cast<uint8_t*>(sc.side(w, n * 8 + ((n * 4 + 255) & ~size_t(255)), s));
+    sym[w] = reinterpret_cast<uint32_t*>(p);
+    pos[w] = reinterpret_cast<uint64_t*>(p + ((n * 4 + 255) & ~size_t(255)));
+  };
   int cur = 0;
   uint64_t m = entering[top];
   uint64_t children = 0;  // children of the current level's items
-  launch_zero(ctr.p, 2 * sizeof(uint64_t), s);
+  launch_zero(ctr, 2 * sizeof(uint64_t), s);
   if (top >= 1) {
-    sym[cur].need(std::max<uint64_t>(m, 1), s);
-    pos[cur].need(std::max<uint64_t>(m, 1), s);
-    launch_xs_enter(cl, cs, ks, top, str_off.p, sym[cur].p, pos[cur].p, ctr.p, d_out, s);
+    items(cur, m);
+    launch_xs_enter(cl, cs, ks, top, str_off, sym[cur], pos[cur], ctr, d_out, s);
     if (top >= 3) {
-      launch_xs_count(sym[cur].p, m, g->levels[top - 1].off.p, ctr.p + 1, s);
-      children = read_dev(ctr.p + 1, s);
+      launch_xs_count(sym[cur], m, g->levels[top - 1].off.p, ctr + 1, s);
+      children = read_dev(ctr + 1, s);
     }
   }
   for (uint32_t lv = top; lv >= 1; --lv) {
     const Level& L = g->levels[lv - 1];
     if (lv == 1) {
-      launch_xs_expand(true, sym[cur].p, pos[cur].p, m, L.off.p, L.rhs8.p, nullptr, nullptr,
+      launch_xs_expand(true, sym[cur], pos[cur], m, L.off.p, L.rhs8.p, nullptr, nullptr,
                        nullptr, nullptr, nullptr, nullptr, d_out, s);
       break;
     }
     if (lv == 2) {
       // level-2 items write the bytes of their level-1 children in place; the
-      // level-1 items left are the strings entering there
-      const Level& L1 = g->levels[0];
-      launch_xs_bytes2(sym[cur].p, pos[cur].p, m, L.off.p, L.rhs32.p, L1.off.p, L1.rhs8.p, d_out, s);
+      // level-1 items left are the strings entering there (their room is
+      // taken first, so that a refusal comes before any byte is written)
       const uint64_t m1 = entering[1];
-      sym[cur ^ 1].need(std::max<uint64_t>(m1, 1), s);
-      pos[cur ^ 1].need(std::max<uint64_t>(m1, 1), s);
-      launch_zero(ctr.p, 2 * sizeof(uint64_t), s);
-      launch_xs_enter(cl, cs, ks, 1, str_off.p, sym[cur ^ 1].p, pos[cur ^ 1].p, ctr.p, d_out, s);
+      items(cur ^ 1, m1);
+      const Level& L1 = g->levels[0];
+      launch_xs_bytes2(sym[cur], pos[cur], m, L.off.p, L.rhs32.p, L1.off.p, L1.rhs8.p, d_out, s);
+      launch_zero(ctr, 2 * sizeof(uint64_t), s);
+      launch_xs_enter(cl, cs, ks, 1, str_off, sym[cur ^ 1], pos[cur ^ 1], ctr, d_out, s);
       cur ^= 1;
       m = m1;
       continue;
@@ -994,35 +1103,83 @@ static void expand_strings_core(lcg_grammar* g, uint32_t j0, uint32_t j1, uint8_
     // the children are counted by the previous pass (or above, at the top);
     // this pass counts the grandchildren, except those of entering strings
     const uint64_t m_next = children + entering[lv - 1];
-    sym[cur ^ 1].need(std::max<uint64_t>(m_next, 1), s);
-    pos[cur ^ 1].need(std::max<uint64_t>(m_next, 1), s);
-    launch_zero(ctr.p, 2 * sizeof(uint64_t), s);
+    items(cur ^ 1, m_next);
+    launch_zero(ctr, 2 * sizeof(uint64_t), s);
     // grandchildren are counted while they will be items (level >= 2)
     const uint64_t* off_below = lv >= 4 ? g->levels[lv - 2].off.p : nullptr;
-    launch_xs_expand(false, sym[cur].p, pos[cur].p, m, L.off.p, L.rhs32.p, g->explen[lv - 2].p,
-                     lv >= 4 ? g->gc[lv - 1].p : nullptr, sym[cur ^ 1].p, pos[cur ^ 1].p, ctr.p,
-                     ctr.p + 1, nullptr, s);
-    launch_xs_enter(cl, cs, ks, lv - 1, str_off.p, sym[cur ^ 1].p, pos[cur ^ 1].p, ctr.p, d_out, s);
+    launch_xs_expand(false, sym[cur], pos[cur], m, L.off.p, L.rhs32.p, g->explen[lv - 2].p,
+                     lv >= 4 ? g->gc[lv - 1].p : nullptr, sym[cur ^ 1], pos[cur ^ 1], ctr,
+                     ctr + 1, nullptr, s);
+    launch_xs_enter(cl, cs, ks, lv - 1, str_off, sym[cur ^ 1], pos[cur ^ 1], ctr, d_out, s);
     if (lv >= 4) {
-      children = read_dev(ctr.p + 1, s);
+      children = read_dev(ctr + 1, s);
       if (entering[lv - 1]) {
         // the entering strings' own children
-        DBuf<uint64_t> extra;
-        extra.need(1, s);
-        launch_zero(extra.p, sizeof(uint64_t), s);
-        launch_xs_count(sym[cur ^ 1].p + children_before(m_next, entering[lv - 1]),
-                        entering[lv - 1], off_below, extra.p, s);
-        children += read_dev(extra.p, s);
+        launch_zero(extra, sizeof(uint64_t), s);
+        launch_xs_count(sym[cur ^ 1] + children_before(m_next, entering[lv - 1]),
+                        entering[lv - 1], off_below, extra, s);
+        children += read_dev(extra, s);
       }
     }
     cur ^= 1;
     m = m_next;
   }
-  if (entering[0]) launch_xs_enter(cl, cs, ks, 0, str_off.p, nullptr, nullptr, ctr.p, d_out, s);
+  if (entering[0]) launch_xs_enter(cl, cs, ks, 0, str_off, nullptr, nullptr, ctr, d_out, s);
+  if (d_offsets)
+    HIP_CHECK(hipMemcpyAsync(d_offsets, str_off, (ks + 1) * sizeof(uint64_t),
+                             hipMemcpyDeviceToDevice, s));
   sync(s);
 }
 
+// The fixed scratch of lcg_expand_strings_noalloc: one copy per device,
+// reserved when the library's code object is loaded there and kept until the
+// process ends.  Host code must not use the array's name as an address: its
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kNoAllocScratch = 64ull << 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratch];
+
+static uint8_t* scratch_ptr() {
+  static std::mutex mu;
+  static std::unordered_map<int, uint8_t*> per_device;
+  int dev = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = per_device.find(dev);
+  if (it != per_device.end()) return it->second;
+  void* p = nullptr;
+  HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw LcgError{LCG_EHIP, "no device address for the fixed scratch"};
+  per_device.emplace(dev, static_cast<uint8_t*>(p));
+  return static_cast<uint8_t*>(p);
+}
+
+// Serving session: batches admitted at any time are compressed into one
+// running grammar round by round; every step advances each admitted batch by
+// one round (a batch whose sequence is short runs all its remaining rounds),
+// so that a batch admitted while others are deep in their rounds starts at
+// round 1 at once instead of waiting for them to finish.  The batches share
+// g's dictionaries: each phrase is looked up in the level's dictionary and
+// added if absent (App. A.2's BuildGram against a grammar being extended).
+struct Session {
+  struct Entry {
+    uint64_t ticket;
+    uint64_t bytes;  // working-memory bound of the batch
+    std::unique_ptr<Work> w;
+    std::unique_ptr<Cohort> c;
+  };
+  lcg_grammar* g;
+  Opts o;
+  std::vector<Entry> active;  // in admission order
+  uint64_t next_ticket = 1;
+  uint64_t held = 0;          // working-memory bound of the active batches
+  bool failed = false;
+};
+
 }  // namespace lcg
+
+struct lcg_session {
+  lcg::Session s;
+};
 
 using namespace lcg;
 
@@ -1151,13 +1308,119 @@ lcg_status lcg_merge(lcg_grammar_t a, lcg_grammar_t b, hipStream_t stream) {
   });
 }
 
+lcg_status lcg_session_new(lcg_grammar_t g, const lcg_opts* opts, lcg_session_t* out) {
+  return guard([&] {
+    live(g);
+    if (!out) throw LcgError{LCG_EINVAL, "out is NULL"};
+    Opts o = read_opts(opts);
+    if (opts && o.seed != g->seed) throw LcgError{LCG_ESEED, "opts seed differs from the grammar's"};
+    o.mode = LCG_MODE_BATCHED;
+    lcg_session* ss = new lcg_session();
+    ss->s.g = g;
+    ss->s.o = o;
+    *out = ss;
+  });
+}
+
+lcg_status lcg_session_admit(lcg_session_t ss, const uint8_t* d_text, const uint64_t* d_offsets,
+                             uint32_t k, hipStream_t stream, uint32_t* first_index,
+                             uint64_t* ticket) {
+  return guard([&] {
+    if (!ss) throw LcgError{LCG_EINVAL, "session is NULL"};
+    Session& S = ss->s;
+    if (S.failed) throw LcgError{LCG_EINVAL, "the session failed earlier"};
+    lcg_grammar* g = live(S.g);
+    if (!d_text) throw LcgError{LCG_EINVAL, "text is NULL"};
+    std::vector<uint64_t> h_off = fetch_offsets(d_offsets, k, stream);
+    const uint64_t need = build_bytes(h_off[k], k);
+    if (S.o.budget && (need > S.o.budget || (!S.active.empty() && S.held + need > S.o.budget)))
+      throw LcgError{LCG_ENOMEM, "the batch does not fit hbm_budget beside the active ones"};
+    const uint32_t first = g->k;
+    Session::Entry e{S.next_ticket, need, std::make_unique<Work>(), nullptr};
+    // a failure here leaves g as it was (the batch is not admitted)
+    restoring(g, stream, [&] {
+      ++g->version;
+      e.c = std::make_unique<Cohort>(g, d_text, d_offsets, k, h_off, S.o, *e.w, stream);
+    });
+    ++S.next_ticket;
+    S.held += need;
+    S.active.push_back(std::move(e));
+    if (first_index) *first_index = first;
+    if (ticket) *ticket = S.active.back().ticket;
+  });
+}
+
+lcg_status lcg_session_step(lcg_session_t ss, hipStream_t stream, uint64_t* h_done, uint32_t cap,
+                            uint32_t* n_done, uint32_t* n_active) {
+  return guard([&] {
+    if (!ss) throw LcgError{LCG_EINVAL, "session is NULL"};
+    Session& S = ss->s;
+    if (S.failed) throw LcgError{LCG_EINVAL, "the session failed earlier"};
+    lcg_grammar* g = live(S.g);
+    if (cap < S.active.size())
+      throw LcgError{LCG_EINVAL, "h_done has room for fewer tickets than batches are active"};
+    if (!h_done && !S.active.empty()) throw LcgError{LCG_EINVAL, "h_done is NULL"};
+    uint32_t nd = 0;
+    try {
+      if (!S.active.empty()) ++g->version;
+      for (auto& e : S.active) e.c->step(stream);
+      std::vector<Session::Entry> keep;
+      for (auto& e : S.active) {
+        if (e.c->done) {
+          h_done[nd++] = e.ticket;
+          S.held -= e.bytes;
+          e.c.reset();
+          e.w->release_after(stream);
+        } else {
+          keep.push_back(std::move(e));
+        }
+      }
+      S.active = std::move(keep);
+      sync(stream);
+    } catch (...) {
+      // the active batches share the grammar's dictionaries, so one of them
+      // cannot be taken back alone: the session and the grammar are given up
+      (void)hipStreamSynchronize(stream);
+      (void)hipGetLastError();
+      S.failed = true;
+      g->poisoned = true;
+      S.active.clear();
+      throw;
+    }
+    if (n_done) *n_done = nd;
+    if (n_active) *n_active = (uint32_t)S.active.size();
+  });
+}
+
+void lcg_session_free(lcg_session_t ss) {
+  if (!ss) return;
+  if (!ss->s.active.empty()) {
+    // unfinished batches: their strings stay in C, unfinished
+    ss->s.g->poisoned = true;
+    (void)hipDeviceSynchronize();
+  }
+  delete ss;
+}
+
 lcg_status lcg_expand_strings(lcg_grammar_t g, uint32_t j0, uint32_t j1, uint8_t* d_out,
                               uint64_t cap, uint64_t* d_offsets, uint64_t* total,
                               hipStream_t stream) {
   return guard([&] {
     live(g);
     if (!d_out && cap) throw LcgError{LCG_EINVAL, "d_out is NULL"};
-    expand_strings_core(g, j0, j1, d_out, cap, d_offsets, total, stream);
+    PoolXs sc;
+    expand_strings_core(g, j0, j1, d_out, cap, d_offsets, total, stream, sc);
+  });
+}
+
+lcg_status lcg_expand_strings_noalloc(lcg_grammar_t g, uint32_t j0, uint32_t j1, uint8_t* d_out,
+                                      uint64_t cap, uint64_t* d_offsets, uint64_t* total,
+                                      hipStream_t stream) {
+  return guard([&] {
+    live(g);
+    if (!d_out && cap) throw LcgError{LCG_EINVAL, "d_out is NULL"};
+    ArenaXs sc(scratch_ptr(), kNoAllocScratch);
+    expand_strings_core(g, j0, j1, d_out, cap, d_offsets, total, stream, sc, /*prepared=*/true);
   });
 }
 

@@ -27,13 +27,14 @@ _STATUS = {0: "LCG_OK", -1: "LCG_EINVAL", -2: "LCG_ENOMEM", -3: "LCG_ESEED",
 
 # Every symbol include/lcg.h declares (checked by the CPU test suite).
 EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_expand",
-           "lcg_expand_strings", "lcg_tune", "lcg_new",
+           "lcg_expand_strings", "lcg_expand_strings_noalloc", "lcg_tune", "lcg_new",
            "lcg_info", "lcg_level_size", "lcg_level_copy", "lcg_c_copy", "lcg_stats",
            "lcg_stats_clear", "lcg_build_bytes", "lcg_free", "lcg_release_pool", "lcg_last_error",
            "lcg_postprocess", "lcg_slp_size", "lcg_slp_stats", "lcg_slp_device", "lcg_slp_copy",
            "lcg_slp_expand_strings", "lcg_slp_free", "lcg_extract", "lcg_build_file", "lcg_lce",
            "lcg_slp_encode", "lcg_slp_decode", "lcg_symbol_lce", "lcg_set_allocator",
-           "lcg_slp_extract", "lcg_export", "lcg_host_free")
+           "lcg_slp_extract", "lcg_export", "lcg_host_free", "lcg_session_new",
+           "lcg_session_admit", "lcg_session_step", "lcg_session_free")
 
 EXTRACT_MAX = 2048
 
@@ -109,6 +110,17 @@ def lib():
     L.lcg_expand_strings.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, vp, ctypes.c_uint64, vp,
                                      u64p, vp]
     L.lcg_expand_strings.restype = st
+    L.lcg_expand_strings_noalloc.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, vp,
+                                             ctypes.c_uint64, vp, u64p, vp]
+    L.lcg_expand_strings_noalloc.restype = st
+    L.lcg_session_new.argtypes = [vp, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+    L.lcg_session_new.restype = st
+    L.lcg_session_admit.argtypes = [vp, vp, vp, ctypes.c_uint32, vp, u32p, u64p]
+    L.lcg_session_admit.restype = st
+    L.lcg_session_step.argtypes = [vp, vp, u64p, ctypes.c_uint32, u32p, u32p]
+    L.lcg_session_step.restype = st
+    L.lcg_session_free.argtypes = [vp]
+    L.lcg_session_free.restype = None
     L.lcg_tune.argtypes = [vp, vp, ctypes.c_uint32, ctypes.POINTER(Opts), vp, ctypes.POINTER(Opts),
                            ctypes.POINTER(ctypes.c_double)]
     L.lcg_tune.restype = st
@@ -331,6 +343,19 @@ class Grammar:
         return out[:total.value], offs
 
 
+    def expand_strings_noalloc(self, out, offsets=None, j0=0, j1=None, stream=None):
+        """lcg_expand_strings_noalloc: strings j0..j1-1 into the caller's device
+        tensors `out` (uint8) and `offsets` (int64, j1-j0+1, or None), with no
+        device allocation by the library.  Returns the total length."""
+        _, _, k = self.info()
+        j1 = k if j1 is None else j1
+        total = ctypes.c_uint64()
+        _check(lib().lcg_expand_strings_noalloc(
+            self.h, j0, j1, ctypes.c_void_p(out.data_ptr()), out.numel(),
+            None if offsets is None else ctypes.c_void_p(offsets.data_ptr()),
+            ctypes.byref(total), _stream(stream)))
+        return total.value
+
     def extract(self, j, start, length, stream=None):
         """Random access: bytes [start[q], start[q] + length[q]) of string j[q] for every
         query (device tensors or array-likes; 1 <= length <= EXTRACT_MAX).
@@ -544,6 +569,60 @@ def build_into(g, text, offsets, seed=None, flags=0, hbm_budget=0, key_bits=0, t
                                 ctypes.c_void_p(offsets.data_ptr()), offsets.numel() - 1,
                                 ctypes.byref(o), _stream(stream), ctypes.byref(first)))
     return first.value
+
+
+class Session:
+    """Serving session (lcg_session_*): batches admitted at any time are
+    compressed into grammar g round by round, each step advancing every
+    active batch by one round."""
+
+    def __init__(self, g, hbm_budget=0, tail_log2=0, **opts):
+        o = make_opts(g.info()[0], MODE_BATCHED, hbm_budget=hbm_budget, tail_log2=tail_log2,
+                      **opts)
+        h = ctypes.c_void_p()
+        _check(lib().lcg_session_new(g.h, ctypes.byref(o), ctypes.byref(h)))
+        self.h = h.value
+        self.g = g
+        self._inputs = {}       # ticket -> the batch's tensors, kept alive until done
+
+    def admit(self, text, offsets, stream=None):
+        """Admit the strings text[offsets[j]:offsets[j+1]] (device tensors, kept
+        referenced until done).  Returns (C index of the first string, ticket)."""
+        _check_inputs(text, offsets)
+        first = ctypes.c_uint32()
+        ticket = ctypes.c_uint64()
+        _check(lib().lcg_session_admit(self.h, ctypes.c_void_p(text.data_ptr()),
+                                       ctypes.c_void_p(offsets.data_ptr()), offsets.numel() - 1,
+                                       _stream(stream), ctypes.byref(first), ctypes.byref(ticket)))
+        self._inputs[ticket.value] = (text, offsets)
+        return first.value, ticket.value
+
+    def step(self, stream=None):
+        """One round of every active batch: (tickets finished, batches still active)."""
+        cap = max(1, len(self._inputs))
+        done = np.zeros(cap, np.uint64)
+        nd = ctypes.c_uint32()
+        na = ctypes.c_uint32()
+        _check(lib().lcg_session_step(self.h, _stream(stream), _ptr(done, ctypes.c_uint64), cap,
+                                      ctypes.byref(nd), ctypes.byref(na)))
+        out = [int(x) for x in done[:nd.value]]
+        for t in out:
+            self._inputs.pop(t, None)
+        return out, na.value
+
+    def active(self):
+        return len(self._inputs)
+
+    def free(self):
+        if self.h:
+            lib().lcg_session_free(self.h)
+            self.h = None
+            self._inputs.clear()
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.lcg_session_free(self.h)
+            self.h = None
 
 
 def build_file(g, path, chunk_bytes=64 << 20, stream=None, **opts):
