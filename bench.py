@@ -295,9 +295,13 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="only the headline builds: no secondary collection, decompression, "
                          "post-processing, random access, LCE or streaming legs")
-    ap.add_argument("--serving-seconds", type=float, default=4.0,
+    ap.add_argument("--serving-seconds", type=float, default=20.0,
                     help="seconds per offered load of the serving leg (0 = skip)")
-    ap.add_argument("--serving-loads", default="0.5,2,8")
+    ap.add_argument("--serving-requests", type=int, default=2000,
+                    help="at least this many requests per offered load")
+    ap.add_argument("--serving-loads", default="0.5,2,8,max",
+                    help="offered loads in GB/s; max = every request there from the start "
+                         "(the sustained rate is then the capacity)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (lcg_tune) and time the default options")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -730,10 +734,14 @@ def serving_and_cpu(args, out, text, off, seed):
         from paper_2411_12439_amd import serve
         src = datagen.ServingSource()
         rows = []
-        for load in (float(x) for x in args.serving_loads.split(",")):
-            summary, srv, reqs = serve.run_load(src, load, args.serving_seconds)
+        for x in args.serving_loads.split(","):
+            load = None if x.strip() == "max" else float(x)
+            summary, srv, reqs = serve.run_load(src, load, args.serving_seconds if load else 0.0,
+                                                min_requests=args.serving_requests)
             rng = np.random.default_rng(0)
-            sample = rng.choice(len(reqs), size=min(4, len(reqs)), replace=False)
+            cand = serve.checkable(srv, reqs)
+            sample = [cand[i] for i in rng.choice(len(cand), size=min(8, len(cand)),
+                                                  replace=False)]
             summary["alone_vs_mix_checked"] = serve.check_alone_vs_mix(srv, src, reqs, sample)
             rows.append(summary)
             print("[bench] serving %s" % json.dumps(summary), file=sys.stderr, flush=True)

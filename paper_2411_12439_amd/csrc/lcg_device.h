@@ -11,25 +11,30 @@ namespace lcg {
 constexpr uint64_t kP61 = (1ULL << 61) - 1;  // p_i of every level
 constexpr uint64_t kEmpty = ~0ULL;           // free dictionary slot
 constexpr uint32_t kNone = 0xFFFFFFFFu;      // no rank / no occurrence
-constexpr uint64_t kLongTag = 1ULL << 63;    // key bit 63: long phrase (fingerprint key)
+constexpr uint64_t kLongTag = 1ULL << 63;    // key bit 63: not a short exact key
+constexpr uint64_t kWideTag = 1ULL << 62;    // with bit 63: wide exact key (content in the slot)
 constexpr uint64_t kHiMask = 0xFFFFFFFF00000000ULL;
 
-// One dictionary slot (16 bytes).  w0 is the claimed word:
+// One dictionary slot (32 bytes).  w0 is the claimed word:
 //   short phrase : exact key (bit 63 = 0), never equal to kEmpty;
-//   long phrase  : kLongTag | h31 << 32 | ref, where h31 is 31 bits of the
-//                  phrase fingerprint and ref is the phrase occurrence that
-//                  claimed the slot while the round runs, or the rule's rank
-//                  once committed.
+//   wide phrase  : kLongTag | kWideTag | qcode << 59 | h27 << 32 | ref, the
+//                  content in c0, c1 (see wide keys below);
+//   long phrase  : kLongTag | h30 << 32 | ref, where h30 is 30 bits of the
+//                  phrase fingerprint;
+// ref is the phrase occurrence that claimed the slot while the round runs,
+// or the rule's rank once committed.
 // While the rule is uncommitted (rank == kNone), minocc is the smallest
 // occurrence index holding the phrase in the running round (its first
 // occurrence); once committed, the same word holds the rule's fingerprint F,
-// so that (F, rank) is one 8-byte load.
+// so that (F, rank) is one 8-byte load.  c0, c1 hold a wide phrase's content
+// (kEmpty until its claimer has written them); other slots leave them empty.
 struct Slot {
   uint64_t w0;
   uint32_t minocc;
   uint32_t rank;
+  uint64_t c0, c1;
 };
-static_assert(sizeof(Slot) == 16, "slot layout");
+static_assert(sizeof(Slot) == 32, "slot layout");
 
 // Coefficients of one level of the hash family.
 struct LevelHash {
@@ -74,12 +79,35 @@ __device__ __forceinline__ int rank_bits_for(uint32_t q) {
   return q == 1 ? 32 : q == 2 ? 29 : q == 3 ? 19 : q == 4 ? 14 : 0;
 }
 
-// The long-phrase key: tag plus 31 bits of the 61-bit fingerprint P
+// The long-phrase key: tag plus 30 bits of the 61-bit fingerprint P
 // (optionally truncated by the key_bits test hook).
 __device__ __forceinline__ uint64_t long_key(uint64_t P, uint32_t key_bits) {
-  uint64_t h = (P >> 29) & 0x7FFFFFFFULL;
+  uint64_t h = (P >> 29) & 0x3FFFFFFFULL;
   if (key_bits) h &= (1ULL << key_bits) - 1;
   return kLongTag | (h << 32);
+}
+
+// Wide exact keys: phrases too long for a short key but whose content fits
+// two 62-bit words c0, c1 (bit 63 of both stays clear, so a valid word never
+// equals kEmpty).  Level 1: 8..14 bytes, seven in each word (qcode = q - 8);
+// levels >= 2: at most four ranks below 2^31, two in each word (qcode =
+// q - 1).  Equal (qcode, c0, c1) means equal phrases.  The key word carries
+// the tags, qcode and 27 bits of a mix of the content, which place the
+// phrase in the table; a match of the key word is confirmed on c0, c1.
+constexpr uint64_t kWideMaxBytes = 14;
+constexpr uint32_t kWideMaxRanks = 4;
+__host__ __device__ __forceinline__ uint64_t wide_key(uint64_t qcode, uint64_t c0, uint64_t c1) {
+  const uint64_t h = mix64(c0 * 0x9E3779B97F4A7C15ULL ^ c1 ^ (qcode << 60)) >> 37;  // 27 bits
+  return kLongTag | kWideTag | (qcode << 59) | (h << 32);
+}
+__host__ __device__ __forceinline__ bool is_wide(uint64_t kk) {
+  return (kk & (kLongTag | kWideTag)) == (kLongTag | kWideTag);
+}
+__host__ __device__ __forceinline__ bool is_long(uint64_t kk) {
+  return (kk & (kLongTag | kWideTag)) == kLongTag;
+}
+__host__ __device__ __forceinline__ uint32_t wide_qcode(uint64_t kk) {
+  return (uint32_t)((kk >> 59) & 7);
 }
 
 }  // namespace lcg

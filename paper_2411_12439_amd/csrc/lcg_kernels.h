@@ -56,8 +56,8 @@ void launch_classify(const RoundIn& in, uint64_t* bits, uint64_t* tile_cnt, Tile
                      hipStream_t s);
 void launch_emit(const RoundIn& in, const uint64_t* bits, const uint64_t* tile_base,
                  const TileSeg* tile_seg, LevelHash h,
-                 uint32_t key_bits, uint64_t* pstart, uint32_t* plen, uint64_t* key, uint32_t* fnew,
-                 uint8_t* hll_part, Counters* ctr, hipStream_t s);
+                 uint32_t key_bits, uint64_t* pstart, uint32_t* plen, uint64_t* key, uint64_t* wkey,
+                 uint32_t* fnew, uint8_t* hll_part, Counters* ctr, hipStream_t s);
 
 // Exclusive scan of n uint64 values into out[0..n]; out[n] receives the total.
 // tmp must hold scan_tmp_words(n) uint64.
@@ -75,29 +75,37 @@ void scan_one(const uint64_t* in, uint64_t* out, uint64_t count, const uint64_t*
 // memory, the host passes a bound of it in d / in.n) are launched over the
 // bound and stop at the count: rounds can then be queued without reading
 // sizes back.
-// won: room for d slot indices; every slot the insert claims is listed there
-// (count in ctr->won_len, zero on entry).
+// The slots an insert over (a bound of) d phrases claims are listed per wave
+// of its grid, with no atomics: wave v writes its claims from won + v *
+// per_wave and their number to won_cnt[v].  won needs waves * per_wave
+// entries (at most d + 256 * kInsertBlocks), won_cnt `waves`.
+constexpr uint64_t kInsertBlocks = 2048;  // largest grid of the insert
+struct WonGeom {
+  uint32_t waves;
+  uint64_t per_wave;
+};
+WonGeom won_geometry(uint64_t d);
+// The combining insert lists its claims in won2 (room for the table's
+// capacity; count in ctr->won_len, zero on entry).
 void launch_insert(bool bytes, uint64_t d, const uint64_t* d_dev, const uint64_t* key,
-                   const uint64_t* pstart, const uint32_t* plen, const void* content,
-                   const uint64_t* rule_off, const void* rule_rhs, uint32_t u_committed,
-                   Slot* table, uint64_t mask, uint32_t* slot_idx, bool combine, uint32_t* rest,
-                   uint32_t* rest_len, uint32_t* won, Counters* ctr, hipStream_t s);
-// First-occurrence flags of the new phrases from the insert's won list (the
+                   const uint64_t* wkey, const uint64_t* pstart, const uint32_t* plen,
+                   const void* content, const uint64_t* rule_off, const void* rule_rhs,
+                   uint32_t u_committed, Slot* table, uint64_t mask, uint32_t* slot_idx,
+                   bool combine, uint32_t* rest, uint32_t* rest_len, uint32_t* won,
+                   uint32_t* won_cnt, uint32_t* won2, Counters* ctr, hipStream_t s);
+// First-occurrence flags of the new phrases from the insert's claims (the
 // first occurrence of every slot claimed in the round is new), then per flag
-// word the new rules and their right-hand-side lengths.  W: flag words to
-// fill (a bound of ceil(d / 64) when the count is on the device).
-void launch_newflags_won(bool bytes, const uint32_t* won, const Counters* ctr, const Slot* table,
-                         uint64_t W, const uint64_t* key, const uint32_t* plen, uint64_t* newbits,
+// word the new rules and their right-hand-side lengths.  d: the insert's
+// phrase bound; W: flag words to fill (a bound of ceil(d / 64) when the
+// count is on the device).
+void launch_newflags_won(bool bytes, uint64_t d, const uint32_t* won, const uint32_t* won_cnt,
+                         const uint32_t* won2, const Counters* ctr, const Slot* table, uint64_t W,
+                         const uint64_t* key, const uint32_t* plen, uint64_t* newbits,
                          uint64_t* wcnt, uint64_t* wlen, hipStream_t s);
-void launch_newflags(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t* slot_idx,
-                     const Slot* table, const uint64_t* key, const uint32_t* plen,
-                     uint64_t* newbits, uint64_t* wcnt, uint64_t* wlen, hipStream_t s);
-void launch_newflags_table(bool bytes, const Slot* table, uint64_t cap, uint64_t d,
-                           const uint64_t* key, const uint32_t* plen, uint64_t* newbits,
-                           uint64_t* wcnt, uint64_t* wlen, hipStream_t s);
 void launch_commit(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t* slot_idx, Slot* table,
                    const uint64_t* newbits, const uint64_t* wcnt_base, const uint64_t* wlen_base,
-                   const uint64_t* key, const uint64_t* pstart, const uint32_t* plen,
+                   const uint64_t* key, const uint64_t* wkey, const uint64_t* pstart,
+                   const uint32_t* plen,
                    const void* content, const uint32_t* fnew, const uint32_t* fprev, LevelHash h,
                    uint32_t u_prev, uint64_t q_prev, uint64_t* rule_off, void* rule_rhs,
                    uint32_t* rule_fp, uint32_t* sym_next, uint32_t* fnext, uint64_t u_new,
@@ -123,7 +131,7 @@ void launch_finish(const uint64_t* off, const uint64_t* new_off, uint32_t k,
 void launch_merge_prepare(bool bytes, uint32_t u_b, const uint64_t* b_off, const void* b_rhs,
                           const uint32_t* remap_prev, const uint32_t* f_prev, LevelHash h,
                           uint32_t key_bits, void* content, uint64_t* pstart, uint32_t* plen,
-                          uint64_t* key, hipStream_t s);
+                          uint64_t* key, uint64_t* wkey, hipStream_t s);
 void launch_c_merge(const uint8_t* b_level, const uint32_t* b_sym, uint32_t kb, uint32_t level,
                     const uint32_t* remap, uint8_t* out_level, uint32_t* out_sym, hipStream_t s);
 

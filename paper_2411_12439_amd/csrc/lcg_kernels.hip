@@ -157,20 +157,69 @@ __device__ __forceinline__ bool exact_key(const void* sym, uint64_t p, uint64_t 
   }
 }
 
-// Dictionary key of a phrase with fingerprint P.
+// Content words of a wide key for the phrase sym[p .. p+q), if it has one
+// (see lcg_device.h): 8..14 bytes at level 1, at most four ranks below 2^31
+// above.  *qcode receives the length code.
+template <bool BYTES>
+__device__ __forceinline__ bool wide_content(const void* sym, uint64_t p, uint64_t q,
+                                             uint64_t& c0, uint64_t& c1, uint64_t& qcode) {
+  c0 = 0;
+  c1 = 0;
+  if constexpr (BYTES) {
+    if (q < 8 || q > kWideMaxBytes) return false;
+    const uint8_t* s = static_cast<const uint8_t*>(sym) + p;
+#pragma unroll
+    for (uint32_t x = 0; x < kWideMaxBytes; ++x) {
+      const uint64_t b = x < q ? (uint64_t)s[x] : 0;
+      if (x < 7) c0 |= b << (8 * x);
+      else c1 |= b << (8 * (x - 7));
+    }
+    qcode = q - 8;
+    return true;
+  } else {
+    if (q > kWideMaxRanks) return false;
+    const uint32_t* s = static_cast<const uint32_t*>(sym) + p;
+    bool fits = true;
+#pragma unroll
+    for (uint32_t x = 0; x < kWideMaxRanks; ++x) {
+      const uint64_t r = x < q ? (uint64_t)s[x] : 0;
+      fits = fits && (r >> 31) == 0;
+      if (x < 2) c0 |= r << (31 * x);
+      else c1 |= r << (31 * (x - 2));
+    }
+    qcode = q - 1;
+    return fits;
+  }
+}
+
+// Dictionary key of a phrase with fingerprint P; a wide key's content goes
+// to wk[0..1].
 template <bool BYTES>
 __device__ __forceinline__ uint64_t make_key(const void* sym, uint64_t p, uint64_t q, uint64_t P,
-                                             uint32_t key_bits) {
-  uint64_t k;
+                                             uint32_t key_bits, uint64_t* wk) {
+  uint64_t k, c0, c1, qc;
   if (key_bits == 0 && exact_key<BYTES>(sym, p, q, k)) return k;
+  if (key_bits == 0 && wide_content<BYTES>(sym, p, q, c0, c1, qc)) {
+    wk[0] = c0;
+    wk[1] = c1;
+    return wide_key(qc, c0, c1);
+  }
   return long_key(P, key_bits);
 }
 
-// Length of a phrase from its key (exact keys) or from plen (long keys).
+// Length of a phrase from its key (exact and wide keys) or from plen (long keys).
 template <bool BYTES>
 __device__ __forceinline__ uint32_t key_len(uint64_t kk, const uint32_t* plen, uint64_t o) {
+  if (is_wide(kk)) return wide_qcode(kk) + (BYTES ? 8u : 1u);
   if (kk & kLongTag) return plen[o];
   return BYTES ? (uint32_t)((kk >> 56) & 7) : (uint32_t)((kk >> 58) & 7);
+}
+
+// Symbol x of a wide key's content.
+template <bool BYTES>
+__device__ __forceinline__ uint32_t wide_sym(uint64_t c0, uint64_t c1, uint32_t x) {
+  if constexpr (BYTES) return (uint32_t)((x < 7 ? c0 >> (8 * x) : c1 >> (8 * (x - 7))) & 0xFF);
+  else return (uint32_t)((x < 2 ? c0 >> (31 * x) : c1 >> (31 * (x - 2))) & 0x7FFFFFFFu);
 }
 
 // Symbol x of a phrase with an exact key.
@@ -201,7 +250,7 @@ void launch_f0_lut(uint32_t* lut, uint64_t a0, uint64_t b0, hipStream_t s) {
 __global__ void k_fill_slots(Slot* t, uint64_t cap) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap;
        i += (uint64_t)gridDim.x * blockDim.x)
-    t[i] = Slot{kEmpty, kNone, kNone};
+    t[i] = Slot{kEmpty, kNone, kNone, kEmpty, kEmpty};
 }
 
 void launch_fill_slots(Slot* t, uint64_t cap, hipStream_t s) {
@@ -655,7 +704,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in0, const uint64_t* __
                                                  const TileSeg* __restrict__ tile_seg, uint64_t tiles,
                                                  LevelHash h, uint32_t key_bits,
                                                  uint64_t* __restrict__ pstart, uint32_t* __restrict__ plen,
-                                                 uint64_t* __restrict__ key, uint32_t* __restrict__ fnew,
+                                                 uint64_t* __restrict__ key, uint64_t* __restrict__ wkey,
+                                                 uint32_t* __restrict__ fnew,
                                                  uint8_t* __restrict__ hll_part) {
   __shared__ uint32_t s_lut[256];
   __shared__ uint16_t s_start[kTile];
@@ -711,18 +761,29 @@ __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in0, const uint64_t* __
       const uint64_t l = t0 + s_start[jj];
       const uint64_t e = phrase_end(jj, c, t0, s_start, slo, shi, cached, s_off, in.off, bits);
       const uint64_t q = e - l;
-      uint64_t kk = 0;
-      bool exact = false;
+      uint64_t kk = 0, c0 = 0, c1 = 0, qc = 0;
+      bool exact = false, wide = false;
       if (key_bits == 0) {
-        if (e <= t0 + kStage) {
+        const bool staged = e <= t0 + kStage;
+        if (staged) {
           exact = exact_key_staged(st.sym, (uint32_t)(l - t0), q, kk);
         } else {
           exact = exact_key<BYTES>(in.sym, l, q, kk);
         }
+        // too long for a short key: a wide key if its content fits two words
+        if (!exact)
+          wide = staged ? wide_content<BYTES>(st.sym, l - t0, q, c0, c1, qc)
+                        : wide_content<BYTES>(in.sym, l, q, c0, c1, qc);
       }
       if (exact) {
         key[base + jj] = kk;
         hll_add(s_hll, kk);
+      } else if (wide) {
+        const uint64_t o = base + jj;
+        key[o] = wide_key(qc, c0, c1);
+        wkey[2 * o] = c0;
+        wkey[2 * o + 1] = c1;
+        hll_add(s_hll, c0 ^ mix64(c1 + (qc << 60)));
       } else {
         const uint32_t slot = atomicAdd(&s_nlong, 1u);
         if (slot < kLongList) {
@@ -781,18 +842,18 @@ __global__ __launch_bounds__(256) void k_hll_reduce(const uint8_t* __restrict__ 
 
 void launch_emit(const RoundIn& in, const uint64_t* bits, const uint64_t* tile_base,
                  const TileSeg* tile_seg, LevelHash h,
-                 uint32_t key_bits, uint64_t* pstart, uint32_t* plen, uint64_t* key, uint32_t* fnew,
-                 uint8_t* hll_part, Counters* ctr, hipStream_t s) {
+                 uint32_t key_bits, uint64_t* pstart, uint32_t* plen, uint64_t* key, uint64_t* wkey,
+                 uint32_t* fnew, uint8_t* hll_part, Counters* ctr, hipStream_t s) {
   uint64_t tiles = grid_for(in.n, kTile);
   unsigned g = resident_blocks(in.bytes ? (const void*)k_emit<true> : (const void*)k_emit<false>, kBlock);
   if (g > kEmitBlocks) g = kEmitBlocks;  // rows of hll_part
   if (g > tiles) g = (unsigned)tiles;
   if (in.bytes)
     k_emit<true><<<g, kBlock, 0, s>>>(in, bits, tile_base, tile_seg, tiles, h, key_bits, pstart, plen, key,
-                                      fnew, hll_part);
+                                      wkey, fnew, hll_part);
   else
     k_emit<false><<<g, kBlock, 0, s>>>(in, bits, tile_base, tile_seg, tiles, h, key_bits, pstart, plen, key,
-                                       fnew, hll_part);
+                                       wkey, fnew, hll_part);
   LCG_LAUNCH_CHECK("emit");
   if (ctr) {
     k_hll_reduce<<<kHll, 256, 0, s>>>(hll_part, g, ctr);
@@ -942,14 +1003,20 @@ __device__ __forceinline__ bool same_seq(const Sym* a, const Sym* b, uint32_t le
   return diff == 0;
 }
 
-// Insert-or-find every phrase.  A claimed slot keeps the claimer's key; a
-// long phrase whose 31 key bits match is compared symbol by symbol against
-// the slot's phrase (the claiming occurrence, or the committed rule).
+// Insert-or-find every phrase.  A claimed slot keeps the claimer's key.  A
+// wide phrase whose key word matches is confirmed on its two content words:
+// the slot's own copy (written by the claimer right after its claim, and by
+// every earlier round), or, while that copy is not visible yet, the claiming
+// occurrence's (each content word is written once, from empty to its value,
+// so two non-empty words are the whole content).  A long phrase whose 30
+// fingerprint bits match is compared symbol by symbol against the slot's
+// phrase (the claiming occurrence, or the committed rule).
 //
 // The claimed word of a slot never changes during the kernel, so it is read
-// with a plain (L1-cacheable) load: frequent short phrases are then served by
-// each CU's L1 instead of one L2 line.  A stale empty word only sends the
-// thread to the compare-and-swap, which returns the current value.
+// with a workgroup-scope atomic load (L1-cacheable): frequent short phrases
+// are then served by each CU's L1 instead of one L2 line.  A stale empty word
+// only sends the thread to the compare-and-swap, which returns the current
+// value.
 //
 // One phrase per thread and iteration (batches of several measured slower on
 // gfx950: they cost more in occupancy than they gain in overlap).  The probe
@@ -967,6 +1034,7 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t begin, uint64_t end, ui
                                                 const uint32_t* __restrict__ list,
                                                 const uint32_t* __restrict__ list_len,
                                                 const uint64_t* __restrict__ key,
+                                                const uint64_t* __restrict__ wkey,
                                                 const uint64_t* __restrict__ pstart,
                                                 const uint32_t* __restrict__ plen,
                                                 const Sym* __restrict__ content,
@@ -975,6 +1043,8 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t begin, uint64_t end, ui
                                                 Slot* table, uint64_t mask,
                                                 uint32_t* __restrict__ slot_idx,
                                                 uint32_t* __restrict__ won_list,
+                                                uint64_t won_per_wave,
+                                                uint32_t* __restrict__ won_cnt,
                                                 Counters* __restrict__ ctr) {
   __shared__ unsigned long long s_sum[4];
   if (threadIdx.x < 4) s_sum[threadIdx.x] = 0;
@@ -983,21 +1053,35 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t begin, uint64_t end, ui
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   if constexpr (DEV_COUNT) end = d = *d_dev;  // launched over a bound; the count is on the device
   const uint64_t lim = list ? (uint64_t)*list_len : end;
-  for (uint64_t i = begin + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < lim; i += stride) {
+  // every wave walks its own phrases (the same trip count for all its lanes)
+  // and lists the slots it claims in its own region of the won list
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t wave = blockIdx.x * (uint64_t)(blockDim.x / 64) + (threadIdx.x >> 6);
+  uint32_t* const my_won = won_list + wave * won_per_wave;
+  uint32_t nwon = 0;
+  for (uint64_t wb = begin + wave * 64; wb < lim; wb += stride) {
+    const uint64_t i = wb + lane;
+    uint32_t result = kNone;
+    bool claimed = false;
+    if (i < lim) {
     const uint64_t o = list ? (uint64_t)list[i] : i;
     const uint64_t kk = __builtin_nontemporal_load(&key[o]);  // streams past L1
     uint64_t pos = mix64(kk) & mask;
     uint64_t w = hint_load(&table[pos].w0);
-    const bool is_long = (kk & kLongTag) != 0;
-    const uint64_t want = is_long ? (kk | o) : kk;
-    uint64_t my_pos = 0;
+    const bool tagged = (kk & kLongTag) != 0;  // wide or long: the slot word carries a reference
+    const bool wide = is_wide(kk);
+    const bool is_long = tagged && !wide;
+    const uint64_t want = tagged ? (kk | o) : kk;
+    uint64_t my_pos = 0, my_c0 = 0, my_c1 = 0;
     uint32_t my_len = 0;
     if (is_long) {
       my_pos = pstart[o];
       my_len = plen[o];
     }
-    uint32_t result = kNone;
-    bool claimed = false;
+    if (wide) {
+      my_c0 = wkey[2 * o];
+      my_c1 = wkey[2 * o + 1];
+    }
     for (uint32_t probe = 0; probe < kMaxProbe && result == kNone; ++probe) {
       Slot* sl = &table[pos];
       ++probes;
@@ -1011,13 +1095,30 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t begin, uint64_t end, ui
           hit = true;
           claimed = true;
           ++won;
+          if (wide) {  // the content beside the claim, for the phrases that follow
+            __hip_atomic_store(&sl->c0, my_c0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&sl->c1, my_c1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
         } else {
           w = prev;
         }
       }
       if (!hit) {
-        if (!is_long) {
+        if (!tagged) {
           hit = w == kk;
+        } else if (wide) {
+          if ((w & kHiMask) == kk) {
+            uint64_t c0 = hint_load(&sl->c0), c1 = hint_load(&sl->c1);
+            if (c0 == kEmpty || c1 == kEmpty) {
+              // not visible here yet: the claim is from this pass (a committed
+              // rule's content was written by an earlier kernel), so the
+              // claiming occurrence has the same content words
+              const uint32_t ref = (uint32_t)w;
+              c0 = ref < d ? wkey[2 * (uint64_t)ref] : ~my_c0;
+              c1 = ref < d ? wkey[2 * (uint64_t)ref + 1] : ~my_c1;
+            }
+            hit = c0 == my_c0 && c1 == my_c1;
+          }
         } else if ((w & kHiMask) == kk) {
           const uint32_t rk = hint_load(&sl->rank);
           const uint32_t ref = (uint32_t)w;
@@ -1055,8 +1156,12 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t begin, uint64_t end, ui
         atomicMin(&sl->minocc, (uint32_t)o);
     }
     __builtin_nontemporal_store(result, &slot_idx[o]);
-    push_won(claimed, result, won_list, &ctr->won_len);
+    }
+    const uint64_t bal = __ballot(claimed);
+    if (claimed) my_won[nwon + __builtin_popcountll(bal & ((1ull << lane) - 1ull))] = result;
+    nwon += (uint32_t)__builtin_popcountll(bal);
   }
+  if (lane == 0) won_cnt[wave] = nwon;
   // one global atomic per block and counter
   won = wave_sum(won);
   probes = wave_sum(probes);
@@ -1248,12 +1353,22 @@ __global__ __launch_bounds__(256) void k_insert_comb(uint64_t begin, uint64_t en
 // occurrence from its L1).  What k_insert_comb leaves (rest, count
 // *rest_len, zero on entry) then goes through k_insert.  Otherwise one
 // k_insert launch takes all d phrases.
+WonGeom won_geometry(uint64_t d) {
+  if (!d) return WonGeom{0, 0};
+  uint64_t g = (d + 255) / 256;
+  if (g > kPersistentBlocks) g = kPersistentBlocks;
+  const uint64_t stride = g * 256;
+  return WonGeom{(uint32_t)(g * 4), 64 * ((d + stride - 1) / stride)};
+}
+
 void launch_insert(bool bytes, uint64_t d, const uint64_t* d_dev, const uint64_t* key,
-                   const uint64_t* pstart, const uint32_t* plen, const void* content,
-                   const uint64_t* rule_off, const void* rule_rhs, uint32_t u_committed,
-                   Slot* table, uint64_t mask, uint32_t* slot_idx, bool combine, uint32_t* rest,
-                   uint32_t* rest_len, uint32_t* won, Counters* ctr, hipStream_t s) {
+                   const uint64_t* wkey, const uint64_t* pstart, const uint32_t* plen,
+                   const void* content, const uint64_t* rule_off, const void* rule_rhs,
+                   uint32_t u_committed, Slot* table, uint64_t mask, uint32_t* slot_idx,
+                   bool combine, uint32_t* rest, uint32_t* rest_len, uint32_t* won,
+                   uint32_t* won_cnt, uint32_t* won2, Counters* ctr, hipStream_t s) {
   if (!d) return;
+  const WonGeom geo = won_geometry(d);
   if (d_dev && combine) throw std::runtime_error("insert: combining needs the count on the host");
   const uint32_t* list = nullptr;
   const uint32_t* list_len = nullptr;
@@ -1264,7 +1379,7 @@ void launch_insert(bool bytes, uint64_t d, const uint64_t* d_dev, const uint64_t
          begin = end, end = end * 16 < d ? end * 16 : d) {
       unsigned gc = grid_for(end - begin, kCombChunk);
       if (gc > r) gc = r;
-      k_insert_comb<<<gc, 256, 0, s>>>(begin, end, key, table, mask, slot_idx, rest, rest_len, won,
+      k_insert_comb<<<gc, 256, 0, s>>>(begin, end, key, table, mask, slot_idx, rest, rest_len, won2,
                                        ctr);
       LCG_LAUNCH_CHECK("insert_comb");
     }
@@ -1272,88 +1387,31 @@ void launch_insert(bool bytes, uint64_t d, const uint64_t* d_dev, const uint64_t
     list_len = rest_len;
   }
   if (g > kPersistentBlocks) g = kPersistentBlocks;
+  if (g * 4 != geo.waves) throw std::runtime_error("insert: grid differs from the won geometry");
   const uint8_t* c8 = static_cast<const uint8_t*>(content);
   const uint8_t* r8 = static_cast<const uint8_t*>(rule_rhs);
   const uint32_t* c32 = static_cast<const uint32_t*>(content);
   const uint32_t* r32 = static_cast<const uint32_t*>(rule_rhs);
   if (bytes && d_dev)
-    k_insert<uint8_t, true><<<g, 256, 0, s>>>(0, d, d, d_dev, list, list_len, key, pstart, plen, c8,
-                                              rule_off, r8, u_committed, table, mask, slot_idx, won, ctr);
+    k_insert<uint8_t, true><<<g, 256, 0, s>>>(0, d, d, d_dev, list, list_len, key, wkey, pstart, plen, c8,
+                                              rule_off, r8, u_committed, table, mask, slot_idx, won, geo.per_wave,
+                                              won_cnt, ctr);
   else if (bytes)
-    k_insert<uint8_t, false><<<g, 256, 0, s>>>(0, d, d, d_dev, list, list_len, key, pstart, plen, c8,
-                                               rule_off, r8, u_committed, table, mask, slot_idx, won, ctr);
+    k_insert<uint8_t, false><<<g, 256, 0, s>>>(0, d, d, d_dev, list, list_len, key, wkey, pstart, plen, c8,
+                                               rule_off, r8, u_committed, table, mask, slot_idx, won, geo.per_wave,
+                                              won_cnt, ctr);
   else if (d_dev)
-    k_insert<uint32_t, true><<<g, 256, 0, s>>>(0, d, d, d_dev, list, list_len, key, pstart, plen,
-                                               c32, rule_off, r32, u_committed, table, mask,
-                                               slot_idx, won, ctr);
+    k_insert<uint32_t, true><<<g, 256, 0, s>>>(0, d, d, d_dev, list, list_len, key, wkey, pstart,
+                                               plen, c32, rule_off, r32, u_committed, table, mask,
+                                               slot_idx, won, geo.per_wave, won_cnt, ctr);
   else
-    k_insert<uint32_t, false><<<g, 256, 0, s>>>(0, d, d, d_dev, list, list_len, key, pstart, plen,
-                                                c32, rule_off, r32, u_committed, table, mask,
-                                                slot_idx, won, ctr);
+    k_insert<uint32_t, false><<<g, 256, 0, s>>>(0, d, d, d_dev, list, list_len, key, wkey, pstart,
+                                                plen, c32, rule_off, r32, u_committed, table, mask,
+                                                slot_idx, won, geo.per_wave, won_cnt, ctr);
   LCG_LAUNCH_CHECK("insert");
 }
 
 // ------------------------------------------------------------------ newflags
-template <bool BYTES>
-__global__ __launch_bounds__(256) void k_newflags(uint64_t d, const uint64_t* __restrict__ d_dev,
-                                                  const uint32_t* __restrict__ slot_idx,
-                                                  const Slot* __restrict__ table,
-                                                  const uint64_t* __restrict__ key,
-                                                  const uint32_t* __restrict__ plen,
-                                                  uint64_t* __restrict__ newbits,
-                                                  uint64_t* __restrict__ wcnt,
-                                                  uint64_t* __restrict__ wlen) {
-  if (d_dev) d = *d_dev;
-  const uint64_t o = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (((o >> 6) << 6) >= d) return;  // the whole wave is past the end
-  bool f = false;
-  unsigned long long len = 0;
-  if (o < d) {
-    const uint32_t sidx = slot_idx[o];
-    if (sidx != kNone) {
-      const Slot sl = table[sidx];
-      f = sl.rank == kNone && sl.minocc == (uint32_t)o;
-    }
-    if (f) len = key_len<BYTES>(key[o], plen, o);
-  }
-  const uint64_t bal = __ballot(f);
-  len = wave_sum(len);
-  const uint64_t w = o >> 6;
-  if ((threadIdx.x & 63) == 0 && (w << 6) < d) {
-    newbits[w] = bal;
-    wcnt[w] = __builtin_popcountll(bal);
-    wlen[w] = len;
-  }
-}
-
-void launch_newflags(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t* slot_idx,
-                     const Slot* table, const uint64_t* key, const uint32_t* plen,
-                     uint64_t* newbits, uint64_t* wcnt, uint64_t* wlen, hipStream_t s) {
-  if (!d) return;
-  if (bytes)
-    k_newflags<true><<<grid_for(d, 256), 256, 0, s>>>(d, d_dev, slot_idx, table, key, plen, newbits,
-                                                      wcnt, wlen);
-  else
-    k_newflags<false><<<grid_for(d, 256), 256, 0, s>>>(d, d_dev, slot_idx, table, key, plen,
-                                                       newbits, wcnt, wlen);
-  LCG_LAUNCH_CHECK("newflags");
-}
-
-// The same flags from the table side, for tables smaller than the phrase
-// array: every slot claimed in this pass marks its first occurrence.
-// newbits must be zero on entry; k_word_counts then takes each word's counts.
-__global__ __launch_bounds__(256) void k_newflags_table(const Slot* __restrict__ table, uint64_t cap,
-                                                        uint64_t d,
-                                                        unsigned long long* __restrict__ newbits) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    const Slot sl = table[i];
-    if (sl.w0 == kEmpty || sl.rank != kNone || sl.minocc >= d) continue;
-    const uint64_t m = sl.minocc;
-    atomicOr(&newbits[m >> 6], 1ULL << (m & 63));
-  }
-}
-
 // Per flag word: its new rules and their right-hand-side lengths (the keys of
 // one word's phrases lie side by side).
 template <bool BYTES>
@@ -1373,44 +1431,45 @@ __global__ void k_word_counts(const uint64_t* __restrict__ newbits, uint64_t W,
   wlen[w] = len;
 }
 
-void launch_newflags_table(bool bytes, const Slot* table, uint64_t cap, uint64_t d,
-                           const uint64_t* key, const uint32_t* plen, uint64_t* newbits,
-                           uint64_t* wcnt, uint64_t* wlen, hipStream_t s) {
-  if (!d) return;
-  const uint64_t W = (d + 63) / 64;
-  launch_zero(newbits, W * 8, s);
-  unsigned g = grid_for(cap, 256);
-  if (g > 8192) g = 8192;
-  k_newflags_table<<<g, 256, 0, s>>>(table, cap, d, reinterpret_cast<unsigned long long*>(newbits));
-  LCG_LAUNCH_CHECK("newflags_table");
-  if (bytes)
-    k_word_counts<true><<<grid_for(W, 256), 256, 0, s>>>(newbits, W, key, plen, wcnt, wlen);
-  else
-    k_word_counts<false><<<grid_for(W, 256), 256, 0, s>>>(newbits, W, key, plen, wcnt, wlen);
-  LCG_LAUNCH_CHECK("word_counts");
-}
-
 // The first occurrence of every slot claimed in the round marks its phrase
-// new (newbits zero on entry).
+// new (newbits zero on entry): the combining insert's list (won2, count in
+// ctr->won_len), then the regions of the insert's waves (region v holds
+// won_cnt[v] slots from won + v * per_wave).
 __global__ __launch_bounds__(256) void k_newflags_won(const uint32_t* __restrict__ won,
+                                                      const uint32_t* __restrict__ won_cnt,
+                                                      uint32_t waves, uint64_t per_wave,
+                                                      const uint32_t* __restrict__ won2,
                                                       const Counters* __restrict__ ctr,
                                                       const Slot* __restrict__ table,
                                                       unsigned long long* __restrict__ newbits) {
-  const uint32_t n = ctr->won_len;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const uint64_t m = table[won[i]].minocc;
+  const uint32_t n2 = ctr->won_len;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += gridDim.x * blockDim.x) {
+    const uint64_t m = table[won2[i]].minocc;
     atomicOr(&newbits[m >> 6], 1ULL << (m & 63));
+  }
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t nw = gridDim.x * (blockDim.x / 64);
+  for (uint32_t v = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); v < waves; v += nw) {
+    const uint32_t c = won_cnt[v];
+    const uint32_t* r = won + (uint64_t)v * per_wave;
+    for (uint32_t i = lane; i < c; i += 64) {
+      const uint64_t m = table[r[i]].minocc;
+      atomicOr(&newbits[m >> 6], 1ULL << (m & 63));
+    }
   }
 }
 
-void launch_newflags_won(bool bytes, const uint32_t* won, const Counters* ctr, const Slot* table,
-                         uint64_t W, const uint64_t* key, const uint32_t* plen, uint64_t* newbits,
+void launch_newflags_won(bool bytes, uint64_t d, const uint32_t* won, const uint32_t* won_cnt,
+                         const uint32_t* won2, const Counters* ctr, const Slot* table, uint64_t W,
+                         const uint64_t* key, const uint32_t* plen, uint64_t* newbits,
                          uint64_t* wcnt, uint64_t* wlen, hipStream_t s) {
-  if (!W) return;
+  if (!W || !d) return;
+  const WonGeom geo = won_geometry(d);
   launch_zero(newbits, W * 8, s);
-  unsigned g = grid_for(W * 64, 256);
-  if (g > 4096) g = 4096;
-  k_newflags_won<<<g, 256, 0, s>>>(won, ctr, table, reinterpret_cast<unsigned long long*>(newbits));
+  unsigned g = (geo.waves + 3) / 4;
+  if (g > 2048) g = 2048;
+  k_newflags_won<<<g, 256, 0, s>>>(won, won_cnt, geo.waves, geo.per_wave, won2, ctr, table,
+                                   reinterpret_cast<unsigned long long*>(newbits));
   LCG_LAUNCH_CHECK("newflags_won");
   if (bytes)
     k_word_counts<true><<<grid_for(W, 256), 256, 0, s>>>(newbits, W, key, plen, wcnt, wlen);
@@ -1445,6 +1504,7 @@ __device__ __forceinline__ unsigned long long wave_excl_scan(unsigned long long 
 template <typename Sym>
 __device__ __forceinline__ void commit_one(uint64_t o, uint32_t r, uint64_t q, uint64_t kk,
                                            uint32_t L, uint32_t sidx, Slot* table,
+                                           const uint64_t* __restrict__ wkey,
                                            const uint64_t* __restrict__ pstart,
                                            const Sym* __restrict__ content,
                                            const uint32_t* __restrict__ fnew,
@@ -1454,7 +1514,26 @@ __device__ __forceinline__ void commit_one(uint64_t o, uint32_t r, uint64_t q, u
                                            uint32_t* __restrict__ rule_fp) {
   constexpr bool kBytes = sizeof(Sym) == 1;
   uint32_t F;
-  if (kk & kLongTag) {
+  if (is_wide(kk)) {
+    // at most 14 symbols (4 above level 1) from the content words, then Horner
+    constexpr uint32_t kMaxWide = kBytes ? kWideMaxBytes : kWideMaxRanks;
+    const uint64_t c0 = wkey[2 * o], c1 = wkey[2 * o + 1];
+    uint32_t v[kMaxWide], f[kMaxWide];
+#pragma unroll
+    for (uint32_t x = 0; x < kMaxWide; ++x) {
+      v[x] = x < L ? wide_sym<kBytes>(c0, c1, x) : 0u;
+      f[x] = x < L ? fprev[v[x]] : 0u;
+    }
+    uint64_t S = 0;
+#pragma unroll
+    for (int x = kMaxWide - 1; x >= 0; --x) {
+      if ((uint32_t)x < L) {
+        rule_rhs[q + x] = (Sym)v[x];
+        S = addmod61(mulmod61(S, h.c), f[x]);
+      }
+    }
+    F = (uint32_t)(addmod61(mulmod61(h.a, S), h.b) & 0xFFFFFFFFULL);
+  } else if (kk & kLongTag) {
     // eight symbols per step, so that their loads are in flight together
     const Sym* src = content + pstart[o];
     for (uint32_t i = 0; i < L; i += 8) {
@@ -1503,6 +1582,7 @@ __global__ __launch_bounds__(256) void k_commit_new(uint64_t d, const uint64_t* 
                                                     const uint64_t* __restrict__ wcnt_base,
                                                     const uint64_t* __restrict__ wlen_base,
                                                     const uint64_t* __restrict__ key,
+                                                    const uint64_t* __restrict__ wkey,
                                                     const uint64_t* __restrict__ pstart,
                                                     const uint32_t* __restrict__ plen,
                                                     const Sym* __restrict__ content,
@@ -1529,8 +1609,8 @@ __global__ __launch_bounds__(256) void k_commit_new(uint64_t d, const uint64_t* 
   const uint32_t r = u_prev + (uint32_t)(wcnt_base[wd] +
                                          __builtin_popcountll(fw & ((1ULL << lane) - 1ULL)));
   const uint64_t q = q_prev + wlen_base[wd] + excl;
-  commit_one<Sym>(o, r, q, kk, L, slot_idx[o], table, pstart, content, fnew, fprev, h, rule_off,
-                  rule_rhs, rule_fp);
+  commit_one<Sym>(o, r, q, kk, L, slot_idx[o], table, wkey, pstart, content, fnew, fprev, h,
+                  rule_off, rule_rhs, rule_fp);
 }
 
 // When few phrases are new, one wave per word leaves most lanes idle: the new
@@ -1564,6 +1644,7 @@ __global__ __launch_bounds__(256) void k_commit_list(uint64_t u_new, const uint3
                                                      const uint64_t* __restrict__ qoff,
                                                      const uint32_t* __restrict__ slot_idx,
                                                      Slot* table, const uint64_t* __restrict__ key,
+                                                     const uint64_t* __restrict__ wkey,
                                                      const uint64_t* __restrict__ pstart,
                                                      const uint32_t* __restrict__ plen,
                                                      const Sym* __restrict__ content,
@@ -1579,7 +1660,7 @@ __global__ __launch_bounds__(256) void k_commit_list(uint64_t u_new, const uint3
     const uint64_t o = list[i];
     const uint64_t kk = key[o];
     commit_one<Sym>(o, u_prev + (uint32_t)i, q_prev + qoff[i], kk, key_len<kBytes>(kk, plen, o),
-                    slot_idx[o], table, pstart, content, fnew, fprev, h, rule_off, rule_rhs,
+                    slot_idx[o], table, wkey, pstart, content, fnew, fprev, h, rule_off, rule_rhs,
                     rule_fp);
   }
 }
@@ -1626,7 +1707,8 @@ __global__ __launch_bounds__(256) void k_rewrite(uint64_t d, const uint64_t* __r
 
 void launch_commit(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t* slot_idx, Slot* table,
                    const uint64_t* newbits, const uint64_t* wcnt_base, const uint64_t* wlen_base,
-                   const uint64_t* key, const uint64_t* pstart, const uint32_t* plen,
+                   const uint64_t* key, const uint64_t* wkey, const uint64_t* pstart,
+                   const uint32_t* plen,
                    const void* content, const uint32_t* fnew, const uint32_t* fprev, LevelHash h,
                    uint32_t u_prev, uint64_t q_prev, uint64_t* rule_off, void* rule_rhs,
                    uint32_t* rule_fp, uint32_t* sym_next, uint32_t* fnext, uint64_t u_new,
@@ -1643,7 +1725,7 @@ void launch_commit(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t
       k_new_list<true><<<gw, 256, 0, s>>>(W, newbits, wcnt_base, wlen_base, key, plen, nlist, nqoff);
       if (u_new)
         k_commit_list<uint8_t><<<gu, 256, 0, s>>>(
-            u_new, nlist, nqoff, slot_idx, table, key, pstart, plen,
+            u_new, nlist, nqoff, slot_idx, table, key, wkey, pstart, plen,
             static_cast<const uint8_t*>(content), fnew, fprev, h, u_prev, q_prev, rule_off,
             static_cast<uint8_t*>(rule_rhs), rule_fp);
     } else {
@@ -1651,19 +1733,19 @@ void launch_commit(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t
                                            nqoff);
       if (u_new)
         k_commit_list<uint32_t><<<gu, 256, 0, s>>>(
-            u_new, nlist, nqoff, slot_idx, table, key, pstart, plen,
+            u_new, nlist, nqoff, slot_idx, table, key, wkey, pstart, plen,
             static_cast<const uint32_t*>(content), fnew, fprev, h, u_prev, q_prev, rule_off,
             static_cast<uint32_t*>(rule_rhs), rule_fp);
     }
     LCG_LAUNCH_CHECK("commit_list");
   } else if (bytes)
     k_commit_new<uint8_t><<<g, 256, 0, s>>>(
-        d, d_dev, slot_idx, table, newbits, wcnt_base, wlen_base, key, pstart, plen,
+        d, d_dev, slot_idx, table, newbits, wcnt_base, wlen_base, key, wkey, pstart, plen,
         static_cast<const uint8_t*>(content), fnew, fprev, h, u_prev, q_prev, rule_off,
         static_cast<uint8_t*>(rule_rhs), rule_fp);
   else
     k_commit_new<uint32_t><<<g, 256, 0, s>>>(
-        d, d_dev, slot_idx, table, newbits, wcnt_base, wlen_base, key, pstart, plen,
+        d, d_dev, slot_idx, table, newbits, wcnt_base, wlen_base, key, wkey, pstart, plen,
         static_cast<const uint32_t*>(content), fnew, fprev, h, u_prev, q_prev, rule_off,
         static_cast<uint32_t*>(rule_rhs), rule_fp);
   LCG_LAUNCH_CHECK("commit_new");
@@ -1694,6 +1776,8 @@ __global__ void k_rehash(const Slot* __restrict__ old_t, uint64_t old_cap, Slot*
       if (done) {
         new_t[pos].minocc = sl.minocc;  // the committed rule's F
         new_t[pos].rank = sl.rank;
+        new_t[pos].c0 = sl.c0;
+        new_t[pos].c1 = sl.c1;
       }
       else pos = (pos + 1) & mask;
     }
@@ -1795,7 +1879,8 @@ __global__ void k_merge_prepare(uint32_t u_b, const uint64_t* __restrict__ b_off
                                 const Sym* __restrict__ b_rhs, const uint32_t* __restrict__ remap_prev,
                                 const uint32_t* __restrict__ f_prev, LevelHash h, uint32_t key_bits,
                                 Sym* __restrict__ content, uint64_t* __restrict__ pstart,
-                                uint32_t* __restrict__ plen, uint64_t* __restrict__ key) {
+                                uint32_t* __restrict__ plen, uint64_t* __restrict__ key,
+                                uint64_t* __restrict__ wkey) {
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= u_b) return;
   const uint64_t p0 = b_off[r], p1 = b_off[r + 1];
@@ -1809,22 +1894,22 @@ __global__ void k_merge_prepare(uint32_t u_b, const uint64_t* __restrict__ b_off
   const uint64_t P = addmod61(mulmod61(h.a, S), h.b);
   pstart[r] = p0;
   plen[r] = (uint32_t)(p1 - p0);
-  key[r] = make_key<sizeof(Sym) == 1>(content, p0, p1 - p0, P, key_bits);
+  key[r] = make_key<sizeof(Sym) == 1>(content, p0, p1 - p0, P, key_bits, wkey + 2 * (uint64_t)r);
 }
 
 void launch_merge_prepare(bool bytes, uint32_t u_b, const uint64_t* b_off, const void* b_rhs,
                           const uint32_t* remap_prev, const uint32_t* f_prev, LevelHash h,
                           uint32_t key_bits, void* content, uint64_t* pstart, uint32_t* plen,
-                          uint64_t* key, hipStream_t s) {
+                          uint64_t* key, uint64_t* wkey, hipStream_t s) {
   if (!u_b) return;
   if (bytes)
     k_merge_prepare<uint8_t><<<grid_for(u_b, 256), 256, 0, s>>>(
         u_b, b_off, static_cast<const uint8_t*>(b_rhs), nullptr, f_prev, h, key_bits,
-        static_cast<uint8_t*>(content), pstart, plen, key);
+        static_cast<uint8_t*>(content), pstart, plen, key, wkey);
   else
     k_merge_prepare<uint32_t><<<grid_for(u_b, 256), 256, 0, s>>>(
         u_b, b_off, static_cast<const uint32_t*>(b_rhs), remap_prev, f_prev, h, key_bits,
-        static_cast<uint32_t*>(content), pstart, plen, key);
+        static_cast<uint32_t*>(content), pstart, plen, key, wkey);
   LCG_LAUNCH_CHECK("merge_prepare");
 }
 

@@ -91,10 +91,11 @@ static double hll_estimate(const unsigned int* regs) {
 
 // Working memory of one build call besides the grammar: the phrase arrays of
 // a round are sized for the worst case n/2 + k phrases (start 8 B, length 4,
-// key 8, slot 4, two symbol and two fingerprint streams 4 each = 40 B per
-// phrase), plus break bits, scan and sketch buffers.
+// key 8, wide-key content 16, slot 4, claimed slot 4, two symbol and two
+// fingerprint streams 4 each = 60 B per phrase), plus break bits, scan and
+// sketch buffers.
 static uint64_t build_bytes(uint64_t n, uint32_t k) {
-  return 21 * n + 48ull * k + (64ull << 20);
+  return 31 * n + 64ull * k + (64ull << 20);
 }
 
 // What the device records of one round run without host reads (tail mode).
@@ -110,7 +111,7 @@ struct TailRec {
 // Reusable per-call scratch.
 struct Work {
   DBuf<uint64_t> bits, tile_cnt, tile_base, scan_tmp;
-  DBuf<uint64_t> pstart, key;
+  DBuf<uint64_t> pstart, key, wkey;  // wkey: two content words per phrase with a wide key
   DBuf<uint32_t> plen, slot_idx;
   DBuf<uint32_t> sym[2], fpv[2];
   DBuf<uint64_t> off[2];
@@ -119,13 +120,14 @@ struct Work {
   DBuf<Counters> ctr, fin;
   DBuf<uint8_t> content8, hll_part;
   DBuf<TileSeg> tile_seg;
-  DBuf<uint32_t> content32, remap[2], rest, won;
+  DBuf<uint32_t> content32, remap[2], rest, won, won_cnt, won2;
   DBuf<struct TailRec> tail;
   void release_after(hipStream_t s) {
-    DBuf<uint64_t>* b64[] = {&bits, &tile_cnt, &tile_base, &scan_tmp, &pstart, &key, &off[0],
+    DBuf<uint64_t>* b64[] = {&bits, &tile_cnt, &tile_base, &scan_tmp, &pstart, &key, &wkey, &off[0],
                              &off[1], &newbits, &wcnt, &wlen, &wcnt_base, &wlen_base, &nqoff};
     DBuf<uint32_t>* b32[] = {&plen, &slot_idx, &sym[0], &sym[1], &fpv[0], &fpv[1], &lut,
-                             &content32, &remap[0], &remap[1], &rest, &nlist, &won};
+                             &content32, &remap[0], &remap[1], &rest, &nlist, &won, &won_cnt,
+                             &won2};
     for (auto* b : b64) b->reset_after(s);
     for (auto* b : b32) b->reset_after(s);
     ctr.reset_after(s);
@@ -249,6 +251,16 @@ static void ensure_level(lcg_grammar* g, size_t i, hipStream_t s, size_t off_cap
 }
 
 
+// Room for the slots an insert over (a bound of) d phrases claims: the
+// per-wave regions and counts, and the combining insert's list (at most one
+// entry per slot of a table of `cap` slots).
+static void need_won(Work& w, uint64_t d, uint64_t cap, hipStream_t s) {
+  const WonGeom geo = won_geometry(d);
+  w.won.need(std::max<uint64_t>((uint64_t)geo.waves * geo.per_wave, 1), s);
+  w.won_cnt.need(std::max<uint32_t>(geo.waves, 1), s);
+  w.won2.need(std::max<uint64_t>(cap, 1), s);
+}
+
 struct DedupResult {
   uint32_t u_new;
   uint64_t q_new;
@@ -271,7 +283,7 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
   // few distinct keys for many phrases: combine equal keys per chunk first
   const bool combine = o.combine_log2 < 31 && (est_new << o.combine_log2) <= d;
   w.slot_idx.need(d, s);
-  w.won.need(d, s);
+  need_won(w, d, combine ? L.tcap : 1, s);
   if (combine) w.rest.need(d, s);
   w.newbits.need(W, s);
   w.wcnt.need(W, s);
@@ -286,14 +298,14 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
     zero_counters(w.ctr.p, s);
     const void* rule_rhs = bytes ? (const void*)L.rhs8.p : (const void*)L.rhs32.p;
     if (pe) pe->rec(3, s);
-    launch_insert(bytes, d, nullptr, w.key.p, w.pstart.p, w.plen.p, content, L.off.p, rule_rhs, L.u,
-                  L.table.p, L.tcap - 1, w.slot_idx.p, combine, w.rest.p, &w.ctr.p->rest_len,
-                  w.won.p, w.ctr.p, s);
+    launch_insert(bytes, d, nullptr, w.key.p, w.wkey.p, w.pstart.p, w.plen.p, content, L.off.p,
+                  rule_rhs, L.u, L.table.p, L.tcap - 1, w.slot_idx.p, combine, w.rest.p,
+                  &w.ctr.p->rest_len, w.won.p, w.won_cnt.p, w.won2.p, w.ctr.p, s);
     if (pe) pe->rec(4, s);
     // first occurrences from the slots the insert claimed: one slot read and
     // one flag per new rule, not per phrase
-    launch_newflags_won(bytes, w.won.p, w.ctr.p, L.table.p, W, w.key.p, w.plen.p, w.newbits.p,
-                        w.wcnt.p, w.wlen.p, s);
+    launch_newflags_won(bytes, d, w.won.p, w.won_cnt.p, w.won2.p, w.ctr.p, L.table.p, W, w.key.p,
+                        w.plen.p, w.newbits.p, w.wcnt.p, w.wlen.p, s);
     scan_exclusive(w.wcnt.p, w.wcnt_base.p, W, w.scan_tmp.p, s);
     scan_exclusive(w.wlen.p, w.wlen_base.p, W, w.scan_tmp.p, s);
     if (pe) pe->rec(5, s);
@@ -330,7 +342,7 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
     w.nqoff.need(std::max<uint64_t>(u_new, 1), s);
   }
   launch_commit(bytes, d, nullptr, w.slot_idx.p, L.table.p, w.newbits.p, w.wcnt_base.p, w.wlen_base.p,
-                w.key.p, w.pstart.p, w.plen.p, content, fnew, fprev, g->H.lv[lv], L.u, L.q,
+                w.key.p, w.wkey.p, w.pstart.p, w.plen.p, content, fnew, fprev, g->H.lv[lv], L.u, L.q,
                 L.off.p, rule_rhs, L.fp.p, sym_next, fnext, u_new, w.nlist.p, w.nqoff.p, s);
   if (pe) pe->rec(6, s);
   L.u += (uint32_t)u_new;
@@ -400,8 +412,9 @@ static void tail_rounds(lcg_grammar* g, uint32_t lv, uint64_t n_i, uint64_t acti
     w.pstart.need(d_b, s);
     w.plen.need(d_b, s);
     w.key.need(d_b, s);
+    w.wkey.need(2 * d_b, s);
     w.slot_idx.need(d_b, s);
-    w.won.need(d_b, s);
+    need_won(w, d_b, 1, s);
     w.sym[cur].need(d_b, s);
     w.fpv[cur].need(d_b, s);
     w.off[cur].need(k + 1, s);
@@ -436,21 +449,21 @@ static void tail_rounds(lcg_grammar* g, uint32_t lv, uint64_t n_i, uint64_t acti
     if (pe) pe->rec(1, s);
     if (pe) pe->rec(2, s);
     launch_emit(in, w.bits.p, w.tile_base.p, w.tile_seg.p, g->H.lv[lv], o.key_bits, w.pstart.p,
-                w.plen.p, w.key.p, w.fpv[cur].p, w.hll_part.p, nullptr, s);
+                w.plen.p, w.key.p, w.wkey.p, w.fpv[cur].p, w.hll_part.p, nullptr, s);
     if (pe) pe->rec(8, s);
     if (pe) pe->rec(3, s);
-    launch_insert(bytes, d_b, &rec->d, w.key.p, w.pstart.p, w.plen.p, content, L.off.p, rule_rhs,
-                  L.u, L.table.p, L.tcap - 1, w.slot_idx.p, false, nullptr, nullptr, w.won.p,
-                  &rec->ctr, s);
+    launch_insert(bytes, d_b, &rec->d, w.key.p, w.wkey.p, w.pstart.p, w.plen.p, content, L.off.p,
+                  rule_rhs, L.u, L.table.p, L.tcap - 1, w.slot_idx.p, false, nullptr, nullptr,
+                  w.won.p, w.won_cnt.p, w.won2.p, &rec->ctr, s);
     if (pe) pe->rec(4, s);
-    launch_newflags_won(bytes, w.won.p, &rec->ctr, L.table.p, W_b, w.key.p, w.plen.p, w.newbits.p,
-                        w.wcnt.p, w.wlen.p, s);
+    launch_newflags_won(bytes, d_b, w.won.p, w.won_cnt.p, w.won2.p, &rec->ctr, L.table.p, W_b,
+                        w.key.p, w.plen.p, w.newbits.p, w.wcnt.p, w.wlen.p, s);
     scan_one(w.wcnt.p, w.wcnt_base.p, W_b, &rec->d, 6, &rec->u, s);
     scan_one(w.wlen.p, w.wlen_base.p, W_b, &rec->d, 6, &rec->q, s);
     if (pe) pe->rec(5, s);
     const uint32_t* fprev = bytes ? w.lut.p : g->levels[lv - 2].fp.p;
     launch_commit(bytes, d_b, &rec->d, w.slot_idx.p, L.table.p, w.newbits.p, w.wcnt_base.p,
-                  w.wlen_base.p, w.key.p, w.pstart.p, w.plen.p, content, w.fpv[cur].p, fprev,
+                  w.wlen_base.p, w.key.p, w.wkey.p, w.pstart.p, w.plen.p, content, w.fpv[cur].p, fprev,
                   g->H.lv[lv], L.u, L.q, L.off.p, rule_rhs, L.fp.p, w.sym[cur].p, w.fpv[cur].p,
                   0, nullptr, nullptr, s);
     if (pe) pe->rec(6, s);
@@ -516,11 +529,13 @@ static void tail_rounds(lcg_grammar* g, uint32_t lv, uint64_t n_i, uint64_t acti
 // one grammar can advance in turns (the serving session) as well as one
 // build to its end (build_core).
 //
-// A round with host reads synchronises twice: the phrase count and key
-// sketch (sizes the dictionary; also returns the previous round's count of
-// strings still active), and the new-rule counts (sizes the level).  The
-// round after the last one runs classify/emit on strings of length <= 1 and
-// finds no phrase; that is how the build learns that every string is done.
+// A round with host reads synchronises up to three times: the phrase count
+// after classify (sizes the phrase arrays exactly; also returns the previous
+// round's count of strings still active), the key sketch after emit (sizes
+// the dictionary; rounds over at most 2^20 symbols skip it and size by the
+// phrase count), and the new-rule counts (sizes the level).  The round after
+// the last one runs classify on strings of length <= 1 and finds no phrase;
+// that is how the build learns that every string is done.
 // Once the sequence is short, one step queues all remaining rounds without
 // host reads (tail_rounds).
 struct Cohort {
@@ -627,27 +642,14 @@ struct Cohort {
     w.tile_base.need(tiles + 1, s);
     w.tile_seg.need(tiles, s);
     w.scan_tmp.need(std::max<size_t>(scan_tmp_words(tiles), 1), s);
-    w.pstart.need(d_cap, s);
-    w.plen.need(d_cap, s);
-    w.key.need(d_cap, s);
-    w.sym[cur].need(d_cap, s);
-    w.fpv[cur].need(d_cap, s);
     w.off[cur].need(k + 1, s);
     pe.rec(0, s);
     launch_classify(in, w.bits.p, w.tile_cnt.p, w.tile_seg.p, s);
     scan_exclusive(w.tile_cnt.p, w.tile_base.p, tiles, w.scan_tmp.p, s);
     pe.rec(1, s);
-    zero_counters(w.ctr.p, s);
-    pe.rec(2, s);
-    // small rounds size the dictionary by the phrase count itself
-    const bool sketch = n_i > (1u << 20);
-    launch_emit(in, w.bits.p, w.tile_base.p, w.tile_seg.p, g->H.lv[lv], o.key_bits, w.pstart.p,
-                w.plen.p, w.key.p, w.fpv[cur].p, w.hll_part.p, sketch ? w.ctr.p : nullptr, s);
-    pe.rec(8, s);
+    // the phrase count sizes the phrase arrays exactly (about 0.29 n at round 1
+    // of DNA, against the worst case n/2 + k)
     HIP_CHECK(hipMemcpyAsync(&mb->d, w.tile_base.p + tiles, 8, hipMemcpyDeviceToHost, s));
-    if (sketch)
-      HIP_CHECK(hipMemcpyAsync(mb->ctr.hll, w.ctr.p->hll, sizeof(unsigned int) * kHll,
-                               hipMemcpyDeviceToHost, s));
     if (pending)
       HIP_CHECK(hipMemcpyAsync(&hf, w.fin.p, offsetof(Counters, hll), hipMemcpyDeviceToHost, s));
     sync(s);
@@ -662,6 +664,25 @@ struct Cohort {
       }
     }
     if (d == 0 || d >= d_cap) throw LcgError{LCG_EHIP, "internal: phrase count out of range"};
+    w.pstart.need(d, s);
+    w.plen.need(d, s);
+    w.key.need(d, s);
+    w.wkey.need(2 * d, s);
+    w.sym[cur].need(d, s);
+    w.fpv[cur].need(d, s);
+    zero_counters(w.ctr.p, s);
+    pe.rec(2, s);
+    // small rounds size the dictionary by the phrase count itself
+    const bool sketch = n_i > (1u << 20);
+    launch_emit(in, w.bits.p, w.tile_base.p, w.tile_seg.p, g->H.lv[lv], o.key_bits, w.pstart.p,
+                w.plen.p, w.key.p, w.wkey.p, w.fpv[cur].p, w.hll_part.p,
+                sketch ? w.ctr.p : nullptr, s);
+    pe.rec(8, s);
+    if (sketch) {
+      HIP_CHECK(hipMemcpyAsync(mb->ctr.hll, w.ctr.p->hll, sizeof(unsigned int) * kHll,
+                               hipMemcpyDeviceToHost, s));
+      sync(s);
+    }
     ensure_level(g, lv, s);
     const uint64_t t_classify = pe.ns(0, 1), t_emit = pe.ns(2, 8);
     const uint64_t est =
@@ -716,18 +737,19 @@ static void merge_core(lcg_grammar* a, const lcg_grammar* b, Work& w, hipStream_
       w.pstart.need(ub, s);
       w.plen.need(ub, s);
       w.key.need(ub, s);
+      w.wkey.need(2 * (size_t)ub, s);
       const void* content;
       const uint32_t* f_prev = bytes ? w.lut.p : a->levels[lv - 2].fp.p;
       if (bytes) {
         w.content8.need(B.q, s);
         content = w.content8.p;
         launch_merge_prepare(true, ub, B.off.p, B.rhs8.p, nullptr, f_prev, a->H.lv[lv], 0,
-                             w.content8.p, w.pstart.p, w.plen.p, w.key.p, s);
+                             w.content8.p, w.pstart.p, w.plen.p, w.key.p, w.wkey.p, s);
       } else {
         w.content32.need(B.q, s);
         content = w.content32.p;
         launch_merge_prepare(false, ub, B.off.p, B.rhs32.p, remap_prev, f_prev, a->H.lv[lv], 0,
-                             w.content32.p, w.pstart.p, w.plen.p, w.key.p, s);
+                             w.content32.p, w.pstart.p, w.plen.p, w.key.p, w.wkey.p, s);
       }
       dedup_commit(a, (uint32_t)lv, ub, content, B.fp.p, w.remap[cur].p, nullptr, ub, o, w, s);
       launch_c_merge(b->c_level.p, b->c_sym.p, kb, (uint32_t)lv, w.remap[cur].p,

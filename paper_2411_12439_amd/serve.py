@@ -12,6 +12,12 @@ The scheduler loop alternates two things:
   (``lcg_session_step``); a batch whose sequence is short runs all its
   remaining rounds in that step.
 
+A running grammar keeps growing with every request's new content (each one
+carries fresh divergence).  Once a level of it holds max_level_rules rules,
+the server starts a new running grammar (a new generation) for the batches
+admitted from then on, lets the old one finish its batches in flight, and
+retires it: dictionary slots are 32-bit indices, so one grammar is bounded.
+
 So a request that arrives while a large one is deep in its rounds waits for
 at most one round of the others, not for their whole builds: batches at
 different rounds share the GPU, each round of each batch looking up and
@@ -83,7 +89,7 @@ class RingBuffer:
 
 
 class Request:
-    __slots__ = ("rid", "desc", "n", "arrival", "off", "event", "done", "c_index")
+    __slots__ = ("rid", "desc", "n", "arrival", "off", "event", "done", "c_index", "gen")
 
     def __init__(self, rid, desc, arrival):
         self.rid = rid
@@ -94,32 +100,51 @@ class Request:
         self.event = None
         self.done = None
         self.c_index = None
+        self.gen = None           # generation of the running grammar holding it
 
 
 class Batch:
     """Requests admitted together (a contiguous span of the ring)."""
-    __slots__ = ("reqs", "start", "nbytes", "ticket", "finished")
+    __slots__ = ("reqs", "start", "nbytes", "ticket", "gen", "finished")
 
-    def __init__(self, reqs, start, nbytes, ticket):
+    def __init__(self, reqs, start, nbytes, ticket, gen):
         self.reqs = reqs
         self.start = start
         self.nbytes = nbytes
         self.ticket = ticket
+        self.gen = gen
         self.finished = False
+
+
+class Generation:
+    """One running grammar, its serving session and its batches in flight."""
+
+    def __init__(self, index, seed, hbm_budget):
+        self.index = index
+        self.g = _lcg.new(seed)
+        self.session = _lcg.Session(self.g, hbm_budget=hbm_budget)
+        self.inflight = 0
+
+    def close(self):
+        self.session.free()
+        self.g.free()
 
 
 class Server:
     """Continuous-batching compressor around one device-resident running grammar."""
 
     def __init__(self, source, seed=_datagen.HASH_SEED, hbm_budget=16 << 30, ring_bytes=1 << 30,
-                 max_batches=32, device="cuda"):
+                 max_batches=32, max_level_rules=1 << 27, device="cuda"):
         import torch
         self.torch = torch
         self.source = source
         self.seed = seed
-        self.g = _lcg.new(seed)
         self.budget = int(hbm_budget)
-        self.session = _lcg.Session(self.g, hbm_budget=self.budget)
+        self.max_level_rules = int(max_level_rules)
+        self.gens = {}                       # live generations by index
+        self.current = None
+        self.generations = 0
+        self._new_generation()
         self.max_batches = max_batches
         self.ring = RingBuffer(ring_bytes, device)
         self.copy_stream = torch.cuda.Stream()
@@ -131,10 +156,31 @@ class Server:
         self.batch_sizes = []
         self.steps = 0
 
+    @property
+    def g(self):
+        """The current running grammar."""
+        return self.current.g
+
+    def _new_generation(self):
+        gen = Generation(self.generations, self.seed, self.budget)
+        self.generations += 1
+        self.gens[gen.index] = gen
+        self.current = gen
+
+    def _rotate_if_full(self):
+        """Start a new running grammar once a level of the current one is full;
+        retire drained old ones."""
+        if max((u for u, _ in self.current.g.level_sizes()), default=0) >= self.max_level_rules:
+            self._new_generation()
+        for i in [i for i, gen in self.gens.items()
+                  if gen is not self.current and gen.inflight == 0]:
+            self.gens.pop(i).close()
+
     def close(self):
-        """Free the session and the running grammar."""
-        self.session.free()
-        self.g.free()
+        """Free the sessions and the running grammars."""
+        for gen in self.gens.values():
+            gen.close()
+        self.gens.clear()
 
     def submit(self, req):
         self.waiting.append(req)
@@ -178,8 +224,9 @@ class Server:
         offs = np.zeros(len(batch) + 1, np.int64)
         offs[1:] = np.cumsum([r.n for r in batch])
         d_offs = torch.from_numpy(offs).to(self.ring.buf.device)
+        gen = self.current
         try:
-            first, ticket = self.session.admit(self.ring.buf[start:start + total], d_offs)
+            first, ticket = gen.session.admit(self.ring.buf[start:start + total], d_offs)
         except _lcg.LcgError as e:
             if e.name == "LCG_ENOMEM" and self.inflight:
                 return 0                   # waits for memory to free up
@@ -188,9 +235,11 @@ class Server:
             self.ready.popleft()
         for i, req in enumerate(batch):
             req.c_index = first + i
-        b = Batch(batch, start, total, ticket)
+            req.gen = gen.index
+        b = Batch(batch, start, total, ticket, gen.index)
+        gen.inflight += 1
         self.inflight.append(b)
-        self.by_ticket[ticket] = b
+        self.by_ticket[(gen.index, ticket)] = b
         self.batch_sizes.append(len(batch))
         return len(batch)
 
@@ -200,17 +249,24 @@ class Server:
         self.admit()
         if not self.inflight:
             return 0
-        done, _ = self.session.step()
+        finished = []
+        for gen in list(self.gens.values()):
+            if gen.inflight:
+                done, _ = gen.session.step()
+                finished += [(gen.index, t) for t in done]
         self.steps += 1
         now = time.perf_counter()
         n = 0
-        for t in done:
-            b = self.by_ticket.pop(t)
+        for key in finished:
+            b = self.by_ticket.pop(key)
             b.finished = True
+            self.gens[b.gen].inflight -= 1
             for req in b.reqs:
                 req.done = now
                 self.completed.append(req)
             n += len(b.reqs)
+        if self.steps % 8 == 0 or finished:
+            self._rotate_if_full()
         # the ring is released in allocation order, as far as batches are finished
         while self.inflight and self.inflight[0].finished:
             b = self.inflight.popleft()
@@ -229,7 +285,8 @@ class Server:
 
 
 def run_load(source, load_gbps, seconds, max_requests=None, min_requests=0,
-             seed=_datagen.HASH_SEED, hbm_budget=16 << 30, ring_bytes=1 << 30):
+             seed=_datagen.HASH_SEED, hbm_budget=16 << 30, ring_bytes=1 << 30,
+             max_level_rules=1 << 27):
     """Serve a Poisson stream offering `load_gbps` GB/s (None: every request is
     there from the start, which measures the capacity) for `seconds`, or until
     max_requests have arrived; at least min_requests arrive.
@@ -237,7 +294,7 @@ def run_load(source, load_gbps, seconds, max_requests=None, min_requests=0,
     Returns (summary, server, requests); requests[i] = (Request, descriptor).
     """
     import torch
-    srv = Server(source, seed, hbm_budget, ring_bytes)
+    srv = Server(source, seed, hbm_budget, ring_bytes, max_level_rules=max_level_rules)
     saturate = load_gbps is None
     gaps = None if saturate else source.arrivals(load_gbps * 1e9, 1 << 16)
     reqs = []
@@ -284,6 +341,7 @@ def run_load(source, load_gbps, seconds, max_requests=None, min_requests=0,
         "p99_ms": round(float(np.percentile(lat, 99)), 3),
         "steps": srv.steps,
         "batches": len(srv.batch_sizes),
+        "generations": srv.generations,
         "mean_batch": round(float(np.mean(srv.batch_sizes)), 2) if srv.batch_sizes else 0.0,
         "max_batch": int(max(srv.batch_sizes)) if srv.batch_sizes else 0,
         "wall_s": round(t1 - t0, 3),
@@ -291,14 +349,23 @@ def run_load(source, load_gbps, seconds, max_requests=None, min_requests=0,
     return summary, srv, reqs
 
 
+def checkable(srv, reqs):
+    """Indices of the requests held by the current running grammar."""
+    return [i for i, (r, _) in enumerate(reqs) if r.gen == srv.current.index]
+
+
 def check_alone_vs_mix(srv, source, reqs, sample):
-    """For the sampled requests: rules reachable from the request's C entry in the
-    running grammar == the grammar of the request compressed alone (canonically)."""
+    """For the sampled requests (held by the current running grammar): the rules
+    reachable from the request's C entry, renumbered in the request's own
+    first-occurrence order, equal the grammar of the request compressed alone,
+    rank for rank."""
     import torch
     g_all = srv.g.export()
     ok = 0
     for idx in sample:
         req, desc = reqs[idx]
+        if req.gen != srv.current.index:
+            raise ValueError("request %d is in a retired running grammar" % req.rid)
         t = source.materialize(desc)
         o = torch.tensor([0, req.n], dtype=torch.int64, device=t.device)
         alone = _lcg.build(t, o, seed=srv.seed).export()
@@ -325,7 +392,9 @@ def main():
         summary, srv, reqs = run_load(src, load, args.seconds if load else 0.0,
                                       min_requests=args.min_requests)
         rng = np.random.default_rng(0)
-        sample = rng.choice(len(reqs), size=min(args.check, len(reqs)), replace=False)
+        cand = checkable(srv, reqs)
+        sample = [cand[i] for i in rng.choice(len(cand), size=min(args.check, len(cand)),
+                                              replace=False)]
         summary["alone_vs_mix_checked"] = check_alone_vs_mix(srv, src, reqs, sample)
         print(json.dumps(summary), flush=True)
         srv.close()

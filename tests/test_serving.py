@@ -115,3 +115,23 @@ def test_requests_carry_their_own_divergence():
     assert set(np.unique(a[diff]).tolist()) <= set(b"ACGT")
     assert (a != c).mean() > 0.015          # fresh substitutions on both
     assert np.array_equal(a[~diff], win[~diff])
+
+
+@pytest.mark.gpu
+def test_serving_rotates_full_running_grammars():
+    """A running grammar whose level reaches the rule limit is retired once its
+    batches finish; later requests go to a new one.  Every request completes,
+    and every request of the last running grammar equals itself built alone."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2411_12439_amd import serve
+    src = D.ServingSource(scale=0.02, n_bases=4)
+    summary, srv, reqs = serve.run_load(src, load_gbps=5.0, seconds=30.0, max_requests=80,
+                                        ring_bytes=4 << 20, max_level_rules=3000)
+    assert summary["requests"] == 80 == len(srv.completed)
+    assert summary["generations"] >= 3
+    last = serve.checkable(srv, reqs)
+    assert last and serve.check_alone_vs_mix(srv, src, reqs, last) == len(last)
+    # the last grammar's strings are its requests in C order
+    assert sorted(reqs[i][0].c_index for i in last) == list(range(len(last)))
+    srv.close()
