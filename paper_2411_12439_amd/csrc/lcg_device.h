@@ -89,16 +89,27 @@ __device__ __forceinline__ uint64_t long_key(uint64_t P, uint32_t key_bits) {
 
 // Wide exact keys: phrases too long for a short key but whose content fits
 // two 62-bit words c0, c1 (bit 63 of both stays clear, so a valid word never
-// equals kEmpty).  Level 1: 8..14 bytes, seven in each word (qcode = q - 8);
-// levels >= 2: at most four ranks below 2^31, two in each word (qcode =
-// q - 1).  Equal (qcode, c0, c1) means equal phrases.  The key word carries
-// the tags, qcode and 27 bits of a mix of the content, which place the
+// equals kEmpty).  Level 1: 8..14 bytes, seven in each word (qcode = q - 8).
+// Levels >= 2: up to eight ranks, packed at the smallest width b of
+// {12, 16, 20, 31} bits that holds every rank of the phrase (bcode 0..3),
+// 5, 3, 3 or 2 ranks per word (so at most 8, 6, 6 or 4 ranks; qcode = q - 1).
+// The width depends on the phrase alone, so equal phrases get equal keys and
+// equal (qcode, bcode, c0, c1) means equal phrases.  The key word carries the
+// tags, qcode, bcode and 25 bits of a mix of the content, which place the
 // phrase in the table; a match of the key word is confirmed on c0, c1.
 constexpr uint64_t kWideMaxBytes = 14;
-constexpr uint32_t kWideMaxRanks = 4;
-__host__ __device__ __forceinline__ uint64_t wide_key(uint64_t qcode, uint64_t c0, uint64_t c1) {
-  const uint64_t h = mix64(c0 * 0x9E3779B97F4A7C15ULL ^ c1 ^ (qcode << 60)) >> 37;  // 27 bits
-  return kLongTag | kWideTag | (qcode << 59) | (h << 32);
+constexpr uint32_t kWideMaxRanks = 8;
+__host__ __device__ __forceinline__ uint32_t wide_bits(uint32_t bcode) {
+  return bcode == 0 ? 12u : bcode == 1 ? 16u : bcode == 2 ? 20u : 31u;
+}
+__host__ __device__ __forceinline__ uint32_t wide_per_word(uint32_t bcode) {
+  return bcode == 0 ? 5u : bcode == 3 ? 2u : 3u;
+}
+__host__ __device__ __forceinline__ uint64_t wide_key(uint64_t qcode, uint64_t bcode, uint64_t c0,
+                                                      uint64_t c1) {
+  const uint64_t h =
+      mix64(c0 * 0x9E3779B97F4A7C15ULL ^ c1 ^ (qcode << 60) ^ (bcode << 56)) >> 39;  // 25 bits
+  return kLongTag | kWideTag | (qcode << 59) | (bcode << 57) | (h << 32);
 }
 __host__ __device__ __forceinline__ bool is_wide(uint64_t kk) {
   return (kk & (kLongTag | kWideTag)) == (kLongTag | kWideTag);
@@ -108,6 +119,9 @@ __host__ __device__ __forceinline__ bool is_long(uint64_t kk) {
 }
 __host__ __device__ __forceinline__ uint32_t wide_qcode(uint64_t kk) {
   return (uint32_t)((kk >> 59) & 7);
+}
+__host__ __device__ __forceinline__ uint32_t wide_bcode(uint64_t kk) {
+  return (uint32_t)((kk >> 57) & 3);
 }
 
 }  // namespace lcg

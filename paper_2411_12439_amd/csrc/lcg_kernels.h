@@ -93,6 +93,12 @@ void launch_insert(bool bytes, uint64_t d, const uint64_t* d_dev, const uint64_t
                    uint32_t u_committed, Slot* table, uint64_t mask, uint32_t* slot_idx,
                    bool combine, uint32_t* rest, uint32_t* rest_len, uint32_t* won,
                    uint32_t* won_cnt, uint32_t* won2, Counters* ctr, hipStream_t s);
+// First-occurrence flags of the new phrases, one pass over the phrases (for
+// rounds where most phrases are new), with per flag word the new rules and
+// their right-hand-side lengths.
+void launch_newflags(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t* slot_idx,
+                     const Slot* table, const uint64_t* key, const uint32_t* plen,
+                     uint64_t* newbits, uint64_t* wcnt, uint64_t* wlen, hipStream_t s);
 // First-occurrence flags of the new phrases from the insert's claims (the
 // first occurrence of every slot claimed in the round is new), then per flag
 // word the new rules and their right-hand-side lengths.  d: the insert's

@@ -158,13 +158,15 @@ __device__ __forceinline__ bool exact_key(const void* sym, uint64_t p, uint64_t 
 }
 
 // Content words of a wide key for the phrase sym[p .. p+q), if it has one
-// (see lcg_device.h): 8..14 bytes at level 1, at most four ranks below 2^31
-// above.  *qcode receives the length code.
+// (see lcg_device.h): 8..14 bytes at level 1, up to eight ranks above.
+// *qcode and *bcode receive the length and width codes.
 template <bool BYTES>
 __device__ __forceinline__ bool wide_content(const void* sym, uint64_t p, uint64_t q,
-                                             uint64_t& c0, uint64_t& c1, uint64_t& qcode) {
+                                             uint64_t& c0, uint64_t& c1, uint64_t& qcode,
+                                             uint64_t& bcode) {
   c0 = 0;
   c1 = 0;
+  bcode = 0;
   if constexpr (BYTES) {
     if (q < 8 || q > kWideMaxBytes) return false;
     const uint8_t* s = static_cast<const uint8_t*>(sym) + p;
@@ -179,16 +181,28 @@ __device__ __forceinline__ bool wide_content(const void* sym, uint64_t p, uint64
   } else {
     if (q > kWideMaxRanks) return false;
     const uint32_t* s = static_cast<const uint32_t*>(sym) + p;
-    bool fits = true;
+    uint32_t r[kWideMaxRanks];
+    uint32_t m = 0;
 #pragma unroll
     for (uint32_t x = 0; x < kWideMaxRanks; ++x) {
-      const uint64_t r = x < q ? (uint64_t)s[x] : 0;
-      fits = fits && (r >> 31) == 0;
-      if (x < 2) c0 |= r << (31 * x);
-      else c1 |= r << (31 * (x - 2));
+      r[x] = x < q ? s[x] : 0u;
+      m |= r[x];
+    }
+    const uint32_t bc = m < (1u << 12) ? 0u : m < (1u << 16) ? 1u : m < (1u << 20) ? 2u
+                      : m < (1u << 31) ? 3u : 4u;
+    if (bc == 4 || q > 2 * wide_per_word(bc)) return false;
+    const uint32_t b = wide_bits(bc), per = wide_per_word(bc);
+#pragma unroll
+    for (uint32_t x = 0; x < kWideMaxRanks; ++x) {
+      if (x < q) {
+        const uint32_t word = x >= per, at = word ? x - per : x;
+        if (word) c1 |= (uint64_t)r[x] << (b * at);
+        else c0 |= (uint64_t)r[x] << (b * at);
+      }
     }
     qcode = q - 1;
-    return fits;
+    bcode = bc;
+    return true;
   }
 }
 
@@ -197,12 +211,12 @@ __device__ __forceinline__ bool wide_content(const void* sym, uint64_t p, uint64
 template <bool BYTES>
 __device__ __forceinline__ uint64_t make_key(const void* sym, uint64_t p, uint64_t q, uint64_t P,
                                              uint32_t key_bits, uint64_t* wk) {
-  uint64_t k, c0, c1, qc;
+  uint64_t k, c0, c1, qc, bc;
   if (key_bits == 0 && exact_key<BYTES>(sym, p, q, k)) return k;
-  if (key_bits == 0 && wide_content<BYTES>(sym, p, q, c0, c1, qc)) {
+  if (key_bits == 0 && wide_content<BYTES>(sym, p, q, c0, c1, qc, bc)) {
     wk[0] = c0;
     wk[1] = c1;
-    return wide_key(qc, c0, c1);
+    return wide_key(qc, bc, c0, c1);
   }
   return long_key(P, key_bits);
 }
@@ -215,11 +229,17 @@ __device__ __forceinline__ uint32_t key_len(uint64_t kk, const uint32_t* plen, u
   return BYTES ? (uint32_t)((kk >> 56) & 7) : (uint32_t)((kk >> 58) & 7);
 }
 
-// Symbol x of a wide key's content.
+// Symbol x of a wide key's content (kk: the key word, for the rank width).
 template <bool BYTES>
-__device__ __forceinline__ uint32_t wide_sym(uint64_t c0, uint64_t c1, uint32_t x) {
-  if constexpr (BYTES) return (uint32_t)((x < 7 ? c0 >> (8 * x) : c1 >> (8 * (x - 7))) & 0xFF);
-  else return (uint32_t)((x < 2 ? c0 >> (31 * x) : c1 >> (31 * (x - 2))) & 0x7FFFFFFFu);
+__device__ __forceinline__ uint32_t wide_sym(uint64_t kk, uint64_t c0, uint64_t c1, uint32_t x) {
+  if constexpr (BYTES) {
+    return (uint32_t)((x < 7 ? c0 >> (8 * x) : c1 >> (8 * (x - 7))) & 0xFF);
+  } else {
+    const uint32_t bc = wide_bcode(kk), b = wide_bits(bc), per = wide_per_word(bc);
+    const uint64_t w = x < per ? c0 : c1;
+    const uint32_t at = x < per ? x : x - per;
+    return (uint32_t)((w >> (b * at)) & ((1ull << b) - 1ull));
+  }
 }
 
 // Symbol x of a phrase with an exact key.
@@ -761,7 +781,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in0, const uint64_t* __
       const uint64_t l = t0 + s_start[jj];
       const uint64_t e = phrase_end(jj, c, t0, s_start, slo, shi, cached, s_off, in.off, bits);
       const uint64_t q = e - l;
-      uint64_t kk = 0, c0 = 0, c1 = 0, qc = 0;
+      uint64_t kk = 0, c0 = 0, c1 = 0, qc = 0, bc = 0;
       bool exact = false, wide = false;
       if (key_bits == 0) {
         const bool staged = e <= t0 + kStage;
@@ -772,18 +792,18 @@ __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in0, const uint64_t* __
         }
         // too long for a short key: a wide key if its content fits two words
         if (!exact)
-          wide = staged ? wide_content<BYTES>(st.sym, l - t0, q, c0, c1, qc)
-                        : wide_content<BYTES>(in.sym, l, q, c0, c1, qc);
+          wide = staged ? wide_content<BYTES>(st.sym, l - t0, q, c0, c1, qc, bc)
+                        : wide_content<BYTES>(in.sym, l, q, c0, c1, qc, bc);
       }
       if (exact) {
         key[base + jj] = kk;
         hll_add(s_hll, kk);
       } else if (wide) {
         const uint64_t o = base + jj;
-        key[o] = wide_key(qc, c0, c1);
+        key[o] = wide_key(qc, bc, c0, c1);
         wkey[2 * o] = c0;
         wkey[2 * o + 1] = c1;
-        hll_add(s_hll, c0 ^ mix64(c1 + (qc << 60)));
+        hll_add(s_hll, c0 ^ mix64(c1 + (qc << 60) + (bc << 56)));
       } else {
         const uint32_t slot = atomicAdd(&s_nlong, 1u);
         if (slot < kLongList) {
@@ -1412,6 +1432,56 @@ void launch_insert(bool bytes, uint64_t d, const uint64_t* d_dev, const uint64_t
 }
 
 // ------------------------------------------------------------------ newflags
+// Per phrase: new if it is the first occurrence of a slot claimed in this
+// pass (one (first occurrence, rank) read from its slot); per flag word of 64
+// phrases the new rules and their right-hand-side lengths.  For rounds where
+// most phrases are new: a coalesced pass over the phrases beats one random
+// flag per new rule.
+template <bool BYTES>
+__global__ __launch_bounds__(256) void k_newflags(uint64_t d, const uint64_t* __restrict__ d_dev,
+                                                  const uint32_t* __restrict__ slot_idx,
+                                                  const Slot* __restrict__ table,
+                                                  const uint64_t* __restrict__ key,
+                                                  const uint32_t* __restrict__ plen,
+                                                  uint64_t* __restrict__ newbits,
+                                                  uint64_t* __restrict__ wcnt,
+                                                  uint64_t* __restrict__ wlen) {
+  if (d_dev) d = *d_dev;
+  const uint64_t o = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (((o >> 6) << 6) >= d) return;  // the whole wave is past the end
+  bool f = false;
+  unsigned long long len = 0;
+  if (o < d) {
+    const uint32_t sidx = slot_idx[o];
+    if (sidx != kNone) {
+      const uint64_t mr = *reinterpret_cast<const uint64_t*>(&table[sidx].minocc);
+      f = (uint32_t)(mr >> 32) == kNone && (uint32_t)mr == (uint32_t)o;
+    }
+    if (f) len = key_len<BYTES>(key[o], plen, o);
+  }
+  const uint64_t bal = __ballot(f);
+  len = wave_sum(len);
+  const uint64_t w = o >> 6;
+  if ((threadIdx.x & 63) == 0 && (w << 6) < d) {
+    newbits[w] = bal;
+    wcnt[w] = __builtin_popcountll(bal);
+    wlen[w] = len;
+  }
+}
+
+void launch_newflags(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t* slot_idx,
+                     const Slot* table, const uint64_t* key, const uint32_t* plen,
+                     uint64_t* newbits, uint64_t* wcnt, uint64_t* wlen, hipStream_t s) {
+  if (!d) return;
+  if (bytes)
+    k_newflags<true><<<grid_for(d, 256), 256, 0, s>>>(d, d_dev, slot_idx, table, key, plen, newbits,
+                                                      wcnt, wlen);
+  else
+    k_newflags<false><<<grid_for(d, 256), 256, 0, s>>>(d, d_dev, slot_idx, table, key, plen,
+                                                       newbits, wcnt, wlen);
+  LCG_LAUNCH_CHECK("newflags");
+}
+
 // Per flag word: its new rules and their right-hand-side lengths (the keys of
 // one word's phrases lie side by side).
 template <bool BYTES>
@@ -1521,7 +1591,7 @@ __device__ __forceinline__ void commit_one(uint64_t o, uint32_t r, uint64_t q, u
     uint32_t v[kMaxWide], f[kMaxWide];
 #pragma unroll
     for (uint32_t x = 0; x < kMaxWide; ++x) {
-      v[x] = x < L ? wide_sym<kBytes>(c0, c1, x) : 0u;
+      v[x] = x < L ? wide_sym<kBytes>(kk, c0, c1, x) : 0u;
       f[x] = x < L ? fprev[v[x]] : 0u;
     }
     uint64_t S = 0;

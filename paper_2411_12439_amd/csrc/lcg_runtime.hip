@@ -261,6 +261,10 @@ static void need_won(Work& w, uint64_t d, uint64_t cap, hipStream_t s) {
   w.won2.need(std::max<uint64_t>(cap, 1), s);
 }
 
+// A round whose key sketch estimates at most d / kWonRatio new rules takes
+// its first-occurrence flags from the insert's claims.
+constexpr uint64_t kWonRatio = 4;
+
 struct DedupResult {
   uint32_t u_new;
   uint64_t q_new;
@@ -302,10 +306,15 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
                   rule_rhs, L.u, L.table.p, L.tcap - 1, w.slot_idx.p, combine, w.rest.p,
                   &w.ctr.p->rest_len, w.won.p, w.won_cnt.p, w.won2.p, w.ctr.p, s);
     if (pe) pe->rec(4, s);
-    // first occurrences from the slots the insert claimed: one slot read and
-    // one flag per new rule, not per phrase
-    launch_newflags_won(bytes, d, w.won.p, w.won_cnt.p, w.won2.p, w.ctr.p, L.table.p, W, w.key.p,
-                        w.plen.p, w.newbits.p, w.wcnt.p, w.wlen.p, s);
+    // first occurrences: from the slots the insert claimed (one slot read and
+    // one flag per new rule) when few phrases are new, else one coalesced
+    // pass over the phrases
+    if (est_new * kWonRatio <= d)
+      launch_newflags_won(bytes, d, w.won.p, w.won_cnt.p, w.won2.p, w.ctr.p, L.table.p, W, w.key.p,
+                          w.plen.p, w.newbits.p, w.wcnt.p, w.wlen.p, s);
+    else
+      launch_newflags(bytes, d, nullptr, w.slot_idx.p, L.table.p, w.key.p, w.plen.p, w.newbits.p,
+                      w.wcnt.p, w.wlen.p, s);
     scan_exclusive(w.wcnt.p, w.wcnt_base.p, W, w.scan_tmp.p, s);
     scan_exclusive(w.wlen.p, w.wlen_base.p, W, w.scan_tmp.p, s);
     if (pe) pe->rec(5, s);
@@ -456,8 +465,9 @@ static void tail_rounds(lcg_grammar* g, uint32_t lv, uint64_t n_i, uint64_t acti
                   rule_rhs, L.u, L.table.p, L.tcap - 1, w.slot_idx.p, false, nullptr, nullptr,
                   w.won.p, w.won_cnt.p, w.won2.p, &rec->ctr, s);
     if (pe) pe->rec(4, s);
-    launch_newflags_won(bytes, d_b, w.won.p, w.won_cnt.p, w.won2.p, &rec->ctr, L.table.p, W_b,
-                        w.key.p, w.plen.p, w.newbits.p, w.wcnt.p, w.wlen.p, s);
+    // short rounds: most phrases are new
+    launch_newflags(bytes, d_b, &rec->d, w.slot_idx.p, L.table.p, w.key.p, w.plen.p, w.newbits.p,
+                    w.wcnt.p, w.wlen.p, s);
     scan_one(w.wcnt.p, w.wcnt_base.p, W_b, &rec->d, 6, &rec->u, s);
     scan_one(w.wlen.p, w.wlen_base.p, W_b, &rec->d, 6, &rec->q, s);
     if (pe) pe->rec(5, s);
@@ -684,7 +694,6 @@ struct Cohort {
       sync(s);
     }
     ensure_level(g, lv, s);
-    const uint64_t t_classify = pe.ns(0, 1), t_emit = pe.ns(2, 8);
     const uint64_t est =
         sketch ? std::min<uint64_t>(d, (uint64_t)(hll_estimate(mb->ctr.hll) * 1.25) + 64) : d;
     const void* content = bytes ? (const void*)d_text : (const void*)w.sym[cur ^ 1].p;
@@ -695,6 +704,8 @@ struct Cohort {
     launch_finish(cur_off, w.off[cur].p, k, w.sym[cur].p, lv, g->c_level.p + c_base,
                   g->c_sym.p + c_base, w.fin.p, s);
     pe.rec(7, s);
+    // dedup_commit has waited for the insert: every earlier event is complete
+    const uint64_t t_classify = pe.ns(0, 1), t_emit = pe.ns(2, 8);
     const uint64_t t_insert = pe.ns(3, 4), t_rank = pe.ns(4, 5);
     prev = Stat{active_len, d, r.u_new, r.q_new, 0, r.probes, r.compares, g->levels[lv - 1].tcap,
                 t_classify + t_emit + t_insert + t_rank, t_classify, t_emit, t_insert, t_rank, 0, 0,
