@@ -62,11 +62,15 @@ enum {
 
 enum {
   LCG_FLAG_TIMING = 1u,        /* record per-round device time in the round statistics */
-  LCG_FLAG_TIMING_INSERT = 2u  /* record only the dictionary insert's device time, and only
+  LCG_FLAG_TIMING_INSERT = 2u, /* record only the dictionary insert's device time, and only
                                   in rounds that read their sizes back (not in rounds queued
                                   without host reads, see tail_log2); every other time field
                                   is 0.  Two events per such round instead of about nine per
                                   round: timing every phase slows a build by a few percent */
+  LCG_FLAG_SPLIT_TAIL = 4u     /* run the rounds queued without host reads (tail_log2) as
+                                  separate kernels per phase instead of one cooperative launch
+                                  for all of them (also the case with LCG_FLAG_TIMING).
+                                  Results do not depend on it. */
 };
 
 typedef struct {
@@ -79,9 +83,11 @@ typedef struct {
                           right-hand-side comparison; 0 = normal keys */
   uint32_t table_min_log2; /* smallest dictionary capacity, log2 (6..34; 0 = 12) */
   uint32_t tail_log2;  /* rounds over at most 2^tail_log2 symbols are queued without reading
-                          sizes back to the host (each kernel reads its size from device
-                          memory, dictionaries are sized for the worst case); 1..40,
-                          0 = 22.  Results do not depend on it. */
+                          sizes back to the host (dictionaries are sized for the worst
+                          case): all of them in one cooperative launch whose phases are
+                          separated by grid-wide barriers, or, with LCG_FLAG_SPLIT_TAIL,
+                          as separate kernels that read their sizes from device memory;
+                          1..40, 0 = 22.  Results do not depend on it. */
   uint32_t table_load_log2; /* dictionaries are sized for a load of at most 2^-table_load_log2
                                of their capacity; 1..3, 0 = 1.  Results do not depend on it. */
   uint32_t combine_log2;    /* a round whose key sketch estimates at most d / 2^combine_log2

@@ -29,6 +29,16 @@ struct Counters {
   unsigned int hll[kHll];       // HyperLogLog registers of the round's phrase keys
 };
 
+// What the device records of one round run without host reads (tail mode).
+struct TailRec {
+  uint64_t d;    // phrases (the length of the next round's sequence)
+  uint64_t u;    // new rules
+  uint64_t q;    // new right-hand-side symbols
+  uint64_t pad;
+  Counters ctr;  // dictionary counters
+  Counters fin;  // strings still longer than one symbol after the round
+};
+
 // Strings a tile of kTile positions overlaps (lo..hi) and the offsets of
 // string lo.
 struct TileSeg {
@@ -123,6 +133,65 @@ constexpr uint64_t kCommitListRatio = 4;
 // Rules with rank < rank_limit (kNone: every committed rule) into new_t.
 void launch_rehash(const Slot* old_t, uint64_t old_cap, Slot* new_t, uint64_t new_mask,
                    uint32_t rank_limit, Counters* ctr, hipStream_t s);
+
+// ---- the short rounds fused into one cooperative launch
+// One round of the fused tail, as the host prepared it: level `level`'s
+// coefficients, dictionary and rule arrays (grown for the round's worst
+// case), the fingerprints of the level below, and where the round's counts
+// go.
+struct TailRound {
+  LevelHash h;
+  Slot* table;
+  uint64_t mask;
+  uint32_t u0;            // rules of the level before the round
+  uint32_t level;
+  uint64_t q0;            // right-hand-side symbols of the level before the round
+  uint64_t* rule_off;
+  void* rule_rhs;         // bytes at level 1, ranks above
+  uint32_t* rule_fp;
+  const uint32_t* fprev;  // F of the level-(level-1) symbols (h^0 of the bytes at level 1)
+  TailRec* rec;
+};
+// Everything the fused tail kernel reads besides its rounds; the work arrays
+// are sized for the first round's bounds, which bound every later round's.
+struct TailArgs {
+  const TailRound* rounds;
+  uint32_t nrounds;
+  uint32_t k;
+  uint64_t n0;             // length of the first round's sequence
+  const uint64_t* off0;    // its segment offsets
+  const uint8_t* text;     // its symbols when it is level 1
+  bool first_bytes;
+  int cur0;                // ping-pong index the first round writes
+  uint32_t key_bits;
+  const uint32_t* lut;
+  uint64_t* bits;
+  uint64_t* tile_cnt;
+  uint64_t* tile_base;
+  TileSeg* tile_seg;
+  uint64_t* pstart;
+  uint32_t* plen;
+  uint64_t* key;
+  uint64_t* wkey;
+  uint32_t* slot_idx;
+  uint32_t* sym[2];
+  uint32_t* fpv[2];
+  uint64_t* off[2];
+  uint64_t* newbits;
+  uint64_t* wcnt;
+  uint64_t* wlen;
+  uint64_t* wcnt_base;
+  uint64_t* wlen_base;
+  uint8_t* c_level;        // the batch's C entries
+  uint32_t* c_sym;
+  uint32_t* rounds_run;    // out: rounds the kernel ran
+};
+// Blocks of the fused tail kernel that the device holds at once (its grid
+// must not exceed them: the rounds synchronise the whole grid).
+unsigned tail_grid();
+// All rounds of a.rounds in one cooperative launch; the kernel stops after
+// the round that leaves no string active.
+void launch_tail(const TailArgs& a, unsigned grid, hipStream_t s);
 
 void launch_c_init(const uint8_t* text, const uint64_t* off, uint32_t k, uint8_t* c_level,
                    uint32_t* c_sym, hipStream_t s);

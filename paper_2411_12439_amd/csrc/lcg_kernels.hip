@@ -15,6 +15,8 @@
 //             store it in C and become inactive (Sec. 3.3)
 // MergeGrams (Sec. 3.6) reuses insert/newflags/scan/commit with G_b's rules
 // as the phrases.
+#include <hip/hip_cooperative_groups.h>
+
 #include <mutex>
 #include <stdexcept>
 #include <string>
@@ -315,22 +317,29 @@ constexpr int kCStagePadded = kCStage + kCStage / 16 + 1;
 // The first and last string each tile overlaps, and the offsets of the first
 // (one thread per tile, so the binary searches over the offsets run side by
 // side, not inside the tile's block).
+__device__ __forceinline__ void tile_seg_range(const uint64_t* __restrict__ off, uint32_t k,
+                                               uint64_t n, TileSeg* __restrict__ tile_seg,
+                                               uint64_t tid, uint64_t nthreads) {
+  const uint64_t tiles = (n + kTile - 1) / kTile;
+  for (uint64_t t = tid; t < tiles; t += nthreads) {
+    const uint64_t t0 = t * kTile;
+    const uint64_t tl = (t0 + kTile < n ? t0 + kTile : n) - 1;
+    const uint32_t lo = seg_search(off, 0, k - 1, t0);
+    const uint32_t hi = seg_search(off, lo, k - 1, tl);
+    TileSeg ts;
+    ts.lo = lo;
+    ts.hi = hi;
+    ts.start = off[lo];
+    ts.end = off[lo + 1];
+    tile_seg[t] = ts;
+  }
+}
+
 __global__ void k_tile_seg(const uint64_t* __restrict__ off, uint32_t k, uint64_t n,
                            const uint64_t* __restrict__ n_dev, TileSeg* __restrict__ tile_seg) {
   if (n_dev) n = *n_dev;
-  const uint64_t tiles = (n + kTile - 1) / kTile;
-  const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (t >= tiles) return;
-  const uint64_t t0 = t * kTile;
-  const uint64_t tl = (t0 + kTile < n ? t0 + kTile : n) - 1;
-  const uint32_t lo = seg_search(off, 0, k - 1, t0);
-  const uint32_t hi = seg_search(off, lo, k - 1, tl);
-  TileSeg ts;
-  ts.lo = lo;
-  ts.hi = hi;
-  ts.start = off[lo];
-  ts.end = off[lo + 1];
-  tile_seg[t] = ts;
+  tile_seg_range(off, k, n, tile_seg, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x,
+                 (uint64_t)gridDim.x * blockDim.x);
 }
 
 // A tile's raw input, held in registers from its load to its staging: 16
@@ -422,19 +431,28 @@ __device__ __forceinline__ void tile_store(const TileRegs<BYTES>& r, const uint3
 // for memory once; the map brings the offsets of the tile's first string.
 // (A resident-sized grid looping over tiles measured slower: the loop form
 // needs 92-116 VGPRs, half the occupancy.)
+// LDS of one classified tile.
+struct ClassifyLds {
+  uint32_t s_lut[256];
+  uint32_t s_f[kCStagePadded];
+  uint32_t s_mask[kBlock];
+  uint32_t s_cnt;
+};
+
+// Break bits and break count of one tile (the whole block; returns at once,
+// for every thread, past the end of the sequence).
 template <bool BYTES>
-__global__ __launch_bounds__(kBlock) void k_classify(RoundIn in0, uint64_t* __restrict__ bits,
-                                                     uint64_t* __restrict__ tile_cnt,
-                                                     const TileSeg* __restrict__ tile_seg) {
-  RoundIn in = in0;
-  if (in0.n_dev) in.n = *in0.n_dev;  // launched over a bound; the size is on the device
-  const uint64_t tile = blockIdx.x;
+__device__ __forceinline__ void classify_tile(const RoundIn& in, uint64_t tile,
+                                              uint64_t* __restrict__ bits,
+                                              uint64_t* __restrict__ tile_cnt,
+                                              const TileSeg* __restrict__ tile_seg,
+                                              ClassifyLds& sh) {
   const uint64_t t0 = tile * kTile;
   if (t0 >= in.n) return;
-  __shared__ uint32_t s_lut[256];
-  __shared__ uint32_t s_f[kCStagePadded];
-  __shared__ uint32_t s_mask[kBlock];
-  __shared__ uint32_t s_cnt;
+  uint32_t* const s_lut = sh.s_lut;
+  uint32_t* const s_f = sh.s_f;
+  uint32_t* const s_mask = sh.s_mask;
+  uint32_t& s_cnt = sh.s_cnt;
   TileRegs<BYTES> regs;
   tile_load<BYTES>(in, t0, regs);
   const TileSeg ts = tile_seg[tile];
@@ -546,6 +564,16 @@ __global__ __launch_bounds__(kBlock) void k_classify(RoundIn in0, uint64_t* __re
     bits[tile * kTileWords + threadIdx.x] = w;
   }
   if (threadIdx.x == 0) tile_cnt[tile] = s_cnt;
+}
+
+template <bool BYTES>
+__global__ __launch_bounds__(kBlock) void k_classify(RoundIn in0, uint64_t* __restrict__ bits,
+                                                     uint64_t* __restrict__ tile_cnt,
+                                                     const TileSeg* __restrict__ tile_seg) {
+  __shared__ ClassifyLds sh;
+  RoundIn in = in0;
+  if (in0.n_dev) in.n = *in0.n_dev;  // launched over a bound; the size is on the device
+  classify_tile<BYTES>(in, blockIdx.x, bits, tile_cnt, tile_seg, sh);
 }
 
 void launch_classify(const RoundIn& in, uint64_t* bits, uint64_t* tile_cnt, TileSeg* tile_seg,
@@ -718,32 +746,43 @@ __device__ __forceinline__ uint64_t phrase_fp(const RoundIn& in, const uint32_t*
 
 constexpr uint32_t kLongList = 2048;  // long phrases deferred per tile; more are done inline
 
+// LDS of the emit pass.
 template <bool BYTES>
-__global__ __launch_bounds__(kBlock) void k_emit(RoundIn in0, const uint64_t* __restrict__ bits,
-                                                 const uint64_t* __restrict__ tile_base,
-                                                 const TileSeg* __restrict__ tile_seg, uint64_t tiles,
-                                                 LevelHash h, uint32_t key_bits,
-                                                 uint64_t* __restrict__ pstart, uint32_t* __restrict__ plen,
-                                                 uint64_t* __restrict__ key, uint64_t* __restrict__ wkey,
-                                                 uint32_t* __restrict__ fnew,
-                                                 uint8_t* __restrict__ hll_part) {
-  __shared__ uint32_t s_lut[256];
-  __shared__ uint16_t s_start[kTile];
-  __shared__ uint16_t s_long[kLongList];
-  __shared__ uint64_t s_off[kSegCache + 1];
-  __shared__ uint32_t s_seg[2];
-  __shared__ uint32_t s_wave[kBlock / 64];
-  __shared__ uint32_t s_nlong;
-  __shared__ uint32_t s_hll[kHll];
-  __shared__ EmitStage<BYTES> st;
-  RoundIn in = in0;
-  if (in0.n_dev) {  // launched over a bound; the size is on the device
-    in.n = *in0.n_dev;
-    tiles = (in.n + kTile - 1) / kTile;
-  }
+struct EmitLds {
+  uint32_t s_lut[256];
+  uint16_t s_start[kTile];
+  uint16_t s_long[kLongList];
+  uint64_t s_off[kSegCache + 1];
+  uint32_t s_seg[2];
+  uint32_t s_wave[kBlock / 64];
+  uint32_t s_nlong;
+  uint32_t s_hll[kHll];
+  EmitStage<BYTES> st;
+};
+
+// Phrases of tiles block, block + blocks, ... (the whole block); the block's
+// HyperLogLog registers go to hll_part row `block` when hll_part is given.
+template <bool BYTES>
+__device__ __forceinline__ void emit_tiles(const RoundIn& in, uint64_t tiles, uint64_t block,
+                                           uint64_t blocks, const uint64_t* __restrict__ bits,
+                                           const uint64_t* __restrict__ tile_base,
+                                           const TileSeg* __restrict__ tile_seg, LevelHash h,
+                                           uint32_t key_bits, uint64_t* __restrict__ pstart,
+                                           uint32_t* __restrict__ plen, uint64_t* __restrict__ key,
+                                           uint64_t* __restrict__ wkey, uint32_t* __restrict__ fnew,
+                                           uint8_t* __restrict__ hll_part, EmitLds<BYTES>& sh) {
+  uint32_t* const s_lut = sh.s_lut;
+  uint16_t* const s_start = sh.s_start;
+  uint16_t* const s_long = sh.s_long;
+  uint64_t* const s_off = sh.s_off;
+  uint32_t* const s_seg = sh.s_seg;
+  uint32_t* const s_wave = sh.s_wave;
+  uint32_t& s_nlong = sh.s_nlong;
+  uint32_t* const s_hll = sh.s_hll;
+  EmitStage<BYTES>& st = sh.st;
   if constexpr (BYTES) s_lut[threadIdx.x] = in.lut[threadIdx.x];
   for (int i = threadIdx.x; i < kHll; i += kBlock) s_hll[i] = 0;
-  for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+  for (uint64_t tile = block; tile < tiles; tile += blocks) {
     const uint64_t t0 = tile * kTile;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -838,8 +877,28 @@ __global__ __launch_bounds__(kBlock) void k_emit(RoundIn in0, const uint64_t* __
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kHll; i += kBlock)
-    hll_part[(uint64_t)blockIdx.x * kHll + i] = (uint8_t)s_hll[i];
+  if (hll_part)
+    for (int i = threadIdx.x; i < kHll; i += kBlock)
+      hll_part[block * kHll + i] = (uint8_t)s_hll[i];
+}
+
+template <bool BYTES>
+__global__ __launch_bounds__(kBlock) void k_emit(RoundIn in0, const uint64_t* __restrict__ bits,
+                                                 const uint64_t* __restrict__ tile_base,
+                                                 const TileSeg* __restrict__ tile_seg, uint64_t tiles,
+                                                 LevelHash h, uint32_t key_bits,
+                                                 uint64_t* __restrict__ pstart, uint32_t* __restrict__ plen,
+                                                 uint64_t* __restrict__ key, uint64_t* __restrict__ wkey,
+                                                 uint32_t* __restrict__ fnew,
+                                                 uint8_t* __restrict__ hll_part) {
+  __shared__ EmitLds<BYTES> sh;
+  RoundIn in = in0;
+  if (in0.n_dev) {  // launched over a bound; the size is on the device
+    in.n = *in0.n_dev;
+    tiles = (in.n + kTile - 1) / kTile;
+  }
+  emit_tiles<BYTES>(in, tiles, blockIdx.x, gridDim.x, bits, tile_base, tile_seg, h, key_bits,
+                    pstart, plen, key, wkey, fnew, hll_part, sh);
 }
 
 // register-wise maximum of the per-block HyperLogLog sketches: block i
@@ -942,19 +1001,24 @@ void scan_exclusive(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* tmp
 // device: count = ceil(*x_dev / 2^shift) (or count_host without x_dev).
 // out[count] and, if given, *total receive the sum.
 constexpr int kScanOneThreads = 1024;
-__global__ __launch_bounds__(kScanOneThreads) void k_scan_one(const uint64_t* __restrict__ in,
-                                                              uint64_t* __restrict__ out,
-                                                              uint64_t count,
-                                                              const uint64_t* __restrict__ x_dev,
-                                                              int shift,
-                                                              uint64_t* __restrict__ total) {
-  __shared__ uint64_t s_wave[kScanOneThreads / 64];
-  __shared__ uint64_t s_carry;
-  if (x_dev) count = (*x_dev + (1ull << shift) - 1) >> shift;
+
+// LDS of a one-block scan (blocks of up to kScanOneThreads threads).
+struct ScanLds {
+  uint64_t s_wave[kScanOneThreads / 64];
+  uint64_t s_carry;
+};
+
+// Exclusive scan of in[0..count) into out[0..count] by the whole block
+// (blockDim.x a multiple of 64); out[count] and *total (if given) receive
+// the sum.
+__device__ __forceinline__ void scan_block(const uint64_t* __restrict__ in,
+                                           uint64_t* __restrict__ out, uint64_t count,
+                                           uint64_t* __restrict__ total, ScanLds& sh) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (threadIdx.x == 0) s_carry = 0;
+  const int nw = blockDim.x / 64;
+  if (threadIdx.x == 0) sh.s_carry = 0;
   __syncthreads();
-  for (uint64_t c0 = 0; c0 < count; c0 += kScanOneThreads) {
+  for (uint64_t c0 = 0; c0 < count; c0 += blockDim.x) {
     const uint64_t i = c0 + threadIdx.x;
     const uint64_t v = i < count ? in[i] : 0;
     uint64_t x = v;
@@ -963,23 +1027,34 @@ __global__ __launch_bounds__(kScanOneThreads) void k_scan_one(const uint64_t* __
       const uint64_t y = __shfl_up(x, d, 64);
       if (lane >= d) x += y;
     }
-    if (lane == 63) s_wave[wid] = x;
+    if (lane == 63) sh.s_wave[wid] = x;
     __syncthreads();
-    uint64_t base = s_carry, tot = 0;
-    for (int w = 0; w < kScanOneThreads / 64; ++w) {
-      const uint64_t sw = s_wave[w];
+    uint64_t base = sh.s_carry, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+      const uint64_t sw = sh.s_wave[w];
       if (w < wid) base += sw;
       tot += sw;
     }
     if (i < count) out[i] = base + x - v;
     __syncthreads();
-    if (threadIdx.x == 0) s_carry += tot;
+    if (threadIdx.x == 0) sh.s_carry += tot;
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[count] = s_carry;
-    if (total) *total = s_carry;
+    out[count] = sh.s_carry;
+    if (total) *total = sh.s_carry;
   }
+}
+
+__global__ __launch_bounds__(kScanOneThreads) void k_scan_one(const uint64_t* __restrict__ in,
+                                                              uint64_t* __restrict__ out,
+                                                              uint64_t count,
+                                                              const uint64_t* __restrict__ x_dev,
+                                                              int shift,
+                                                              uint64_t* __restrict__ total) {
+  __shared__ ScanLds sh;
+  if (x_dev) count = (*x_dev + (1ull << shift) - 1) >> shift;
+  scan_block(in, out, count, total, sh);
 }
 
 void scan_one(const uint64_t* in, uint64_t* out, uint64_t count, const uint64_t* x_dev, int shift,
@@ -1049,35 +1124,36 @@ __device__ __forceinline__ bool same_seq(const Sym* a, const Sym* b, uint32_t le
 // *d_dev; a separate instance, so that profiles tell the rounds queued without
 // host reads from the others).
 template <typename Sym, bool DEV_COUNT>
-__global__ __launch_bounds__(256) void k_insert(uint64_t begin, uint64_t end, uint64_t d,
-                                                const uint64_t* __restrict__ d_dev,
-                                                const uint32_t* __restrict__ list,
-                                                const uint32_t* __restrict__ list_len,
-                                                const uint64_t* __restrict__ key,
-                                                const uint64_t* __restrict__ wkey,
-                                                const uint64_t* __restrict__ pstart,
-                                                const uint32_t* __restrict__ plen,
-                                                const Sym* __restrict__ content,
-                                                const uint64_t* __restrict__ rule_off,
-                                                const Sym* __restrict__ rule_rhs, uint32_t u_committed,
-                                                Slot* table, uint64_t mask,
-                                                uint32_t* __restrict__ slot_idx,
-                                                uint32_t* __restrict__ won_list,
-                                                uint64_t won_per_wave,
-                                                uint32_t* __restrict__ won_cnt,
-                                                Counters* __restrict__ ctr) {
-  __shared__ unsigned long long s_sum[4];
+__device__ __forceinline__ void insert_phrases(uint64_t block, uint64_t blocks, uint64_t begin,
+                                               uint64_t end, uint64_t d,
+                                               const uint64_t* __restrict__ d_dev,
+                                               const uint32_t* __restrict__ list,
+                                               const uint32_t* __restrict__ list_len,
+                                               const uint64_t* __restrict__ key,
+                                               const uint64_t* __restrict__ wkey,
+                                               const uint64_t* __restrict__ pstart,
+                                               const uint32_t* __restrict__ plen,
+                                               const Sym* __restrict__ content,
+                                               const uint64_t* __restrict__ rule_off,
+                                               const Sym* __restrict__ rule_rhs,
+                                               uint32_t u_committed, Slot* table, uint64_t mask,
+                                               uint32_t* __restrict__ slot_idx,
+                                               uint32_t* __restrict__ won_list,
+                                               uint64_t won_per_wave,
+                                               uint32_t* __restrict__ won_cnt,
+                                               Counters* __restrict__ ctr,
+                                               unsigned long long* s_sum) {
   if (threadIdx.x < 4) s_sum[threadIdx.x] = 0;
   __syncthreads();
   unsigned long long won = 0, probes = 0, cmps = 0, fails = 0;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t stride = blocks * blockDim.x;
   if constexpr (DEV_COUNT) end = d = *d_dev;  // launched over a bound; the count is on the device
   const uint64_t lim = list ? (uint64_t)*list_len : end;
   // every wave walks its own phrases (the same trip count for all its lanes)
   // and lists the slots it claims in its own region of the won list
   const uint32_t lane = threadIdx.x & 63;
-  const uint64_t wave = blockIdx.x * (uint64_t)(blockDim.x / 64) + (threadIdx.x >> 6);
-  uint32_t* const my_won = won_list + wave * won_per_wave;
+  const uint64_t wave = block * (uint64_t)(blockDim.x / 64) + (threadIdx.x >> 6);
+  uint32_t* const my_won = won_list ? won_list + wave * won_per_wave : nullptr;
   uint32_t nwon = 0;
   for (uint64_t wb = begin + wave * 64; wb < lim; wb += stride) {
     const uint64_t i = wb + lane;
@@ -1177,11 +1253,13 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t begin, uint64_t end, ui
     }
     __builtin_nontemporal_store(result, &slot_idx[o]);
     }
-    const uint64_t bal = __ballot(claimed);
-    if (claimed) my_won[nwon + __builtin_popcountll(bal & ((1ull << lane) - 1ull))] = result;
-    nwon += (uint32_t)__builtin_popcountll(bal);
+    if (my_won) {
+      const uint64_t bal = __ballot(claimed);
+      if (claimed) my_won[nwon + __builtin_popcountll(bal & ((1ull << lane) - 1ull))] = result;
+      nwon += (uint32_t)__builtin_popcountll(bal);
+    }
   }
-  if (lane == 0) won_cnt[wave] = nwon;
+  if (my_won && lane == 0) won_cnt[wave] = nwon;
   // one global atomic per block and counter
   won = wave_sum(won);
   probes = wave_sum(probes);
@@ -1200,6 +1278,30 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t begin, uint64_t end, ui
     if (s_sum[2]) atomicAdd(&ctr->compares, s_sum[2]);
     if (s_sum[3]) atomicAdd(&ctr->overflow, (unsigned int)s_sum[3]);
   }
+}
+
+template <typename Sym, bool DEV_COUNT>
+__global__ __launch_bounds__(256) void k_insert(uint64_t begin, uint64_t end, uint64_t d,
+                                                const uint64_t* __restrict__ d_dev,
+                                                const uint32_t* __restrict__ list,
+                                                const uint32_t* __restrict__ list_len,
+                                                const uint64_t* __restrict__ key,
+                                                const uint64_t* __restrict__ wkey,
+                                                const uint64_t* __restrict__ pstart,
+                                                const uint32_t* __restrict__ plen,
+                                                const Sym* __restrict__ content,
+                                                const uint64_t* __restrict__ rule_off,
+                                                const Sym* __restrict__ rule_rhs, uint32_t u_committed,
+                                                Slot* table, uint64_t mask,
+                                                uint32_t* __restrict__ slot_idx,
+                                                uint32_t* __restrict__ won_list,
+                                                uint64_t won_per_wave,
+                                                uint32_t* __restrict__ won_cnt,
+                                                Counters* __restrict__ ctr) {
+  __shared__ unsigned long long s_sum[4];
+  insert_phrases<Sym, DEV_COUNT>(blockIdx.x, gridDim.x, begin, end, d, d_dev, list, list_len, key,
+                                 wkey, pstart, plen, content, rule_off, rule_rhs, u_committed,
+                                 table, mask, slot_idx, won_list, won_per_wave, won_cnt, ctr, s_sum);
 }
 
 // Combining insert for rounds whose phrases repeat a few keys many times
@@ -1437,6 +1539,39 @@ void launch_insert(bool bytes, uint64_t d, const uint64_t* d_dev, const uint64_t
 // phrases the new rules and their right-hand-side lengths.  For rounds where
 // most phrases are new: a coalesced pass over the phrases beats one random
 // flag per new rule.
+// Flag words wave, wave + waves, ... (one wave per word of 64 phrases).
+template <bool BYTES>
+__device__ __forceinline__ void newflags_words(uint64_t d, uint64_t wave, uint64_t waves,
+                                               const uint32_t* __restrict__ slot_idx,
+                                               const Slot* __restrict__ table,
+                                               const uint64_t* __restrict__ key,
+                                               const uint32_t* __restrict__ plen,
+                                               uint64_t* __restrict__ newbits,
+                                               uint64_t* __restrict__ wcnt,
+                                               uint64_t* __restrict__ wlen) {
+  const uint32_t lane = threadIdx.x & 63;
+  for (uint64_t w = wave; (w << 6) < d; w += waves) {
+    const uint64_t o = (w << 6) + lane;
+    bool f = false;
+    unsigned long long len = 0;
+    if (o < d) {
+      const uint32_t sidx = slot_idx[o];
+      if (sidx != kNone) {
+        const uint64_t mr = *reinterpret_cast<const uint64_t*>(&table[sidx].minocc);
+        f = (uint32_t)(mr >> 32) == kNone && (uint32_t)mr == (uint32_t)o;
+      }
+      if (f) len = key_len<BYTES>(key[o], plen, o);
+    }
+    const uint64_t bal = __ballot(f);
+    len = wave_sum(len);
+    if (lane == 0) {
+      newbits[w] = bal;
+      wcnt[w] = __builtin_popcountll(bal);
+      wlen[w] = len;
+    }
+  }
+}
+
 template <bool BYTES>
 __global__ __launch_bounds__(256) void k_newflags(uint64_t d, const uint64_t* __restrict__ d_dev,
                                                   const uint32_t* __restrict__ slot_idx,
@@ -1447,26 +1582,9 @@ __global__ __launch_bounds__(256) void k_newflags(uint64_t d, const uint64_t* __
                                                   uint64_t* __restrict__ wcnt,
                                                   uint64_t* __restrict__ wlen) {
   if (d_dev) d = *d_dev;
-  const uint64_t o = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (((o >> 6) << 6) >= d) return;  // the whole wave is past the end
-  bool f = false;
-  unsigned long long len = 0;
-  if (o < d) {
-    const uint32_t sidx = slot_idx[o];
-    if (sidx != kNone) {
-      const uint64_t mr = *reinterpret_cast<const uint64_t*>(&table[sidx].minocc);
-      f = (uint32_t)(mr >> 32) == kNone && (uint32_t)mr == (uint32_t)o;
-    }
-    if (f) len = key_len<BYTES>(key[o], plen, o);
-  }
-  const uint64_t bal = __ballot(f);
-  len = wave_sum(len);
-  const uint64_t w = o >> 6;
-  if ((threadIdx.x & 63) == 0 && (w << 6) < d) {
-    newbits[w] = bal;
-    wcnt[w] = __builtin_popcountll(bal);
-    wlen[w] = len;
-  }
+  newflags_words<BYTES>(d, blockIdx.x * (uint64_t)(blockDim.x / 64) + (threadIdx.x >> 6),
+                        (uint64_t)gridDim.x * (blockDim.x / 64), slot_idx, table, key, plen,
+                        newbits, wcnt, wlen);
 }
 
 void launch_newflags(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t* slot_idx,
@@ -1644,7 +1762,45 @@ __device__ __forceinline__ void commit_one(uint64_t o, uint32_t r, uint64_t q, u
 
 // one wave per flag word of 64 phrases: ranks from the word's count base and
 // the wave's ballot prefix, right-hand-side offsets from the word's length
-// base and a wave scan
+// base and a wave scan.  Words wave, wave + waves, ...
+template <typename Sym>
+__device__ __forceinline__ void commit_words(uint64_t d, uint64_t wave, uint64_t waves,
+                                             const uint32_t* __restrict__ slot_idx, Slot* table,
+                                             const uint64_t* __restrict__ newbits,
+                                             const uint64_t* __restrict__ wcnt_base,
+                                             const uint64_t* __restrict__ wlen_base,
+                                             const uint64_t* __restrict__ key,
+                                             const uint64_t* __restrict__ wkey,
+                                             const uint64_t* __restrict__ pstart,
+                                             const uint32_t* __restrict__ plen,
+                                             const Sym* __restrict__ content,
+                                             const uint32_t* __restrict__ fnew,
+                                             const uint32_t* __restrict__ fprev, LevelHash h,
+                                             uint32_t u_prev, uint64_t q_prev,
+                                             uint64_t* __restrict__ rule_off,
+                                             Sym* __restrict__ rule_rhs,
+                                             uint32_t* __restrict__ rule_fp) {
+  constexpr bool kBytes = sizeof(Sym) == 1;
+  const uint64_t W = (d + 63) / 64;
+  const uint32_t lane = threadIdx.x & 63;
+  for (uint64_t wd = wave; wd < W; wd += waves) {
+    const uint64_t fw = newbits[wd];
+    if (!fw) continue;  // uniform in the wave
+    const uint64_t o = wd * 64 + lane;
+    const bool isnew = (fw >> lane) & 1ULL;
+    const uint64_t kk = isnew ? key[o] : 0;
+    const uint32_t L = isnew ? key_len<kBytes>(kk, plen, o) : 0;
+    const unsigned long long excl = wave_excl_scan(L);
+    if (isnew) {
+      const uint32_t r = u_prev + (uint32_t)(wcnt_base[wd] +
+                                             __builtin_popcountll(fw & ((1ULL << lane) - 1ULL)));
+      const uint64_t q = q_prev + wlen_base[wd] + excl;
+      commit_one<Sym>(o, r, q, kk, L, slot_idx[o], table, wkey, pstart, content, fnew, fprev, h,
+                      rule_off, rule_rhs, rule_fp);
+    }
+  }
+}
+
 template <typename Sym>
 __global__ __launch_bounds__(256) void k_commit_new(uint64_t d, const uint64_t* __restrict__ d_dev,
                                                     const uint32_t* __restrict__ slot_idx,
@@ -1662,25 +1818,11 @@ __global__ __launch_bounds__(256) void k_commit_new(uint64_t d, const uint64_t* 
                                                     uint64_t* __restrict__ rule_off,
                                                     Sym* __restrict__ rule_rhs,
                                                     uint32_t* __restrict__ rule_fp) {
-  constexpr bool kBytes = sizeof(Sym) == 1;
   if (d_dev) d = *d_dev;
-  const uint64_t W = (d + 63) / 64;
-  const uint32_t lane = threadIdx.x & 63;
-  const uint64_t wd = blockIdx.x * (uint64_t)(blockDim.x / 64) + (threadIdx.x >> 6);
-  if (wd >= W) return;  // uniform in the wave
-  const uint64_t fw = newbits[wd];
-  if (!fw) return;  // uniform in the wave
-  const uint64_t o = wd * 64 + lane;
-  const bool isnew = (fw >> lane) & 1ULL;
-  const uint64_t kk = isnew ? key[o] : 0;
-  const uint32_t L = isnew ? key_len<kBytes>(kk, plen, o) : 0;
-  const unsigned long long excl = wave_excl_scan(L);
-  if (!isnew) return;
-  const uint32_t r = u_prev + (uint32_t)(wcnt_base[wd] +
-                                         __builtin_popcountll(fw & ((1ULL << lane) - 1ULL)));
-  const uint64_t q = q_prev + wlen_base[wd] + excl;
-  commit_one<Sym>(o, r, q, kk, L, slot_idx[o], table, wkey, pstart, content, fnew, fprev, h,
-                  rule_off, rule_rhs, rule_fp);
+  commit_words<Sym>(d, blockIdx.x * (uint64_t)(blockDim.x / 64) + (threadIdx.x >> 6),
+                    (uint64_t)gridDim.x * (blockDim.x / 64), slot_idx, table, newbits, wcnt_base,
+                    wlen_base, key, wkey, pstart, plen, content, fnew, fprev, h, u_prev, q_prev,
+                    rule_off, rule_rhs, rule_fp);
 }
 
 // When few phrases are new, one wave per word leaves most lanes idle: the new
@@ -1746,14 +1888,13 @@ __device__ __forceinline__ uint64_t rank_and_fp(const Slot* __restrict__ table, 
   return sidx == kNone ? 0 : *reinterpret_cast<const uint64_t*>(&table[sidx].minocc);
 }
 
-__global__ __launch_bounds__(256) void k_rewrite(uint64_t d, const uint64_t* __restrict__ d_dev,
-                                                 const uint32_t* __restrict__ slot_idx,
-                                                 const Slot* __restrict__ table,
-                                                 uint32_t* __restrict__ sym_next,
-                                                 uint32_t* __restrict__ fnext) {
-  if (d_dev) d = *d_dev;
-  const uint64_t o = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) * kRewriteItems;
-  if (o >= d) return;
+// Phrases of the groups of four g = tid, tid + nthreads, ...
+__device__ __forceinline__ void rewrite_range(uint64_t d, uint64_t tid, uint64_t nthreads,
+                                              const uint32_t* __restrict__ slot_idx,
+                                              const Slot* __restrict__ table,
+                                              uint32_t* __restrict__ sym_next,
+                                              uint32_t* __restrict__ fnext) {
+  for (uint64_t o = tid * kRewriteItems; o < d; o += nthreads * kRewriteItems) {
   if (o + kRewriteItems <= d) {
     // the phrase arrays stream past (non-temporal), the table lines stay cached
     const u32x4 si = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(slot_idx + o));
@@ -1773,6 +1914,17 @@ __global__ __launch_bounds__(256) void k_rewrite(uint64_t d, const uint64_t* __r
       if (fnext) fnext[x] = (uint32_t)fr;
     }
   }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rewrite(uint64_t d, const uint64_t* __restrict__ d_dev,
+                                                 const uint32_t* __restrict__ slot_idx,
+                                                 const Slot* __restrict__ table,
+                                                 uint32_t* __restrict__ sym_next,
+                                                 uint32_t* __restrict__ fnext) {
+  if (d_dev) d = *d_dev;
+  rewrite_range(d, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x,
+                (uint64_t)gridDim.x * blockDim.x, slot_idx, table, sym_next, fnext);
 }
 
 void launch_commit(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t* slot_idx, Slot* table,
@@ -1886,22 +2038,32 @@ void launch_c_init(const uint8_t* text, const uint64_t* off, uint32_t k, uint8_t
 
 // Next-round offsets: the phrases of string j start at the number of breaks
 // before its first position (tile prefix + popcount inside the tile).
+// Next-round offsets of strings j = tid, tid + nthreads, ... <= k.
+__device__ __forceinline__ void segments_range(const uint64_t* __restrict__ off, uint32_t k,
+                                               const uint64_t* __restrict__ bits,
+                                               const uint64_t* __restrict__ tile_base, uint64_t d,
+                                               uint64_t* __restrict__ new_off, uint64_t tid,
+                                               uint64_t nthreads) {
+  for (uint64_t j = tid; j <= k; j += nthreads) {
+    if (j == k) {
+      new_off[k] = d;
+      continue;
+    }
+    const uint64_t x = off[j];
+    const uint64_t tile = x / kTile;
+    uint64_t r = tile_base[tile];
+    for (uint64_t wd = tile * kTileWords; wd < (x >> 6); ++wd) r += __builtin_popcountll(bits[wd]);
+    if (x & 63) r += __builtin_popcountll(bits[x >> 6] & ((1ULL << (x & 63)) - 1ULL));
+    new_off[j] = r;
+  }
+}
+
 __global__ void k_segments(const uint64_t* __restrict__ off, uint32_t k,
                            const uint64_t* __restrict__ bits, const uint64_t* __restrict__ tile_base,
                            uint64_t d, const uint64_t* __restrict__ d_dev,
                            uint64_t* __restrict__ new_off) {
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j > k) return;
-  if (j == k) {
-    new_off[k] = d_dev ? *d_dev : d;
-    return;
-  }
-  const uint64_t x = off[j];
-  const uint64_t tile = x / kTile;
-  uint64_t r = tile_base[tile];
-  for (uint64_t wd = tile * kTileWords; wd < (x >> 6); ++wd) r += __builtin_popcountll(bits[wd]);
-  if (x & 63) r += __builtin_popcountll(bits[x >> 6] & ((1ULL << (x & 63)) - 1ULL));
-  new_off[j] = r;
+  segments_range(off, k, bits, tile_base, d_dev ? *d_dev : d, new_off,
+                 blockIdx.x * (uint64_t)blockDim.x + threadIdx.x, (uint64_t)gridDim.x * blockDim.x);
 }
 
 void launch_segments(const uint64_t* off, uint32_t k, const uint64_t* bits,
@@ -1912,28 +2074,44 @@ void launch_segments(const uint64_t* off, uint32_t k, const uint64_t* bits,
   LCG_LAUNCH_CHECK("segments");
 }
 
+// Strings of the waves' groups of 64 (wave, wave + waves, ...): a string
+// reduced to one symbol stores it in C; the others are counted as active.
+__device__ __forceinline__ void finish_range(const uint64_t* __restrict__ off,
+                                             const uint64_t* __restrict__ new_off, uint32_t k,
+                                             const uint32_t* __restrict__ sym_next,
+                                             uint32_t level, uint8_t* __restrict__ c_level,
+                                             uint32_t* __restrict__ c_sym,
+                                             Counters* __restrict__ ctr, uint64_t wave,
+                                             uint64_t waves) {
+  for (uint64_t w = wave; (w << 6) < k; w += waves) {
+    const uint64_t j = (w << 6) + (threadIdx.x & 63);
+    unsigned long long act = 0, act_len = 0;
+    if (j < k) {
+      const uint64_t lo = off[j + 1] - off[j];
+      const uint64_t ln = new_off[j + 1] - new_off[j];
+      if (lo >= 2 && ln == 1) {
+        c_level[j] = (uint8_t)level;
+        c_sym[j] = sym_next[new_off[j]];
+      }
+      act = ln >= 2;
+      act_len = ln >= 2 ? ln : 0;
+    }
+    act = wave_sum(act);
+    act_len = wave_sum(act_len);
+    if ((threadIdx.x & 63) == 0 && act) {
+      atomicAdd(&ctr->active, (unsigned int)act);
+      atomicAdd(&ctr->active_len, act_len);
+    }
+  }
+}
+
 __global__ void k_finish(const uint64_t* __restrict__ off, const uint64_t* __restrict__ new_off,
                          uint32_t k, const uint32_t* __restrict__ sym_next, uint32_t level,
                          uint8_t* __restrict__ c_level, uint32_t* __restrict__ c_sym,
                          Counters* __restrict__ ctr) {
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long act = 0, act_len = 0;
-  if (j < k) {
-    const uint64_t lo = off[j + 1] - off[j];
-    const uint64_t ln = new_off[j + 1] - new_off[j];
-    if (lo >= 2 && ln == 1) {
-      c_level[j] = (uint8_t)level;
-      c_sym[j] = sym_next[new_off[j]];
-    }
-    act = ln >= 2;
-    act_len = ln >= 2 ? ln : 0;
-  }
-  act = wave_sum(act);
-  act_len = wave_sum(act_len);
-  if ((threadIdx.x & 63) == 0 && act) {
-    atomicAdd(&ctr->active, (unsigned int)act);
-    atomicAdd(&ctr->active_len, act_len);
-  }
+  finish_range(off, new_off, k, sym_next, level, c_level, c_sym, ctr,
+               blockIdx.x * (uint64_t)(blockDim.x / 64) + (threadIdx.x >> 6),
+               (uint64_t)gridDim.x * (blockDim.x / 64));
 }
 
 void launch_finish(const uint64_t* off, const uint64_t* new_off, uint32_t k,
@@ -2271,6 +2449,132 @@ void launch_xs_expand(bool to_bytes, const uint32_t* sym, const uint64_t* pos, u
     k_xs_expand<false><<<g, kBlock, 0, s>>>(sym, pos, m, rule_off, rule_rhs, e_below,
                                             gc_rule, nsym, npos, nc, gc, out);
   LCG_LAUNCH_CHECK("xs_expand");
+}
+
+// ------------------------------------------------------------------ fused tail
+// The short rounds (the tail) in one cooperative launch: the phases of a
+// round (tile map, classify, tile scan, emit, insert, first-occurrence flags,
+// rank scans, commit, rewrite and segments, finish) run one after another
+// over the whole grid, separated by grid-wide barriers, with the same device
+// functions as the separate kernels.  After each round every block reads the
+// count of strings still active and the loop stops, uniformly, at zero.
+//
+// Blocks on different XCDs do not share an L2, so each barrier is wrapped in
+// agent-scope fences: the release makes a block's writes visible beyond its
+// L2, the acquire drops stale lines from its L1 and L2 before it reads what
+// other blocks wrote.
+union TailLds {
+  ClassifyLds classify;
+  EmitLds<true> emit_bytes;
+  EmitLds<false> emit_ranks;
+  ScanLds scan;
+  unsigned long long sum[4];
+};
+
+__device__ __forceinline__ void grid_barrier(cooperative_groups::grid_group& grid) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  grid.sync();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+template <bool BYTES>
+__device__ __forceinline__ void tail_round(const TailArgs& a, const TailRound& R,
+                                           const uint64_t* cur_off, uint64_t n, int cur,
+                                           cooperative_groups::grid_group& grid, TailLds& sh) {
+  using Sym = typename std::conditional<BYTES, uint8_t, uint32_t>::type;
+  const uint64_t B = gridDim.x, bid = blockIdx.x;
+  const uint64_t T = B * blockDim.x, tid = bid * blockDim.x + threadIdx.x;
+  const uint64_t NW = B * (blockDim.x / 64), wid = bid * (blockDim.x / 64) + (threadIdx.x >> 6);
+  RoundIn in;
+  in.sym = BYTES ? (const void*)a.text : (const void*)a.sym[cur ^ 1];
+  in.fp = BYTES ? nullptr : a.fpv[cur ^ 1];
+  in.lut = a.lut;
+  in.off = cur_off;
+  in.k = a.k;
+  in.n = n;
+  in.n_dev = nullptr;
+  in.bytes = BYTES;
+  const Sym* content = static_cast<const Sym*>(in.sym);
+  const uint64_t tiles = (n + kTile - 1) / kTile;
+  // tile map, then break bits and counts per tile
+  tile_seg_range(cur_off, a.k, n, a.tile_seg, tid, T);
+  grid_barrier(grid);
+  for (uint64_t t = bid; t < tiles; t += B) {
+    __syncthreads();
+    classify_tile<BYTES>(in, t, a.bits, a.tile_cnt, a.tile_seg, sh.classify);
+  }
+  grid_barrier(grid);
+  if (bid == 0) scan_block(a.tile_cnt, a.tile_base, tiles, &R.rec->d, sh.scan);
+  grid_barrier(grid);
+  const uint64_t d = R.rec->d;
+  // phrases: keys, fingerprints of long ones
+  if constexpr (BYTES)
+    emit_tiles<true>(in, tiles, bid, B, a.bits, a.tile_base, a.tile_seg, R.h, a.key_bits, a.pstart,
+                     a.plen, a.key, a.wkey, a.fpv[cur], nullptr, sh.emit_bytes);
+  else
+    emit_tiles<false>(in, tiles, bid, B, a.bits, a.tile_base, a.tile_seg, R.h, a.key_bits,
+                      a.pstart, a.plen, a.key, a.wkey, a.fpv[cur], nullptr, sh.emit_ranks);
+  grid_barrier(grid);
+  insert_phrases<Sym, false>(bid, B, 0, d, d, nullptr, nullptr, nullptr, a.key, a.wkey, a.pstart,
+                             a.plen, content, R.rule_off, static_cast<const Sym*>(R.rule_rhs),
+                             R.u0, R.table, R.mask, a.slot_idx, nullptr, 0, nullptr, &R.rec->ctr,
+                             sh.sum);
+  grid_barrier(grid);
+  newflags_words<BYTES>(d, wid, NW, a.slot_idx, R.table, a.key, a.plen, a.newbits, a.wcnt, a.wlen);
+  grid_barrier(grid);
+  const uint64_t W = (d + 63) / 64;
+  if (bid == 0) scan_block(a.wcnt, a.wcnt_base, W, &R.rec->u, sh.scan);
+  if (bid == (B > 1 ? 1 : 0)) {
+    __syncthreads();
+    scan_block(a.wlen, a.wlen_base, W, &R.rec->q, sh.scan);
+  }
+  grid_barrier(grid);
+  commit_words<Sym>(d, wid, NW, a.slot_idx, R.table, a.newbits, a.wcnt_base, a.wlen_base, a.key,
+                    a.wkey, a.pstart, a.plen, content, a.fpv[cur], R.fprev, R.h, R.u0, R.q0,
+                    R.rule_off, static_cast<Sym*>(R.rule_rhs), R.rule_fp);
+  grid_barrier(grid);
+  rewrite_range(d, tid, T, a.slot_idx, R.table, a.sym[cur], a.fpv[cur]);
+  segments_range(cur_off, a.k, a.bits, a.tile_base, d, a.off[cur], tid, T);
+  grid_barrier(grid);
+  finish_range(cur_off, a.off[cur], a.k, a.sym[cur], R.level, a.c_level, a.c_sym, &R.rec->fin,
+               wid, NW);
+  grid_barrier(grid);
+}
+
+__global__ __launch_bounds__(kBlock) void k_tail(TailArgs a) {
+  __shared__ TailLds sh;
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  const uint64_t* cur_off = a.off0;
+  uint64_t n = a.n0;
+  int cur = a.cur0;
+  uint32_t r = 0;
+  while (r < a.nrounds) {
+    const TailRound& R = a.rounds[r];
+    if (r == 0 && a.first_bytes) tail_round<true>(a, R, cur_off, n, cur, grid, sh);
+    else tail_round<false>(a, R, cur_off, n, cur, grid, sh);
+    ++r;
+    // the same values for every block: written before the last barrier
+    const uint32_t still = R.rec->fin.active;
+    n = R.rec->d;
+    cur_off = a.off[cur];
+    cur ^= 1;
+    if (!still) break;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.rounds_run = r;
+}
+
+unsigned tail_grid() {
+  return resident_blocks((const void*)k_tail, kBlock);
+}
+
+void launch_tail(const TailArgs& a, unsigned grid, hipStream_t s) {
+  if (!grid || grid > tail_grid()) throw std::runtime_error("fused tail: grid not co-resident");
+  TailArgs args = a;
+  void* kargs[] = {&args};
+  const hipError_t e = hipLaunchCooperativeKernel((const void*)k_tail, dim3(grid), dim3(kBlock),
+                                                  kargs, 0, s);
+  if (e != hipSuccess)
+    throw std::runtime_error(std::string("launch of the fused tail: ") + hipGetErrorString(e));
 }
 
 }  // namespace lcg

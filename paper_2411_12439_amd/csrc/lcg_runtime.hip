@@ -56,7 +56,7 @@ static Opts read_opts(const lcg_opts* o) {
   if (o->combine_log2) r.combine_log2 = o->combine_log2;
   if (r.combine_log2 > 31) throw LcgError{LCG_EINVAL, "combine_log2 out of range"};
   r.fail_round = o->fail_round;
-  if (r.flags & ~(uint32_t)(LCG_FLAG_TIMING | LCG_FLAG_TIMING_INSERT))
+  if (r.flags & ~(uint32_t)(LCG_FLAG_TIMING | LCG_FLAG_TIMING_INSERT | LCG_FLAG_SPLIT_TAIL))
     throw LcgError{LCG_EINVAL, "unknown flag"};
   if (r.mode != LCG_MODE_BATCHED && r.mode != LCG_MODE_PLAIN)
     throw LcgError{LCG_EINVAL, "unknown mode"};
@@ -98,16 +98,6 @@ static uint64_t build_bytes(uint64_t n, uint32_t k) {
   return 31 * n + 64ull * k + (64ull << 20);
 }
 
-// What the device records of one round run without host reads (tail mode).
-struct TailRec {
-  uint64_t d;    // phrases (the length of the next round's sequence)
-  uint64_t u;    // new rules
-  uint64_t q;    // new right-hand-side symbols
-  uint64_t pad;
-  Counters ctr;  // dictionary counters
-  Counters fin;  // strings still longer than one symbol after the round
-};
-
 // Reusable per-call scratch.
 struct Work {
   DBuf<uint64_t> bits, tile_cnt, tile_base, scan_tmp;
@@ -122,6 +112,8 @@ struct Work {
   DBuf<TileSeg> tile_seg;
   DBuf<uint32_t> content32, remap[2], rest, won, won_cnt, won2;
   DBuf<struct TailRec> tail;
+  DBuf<TailRound> tail_rounds;
+  DBuf<uint32_t> tail_run;
   void release_after(hipStream_t s) {
     DBuf<uint64_t>* b64[] = {&bits, &tile_cnt, &tile_base, &scan_tmp, &pstart, &key, &wkey, &off[0],
                              &off[1], &newbits, &wcnt, &wlen, &wcnt_base, &wlen_base, &nqoff};
@@ -133,6 +125,8 @@ struct Work {
     ctr.reset_after(s);
     fin.reset_after(s);
     tail.reset_after(s);
+    tail_rounds.reset_after(s);
+    tail_run.reset_after(s);
     content8.reset_after(s);
     hll_part.reset_after(s);
     tile_seg.reset_after(s);
@@ -534,6 +528,174 @@ static void tail_rounds(lcg_grammar* g, uint32_t lv, uint64_t n_i, uint64_t acti
     g->levels.pop_back();
 }
 
+// The tail rounds in one cooperative launch (launch_tail): the host sizes
+// every round it may need for the worst case (Theorem 1's halving from
+// n_i: ceil(log2 n_i) + 2 rounds, each with at most n/2 + k phrases), then
+// the kernel runs them back to back and stops after the round that leaves
+// no string active.  Results are those of tail_rounds, rank for rank.
+static void fused_tail(lcg_grammar* g, uint32_t lv, uint64_t n_i, uint64_t active_len,
+                       const uint8_t* d_text, const uint64_t* cur_off, int cur, uint32_t k,
+                       uint32_t c_base, const Opts& o, Work& w, hipStream_t s) {
+  const size_t levels_before = g->levels.size();
+  const uint32_t lv_start = lv;
+  for (;;) {
+    if (lv >= (uint32_t)HashFamily::kLevels) throw LcgError{LCG_EOVERFLOW, "more than 63 rounds"};
+    uint32_t bits = 0;
+    while (bits < 63 && (1ull << bits) < n_i) ++bits;
+    const uint32_t R = std::min<uint32_t>((uint32_t)HashFamily::kLevels - lv, bits + 2);
+    const bool first_bytes = lv == 1;
+    // bounds of every round: n_0 = n_i, d_r <= n_r / 2 + k + 1, n_{r+1} = d_r
+    std::vector<uint64_t> nb(R), db(R);
+    for (uint32_t r = 0; r < R; ++r) {
+      nb[r] = r ? db[r - 1] : n_i;
+      db[r] = nb[r] / 2 + k + 1;
+    }
+    const uint64_t tiles0 = (nb[0] + kTile - 1) / kTile;
+    const uint64_t W0 = (db[0] + 63) / 64;
+    uint64_t dmax = 0;
+    for (uint32_t r = 0; r < R; ++r) dmax = std::max(dmax, db[r]);
+    w.bits.need(tiles0 * kTileWords, s);
+    w.tile_cnt.need(tiles0, s);
+    w.tile_base.need(tiles0 + 1, s);
+    w.tile_seg.need(tiles0, s);
+    w.pstart.need(dmax, s);
+    w.plen.need(dmax, s);
+    w.key.need(dmax, s);
+    w.wkey.need(2 * dmax, s);
+    w.slot_idx.need(dmax, s);
+    // T^lv (input of the first round) stays in sym / fpv [cur ^ 1] and its
+    // offsets possibly in off[cur ^ 1]: grown keeping their contents
+    if (first_bytes) {
+      w.sym[cur ^ 1].need(dmax, s);
+      w.fpv[cur ^ 1].need(dmax, s);
+    } else {
+      w.sym[cur ^ 1].grow(std::max<uint64_t>(dmax, n_i), n_i, s);
+      w.fpv[cur ^ 1].grow(std::max<uint64_t>(dmax, n_i), n_i, s);
+    }
+    w.sym[cur].need(dmax, s);
+    w.fpv[cur].need(dmax, s);
+    w.off[cur].need(k + 1, s);
+    if (cur_off == w.off[cur ^ 1].p) w.off[cur ^ 1].grow(k + 1, k + 1, s);
+    else w.off[cur ^ 1].need(k + 1, s);
+    w.newbits.need(W0, s);
+    w.wcnt.need(W0, s);
+    w.wlen.need(W0, s);
+    w.wcnt_base.need(W0 + 1, s);
+    w.wlen_base.need(W0 + 1, s);
+    w.tail.need(R, s);
+    w.tail_rounds.need(R, s);
+    w.tail_run.need(1, s);
+    launch_zero(w.tail.p, sizeof(TailRec) * R, s);
+    std::vector<TailRound> rounds(R);
+    for (uint32_t r = 0; r < R; ++r) {
+      const uint32_t lr = lv + r;
+      ensure_level(g, lr, s, db[r] + 1);
+      Level& L = g->levels[lr - 1];
+      ensure_table(L, (uint64_t)L.u + db[r], o, w, s);
+      if ((uint64_t)L.u + db[r] >= kNone) throw LcgError{LCG_EOVERFLOW, "level needs 2^32 ranks"};
+      L.off.grow(L.u + db[r] + 1, L.u + 1, s);
+      L.fp.grow(L.u + db[r], L.u, s);
+      TailRound& T = rounds[r];
+      if (lr == 1) {
+        L.rhs8.grow(L.q + nb[r], L.q, s);
+        T.rule_rhs = L.rhs8.p;
+      } else {
+        L.rhs32.grow(L.q + nb[r], L.q, s);
+        T.rule_rhs = L.rhs32.p;
+      }
+      T.h = g->H.lv[lr];
+      T.table = L.table.p;
+      T.mask = L.tcap - 1;
+      T.u0 = L.u;
+      T.level = lr;
+      T.q0 = L.q;
+      T.rule_off = L.off.p;
+      T.rule_fp = L.fp.p;
+      T.fprev = lr == 1 ? w.lut.p : g->levels[lr - 2].fp.p;
+      T.rec = w.tail.p + r;
+    }
+    HIP_CHECK(hipMemcpyAsync(w.tail_rounds.p, rounds.data(), sizeof(TailRound) * R,
+                             hipMemcpyHostToDevice, s));
+    TailArgs a{};
+    a.rounds = w.tail_rounds.p;
+    a.nrounds = R;
+    a.k = k;
+    a.n0 = n_i;
+    a.off0 = cur_off;
+    a.text = d_text;
+    a.first_bytes = first_bytes;
+    a.cur0 = cur;
+    a.key_bits = o.key_bits;
+    a.lut = w.lut.p;
+    a.bits = w.bits.p;
+    a.tile_cnt = w.tile_cnt.p;
+    a.tile_base = w.tile_base.p;
+    a.tile_seg = w.tile_seg.p;
+    a.pstart = w.pstart.p;
+    a.plen = w.plen.p;
+    a.key = w.key.p;
+    a.wkey = w.wkey.p;
+    a.slot_idx = w.slot_idx.p;
+    for (int x = 0; x < 2; ++x) {
+      a.sym[x] = w.sym[x].p;
+      a.fpv[x] = w.fpv[x].p;
+      a.off[x] = w.off[x].p;
+    }
+    a.newbits = w.newbits.p;
+    a.wcnt = w.wcnt.p;
+    a.wlen = w.wlen.p;
+    a.wcnt_base = w.wcnt_base.p;
+    a.wlen_base = w.wlen_base.p;
+    a.c_level = g->c_level.p + c_base;
+    a.c_sym = g->c_sym.p + c_base;
+    a.rounds_run = w.tail_run.p;
+    // a grid no larger than the device holds at once (the rounds synchronise
+    // it), and no larger than the first round's work needs
+    const unsigned grid = (unsigned)std::max<uint64_t>(
+        1, std::min<uint64_t>({(uint64_t)tail_grid(), 512ull, (db[0] + 255) / 256}));
+    launch_tail(a, grid, s);
+    std::vector<TailRec> rec(R);
+    uint32_t ran = 0;
+    HIP_CHECK(hipMemcpyAsync(rec.data(), w.tail.p, sizeof(TailRec) * R, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(&ran, w.tail_run.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    sync(s);  // also keeps `rounds` alive until its copy is done
+    if (ran == 0 || ran > R) throw LcgError{LCG_EHIP, "internal: fused tail ran no round"};
+    for (uint32_t j = 0; j < ran; ++j) {
+      const TailRec& t = rec[j];
+      if (t.ctr.overflow) throw LcgError{LCG_ETABLE, "dictionary overflow in a tail round"};
+      Level& L = g->levels[lv - 1 + j];
+      if ((uint64_t)L.u + t.u >= kNone) throw LcgError{LCG_EOVERFLOW, "level needs 2^32 ranks"};
+      L.u += (uint32_t)t.u;
+      L.q += t.q;
+      Stat row{};
+      row[0] = j ? rec[j - 1].fin.active_len : active_len;
+      row[1] = t.d;
+      row[2] = t.u;
+      row[3] = t.q;
+      row[4] = t.fin.active;
+      row[5] = t.ctr.probes;
+      row[6] = t.ctr.compares;
+      row[7] = L.tcap;
+      row[15] = 3;  // in one cooperative launch with the other tail rounds
+      g->stats.push_back(row);
+    }
+    const TailRec& last = rec[ran - 1];
+    // levels opened for rounds that did not run stay empty
+    while (g->levels.size() > levels_before && g->levels.size() > lv - 1 + ran &&
+           g->levels.back().u == 0)
+      g->levels.pop_back();
+    if (!last.fin.active) return;
+    // more rounds than prepared (not reached by Theorem 1's bound): go on
+    active_len = last.fin.active_len;
+    n_i = last.d;
+    cur ^= (int)(ran & 1);
+    cur_off = w.off[cur ^ 1].p;
+    lv += ran;
+    if (lv - lv_start > (uint32_t)HashFamily::kLevels)
+      throw LcgError{LCG_EOVERFLOW, "more than 63 rounds"};
+  }
+}
+
 // BuildGram of k strings into g (fresh or existing), the batched form, kept
 // as the state of a build between its rounds, so that several builds into
 // one grammar can advance in turns (the serving session) as well as one
@@ -630,7 +792,12 @@ struct Cohort {
           return;
         }
       }
-      tail_rounds(g, lv, n_i, active_len, d_text, cur_off, cur, k, c_base, o, w, s);
+      // one cooperative launch for all of them, unless each phase is timed
+      // (phase events need kernel boundaries) or the split form is asked for
+      if (o.flags & (LCG_FLAG_TIMING | LCG_FLAG_SPLIT_TAIL))
+        tail_rounds(g, lv, n_i, active_len, d_text, cur_off, cur, k, c_base, o, w, s);
+      else
+        fused_tail(g, lv, n_i, active_len, d_text, cur_off, cur, k, c_base, o, w, s);
       done = true;
       return;
     }

@@ -155,6 +155,7 @@ class Server:
         self.completed = []
         self.batch_sizes = []
         self.steps = 0
+        self.admitted_since_check = 0
 
     @property
     def g(self):
@@ -168,10 +169,14 @@ class Server:
         self.current = gen
 
     def _rotate_if_full(self):
-        """Start a new running grammar once a level of the current one is full;
-        retire drained old ones."""
+        """Before a batch is admitted: start a new running grammar if a level of
+        the current one is full (so the newest requests always sit in the
+        current one)."""
         if max((u for u, _ in self.current.g.level_sizes()), default=0) >= self.max_level_rules:
             self._new_generation()
+
+    def _retire_drained(self):
+        """Free the old running grammars whose batches have all finished."""
         for i in [i for i, gen in self.gens.items()
                   if gen is not self.current and gen.inflight == 0]:
             self.gens.pop(i).close()
@@ -218,6 +223,10 @@ class Server:
                 break
             batch.append(req)
             total += req.n
+        if self.admitted_since_check >= 8:
+            self._rotate_if_full()
+            self.admitted_since_check = 0
+        self.admitted_since_check += 1
         cur = torch.cuda.current_stream()
         for req in batch:
             cur.wait_event(req.event)
@@ -265,8 +274,8 @@ class Server:
                 req.done = now
                 self.completed.append(req)
             n += len(b.reqs)
-        if self.steps % 8 == 0 or finished:
-            self._rotate_if_full()
+        if finished:
+            self._retire_drained()
         # the ring is released in allocation order, as far as batches are finished
         while self.inflight and self.inflight[0].finished:
             b = self.inflight.popleft()

@@ -148,31 +148,61 @@ def test_autotuner_cache(L, tmp_path, monkeypatch):
 def test_timing_flags(L):
     """LCG_FLAG_TIMING_INSERT records the insert's device time in the rounds
     with host reads and nothing else; neither timing flag changes the grammar
-    or the counts; an unknown flag bit is refused."""
+    or the counts; the rounds queued without host reads run in one cooperative
+    launch (mode 3) unless every phase is timed or the split form is asked
+    for (mode 2); an unknown flag bit is refused."""
     text, off = D.make_config("tiny")
     t, o = L.to_device(text, off)
     kw = dict(seed=SEED, tail_log2=14)  # rounds above 2^14 symbols read their sizes back
     sp = L.build(t, o, **kw)
     si = L.build(t, o, flags=L.FLAG_TIMING_INSERT, **kw)
     sf = L.build(t, o, flags=L.FLAG_TIMING, **kw)
+    ss = L.build(t, o, flags=L.FLAG_SPLIT_TAIL, **kw)
     want = _oracle(text, off).export()
-    for g in (sp, si, sf):
+    for g in (sp, si, sf, ss):
         _assert_same(g.export(), want)
-    p, i, f = sp.stats(), si.stats(), sf.stats()
-    # n, d, u, Q, active strings, capacity and mode; the probe and comparison
-    # counts depend on which thread claims a slot first
-    det = [0, 1, 2, 3, 4, 7, 15]
-    for st in (i, f):
+    p, i, f, sp_ = sp.stats(), si.stats(), sf.stats(), ss.stats()
+    # n, d, u, Q, active strings and capacity; the probe and comparison counts
+    # depend on which thread claims a slot first
+    det = [0, 1, 2, 3, 4, 7]
+    for st in (i, f, sp_):
         assert np.array_equal(st[:, det], p[:, det])
-    assert (p[:, 8:15] == 0).all()
-    host = i[:, 15] != 2
+    host = p[:, 15] < 2
     assert host.any() and (~host).any()
+    for st in (p, i):
+        assert np.array_equal(st[:, 15], p[:, 15]) and (st[~host, 15] == 3).all()
+    for st in (f, sp_):
+        assert np.array_equal(st[host, 15], p[host, 15]) and (st[~host, 15] == 2).all()
+    assert (p[:, 8:15] == 0).all()
     assert (i[host, 11] > 0).all() and np.array_equal(i[host, 8], i[host, 11])
     assert (i[:, [9, 10, 12, 13, 14]] == 0).all() and (i[~host, 8:15] == 0).all()
     assert (f[:, 8] > 0).all() and np.array_equal(f[:, 8], f[:, 9:15].sum(axis=1))
     with pytest.raises(L.LcgError) as e:
-        L.build(t, o, flags=4, **kw)
+        L.build(t, o, flags=8, **kw)
     assert e.value.name == "LCG_EINVAL"
+
+
+@pytest.mark.parametrize("name,scale", [("tiny", 1.0), ("bacterial", 0.01), ("batched", 0.0005)])
+def test_fused_and_split_tail_agree(L, name, scale):
+    """The tail rounds in one cooperative launch and as separate kernels give
+    the same grammar rank for rank (and the oracle's), also for builds that
+    start in the tail (every round of these collections) and into a grammar
+    that already holds rules."""
+    text, off = D.make_config(name, scale=scale)
+    t, o = L.to_device(text, off)
+    want = _oracle(text, off).export()
+    fused = L.build(t, o, seed=SEED)
+    split = L.build(t, o, seed=SEED, flags=L.FLAG_SPLIT_TAIL)
+    _assert_same(fused.export(), want)
+    _assert_same(split.export(), want)
+    assert (fused.stats()[:, 15] == 3).all() and (split.stats()[:, 15] == 2).all()
+    k = len(off) - 1
+    h = k // 2
+    ta, oa = L.to_device(text[:off[h]], off[:h + 1])
+    tb, ob = L.to_device(text[off[h]:], (off[h:] - off[h]).astype(np.uint64))
+    g = L.build(ta, oa, seed=SEED)
+    L.build_into(g, tb, ob)
+    _assert_same(g.export(), want)
 
 def test_deterministic(L):
     text, off = D.make_config("tiny", scale=0.5)
