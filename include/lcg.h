@@ -67,10 +67,12 @@ enum {
                                   without host reads, see tail_log2); every other time field
                                   is 0.  Two events per such round instead of about nine per
                                   round: timing every phase slows a build by a few percent */
-  LCG_FLAG_SPLIT_TAIL = 4u     /* run the rounds queued without host reads (tail_log2) as
-                                  separate kernels per phase instead of one cooperative launch
-                                  for all of them (also the case with LCG_FLAG_TIMING).
-                                  Results do not depend on it. */
+  LCG_FLAG_FUSED_TAIL = 4u     /* run all rounds queued without host reads (tail_log2) in one
+                                  cooperative launch, their phases separated by grid-wide
+                                  barriers, instead of separate kernels per phase (ignored
+                                  with LCG_FLAG_TIMING).  Results do not depend on it; it is
+                                  slower on gfx950, where a grid-wide barrier must write back
+                                  and invalidate the L2 of every XCD */
 };
 
 typedef struct {
@@ -84,9 +86,8 @@ typedef struct {
   uint32_t table_min_log2; /* smallest dictionary capacity, log2 (6..34; 0 = 12) */
   uint32_t tail_log2;  /* rounds over at most 2^tail_log2 symbols are queued without reading
                           sizes back to the host (dictionaries are sized for the worst
-                          case): all of them in one cooperative launch whose phases are
-                          separated by grid-wide barriers, or, with LCG_FLAG_SPLIT_TAIL,
-                          as separate kernels that read their sizes from device memory;
+                          case): separate kernels that read their sizes from device
+                          memory, or, with LCG_FLAG_FUSED_TAIL, one cooperative launch;
                           1..40, 0 = 22.  Results do not depend on it. */
   uint32_t table_load_log2; /* dictionaries are sized for a load of at most 2^-table_load_log2
                                of their capacity; 1..3, 0 = 1.  Results do not depend on it. */

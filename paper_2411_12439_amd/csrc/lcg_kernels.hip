@@ -2459,10 +2459,10 @@ void launch_xs_expand(bool to_bytes, const uint32_t* sym, const uint64_t* pos, u
 // functions as the separate kernels.  After each round every block reads the
 // count of strings still active and the loop stops, uniformly, at zero.
 //
-// Blocks on different XCDs do not share an L2, so each barrier is wrapped in
-// agent-scope fences: the release makes a block's writes visible beyond its
-// L2, the acquire drops stale lines from its L1 and L2 before it reads what
-// other blocks wrote.
+// Blocks on different XCDs do not share an L2: the grid barrier's own
+// agent-scope fences (one thread per block, after a block barrier) write the
+// block's L2 back before it arrives and invalidate its caches after it
+// leaves, so that reads after the barrier see what other blocks wrote.
 union TailLds {
   ClassifyLds classify;
   EmitLds<true> emit_bytes;
@@ -2472,9 +2472,7 @@ union TailLds {
 };
 
 __device__ __forceinline__ void grid_barrier(cooperative_groups::grid_group& grid) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   grid.sync();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 template <bool BYTES>

@@ -56,7 +56,7 @@ static Opts read_opts(const lcg_opts* o) {
   if (o->combine_log2) r.combine_log2 = o->combine_log2;
   if (r.combine_log2 > 31) throw LcgError{LCG_EINVAL, "combine_log2 out of range"};
   r.fail_round = o->fail_round;
-  if (r.flags & ~(uint32_t)(LCG_FLAG_TIMING | LCG_FLAG_TIMING_INSERT | LCG_FLAG_SPLIT_TAIL))
+  if (r.flags & ~(uint32_t)(LCG_FLAG_TIMING | LCG_FLAG_TIMING_INSERT | LCG_FLAG_FUSED_TAIL))
     throw LcgError{LCG_EINVAL, "unknown flag"};
   if (r.mode != LCG_MODE_BATCHED && r.mode != LCG_MODE_PLAIN)
     throw LcgError{LCG_EINVAL, "unknown mode"};
@@ -542,7 +542,13 @@ static void fused_tail(lcg_grammar* g, uint32_t lv, uint64_t n_i, uint64_t activ
     if (lv >= (uint32_t)HashFamily::kLevels) throw LcgError{LCG_EOVERFLOW, "more than 63 rounds"};
     uint32_t bits = 0;
     while (bits < 63 && (1ull << bits) < n_i) ++bits;
-    const uint32_t R = std::min<uint32_t>((uint32_t)HashFamily::kLevels - lv, bits + 2);
+    uint32_t R = std::min<uint32_t>((uint32_t)HashFamily::kLevels - lv, bits + 2);
+    if (o.fail_round && o.fail_round >= lv && o.fail_round < lv + R) {
+      if (o.fail_round == lv)
+        throw LcgError{LCG_ETABLE, "test hook: failure forced at round " + std::to_string(lv) +
+                                       " (in one cooperative launch)"};
+      R = o.fail_round - lv;  // the rounds before it run; the loop then stops there
+    }
     const bool first_bytes = lv == 1;
     // bounds of every round: n_0 = n_i, d_r <= n_r / 2 + k + 1, n_{r+1} = d_r
     std::vector<uint64_t> nb(R), db(R);
@@ -792,12 +798,13 @@ struct Cohort {
           return;
         }
       }
-      // one cooperative launch for all of them, unless each phase is timed
-      // (phase events need kernel boundaries) or the split form is asked for
-      if (o.flags & (LCG_FLAG_TIMING | LCG_FLAG_SPLIT_TAIL))
-        tail_rounds(g, lv, n_i, active_len, d_text, cur_off, cur, k, c_base, o, w, s);
-      else
+      // separate kernels per phase, or all rounds in one cooperative launch
+      // when asked for (not with per-phase timing, whose events need kernel
+      // boundaries)
+      if ((o.flags & LCG_FLAG_FUSED_TAIL) && !(o.flags & LCG_FLAG_TIMING))
         fused_tail(g, lv, n_i, active_len, d_text, cur_off, cur, k, c_base, o, w, s);
+      else
+        tail_rounds(g, lv, n_i, active_len, d_text, cur_off, cur, k, c_base, o, w, s);
       done = true;
       return;
     }

@@ -21,7 +21,7 @@ MODE_BATCHED = 0
 MODE_PLAIN = 1
 FLAG_TIMING = 1
 FLAG_TIMING_INSERT = 2
-FLAG_SPLIT_TAIL = 4
+FLAG_FUSED_TAIL = 4
 
 _STATUS = {0: "LCG_OK", -1: "LCG_EINVAL", -2: "LCG_ENOMEM", -3: "LCG_ESEED",
            -4: "LCG_EOVERFLOW", -5: "LCG_ETABLE", -6: "LCG_EHIP"}

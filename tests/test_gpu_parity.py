@@ -149,15 +149,15 @@ def test_timing_flags(L):
     """LCG_FLAG_TIMING_INSERT records the insert's device time in the rounds
     with host reads and nothing else; neither timing flag changes the grammar
     or the counts; the rounds queued without host reads run in one cooperative
-    launch (mode 3) unless every phase is timed or the split form is asked
-    for (mode 2); an unknown flag bit is refused."""
+    launch (mode 3) when asked for and every phase is not timed, else as
+    separate kernels (mode 2); an unknown flag bit is refused."""
     text, off = D.make_config("tiny")
     t, o = L.to_device(text, off)
     kw = dict(seed=SEED, tail_log2=14)  # rounds above 2^14 symbols read their sizes back
     sp = L.build(t, o, **kw)
     si = L.build(t, o, flags=L.FLAG_TIMING_INSERT, **kw)
     sf = L.build(t, o, flags=L.FLAG_TIMING, **kw)
-    ss = L.build(t, o, flags=L.FLAG_SPLIT_TAIL, **kw)
+    ss = L.build(t, o, flags=L.FLAG_FUSED_TAIL, **kw)
     want = _oracle(text, off).export()
     for g in (sp, si, sf, ss):
         _assert_same(g.export(), want)
@@ -169,10 +169,9 @@ def test_timing_flags(L):
         assert np.array_equal(st[:, det], p[:, det])
     host = p[:, 15] < 2
     assert host.any() and (~host).any()
-    for st in (p, i):
-        assert np.array_equal(st[:, 15], p[:, 15]) and (st[~host, 15] == 3).all()
-    for st in (f, sp_):
-        assert np.array_equal(st[host, 15], p[host, 15]) and (st[~host, 15] == 2).all()
+    for st in (p, i, f):
+        assert np.array_equal(st[:, 15], p[:, 15]) and (st[~host, 15] == 2).all()
+    assert np.array_equal(sp_[host, 15], p[host, 15]) and (sp_[~host, 15] == 3).all()
     assert (p[:, 8:15] == 0).all()
     assert (i[host, 11] > 0).all() and np.array_equal(i[host, 8], i[host, 11])
     assert (i[:, [9, 10, 12, 13, 14]] == 0).all() and (i[~host, 8:15] == 0).all()
@@ -191,8 +190,8 @@ def test_fused_and_split_tail_agree(L, name, scale):
     text, off = D.make_config(name, scale=scale)
     t, o = L.to_device(text, off)
     want = _oracle(text, off).export()
-    fused = L.build(t, o, seed=SEED)
-    split = L.build(t, o, seed=SEED, flags=L.FLAG_SPLIT_TAIL)
+    fused = L.build(t, o, seed=SEED, flags=L.FLAG_FUSED_TAIL)
+    split = L.build(t, o, seed=SEED)
     _assert_same(fused.export(), want)
     _assert_same(split.export(), want)
     assert (fused.stats()[:, 15] == 3).all() and (split.stats()[:, 15] == 2).all()
@@ -200,8 +199,8 @@ def test_fused_and_split_tail_agree(L, name, scale):
     h = k // 2
     ta, oa = L.to_device(text[:off[h]], off[:h + 1])
     tb, ob = L.to_device(text[off[h]:], (off[h:] - off[h]).astype(np.uint64))
-    g = L.build(ta, oa, seed=SEED)
-    L.build_into(g, tb, ob)
+    g = L.build(ta, oa, seed=SEED, flags=L.FLAG_FUSED_TAIL)
+    L.build_into(g, tb, ob, flags=L.FLAG_FUSED_TAIL)
     _assert_same(g.export(), want)
 
 def test_deterministic(L):

@@ -39,9 +39,10 @@ def halves():
 
 
 # rounds reached with host reads (tail_log2 small) and queued without them
-@pytest.mark.parametrize("tail_log2,fail_round", [(8, 1), (8, 2), (8, 4), (8, 9), (22, 1),
-                                                  (22, 3), (22, 10)])
-def test_failed_build_into_restores_the_grammar(L, halves, tail_log2, fail_round):
+@pytest.mark.parametrize("tail_log2,fail_round,flags", [(8, 1, 0), (8, 2, 0), (8, 4, 0), (8, 9, 0),
+                                                        (22, 1, 0), (22, 3, 0), (22, 10, 0),
+                                                        (22, 3, 4), (8, 9, 4)])
+def test_failed_build_into_restores_the_grammar(L, halves, tail_log2, fail_round, flags):
     from oracle import oracle as O
     (ta, oa), (tb, ob), (text, off) = halves
     da, doa = L.to_device(ta, oa)
@@ -50,7 +51,7 @@ def test_failed_build_into_restores_the_grammar(L, halves, tail_log2, fail_round
     before = g.export()
     n_stats = len(g.stats())
     with pytest.raises(L.LcgError) as e:
-        L.build_into(g, db, dob, tail_log2=tail_log2, fail_round=fail_round)
+        L.build_into(g, db, dob, tail_log2=tail_log2, fail_round=fail_round, flags=flags)
     assert e.value.name == "LCG_ETABLE"
     after = g.export()
     assert CN.exports_equal(after, before), CN.first_difference(after, before)
