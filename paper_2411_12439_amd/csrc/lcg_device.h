@@ -17,8 +17,8 @@ constexpr uint64_t kHiMask = 0xFFFFFFFF00000000ULL;
 
 // One dictionary slot (32 bytes).  w0 is the claimed word:
 //   short phrase : exact key (bit 63 = 0), never equal to kEmpty;
-//   wide phrase  : kLongTag | kWideTag | qcode << 59 | h27 << 32 | ref, the
-//                  content in c0, c1 (see wide keys below);
+//   wide phrase  : kLongTag | kWideTag | qcode << 59 | bcode << 57 | h25 << 32
+//                  | ref, the content in c0, c1 (see wide keys below);
 //   long phrase  : kLongTag | h30 << 32 | ref, where h30 is 30 bits of the
 //                  phrase fingerprint;
 // ref is the phrase occurrence that claimed the slot while the round runs,

@@ -155,7 +155,6 @@ class Server:
         self.completed = []
         self.batch_sizes = []
         self.steps = 0
-        self.admitted_since_check = 0
 
     @property
     def g(self):
@@ -223,10 +222,7 @@ class Server:
                 break
             batch.append(req)
             total += req.n
-        if self.admitted_since_check >= 8:
-            self._rotate_if_full()
-            self.admitted_since_check = 0
-        self.admitted_since_check += 1
+        self._rotate_if_full()
         cur = torch.cuda.current_stream()
         for req in batch:
             cur.wait_event(req.event)

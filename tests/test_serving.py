@@ -126,9 +126,11 @@ def test_serving_rotates_full_running_grammars():
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     from paper_2411_12439_amd import serve
     src = D.ServingSource(scale=0.02, n_bases=4)
-    summary, srv, reqs = serve.run_load(src, load_gbps=5.0, seconds=30.0, max_requests=80,
-                                        ring_bytes=4 << 20, max_level_rules=3000)
-    assert summary["requests"] == 80 == len(srv.completed)
+    # a 2 MB ring (requests are at most 1 MB here) admits about 1-2 MB per
+    # batch, which fills a level past 3000 rules: about one batch per grammar
+    summary, srv, reqs = serve.run_load(src, load_gbps=5.0, seconds=30.0, max_requests=160,
+                                        ring_bytes=2 << 20, max_level_rules=3000)
+    assert summary["requests"] == 160 == len(srv.completed)
     assert summary["generations"] >= 3
     last = serve.checkable(srv, reqs)
     assert last and serve.check_alone_vs_mix(srv, src, reqs, last) == len(last)
