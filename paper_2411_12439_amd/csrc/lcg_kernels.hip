@@ -607,7 +607,6 @@ struct EmitStage<true> {
 template <>
 struct EmitStage<false> {
   uint32_t sym[kStage + 4];  // 4 spare words: fixed-length reads past the last phrase
-  uint32_t fp[kStage];
 };
 
 template <bool BYTES>
@@ -628,58 +627,95 @@ __device__ __forceinline__ void stage_tile(const RoundIn& in, uint64_t t0, EmitS
     }
   } else {
     const uint32_t* ss = static_cast<const uint32_t*>(in.sym) + t0;
-    const uint32_t* sf = in.fp + t0;
-    if (((reinterpret_cast<uintptr_t>(ss) | reinterpret_cast<uintptr_t>(sf)) & 15) == 0) {
+    if ((reinterpret_cast<uintptr_t>(ss) & 15) == 0) {
       for (uint32_t i = threadIdx.x * 4; i < kStage; i += kBlock * 4) {
         if (i + 4 <= lim) {
           *reinterpret_cast<uint4*>(&st.sym[i]) = *reinterpret_cast<const uint4*>(ss + i);
-          *reinterpret_cast<uint4*>(&st.fp[i]) = *reinterpret_cast<const uint4*>(sf + i);
         } else {
-          for (uint32_t x = i; x < i + 4 && x < lim; ++x) {
-            st.sym[x] = ss[x];
-            st.fp[x] = sf[x];
-          }
+          for (uint32_t x = i; x < i + 4 && x < lim; ++x) st.sym[x] = ss[x];
         }
       }
     } else {
-      for (uint32_t i = threadIdx.x; i < lim; i += kBlock) {
-        st.sym[i] = ss[i];
-        st.fp[i] = sf[i];
-      }
+      for (uint32_t i = threadIdx.x; i < lim; i += kBlock) st.sym[i] = ss[i];
     }
   }
 }
 
-// exact_key of a staged byte phrase (q <= 7 at tile offset p) from three
-// aligned LDS words instead of q byte reads: the same key.
-__device__ __forceinline__ bool exact_key_staged(const uint8_t* sym, uint32_t p, uint64_t q,
-                                                 uint64_t& k) {
-  if (q > 7) return false;
+// Kinds of key a phrase gets in the emit pass.
+constexpr int kKeyExact = 0;  // short exact key
+constexpr int kKeyWide = 1;   // wide exact key, content in c0, c1
+constexpr int kKeyLong = 2;   // fingerprint key (or a phrase left to the general path)
+
+// Content key of a staged phrase of q bytes at tile offset p (the same key as
+// exact_key / wide_content build from memory): the 16 bytes from p are read
+// as five aligned LDS words and byte-aligned, and the exact and wide cases
+// differ only in masks, so that the lanes of a wave stay together.  Phrases
+// longer than a wide key report kKeyLong.  Reads reach at most 19 bytes past
+// the word holding p, inside the staged window's spare bytes.
+__device__ __forceinline__ int staged_key(const uint8_t* sym, uint32_t p, uint64_t q, uint64_t& kk,
+                                          uint64_t& c0, uint64_t& c1, uint64_t& qc, uint64_t& bc) {
+  bc = 0;
+  if (q > kWideMaxBytes) return kKeyLong;
   const uint32_t* w = reinterpret_cast<const uint32_t*>(sym) + (p >> 2);
-  const uint64_t lo = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
-  const uint32_t sh = (p & 3u) * 8u;
-  uint64_t v = sh ? (lo >> sh) | ((uint64_t)w[2] << (64 - sh)) : lo;
-  k = (v & ((1ull << (8 * q)) - 1ull)) | (q << 56);
-  return true;
+  const uint32_t a0 = w[0], a1 = w[1], a2 = w[2], a3 = w[3], a4 = w[4];
+  const uint32_t sh = p & 3u;
+  const uint64_t lo = (uint64_t)__builtin_amdgcn_alignbyte(a1, a0, sh) |
+                      ((uint64_t)__builtin_amdgcn_alignbyte(a2, a1, sh) << 32);
+  const uint64_t hi = (uint64_t)__builtin_amdgcn_alignbyte(a3, a2, sh) |
+                      ((uint64_t)__builtin_amdgcn_alignbyte(a4, a3, sh) << 32);
+  const uint32_t qq = (uint32_t)q;
+  if (qq <= 7) {
+    kk = (lo & ((1ull << (8 * qq)) - 1ull)) | ((uint64_t)qq << 56);
+    return kKeyExact;
+  }
+  c0 = lo & 0x00FFFFFFFFFFFFFFull;
+  c1 = ((lo >> 56) | (hi << 8)) & ((1ull << (8 * (qq - 7))) - 1ull);
+  qc = qq - 8;
+  kk = wide_key(qc, 0, c0, c1);
+  return kKeyWide;
 }
 
-// exact_key of a staged phrase of ranks (q <= 4 at tile offset p): four
-// reads and a fold predicated on q instead of a loop of q steps; the same key.
-__device__ __forceinline__ bool exact_key_staged(const uint32_t* sym, uint32_t p, uint64_t q,
-                                                 uint64_t& k) {
-  if (q > 4) return false;
-  const int rb = rank_bits_for((uint32_t)q);
-  uint64_t kk = 0;
-  bool fits = true;
+// Content key of a staged phrase of q ranks at tile offset p: the ranks are
+// read once (predicated on q, so nothing past the staged window's spare words)
+// and give the exact key if they fit one, else the wide key, else kKeyLong.
+// The same keys as exact_key / wide_content.
+__device__ __forceinline__ int staged_key(const uint32_t* sym, uint32_t p, uint64_t q,
+                                          uint64_t& kk, uint64_t& c0, uint64_t& c1, uint64_t& qc,
+                                          uint64_t& bc) {
+  if (q > kWideMaxRanks) return kKeyLong;
+  uint32_t r[kWideMaxRanks];
+  uint32_t m = 0;
 #pragma unroll
-  for (uint32_t x = 0; x < 4; ++x) {
-    const uint64_t r = sym[p + x];
-    const bool take = x < q;
-    fits = fits && (!take || rb >= 32 || (r >> rb) == 0);
-    kk = take ? ((kk << rb) | r) : kk;
+  for (uint32_t x = 0; x < kWideMaxRanks; ++x) {
+    r[x] = x < q ? sym[p + x] : 0u;
+    m |= r[x];
   }
-  k = (q << 58) | kk;
-  return fits;
+  const uint32_t qq = (uint32_t)q;
+  const int rb = rank_bits_for(qq);
+  if (qq <= 4 && (rb >= 32 || (m >> rb) == 0)) {
+    uint64_t f = 0;
+#pragma unroll
+    for (uint32_t x = 0; x < 4; ++x) f = x < qq ? (f << rb) | r[x] : f;
+    kk = ((uint64_t)qq << 58) | f;
+    return kKeyExact;
+  }
+  const uint32_t b = m < (1u << 12) ? 0u : m < (1u << 16) ? 1u : m < (1u << 20) ? 2u
+                   : m < (1u << 31) ? 3u : 4u;
+  if (b == 4 || qq > 2 * wide_per_word(b)) return kKeyLong;
+  const uint32_t bits = wide_bits(b), per = wide_per_word(b);
+  c0 = 0;
+  c1 = 0;
+#pragma unroll
+  for (uint32_t x = 0; x < kWideMaxRanks; ++x) {
+    const bool second = x >= per;
+    const uint64_t v = x < qq ? (uint64_t)r[x] << (bits * (second ? x - per : x)) : 0;
+    if (second) c1 |= v;
+    else c0 |= v;
+  }
+  qc = qq - 1;
+  bc = b;
+  kk = wide_key(qc, bc, c0, c1);
+  return kKeyWide;
 }
 
 // End of the phrase starting at tile offset s_start[jj]: the next break in
@@ -706,15 +742,22 @@ __device__ __forceinline__ uint64_t phrase_end(uint32_t jj, uint32_t c, uint64_t
   return e > s_end ? s_end : e;
 }
 
+// The word a wide key's content enters the sketch as (a fold of both
+// content words and the codes; hll_add mixes it).
+__device__ __forceinline__ uint64_t wide_hll_word(uint64_t c0, uint64_t c1, uint64_t qc,
+                                                  uint64_t bc) {
+  return c0 ^ ((c1 << 29) | (c1 >> 35)) ^ (qc << 59) ^ (bc << 62) ^ 0x5bd1e9955bd1e995ULL;
+}
+
 // One key into the block's HyperLogLog registers (32-bit mix of the key:
-// enough for a sizing estimate).
+// enough for a sizing estimate; one 32x32+64-bit multiply-add folds the two
+// halves, one multiply and shifts mix the result).
 __device__ __forceinline__ void hll_add(uint32_t* s_hll, uint64_t kk) {
-  uint32_t h = (uint32_t)kk * 0x9E3779B1u ^ (uint32_t)(kk >> 32) * 0x85EBCA77u;
+  const uint64_t t = (uint64_t)(uint32_t)kk * 0x9E3779B1u + (kk >> 32);
+  uint32_t h = (uint32_t)(t >> 32) ^ (uint32_t)t;
   h ^= h >> 16;
   h *= 0x7FEB352Du;
   h ^= h >> 15;
-  h *= 0x846CA68Bu;
-  h ^= h >> 16;
   const uint32_t idx = h >> (32 - kHllLog2);
   const uint32_t rest = h << kHllLog2;
   const uint32_t rho = rest ? (uint32_t)__builtin_clz(rest) + 1 : 32 - kHllLog2 + 1;
@@ -722,26 +765,65 @@ __device__ __forceinline__ void hll_add(uint32_t* s_hll, uint64_t kk) {
 }
 
 // Eq. 4 of the phrase [l, e) by Horner's rule from the right:
-// P = a * sum_j F[Q_j] c^(j-1) + b (mod p); the staged part of the tile is
-// read from LDS, the rest from memory.
+// P = a * sum_j F[Q_j] c^(j-1) + b (mod p).  At level 1 the staged part of
+// the tile is read from LDS (F through the h^0 table), the rest from memory;
+// above it F is read from memory (only the long phrases need it, so the emit
+// pass does not stage it).
 template <bool BYTES>
 __device__ __forceinline__ uint64_t phrase_fp(const RoundIn& in, const uint32_t* s_lut,
                                               const EmitStage<BYTES>& st, uint64_t t0, uint64_t l,
                                               uint64_t e, LevelHash h) {
   uint64_t S = 0;
-  const uint64_t e_st = e < t0 + kStage ? e : t0 + kStage;  // staged part [l, e_st)
-  for (uint64_t p = e; p > e_st;) {
-    --p;
-    S = addmod61(mulmod61(S, h.c), fval<BYTES>(in, s_lut, p));
-  }
-  for (uint64_t p = e_st; p > l;) {
-    --p;
-    uint32_t f;
-    if constexpr (BYTES) f = s_lut[st.sym[p - t0]];
-    else f = st.fp[p - t0];
-    S = addmod61(mulmod61(S, h.c), f);
+  if constexpr (BYTES) {
+    const uint64_t e_st = e < t0 + kStage ? e : t0 + kStage;  // staged part [l, e_st)
+    for (uint64_t p = e; p > e_st;) {
+      --p;
+      S = addmod61(mulmod61(S, h.c), fval<BYTES>(in, s_lut, p));
+    }
+    for (uint64_t p = e_st; p > l;) {
+      --p;
+      S = addmod61(mulmod61(S, h.c), s_lut[st.sym[p - t0]]);
+    }
+  } else {
+    for (uint64_t p = e; p > l;) {
+      --p;
+      S = addmod61(mulmod61(S, h.c), in.fp[p]);
+    }
   }
   return addmod61(mulmod61(h.a, S), h.b);
+}
+
+// Key of the phrase [l, e) from memory, with its fingerprint when it needs
+// one (long phrases): the general path of the emit pass, for phrases not
+// keyed from the staged window.
+template <bool BYTES>
+__device__ __forceinline__ void emit_general(const RoundIn& in, const uint32_t* s_lut,
+                                             const EmitStage<BYTES>& st, uint64_t t0, uint64_t l,
+                                             uint64_t e, uint64_t o, LevelHash h,
+                                             uint32_t key_bits, uint64_t* __restrict__ pstart,
+                                             uint32_t* __restrict__ plen,
+                                             uint64_t* __restrict__ key,
+                                             uint64_t* __restrict__ wkey,
+                                             uint32_t* __restrict__ fnew, uint32_t* s_hll) {
+  const uint64_t q = e - l;
+  uint64_t kk, c0, c1, qc, bc;
+  if (key_bits == 0 && exact_key<BYTES>(in.sym, l, q, kk)) {
+    key[o] = kk;
+    hll_add(s_hll, kk);
+  } else if (key_bits == 0 && wide_content<BYTES>(in.sym, l, q, c0, c1, qc, bc)) {
+    key[o] = wide_key(qc, bc, c0, c1);
+    wkey[2 * o] = c0;
+    wkey[2 * o + 1] = c1;
+    hll_add(s_hll, wide_hll_word(c0, c1, qc, bc));
+  } else {
+    const uint64_t P = phrase_fp<BYTES>(in, s_lut, st, t0, l, e, h);
+    kk = long_key(P, key_bits);
+    pstart[o] = l;
+    plen[o] = (uint32_t)q;
+    fnew[o] = (uint32_t)(P & 0xFFFFFFFFULL);
+    key[o] = kk;
+    hll_add(s_hll, kk);
+  }
 }
 
 constexpr uint32_t kLongList = 2048;  // long phrases deferred per tile; more are done inline
@@ -811,52 +893,41 @@ __device__ __forceinline__ void emit_tiles(const RoundIn& in, uint64_t tiles, ui
     if (cached && shi != slo)
       for (uint32_t i = threadIdx.x; i < shi - slo + 2; i += kBlock) s_off[i] = in.off[slo + i];
     __syncthreads();
-    // Short phrases: their key is their content, taken from the staged tile.
-    // Their fingerprint is computed once per new rule when the rule is
-    // stored, not once per occurrence.  Long phrases (compared in full, keyed
-    // by their fingerprint) are listed and done in a second pass with full
-    // waves, instead of idling the lanes of every wave that holds one.
+    // Phrases that end inside the staged window and whose content fits an
+    // exact or wide key are keyed from the window (no fingerprint: it is
+    // computed once per new rule when the rule is stored).  The others (long
+    // phrases, keyed by their fingerprint and compared in full, and phrases
+    // running past the window) are listed and done in a second pass with full
+    // waves, instead of idling the lanes of every wave that holds one.  In a
+    // tile inside one string every phrase but the last ends at the next break
+    // of the tile.
+    const bool single = slo == shi;
     for (uint32_t jj = threadIdx.x; jj < c; jj += kBlock) {
-      const uint64_t l = t0 + s_start[jj];
-      const uint64_t e = phrase_end(jj, c, t0, s_start, slo, shi, cached, s_off, in.off, bits);
-      const uint64_t q = e - l;
+      const uint32_t p = s_start[jj];
+      const uint64_t l = t0 + p;
+      const uint64_t e = single && jj + 1 < c
+                             ? t0 + s_start[jj + 1]
+                             : phrase_end(jj, c, t0, s_start, slo, shi, cached, s_off, in.off, bits);
+      const uint64_t o = base + jj;
       uint64_t kk = 0, c0 = 0, c1 = 0, qc = 0, bc = 0;
-      bool exact = false, wide = false;
-      if (key_bits == 0) {
-        const bool staged = e <= t0 + kStage;
-        if (staged) {
-          exact = exact_key_staged(st.sym, (uint32_t)(l - t0), q, kk);
-        } else {
-          exact = exact_key<BYTES>(in.sym, l, q, kk);
+      const int kind = key_bits == 0 && e <= t0 + kStage
+                           ? staged_key(st.sym, p, e - l, kk, c0, c1, qc, bc)
+                           : kKeyLong;
+      if (kind != kKeyLong) {
+        key[o] = kk;
+        if (kind == kKeyWide) {
+          wkey[2 * o] = c0;
+          wkey[2 * o + 1] = c1;
+          kk = wide_hll_word(c0, c1, qc, bc);
         }
-        // too long for a short key: a wide key if its content fits two words
-        if (!exact)
-          wide = staged ? wide_content<BYTES>(st.sym, l - t0, q, c0, c1, qc, bc)
-                        : wide_content<BYTES>(in.sym, l, q, c0, c1, qc, bc);
-      }
-      if (exact) {
-        key[base + jj] = kk;
         hll_add(s_hll, kk);
-      } else if (wide) {
-        const uint64_t o = base + jj;
-        key[o] = wide_key(qc, bc, c0, c1);
-        wkey[2 * o] = c0;
-        wkey[2 * o + 1] = c1;
-        hll_add(s_hll, c0 ^ mix64(c1 + (qc << 60) + (bc << 56)));
       } else {
         const uint32_t slot = atomicAdd(&s_nlong, 1u);
-        if (slot < kLongList) {
+        if (slot < kLongList)
           s_long[slot] = (uint16_t)jj;
-        } else {
-          const uint64_t o = base + jj;
-          const uint64_t P = phrase_fp<BYTES>(in, s_lut, st, t0, l, e, h);
-          kk = long_key(P, key_bits);
-          pstart[o] = l;
-          plen[o] = (uint32_t)q;
-          fnew[o] = (uint32_t)(P & 0xFFFFFFFFULL);
-          key[o] = kk;
-          hll_add(s_hll, kk);
-        }
+        else
+          emit_general<BYTES>(in, s_lut, st, t0, l, e, o, h, key_bits, pstart, plen, key, wkey,
+                              fnew, s_hll);
       }
     }
     __syncthreads();
@@ -865,15 +936,8 @@ __device__ __forceinline__ void emit_tiles(const RoundIn& in, uint64_t tiles, ui
       const uint32_t jj = s_long[i];
       const uint64_t l = t0 + s_start[jj];
       const uint64_t e = phrase_end(jj, c, t0, s_start, slo, shi, cached, s_off, in.off, bits);
-      const uint64_t q = e - l;
-      const uint64_t o = base + jj;
-      const uint64_t P = phrase_fp<BYTES>(in, s_lut, st, t0, l, e, h);
-      const uint64_t kk = long_key(P, key_bits);
-      pstart[o] = l;
-      plen[o] = (uint32_t)q;
-      fnew[o] = (uint32_t)(P & 0xFFFFFFFFULL);
-      key[o] = kk;
-      hll_add(s_hll, kk);
+      emit_general<BYTES>(in, s_lut, st, t0, l, e, base + jj, h, key_bits, pstart, plen, key, wkey,
+                          fnew, s_hll);
     }
   }
   __syncthreads();
@@ -1163,7 +1227,12 @@ __device__ __forceinline__ void insert_phrases(uint64_t block, uint64_t blocks, 
     const uint64_t o = list ? (uint64_t)list[i] : i;
     const uint64_t kk = __builtin_nontemporal_load(&key[o]);  // streams past L1
     uint64_t pos = mix64(kk) & mask;
+    const uint64_t home = pos;
+    // the home slot's key word and (first occurrence, rank) together: most
+    // phrases end at their home slot, and then the second word needs no
+    // load of its own
     uint64_t w = hint_load(&table[pos].w0);
+    const uint64_t mr_home = hint_load(reinterpret_cast<const uint64_t*>(&table[pos].minocc));
     const bool tagged = (kk & kLongTag) != 0;  // wide or long: the slot word carries a reference
     const bool wide = is_wide(kk);
     const bool is_long = tagged && !wide;
@@ -1246,8 +1315,12 @@ __device__ __forceinline__ void insert_phrases(uint64_t block, uint64_t blocks, 
     } else {
       Slot* sl = &table[result];
       // (first occurrence, rank) in one load; a stale (larger) first
-      // occurrence only costs an unneeded atomicMin
-      const uint64_t mr = hint_load(reinterpret_cast<const uint64_t*>(&sl->minocc));
+      // occurrence only costs an unneeded atomicMin (first occurrences only
+      // decrease, and a slot's rank does not change within the pass).  The
+      // claimer registers its occurrence without a look.
+      const uint64_t mr = claimed ? (uint64_t)kNone << 32 | kNone
+                          : result == home ? mr_home
+                          : hint_load(reinterpret_cast<const uint64_t*>(&sl->minocc));
       if ((uint32_t)(mr >> 32) == kNone && (uint32_t)mr > (uint32_t)o)
         atomicMin(&sl->minocc, (uint32_t)o);
     }
