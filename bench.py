@@ -23,6 +23,11 @@ Prints one JSON line (see the keys below).  Extra fields:
                          untimed builds with every phase timed
   hbm_copy_gbps          read + write GB/s of a 1 GiB device-to-device copy: the
                          streaming ceiling measured on this GPU
+  gather_ceiling         random 8-byte reads per second at 32-byte strides of a
+                         4 GiB table (torch.take): the random-access ceiling the
+                         dictionary probe of rounds >= 2 runs against; the
+                         roofline object gives the insert's probes per second
+                         and their fraction of it
   cpu_baseline           the CPU oracle (single-threaded) on a bounded sample
   cpu_baseline_parallel  the same oracle on up to 16 host cores: disjoint runs of
                          strings built concurrently, then merged (MergeGrams)
@@ -122,6 +127,32 @@ def path_alg_bytes(st):
         s = 1.0 if i == 1 else 4.0
         tot += n * s + (n * 4.0 if i >= 2 else 0.0) + d * (4 + 8) + u * (8 + 4 + 4) + q * s
     return tot
+
+
+def gather_ceiling(table_log2=27, lookups=1 << 26, reps=5):
+    """Random 8-byte reads per second (in G) from a table of 2^table_log2
+    32-byte slots (4 GiB: the dictionary's slot size, and its capacity in the
+    second round of the 5 GB collection), one read per slot visited, indices
+    uniform: torch.take over a word view of the table."""
+    import torch
+    words = (1 << table_log2) * 4
+    table = torch.empty(words, dtype=torch.int64, device="cuda").fill_(7)
+    gen = torch.Generator(device="cuda").manual_seed(1)
+    idx = torch.randint(0, 1 << table_log2, (lookups,), device="cuda", generator=gen) * 4
+    torch.take(table, idx)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        torch.take(table, idx)
+    b.record()
+    torch.cuda.synchronize()
+    rate = lookups * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del table, idx
+    torch.cuda.empty_cache()
+    return {"lookups_per_s_g": round(rate, 2), "table_bytes": (1 << table_log2) * 32,
+            "slot_bytes": 32, "lookups": lookups,
+            "what": "torch.take of one 8-byte word per random 32-byte slot of a 4 GiB table"}
 
 
 def copy_ceiling(nbytes=1 << 30, reps=5):
@@ -407,6 +438,11 @@ def main():
            "tuned_options": tuned,
            "roofline": roofline}
     out["hbm_copy_gbps"] = copy_ceiling()
+    out["gather_ceiling"] = gather_ceiling()
+    probe_rate = float(sum(r[5] for r in rows)) / (ins_ns * 1e-9) / 1e9 if ins_ns else 0.0
+    roofline["probes_per_s_g"] = round(probe_rate, 2)
+    roofline["frac_of_gather_ceiling"] = round(
+        probe_rate / out["gather_ceiling"]["lookups_per_s_g"], 3)
 
     if not args.no_plain:
         ps = time_plain(lcg, t, o, seed, args.plain_steps)

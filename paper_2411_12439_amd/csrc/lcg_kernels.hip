@@ -1130,6 +1130,25 @@ void scan_one(const uint64_t* in, uint64_t* out, uint64_t count, const uint64_t*
 // ------------------------------------------------------------------ insert
 // Append the slots the active lanes won (mine != kNone) to the won list: one
 // atomic per wave, the lanes' entries in lane order.
+// Whether slot `sl`, whose key word reads w, holds the wide phrase with key
+// word kk and content (c0, c1).  A slot claimed in the running pass may not
+// show its content words here yet (the claimer writes them after its claim);
+// its key word then carries the claiming occurrence ref < d, whose content
+// words are read from the phrase arrays instead (a committed rule's content
+// was written by an earlier kernel).
+__device__ __forceinline__ bool wide_slot_match(const Slot* sl, uint64_t w, uint64_t kk,
+                                                uint64_t c0, uint64_t c1,
+                                                const uint64_t* __restrict__ wkey, uint64_t d) {
+  if ((w & kHiMask) != kk) return false;
+  uint64_t s0 = hint_load(&sl->c0), s1 = hint_load(&sl->c1);
+  if (s0 == kEmpty || s1 == kEmpty) {
+    const uint32_t ref = (uint32_t)w;
+    s0 = ref < d ? wkey[2 * (uint64_t)ref] : ~c0;
+    s1 = ref < d ? wkey[2 * (uint64_t)ref + 1] : ~c1;
+  }
+  return s0 == c0 && s1 == c1;
+}
+
 __device__ __forceinline__ void push_won(bool mine, uint32_t pos, uint32_t* won,
                                          unsigned int* won_len) {
   const uint64_t bal = __ballot(mine);
@@ -1219,13 +1238,26 @@ __device__ __forceinline__ void insert_phrases(uint64_t block, uint64_t blocks, 
   const uint64_t wave = block * (uint64_t)(blockDim.x / 64) + (threadIdx.x >> 6);
   uint32_t* const my_won = won_list ? won_list + wave * won_per_wave : nullptr;
   uint32_t nwon = 0;
+  // the next iteration's phrase index and key are loaded one iteration
+  // ahead, so that the key's load is not on the probe's dependency chain
+  uint64_t o_next = 0, kk_next = 0;
+  {
+    const uint64_t i = begin + wave * 64 + lane;
+    if (i < lim) {
+      o_next = list ? (uint64_t)list[i] : i;
+      kk_next = __builtin_nontemporal_load(&key[o_next]);  // streams past L1
+    }
+  }
   for (uint64_t wb = begin + wave * 64; wb < lim; wb += stride) {
     const uint64_t i = wb + lane;
     uint32_t result = kNone;
     bool claimed = false;
+    const uint64_t o = o_next, kk = kk_next;
+    if (i + stride < lim) {
+      o_next = list ? (uint64_t)list[i + stride] : i + stride;
+      kk_next = __builtin_nontemporal_load(&key[o_next]);
+    }
     if (i < lim) {
-    const uint64_t o = list ? (uint64_t)list[i] : i;
-    const uint64_t kk = __builtin_nontemporal_load(&key[o]);  // streams past L1
     uint64_t pos = mix64(kk) & mask;
     const uint64_t home = pos;
     // the home slot's key word and (first occurrence, rank) together: most
@@ -1272,18 +1304,7 @@ __device__ __forceinline__ void insert_phrases(uint64_t block, uint64_t blocks, 
         if (!tagged) {
           hit = w == kk;
         } else if (wide) {
-          if ((w & kHiMask) == kk) {
-            uint64_t c0 = hint_load(&sl->c0), c1 = hint_load(&sl->c1);
-            if (c0 == kEmpty || c1 == kEmpty) {
-              // not visible here yet: the claim is from this pass (a committed
-              // rule's content was written by an earlier kernel), so the
-              // claiming occurrence has the same content words
-              const uint32_t ref = (uint32_t)w;
-              c0 = ref < d ? wkey[2 * (uint64_t)ref] : ~my_c0;
-              c1 = ref < d ? wkey[2 * (uint64_t)ref + 1] : ~my_c1;
-            }
-            hit = c0 == my_c0 && c1 == my_c1;
-          }
+          hit = wide_slot_match(sl, w, kk, my_c0, my_c1, wkey, d);
         } else if ((w & kHiMask) == kk) {
           const uint32_t rk = hint_load(&sl->rank);
           const uint32_t ref = (uint32_t)w;
@@ -1385,17 +1406,22 @@ __global__ __launch_bounds__(256) void k_insert(uint64_t begin, uint64_t end, ui
 // global dictionary once and lowers the slot's first occurrence once; then
 // every phrase takes its slot from LDS.  Frequent keys thus cost one global
 // access per chunk instead of one per occurrence (which, for a handful of
-// keys, all land on the same few L2 lines).  Long keys and keys that find no
-// room in the LDS table are appended to `rest` for k_insert.
+// keys, all land on the same few L2 lines).  Wide keys (not combined: equal
+// key words need not mean equal content) are listed per chunk and probe the
+// global dictionary directly, in the chunk's order; long keys, and keys that
+// find no room in the LDS table or list, are appended to `rest` for k_insert.
 constexpr int kCombLog2 = 11;
 constexpr int kComb = 1 << kCombLog2;   // LDS dictionary entries
 constexpr int kCombChunk = 4096;        // phrases per block and iteration
 constexpr int kCombProbe = 32;          // LDS probe budget
 constexpr int kCombItems = kCombChunk / 256;
 constexpr uint16_t kCombNone = 0xFFFF;
+constexpr uint16_t kCombWide = 0xFFFE;  // s_loc mark: the phrase is on the wide list
+constexpr int kCombWideList = 512;      // wide phrases listed per chunk
 
-__global__ __launch_bounds__(256) void k_insert_comb(uint64_t begin, uint64_t end,
-                                                     const uint64_t* __restrict__ key, Slot* table,
+__global__ __launch_bounds__(256) void k_insert_comb(uint64_t begin, uint64_t end, uint64_t d,
+                                                     const uint64_t* __restrict__ key,
+                                                     const uint64_t* __restrict__ wkey, Slot* table,
                                                      uint64_t mask, uint32_t* __restrict__ slot_idx,
                                                      uint32_t* __restrict__ rest,
                                                      uint32_t* __restrict__ rest_len,
@@ -1405,8 +1431,9 @@ __global__ __launch_bounds__(256) void k_insert_comb(uint64_t begin, uint64_t en
   __shared__ uint32_t s_min[kComb];
   __shared__ uint32_t s_slot[kComb];
   __shared__ uint16_t s_loc[kCombChunk];
+  __shared__ uint16_t s_wide[kCombWideList];
   __shared__ unsigned long long s_sum[3];
-  __shared__ uint32_t s_nrest, s_rbase;
+  __shared__ uint32_t s_nrest, s_rbase, s_nwide;
   static_assert(kComb * sizeof(unsigned long long) >= kCombChunk * sizeof(uint32_t),
                 "the rest list reuses the key table");
   if (threadIdx.x < 3) s_sum[threadIdx.x] = 0;
@@ -1417,7 +1444,10 @@ __global__ __launch_bounds__(256) void k_insert_comb(uint64_t begin, uint64_t en
       s_key[i] = kEmpty;
       s_min[i] = kNone;
     }
-    if (threadIdx.x == 0) s_nrest = 0;
+    if (threadIdx.x == 0) {
+      s_nrest = 0;
+      s_nwide = 0;
+    }
     __syncthreads();
     // 1: the chunk's exact keys into the LDS dictionary (all keys loaded first,
     // so that their loads overlap)
@@ -1450,7 +1480,16 @@ __global__ __launch_bounds__(256) void k_insert_comb(uint64_t begin, uint64_t en
             if (hit) found = lpos;
             else lpos = (lpos + 1) & (kComb - 1);
           }
-          if (found != kNone) atomicMin(&s_min[found], (uint32_t)o);
+          // a frequent key's first occurrence is usually set already
+          if (found != kNone && (uint32_t)o < __hip_atomic_load(&s_min[found], __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_WORKGROUP))
+            atomicMin(&s_min[found], (uint32_t)o);
+        } else if (is_wide(kk)) {
+          const uint32_t at = atomicAdd(&s_nwide, 1u);
+          if (at < (uint32_t)kCombWideList) {
+            s_wide[at] = (uint16_t)li;
+            found = kCombWide;
+          }
         }
       }
       s_loc[li] = found == kNone ? kCombNone : (uint16_t)found;
@@ -1505,6 +1544,54 @@ __global__ __launch_bounds__(256) void k_insert_comb(uint64_t begin, uint64_t en
       s_slot[i] = res;
       push_won(claimed, res, won_list, &ctr->won_len);
     }
+    // 2b: the chunk's wide phrases, each straight into the global dictionary
+    // (the list's length is block-uniform, so every lane reaches push_won)
+    const uint32_t nwide = s_nwide < (uint32_t)kCombWideList ? s_nwide : (uint32_t)kCombWideList;
+    for (uint32_t b = 0; b < nwide; b += blockDim.x) {
+      const uint32_t i = b + threadIdx.x;
+      uint32_t res = kNone;
+      bool claimed = false;
+      if (i < nwide) {
+        const uint64_t o = c0 + s_wide[i];
+        const uint64_t kk = key[o];
+        const uint64_t my0 = wkey[2 * o], my1 = wkey[2 * o + 1];
+        uint64_t pos = mix64(kk) & mask;
+        for (uint32_t probe = 0; probe < kMaxProbe && res == kNone; ++probe) {
+          Slot* sl = &table[pos];
+          ++probes;
+          uint64_t w = hint_load(&sl->w0);
+          bool hit = false;
+          if (w == kEmpty) {
+            const unsigned long long prev =
+                atomicCAS(reinterpret_cast<unsigned long long*>(&sl->w0),
+                          (unsigned long long)kEmpty, (unsigned long long)(kk | o));
+            if (prev == kEmpty) {
+              hit = true;
+              claimed = true;
+              ++won;
+              __hip_atomic_store(&sl->c0, my0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              __hip_atomic_store(&sl->c1, my1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+              w = prev;
+            }
+          }
+          if (!hit) hit = wide_slot_match(sl, w, kk, my0, my1, wkey, d);
+          if (hit) res = (uint32_t)pos;
+          else pos = (pos + 1) & mask;
+        }
+        if (res == kNone) {
+          ++fails;
+        } else {
+          Slot* sl = &table[res];
+          const uint64_t mr = claimed ? (uint64_t)kNone << 32 | kNone
+                                      : hint_load(reinterpret_cast<const uint64_t*>(&sl->minocc));
+          if ((uint32_t)(mr >> 32) == kNone && (uint32_t)mr > (uint32_t)o)
+            atomicMin(&sl->minocc, (uint32_t)o);
+        }
+        slot_idx[o] = res;
+      }
+      push_won(claimed, res, won_list, &ctr->won_len);
+    }
     __syncthreads();
     // 3: slots of the combined phrases; the others join the rest list
     uint32_t* s_list = reinterpret_cast<uint32_t*>(s_key);
@@ -1513,8 +1600,8 @@ __global__ __launch_bounds__(256) void k_insert_comb(uint64_t begin, uint64_t en
       const uint64_t o = c0 + li;
       if (o < end) {
         const uint16_t lr = s_loc[li];
-        if (lr != kCombNone) slot_idx[o] = s_slot[lr];
-        else s_list[atomicAdd(&s_nrest, 1u)] = (uint32_t)o;
+        if (lr == kCombNone) s_list[atomicAdd(&s_nrest, 1u)] = (uint32_t)o;
+        else if (lr != kCombWide) slot_idx[o] = s_slot[lr];
       }
     }
     __syncthreads();
@@ -1574,8 +1661,8 @@ void launch_insert(bool bytes, uint64_t d, const uint64_t* d_dev, const uint64_t
          begin = end, end = end * 16 < d ? end * 16 : d) {
       unsigned gc = grid_for(end - begin, kCombChunk);
       if (gc > r) gc = r;
-      k_insert_comb<<<gc, 256, 0, s>>>(begin, end, key, table, mask, slot_idx, rest, rest_len, won2,
-                                       ctr);
+      k_insert_comb<<<gc, 256, 0, s>>>(begin, end, d, key, wkey, table, mask, slot_idx, rest,
+                                       rest_len, won2, ctr);
       LCG_LAUNCH_CHECK("insert_comb");
     }
     list = rest;  // at most d phrases; the count is on the device
