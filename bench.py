@@ -23,6 +23,10 @@ Prints one JSON line (see the keys below).  Extra fields:
                          untimed builds with every phase timed
   hbm_copy_gbps          read + write GB/s of a 1 GiB device-to-device copy: the
                          streaming ceiling measured on this GPU
+  path_traffic           the build's counted traffic per build (FETCH_SIZE + WRITE_SIZE,
+                         copy-calibrated, committed in profiles/) over the step time,
+                         against 8 TB/s and the copy ceiling; null once the kernels
+                         have changed since the counters were taken
   gather_ceiling         random 8-byte reads per second at 32-byte strides of a
                          4 GiB table (torch.take): the random-access ceiling the
                          dictionary probe of rounds >= 2 runs against; the
@@ -95,12 +99,10 @@ def source_digest():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def profile_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` from the committed PMC summary of the
-    workload, or None when there is none or the kernel source has changed
-    since its counters were taken."""
-    name = "%s_%s_traffic.txt" % ("".join(c if c.isalnum() else "_" for c in kernel).strip("_"),
-                                  workload)
+def profile_value(name, field):
+    """A number from a committed PMC summary (key: value lines) in profiles/,
+    or None when there is none or the kernel source has changed since its
+    counters were taken."""
     path = os.path.join(PROFILE_DIR, name)
     if not os.path.exists(path):
         return None
@@ -113,9 +115,17 @@ def profile_traffic(kernel, workload):
     if kv.get("kernel_source_sha256") != source_digest():
         return None
     try:
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv[field])
     except (KeyError, ValueError):
         return None
+
+
+def profile_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed PMC summary of the
+    workload (None as for profile_value)."""
+    name = "%s_%s_traffic.txt" % ("".join(c if c.isalnum() else "_" for c in kernel).strip("_"),
+                                  workload)
+    return profile_value(name, "traffic_bytes_per_launch")
 
 
 def path_alg_bytes(st):
@@ -335,6 +345,10 @@ def main():
                          "(the sustained rate is then the capacity)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (lcg_tune) and time the default options")
+    ap.add_argument("--options", default="", metavar="NAME=V,...",
+                    help="skip the autotuner and time these speed-only options (e.g. the "
+                         "ones a tuned run reported, so that a profiled run builds the same "
+                         "rounds the same way)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 3 times (calibrates rocprof "
                          "FETCH_SIZE / WRITE_SIZE against a copy of known size) and exit")
@@ -372,9 +386,17 @@ def main():
         args.config, k, n, time.perf_counter() - t_gen), file=sys.stderr, flush=True)
 
     # the autotuner picks the speed-only options for this workload (untimed)
-    tuned, tuned_ms = ({}, None) if args.no_tune else lcg.tune(t, o, seed=seed)
+    if args.options:
+        tuned = {k: int(v) for k, v in (kv.split("=") for kv in args.options.split(","))}
+        bad = set(tuned) - set(lcg.TUNABLE)
+        if bad:
+            raise SystemExit("--options: not a speed-only option: %s" % ", ".join(sorted(bad)))
+        tuned_ms = None
+    else:
+        tuned, tuned_ms = ({}, None) if args.no_tune else lcg.tune(t, o, seed=seed)
     if tuned:
-        print("[bench] tuned %s (%.2f ms)" % (tuned, tuned_ms), file=sys.stderr, flush=True)
+        print("[bench] options %s%s" % (tuned, "" if tuned_ms is None else " (tuned, %.2f ms)"
+                                        % tuned_ms), file=sys.stderr, flush=True)
     step_s, ins_ns_steps, stats, phase_ns, wall = time_builds(
         lcg, t, o, seed, args.steps, args.warmup, args.phase_builds, tuned)
     if args.rounds:
@@ -438,6 +460,15 @@ def main():
            "tuned_options": tuned,
            "roofline": roofline}
     out["hbm_copy_gbps"] = copy_ceiling()
+    # the build's counted traffic (committed counters of this workload) over
+    # the measured step time: how busy the memory system is kept, next to the
+    # algorithmic-byte model above
+    pb = profile_value("path_%s_traffic.txt" % args.config, "path_bytes_per_build")
+    out["path_traffic"] = None if pb is None else {
+        "bytes_per_build": int(pb), "gbps": round(pb / float(step_s.mean()) / 1e9, 1),
+        "frac_hbm": round(pb / float(step_s.mean()) / 1e9 / HBM_PEAK_GBPS, 4),
+        "frac_copy_ceiling": round(pb / float(step_s.mean()) / 1e9 / out["hbm_copy_gbps"], 4),
+        "source": "profiles/path_%s_traffic.txt" % args.config}
     out["gather_ceiling"] = gather_ceiling()
     probe_rate = float(sum(r[5] for r in rows)) / (ins_ns * 1e-9) / 1e9 if ins_ns else 0.0
     roofline["probes_per_s_g"] = round(probe_rate, 2)
