@@ -338,6 +338,9 @@ def main():
                          "post-processing, random access, LCE or streaming legs")
     ap.add_argument("--serving-seconds", type=float, default=20.0,
                     help="seconds per offered load of the serving leg (0 = skip)")
+    ap.add_argument("--serving-warmup", type=float, default=2.0,
+                    help="seconds of each offered load served before its measured window "
+                         "(left out of the latencies: a fresh server's first allocations)")
     ap.add_argument("--serving-requests", type=int, default=2000,
                     help="at least this many requests per offered load")
     ap.add_argument("--serving-loads", default="0.5,2,8,max",
@@ -804,7 +807,8 @@ def serving_and_cpu(args, out, text, off, seed):
         for x in args.serving_loads.split(","):
             load = None if x.strip() == "max" else float(x)
             summary, srv, reqs = serve.run_load(src, load, args.serving_seconds if load else 0.0,
-                                                min_requests=args.serving_requests)
+                                                min_requests=args.serving_requests,
+                                                warmup_s=args.serving_warmup)
             rng = np.random.default_rng(0)
             cand = serve.checkable(srv, reqs)
             sample = [cand[i] for i in rng.choice(len(cand), size=min(8, len(cand)),

@@ -190,6 +190,23 @@ lcg_status lcg_session_step(lcg_session_t s, hipStream_t stream, uint64_t* h_don
 void lcg_session_free(lcg_session_t s);
 
 /*
+ * Reserve dictionary room in g: rules (host, `levels` counts) gives, for
+ * each level i = 1..levels, the number of rules the level's dictionary H^i
+ * (Sec. 3.3, App. A.1) is to hold without growing; 0 leaves a level as it
+ * is.  A dictionary that grows rehashes every rule it holds, in whichever
+ * call crosses its capacity: for a running grammar fed batch after batch
+ * (lcg_build_into, sessions) that is a latency spike on one batch, which a
+ * reservation moves to the call that first creates the level (or to this
+ * call, for levels that already exist).  Room costs 64 device bytes per
+ * reserved rule (32-byte slots at load <= 1/2).  Results never depend on it.
+ * Errors: LCG_EINVAL (g NULL or unusable, rules NULL with levels > 0, more
+ * than 64 levels), LCG_ETABLE (more than 2^30 rules at a level), LCG_ENOMEM,
+ * LCG_EHIP.
+ */
+lcg_status lcg_reserve(lcg_grammar_t g, const uint64_t* rules, uint32_t levels,
+                       hipStream_t stream);
+
+/*
  * MergeGrams(G_a, G_b) (Sec. 3.5-3.6), in the rank encoding of App. A.1:
  * level by level, every rule of b (right-hand side renamed into a's ranks of
  * the level below) is looked up in a's dictionary of that level; a hit reuses

@@ -291,6 +291,9 @@ struct lcg_grammar {
   uint64_t explen_version = ~0ull;
   // set when a failed call could not restore the grammar: later calls refuse it
   bool poisoned = false;
+  // reserve[i]: the rules lcg_reserve made dictionary room for at level i+1
+  // (a level's dictionary is never sized below it)
+  std::vector<uint64_t> reserve;
   explicit lcg_grammar(uint64_t s) : seed(s), H(s) {}
 };
 

@@ -232,6 +232,16 @@ static void ensure_table(Level& L, uint64_t need, const Opts& o, Work& w, hipStr
   L.tcap = want;
 }
 
+// lcg_reserve's bounds: levels it takes, rules per level (2^30 at load 1/2
+// fills the largest dictionary, 2^31 slots).
+constexpr uint32_t kMaxReserveLevels = 64;
+constexpr uint64_t kMaxReserveRules = 1ull << 30;
+
+// The rules lcg_reserve made room for at level lv (1-based), else 0.
+static uint64_t reserved(const lcg_grammar* g, uint32_t lv) {
+  return lv - 1 < g->reserve.size() ? g->reserve[lv - 1] : 0;
+}
+
 // Levels up to i exist; a level created here gets room for off_cap offsets
 // if it is level i (a caller that knows the level's size saves the copy of
 // the first offset when the array is grown to it), else for one.
@@ -276,7 +286,7 @@ static DedupResult dedup_commit(lcg_grammar* g, uint32_t lv, uint64_t d, const v
                                 PhaseEvents* pe = nullptr) {
   Level& L = g->levels[lv - 1];
   const bool bytes = lv == 1;
-  ensure_table(L, (uint64_t)L.u + est_new, o, w, s);
+  ensure_table(L, std::max<uint64_t>((uint64_t)L.u + est_new, reserved(g, lv)), o, w, s);
   const uint64_t W = (d + 63) / 64;
   // few distinct keys for many phrases: combine equal keys per chunk first
   const bool combine = o.combine_log2 < 31 && (est_new << o.combine_log2) <= d;
@@ -428,7 +438,7 @@ static void tail_rounds(lcg_grammar* g, uint32_t lv, uint64_t n_i, uint64_t acti
     w.wlen_base.need(W_b + 1, s);
     ensure_level(g, lv, s, d_b + 1);
     Level& L = g->levels[lv - 1];
-    ensure_table(L, (uint64_t)L.u + d_b, o, w, s);
+    ensure_table(L, std::max<uint64_t>((uint64_t)L.u + d_b, reserved(g, lv)), o, w, s);
     if ((uint64_t)L.u + d_b >= kNone) throw LcgError{LCG_EOVERFLOW, "level needs 2^32 ranks"};
     L.off.grow(L.u + d_b + 1, L.u + 1, s);
     L.fp.grow(L.u + d_b, L.u, s);
@@ -597,7 +607,7 @@ static void fused_tail(lcg_grammar* g, uint32_t lv, uint64_t n_i, uint64_t activ
       const uint32_t lr = lv + r;
       ensure_level(g, lr, s, db[r] + 1);
       Level& L = g->levels[lr - 1];
-      ensure_table(L, (uint64_t)L.u + db[r], o, w, s);
+      ensure_table(L, std::max<uint64_t>((uint64_t)L.u + db[r], reserved(g, lr)), o, w, s);
       if ((uint64_t)L.u + db[r] >= kNone) throw LcgError{LCG_EOVERFLOW, "level needs 2^32 ranks"};
       L.off.grow(L.u + db[r] + 1, L.u + 1, s);
       L.fp.grow(L.u + db[r], L.u, s);
@@ -1502,6 +1512,28 @@ lcg_status lcg_build_into(lcg_grammar_t g, const uint8_t* d_text, const uint64_t
     uint32_t first = g->k;
     restoring(g, stream, [&] { build_any(g, d_text, d_offsets, k, oo, stream); });
     if (first_index) *first_index = first;
+  });
+}
+
+lcg_status lcg_reserve(lcg_grammar_t g, const uint64_t* rules, uint32_t levels,
+                       hipStream_t stream) {
+  return guard([&] {
+    live(g);
+    if (levels && !rules) throw LcgError{LCG_EINVAL, "rules is NULL"};
+    if (levels > kMaxReserveLevels) throw LcgError{LCG_EINVAL, "too many levels"};
+    for (uint32_t i = 0; i < levels; ++i)
+      if (rules[i] > kMaxReserveRules)
+        throw LcgError{LCG_ETABLE, "reservation beyond the dictionary capacity limit"};
+    if (g->reserve.size() < levels) g->reserve.resize(levels, 0);
+    Opts o;  // reserved room is sized at the default load
+    Work w;
+    w.ctr.need(1, stream);
+    for (uint32_t i = 0; i < levels; ++i) {
+      g->reserve[i] = rules[i];
+      // an existing level grows (and rehashes) now rather than in a later build
+      if (i < g->levels.size() && rules[i]) ensure_table(g->levels[i], rules[i], o, w, stream);
+    }
+    sync(stream);
   });
 }
 

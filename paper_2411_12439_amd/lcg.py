@@ -27,7 +27,8 @@ _STATUS = {0: "LCG_OK", -1: "LCG_EINVAL", -2: "LCG_ENOMEM", -3: "LCG_ESEED",
            -4: "LCG_EOVERFLOW", -5: "LCG_ETABLE", -6: "LCG_EHIP"}
 
 # Every symbol include/lcg.h declares (checked by the CPU test suite).
-EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_expand",
+EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_reserve",
+           "lcg_expand",
            "lcg_expand_strings", "lcg_expand_strings_noalloc", "lcg_tune", "lcg_new",
            "lcg_info", "lcg_level_size", "lcg_level_copy", "lcg_c_copy", "lcg_stats",
            "lcg_stats_clear", "lcg_build_bytes", "lcg_free", "lcg_release_pool", "lcg_last_error",
@@ -106,6 +107,8 @@ def lib():
     L.lcg_build_into.restype = st
     L.lcg_merge.argtypes = [vp, vp, vp]
     L.lcg_merge.restype = st
+    L.lcg_reserve.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint32, vp]
+    L.lcg_reserve.restype = st
     L.lcg_expand.argtypes = [vp, ctypes.c_uint32, vp, ctypes.c_uint64, u64p, vp]
     L.lcg_expand.restype = st
     L.lcg_expand_strings.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, vp, ctypes.c_uint64, vp,
@@ -306,6 +309,13 @@ class Grammar:
 
     def clear_stats(self):
         _check(lib().lcg_stats_clear(self.h))
+
+    def reserve(self, rules, stream=None):
+        """lcg_reserve: dictionary room for rules[i] rules at level i+1 (0: leave
+        the level as it is)."""
+        arr = (ctypes.c_uint64 * max(len(rules), 1))(*[int(x) for x in rules])
+        _check(lib().lcg_reserve(self.h, arr, len(rules), _stream(stream)))
+        return self
 
     def merge(self, other, stream=None):
         """MergeGrams(self, other): self absorbs other (other unchanged)."""

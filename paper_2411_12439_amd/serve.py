@@ -119,9 +119,11 @@ class Batch:
 class Generation:
     """One running grammar, its serving session and its batches in flight."""
 
-    def __init__(self, index, seed, hbm_budget):
+    def __init__(self, index, seed, hbm_budget, reserve=()):
         self.index = index
         self.g = _lcg.new(seed)
+        if reserve:
+            self.g.reserve(reserve)
         self.session = _lcg.Session(self.g, hbm_budget=hbm_budget)
         self.inflight = 0
 
@@ -134,13 +136,21 @@ class Server:
     """Continuous-batching compressor around one device-resident running grammar."""
 
     def __init__(self, source, seed=_datagen.HASH_SEED, hbm_budget=16 << 30, ring_bytes=1 << 30,
-                 max_batches=32, max_level_rules=1 << 27, device="cuda"):
+                 max_batches=32, max_level_rules=1 << 27, reserve_levels=None, device="cuda"):
         import torch
         self.torch = torch
         self.source = source
         self.seed = seed
         self.budget = int(hbm_budget)
         self.max_level_rules = int(max_level_rules)
+        # with reserve_levels = (lo, hi), levels lo..hi of every running
+        # grammar get dictionary room for max_level_rules rules when it
+        # starts, instead of doubling (and rehashing) their dictionaries as
+        # they grow, each time on some batch's clock; measured, the room's
+        # fill on the first batch of each grammar cost more than the
+        # doublings it saves, so it is off by default
+        lo, hi = reserve_levels if reserve_levels else (1, 0)
+        self.reserve = [self.max_level_rules if lo <= i + 1 <= hi else 0 for i in range(hi)]
         self.gens = {}                       # live generations by index
         self.current = None
         self.generations = 0
@@ -162,7 +172,7 @@ class Server:
         return self.current.g
 
     def _new_generation(self):
-        gen = Generation(self.generations, self.seed, self.budget)
+        gen = Generation(self.generations, self.seed, self.budget, self.reserve)
         self.generations += 1
         self.gens[gen.index] = gen
         self.current = gen
@@ -291,35 +301,47 @@ class Server:
 
 def run_load(source, load_gbps, seconds, max_requests=None, min_requests=0,
              seed=_datagen.HASH_SEED, hbm_budget=16 << 30, ring_bytes=1 << 30,
-             max_level_rules=1 << 27):
+             max_level_rules=1 << 27, reserve_levels=None, warmup_s=0.0):
     """Serve a Poisson stream offering `load_gbps` GB/s (None: every request is
     there from the start, which measures the capacity) for `seconds`, or until
-    max_requests have arrived; at least min_requests arrive.
+    max_requests have arrived; at least min_requests arrive.  With warmup_s
+    (offered loads only) the stream starts that long before the measured
+    window: those requests are served alike but left out of the summary, so
+    that it shows the steady state rather than the first allocations and
+    dictionary growth of a fresh server.
 
     Returns (summary, server, requests); requests[i] = (Request, descriptor).
     """
     import torch
-    srv = Server(source, seed, hbm_budget, ring_bytes, max_level_rules=max_level_rules)
+    srv = Server(source, seed, hbm_budget, ring_bytes, max_level_rules=max_level_rules,
+                 reserve_levels=reserve_levels)
     saturate = load_gbps is None
     gaps = None if saturate else source.arrivals(load_gbps * 1e9, 1 << 16)
     reqs = []
     t0 = time.perf_counter()
+    warm = 0.0 if saturate else float(warmup_s)
+    t_meas = t0 + warm                   # requests arriving from here on are measured
     nxt = t0 if saturate else t0 + gaps[0]
     i = 0
+    i_meas = 0
+
+    def still_open(now):
+        return (now - t0 < warm + seconds or i_meas < min_requests) and \
+            (max_requests is None or i_meas < max_requests)
+
     while True:
         now = time.perf_counter()
-        open_ = (now - t0 < seconds or i < min_requests) and \
-            (max_requests is None or i < max_requests)
+        open_ = still_open(now)
         while open_ and nxt <= now:
             desc = source.draw()
             r = Request(i, desc, time.perf_counter() if saturate else nxt)
             srv.submit(r)
             reqs.append((r, desc))
             i += 1
+            i_meas += r.arrival >= t_meas
             if not saturate:
                 nxt += gaps[i % len(gaps)]
-            open_ = (max_requests is None or i < max_requests) and \
-                (now - t0 < seconds or i < min_requests)
+            open_ = still_open(now)
             if saturate and len(srv.waiting) > 64:
                 break
         if srv.inflight or srv.ready:
@@ -333,15 +355,18 @@ def run_load(source, load_gbps, seconds, max_requests=None, min_requests=0,
         time.sleep(max(0.0, min(nxt - time.perf_counter(), 0.0005)))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    done = [r for r, _ in reqs]
+    done = [r for r, _ in reqs if r.arrival >= t_meas]
     lat = np.array([(r.done - r.arrival) * 1e3 for r in done]) if done else np.zeros(1)
     nbytes = sum(r.n for r in done)
     start = min((r.arrival for r in done), default=t0)
+    # completion of the last measured request ends the window
+    end = max((r.done for r in done), default=t1)
     summary = {
         "offered_gbps": "saturated" if saturate else load_gbps,
         "requests": len(done),
+        "warmup_requests": len(reqs) - len(done),
         "bytes": int(nbytes),
-        "sustained_gbps": round(nbytes / max(t1 - start, 1e-9) / 1e9, 4),
+        "sustained_gbps": round(nbytes / max(end - start, 1e-9) / 1e9, 4),
         "p50_ms": round(float(np.percentile(lat, 50)), 3),
         "p99_ms": round(float(np.percentile(lat, 99)), 3),
         "steps": srv.steps,

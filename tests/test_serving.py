@@ -66,6 +66,25 @@ def test_serving_completes_every_request(served):
 
 
 @pytest.mark.gpu
+def test_serving_warmup_is_served_but_not_measured():
+    """Requests of the warm-up window are compressed like the others (every one
+    completes and is in the running grammar) and only the later ones enter the
+    summary."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2411_12439_amd import serve
+    src = D.ServingSource(scale=0.02, n_bases=4)
+    # about 80 requests per second: some 25 in each window
+    summary, srv, reqs = serve.run_load(src, load_gbps=0.005, seconds=0.3, warmup_s=0.3,
+                                        min_requests=10, max_requests=40)
+    assert summary["warmup_requests"] > 0 and 10 <= summary["requests"] <= 40
+    assert summary["requests"] + summary["warmup_requests"] == len(reqs) == len(srv.completed)
+    assert sorted(r.c_index for r, _ in reqs) == list(range(len(reqs)))
+    assert serve.check_alone_vs_mix(srv, src, reqs, range(len(reqs))) == len(reqs)
+    srv.close()
+
+
+@pytest.mark.gpu
 def test_serving_alone_equals_in_the_mix(served):
     """Def. 1: each request's rules inside the running grammar == the request built alone."""
     serve, src, summary, srv, reqs = served
