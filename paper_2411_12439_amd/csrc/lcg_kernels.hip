@@ -426,6 +426,45 @@ __device__ __forceinline__ void tile_store(const TileRegs<BYTES>& r, const uint3
   }
 }
 
+// For the 16 positions b .. b+15 of a thread's window when b-1 .. b+16 lie
+// inside one string ending at s_end and hold no string start: bit x set iff
+// the first position r > b+x with F[r] != F[b+x] exists in the string and has
+// F[r] > F[b+x].  S(x) = G(x) | (E(x) & S(x+1)) with G = change to a larger
+// value and E = equal neighbour is a carry chain running from high x to low
+// x, i.e. the carries of an addition on the bit-reversed masks; positions
+// whose equal run reaches past the window take the value found by walking
+// the run (LDS, then memory), fl being its value.  Only positions in `desc`
+// (F[l-1] > F[l]) use it, so the walk is skipped when none of them needs it.
+template <bool BYTES>
+__device__ __forceinline__ uint32_t window_first_change(uint32_t desc, uint32_t eq, uint32_t gt,
+                                                        uint32_t fl, uint64_t b, uint64_t t0,
+                                                        uint64_t s_end, const RoundIn& in,
+                                                        const uint32_t* s_lut, const uint32_t* s_f) {
+  const uint32_t full = (1u << kItems) - 1u;
+  const uint32_t ne = ~eq & full;
+  const uint32_t G = ne & gt;
+  const uint32_t gr = __builtin_bitreverse32(G) >> (32 - kItems);
+  const uint32_t pr = __builtin_bitreverse32(eq & full) >> (32 - kItems);
+  const uint32_t A = gr | pr, B = gr;
+  const uint32_t carries = ((A + B) ^ A ^ B) >> 1;  // carry out of reversed bit i
+  uint32_t S = __builtin_bitreverse32(carries & full) >> (32 - kItems);
+  // positions whose equal run reaches the end of the window
+  const uint32_t tail = ne ? ~((2u << (31 - __builtin_clz(ne))) - 1u) & full : full;
+  if (desc & tail) {
+    uint64_t r = b + kItems + 1;
+    uint32_t fr = 0;
+    bool more = true;
+    while (more && r < s_end) {
+      const uint64_t i = r - t0 + 1;
+      fr = i < (uint64_t)kCStage ? s_f[cpad((uint32_t)i)] : fval<BYTES>(in, s_lut, r);
+      more = fr == fl;
+      r += more ? 1 : 0;
+    }
+    if (r < s_end && fr > fl) S |= tail;
+  }
+  return S;
+}
+
 // One tile per block.  The tile's input, its entry of the tile map and the
 // h^0 table are all requested before the first barrier, so the block waits
 // for memory once; the map brings the offsets of the tile's first string.
@@ -461,7 +500,29 @@ __device__ __forceinline__ void classify_tile(const RoundIn& in, uint64_t tile,
   __syncthreads();
   tile_store<BYTES>(regs, s_lut, s_f);
   __syncthreads();
-  {
+  // A tile whose windows (one position to the left, one past the tile to the
+  // right) lie inside one string takes the branch-free path in every thread:
+  // a block-uniform test, so the block runs that path alone, without the
+  // per-thread string checks and their branches.
+  const bool interior = ts.lo == ts.hi && ts.start < t0 && t0 + kTile < ts.end;
+  if (interior) {
+    const uint64_t b = t0 + (uint64_t)threadIdx.x * kItems;
+    uint32_t fw[kItems + 2];
+#pragma unroll
+    for (int x = 0; x < kItems + 2; ++x) fw[x] = s_f[cpad(threadIdx.x * kItems + x)];  // position b - 1 + x
+    uint32_t desc = 0, eq = 0, gt = 0;
+#pragma unroll
+    for (int x = 0; x < kItems; ++x) {
+      desc |= (uint32_t)(fw[x] > fw[x + 1]) << x;
+      eq |= (uint32_t)(fw[x + 1] == fw[x + 2]) << x;
+      gt |= (uint32_t)(fw[x + 2] > fw[x + 1]) << x;
+    }
+    const uint32_t mask = desc & window_first_change<BYTES>(desc, eq, gt, fw[kItems + 1], b, t0,
+                                                            ts.end, in, s_lut, s_f);
+    s_mask[threadIdx.x] = mask;
+    const uint32_t c = (uint32_t)wave_sum((unsigned long long)__builtin_popcount(mask));
+    if ((threadIdx.x & 63) == 0) atomicAdd(&s_cnt, c);
+  } else {
     const uint64_t b = t0 + (uint64_t)threadIdx.x * kItems;
     uint32_t mask = 0;
     if (b < in.n) {
@@ -484,38 +545,8 @@ __device__ __forceinline__ void classify_tile(const RoundIn& in, uint64_t tile,
       }
       const int xe = in.n - b < (uint64_t)kItems ? (int)(in.n - b) : kItems;
       if (s_start < b && b + kItems < s_end) {
-        // The window b-1 .. b+16 lies inside one string and holds no string
-        // start: all 16 positions at once.  S(x), the direction of the first
-        // change at or after x (F[r] > F[l] at the first r > l with F[r] !=
-        // F[l]), obeys S(x) = G(x) | (E(x) & S(x+1)) with G = change to a
-        // larger value, E = equal neighbour: a carry chain running from high
-        // x to low x, i.e. the carries of an addition on the bit-reversed
-        // masks.  The run reaching past the window takes the value found by
-        // walking it.
-        const uint32_t full = (1u << kItems) - 1u;
-        const uint32_t ne = ~eq & full;
-        const uint32_t G = ne & gt;
-        const uint32_t gr = __builtin_bitreverse32(G) >> (32 - kItems);
-        const uint32_t pr = __builtin_bitreverse32(eq & full) >> (32 - kItems);
-        const uint32_t A = gr | pr, B = gr;
-        const uint32_t carries = ((A + B) ^ A ^ B) >> 1;  // carry out of reversed bit i
-        uint32_t S = __builtin_bitreverse32(carries & full) >> (32 - kItems);
-        // positions whose equal run reaches the end of the window
-        const uint32_t tail = ne ? ~((2u << (31 - __builtin_clz(ne))) - 1u) & full : full;
-        if (desc & tail) {
-          const uint32_t fl = fw[kItems + 1];
-          uint64_t r = b + kItems + 1;
-          uint32_t fr = 0;
-          bool more = true;
-          while (more && r < s_end) {
-            const uint64_t i = r - t0 + 1;
-            fr = i < (uint64_t)kCStage ? s_f[cpad((uint32_t)i)] : fval<BYTES>(in, s_lut, r);
-            more = fr == fl;
-            r += more ? 1 : 0;
-          }
-          if (r < s_end && fr > fl) S |= tail;
-        }
-        mask = desc & S;
+        mask = desc & window_first_change<BYTES>(desc, eq, gt, fw[kItems + 1], b, t0, s_end, in,
+                                                 s_lut, s_f);
       } else {
       for (int x = 0; x < xe; ++x) {
         const uint64_t l = b + x;
@@ -1128,8 +1159,6 @@ void scan_one(const uint64_t* in, uint64_t* out, uint64_t count, const uint64_t*
 }
 
 // ------------------------------------------------------------------ insert
-// Append the slots the active lanes won (mine != kNone) to the won list: one
-// atomic per wave, the lanes' entries in lane order.
 // Whether slot `sl`, whose key word reads w, holds the wide phrase with key
 // word kk and content (c0, c1).  A slot claimed in the running pass may not
 // show its content words here yet (the claimer writes them after its claim);
@@ -1149,6 +1178,8 @@ __device__ __forceinline__ bool wide_slot_match(const Slot* sl, uint64_t w, uint
   return s0 == c0 && s1 == c1;
 }
 
+// Append the slots the active lanes won (mine != kNone) to the won list: one
+// atomic per wave, the lanes' entries in lane order.
 __device__ __forceinline__ void push_won(bool mine, uint32_t pos, uint32_t* won,
                                          unsigned int* won_len) {
   const uint64_t bal = __ballot(mine);
