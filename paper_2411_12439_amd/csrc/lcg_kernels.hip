@@ -1886,11 +1886,12 @@ __device__ __forceinline__ void commit_one(uint64_t o, uint32_t r, uint64_t q, u
                                            const uint64_t* __restrict__ wkey,
                                            const uint64_t* __restrict__ pstart,
                                            const Sym* __restrict__ content,
-                                           const uint32_t* __restrict__ fnew,
+                                           const uint32_t* fnew,
                                            const uint32_t* __restrict__ fprev, LevelHash h,
                                            uint64_t* __restrict__ rule_off,
                                            Sym* __restrict__ rule_rhs,
-                                           uint32_t* __restrict__ rule_fp) {
+                                           uint32_t* __restrict__ rule_fp, uint32_t* sym_next,
+                                           uint32_t* fnext) {
   constexpr bool kBytes = sizeof(Sym) == 1;
   uint32_t F;
   if (is_wide(kk)) {
@@ -1949,6 +1950,12 @@ __device__ __forceinline__ void commit_one(uint64_t o, uint32_t r, uint64_t q, u
   *reinterpret_cast<uint64_t*>(&sl->minocc) = (uint64_t)F | ((uint64_t)r << 32);
   // a long key's slot word switches from the claiming occurrence to the rank
   if (kk & kLongTag) sl->w0 = (kk & kHiMask) | r;
+  // the new phrase's own symbol and F of T^{i+1}: the rewrite need not read
+  // them back from the slot
+  if (sym_next) {
+    sym_next[o] = r;
+    if (fnext) fnext[o] = F;
+  }
 }
 
 // one wave per flag word of 64 phrases: ranks from the word's count base and
@@ -1965,12 +1972,13 @@ __device__ __forceinline__ void commit_words(uint64_t d, uint64_t wave, uint64_t
                                              const uint64_t* __restrict__ pstart,
                                              const uint32_t* __restrict__ plen,
                                              const Sym* __restrict__ content,
-                                             const uint32_t* __restrict__ fnew,
+                                             const uint32_t* fnew,
                                              const uint32_t* __restrict__ fprev, LevelHash h,
                                              uint32_t u_prev, uint64_t q_prev,
                                              uint64_t* __restrict__ rule_off,
                                              Sym* __restrict__ rule_rhs,
-                                             uint32_t* __restrict__ rule_fp) {
+                                             uint32_t* __restrict__ rule_fp, uint32_t* sym_next,
+                                             uint32_t* fnext) {
   constexpr bool kBytes = sizeof(Sym) == 1;
   const uint64_t W = (d + 63) / 64;
   const uint32_t lane = threadIdx.x & 63;
@@ -1987,7 +1995,7 @@ __device__ __forceinline__ void commit_words(uint64_t d, uint64_t wave, uint64_t
                                              __builtin_popcountll(fw & ((1ULL << lane) - 1ULL)));
       const uint64_t q = q_prev + wlen_base[wd] + excl;
       commit_one<Sym>(o, r, q, kk, L, slot_idx[o], table, wkey, pstart, content, fnew, fprev, h,
-                      rule_off, rule_rhs, rule_fp);
+                      rule_off, rule_rhs, rule_fp, sym_next, fnext);
     }
   }
 }
@@ -2003,17 +2011,18 @@ __global__ __launch_bounds__(256) void k_commit_new(uint64_t d, const uint64_t* 
                                                     const uint64_t* __restrict__ pstart,
                                                     const uint32_t* __restrict__ plen,
                                                     const Sym* __restrict__ content,
-                                                    const uint32_t* __restrict__ fnew,
+                                                    const uint32_t* fnew,
                                                     const uint32_t* __restrict__ fprev, LevelHash h,
                                                     uint32_t u_prev, uint64_t q_prev,
                                                     uint64_t* __restrict__ rule_off,
                                                     Sym* __restrict__ rule_rhs,
-                                                    uint32_t* __restrict__ rule_fp) {
+                                                    uint32_t* __restrict__ rule_fp,
+                                                    uint32_t* sym_next, uint32_t* fnext) {
   if (d_dev) d = *d_dev;
   commit_words<Sym>(d, blockIdx.x * (uint64_t)(blockDim.x / 64) + (threadIdx.x >> 6),
                     (uint64_t)gridDim.x * (blockDim.x / 64), slot_idx, table, newbits, wcnt_base,
                     wlen_base, key, wkey, pstart, plen, content, fnew, fprev, h, u_prev, q_prev,
-                    rule_off, rule_rhs, rule_fp);
+                    rule_off, rule_rhs, rule_fp, sym_next, fnext);
 }
 
 // When few phrases are new, one wave per word leaves most lanes idle: the new
@@ -2051,12 +2060,13 @@ __global__ __launch_bounds__(256) void k_commit_list(uint64_t u_new, const uint3
                                                      const uint64_t* __restrict__ pstart,
                                                      const uint32_t* __restrict__ plen,
                                                      const Sym* __restrict__ content,
-                                                     const uint32_t* __restrict__ fnew,
+                                                     const uint32_t* fnew,
                                                      const uint32_t* __restrict__ fprev, LevelHash h,
                                                      uint32_t u_prev, uint64_t q_prev,
                                                      uint64_t* __restrict__ rule_off,
                                                      Sym* __restrict__ rule_rhs,
-                                                     uint32_t* __restrict__ rule_fp) {
+                                                     uint32_t* __restrict__ rule_fp,
+                                                     uint32_t* sym_next, uint32_t* fnext) {
   constexpr bool kBytes = sizeof(Sym) == 1;
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < u_new;
        i += (uint64_t)gridDim.x * blockDim.x) {
@@ -2064,7 +2074,7 @@ __global__ __launch_bounds__(256) void k_commit_list(uint64_t u_new, const uint3
     const uint64_t kk = key[o];
     commit_one<Sym>(o, u_prev + (uint32_t)i, q_prev + qoff[i], kk, key_len<kBytes>(kk, plen, o),
                     slot_idx[o], table, wkey, pstart, content, fnew, fprev, h, rule_off, rule_rhs,
-                    rule_fp);
+                    rule_fp, sym_next, fnext);
   }
 }
 
@@ -2079,27 +2089,48 @@ __device__ __forceinline__ uint64_t rank_and_fp(const Slot* __restrict__ table, 
   return sidx == kNone ? 0 : *reinterpret_cast<const uint64_t*>(&table[sidx].minocc);
 }
 
-// Phrases of the groups of four g = tid, tid + nthreads, ...
+// Phrases of the groups of four g = tid, tid + nthreads, ...  With newbits,
+// the phrases flagged new were written by the commit (their rank and F are
+// known there): their slots are not read; a group with some of them merges
+// what the commit wrote, a group of four new ones is left as it is.
 __device__ __forceinline__ void rewrite_range(uint64_t d, uint64_t tid, uint64_t nthreads,
                                               const uint32_t* __restrict__ slot_idx,
                                               const Slot* __restrict__ table,
-                                              uint32_t* __restrict__ sym_next,
-                                              uint32_t* __restrict__ fnext) {
+                                              const uint64_t* __restrict__ newbits,
+                                              uint32_t* sym_next, uint32_t* fnext) {
   for (uint64_t o = tid * kRewriteItems; o < d; o += nthreads * kRewriteItems) {
+  const uint32_t nw =
+      newbits ? (uint32_t)(newbits[o >> 6] >> (o & 63)) & ((1u << kRewriteItems) - 1u) : 0u;
   if (o + kRewriteItems <= d) {
+    if (nw == (1u << kRewriteItems) - 1u) continue;
     // the phrase arrays stream past (non-temporal), the table lines stay cached
     const u32x4 si = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(slot_idx + o));
-    const uint64_t f0 = rank_and_fp(table, si.x), f1 = rank_and_fp(table, si.y),
-                   f2 = rank_and_fp(table, si.z), f3 = rank_and_fp(table, si.w);
-    const u32x4 sv = {(uint32_t)(f0 >> 32), (uint32_t)(f1 >> 32), (uint32_t)(f2 >> 32),
-                      (uint32_t)(f3 >> 32)};
-    __builtin_nontemporal_store(sv, reinterpret_cast<u32x4*>(sym_next + o));
-    if (fnext) {
-      const u32x4 fv = {(uint32_t)f0, (uint32_t)f1, (uint32_t)f2, (uint32_t)f3};
-      __builtin_nontemporal_store(fv, reinterpret_cast<u32x4*>(fnext + o));
+    const uint64_t f0 = nw & 1u ? 0 : rank_and_fp(table, si.x),
+                   f1 = nw & 2u ? 0 : rank_and_fp(table, si.y),
+                   f2 = nw & 4u ? 0 : rank_and_fp(table, si.z),
+                   f3 = nw & 8u ? 0 : rank_and_fp(table, si.w);
+    u32x4 sv = {(uint32_t)(f0 >> 32), (uint32_t)(f1 >> 32), (uint32_t)(f2 >> 32),
+                (uint32_t)(f3 >> 32)};
+    u32x4 fv = {(uint32_t)f0, (uint32_t)f1, (uint32_t)f2, (uint32_t)f3};
+    if (nw) {
+      const u32x4 sc = *reinterpret_cast<const u32x4*>(sym_next + o);
+      sv.x = nw & 1u ? sc.x : sv.x;
+      sv.y = nw & 2u ? sc.y : sv.y;
+      sv.z = nw & 4u ? sc.z : sv.z;
+      sv.w = nw & 8u ? sc.w : sv.w;
+      if (fnext) {
+        const u32x4 fc = *reinterpret_cast<const u32x4*>(fnext + o);
+        fv.x = nw & 1u ? fc.x : fv.x;
+        fv.y = nw & 2u ? fc.y : fv.y;
+        fv.z = nw & 4u ? fc.z : fv.z;
+        fv.w = nw & 8u ? fc.w : fv.w;
+      }
     }
+    __builtin_nontemporal_store(sv, reinterpret_cast<u32x4*>(sym_next + o));
+    if (fnext) __builtin_nontemporal_store(fv, reinterpret_cast<u32x4*>(fnext + o));
   } else {
     for (uint64_t x = o; x < d; ++x) {
+      if ((nw >> (x - o)) & 1u) continue;
       const uint64_t fr = rank_and_fp(table, slot_idx[x]);
       sym_next[x] = (uint32_t)(fr >> 32);
       if (fnext) fnext[x] = (uint32_t)fr;
@@ -2111,11 +2142,11 @@ __device__ __forceinline__ void rewrite_range(uint64_t d, uint64_t tid, uint64_t
 __global__ __launch_bounds__(256) void k_rewrite(uint64_t d, const uint64_t* __restrict__ d_dev,
                                                  const uint32_t* __restrict__ slot_idx,
                                                  const Slot* __restrict__ table,
-                                                 uint32_t* __restrict__ sym_next,
-                                                 uint32_t* __restrict__ fnext) {
+                                                 const uint64_t* __restrict__ newbits,
+                                                 uint32_t* sym_next, uint32_t* fnext) {
   if (d_dev) d = *d_dev;
   rewrite_range(d, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x,
-                (uint64_t)gridDim.x * blockDim.x, slot_idx, table, sym_next, fnext);
+                (uint64_t)gridDim.x * blockDim.x, slot_idx, table, newbits, sym_next, fnext);
 }
 
 void launch_commit(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t* slot_idx, Slot* table,
@@ -2128,6 +2159,10 @@ void launch_commit(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t
                    uint32_t* nlist, uint64_t* nqoff, hipStream_t s) {
   if (!d) return;
   const unsigned g = grid_for((d + 63) / 64, 4);  // one wave per flag word
+  // Where many phrases are new, the per-word commit also writes each new
+  // phrase's own symbol and F of T^{i+1} (coalesced within its word) and the
+  // rewrite skips their slots; the listed commit of rounds where few are new
+  // would write them scattered, which costs more than the slot reads saved.
   if (!d_dev && nlist && nqoff && u_new * kCommitListRatio < d) {
     const uint64_t W = (d + 63) / 64;
     unsigned gw = grid_for(W, 256);
@@ -2140,7 +2175,7 @@ void launch_commit(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t
         k_commit_list<uint8_t><<<gu, 256, 0, s>>>(
             u_new, nlist, nqoff, slot_idx, table, key, wkey, pstart, plen,
             static_cast<const uint8_t*>(content), fnew, fprev, h, u_prev, q_prev, rule_off,
-            static_cast<uint8_t*>(rule_rhs), rule_fp);
+            static_cast<uint8_t*>(rule_rhs), rule_fp, nullptr, nullptr);
     } else {
       k_new_list<false><<<gw, 256, 0, s>>>(W, newbits, wcnt_base, wlen_base, key, plen, nlist,
                                            nqoff);
@@ -2148,25 +2183,26 @@ void launch_commit(bool bytes, uint64_t d, const uint64_t* d_dev, const uint32_t
         k_commit_list<uint32_t><<<gu, 256, 0, s>>>(
             u_new, nlist, nqoff, slot_idx, table, key, wkey, pstart, plen,
             static_cast<const uint32_t*>(content), fnew, fprev, h, u_prev, q_prev, rule_off,
-            static_cast<uint32_t*>(rule_rhs), rule_fp);
+            static_cast<uint32_t*>(rule_rhs), rule_fp, nullptr, nullptr);
     }
     LCG_LAUNCH_CHECK("commit_list");
+    newbits = nullptr;  // the rewrite reads every phrase's slot
   } else if (bytes)
     k_commit_new<uint8_t><<<g, 256, 0, s>>>(
         d, d_dev, slot_idx, table, newbits, wcnt_base, wlen_base, key, wkey, pstart, plen,
         static_cast<const uint8_t*>(content), fnew, fprev, h, u_prev, q_prev, rule_off,
-        static_cast<uint8_t*>(rule_rhs), rule_fp);
+        static_cast<uint8_t*>(rule_rhs), rule_fp, sym_next, fnext);
   else
     k_commit_new<uint32_t><<<g, 256, 0, s>>>(
         d, d_dev, slot_idx, table, newbits, wcnt_base, wlen_base, key, wkey, pstart, plen,
         static_cast<const uint32_t*>(content), fnew, fprev, h, u_prev, q_prev, rule_off,
-        static_cast<uint32_t*>(rule_rhs), rule_fp);
+        static_cast<uint32_t*>(rule_rhs), rule_fp, sym_next, fnext);
   LCG_LAUNCH_CHECK("commit_new");
   if ((reinterpret_cast<uintptr_t>(slot_idx) | reinterpret_cast<uintptr_t>(sym_next) |
        reinterpret_cast<uintptr_t>(fnext)) & 15)
     throw std::runtime_error("rewrite arrays are not 16-byte aligned");
   k_rewrite<<<grid_for((d + kRewriteItems - 1) / kRewriteItems, 256), 256, 0, s>>>(
-      d, d_dev, slot_idx, table, sym_next, fnext);
+      d, d_dev, slot_idx, table, newbits, sym_next, fnext);
   LCG_LAUNCH_CHECK("rewrite");
 }
 
@@ -2720,9 +2756,9 @@ __device__ __forceinline__ void tail_round(const TailArgs& a, const TailRound& R
   grid_barrier(grid);
   commit_words<Sym>(d, wid, NW, a.slot_idx, R.table, a.newbits, a.wcnt_base, a.wlen_base, a.key,
                     a.wkey, a.pstart, a.plen, content, a.fpv[cur], R.fprev, R.h, R.u0, R.q0,
-                    R.rule_off, static_cast<Sym*>(R.rule_rhs), R.rule_fp);
+                    R.rule_off, static_cast<Sym*>(R.rule_rhs), R.rule_fp, nullptr, nullptr);
   grid_barrier(grid);
-  rewrite_range(d, tid, T, a.slot_idx, R.table, a.sym[cur], a.fpv[cur]);
+  rewrite_range(d, tid, T, a.slot_idx, R.table, nullptr, a.sym[cur], a.fpv[cur]);
   segments_range(cur_off, a.k, a.bits, a.tile_base, d, a.off[cur], tid, T);
   grid_barrier(grid);
   finish_range(cur_off, a.off[cur], a.k, a.sym[cur], R.level, a.c_level, a.c_sym, &R.rec->fin,
