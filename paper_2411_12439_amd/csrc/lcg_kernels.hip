@@ -1496,7 +1496,10 @@ __global__ __launch_bounds__(256) void k_insert_comb(uint64_t begin, uint64_t en
       {
         const uint64_t kk = kc[x];
         if (!(kk & kLongTag)) {
-          uint32_t lpos = (uint32_t)(mix64(kk) >> 40) & (kComb - 1);
+          // LDS position: the key's halves folded and one 32-bit multiply
+          // (the global table's 64-bit mix is needed only once per distinct key)
+          uint32_t lpos = (((uint32_t)kk ^ (uint32_t)(kk >> 32) * 0x85EBCA77u) * 0x9E3779B1u) >>
+                          (32 - kCombLog2);
           for (int t = 0; t < kCombProbe && found == kNone; ++t) {
             const unsigned long long w =
                 __hip_atomic_load(&s_key[lpos], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
