@@ -65,6 +65,16 @@ def test_traffic_needs_the_measured_source(tmp_path, monkeypatch):
     assert B.profile_traffic("k_insert<unsigned int, false>", "absent") is None
 
 
+def test_path_traffic_needs_the_measured_source(tmp_path, monkeypatch):
+    monkeypatch.setattr(B, "PROFILE_DIR", str(tmp_path))
+    f = tmp_path / "path_demo_traffic.txt"
+    f.write_text("# header\nkernel_source_sha256: %s\npath_bytes_per_build: 4.5e9\n" % B.source_digest())
+    assert B.profile_value("path_demo_traffic.txt", "path_bytes_per_build") == 4.5e9
+    assert B.profile_value("path_demo_traffic.txt", "missing_field") is None
+    f.write_text("kernel_source_sha256: 00\npath_bytes_per_build: 4.5e9\n")
+    assert B.profile_value("path_demo_traffic.txt", "path_bytes_per_build") is None
+
+
 def test_cpu_baselines_name_the_host():
     """Both oracle timings record the host CPU beside their core count."""
     from oracle import oracle as O
