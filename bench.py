@@ -68,7 +68,10 @@ WORKLOADS = {
 PHASES = ("classify", "emit", "insert", "rank", "commit", "segments")
 ROOFLINE_KERNEL = "k_insert<unsigned int, false>"
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2411_12439_amd", "csrc", "lcg_kernels.hip")
+# the round kernels and the device header they include: a change to either
+# makes the committed counter summaries stale
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2411_12439_amd", "csrc", f)
+                  for f in ("lcg_kernels.hip", "lcg_device.h")]
 
 
 def phase_alg_bytes(st):
@@ -95,8 +98,11 @@ def insert_rounds(st):
 
 def source_digest():
     import hashlib
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def profile_value(name, field):

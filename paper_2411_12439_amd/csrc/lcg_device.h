@@ -124,4 +124,31 @@ __host__ __device__ __forceinline__ uint32_t wide_bcode(uint64_t kk) {
   return (uint32_t)((kk >> 57) & 3);
 }
 
+// Exclusive scan of one value per thread over a block of THREADS threads
+// (a multiple of 64): wave prefix by shuffles, then the waves' totals from
+// LDS (s_wave: THREADS / 64 values).  *total (if given) receives the block's
+// sum.  Every thread of the block must call it.
+template <typename T, int THREADS = 256>
+__device__ __forceinline__ T block_excl_scan(T v, T* s_wave, T* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  T x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    T y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) s_wave[wid] = x;
+  __syncthreads();
+  T base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < THREADS / 64; ++w) {
+    T sw = s_wave[w];
+    if (w < wid) base += sw;
+    tot += sw;
+  }
+  __syncthreads();
+  if (total) *total = tot;
+  return base + x - v;
+}
+
 }  // namespace lcg

@@ -90,30 +90,6 @@ __device__ __forceinline__ uint32_t seg_search(const uint64_t* off, uint32_t lo,
   return lo;
 }
 
-// Exclusive block scan of one value per thread (kBlock threads).
-template <typename T>
-__device__ __forceinline__ T block_excl_scan(T v, T* s_wave, T* total) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  T x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    T y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
-  if (lane == 63) s_wave[wid] = x;
-  __syncthreads();
-  T base = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w) {
-    T sw = s_wave[w];
-    if (w < wid) base += sw;
-    tot += sw;
-  }
-  __syncthreads();
-  if (total) *total = tot;
-  return base + x - v;
-}
-
 template <bool BYTES>
 __device__ __forceinline__ uint32_t fval(const RoundIn& in, const uint32_t* s_lut, uint64_t i) {
   if constexpr (BYTES) return s_lut[static_cast<const uint8_t*>(in.sym)[i]];

@@ -31,25 +31,6 @@ constexpr int kSBlock = 256;
 constexpr int kSItems = 16;
 constexpr uint64_t kSTile = kSBlock * kSItems;  // bytes per tile
 
-__device__ __forceinline__ uint32_t block_excl_u32(uint32_t v, uint32_t* s_w, uint32_t* total) {
-  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  uint32_t incl = v;
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t o = __shfl_up(incl, d);
-    if ((int)lane >= d) incl += o;
-  }
-  if (lane == 63) s_w[wv] = incl;
-  __syncthreads();
-  uint32_t before = 0, tot = 0;
-  for (uint32_t w = 0; w < kSBlock / 64; ++w) {
-    before += w < wv ? s_w[w] : 0;
-    tot += s_w[w];
-  }
-  __syncthreads();
-  *total = tot;
-  return before + incl - v;
-}
-
 // newlines per tile
 __global__ __launch_bounds__(kSBlock) void k_nl_count(const uint8_t* __restrict__ raw, uint64_t n,
                                                       uint64_t* __restrict__ cnt) {
@@ -58,7 +39,7 @@ __global__ __launch_bounds__(kSBlock) void k_nl_count(const uint8_t* __restrict_
   uint32_t c = 0;
   for (int i = 0; i < kSItems; ++i) c += (base + i < n && raw[base + i] == '\n') ? 1 : 0;
   uint32_t tot;
-  block_excl_u32(c, s_w, &tot);
+  block_excl_scan<uint32_t, kSBlock>(c, s_w, &tot);
   if (threadIdx.x == 0) cnt[blockIdx.x] = tot;
 }
 
@@ -76,7 +57,7 @@ __global__ __launch_bounds__(kSBlock) void k_nl_split(const uint8_t* __restrict_
     c += (base + i < n && b[i] == '\n') ? 1 : 0;
   }
   uint32_t tot;
-  uint64_t l = lbase[blockIdx.x] + block_excl_u32(c, s_w, &tot);  // newlines before base
+  uint64_t l = lbase[blockIdx.x] + block_excl_scan<uint32_t, kSBlock>(c, s_w, &tot);  // newlines before base
   for (int i = 0; i < kSItems; ++i) {
     const uint64_t x = base + i;
     if (x >= n) break;

@@ -1,7 +1,8 @@
 """Host logic of bench.py, no GPU: the one-GPU guard, the algorithmic-byte
 model (the per-round formula written out for a two-round example), the choice
 of the rounds whose insert phase is one launch, and the rule that a traffic
-figure is used only while the kernel source is the one it was measured on."""
+figure is used only while the kernel source (the round kernels and their device
+header) is the one it was measured on."""
 import os
 import subprocess
 import sys
