@@ -3,7 +3,8 @@
 // A plain, slow, single-threaded CPU implementation of the stable locally
 // consistent grammar construction (BuildGram), of MergeGrams, of grammar
 // expansion, of the RL and Simp post-processing and of the stored file of its
-// result, written from the paper "Efficient terabyte-scale text
+// result, and of App. B's match queries (longest common extensions, maximal
+// exact matches through the grammar), written from the paper "Efficient terabyte-scale text
 // compression via stable local consistency and parallel grammar processing"
 // (Diaz-Dominguez, arXiv 2411.12439).  Only the test suite, the smoke check
 // and the CPU-baseline leg of the benchmark load it.  It shares no code,
@@ -34,6 +35,7 @@
 //     convert ranks to global ids and are not materialised.
 
 #include <algorithm>
+#include <array>
 #include <cstdint>
 #include <cstring>
 #include <cstdio>
@@ -859,6 +861,83 @@ void oracle_lce(const uint8_t* text, const uint64_t* off, uint32_t nq, const uin
     }
     out[q] = l;
   }
+}
+
+// Maximal exact matches between strings a and b found through the grammar
+// (App. B): the level-`level` parse of each string is obtained by
+// substituting right-hand sides from C[j] down to that level; every pair of
+// equal symbols, one in each parse, is an anchor, and the match it seeds is
+// the longest run of equal bytes on the anchor's diagonal that contains the
+// anchor's first byte (the lcs before it and the lcp from it, both on the
+// text).  Result: the distinct such matches of at least min_len bytes as
+// (start in a, start in b, length), sorted by start in a, then in b; with
+// a == b an anchor pairs two different positions of the parse.  Returns the
+// number of matches and writes the first min(count, cap); on a bad argument
+// returns UINT64_MAX (oracle_last_error).
+uint64_t oracle_mems(const OracleGrammar* g, const uint8_t* text, const uint64_t* off, uint32_t a,
+                     uint32_t b, uint32_t level, uint64_t min_len, uint64_t cap, uint64_t* pa,
+                     uint64_t* pb, uint64_t* len) {
+  const uint32_t k = (uint32_t)g->c_level.size();
+  if (a >= k || b >= k) {
+    g_err = "no such string";
+    return UINT64_MAX;
+  }
+  if (level < 1 || level > g->c_level[a] || level > g->c_level[b]) {
+    g_err = "level outside 1..min(level of C[a], level of C[b])";
+    return UINT64_MAX;
+  }
+  auto parse = [&](uint32_t j) {
+    std::vector<uint32_t> cur(1, g->c_sym[j]);
+    for (uint32_t l = g->c_level[j]; l > level; --l) {
+      const Level& L = g->levels[l - 1];
+      std::vector<uint32_t> next;
+      for (uint32_t x : cur)
+        for (uint64_t t = L.rhs_off[x]; t < L.rhs_off[x + 1]; ++t) next.push_back(L.rhs[t]);
+      cur.swap(next);
+    }
+    return cur;
+  };
+  std::unordered_map<uint32_t, uint64_t> elen;  // expansion length per level symbol
+  auto starts = [&](const std::vector<uint32_t>& ps) {
+    std::vector<uint64_t> st(ps.size());
+    uint64_t p = 0;
+    for (size_t i = 0; i < ps.size(); ++i) {
+      st[i] = p;
+      auto it = elen.find(ps[i]);
+      if (it == elen.end())
+        it = elen.emplace(ps[i], oracle_expand_symbol(g, level, ps[i], nullptr, 0)).first;
+      p += it->second;
+    }
+    return st;
+  };
+  const std::vector<uint32_t> A = parse(a), B = parse(b);
+  const std::vector<uint64_t> xa = starts(A), xb = starts(B);
+  std::unordered_map<uint32_t, std::vector<uint32_t>> where;  // symbol -> its indexes in B
+  for (uint32_t j = 0; j < B.size(); ++j) where[B[j]].push_back(j);
+  const uint8_t* ta = text + off[a];
+  const uint8_t* tb = text + off[b];
+  const uint64_t na = off[a + 1] - off[a], nb = off[b + 1] - off[b];
+  std::vector<std::array<uint64_t, 3>> found;
+  for (uint32_t i = 0; i < A.size(); ++i) {
+    auto it = where.find(A[i]);
+    if (it == where.end()) continue;
+    for (uint32_t j : it->second) {
+      if (a == b && i == j) continue;
+      const uint64_t x = xa[i], y = xb[j];
+      uint64_t back = 0, fwd = 0;
+      while (back < x && back < y && ta[x - 1 - back] == tb[y - 1 - back]) ++back;
+      while (x + fwd < na && y + fwd < nb && ta[x + fwd] == tb[y + fwd]) ++fwd;
+      if (back + fwd >= min_len) found.push_back({x - back, y - back, back + fwd});
+    }
+  }
+  std::sort(found.begin(), found.end());
+  found.erase(std::unique(found.begin(), found.end()), found.end());
+  for (uint64_t q = 0; q < found.size() && q < cap; ++q) {
+    pa[q] = found[q][0];
+    pb[q] = found[q][1];
+    len[q] = found[q][2];
+  }
+  return found.size();
 }
 
 }  // extern "C"

@@ -90,6 +90,10 @@ def lib():
         L.oracle_slp_decode.restype = vp
         L.oracle_lce.argtypes = [u8p, u64p, ctypes.c_uint32, u32p, u64p, u32p, u64p,
                                  ctypes.c_uint32, u64p]
+        L.oracle_mems.argtypes = [vp, u8p, u64p, ctypes.c_uint32, ctypes.c_uint32,
+                                  ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, u64p, u64p,
+                                  u64p]
+        L.oracle_mems.restype = ctypes.c_uint64
         _lib = L
     return _lib
 
@@ -182,6 +186,27 @@ class Grammar:
         if rc != 0:
             raise ValueError(lib().oracle_last_error().decode())
         return out[:len(s1)]
+
+    def mems(self, text, offsets, a, b, level, min_len):
+        """Maximal exact matches of at least min_len bytes between strings a
+        and b seeded by equal symbols of their level-``level`` parses (see
+        oracle_mems); ``text``/``offsets`` are the collection this grammar was
+        built from.  Returns (start in a, start in b, length) as three
+        uint64 arrays sorted by start in a, then in b."""
+        text = np.ascontiguousarray(text, np.uint8)
+        offsets = np.ascontiguousarray(offsets, np.uint64)
+        L = lib()
+        z = np.zeros(1, np.uint64)
+        args = (self.h, _ptr(text, ctypes.c_uint8), _ptr(offsets, ctypes.c_uint64), a, b, level,
+                min_len)
+        n = L.oracle_mems(*args, 0, _ptr(z, ctypes.c_uint64), _ptr(z, ctypes.c_uint64),
+                          _ptr(z, ctypes.c_uint64))
+        if n == 2**64 - 1:
+            raise ValueError(L.oracle_last_error().decode())
+        pa, pb, ln = (np.zeros(max(n, 1), np.uint64) for _ in range(3))
+        L.oracle_mems(*args, n, _ptr(pa, ctypes.c_uint64), _ptr(pb, ctypes.c_uint64),
+                      _ptr(ln, ctypes.c_uint64))
+        return pa[:n], pb[:n], ln[:n]
 
     def expand_symbol(self, level, sym):
         """exp(X) of the symbol (level, rank) as bytes."""
