@@ -337,6 +337,33 @@ lcg_status lcg_lce(lcg_grammar_t g, uint32_t nq, const uint32_t* d_j1, const uin
 lcg_status lcg_symbol_lce(lcg_grammar_t g, uint32_t nq, const uint8_t* d_lv1, const uint32_t* d_s1,
                           const uint8_t* d_lv2, const uint32_t* d_s2, uint32_t backward,
                           uint64_t* d_out, hipStream_t stream);
+/*
+ * Maximal exact matches between strings a and b through the grammar (the
+ * MEM example of App. B, on the level-`level` parses of the two strings
+ * rather than on right-hand sides, so that matches come out in text
+ * positions).  The parse of string j at level l is what substituting
+ * right-hand sides from C[j] down to level l gives.  Every pair of equal
+ * symbols, one in each parse, is an anchor (with a == b, two different
+ * positions of the parse); the match it seeds is the maximal run of equal
+ * bytes T_a[pa + t] == T_b[pb + t] on the anchor's diagonal that contains its
+ * first byte, completed by the lcs before the anchor and the lcp from it
+ * (the cursor walk of lcg_lce).  A match holding no anchor is not reported:
+ * a lower level finds more of the short ones, at the cost of more anchors;
+ * matches that cover a whole level-1 phrase alike in both strings are found
+ * at level 1.
+ * Output: the distinct matches of at least min_len bytes, sorted by start in
+ * a, then start in b: d_pa[t], d_pb[t] (starts) and d_len[t] (uint64 device
+ * arrays of `cap` entries; the first min(count, cap) are written).  *n_mems
+ * (host) receives the count, which may exceed cap: call again with a larger
+ * cap for all of them.  Synchronises the stream.  Errors: LCG_EINVAL (NULL
+ * n_mems, NULL arrays with cap > 0, a string index beyond the grammar's,
+ * level outside 1..min(level of C[a], level of C[b])), LCG_EOVERFLOW (a parse
+ * of 2^31 symbols or more, more than 2^31 symbol pairs at this level --
+ * choose a higher one --, 64 levels or more), LCG_ENOMEM.
+ */
+lcg_status lcg_mems(lcg_grammar_t g, uint32_t a, uint32_t b, uint32_t level, uint64_t min_len,
+                    uint64_t cap, uint64_t* d_pa, uint64_t* d_pb, uint64_t* d_len,
+                    uint64_t* n_mems, hipStream_t stream);
 
 /* An empty grammar with hash family `seed` (no levels, no strings). */
 lcg_status lcg_new(uint64_t seed, lcg_grammar_t* out);

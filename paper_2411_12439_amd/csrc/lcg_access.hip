@@ -7,6 +7,7 @@
 // byte each, so there are never more than len of them -- and the level-1
 // symbols finally write their bytes.
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include "lcg_host.h"
 
@@ -379,6 +380,224 @@ __global__ __launch_bounds__(64) void k_symbol_lce(const LevelPtrs* __restrict__
   }
 }
 
+// ---------------------------------------------------------------- MEMs
+// Maximal exact matches between two strings through the grammar (App. B):
+// the level-l parses of both strings are the search space; equal symbols, one
+// in each parse, are anchors, and each is completed into the maximal run of
+// equal bytes on its diagonal by the two grammar walks above (the lcs before
+// the anchor, the lcp from it).  Only the first anchor of a run of
+// consecutive anchors on one diagonal (the symbols before it differ) is
+// completed: the others lie inside the same match.
+constexpr int kMB = 256;
+constexpr uint64_t kMemMaxAnchors = 1ull << 31;  // 32-bit counts in the radix sorts
+
+inline unsigned mem_grid(uint64_t n) {
+  return (unsigned)std::min<uint64_t>((n + kMB - 1) / kMB, 16384);
+}
+
+__global__ __launch_bounds__(kMB) void k_mem_set(uint32_t* v, uint32_t y) { v[0] = y; }
+
+// right-hand-side length of every symbol of a parse (levels >= 2)
+__global__ __launch_bounds__(kMB) void k_mem_rhslen(const uint64_t* __restrict__ off,
+                                                    const uint32_t* __restrict__ cur, uint64_t n,
+                                                    uint64_t* __restrict__ cnt) {
+  for (uint64_t i = blockIdx.x * (uint64_t)kMB + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * kMB) {
+    const uint32_t x = cur[i];
+    cnt[i] = off[x + 1] - off[x];
+  }
+}
+
+// the parse one level down: every symbol's right-hand side at its place
+__global__ __launch_bounds__(kMB) void k_mem_children(const uint64_t* __restrict__ off,
+                                                      const uint32_t* __restrict__ rhs,
+                                                      const uint32_t* __restrict__ cur, uint64_t n,
+                                                      const uint64_t* __restrict__ pos,
+                                                      uint32_t* __restrict__ next) {
+  for (uint64_t i = blockIdx.x * (uint64_t)kMB + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * kMB) {
+    const uint32_t x = cur[i];
+    uint64_t p = pos[i];
+    for (uint64_t t = off[x], e = off[x + 1]; t < e; ++t) next[p++] = rhs[t];
+  }
+}
+
+// expansion length of every symbol of the level-l parse; index order for the sort
+__global__ __launch_bounds__(kMB) void k_mem_elen(const uint64_t* __restrict__ explen_l,
+                                                  const uint32_t* __restrict__ cur, uint64_t n,
+                                                  uint64_t* __restrict__ e,
+                                                  uint32_t* __restrict__ idx) {
+  for (uint64_t i = blockIdx.x * (uint64_t)kMB + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * kMB) {
+    e[i] = explen_l[cur[i]];
+    idx[i] = (uint32_t)i;
+  }
+}
+
+// the entries of b's parse sorted by symbol that hold a's symbol at i
+__global__ __launch_bounds__(kMB) void k_mem_range(const uint32_t* __restrict__ A, uint64_t na,
+                                                   const uint32_t* __restrict__ keys, uint64_t nb,
+                                                   uint64_t* __restrict__ lo,
+                                                   uint64_t* __restrict__ cnt) {
+  for (uint64_t i = blockIdx.x * (uint64_t)kMB + threadIdx.x; i < na;
+       i += (uint64_t)gridDim.x * kMB) {
+    const uint32_t x = A[i];
+    uint64_t l = 0, h = nb;
+    while (l < h) {  // first key >= x
+      const uint64_t m = (l + h) >> 1;
+      if (keys[m] < x) l = m + 1; else h = m;
+    }
+    uint64_t r = l, h2 = nb;
+    while (r < h2) {  // first key > x
+      const uint64_t m = (r + h2) >> 1;
+      if (keys[m] <= x) r = m + 1; else h2 = m;
+    }
+    lo[i] = l;
+    cnt[i] = r - l;
+  }
+}
+
+// Anchors (i, j) that start a run on their diagonal; counted per i, then
+// written at the scanned positions.  With one string on both sides the pairs
+// of a position with itself are not anchors.
+template <bool WRITE>
+__global__ __launch_bounds__(kMB) void k_mem_seeds(
+    const uint32_t* __restrict__ A, uint64_t na, const uint32_t* __restrict__ B,
+    const uint32_t* __restrict__ where, const uint64_t* __restrict__ lo,
+    const uint64_t* __restrict__ cnt, int same, uint64_t* __restrict__ nseed,
+    const uint64_t* __restrict__ spos, uint32_t* __restrict__ si, uint32_t* __restrict__ sj) {
+  for (uint64_t i = blockIdx.x * (uint64_t)kMB + threadIdx.x; i < na;
+       i += (uint64_t)gridDim.x * kMB) {
+    const uint64_t b = lo[i], e = b + cnt[i];
+    const bool has_prev = i > 0;
+    const uint32_t prev = has_prev ? A[i - 1] : 0;
+    uint64_t c = WRITE ? spos[i] : 0;
+    for (uint64_t t = b; t < e; ++t) {
+      const uint32_t j = where[t];
+      if (same && j == i) continue;
+      if (has_prev && j > 0 && B[j - 1] == prev) continue;
+      if (WRITE) {
+        si[c] = (uint32_t)i;
+        sj[c] = j;
+      }
+      ++c;
+    }
+    if (!WRITE) nseed[i] = c;
+  }
+}
+
+// the match through each seed: lcs before it, lcp from its first byte
+__global__ __launch_bounds__(64) void k_mem_extend(
+    const LevelPtrs* __restrict__ lv_ptr, const uint64_t* const* __restrict__ explen, int ta,
+    uint32_t ya, uint64_t na, int tb, uint32_t yb, uint64_t nb, const uint64_t* __restrict__ sa,
+    const uint64_t* __restrict__ sb, const uint32_t* __restrict__ si,
+    const uint32_t* __restrict__ sj, uint64_t ns, uint64_t min_len, uint64_t* __restrict__ mpa,
+    uint64_t* __restrict__ mpb, uint64_t* __restrict__ mlen, uint64_t* __restrict__ keep) {
+  for (uint64_t q = blockIdx.x * (uint64_t)64 + threadIdx.x; q < ns;
+       q += (uint64_t)gridDim.x * 64) {
+    const uint64_t x = sa[si[q]], y = sb[sj[q]];
+    const uint64_t back = lce_walk<true>(lv_ptr, explen, ta, ya, x, na, tb, yb, y, nb);
+    const uint64_t fwd = lce_walk<false>(lv_ptr, explen, ta, ya, x, na, tb, yb, y, nb);
+    mpa[q] = x - back;
+    mpb[q] = y - back;
+    mlen[q] = back + fwd;
+    keep[q] = back + fwd >= min_len;
+  }
+}
+
+// kept matches packed; sort values start as their index
+__global__ __launch_bounds__(kMB) void k_mem_pack(
+    const uint64_t* __restrict__ mpa, const uint64_t* __restrict__ mpb,
+    const uint64_t* __restrict__ mlen, const uint64_t* __restrict__ keep,
+    const uint64_t* __restrict__ kpos, uint64_t ns, uint64_t* __restrict__ pa,
+    uint64_t* __restrict__ pb, uint64_t* __restrict__ ln, uint32_t* __restrict__ idx) {
+  for (uint64_t q = blockIdx.x * (uint64_t)kMB + threadIdx.x; q < ns;
+       q += (uint64_t)gridDim.x * kMB) {
+    if (!keep[q]) continue;
+    const uint64_t p = kpos[q];
+    pa[p] = mpa[q];
+    pb[p] = mpb[q];
+    ln[p] = mlen[q];
+    idx[p] = (uint32_t)p;
+  }
+}
+
+__global__ __launch_bounds__(kMB) void k_mem_gather(const uint64_t* __restrict__ src,
+                                                    const uint32_t* __restrict__ idx, uint64_t m,
+                                                    uint64_t* __restrict__ dst) {
+  for (uint64_t t = blockIdx.x * (uint64_t)kMB + threadIdx.x; t < m;
+       t += (uint64_t)gridDim.x * kMB)
+    dst[t] = src[idx[t]];
+}
+
+// after the sort by (start in a, start in b): the first of equal matches
+__global__ __launch_bounds__(kMB) void k_mem_first(const uint64_t* __restrict__ pa_s,
+                                                   const uint64_t* __restrict__ pb,
+                                                   const uint32_t* __restrict__ idx, uint64_t m,
+                                                   uint64_t* __restrict__ flag) {
+  for (uint64_t t = blockIdx.x * (uint64_t)kMB + threadIdx.x; t < m;
+       t += (uint64_t)gridDim.x * kMB)
+    flag[t] = t == 0 || pa_s[t] != pa_s[t - 1] || pb[idx[t]] != pb[idx[t - 1]];
+}
+
+__global__ __launch_bounds__(kMB) void k_mem_out(
+    const uint64_t* __restrict__ pa_s, const uint64_t* __restrict__ pb,
+    const uint64_t* __restrict__ ln, const uint32_t* __restrict__ idx,
+    const uint64_t* __restrict__ flag, const uint64_t* __restrict__ fpos, uint64_t m, uint64_t cap,
+    uint64_t* __restrict__ opa, uint64_t* __restrict__ opb, uint64_t* __restrict__ olen) {
+  for (uint64_t t = blockIdx.x * (uint64_t)kMB + threadIdx.x; t < m;
+       t += (uint64_t)gridDim.x * kMB) {
+    const uint64_t p = fpos[t];
+    if (!flag[t] || p >= cap) continue;
+    opa[p] = pa_s[t];
+    opb[p] = pb[idx[t]];
+    olen[p] = ln[idx[t]];
+  }
+}
+
+inline int bits_for(uint64_t v) {  // radix-sort key width that holds 0..v
+  int b = 1;
+  while (b < 64 && (v >> b)) ++b;
+  return b;
+}
+
+// the level-`level` parse of a string whose C entry is (top, y): symbols in
+// cur[0..n), byte starts in starts[0..n] (starts[n] = the string's length)
+uint64_t mem_parse(lcg_grammar* g, int top, uint32_t y, uint32_t level, DBuf<uint32_t>& cur,
+                   DBuf<uint64_t>& starts, DBuf<uint32_t>& idx, hipStream_t s) {
+  cur.need(1, s);
+  k_mem_set<<<1, 1, 0, s>>>(cur.p, y);
+  HIP_CHECK(hipGetLastError());
+  uint64_t n = 1;
+  DBuf<uint32_t> next;
+  DBuf<uint64_t> cnt, pos, tmp;
+  for (int l = top; l > (int)level; --l) {
+    const Level& L = g->levels[l - 1];
+    cnt.need(n, s);
+    k_mem_rhslen<<<mem_grid(n), kMB, 0, s>>>(L.off.p, cur.p, n, cnt.p);
+    HIP_CHECK(hipGetLastError());
+    pos.need(n + 1, s);
+    tmp.need(std::max<size_t>(scan_tmp_words(n), 1), s);
+    scan_exclusive(cnt.p, pos.p, n, tmp.p, s);
+    const uint64_t m = read_dev(pos.p + n, s);
+    if (m >= (1ull << 31)) throw LcgError{LCG_EOVERFLOW, "a parse of 2^31 symbols or more"};
+    next.need(m, s);
+    k_mem_children<<<mem_grid(n), kMB, 0, s>>>(L.off.p, L.rhs32.p, cur.p, n, pos.p, next.p);
+    HIP_CHECK(hipGetLastError());
+    std::swap(cur, next);
+    n = m;
+  }
+  cnt.need(n, s);
+  idx.need(n, s);
+  k_mem_elen<<<mem_grid(n), kMB, 0, s>>>(g->explen[level - 1].p, cur.p, n, cnt.p, idx.p);
+  HIP_CHECK(hipGetLastError());
+  starts.need(n + 1, s);
+  tmp.need(std::max<size_t>(scan_tmp_words(n), 1), s);
+  scan_exclusive(cnt.p, starts.p, n, tmp.p, s);
+  sync(s);  // the temporaries go back to the pool
+  return n;
+}
+
 }  // namespace
 }  // namespace lcg
 
@@ -484,6 +703,128 @@ lcg_status lcg_symbol_lce(lcg_grammar_t g, uint32_t nq, const uint8_t* d_lv1, co
       throw LcgError{LCG_EINVAL, std::to_string(nbad) + " quer" + (nbad == 1 ? "y names" : "ies name") +
                                      " no symbol (level beyond the grammar's, or rank beyond "
                                      "the level's rules)"};
+  });
+}
+
+lcg_status lcg_mems(lcg_grammar_t g, uint32_t a, uint32_t b, uint32_t level, uint64_t min_len,
+                    uint64_t cap, uint64_t* d_pa, uint64_t* d_pb, uint64_t* d_len,
+                    uint64_t* n_mems, hipStream_t stream) {
+  return guard([&] {
+    live(g);
+    if (!n_mems) throw LcgError{LCG_EINVAL, "n_mems is NULL"};
+    *n_mems = 0;
+    if (cap && (!d_pa || !d_pb || !d_len)) throw LcgError{LCG_EINVAL, "NULL output array"};
+    if (a >= g->k || b >= g->k) throw LcgError{LCG_EINVAL, "string index beyond the grammar's"};
+    if (g->levels.size() >= (size_t)kMaxLv) throw LcgError{LCG_EOVERFLOW, "too many levels"};
+    hipStream_t s = stream;
+    ensure_explen(g, s);
+    const int ta = read_dev(g->c_level.p + a, s), tb = read_dev(g->c_level.p + b, s);
+    const uint32_t ya = read_dev(g->c_sym.p + a, s), yb = read_dev(g->c_sym.p + b, s);
+    if (level < 1 || (int)level > std::min(ta, tb))
+      throw LcgError{LCG_EINVAL, "level outside 1..min(level of C[a], level of C[b])"};
+    DBuf<uint32_t> A, B, ia, ib;
+    DBuf<uint64_t> sa, sb;
+    const uint64_t na = mem_parse(g, ta, ya, level, A, sa, ia, s);
+    const uint64_t nb = mem_parse(g, tb, yb, level, B, sb, ib, s);
+    const uint64_t la = read_dev(sa.p + na, s), lb = read_dev(sb.p + nb, s);
+    // b's parse sorted by symbol, with each entry's index
+    DBuf<uint32_t> keys, where;
+    keys.need(nb, s);
+    where.need(nb, s);
+    const int kbits = bits_for(g->levels[level - 1].u);
+    size_t tbytes = 0;
+    HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, B.p, keys.p, ib.p, where.p,
+                                                 (int)nb, 0, kbits, s));
+    DBuf<uint8_t> stmp;
+    stmp.need(std::max<size_t>(tbytes, 4), s);
+    HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(stmp.p, tbytes, B.p, keys.p, ib.p, where.p,
+                                                 (int)nb, 0, kbits, s));
+    DBuf<uint64_t> lo, cnt, pos, tmp;
+    lo.need(na, s);
+    cnt.need(na, s);
+    pos.need(na + 1, s);
+    tmp.need(std::max<size_t>(scan_tmp_words(na), 1), s);
+    k_mem_range<<<mem_grid(na), kMB, 0, s>>>(A.p, na, keys.p, nb, lo.p, cnt.p);
+    HIP_CHECK(hipGetLastError());
+    scan_exclusive(cnt.p, pos.p, na, tmp.p, s);
+    const uint64_t anchors = read_dev(pos.p + na, s);
+    if (anchors > kMemMaxAnchors)
+      throw LcgError{LCG_EOVERFLOW, std::to_string(anchors) +
+                                        " anchors at this level (at most 2^31): choose a higher "
+                                        "level"};
+    DBuf<uint64_t> nseed;
+    nseed.need(na, s);
+    const int same = a == b;
+    k_mem_seeds<false><<<mem_grid(na), kMB, 0, s>>>(A.p, na, B.p, where.p, lo.p, cnt.p, same,
+                                                    nseed.p, nullptr, nullptr, nullptr);
+    HIP_CHECK(hipGetLastError());
+    scan_exclusive(nseed.p, pos.p, na, tmp.p, s);
+    const uint64_t ns = read_dev(pos.p + na, s);
+    if (!ns) return;
+    DBuf<uint32_t> si, sj;
+    si.need(ns, s);
+    sj.need(ns, s);
+    k_mem_seeds<true><<<mem_grid(na), kMB, 0, s>>>(A.p, na, B.p, where.p, lo.p, cnt.p, same,
+                                                   nullptr, pos.p, si.p, sj.p);
+    HIP_CHECK(hipGetLastError());
+    DBuf<uint64_t> mpa, mpb, mlen, keep, kpos, ktmp;
+    mpa.need(ns, s);
+    mpb.need(ns, s);
+    mlen.need(ns, s);
+    keep.need(ns, s);
+    k_mem_extend<<<(unsigned)std::min<uint64_t>((ns + 63) / 64, 65536), 64, 0, s>>>(
+        g->level_ptrs.p, g->explen_ptrs.p, ta, ya, la, tb, yb, lb, sa.p, sb.p, si.p, sj.p, ns,
+        min_len, mpa.p, mpb.p, mlen.p, keep.p);
+    HIP_CHECK(hipGetLastError());
+    kpos.need(ns + 1, s);
+    ktmp.need(std::max<size_t>(scan_tmp_words(ns), 1), s);
+    scan_exclusive(keep.p, kpos.p, ns, ktmp.p, s);
+    const uint64_t m = read_dev(kpos.p + ns, s);
+    if (!m) return;
+    // sort by (start in a, start in b): by b, then stably by a
+    DBuf<uint64_t> pa, pb, ln, k1, k2;
+    DBuf<uint32_t> i0, i1, i2;
+    pa.need(m, s);
+    pb.need(m, s);
+    ln.need(m, s);
+    i0.need(m, s);
+    k_mem_pack<<<mem_grid(ns), kMB, 0, s>>>(mpa.p, mpb.p, mlen.p, keep.p, kpos.p, ns, pa.p, pb.p,
+                                           ln.p, i0.p);
+    HIP_CHECK(hipGetLastError());
+    k1.need(m, s);
+    k2.need(m, s);
+    i1.need(m, s);
+    i2.need(m, s);
+    const int bb = bits_for(lb), ab = bits_for(la);
+    size_t t1 = 0, t2 = 0;
+    HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, t1, pb.p, k1.p, i0.p, i1.p, (int)m, 0,
+                                                 bb, s));
+    HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, t2, k2.p, k1.p, i1.p, i2.p, (int)m, 0,
+                                                 ab, s));
+    stmp.need(std::max<size_t>(std::max(t1, t2), 4), s);
+    t1 = std::max(t1, t2);
+    HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(stmp.p, t1, pb.p, k1.p, i0.p, i1.p, (int)m, 0,
+                                                 bb, s));
+    k_mem_gather<<<mem_grid(m), kMB, 0, s>>>(pa.p, i1.p, m, k2.p);
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(stmp.p, t1, k2.p, k1.p, i1.p, i2.p, (int)m, 0,
+                                                 ab, s));
+    // k1: starts in a in order, i2: the match each came from
+    DBuf<uint64_t> flag, fpos;
+    flag.need(m, s);
+    fpos.need(m + 1, s);
+    k_mem_first<<<mem_grid(m), kMB, 0, s>>>(k1.p, pb.p, i2.p, m, flag.p);
+    HIP_CHECK(hipGetLastError());
+    ktmp.need(std::max<size_t>(scan_tmp_words(m), 1), s);
+    scan_exclusive(flag.p, fpos.p, m, ktmp.p, s);
+    const uint64_t count = read_dev(fpos.p + m, s);
+    if (cap) {
+      k_mem_out<<<mem_grid(m), kMB, 0, s>>>(k1.p, pb.p, ln.p, i2.p, flag.p, fpos.p, m, cap, d_pa,
+                                           d_pb, d_len);
+      HIP_CHECK(hipGetLastError());
+    }
+    sync(s);
+    *n_mems = count;
   });
 }
 

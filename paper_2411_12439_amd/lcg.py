@@ -36,7 +36,7 @@ EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_res
            "lcg_slp_expand_strings", "lcg_slp_free", "lcg_extract", "lcg_build_file", "lcg_lce",
            "lcg_slp_encode", "lcg_slp_decode", "lcg_symbol_lce", "lcg_set_allocator",
            "lcg_slp_extract", "lcg_export", "lcg_host_free", "lcg_session_new",
-           "lcg_session_admit", "lcg_session_step", "lcg_session_free")
+           "lcg_session_admit", "lcg_session_step", "lcg_session_free", "lcg_mems")
 
 EXTRACT_MAX = 2048
 
@@ -176,6 +176,10 @@ def lib():
     L.lcg_lce.restype = st
     L.lcg_symbol_lce.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, vp, ctypes.c_uint32, vp, vp]
     L.lcg_symbol_lce.restype = st
+    L.lcg_mems.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                           ctypes.c_uint64, ctypes.c_uint64, vp, vp, vp,
+                           ctypes.POINTER(ctypes.c_uint64), vp]
+    L.lcg_mems.restype = st
     L.lcg_export.argtypes = [vp, ctypes.POINTER(HostGrammar)]
     L.lcg_export.restype = st
     L.lcg_host_free.argtypes = [ctypes.POINTER(HostGrammar)]
@@ -403,6 +407,22 @@ class Grammar:
                                     ctypes.c_void_p(s2.data_ptr()), 1 if backward else 0,
                                     ctypes.c_void_p(out.data_ptr()), _stream(stream)))
         return out[:s1.numel()]
+
+    def mems(self, a, b, level, min_len, cap=1 << 16, stream=None):
+        """Maximal exact matches of at least min_len bytes between strings a and
+        b seeded by equal symbols of their level-``level`` parses (lcg_mems):
+        (start in a, start in b, length) as three int64 device tensors sorted
+        by start in a, then in b."""
+        import torch
+        n = ctypes.c_uint64()
+        while True:
+            out = [torch.empty(max(cap, 1), dtype=torch.int64, device="cuda") for _ in range(3)]
+            _check(lib().lcg_mems(self.h, a, b, level, min_len, cap,
+                                  *(ctypes.c_void_p(t.data_ptr()) for t in out), ctypes.byref(n),
+                                  _stream(stream)))
+            if n.value <= cap:
+                return tuple(t[:n.value] for t in out)
+            cap = n.value
 
     def postprocess(self, rl=True, simp=True, stream=None):
         """RL and/or Simp (Sec. 2.2) on the device: a new Slp (this grammar is unchanged)."""

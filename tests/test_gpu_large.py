@@ -11,10 +11,11 @@ after it and the last one (the 64-bit offset paths), and the shortest and
 longest strings; on the repeat-heavy collection whole 250 MB strings (the
 first and the last), whose 20 kb homopolymers and tandem repeats make the
 deepest equal-run cases; random substrings and longest common extensions
-match the input; and for the repeat-heavy collection the RL + Simp grammar
-decompresses to the input, also through its stored file, gives random
-substrings of the input from the decoded grammar, and keeps Simp's size
-identity.
+match the input; maximal exact matches between batched strings of one base
+equal the oracle's in the two strings alone; and for the repeat-heavy
+collection the RL + Simp grammar decompresses to the input, also through its
+stored file, gives random substrings of the input from the decoded grammar,
+and keeps Simp's size identity.
 """
 import numpy as np
 import pytest
@@ -114,6 +115,34 @@ def test_full_batched_strings_equal_oracle(batched):
     sample = [j32, j32 + 1, j32 + 2, k - 1, int(np.argmin(lens)), int(np.argmax(lens))]
     assert all(o[j] > (1 << 32) for j in sample[1:4])
     _strings_equal_oracle(e, text, off, sample)
+
+
+def test_full_batched_mems_equal_oracle(batched):
+    """Maximal exact matches between strings from one base (j and j + 32): the
+    string holding byte 2^32, the last string, and the first, each against the
+    oracle's matches in its build of the two strings alone -- by stability
+    (Def. 1) the parses, hence the matches in text positions, do not depend on
+    the other strings."""
+    from oracle import oracle as O
+    text, off, t, g, e = batched
+    o = off.astype(np.int64)
+    k = len(o) - 1
+    j32 = int(np.searchsorted(o, 1 << 32, side="right")) - 1
+    found = 0
+    for a, b in [(j32, j32 + 32), (k - 1, k - 33), (0, 32)]:
+        pair = [text[o[a]:o[a + 1]], text[o[b]:o[b + 1]]]
+        pt = np.concatenate(pair)
+        po = np.array([0, len(pair[0]), len(pt)], np.uint64)
+        print("oracle on strings %d and %d (%d + %d bytes)" % (a, b, len(pair[0]), len(pair[1])),
+              flush=True)
+        og = O.build(pt, po, SEED)
+        for level, min_len in [(2, 32), (3, 100)]:
+            pa, pb, ln = g.mems(a, b, level, min_len)
+            wa, wb, wl = og.mems(pt, po, 0, 1, level, min_len)
+            got = np.stack([x.cpu().numpy().astype(np.uint64) for x in (pa, pb, ln)])
+            assert np.array_equal(got, np.stack([wa, wb, wl])), (a, b, level)
+            found += got.shape[1]
+    assert found > 0
 
 
 def test_full_batched_random_access(L, batched):
