@@ -755,43 +755,49 @@ def extra_legs(args, out, text, off, t, o, n, k, seed):
     print("[bench] symbol lce: %.2f ms for %d queries" % (s_s * 1e3, 2 * ns), file=sys.stderr,
           flush=True)
     # maximal exact matches between two copies of a base through the grammar
-    # (App. B): 16 string pairs, level-2 anchors, at least 32 bytes; 200
-    # matches checked on the bytes (equal, and not extendable either way)
+    # (App. B): 16 string pairs, at least 32 bytes, anchors at level 3 and at
+    # level 2 (more anchors: frequent short symbols pair up quadratically, and
+    # more of the shorter matches are found); 13 matches per pair checked on
+    # the bytes (equal, and not extendable either way)
     mpairs = [(j, (j + 4) % k) for j in range(min(16, k))]
-    mlevel, mmin = 2, 32
-    res = [g.mems(a, b, mlevel, mmin) for a, b in mpairs]
-    nm = sum(int(r[0].numel()) for r in res)
-    mlen_sum = sum(int(r[2].sum()) for r in res)
-    chk = 0
-    for (a, b), (pa_t, pb_t, ln_t) in zip(mpairs, res):
-        sa, sb = string(a), string(b)
-        pa_h, pb_h, ln_h = (x.cpu().numpy() for x in (pa_t, pb_t, ln_t))
-        for t in np.linspace(0, len(pa_h) - 1, min(len(pa_h), 13)).astype(np.int64):
-            x, y, m = int(pa_h[t]), int(pb_h[t]), int(ln_h[t])
-            ok = (m >= mmin and sa[x:x + m] == sb[y:y + m]
-                  and (x == 0 or y == 0 or sa[x - 1] != sb[y - 1])
-                  and (x + m == len(sa) or y + m == len(sb) or sa[x + m] != sb[y + m]))
-            if not ok:
-                raise SystemExit("lcg_mems match %d of pair %d, %d is not maximal" % (t, a, b))
-            chk += 1
+    mmin = 32
     pair_bytes = sum(len(string(a)) + len(string(b)) for a, b in mpairs)
-    mts = []
-    for i in range(max(1, args.steps)):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for a, b in mpairs:
-            g.mems(a, b, mlevel, mmin)
-        torch.cuda.synchronize()
-        mts.append(time.perf_counter() - t0)
-    m_s = float(np.mean(mts))
+    mres = {}
+    chk = 0
+    for mlevel in (3, 2):
+        res = [g.mems(a, b, mlevel, mmin) for a, b in mpairs]
+        nm = sum(int(r[0].numel()) for r in res)
+        mlen_sum = sum(int(r[2].sum()) for r in res)
+        for (a, b), (pa_t, pb_t, ln_t) in zip(mpairs, res):
+            sa, sb = string(a), string(b)
+            pa_h, pb_h, ln_h = (x.cpu().numpy() for x in (pa_t, pb_t, ln_t))
+            for t in np.linspace(0, len(pa_h) - 1, min(len(pa_h), 13)).astype(np.int64):
+                x, y, m = int(pa_h[t]), int(pb_h[t]), int(ln_h[t])
+                ok = (m >= mmin and sa[x:x + m] == sb[y:y + m]
+                      and (x == 0 or y == 0 or sa[x - 1] != sb[y - 1])
+                      and (x + m == len(sa) or y + m == len(sb) or sa[x + m] != sb[y + m]))
+                if not ok:
+                    raise SystemExit("lcg_mems match %d of pair %d, %d is not maximal" % (t, a, b))
+                chk += 1
+        del res
+        mts = []
+        for i in range(max(1, args.steps)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for a, b in mpairs:
+                g.mems(a, b, mlevel, mmin)
+            torch.cuda.synchronize()
+            mts.append(time.perf_counter() - t0)
+        m_s = float(np.mean(mts))
+        mres[str(mlevel)] = {"ms": round(m_s * 1e3, 3), "matches": nm,
+                             "mean_match_bytes": round(mlen_sum / max(nm, 1), 1),
+                             "input_gbps": round(pair_bytes / m_s / 1e9, 3)}
+        print("[bench] mems level %d: %.2f ms for %d pairs, %d matches" %
+              (mlevel, m_s * 1e3, len(mpairs), nm), file=sys.stderr, flush=True)
     out["mems"] = {"what": "lcg_mems: maximal exact matches of >= 32 bytes between two copies of "
-                           "a base, level-2 anchors, %d string pairs (%d matches checked on the "
-                           "bytes)" % (len(mpairs), chk),
-                   "ms": round(m_s * 1e3, 3), "pairs": len(mpairs), "matches": nm,
-                   "mean_match_bytes": round(mlen_sum / max(nm, 1), 1),
-                   "input_gbps": round(pair_bytes / m_s / 1e9, 3)}
-    print("[bench] mems: %.2f ms for %d pairs, %d matches" % (m_s * 1e3, len(mpairs), nm),
-          file=sys.stderr, flush=True)
+                           "a base, %d string pairs, anchors at level 3 and level 2 (%d matches "
+                           "checked on the bytes)" % (len(mpairs), chk),
+                   "pairs": len(mpairs), "pair_bytes": pair_bytes, "by_level": mres}
     g.free()
     del out_t, offs_t
     out["expand"] = {"what": "lcg_expand_strings of all strings (decompression), output bytes/s",

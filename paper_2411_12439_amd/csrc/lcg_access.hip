@@ -384,8 +384,9 @@ __global__ __launch_bounds__(64) void k_symbol_lce(const LevelPtrs* __restrict__
 // Maximal exact matches between two strings through the grammar (App. B):
 // the level-l parses of both strings are the search space; equal symbols, one
 // in each parse, are anchors, and each is completed into the maximal run of
-// equal bytes on its diagonal by the two grammar walks above (the lcs before
-// the anchor, the lcp from it).  Only the first anchor of a run of
+// equal bytes on its diagonal (k_mem_extend: the lcs of the symbols before
+// the anchor, the lcp of the first different symbols after it, with the
+// cursor walks above).  Only the first anchor of a run of
 // consecutive anchors on one diagonal (the symbols before it differ) is
 // completed: the others lie inside the same match.
 constexpr int kMB = 256;
@@ -395,7 +396,16 @@ inline unsigned mem_grid(uint64_t n) {
   return (unsigned)std::min<uint64_t>((n + kMB - 1) / kMB, 16384);
 }
 
-__global__ __launch_bounds__(kMB) void k_mem_set(uint32_t* v, uint32_t y) { v[0] = y; }
+// the C entries (level, symbol) of strings a and b
+__global__ __launch_bounds__(kMB) void k_mem_centries(const uint8_t* __restrict__ c_level,
+                                                      const uint32_t* __restrict__ c_sym,
+                                                      uint32_t a, uint32_t b,
+                                                      uint32_t* __restrict__ out) {
+  out[0] = c_level[a];
+  out[1] = c_sym[a];
+  out[2] = c_level[b];
+  out[3] = c_sym[b];
+}
 
 // right-hand-side length of every symbol of a parse (levels >= 2)
 __global__ __launch_bounds__(kMB) void k_mem_rhslen(const uint64_t* __restrict__ off,
@@ -419,6 +429,65 @@ __global__ __launch_bounds__(kMB) void k_mem_children(const uint64_t* __restrict
     const uint32_t x = cur[i];
     uint64_t p = pos[i];
     for (uint64_t t = off[x], e = off[x + 1]; t < e; ++t) next[p++] = rhs[t];
+  }
+}
+
+// The parse of the upper levels, while it is small, in one block: from the
+// C entry (top, y) down towards `level`, the frontier alternating between two
+// global buffers of kMemTopCap entries, each thread holding kMemPer
+// consecutive entries (their rule offsets loaded together, so a level costs
+// one round of dependent loads); it stops at `level` or above the first level
+// whose parse would not fit.  res = {level reached, its parse length, 1 if
+// the parse is in buf1}.
+constexpr int kMPT = 1024;
+constexpr int kMemPer = 8;
+constexpr uint32_t kMemTopCap = kMPT * kMemPer;
+
+__global__ __launch_bounds__(kMPT) void k_mem_parse_top(const LevelPtrs* __restrict__ lv_ptr,
+                                                        int top, uint32_t y, int level,
+                                                        uint32_t* __restrict__ buf0,
+                                                        uint32_t* __restrict__ buf1,
+                                                        uint32_t* __restrict__ res) {
+  __shared__ uint64_t s_wave[kMPT / 64];
+  uint32_t* cur = buf0;
+  uint32_t* nxt = buf1;
+  if (threadIdx.x == 0) cur[0] = y;
+  __syncthreads();
+  uint32_t n = 1;
+  int l = top;
+  while (l > level) {
+    const LevelPtrs L = lv_ptr[l - 1];
+    const uint32_t* rhs = static_cast<const uint32_t*>(L.rhs);
+    const uint32_t i0 = threadIdx.x * kMemPer;
+    uint64_t a[kMemPer], e[kMemPer];
+    uint64_t part = 0;
+#pragma unroll
+    for (int r = 0; r < kMemPer; ++r) {
+      a[r] = e[r] = 0;
+      if (i0 + r < n) {
+        const uint32_t x = cur[i0 + r];
+        a[r] = L.off[x];
+        e[r] = L.off[x + 1];
+      }
+      part += e[r] - a[r];
+    }
+    uint64_t tot;
+    uint64_t p = block_excl_scan<uint64_t, kMPT>(part, s_wave, &tot);
+    if (tot > kMemTopCap) break;  // the same total in every thread
+#pragma unroll
+    for (int r = 0; r < kMemPer; ++r)
+      for (uint64_t t = a[r]; t < e[r]; ++t) nxt[p++] = rhs[t];
+    __syncthreads();  // the new frontier is read by other threads next
+    uint32_t* w = cur;
+    cur = nxt;
+    nxt = w;
+    n = (uint32_t)tot;
+    --l;
+  }
+  if (threadIdx.x == 0) {
+    res[0] = (uint32_t)l;
+    res[1] = n;
+    res[2] = cur == buf1;
   }
 }
 
@@ -486,18 +555,53 @@ __global__ __launch_bounds__(kMB) void k_mem_seeds(
   }
 }
 
-// the match through each seed: lcs before it, lcp from its first byte
+// The match through each seed, completed as App. B completes a match found
+// among symbols: forward, the equal symbols after the anchor in both parses
+// (at most kMemRun of them), then the lcp of the first different pair; backward,
+// the lcs of the two symbols before the anchor (they differ: the seed starts
+// its run).  Those walks start at the symbols and go `level` levels deep.  Only
+// when one expansion is a prefix (suffix) of the other does the match go on
+// past it, and the rest comes from the walk over the whole strings.
+constexpr int kMemRun = 64;
+
 __global__ __launch_bounds__(64) void k_mem_extend(
-    const LevelPtrs* __restrict__ lv_ptr, const uint64_t* const* __restrict__ explen, int ta,
-    uint32_t ya, uint64_t na, int tb, uint32_t yb, uint64_t nb, const uint64_t* __restrict__ sa,
-    const uint64_t* __restrict__ sb, const uint32_t* __restrict__ si,
-    const uint32_t* __restrict__ sj, uint64_t ns, uint64_t min_len, uint64_t* __restrict__ mpa,
-    uint64_t* __restrict__ mpb, uint64_t* __restrict__ mlen, uint64_t* __restrict__ keep) {
+    const LevelPtrs* __restrict__ lv_ptr, const uint64_t* const* __restrict__ explen, int level,
+    int ta, uint32_t ya, uint64_t la, int tb, uint32_t yb, uint64_t lb,
+    const uint32_t* __restrict__ A, uint64_t na, const uint64_t* __restrict__ sa,
+    const uint32_t* __restrict__ B, uint64_t nb, const uint64_t* __restrict__ sb,
+    const uint32_t* __restrict__ si, const uint32_t* __restrict__ sj, uint64_t ns,
+    uint64_t min_len, uint64_t* __restrict__ mpa, uint64_t* __restrict__ mpb,
+    uint64_t* __restrict__ mlen, uint64_t* __restrict__ keep) {
   for (uint64_t q = blockIdx.x * (uint64_t)64 + threadIdx.x; q < ns;
        q += (uint64_t)gridDim.x * 64) {
-    const uint64_t x = sa[si[q]], y = sb[sj[q]];
-    const uint64_t back = lce_walk<true>(lv_ptr, explen, ta, ya, x, na, tb, yb, y, nb);
-    const uint64_t fwd = lce_walk<false>(lv_ptr, explen, ta, ya, x, na, tb, yb, y, nb);
+    const uint64_t i = si[q], j = sj[q];
+    const uint64_t x = sa[i], y = sb[j];
+    uint64_t back = 0;
+    if (i > 0 && j > 0) {
+      const uint64_t nx = x - sa[i - 1], ny = y - sb[j - 1];
+      back = lce_walk<true>(lv_ptr, explen, level, A[i - 1], nx, nx, level, B[j - 1], ny, ny);
+      if (back == nx || back == ny)
+        back += lce_walk<true>(lv_ptr, explen, ta, ya, x - back, la, tb, yb, y - back, lb);
+    }
+    uint64_t ii = i + 1, jj = j + 1;
+    int run = 0;
+    while (ii < na && jj < nb && run < kMemRun && A[ii] == B[jj]) {
+      ++ii;
+      ++jj;
+      ++run;
+    }
+    uint64_t fwd = sa[ii] - x;
+    if (ii < na && jj < nb) {
+      bool rest = run == kMemRun;
+      if (!rest) {
+        const uint64_t nx = sa[ii + 1] - sa[ii], ny = sb[jj + 1] - sb[jj];
+        const uint64_t l1 = lce_walk<false>(lv_ptr, explen, level, A[ii], 0, nx, level, B[jj], 0, ny);
+        fwd += l1;
+        rest = l1 == nx || l1 == ny;
+      }
+      if (rest)
+        fwd += lce_walk<false>(lv_ptr, explen, ta, ya, x + fwd, la, tb, yb, y + fwd, lb);
+    }
     mpa[q] = x - back;
     mpb[q] = y - back;
     mlen[q] = back + fwd;
@@ -562,19 +666,33 @@ inline int bits_for(uint64_t v) {  // radix-sort key width that holds 0..v
 }
 
 // the level-`level` parse of a string whose C entry is (top, y): symbols in
-// cur[0..n), byte starts in starts[0..n] (starts[n] = the string's length)
+// cur[0..n), byte starts in starts[0..n] (starts[n] = the string's length).
+// The upper levels come from one block; each larger level takes a scan and a
+// read of its length.
 uint64_t mem_parse(lcg_grammar* g, int top, uint32_t y, uint32_t level, DBuf<uint32_t>& cur,
                    DBuf<uint64_t>& starts, DBuf<uint32_t>& idx, hipStream_t s) {
-  cur.need(1, s);
-  k_mem_set<<<1, 1, 0, s>>>(cur.p, y);
+  DBuf<uint32_t> t0, t1, res;
+  t0.need(kMemTopCap, s);
+  t1.need(kMemTopCap, s);
+  res.need(3, s);
+  k_mem_parse_top<<<1, kMPT, 0, s>>>(g->level_ptrs.p, top, y, (int)level, t0.p, t1.p, res.p);
   HIP_CHECK(hipGetLastError());
-  uint64_t n = 1;
+  uint32_t r[3];
+  HIP_CHECK(hipMemcpyAsync(r, res.p, sizeof(r), hipMemcpyDeviceToHost, s));
+  sync(s);
+  int l = (int)r[0];
+  uint64_t n = r[1];
+  const uint32_t* src = r[2] ? t1.p : t0.p;
   DBuf<uint32_t> next;
   DBuf<uint64_t> cnt, pos, tmp;
-  for (int l = top; l > (int)level; --l) {
+  if (l == (int)level) {
+    cur.need(n, s);
+    HIP_CHECK(hipMemcpyAsync(cur.p, src, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+  }
+  for (; l > (int)level; --l) {
     const Level& L = g->levels[l - 1];
     cnt.need(n, s);
-    k_mem_rhslen<<<mem_grid(n), kMB, 0, s>>>(L.off.p, cur.p, n, cnt.p);
+    k_mem_rhslen<<<mem_grid(n), kMB, 0, s>>>(L.off.p, src, n, cnt.p);
     HIP_CHECK(hipGetLastError());
     pos.need(n + 1, s);
     tmp.need(std::max<size_t>(scan_tmp_words(n), 1), s);
@@ -582,9 +700,10 @@ uint64_t mem_parse(lcg_grammar* g, int top, uint32_t y, uint32_t level, DBuf<uin
     const uint64_t m = read_dev(pos.p + n, s);
     if (m >= (1ull << 31)) throw LcgError{LCG_EOVERFLOW, "a parse of 2^31 symbols or more"};
     next.need(m, s);
-    k_mem_children<<<mem_grid(n), kMB, 0, s>>>(L.off.p, L.rhs32.p, cur.p, n, pos.p, next.p);
+    k_mem_children<<<mem_grid(n), kMB, 0, s>>>(L.off.p, L.rhs32.p, src, n, pos.p, next.p);
     HIP_CHECK(hipGetLastError());
     std::swap(cur, next);
+    src = cur.p;
     n = m;
   }
   cnt.need(n, s);
@@ -718,8 +837,15 @@ lcg_status lcg_mems(lcg_grammar_t g, uint32_t a, uint32_t b, uint32_t level, uin
     if (g->levels.size() >= (size_t)kMaxLv) throw LcgError{LCG_EOVERFLOW, "too many levels"};
     hipStream_t s = stream;
     ensure_explen(g, s);
-    const int ta = read_dev(g->c_level.p + a, s), tb = read_dev(g->c_level.p + b, s);
-    const uint32_t ya = read_dev(g->c_sym.p + a, s), yb = read_dev(g->c_sym.p + b, s);
+    DBuf<uint32_t> ce;
+    ce.need(4, s);
+    k_mem_centries<<<1, 1, 0, s>>>(g->c_level.p, g->c_sym.p, a, b, ce.p);
+    HIP_CHECK(hipGetLastError());
+    uint32_t cv[4];
+    HIP_CHECK(hipMemcpyAsync(cv, ce.p, sizeof(cv), hipMemcpyDeviceToHost, s));
+    sync(s);
+    const int ta = (int)cv[0], tb = (int)cv[2];
+    const uint32_t ya = cv[1], yb = cv[3];
     if (level < 1 || (int)level > std::min(ta, tb))
       throw LcgError{LCG_EINVAL, "level outside 1..min(level of C[a], level of C[b])"};
     DBuf<uint32_t> A, B, ia, ib;
@@ -773,8 +899,8 @@ lcg_status lcg_mems(lcg_grammar_t g, uint32_t a, uint32_t b, uint32_t level, uin
     mlen.need(ns, s);
     keep.need(ns, s);
     k_mem_extend<<<(unsigned)std::min<uint64_t>((ns + 63) / 64, 65536), 64, 0, s>>>(
-        g->level_ptrs.p, g->explen_ptrs.p, ta, ya, la, tb, yb, lb, sa.p, sb.p, si.p, sj.p, ns,
-        min_len, mpa.p, mpb.p, mlen.p, keep.p);
+        g->level_ptrs.p, g->explen_ptrs.p, (int)level, ta, ya, la, tb, yb, lb, A.p, na, sa.p, B.p,
+        nb, sb.p, si.p, sj.p, ns, min_len, mpa.p, mpb.p, mlen.p, keep.p);
     HIP_CHECK(hipGetLastError());
     kpos.need(ns + 1, s);
     ktmp.need(std::max<size_t>(scan_tmp_words(ns), 1), s);
