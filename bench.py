@@ -484,6 +484,28 @@ def main():
     roofline["frac_of_gather_ceiling"] = round(
         probe_rate / out["gather_ceiling"]["lookups_per_s_g"], 3)
 
+    if not args.no_extra:
+        # RL + Simp of this collection's grammar, against its build time
+        gh = lcg.build(t, o, seed=seed)
+        gh.postprocess().free()
+        hps = []
+        for i in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p = gh.postprocess()
+            torch.cuda.synchronize()
+            hps.append(time.perf_counter() - t0)
+            hst = [int(x) for x in p.stats()]
+            p.free()
+        gh.free()
+        h_ms = float(np.mean(hps)) * 1e3
+        out["postprocess_headline"] = {
+            "what": "lcg_postprocess (RL, then Simp) of this collection's grammar on the device",
+            "ms": round(h_ms, 3), "rules_in": hst[0], "size_in": hst[1], "rules_out": hst[6],
+            "size_out": hst[7], "vs_build_ms": round(h_ms / out["ms_per_step"], 4)}
+        print("[bench] postprocess of the %s grammar: %.2f ms (%.1f %% of a build)" %
+              (args.config, h_ms, 100 * h_ms / out["ms_per_step"]), file=sys.stderr, flush=True)
+
     if not args.no_plain:
         ps = time_plain(lcg, t, o, seed, args.plain_steps)
         plain = n / float(np.median(ps)) / 1e9

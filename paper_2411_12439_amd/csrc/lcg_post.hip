@@ -88,9 +88,9 @@ __global__ void k_pp_set(uint64_t* p, uint64_t v) { *p = v; }
 
 // ---------------------------------------------------------------- rule groups
 // Kernels that visit right-hand-side positions take groups of kGrp
-// consecutive rules per block: the group's offsets go to LDS, the block reads
-// the group's positions kGrp at a time (consecutive threads, consecutive
-// positions) and each position finds its rule by binary search in LDS.
+// consecutive rules per block (one thread per rule of the group): the
+// group's offsets go to LDS, the block reads the group's positions in tiles
+// (below) and each position finds its rule by binary search in LDS.
 constexpr uint32_t kGrp = 256;
 
 #define GROUP_LOOP(grp, ngroups) for (uint64_t grp = blockIdx.x; grp < (ngroups); grp += gridDim.x)
@@ -109,6 +109,40 @@ __device__ __forceinline__ uint32_t owner_in(const uint64_t* s_off, uint32_t n, 
     if (mid < n && s_off[mid] <= t) lo = mid;
   }
   return lo;
+}
+
+// A group's positions go in tiles of kTile: each thread takes kPer
+// consecutive positions, loads all of them before using any (the loads of a
+// tile are in flight together), and walks their owners forward from one
+// binary search.  Prefix sums over a tile come from one block scan of the
+// threads' totals.
+constexpr int kPer = 4;
+constexpr uint32_t kTile = kGrp * kPer;
+
+// A tile's right-hand-side symbols staged through LDS: loaded coalesced
+// (thread i takes base + i + kGrp * m, all kPer loads in flight), read back
+// kPer consecutive ones per thread.
+__device__ __forceinline__ void stage_tile(const uint32_t* __restrict__ rhs, uint64_t base,
+                                           uint64_t end, uint32_t* s_buf, uint32_t* y) {
+  uint32_t v[kPer];
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
+    const uint64_t t = base + threadIdx.x + (uint64_t)kGrp * m;
+    v[m] = t < end ? rhs[t] : 0;
+  }
+  __syncthreads();  // the previous tile's reads are done
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) s_buf[threadIdx.x + kGrp * m] = v[m];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) y[m] = s_buf[kPer * threadIdx.x + m];
+}
+
+// the owner of t >= s_off[j], from j forward
+__device__ __forceinline__ uint32_t owner_from(const uint64_t* s_off, uint32_t n, uint32_t j,
+                                               uint64_t t) {
+  while (j + 1 < n && s_off[j + 1] <= t) ++j;
+  return j;
 }
 
 __device__ __forceinline__ uint64_t lower_bound_u64(const uint64_t* a, uint64_t n, uint64_t key) {
@@ -145,9 +179,21 @@ __device__ __forceinline__ uint32_t sym_at(const PLevel& L, uint64_t t) {
                  : static_cast<const uint32_t*>(L.rhs)[t];
 }
 
-__device__ __forceinline__ uint32_t level_of_group(const PLevel* tab, uint32_t h, uint64_t grp) {
-  uint32_t lv = 0;
-  while (lv + 1 < h && tab[lv + 1].gpre <= grp) ++lv;
+// The level table in LDS (the kernels below read it once per group).
+__device__ __forceinline__ void load_tab(const PLevel* __restrict__ tab, uint32_t h,
+                                         PLevel* s_tab) {
+  static_assert(sizeof(PLevel) % 8 == 0, "PLevel is copied in 8-byte words");
+  const uint64_t* src = reinterpret_cast<const uint64_t*>(tab);
+  uint64_t* dst = reinterpret_cast<uint64_t*>(s_tab);
+  for (uint32_t i = threadIdx.x; i < h * (uint32_t)(sizeof(PLevel) / 8); i += blockDim.x)
+    dst[i] = src[i];
+  __syncthreads();
+}
+
+// the level of group grp, from lv forward (a block's groups only increase)
+__device__ __forceinline__ uint32_t level_of_group(const PLevel* s_tab, uint32_t h, uint32_t lv,
+                                                  uint64_t grp) {
+  while (lv + 1 < h && s_tab[lv + 1].gpre <= grp) ++lv;
   return lv;
 }
 
@@ -161,51 +207,78 @@ __device__ __forceinline__ uint32_t level_of_pos(const PLevel* tab, uint32_t h, 
 // symbol as the position before it; the repeated positions, in order, are the
 // list P that RL works from.
 
-// the block's repeat flags of one chunk of kGrp positions: *excl receives
-// the number of flagged threads before this one, the return value the
-// chunk's total (s_w: kGrp / 64 words of LDS)
-__device__ __forceinline__ uint32_t block_flag_scan(bool f, uint32_t* excl, uint32_t* s_w) {
-  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const uint64_t bal = __ballot(f);
-  if (lane == 0) s_w[wv] = (uint32_t)__builtin_popcountll(bal);
-  __syncthreads();
-  uint32_t before = 0, total = 0;
-  for (uint32_t w = 0; w < kGrp / 64; ++w) {
-    const uint32_t c = s_w[w];
-    before += w < wv ? c : 0;
-    total += c;
+// The symbols of positions t0 - 1 .. t0 + kPer of a level (0 outside it),
+// t0 = base + kPer * threadIdx.x: the tile's symbols staged through LDS
+// (coalesced loads, all in flight), the two outside the tile loaded once.
+__device__ __forceinline__ void load_window(const PLevel& L, uint64_t base, uint32_t* s_buf,
+                                            uint32_t* x) {
+  uint32_t v[kPer];
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
+    const uint64_t t = base + threadIdx.x + (uint64_t)kGrp * m;
+    v[m] = t < L.q ? sym_at(L, t) : 0;
   }
-  *excl = before + (uint32_t)__builtin_popcountll(bal & ((1ull << lane) - 1));
-  __syncthreads();  // s_w is rewritten by the next chunk
-  return total;
+  uint32_t edge = 0;
+  if (threadIdx.x == 0) edge = base >= 1 ? sym_at(L, base - 1) : 0;
+  if (threadIdx.x == kGrp - 1) edge = base + kTile < L.q ? sym_at(L, base + kTile) : 0;
+  __syncthreads();  // the previous tile's reads are done
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) s_buf[threadIdx.x + kGrp * m] = v[m];
+  __syncthreads();
+  const uint32_t i0 = kPer * threadIdx.x;
+  x[0] = threadIdx.x ? s_buf[i0 - 1] : edge;
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) x[m + 1] = s_buf[i0 + m];
+  x[kPer + 1] = threadIdx.x + 1 < kGrp ? s_buf[i0 + kPer] : edge;
 }
 
-__device__ __forceinline__ bool repeats_at(const PLevel& L, const uint64_t* s_off, uint32_t n,
-                                           uint64_t t, uint64_t b) {
-  if (t >= b) return false;
-  const uint32_t j = owner_in(s_off, n, t);
-  return t != s_off[j] && sym_at(L, t) == sym_at(L, t - 1);
+// repeat flags of a thread's positions of a tile; returns how many are set
+__device__ __forceinline__ uint32_t tile_repeats(const uint64_t* s_off, uint32_t n, uint64_t t0,
+                                                 uint64_t b, const uint32_t* x, bool* rep,
+                                                 uint32_t* jj) {
+  uint32_t j = t0 < b ? owner_in(s_off, n, t0) : 0, cnt = 0;
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
+    const uint64_t t = t0 + m;
+    rep[m] = false;
+    jj[m] = j;
+    if (t >= b) continue;
+    j = owner_from(s_off, n, j, t);
+    jj[m] = j;
+    rep[m] = t != s_off[j] && x[m + 1] == x[m];
+    cnt += rep[m];
+  }
+  return cnt;
 }
 
 // repeated positions of every rule group
 __global__ __launch_bounds__(kGrp) void k_pp_repcount(const PLevel* __restrict__ tab, uint32_t h,
                                                       uint64_t ngroups, uint64_t* __restrict__ gcnt) {
+  __shared__ uint32_t s_y[kTile];
   __shared__ uint64_t s_off[kGrp + 1];
   __shared__ uint32_t s_w[kGrp / 64];
+  __shared__ PLevel s_tab[64];
+  load_tab(tab, h, s_tab);
+  uint32_t lv = 0;
   GROUP_LOOP(grp, ngroups) {
-    const uint32_t lv = level_of_group(tab, h, grp);
-    const PLevel L = tab[lv];
+    lv = level_of_group(s_tab, h, lv, grp);
+    const PLevel L = s_tab[lv];
     const uint64_t r0 = (grp - L.gpre) * kGrp;
     const uint32_t n = (uint32_t)min<uint64_t>(kGrp, L.u - r0);
     load_offsets(L.off, r0, n, s_off);
     const uint64_t a = s_off[0], b = s_off[n];
-    uint64_t total = 0;
-    for (uint64_t base = a; base < b; base += kGrp) {
-      uint32_t excl;
-      total += block_flag_scan(repeats_at(L, s_off, n, base + threadIdx.x, b), &excl, s_w);
+    uint32_t mine = 0;
+    for (uint64_t base = a; base < b; base += kTile) {
+      const uint64_t t0 = base + kPer * threadIdx.x;
+      uint32_t x[kPer + 2], jj[kPer];
+      bool rep[kPer];
+      load_window(L, base, s_y, x);
+      mine += tile_repeats(s_off, n, t0, b, x, rep, jj);
     }
+    uint32_t total;
+    block_excl_scan<uint32_t, kGrp>(mine, s_w, &total);
     if (threadIdx.x == 0) gcnt[grp] = total;
-    __syncthreads();
+    __syncthreads();  // s_off is rewritten by the next group
   }
 }
 
@@ -213,24 +286,33 @@ __global__ __launch_bounds__(kGrp) void k_pp_repcount(const PLevel* __restrict__
 __global__ __launch_bounds__(kGrp) void k_pp_repwrite(const PLevel* __restrict__ tab, uint32_t h,
                                                       uint64_t ngroups, const uint64_t* __restrict__ gpos,
                                                       uint64_t* __restrict__ P) {
+  __shared__ uint32_t s_y[kTile];
   __shared__ uint64_t s_off[kGrp + 1];
   __shared__ uint32_t s_w[kGrp / 64];
+  __shared__ PLevel s_tab[64];
+  load_tab(tab, h, s_tab);
+  uint32_t lv = 0;
   GROUP_LOOP(grp, ngroups) {
     const uint64_t g0 = gpos[grp];
     if (gpos[grp + 1] == g0) continue;  // no repeats in the group (uniform)
-    const uint32_t lv = level_of_group(tab, h, grp);
-    const PLevel L = tab[lv];
+    lv = level_of_group(s_tab, h, lv, grp);
+    const PLevel L = s_tab[lv];
     const uint64_t r0 = (grp - L.gpre) * kGrp;
     const uint32_t n = (uint32_t)min<uint64_t>(kGrp, L.u - r0);
     load_offsets(L.off, r0, n, s_off);
     const uint64_t a = s_off[0], b = s_off[n];
     uint64_t done = g0;
-    for (uint64_t base = a; base < b; base += kGrp) {
-      const uint64_t t = base + threadIdx.x;
-      const bool rep = repeats_at(L, s_off, n, t, b);
-      uint32_t excl;
-      const uint32_t tot = block_flag_scan(rep, &excl, s_w);
-      if (rep) P[done + excl] = L.p0 + t;
+    for (uint64_t base = a; base < b; base += kTile) {
+      const uint64_t t0 = base + kPer * threadIdx.x;
+      uint32_t x[kPer + 2], jj[kPer];
+      bool rep[kPer];
+      load_window(L, base, s_y, x);
+      const uint32_t cnt = tile_repeats(s_off, n, t0, b, x, rep, jj);
+      uint32_t tot;
+      uint64_t o = done + block_excl_scan<uint32_t, kGrp>(cnt, s_w, &tot);
+#pragma unroll
+      for (int m = 0; m < kPer; ++m)
+        if (rep[m]) P[o++] = L.p0 + t0 + m;
       done += tot;
     }
     __syncthreads();
@@ -295,8 +377,8 @@ __global__ void k_pp_uniqlist(const uint32_t* __restrict__ lvl, const uint64_t* 
 // Every level's ordinary rules after RL: one symbol per maximal run (the run
 // rule's id for a run of length >= 2), the rules' offsets and multiplicities.
 // A group's repeated positions before a position come from gpos and the
-// block's flag prefix; only the first position of a run of length >= 2 looks
-// its length up in P.
+// tile's scan of repeat flags; the first position of a run of length >= 2
+// finds the run's entry in P from that count.
 __global__ __launch_bounds__(kGrp) void k_pp_rl_write(const PLevel* __restrict__ tab, uint32_t h,
                                                       uint64_t ngroups, const uint64_t* __restrict__ gpos,
                                                       const uint64_t* __restrict__ P, uint64_t c,
@@ -305,35 +387,52 @@ __global__ __launch_bounds__(kGrp) void k_pp_rl_write(const PLevel* __restrict__
                                                       uint32_t* __restrict__ rhs1,
                                                       uint64_t* __restrict__ off1,
                                                       uint32_t* __restrict__ mult1) {
+  __shared__ uint32_t s_y[kTile];
   __shared__ uint64_t s_off[kGrp + 1];
   __shared__ uint32_t s_w[kGrp / 64];
+  __shared__ PLevel s_tab[64];
+  load_tab(tab, h, s_tab);
+  uint32_t lv = 0;
   GROUP_LOOP(grp, ngroups) {
-    const uint32_t lv = level_of_group(tab, h, grp);
-    const PLevel L = tab[lv];
+    lv = level_of_group(s_tab, h, lv, grp);
+    const PLevel L = s_tab[lv];
     const uint64_t r0 = (grp - L.gpre) * kGrp;
     const uint32_t n = (uint32_t)min<uint64_t>(kGrp, L.u - r0);
     load_offsets(L.off, r0, n, s_off);
     const uint64_t a = s_off[0], b = s_off[n];
     const bool any = gpos[grp + 1] != gpos[grp];  // uniform
-    uint64_t done = gpos[grp] - L.cpre;           // the level's repeats before the chunk
-    for (uint64_t base = a; base < b; base += kGrp) {
-      const uint64_t t = base + threadIdx.x;
-      const bool valid = t < b;
-      const uint32_t j = valid ? owner_in(s_off, n, t) : 0;
-      bool rep = false;
-      uint32_t excl = 0, tot = 0;
+    uint64_t done = gpos[grp] - L.cpre;           // the level's repeats before the tile
+    for (uint64_t base = a; base < b; base += kTile) {
+      const uint64_t t0 = base + kPer * threadIdx.x;
+      uint32_t x[kPer + 2], jj[kPer];
+      bool rep[kPer];
+      load_window(L, base, s_y, x);
+      const uint32_t cnt = tile_repeats(s_off, n, t0, b, x, rep, jj);
+      uint32_t before = 0, tot = 0;
       if (any) {
-        rep = valid && t != s_off[j] && sym_at(L, t) == sym_at(L, t - 1);
-        tot = block_flag_scan(rep, &excl, s_w);
+        before = block_excl_scan<uint32_t, kGrp>(cnt, s_w, &tot);
+      } else {  // no repeats counted here (or RL is off): every position stays
+#pragma unroll
+        for (int m = 0; m < kPer; ++m) rep[m] = false;
       }
-      if (valid && !rep) {
-        const uint64_t out = L.out0 + t - (done + excl);
-        const uint32_t X = sym_at(L, t);
+      uint64_t gone = done + before;
+#pragma unroll
+      for (int m = 0; m < kPer; ++m) {
+        const uint64_t t = t0 + m;
+        if (t >= b) break;
+        if (rep[m]) {
+          ++gone;
+          continue;
+        }
+        const uint64_t out = L.out0 + t - gone;
+        const uint32_t X = x[m + 1];
+        const uint32_t j = jj[m];
         uint32_t id = L.symbase + X;
-        // the next position repeats: x starts a run of length >= 2
-        if (c && t + 1 < s_off[j + 1] && sym_at(L, t + 1) == X) {
-          const uint64_t lb = lower_bound_u64(P, c, L.p0 + t + 1);
-          const uint64_t key = ((uint64_t)X << 32) | rlen[lb];
+        // the next position repeats: t starts a run of length >= 2
+        if (c && t + 1 < s_off[j + 1] && x[m + 2] == X) {
+          // t + 1 is the next repeated position: its entry in P follows the
+          // level's and the group's repeats before it
+          const uint64_t key = ((uint64_t)X << 32) | rlen[L.cpre + gone];
           id = L.rlbase + (uint32_t)lower_bound_u64(ukey + L.upre, L.v, key);
         }
         rhs1[out] = id;
@@ -375,17 +474,38 @@ __global__ void k_pp_c_global(const uint8_t* __restrict__ cl, const uint32_t* __
 }
 
 // ---------------------------------------------------------------- Simp
-constexpr uint64_t kRemoved = 1ull << 63;
+// Occurrence counts matter only up to 2.  They are counted per rule (occ:
+// +1 in an ordinary rule, +2 in a run rule or C), then folded into a 2-bit
+// field per rule, 16 to a 32-bit word: bit A (the low one) for exactly one
+// ordinary occurrence, bit B for a rule kept for good (two or more, a run
+// rule's symbol, a C entry, or a run rule itself).  A rule is removed by Simp
+// exactly when its field is A alone.  Each word is stored with the number of
+// removed rules in the words before it (rk: fields in the low 32 bits, that
+// count in the high ones), so a kept rule's new id is one 8-byte read of a
+// small array (4 bits per rule) and a popcount.
+__device__ __forceinline__ uint32_t rm_bits(uint32_t f) { return f & 0x55555555u & ~(f >> 1); }
+
+__device__ __forceinline__ bool pp_rm(const uint64_t* __restrict__ rk, uint32_t z) {
+  return (rm_bits((uint32_t)rk[z >> 4]) >> (2 * (z & 15))) & 1;
+}
+
+// 256 + the kept rules before z: the new id of a kept rule z, and for any
+// z <= g1 the first new id at or after it
+__device__ __forceinline__ uint32_t pp_newid(const uint64_t* __restrict__ rk, uint32_t z) {
+  const uint64_t w = rk[z >> 4];
+  const uint32_t below = rm_bits((uint32_t)w) & ((1u << (2 * (z & 15))) - 1);
+  return 256 + z - ((uint32_t)(w >> 32) + (uint32_t)__builtin_popcount(below));
+}
 
 // Occurrences over the right-hand sides: +1 in an ordinary rule, +2 in a run
 // rule (which pins the symbol).  Counts stop mattering at 2.  The first
-// ordinary occurrence records its rule and position; it is the only one when
-// the count ends at 1.
+// ordinary occurrence records its rule; it is the only one when the count
+// ends at 1.  One position per thread and pass (consecutive threads,
+// consecutive positions): the tiles above measured slower here.
 __global__ __launch_bounds__(kGrp) void k_pp_occ(const uint64_t* __restrict__ off1,
                                                  const uint32_t* __restrict__ rhs1,
                                                  const uint32_t* __restrict__ mult1, uint32_t g1,
-                                                 uint32_t* occ, uint32_t* __restrict__ par,
-                                                 uint64_t* __restrict__ at) {
+                                                 uint32_t* occ, uint32_t* __restrict__ par) {
   __shared__ uint64_t s_off[kGrp + 1];
   __shared__ uint8_t s_run[kGrp];
   const uint64_t ngroups = (g1 + kGrp - 1) / kGrp;
@@ -405,7 +525,6 @@ __global__ __launch_bounds__(kGrp) void k_pp_occ(const uint64_t* __restrict__ of
         atomicAdd(&occ[z], 2u);
       } else if (atomicAdd(&occ[z], 1u) == 0) {
         par[z] = (uint32_t)(r0 + j);
-        at[z] = t;
       }
     }
     __syncthreads();
@@ -416,137 +535,199 @@ __global__ void k_pp_occ_c(const uint32_t* __restrict__ c1, uint32_t k, uint32_t
   PP_LOOP(j, k) if (c1[j] >= 256) atomicAdd(&occ[c1[j] - 256], 2u);
 }
 
-__device__ __forceinline__ bool pp_removed(const uint32_t* mult1, const uint32_t* occ, uint32_t z) {
-  return mult1[z] == 1 && occ[z] == 1;
+// the fields of 16 rules per word from the counts, and the removed rules per
+// word, for the scan that rk stores
+__global__ void k_pp_fields(const uint32_t* __restrict__ occ, const uint32_t* __restrict__ mult1,
+                            uint32_t g1, uint64_t nwords, uint32_t* __restrict__ oc2,
+                            uint64_t* __restrict__ cnt) {
+  PP_LOOP(w, nwords) {
+    uint32_t f = 0;
+    for (uint32_t i = 0; i < 16; ++i) {
+      const uint64_t r = w * 16 + i;
+      if (r >= g1) break;
+      const uint32_t o = occ[r];
+      const uint32_t v = (mult1[r] >= 2 || o >= 2) ? 2u : (o == 1 ? 1u : 0u);
+      f |= v << (2 * i);
+    }
+    oc2[w] = f;
+    cnt[w] = (uint64_t)__builtin_popcount(rm_bits(f));
+  }
 }
 
-// flattened length W of the ordinary rules [rb, re) (one level; the levels
-// below are done): a kept symbol counts 1, a removed one its W
+// rk[w] = removed rules before word w << 32 | the word's fields (w <= nwords)
+__global__ void k_pp_pack(const uint32_t* __restrict__ oc2, const uint64_t* __restrict__ pre,
+                          uint64_t nwords, uint64_t* __restrict__ rk) {
+  PP_LOOP(w, nwords + 1) rk[w] = (pre[w] << 32) | (w < nwords ? oc2[w] : 0u);
+}
+
+// The weights of a tile's positions (1 for a terminal or a kept symbol, the
+// flattened length W of a removed one), their prefix within the group
+// (carry: the tiles before), and the prefix at every rule's first position
+// (s_rs).  On return
+// ex[m] is the weight before position t0 + m in the group, jj[m] its rule;
+// after the block barrier that follows, ex[m] - s_rs[jj[m]] is its offset
+// inside the rule.
+__device__ __forceinline__ void tile_prefix(const uint64_t* s_off, uint32_t n, uint64_t t0,
+                                            uint64_t b, const uint64_t* w, uint64_t carry,
+                                            uint64_t* s_rs, uint64_t* s_w, uint64_t* ex,
+                                            uint32_t* jj, uint64_t* tot) {
+  uint64_t sum = 0;
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) sum += w[m];
+  uint64_t e = carry + block_excl_scan<uint64_t, kGrp>(sum, s_w, tot);
+  uint32_t j = t0 < b ? owner_in(s_off, n, t0) : 0;
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
+    const uint64_t t = t0 + m;
+    ex[m] = e;
+    jj[m] = j;
+    if (t >= b) continue;
+    j = owner_from(s_off, n, j, t);
+    jj[m] = j;
+    if (t == s_off[j]) s_rs[j] = e;
+    e += w[m];
+  }
+}
+
+// Flattened length W of the ordinary rules [rb, re) of one level (the levels
+// below are done) and, for every removed symbol they hold, its offset inside
+// the holding rule (inoff).
 __global__ __launch_bounds__(kGrp) void k_pp_flat(const uint64_t* __restrict__ off1,
                                                   const uint32_t* __restrict__ rhs1,
-                                                  const uint32_t* __restrict__ mult1,
-                                                  const uint32_t* __restrict__ occ, uint32_t rb,
-                                                  uint32_t re, uint64_t* W) {
+                                                  const uint64_t* __restrict__ rk, uint32_t rb,
+                                                  uint32_t re, uint64_t* W,
+                                                  uint64_t* __restrict__ inoff) {
+  __shared__ uint32_t s_y[kTile];
   __shared__ uint64_t s_off[kGrp + 1];
-  __shared__ unsigned long long s_acc[kGrp];
+  __shared__ uint64_t s_rs[kGrp + 1];
+  __shared__ uint64_t s_w[kGrp / 64];
   const uint64_t ngroups = (re - rb + kGrp - 1) / kGrp;
   GROUP_LOOP(grp, ngroups) {
     const uint64_t r0 = rb + grp * kGrp;
     const uint32_t n = (uint32_t)min<uint64_t>(kGrp, re - r0);
-    s_acc[threadIdx.x] = 0;
     load_offsets(off1, r0, n, s_off);
     const uint64_t a = s_off[0], b = s_off[n];
-    for (uint64_t t = a + threadIdx.x; t < b; t += kGrp) {
-      const uint32_t y = rhs1[t];
-      const uint64_t w = (y >= 256 && pp_removed(mult1, occ, y - 256)) ? W[y - 256] : 1;
-      atomicAdd(&s_acc[owner_in(s_off, n, t)], (unsigned long long)w);
+    uint64_t carry = 0;
+    for (uint64_t base = a; base < b; base += kTile) {
+      const uint64_t t0 = base + kPer * threadIdx.x;
+      uint32_t y[kPer];
+      stage_tile(rhs1, base, b, s_y, y);
+      uint64_t w[kPer];
+      bool rem[kPer];
+#pragma unroll
+      for (int m = 0; m < kPer; ++m) {
+        const bool valid = t0 + m < b;
+        rem[m] = valid && y[m] >= 256 && pp_rm(rk, y[m] - 256);
+        w[m] = rem[m] ? W[y[m] - 256] : (valid ? 1 : 0);
+      }
+      uint64_t ex[kPer], tot;
+      uint32_t jj[kPer];
+      tile_prefix(s_off, n, t0, b, w, carry, s_rs, s_w, ex, jj, &tot);
+      __syncthreads();  // s_rs of the rules starting in this tile
+#pragma unroll
+      for (int m = 0; m < kPer; ++m)
+        if (rem[m]) inoff[y[m] - 256] = ex[m] - s_rs[jj[m]];
+      carry += tot;
     }
+    if (threadIdx.x == 0) s_rs[n] = carry;
     __syncthreads();
-    if (threadIdx.x < n) W[r0 + threadIdx.x] = s_acc[threadIdx.x];
-    __syncthreads();
+    if (threadIdx.x < n) W[r0 + threadIdx.x] = s_rs[threadIdx.x + 1] - s_rs[threadIdx.x];
+    __syncthreads();  // s_off and s_rs are rewritten by the next group
   }
 }
 
-// kept flag and output length of every rule
-__global__ void k_pp_keep(const uint32_t* __restrict__ mult1, const uint32_t* __restrict__ occ,
-                          const uint64_t* __restrict__ W, uint32_t g1, uint64_t* __restrict__ kf,
-                          uint64_t* __restrict__ len) {
-  PP_LOOP(r, g1) {
-    const bool run = mult1[r] >= 2;
-    const bool keep = run || occ[r] != 1;
-    kf[r] = keep ? 1 : 0;
-    len[r] = keep ? (run ? 1 : W[r]) : 0;
-  }
-}
-
-// per rule: its new id (kept) or kRemoved | W (removed)
-__global__ void k_pp_nw(const uint64_t* __restrict__ kf, const uint64_t* __restrict__ nidx,
-                        const uint64_t* __restrict__ W, uint32_t g1, uint64_t* __restrict__ nw) {
-  PP_LOOP(r, g1) nw[r] = kf[r] ? 256 + nidx[r] : (kRemoved | W[r]);
-}
-
-// weight of every position: 1 for a kept symbol, the flattened length of a removed one
-__global__ void k_pp_weights(const uint32_t* __restrict__ rhs1, uint64_t q1,
-                             const uint64_t* __restrict__ nw, uint64_t* __restrict__ wg) {
-  PP_LOOP(t, q1) {
-    const uint32_t y = rhs1[t];
-    uint64_t w = 1;
-    if (y >= 256) {
-      const uint64_t v = nw[y - 256];
-      if (v & kRemoved) w = v & ~kRemoved;
-    }
-    wg[t] = w;
-  }
+// output length of every rule: 0 removed, 1 for a run rule, W otherwise
+__global__ void k_pp_len(const uint64_t* __restrict__ rk, const uint32_t* __restrict__ mult1,
+                         const uint64_t* __restrict__ W, uint32_t g1, uint64_t* __restrict__ len) {
+  PP_LOOP(r, g1) len[r] = pp_rm(rk, (uint32_t)r) ? 0 : (mult1[r] >= 2 ? 1 : W[r]);
 }
 
 // where the removed rules of [rb, re) land in the output (upper levels done):
 // the output position of the holder plus the weights before the occurrence
-__global__ void k_pp_base(const uint64_t* __restrict__ off1, const uint64_t* __restrict__ nw,
-                          const uint32_t* __restrict__ par, const uint64_t* __restrict__ at,
-                          const uint64_t* __restrict__ sw, const uint64_t* __restrict__ so,
+__global__ void k_pp_base(const uint64_t* __restrict__ rk, const uint32_t* __restrict__ par,
+                          const uint64_t* __restrict__ inoff, const uint64_t* __restrict__ so,
                           uint32_t rb, uint32_t re, uint64_t* base) {
   PP_LOOP(i, re - rb) {
     const uint32_t r = rb + (uint32_t)i;
-    if (!(nw[r] & kRemoved)) continue;
+    if (!pp_rm(rk, r)) continue;
     const uint32_t p = par[r];
-    const uint64_t dp = (nw[p] & kRemoved) ? base[p] : so[p];
-    base[r] = dp + sw[at[r]] - sw[off1[p]];
+    const uint64_t dp = pp_rm(rk, p) ? base[p] : so[p];
+    base[r] = dp + inoff[r];
   }
 }
 
-// every kept symbol of every rule at its output position; kept rules'
-// offsets and multiplicities
+// every kept symbol of every rule at its output position (the rule's, plus
+// the weights before the symbol inside the rule); kept rules' offsets and
+// multiplicities
 __global__ __launch_bounds__(kGrp) void k_pp_write(const uint64_t* __restrict__ off1,
                                                    const uint32_t* __restrict__ rhs1,
                                                    const uint32_t* __restrict__ mult1,
-                                                   const uint64_t* __restrict__ nw,
+                                                   const uint64_t* __restrict__ rk,
+                                                   const uint64_t* __restrict__ W,
                                                    const uint64_t* __restrict__ so,
-                                                   const uint64_t* __restrict__ base,
-                                                   const uint64_t* __restrict__ sw, uint32_t g1,
+                                                   const uint64_t* __restrict__ base, uint32_t g1,
                                                    uint32_t* __restrict__ rhs2,
                                                    uint64_t* __restrict__ off2,
                                                    uint32_t* __restrict__ mult2) {
+  __shared__ uint32_t s_y[kTile];
   __shared__ uint64_t s_off[kGrp + 1];
-  __shared__ uint64_t s_dest[kGrp];  // output position of the rule's first symbol, minus its sw
+  __shared__ uint64_t s_rs[kGrp + 1];
+  __shared__ uint64_t s_dest[kGrp];  // output position of the rule's first symbol
+  __shared__ uint64_t s_w[kGrp / 64];
   const uint64_t ngroups = (g1 + kGrp - 1) / kGrp;
   GROUP_LOOP(grp, ngroups) {
     const uint64_t r0 = grp * kGrp;
     const uint32_t n = (uint32_t)min<uint64_t>(kGrp, g1 - r0);
     if (threadIdx.x < n) {
-      const uint64_t r = r0 + threadIdx.x;
-      const uint64_t v = nw[r];
-      const bool keep = !(v & kRemoved);
-      s_dest[threadIdx.x] = (keep ? so[r] : base[r]) - sw[off1[r]];
+      const uint32_t r = (uint32_t)(r0 + threadIdx.x);
+      const bool keep = !pp_rm(rk, r);
+      s_dest[threadIdx.x] = keep ? so[r] : base[r];
       if (keep) {
-        off2[v - 256] = so[r];
-        mult2[v - 256] = mult1[r];
+        const uint32_t id = pp_newid(rk, r) - 256;
+        off2[id] = so[r];
+        mult2[id] = mult1[r];
       }
     }
     load_offsets(off1, r0, n, s_off);
     const uint64_t a = s_off[0], b = s_off[n];
-    for (uint64_t t = a + threadIdx.x; t < b; t += kGrp) {
-      const uint32_t y = rhs1[t];
-      uint32_t id = y;
-      if (y >= 256) {
-        const uint64_t v = nw[y - 256];
-        if (v & kRemoved) continue;
-        id = (uint32_t)v;
+    uint64_t carry = 0;
+    for (uint64_t base0 = a; base0 < b; base0 += kTile) {
+      const uint64_t t0 = base0 + kPer * threadIdx.x;
+      uint32_t y[kPer];
+      stage_tile(rhs1, base0, b, s_y, y);
+      uint64_t w[kPer];
+      bool rem[kPer];
+#pragma unroll
+      for (int m = 0; m < kPer; ++m) {
+        const bool valid = t0 + m < b;
+        rem[m] = valid && y[m] >= 256 && pp_rm(rk, y[m] - 256);
+        w[m] = rem[m] ? W[y[m] - 256] : (valid ? 1 : 0);
       }
-      rhs2[s_dest[owner_in(s_off, n, t)] + sw[t]] = id;
+      uint64_t ex[kPer], tot;
+      uint32_t jj[kPer];
+      tile_prefix(s_off, n, t0, b, w, carry, s_rs, s_w, ex, jj, &tot);
+      __syncthreads();  // s_rs of the rules starting in this tile
+#pragma unroll
+      for (int m = 0; m < kPer; ++m) {
+        if (t0 + m >= b || rem[m]) continue;
+        const uint32_t id = y[m] < 256 ? y[m] : pp_newid(rk, y[m] - 256);
+        rhs2[s_dest[jj[m]] + ex[m] - s_rs[jj[m]]] = id;
+      }
+      carry += tot;
     }
     __syncthreads();
   }
 }
 
 __global__ void k_pp_c_out(const uint32_t* __restrict__ c1, uint32_t k,
-                           const uint64_t* __restrict__ nw, uint32_t* __restrict__ c2) {
-  PP_LOOP(j, k) c2[j] = c1[j] < 256 ? c1[j] : (uint32_t)nw[c1[j] - 256];
+                           const uint64_t* __restrict__ rk, uint32_t* __restrict__ c2) {
+  PP_LOOP(j, k) c2[j] = c1[j] < 256 ? c1[j] : pp_newid(rk, c1[j] - 256);
 }
 
-// out[i] = a[ids[i] - 256]
-__global__ void k_pp_gather(const uint64_t* __restrict__ a, const uint32_t* __restrict__ ids,
-                            uint32_t n, uint64_t* __restrict__ out) {
-  PP_LOOP(i, n) out[i] = a[ids[i] - 256];
+// new ids of the block bounds (ids 256 .. 256 + g1 of the RL grammar)
+__global__ void k_pp_bounds(const uint64_t* __restrict__ rk, const uint32_t* __restrict__ ids,
+                            uint32_t n, uint32_t* __restrict__ out) {
+  PP_LOOP(i, n) out[i] = pp_newid(rk, ids[i] - 256);
 }
 
 // ---------------------------------------------------------------- expansion
@@ -1209,68 +1390,67 @@ static lcg_slp* postprocess_core(lcg_grammar* g, uint32_t flags, hipStream_t s) 
   }
 
   // ---- Simp
-  DBuf<uint32_t> occ, par;
-  DBuf<uint64_t> at, W, kf, nidx, len, so, nw, wg, sw, base;
+  DBuf<uint32_t> occ, oc2, par;
+  DBuf<uint64_t> rk, cnt, pre, W, inoff, len, so, base;
   const uint32_t g1c = std::max<uint32_t>(g1, 1);
+  const uint64_t nwords = ((uint64_t)g1 + 15) / 16;
   occ.need(g1c, s);
   zero(occ.p, (size_t)g1 * 4, s);
   par.need(g1c, s);
-  at.need(g1c, s);
   const uint64_t ng1 = (g1 + kGrp - 1) / kGrp;
   if (g1) {
-    k_pp_occ<<<groups_grid(ng1), kGrp, 0, s>>>(off1.p, rhs1.p, mult1.p, g1, occ.p, par.p, at.p);
+    k_pp_occ<<<groups_grid(ng1), kGrp, 0, s>>>(off1.p, rhs1.p, mult1.p, g1, occ.p, par.p);
     PP_CHECK("pp_occ");
   }
   k_pp_occ_c<<<pgrid(g->k), kPB, 0, s>>>(c1.p, g->k, occ.p);
   PP_CHECK("pp_occ_c");
+  Scan sc;
+  oc2.need(std::max<uint64_t>(nwords, 1), s);
+  cnt.need(std::max<uint64_t>(nwords, 1), s);
+  pre.need(nwords + 1, s);
+  k_pp_fields<<<pgrid(nwords), kPB, 0, s>>>(occ.p, mult1.p, g1, nwords, oc2.p, cnt.p);
+  PP_CHECK("pp_fields");
+  sc.run(cnt.p, pre.p, nwords, s);
+  rk.need(nwords + 1, s);
+  k_pp_pack<<<pgrid(nwords + 1), kPB, 0, s>>>(oc2.p, pre.p, nwords, rk.p);
+  PP_CHECK("pp_pack");
   W.need(g1c, s);
+  inoff.need(g1c, s);
   for (uint32_t i = 0; i < h; ++i) {
     const uint32_t u = tab[i].u;
     if (!u) continue;
     const uint32_t rb = tab[i].obase - 256;
-    k_pp_flat<<<groups_grid((u + kGrp - 1) / kGrp), kGrp, 0, s>>>(off1.p, rhs1.p, mult1.p, occ.p,
-                                                                    rb, rb + u, W.p);
+    k_pp_flat<<<groups_grid((u + kGrp - 1) / kGrp), kGrp, 0, s>>>(off1.p, rhs1.p, rk.p, rb, rb + u,
+                                                                    W.p, inoff.p);
     PP_CHECK("pp_flat");
   }
-  kf.need(g1c, s);
   len.need(g1c, s);
-  nidx.need(g1 + 1, s);
   so.need(g1 + 1, s);
-  k_pp_keep<<<pgrid(g1), kPB, 0, s>>>(mult1.p, occ.p, W.p, g1, kf.p, len.p);
-  PP_CHECK("pp_keep");
-  Scan sc;
-  sc.run(kf.p, nidx.p, g1, s);
+  k_pp_len<<<pgrid(g1), kPB, 0, s>>>(rk.p, mult1.p, W.p, g1, len.p);
+  PP_CHECK("pp_len");
   sc.run(len.p, so.p, g1, s);
-  nw.need(g1c, s);
-  k_pp_nw<<<pgrid(g1), kPB, 0, s>>>(kf.p, nidx.p, W.p, g1, nw.p);
-  PP_CHECK("pp_nw");
-  wg.need(std::max<uint64_t>(q1, 1), s);
-  sw.need(q1 + 1, s);
-  k_pp_weights<<<pgrid(q1), kPB, 0, s>>>(rhs1.p, q1, nw.p, wg.p);
-  PP_CHECK("pp_weights");
-  sc.run(wg.p, sw.p, q1, s);
   base.need(g1c, s);
   for (uint32_t i = h; i-- > 0;) {
     const uint32_t u = tab[i].u;
     if (!u) continue;
     const uint32_t rb = tab[i].obase - 256;
-    k_pp_base<<<pgrid(u), kPB, 0, s>>>(off1.p, nw.p, par.p, at.p, sw.p, so.p, rb, rb + u, base.p);
+    k_pp_base<<<pgrid(u), kPB, 0, s>>>(rk.p, par.p, inoff.p, so.p, rb, rb + u, base.p);
     PP_CHECK("pp_base");
   }
-  uint64_t g2 = 0, q2 = 0;
-  read_many<uint64_t>({{nidx.p + g1, &g2}, {so.p + g1, &q2}}, s);
+  uint64_t removed = 0, q2 = 0;
+  read_many<uint64_t>({{pre.p + nwords, &removed}, {so.p + g1, &q2}}, s);
+  const uint64_t g2 = g1 - removed;
   {  // block bounds after renumbering: the kept rules before each bound
-    DBuf<uint32_t> bq;
-    DBuf<uint64_t> bv;
+    DBuf<uint32_t> bq, bv;
     bq.need(bounds1.size(), s);
     bv.need(bounds1.size(), s);
     HIP_CHECK(hipMemcpyAsync(bq.p, bounds1.data(), bounds1.size() * 4, hipMemcpyHostToDevice, s));
-    k_pp_gather<<<pgrid(bounds1.size()), kPB, 0, s>>>(nidx.p, bq.p, (uint32_t)bounds1.size(), bv.p);
-    PP_CHECK("pp_gather");
-    std::vector<uint64_t> hb(bounds1.size());
-    HIP_CHECK(hipMemcpyAsync(hb.data(), bv.p, hb.size() * 8, hipMemcpyDeviceToHost, s));
+    k_pp_bounds<<<pgrid(bounds1.size()), kPB, 0, s>>>(rk.p, bq.p, (uint32_t)bounds1.size(), bv.p);
+    PP_CHECK("pp_bounds");
+    std::vector<uint32_t> hb(bounds1.size());
+    HIP_CHECK(hipMemcpyAsync(hb.data(), bv.p, hb.size() * 4, hipMemcpyDeviceToHost, s));
     sync(s);
-    for (uint64_t v : hb) out->bounds.push_back(256 + (uint32_t)v);
+    for (uint32_t v : hb) out->bounds.push_back(v);
   }
   out->g = (uint32_t)g2;
   out->q = q2;
@@ -1279,13 +1459,13 @@ static lcg_slp* postprocess_core(lcg_grammar* g, uint32_t flags, hipStream_t s) 
   out->mult.need(std::max<uint64_t>(g2, 1), s);
   out->c.need(std::max<uint32_t>(g->k, 1), s);
   if (g1) {
-    k_pp_write<<<groups_grid(ng1), kGrp, 0, s>>>(off1.p, rhs1.p, mult1.p, nw.p, so.p, base.p, sw.p,
+    k_pp_write<<<groups_grid(ng1), kGrp, 0, s>>>(off1.p, rhs1.p, mult1.p, rk.p, W.p, so.p, base.p,
                                                  g1, out->rhs.p, out->off.p, out->mult.p);
     PP_CHECK("pp_write");
   }
   k_pp_set<<<1, 1, 0, s>>>(out->off.p + g2, q2);
   PP_CHECK("pp_set");
-  k_pp_c_out<<<pgrid(g->k), kPB, 0, s>>>(c1.p, g->k, nw.p, out->c.p);
+  k_pp_c_out<<<pgrid(g->k), kPB, 0, s>>>(c1.p, g->k, rk.p, out->c.p);
   PP_CHECK("pp_c_out");
   st[5] = g1 - g2;
   st[6] = g2;
