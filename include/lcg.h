@@ -364,6 +364,21 @@ lcg_status lcg_symbol_lce(lcg_grammar_t g, uint32_t nq, const uint8_t* d_lv1, co
 lcg_status lcg_mems(lcg_grammar_t g, uint32_t a, uint32_t b, uint32_t level, uint64_t min_len,
                     uint64_t cap, uint64_t* d_pa, uint64_t* d_pb, uint64_t* d_len,
                     uint64_t* n_mems, hipStream_t stream);
+/*
+ * lcg_mems for many pairs in one call: pair p is (a[p], b[p]) (host arrays
+ * of npairs string indexes; a pair may repeat, and a string may appear in
+ * several pairs and on both sides).  Each pair's matches are exactly what
+ * lcg_mems gives for it; all of them come out sorted by (pair, start in a,
+ * start in b), with d_pair[t] (uint32 device array) naming the pair.  The
+ * parses of all the strings are made together and every later step runs
+ * over all pairs at once, so a batch costs little more than its largest pair.
+ * cap, *n_mems and the errors as for lcg_mems; also LCG_EINVAL for NULL pair
+ * arrays or 2^23 pairs or more.
+ */
+lcg_status lcg_mems_batch(lcg_grammar_t g, uint32_t npairs, const uint32_t* a, const uint32_t* b,
+                          uint32_t level, uint64_t min_len, uint64_t cap, uint32_t* d_pair,
+                          uint64_t* d_pa, uint64_t* d_pb, uint64_t* d_len, uint64_t* n_mems,
+                          hipStream_t stream);
 
 /* An empty grammar with hash family `seed` (no levels, no strings). */
 lcg_status lcg_new(uint64_t seed, lcg_grammar_t* out);

@@ -9,6 +9,9 @@
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
+#include <unordered_map>
+#include <vector>
+
 #include "lcg_host.h"
 
 namespace lcg {
@@ -381,14 +384,17 @@ __global__ __launch_bounds__(64) void k_symbol_lce(const LevelPtrs* __restrict__
 }
 
 // ---------------------------------------------------------------- MEMs
-// Maximal exact matches between two strings through the grammar (App. B):
-// the level-l parses of both strings are the search space; equal symbols, one
-// in each parse, are anchors, and each is completed into the maximal run of
-// equal bytes on its diagonal (k_mem_extend: the lcs of the symbols before
-// the anchor, the lcp of the first different symbols after it, with the
-// cursor walks above).  Only the first anchor of a run of
+// Maximal exact matches between pairs of strings through the grammar
+// (App. B): the level-l parses of the strings are the search space; equal
+// symbols, one in each parse of a pair, are anchors, and each is completed
+// into the maximal run of equal bytes on its diagonal (k_mem_extend: the lcs
+// of the symbols before the anchor, the lcp of the first different symbols
+// after it, with the cursor walks above).  Only the first anchor of a run of
 // consecutive anchors on one diagonal (the symbols before it differ) is
-// completed: the others lie inside the same match.
+// completed: the others lie inside the same match.  Many pairs go through
+// one pipeline: the parses of all their strings side by side in one array
+// (each string a contiguous segment), one sort of all of them by (string,
+// symbol), and every later step over all pairs at once.
 constexpr int kMB = 256;
 constexpr uint64_t kMemMaxAnchors = 1ull << 31;  // 32-bit counts in the radix sorts
 
@@ -396,15 +402,28 @@ inline unsigned mem_grid(uint64_t n) {
   return (unsigned)std::min<uint64_t>((n + kMB - 1) / kMB, 16384);
 }
 
-// the C entries (level, symbol) of strings a and b
+// One pair of a batch: the C entries of its two strings and where their
+// parses sit in the common array (seg_*: first symbol, n*: symbols), with the
+// byte offset of each segment's first symbol in the prefix of all lengths.
+struct MemPair {
+  int ta, tb;
+  uint32_t ya, yb;
+  uint32_t sa, na, sb, nb;
+  uint32_t slot_b;  // b's string slot (the high half of its sort keys)
+  uint32_t same;    // a and b are one string
+  uint64_t la, lb;  // byte lengths
+  uint64_t ga, gb;  // byte prefix at the segments' first symbols
+};
+
+// the C entries (level, symbol) of the strings js[0..n)
 __global__ __launch_bounds__(kMB) void k_mem_centries(const uint8_t* __restrict__ c_level,
                                                       const uint32_t* __restrict__ c_sym,
-                                                      uint32_t a, uint32_t b,
+                                                      const uint32_t* __restrict__ js, uint32_t n,
                                                       uint32_t* __restrict__ out) {
-  out[0] = c_level[a];
-  out[1] = c_sym[a];
-  out[2] = c_level[b];
-  out[3] = c_sym[b];
+  for (uint32_t i = blockIdx.x * kMB + threadIdx.x; i < n; i += gridDim.x * kMB) {
+    out[2 * i] = c_level[js[i]];
+    out[2 * i + 1] = c_sym[js[i]];
+  }
 }
 
 // right-hand-side length of every symbol of a parse (levels >= 2)
@@ -432,26 +451,35 @@ __global__ __launch_bounds__(kMB) void k_mem_children(const uint64_t* __restrict
   }
 }
 
-// The parse of the upper levels, while it is small, in one block: from the
-// C entry (top, y) down towards `level`, the frontier alternating between two
-// global buffers of kMemTopCap entries, each thread holding kMemPer
-// consecutive entries (their rule offsets loaded together, so a level costs
-// one round of dependent loads); it stops at `level` or above the first level
-// whose parse would not fit.  res = {level reached, its parse length, 1 if
-// the parse is in buf1}.
+// pos[idx[i]] for a few indexes (the segments' new starts after a step down)
+__global__ __launch_bounds__(kMB) void k_mem_pick(const uint64_t* __restrict__ pos,
+                                                  const uint64_t* __restrict__ idx, uint32_t n,
+                                                  uint64_t* __restrict__ out) {
+  for (uint32_t i = blockIdx.x * kMB + threadIdx.x; i < n; i += gridDim.x * kMB)
+    out[i] = pos[idx[i]];
+}
+
+// The parse of the upper levels, while it is small, in one block per string:
+// from the C entry (tops[b], ys[b]) down towards `level`, the frontier
+// alternating between two global buffers of kMemTopCap entries, each thread
+// holding kMemPer consecutive entries (their rule offsets loaded together, so
+// a level costs one round of dependent loads); it stops at `level` or above
+// the first level whose parse would not fit.  res[3b..3b+2] = {level
+// reached, its parse length, 1 if the parse is in the second buffer}.
 constexpr int kMPT = 1024;
 constexpr int kMemPer = 8;
 constexpr uint32_t kMemTopCap = kMPT * kMemPer;
 
 __global__ __launch_bounds__(kMPT) void k_mem_parse_top(const LevelPtrs* __restrict__ lv_ptr,
-                                                        int top, uint32_t y, int level,
-                                                        uint32_t* __restrict__ buf0,
+                                                        const uint32_t* __restrict__ cent,
+                                                        int level, uint32_t* __restrict__ buf0,
                                                         uint32_t* __restrict__ buf1,
                                                         uint32_t* __restrict__ res) {
   __shared__ uint64_t s_wave[kMPT / 64];
-  uint32_t* cur = buf0;
-  uint32_t* nxt = buf1;
-  if (threadIdx.x == 0) cur[0] = y;
+  const int top = (int)cent[2 * blockIdx.x];
+  uint32_t* cur = buf0 + (uint64_t)blockIdx.x * kMemTopCap;
+  uint32_t* nxt = buf1 + (uint64_t)blockIdx.x * kMemTopCap;
+  if (threadIdx.x == 0) cur[0] = cent[2 * blockIdx.x + 1];
   __syncthreads();
   uint32_t n = 1;
   int l = top;
@@ -485,73 +513,109 @@ __global__ __launch_bounds__(kMPT) void k_mem_parse_top(const LevelPtrs* __restr
     --l;
   }
   if (threadIdx.x == 0) {
-    res[0] = (uint32_t)l;
-    res[1] = n;
-    res[2] = cur == buf1;
+    res[3 * blockIdx.x] = (uint32_t)l;
+    res[3 * blockIdx.x + 1] = n;
+    res[3 * blockIdx.x + 2] = cur != buf0 + (uint64_t)blockIdx.x * kMemTopCap;
   }
 }
 
-// expansion length of every symbol of the level-l parse; index order for the sort
+// expansion length of every symbol of the level-l parse
 __global__ __launch_bounds__(kMB) void k_mem_elen(const uint64_t* __restrict__ explen_l,
                                                   const uint32_t* __restrict__ cur, uint64_t n,
-                                                  uint64_t* __restrict__ e,
+                                                  uint64_t* __restrict__ e) {
+  for (uint64_t i = blockIdx.x * (uint64_t)kMB + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * kMB)
+    e[i] = explen_l[cur[i]];
+}
+
+// sort key (string slot, symbol) and index of every parse entry; segments
+// (seg_start ascending, one per string slot seg_slot) cover [0, n)
+__global__ __launch_bounds__(kMB) void k_mem_keys(const uint32_t* __restrict__ F, uint64_t n,
+                                                  const uint32_t* __restrict__ seg_start,
+                                                  const uint32_t* __restrict__ seg_slot,
+                                                  uint32_t nseg, uint64_t* __restrict__ key,
                                                   uint32_t* __restrict__ idx) {
   for (uint64_t i = blockIdx.x * (uint64_t)kMB + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * kMB) {
-    e[i] = explen_l[cur[i]];
+    uint32_t lo = 0, hi = nseg;  // last segment starting at or before i
+    while (hi - lo > 1) {
+      const uint32_t m = (lo + hi) >> 1;
+      if (seg_start[m] <= i) lo = m; else hi = m;
+    }
+    key[i] = ((uint64_t)seg_slot[lo] << 32) | F[i];
     idx[i] = (uint32_t)i;
   }
 }
 
-// the entries of b's parse sorted by symbol that hold a's symbol at i
-__global__ __launch_bounds__(kMB) void k_mem_range(const uint32_t* __restrict__ A, uint64_t na,
-                                                   const uint32_t* __restrict__ keys, uint64_t nb,
+__device__ __forceinline__ uint32_t pair_of(const uint64_t* __restrict__ poff, uint32_t np,
+                                            uint64_t t) {
+  uint32_t lo = 0, hi = np;  // last pair whose entries start at or before t
+  while (hi - lo > 1) {
+    const uint32_t m = (lo + hi) >> 1;
+    if (poff[m] <= t) lo = m; else hi = m;
+  }
+  return lo;
+}
+
+// For entry t (pair p, position i of a's parse): the range of b's entries
+// with the same symbol in the sorted keys
+__global__ __launch_bounds__(kMB) void k_mem_range(const MemPair* __restrict__ pairs,
+                                                   const uint64_t* __restrict__ poff, uint32_t np,
+                                                   uint64_t P, const uint32_t* __restrict__ F,
+                                                   const uint64_t* __restrict__ keys, uint64_t n,
                                                    uint64_t* __restrict__ lo,
                                                    uint64_t* __restrict__ cnt) {
-  for (uint64_t i = blockIdx.x * (uint64_t)kMB + threadIdx.x; i < na;
-       i += (uint64_t)gridDim.x * kMB) {
-    const uint32_t x = A[i];
-    uint64_t l = 0, h = nb;
+  for (uint64_t t = blockIdx.x * (uint64_t)kMB + threadIdx.x; t < P;
+       t += (uint64_t)gridDim.x * kMB) {
+    const uint32_t p = pair_of(poff, np, t);
+    const MemPair& M = pairs[p];
+    const uint64_t x = ((uint64_t)M.slot_b << 32) | F[M.sa + (t - poff[p])];
+    uint64_t l = 0, h = n;
     while (l < h) {  // first key >= x
       const uint64_t m = (l + h) >> 1;
       if (keys[m] < x) l = m + 1; else h = m;
     }
-    uint64_t r = l, h2 = nb;
+    uint64_t r = l, h2 = n;
     while (r < h2) {  // first key > x
       const uint64_t m = (r + h2) >> 1;
       if (keys[m] <= x) r = m + 1; else h2 = m;
     }
-    lo[i] = l;
-    cnt[i] = r - l;
+    lo[t] = l;
+    cnt[t] = r - l;
   }
 }
 
-// Anchors (i, j) that start a run on their diagonal; counted per i, then
+// Anchors (i, j) that start a run on their diagonal; counted per entry, then
 // written at the scanned positions.  With one string on both sides the pairs
 // of a position with itself are not anchors.
 template <bool WRITE>
 __global__ __launch_bounds__(kMB) void k_mem_seeds(
-    const uint32_t* __restrict__ A, uint64_t na, const uint32_t* __restrict__ B,
-    const uint32_t* __restrict__ where, const uint64_t* __restrict__ lo,
-    const uint64_t* __restrict__ cnt, int same, uint64_t* __restrict__ nseed,
-    const uint64_t* __restrict__ spos, uint32_t* __restrict__ si, uint32_t* __restrict__ sj) {
-  for (uint64_t i = blockIdx.x * (uint64_t)kMB + threadIdx.x; i < na;
-       i += (uint64_t)gridDim.x * kMB) {
-    const uint64_t b = lo[i], e = b + cnt[i];
-    const bool has_prev = i > 0;
-    const uint32_t prev = has_prev ? A[i - 1] : 0;
-    uint64_t c = WRITE ? spos[i] : 0;
-    for (uint64_t t = b; t < e; ++t) {
-      const uint32_t j = where[t];
-      if (same && j == i) continue;
-      if (has_prev && j > 0 && B[j - 1] == prev) continue;
+    const MemPair* __restrict__ pairs, const uint64_t* __restrict__ poff, uint32_t np, uint64_t P,
+    const uint32_t* __restrict__ F, const uint32_t* __restrict__ where,
+    const uint64_t* __restrict__ lo, const uint64_t* __restrict__ cnt,
+    uint64_t* __restrict__ nseed, const uint64_t* __restrict__ spos, uint32_t* __restrict__ sp,
+    uint32_t* __restrict__ si, uint32_t* __restrict__ sj) {
+  for (uint64_t t = blockIdx.x * (uint64_t)kMB + threadIdx.x; t < P;
+       t += (uint64_t)gridDim.x * kMB) {
+    const uint32_t p = pair_of(poff, np, t);
+    const MemPair& M = pairs[p];
+    const uint32_t i = M.sa + (uint32_t)(t - poff[p]);
+    const uint64_t b = lo[t], e = b + cnt[t];
+    const bool has_prev = i > M.sa;
+    const uint32_t prev = has_prev ? F[i - 1] : 0;
+    uint64_t c = WRITE ? spos[t] : 0;
+    for (uint64_t u = b; u < e; ++u) {
+      const uint32_t j = where[u];
+      if (M.same && j == i) continue;
+      if (has_prev && j > M.sb && F[j - 1] == prev) continue;
       if (WRITE) {
-        si[c] = (uint32_t)i;
+        sp[c] = p;
+        si[c] = i;
         sj[c] = j;
       }
       ++c;
     }
-    if (!WRITE) nseed[i] = c;
+    if (!WRITE) nseed[t] = c;
   }
 }
 
@@ -566,41 +630,44 @@ constexpr int kMemRun = 64;
 
 __global__ __launch_bounds__(64) void k_mem_extend(
     const LevelPtrs* __restrict__ lv_ptr, const uint64_t* const* __restrict__ explen, int level,
-    int ta, uint32_t ya, uint64_t la, int tb, uint32_t yb, uint64_t lb,
-    const uint32_t* __restrict__ A, uint64_t na, const uint64_t* __restrict__ sa,
-    const uint32_t* __restrict__ B, uint64_t nb, const uint64_t* __restrict__ sb,
+    const MemPair* __restrict__ pairs, const uint32_t* __restrict__ F,
+    const uint64_t* __restrict__ G, const uint32_t* __restrict__ sp,
     const uint32_t* __restrict__ si, const uint32_t* __restrict__ sj, uint64_t ns,
     uint64_t min_len, uint64_t* __restrict__ mpa, uint64_t* __restrict__ mpb,
     uint64_t* __restrict__ mlen, uint64_t* __restrict__ keep) {
   for (uint64_t q = blockIdx.x * (uint64_t)64 + threadIdx.x; q < ns;
        q += (uint64_t)gridDim.x * 64) {
+    const MemPair& M = pairs[sp[q]];
     const uint64_t i = si[q], j = sj[q];
-    const uint64_t x = sa[i], y = sb[j];
+    const uint64_t x = G[i] - M.ga, y = G[j] - M.gb;
     uint64_t back = 0;
-    if (i > 0 && j > 0) {
-      const uint64_t nx = x - sa[i - 1], ny = y - sb[j - 1];
-      back = lce_walk<true>(lv_ptr, explen, level, A[i - 1], nx, nx, level, B[j - 1], ny, ny);
+    if (i > M.sa && j > M.sb) {
+      const uint64_t nx = G[i] - G[i - 1], ny = G[j] - G[j - 1];
+      back = lce_walk<true>(lv_ptr, explen, level, F[i - 1], nx, nx, level, F[j - 1], ny, ny);
       if (back == nx || back == ny)
-        back += lce_walk<true>(lv_ptr, explen, ta, ya, x - back, la, tb, yb, y - back, lb);
+        back += lce_walk<true>(lv_ptr, explen, M.ta, M.ya, x - back, M.la, M.tb, M.yb, y - back,
+                               M.lb);
     }
+    const uint64_t ea = (uint64_t)M.sa + M.na, eb = (uint64_t)M.sb + M.nb;
     uint64_t ii = i + 1, jj = j + 1;
     int run = 0;
-    while (ii < na && jj < nb && run < kMemRun && A[ii] == B[jj]) {
+    while (ii < ea && jj < eb && run < kMemRun && F[ii] == F[jj]) {
       ++ii;
       ++jj;
       ++run;
     }
-    uint64_t fwd = sa[ii] - x;
-    if (ii < na && jj < nb) {
+    uint64_t fwd = G[ii] - G[i];
+    if (ii < ea && jj < eb) {
       bool rest = run == kMemRun;
       if (!rest) {
-        const uint64_t nx = sa[ii + 1] - sa[ii], ny = sb[jj + 1] - sb[jj];
-        const uint64_t l1 = lce_walk<false>(lv_ptr, explen, level, A[ii], 0, nx, level, B[jj], 0, ny);
+        const uint64_t nx = G[ii + 1] - G[ii], ny = G[jj + 1] - G[jj];
+        const uint64_t l1 = lce_walk<false>(lv_ptr, explen, level, F[ii], 0, nx, level, F[jj], 0, ny);
         fwd += l1;
         rest = l1 == nx || l1 == ny;
       }
       if (rest)
-        fwd += lce_walk<false>(lv_ptr, explen, ta, ya, x + fwd, la, tb, yb, y + fwd, lb);
+        fwd += lce_walk<false>(lv_ptr, explen, M.ta, M.ya, x + fwd, M.la, M.tb, M.yb, y + fwd,
+                               M.lb);
     }
     mpa[q] = x - back;
     mpb[q] = y - back;
@@ -609,17 +676,19 @@ __global__ __launch_bounds__(64) void k_mem_extend(
   }
 }
 
-// kept matches packed; sort values start as their index
+// kept matches packed: (pair << 40 | start in a), start in b, length; sort
+// values start as their index
 __global__ __launch_bounds__(kMB) void k_mem_pack(
-    const uint64_t* __restrict__ mpa, const uint64_t* __restrict__ mpb,
-    const uint64_t* __restrict__ mlen, const uint64_t* __restrict__ keep,
-    const uint64_t* __restrict__ kpos, uint64_t ns, uint64_t* __restrict__ pa,
-    uint64_t* __restrict__ pb, uint64_t* __restrict__ ln, uint32_t* __restrict__ idx) {
+    const uint32_t* __restrict__ sp, const uint64_t* __restrict__ mpa,
+    const uint64_t* __restrict__ mpb, const uint64_t* __restrict__ mlen,
+    const uint64_t* __restrict__ keep, const uint64_t* __restrict__ kpos, uint64_t ns,
+    uint64_t* __restrict__ pka, uint64_t* __restrict__ pb, uint64_t* __restrict__ ln,
+    uint32_t* __restrict__ idx) {
   for (uint64_t q = blockIdx.x * (uint64_t)kMB + threadIdx.x; q < ns;
        q += (uint64_t)gridDim.x * kMB) {
     if (!keep[q]) continue;
     const uint64_t p = kpos[q];
-    pa[p] = mpa[q];
+    pka[p] = ((uint64_t)sp[q] << 40) | mpa[q];
     pb[p] = mpb[q];
     ln[p] = mlen[q];
     idx[p] = (uint32_t)p;
@@ -634,26 +703,28 @@ __global__ __launch_bounds__(kMB) void k_mem_gather(const uint64_t* __restrict__
     dst[t] = src[idx[t]];
 }
 
-// after the sort by (start in a, start in b): the first of equal matches
-__global__ __launch_bounds__(kMB) void k_mem_first(const uint64_t* __restrict__ pa_s,
+// after the sort by (pair, start in a, start in b): the first of equal matches
+__global__ __launch_bounds__(kMB) void k_mem_first(const uint64_t* __restrict__ pka_s,
                                                    const uint64_t* __restrict__ pb,
                                                    const uint32_t* __restrict__ idx, uint64_t m,
                                                    uint64_t* __restrict__ flag) {
   for (uint64_t t = blockIdx.x * (uint64_t)kMB + threadIdx.x; t < m;
        t += (uint64_t)gridDim.x * kMB)
-    flag[t] = t == 0 || pa_s[t] != pa_s[t - 1] || pb[idx[t]] != pb[idx[t - 1]];
+    flag[t] = t == 0 || pka_s[t] != pka_s[t - 1] || pb[idx[t]] != pb[idx[t - 1]];
 }
 
 __global__ __launch_bounds__(kMB) void k_mem_out(
-    const uint64_t* __restrict__ pa_s, const uint64_t* __restrict__ pb,
+    const uint64_t* __restrict__ pka_s, const uint64_t* __restrict__ pb,
     const uint64_t* __restrict__ ln, const uint32_t* __restrict__ idx,
     const uint64_t* __restrict__ flag, const uint64_t* __restrict__ fpos, uint64_t m, uint64_t cap,
-    uint64_t* __restrict__ opa, uint64_t* __restrict__ opb, uint64_t* __restrict__ olen) {
+    uint32_t* __restrict__ opair, uint64_t* __restrict__ opa, uint64_t* __restrict__ opb,
+    uint64_t* __restrict__ olen) {
   for (uint64_t t = blockIdx.x * (uint64_t)kMB + threadIdx.x; t < m;
        t += (uint64_t)gridDim.x * kMB) {
     const uint64_t p = fpos[t];
     if (!flag[t] || p >= cap) continue;
-    opa[p] = pa_s[t];
+    if (opair) opair[p] = (uint32_t)(pka_s[t] >> 40);
+    opa[p] = pka_s[t] & ((1ull << 40) - 1);
     opb[p] = pb[idx[t]];
     olen[p] = ln[idx[t]];
   }
@@ -665,56 +736,288 @@ inline int bits_for(uint64_t v) {  // radix-sort key width that holds 0..v
   return b;
 }
 
-// the level-`level` parse of a string whose C entry is (top, y): symbols in
-// cur[0..n), byte starts in starts[0..n] (starts[n] = the string's length).
-// The upper levels come from one block; each larger level takes a scan and a
-// read of its length.
-uint64_t mem_parse(lcg_grammar* g, int top, uint32_t y, uint32_t level, DBuf<uint32_t>& cur,
-                   DBuf<uint64_t>& starts, DBuf<uint32_t>& idx, hipStream_t s) {
-  DBuf<uint32_t> t0, t1, res;
-  t0.need(kMemTopCap, s);
-  t1.need(kMemTopCap, s);
-  res.need(3, s);
-  k_mem_parse_top<<<1, kMPT, 0, s>>>(g->level_ptrs.p, top, y, (int)level, t0.p, t1.p, res.p);
-  HIP_CHECK(hipGetLastError());
-  uint32_t r[3];
-  HIP_CHECK(hipMemcpyAsync(r, res.p, sizeof(r), hipMemcpyDeviceToHost, s));
-  sync(s);
-  int l = (int)r[0];
-  uint64_t n = r[1];
-  const uint32_t* src = r[2] ? t1.p : t0.p;
-  DBuf<uint32_t> next;
-  DBuf<uint64_t> cnt, pos, tmp;
-  if (l == (int)level) {
-    cur.need(n, s);
-    HIP_CHECK(hipMemcpyAsync(cur.p, src, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+inline void scan_into(DBuf<uint64_t>& tmp, const uint64_t* in, uint64_t* out, uint64_t n,
+                      hipStream_t s) {
+  tmp.need(std::max<size_t>(scan_tmp_words(n), 1), s);
+  scan_exclusive(in, out, n, tmp.p, s);
+}
+
+// The matches of the pairs (a[p], b[p]), p < np, at `level`: the first
+// min(count, cap) written (pair index optional), *n_mems the count.
+void mems_core(lcg_grammar* g, uint32_t np, const uint32_t* ha, const uint32_t* hb,
+               uint32_t level, uint64_t min_len, uint64_t cap, uint32_t* d_pair, uint64_t* d_pa,
+               uint64_t* d_pb, uint64_t* d_len, uint64_t* n_mems, hipStream_t s) {
+  *n_mems = 0;
+  if (!np) return;
+  if (cap && (!d_pa || !d_pb || !d_len)) throw LcgError{LCG_EINVAL, "NULL output array"};
+  if (!ha || !hb) throw LcgError{LCG_EINVAL, "NULL pair array"};
+  if (np >= (1u << 23)) throw LcgError{LCG_EINVAL, "2^23 pairs or more in one call"};
+  if (g->levels.size() >= (size_t)kMaxLv) throw LcgError{LCG_EOVERFLOW, "too many levels"};
+  // the distinct strings of the batch: one parse each
+  std::vector<uint32_t> strs, slot_a(np), slot_b(np);
+  {
+    std::unordered_map<uint32_t, uint32_t> at;
+    for (uint32_t p = 0; p < np; ++p) {
+      for (int side = 0; side < 2; ++side) {
+        const uint32_t j = side ? hb[p] : ha[p];
+        if (j >= g->k) throw LcgError{LCG_EINVAL, "string index beyond the grammar's"};
+        auto it = at.find(j);
+        if (it == at.end()) {
+          it = at.emplace(j, (uint32_t)strs.size()).first;
+          strs.push_back(j);
+        }
+        (side ? slot_b : slot_a)[p] = it->second;
+      }
+    }
   }
-  for (; l > (int)level; --l) {
+  const uint32_t ns_ = (uint32_t)strs.size();
+  ensure_explen(g, s);
+  DBuf<uint32_t> js, cent;
+  js.need(ns_, s);
+  cent.need(2 * (size_t)ns_, s);
+  HIP_CHECK(hipMemcpyAsync(js.p, strs.data(), ns_ * 4, hipMemcpyHostToDevice, s));
+  k_mem_centries<<<mem_grid(ns_), kMB, 0, s>>>(g->c_level.p, g->c_sym.p, js.p, ns_, cent.p);
+  HIP_CHECK(hipGetLastError());
+  std::vector<uint32_t> hc(2 * (size_t)ns_);
+  HIP_CHECK(hipMemcpyAsync(hc.data(), cent.p, hc.size() * 4, hipMemcpyDeviceToHost, s));
+  sync(s);
+  for (uint32_t i = 0; i < ns_; ++i)
+    if (level < 1 || level > hc[2 * i])
+      throw LcgError{LCG_EINVAL, "level outside 1..min(level of C[a], level of C[b])"};
+  // upper levels, one block per string
+  DBuf<uint32_t> t0, t1, res;
+  t0.need((size_t)ns_ * kMemTopCap, s);
+  t1.need((size_t)ns_ * kMemTopCap, s);
+  res.need(3 * (size_t)ns_, s);
+  k_mem_parse_top<<<ns_, kMPT, 0, s>>>(g->level_ptrs.p, cent.p, (int)level, t0.p, t1.p, res.p);
+  HIP_CHECK(hipGetLastError());
+  std::vector<uint32_t> hr(3 * (size_t)ns_);
+  HIP_CHECK(hipMemcpyAsync(hr.data(), res.p, hr.size() * 4, hipMemcpyDeviceToHost, s));
+  sync(s);
+  // the larger levels: the strings' frontiers side by side, each string
+  // joining once the descent reaches the level its top parse stopped at
+  std::vector<uint64_t> seg_start(ns_, 0), seg_len(ns_, 0);
+  std::vector<uint32_t> order;  // strings in the array, in segment order
+  DBuf<uint32_t> F, next;
+  DBuf<uint64_t> cnt, pos, tmp, sidx, spos;
+  uint64_t n = 0;
+  int lmax = (int)level;
+  for (uint32_t i = 0; i < ns_; ++i) lmax = std::max(lmax, (int)hr[3 * i]);
+  auto join = [&](int l) {
+    uint64_t add = 0;
+    for (uint32_t i = 0; i < ns_; ++i)
+      if ((int)hr[3 * i] == l) add += hr[3 * i + 1];
+    if (!add) return;
+    F.grow(n + add, n, s);
+    for (uint32_t i = 0; i < ns_; ++i) {
+      if ((int)hr[3 * i] != l) continue;
+      const uint32_t* src = (hr[3 * i + 2] ? t1.p : t0.p) + (uint64_t)i * kMemTopCap;
+      HIP_CHECK(hipMemcpyAsync(F.p + n, src, (size_t)hr[3 * i + 1] * 4, hipMemcpyDeviceToDevice,
+                               s));
+      seg_start[i] = n;
+      seg_len[i] = hr[3 * i + 1];
+      order.push_back(i);
+      n += hr[3 * i + 1];
+    }
+  };
+  for (int l = lmax; l > (int)level; --l) {
+    join(l);
+    if (!n) continue;
     const Level& L = g->levels[l - 1];
     cnt.need(n, s);
-    k_mem_rhslen<<<mem_grid(n), kMB, 0, s>>>(L.off.p, src, n, cnt.p);
+    k_mem_rhslen<<<mem_grid(n), kMB, 0, s>>>(L.off.p, F.p, n, cnt.p);
     HIP_CHECK(hipGetLastError());
     pos.need(n + 1, s);
-    tmp.need(std::max<size_t>(scan_tmp_words(n), 1), s);
-    scan_exclusive(cnt.p, pos.p, n, tmp.p, s);
-    const uint64_t m = read_dev(pos.p + n, s);
-    if (m >= (1ull << 31)) throw LcgError{LCG_EOVERFLOW, "a parse of 2^31 symbols or more"};
-    next.need(m, s);
-    k_mem_children<<<mem_grid(n), kMB, 0, s>>>(L.off.p, L.rhs32.p, src, n, pos.p, next.p);
+    scan_into(tmp, cnt.p, pos.p, n, s);
+    // the segments' new starts and the new length, in one read
+    const uint32_t k = (uint32_t)order.size();
+    std::vector<uint64_t> hs(k + 1);
+    for (uint32_t q = 0; q < k; ++q) hs[q] = seg_start[order[q]];
+    hs[k] = n;
+    sidx.need(k + 1, s);
+    spos.need(k + 1, s);
+    HIP_CHECK(hipMemcpyAsync(sidx.p, hs.data(), (k + 1) * 8, hipMemcpyHostToDevice, s));
+    k_mem_pick<<<mem_grid(k + 1), kMB, 0, s>>>(pos.p, sidx.p, k + 1, spos.p);
     HIP_CHECK(hipGetLastError());
-    std::swap(cur, next);
-    src = cur.p;
+    std::vector<uint64_t> hp(k + 1);
+    HIP_CHECK(hipMemcpyAsync(hp.data(), spos.p, (k + 1) * 8, hipMemcpyDeviceToHost, s));
+    sync(s);
+    const uint64_t m = hp[k];
+    if (m >= (1ull << 31)) throw LcgError{LCG_EOVERFLOW, "parses of 2^31 symbols or more"};
+    next.need(m, s);
+    k_mem_children<<<mem_grid(n), kMB, 0, s>>>(L.off.p, L.rhs32.p, F.p, n, pos.p, next.p);
+    HIP_CHECK(hipGetLastError());
+    std::swap(F, next);
+    for (uint32_t q = 0; q < k; ++q) {
+      seg_start[order[q]] = hp[q];
+      seg_len[order[q]] = (q + 1 < k ? hp[q + 1] : m) - hp[q];
+    }
     n = m;
   }
+  join((int)level);
+  if (n >= (1ull << 31)) throw LcgError{LCG_EOVERFLOW, "parses of 2^31 symbols or more"};
+  // byte prefix of all symbols (G), the segments' byte bases and lengths
+  DBuf<uint64_t> G;
   cnt.need(n, s);
-  idx.need(n, s);
-  k_mem_elen<<<mem_grid(n), kMB, 0, s>>>(g->explen[level - 1].p, cur.p, n, cnt.p, idx.p);
+  k_mem_elen<<<mem_grid(n), kMB, 0, s>>>(g->explen[level - 1].p, F.p, n, cnt.p);
   HIP_CHECK(hipGetLastError());
-  starts.need(n + 1, s);
-  tmp.need(std::max<size_t>(scan_tmp_words(n), 1), s);
-  scan_exclusive(cnt.p, starts.p, n, tmp.p, s);
-  sync(s);  // the temporaries go back to the pool
-  return n;
+  G.need(n + 1, s);
+  scan_into(tmp, cnt.p, G.p, n, s);
+  std::vector<uint64_t> gidx(2 * (size_t)ns_);
+  for (uint32_t i = 0; i < ns_; ++i) {
+    gidx[2 * i] = seg_start[i];
+    gidx[2 * i + 1] = seg_start[i] + seg_len[i];
+  }
+  sidx.need(gidx.size(), s);
+  spos.need(gidx.size(), s);
+  HIP_CHECK(hipMemcpyAsync(sidx.p, gidx.data(), gidx.size() * 8, hipMemcpyHostToDevice, s));
+  k_mem_pick<<<mem_grid(gidx.size()), kMB, 0, s>>>(G.p, sidx.p, (uint32_t)gidx.size(), spos.p);
+  HIP_CHECK(hipGetLastError());
+  std::vector<uint64_t> gv(gidx.size());
+  HIP_CHECK(hipMemcpyAsync(gv.data(), spos.p, gv.size() * 8, hipMemcpyDeviceToHost, s));
+  // the sort of all parses by (string, symbol)
+  std::vector<uint32_t> hseg(2 * (size_t)ns_);
+  for (uint32_t q = 0; q < ns_; ++q) {
+    hseg[q] = (uint32_t)seg_start[order[q]];
+    hseg[ns_ + q] = order[q];
+  }
+  DBuf<uint32_t> segd, idx, where;
+  DBuf<uint64_t> key, keys;
+  segd.need(hseg.size(), s);
+  HIP_CHECK(hipMemcpyAsync(segd.p, hseg.data(), hseg.size() * 4, hipMemcpyHostToDevice, s));
+  key.need(n, s);
+  keys.need(n, s);
+  idx.need(n, s);
+  where.need(n, s);
+  k_mem_keys<<<mem_grid(n), kMB, 0, s>>>(F.p, n, segd.p, segd.p + ns_, ns_, key.p, idx.p);
+  HIP_CHECK(hipGetLastError());
+  const int kbits = 32 + bits_for(ns_);
+  size_t tbytes = 0;
+  HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, key.p, keys.p, idx.p, where.p,
+                                               (int)n, 0, kbits, s));
+  DBuf<uint8_t> stmp;
+  stmp.need(std::max<size_t>(tbytes, 4), s);
+  HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(stmp.p, tbytes, key.p, keys.p, idx.p, where.p,
+                                               (int)n, 0, kbits, s));
+  sync(s);  // gv, and hseg's copy, are complete
+  // the pairs, and the entries of their a-side parses
+  std::vector<MemPair> hp(np);
+  std::vector<uint64_t> hpo(np + 1, 0);
+  for (uint32_t p = 0; p < np; ++p) {
+    const uint32_t A = slot_a[p], B = slot_b[p];
+    MemPair& M = hp[p];
+    M.ta = (int)hc[2 * A];
+    M.ya = hc[2 * A + 1];
+    M.tb = (int)hc[2 * B];
+    M.yb = hc[2 * B + 1];
+    M.sa = (uint32_t)seg_start[A];
+    M.na = (uint32_t)seg_len[A];
+    M.sb = (uint32_t)seg_start[B];
+    M.nb = (uint32_t)seg_len[B];
+    M.slot_b = B;
+    M.same = A == B;
+    M.ga = gv[2 * A];
+    M.gb = gv[2 * B];
+    M.la = gv[2 * A + 1] - gv[2 * A];
+    M.lb = gv[2 * B + 1] - gv[2 * B];
+    if (M.la >= (1ull << 40)) throw LcgError{LCG_EOVERFLOW, "a string of 2^40 bytes or more"};
+    hpo[p + 1] = hpo[p] + M.na;
+  }
+  const uint64_t P = hpo[np];
+  DBuf<MemPair> pairs;
+  DBuf<uint64_t> poff, lo;
+  pairs.need(np, s);
+  poff.need(np + 1, s);
+  HIP_CHECK(hipMemcpyAsync(pairs.p, hp.data(), np * sizeof(MemPair), hipMemcpyHostToDevice, s));
+  HIP_CHECK(hipMemcpyAsync(poff.p, hpo.data(), (np + 1) * 8, hipMemcpyHostToDevice, s));
+  lo.need(P, s);
+  cnt.need(P, s);
+  pos.need(P + 1, s);
+  k_mem_range<<<mem_grid(P), kMB, 0, s>>>(pairs.p, poff.p, np, P, F.p, keys.p, n, lo.p, cnt.p);
+  HIP_CHECK(hipGetLastError());
+  scan_into(tmp, cnt.p, pos.p, P, s);
+  const uint64_t anchors = read_dev(pos.p + P, s);
+  if (anchors > kMemMaxAnchors)
+    throw LcgError{LCG_EOVERFLOW, std::to_string(anchors) +
+                                      " anchors at this level (at most 2^31): choose a higher "
+                                      "level"};
+  DBuf<uint64_t> nseed;
+  nseed.need(P, s);
+  k_mem_seeds<false><<<mem_grid(P), kMB, 0, s>>>(pairs.p, poff.p, np, P, F.p, where.p, lo.p,
+                                                 cnt.p, nseed.p, nullptr, nullptr, nullptr,
+                                                 nullptr);
+  HIP_CHECK(hipGetLastError());
+  scan_into(tmp, nseed.p, pos.p, P, s);
+  const uint64_t ns = read_dev(pos.p + P, s);
+  if (!ns) return;
+  DBuf<uint32_t> sp, si, sj;
+  sp.need(ns, s);
+  si.need(ns, s);
+  sj.need(ns, s);
+  k_mem_seeds<true><<<mem_grid(P), kMB, 0, s>>>(pairs.p, poff.p, np, P, F.p, where.p, lo.p,
+                                                cnt.p, nullptr, pos.p, sp.p, si.p, sj.p);
+  HIP_CHECK(hipGetLastError());
+  DBuf<uint64_t> mpa, mpb, mlen, keep, kpos;
+  mpa.need(ns, s);
+  mpb.need(ns, s);
+  mlen.need(ns, s);
+  keep.need(ns, s);
+  k_mem_extend<<<(unsigned)std::min<uint64_t>((ns + 63) / 64, 65536), 64, 0, s>>>(
+      g->level_ptrs.p, g->explen_ptrs.p, (int)level, pairs.p, F.p, G.p, sp.p, si.p, sj.p, ns,
+      min_len, mpa.p, mpb.p, mlen.p, keep.p);
+  HIP_CHECK(hipGetLastError());
+  kpos.need(ns + 1, s);
+  scan_into(tmp, keep.p, kpos.p, ns, s);
+  const uint64_t m = read_dev(kpos.p + ns, s);
+  if (!m) return;
+  // sort by (pair, start in a, start in b): by b, then stably by the rest
+  DBuf<uint64_t> pka, pb, ln, k1, k2;
+  DBuf<uint32_t> i0, i1, i2;
+  pka.need(m, s);
+  pb.need(m, s);
+  ln.need(m, s);
+  i0.need(m, s);
+  k_mem_pack<<<mem_grid(ns), kMB, 0, s>>>(sp.p, mpa.p, mpb.p, mlen.p, keep.p, kpos.p, ns, pka.p,
+                                         pb.p, ln.p, i0.p);
+  HIP_CHECK(hipGetLastError());
+  k1.need(m, s);
+  k2.need(m, s);
+  i1.need(m, s);
+  i2.need(m, s);
+  uint64_t lbmax = 0, lamax = 0;
+  for (const MemPair& M : hp) {
+    lbmax = std::max(lbmax, M.lb);
+    lamax = std::max(lamax, M.la);
+  }
+  const int bb = bits_for(lbmax), ab = std::min(64, 40 + bits_for(np));
+  size_t st1 = 0, st2 = 0;
+  HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, st1, pb.p, k1.p, i0.p, i1.p, (int)m, 0,
+                                               bb, s));
+  HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, st2, k2.p, k1.p, i1.p, i2.p, (int)m, 0,
+                                               ab, s));
+  st1 = std::max(st1, st2);
+  stmp.need(std::max<size_t>(st1, 4), s);
+  HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(stmp.p, st1, pb.p, k1.p, i0.p, i1.p, (int)m, 0,
+                                               bb, s));
+  k_mem_gather<<<mem_grid(m), kMB, 0, s>>>(pka.p, i1.p, m, k2.p);
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(stmp.p, st1, k2.p, k1.p, i1.p, i2.p, (int)m, 0,
+                                               ab, s));
+  // k1: (pair, start in a) in order, i2: the match each came from
+  DBuf<uint64_t> flag, fpos;
+  flag.need(m, s);
+  fpos.need(m + 1, s);
+  k_mem_first<<<mem_grid(m), kMB, 0, s>>>(k1.p, pb.p, i2.p, m, flag.p);
+  HIP_CHECK(hipGetLastError());
+  scan_into(tmp, flag.p, fpos.p, m, s);
+  const uint64_t count = read_dev(fpos.p + m, s);
+  if (cap) {
+    k_mem_out<<<mem_grid(m), kMB, 0, s>>>(k1.p, pb.p, ln.p, i2.p, flag.p, fpos.p, m, cap, d_pair,
+                                         d_pa, d_pb, d_len);
+    HIP_CHECK(hipGetLastError());
+  }
+  sync(s);
+  *n_mems = count;
 }
 
 }  // namespace
@@ -831,126 +1134,19 @@ lcg_status lcg_mems(lcg_grammar_t g, uint32_t a, uint32_t b, uint32_t level, uin
   return guard([&] {
     live(g);
     if (!n_mems) throw LcgError{LCG_EINVAL, "n_mems is NULL"};
-    *n_mems = 0;
-    if (cap && (!d_pa || !d_pb || !d_len)) throw LcgError{LCG_EINVAL, "NULL output array"};
-    if (a >= g->k || b >= g->k) throw LcgError{LCG_EINVAL, "string index beyond the grammar's"};
-    if (g->levels.size() >= (size_t)kMaxLv) throw LcgError{LCG_EOVERFLOW, "too many levels"};
-    hipStream_t s = stream;
-    ensure_explen(g, s);
-    DBuf<uint32_t> ce;
-    ce.need(4, s);
-    k_mem_centries<<<1, 1, 0, s>>>(g->c_level.p, g->c_sym.p, a, b, ce.p);
-    HIP_CHECK(hipGetLastError());
-    uint32_t cv[4];
-    HIP_CHECK(hipMemcpyAsync(cv, ce.p, sizeof(cv), hipMemcpyDeviceToHost, s));
-    sync(s);
-    const int ta = (int)cv[0], tb = (int)cv[2];
-    const uint32_t ya = cv[1], yb = cv[3];
-    if (level < 1 || (int)level > std::min(ta, tb))
-      throw LcgError{LCG_EINVAL, "level outside 1..min(level of C[a], level of C[b])"};
-    DBuf<uint32_t> A, B, ia, ib;
-    DBuf<uint64_t> sa, sb;
-    const uint64_t na = mem_parse(g, ta, ya, level, A, sa, ia, s);
-    const uint64_t nb = mem_parse(g, tb, yb, level, B, sb, ib, s);
-    const uint64_t la = read_dev(sa.p + na, s), lb = read_dev(sb.p + nb, s);
-    // b's parse sorted by symbol, with each entry's index
-    DBuf<uint32_t> keys, where;
-    keys.need(nb, s);
-    where.need(nb, s);
-    const int kbits = bits_for(g->levels[level - 1].u);
-    size_t tbytes = 0;
-    HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, B.p, keys.p, ib.p, where.p,
-                                                 (int)nb, 0, kbits, s));
-    DBuf<uint8_t> stmp;
-    stmp.need(std::max<size_t>(tbytes, 4), s);
-    HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(stmp.p, tbytes, B.p, keys.p, ib.p, where.p,
-                                                 (int)nb, 0, kbits, s));
-    DBuf<uint64_t> lo, cnt, pos, tmp;
-    lo.need(na, s);
-    cnt.need(na, s);
-    pos.need(na + 1, s);
-    tmp.need(std::max<size_t>(scan_tmp_words(na), 1), s);
-    k_mem_range<<<mem_grid(na), kMB, 0, s>>>(A.p, na, keys.p, nb, lo.p, cnt.p);
-    HIP_CHECK(hipGetLastError());
-    scan_exclusive(cnt.p, pos.p, na, tmp.p, s);
-    const uint64_t anchors = read_dev(pos.p + na, s);
-    if (anchors > kMemMaxAnchors)
-      throw LcgError{LCG_EOVERFLOW, std::to_string(anchors) +
-                                        " anchors at this level (at most 2^31): choose a higher "
-                                        "level"};
-    DBuf<uint64_t> nseed;
-    nseed.need(na, s);
-    const int same = a == b;
-    k_mem_seeds<false><<<mem_grid(na), kMB, 0, s>>>(A.p, na, B.p, where.p, lo.p, cnt.p, same,
-                                                    nseed.p, nullptr, nullptr, nullptr);
-    HIP_CHECK(hipGetLastError());
-    scan_exclusive(nseed.p, pos.p, na, tmp.p, s);
-    const uint64_t ns = read_dev(pos.p + na, s);
-    if (!ns) return;
-    DBuf<uint32_t> si, sj;
-    si.need(ns, s);
-    sj.need(ns, s);
-    k_mem_seeds<true><<<mem_grid(na), kMB, 0, s>>>(A.p, na, B.p, where.p, lo.p, cnt.p, same,
-                                                   nullptr, pos.p, si.p, sj.p);
-    HIP_CHECK(hipGetLastError());
-    DBuf<uint64_t> mpa, mpb, mlen, keep, kpos, ktmp;
-    mpa.need(ns, s);
-    mpb.need(ns, s);
-    mlen.need(ns, s);
-    keep.need(ns, s);
-    k_mem_extend<<<(unsigned)std::min<uint64_t>((ns + 63) / 64, 65536), 64, 0, s>>>(
-        g->level_ptrs.p, g->explen_ptrs.p, (int)level, ta, ya, la, tb, yb, lb, A.p, na, sa.p, B.p,
-        nb, sb.p, si.p, sj.p, ns, min_len, mpa.p, mpb.p, mlen.p, keep.p);
-    HIP_CHECK(hipGetLastError());
-    kpos.need(ns + 1, s);
-    ktmp.need(std::max<size_t>(scan_tmp_words(ns), 1), s);
-    scan_exclusive(keep.p, kpos.p, ns, ktmp.p, s);
-    const uint64_t m = read_dev(kpos.p + ns, s);
-    if (!m) return;
-    // sort by (start in a, start in b): by b, then stably by a
-    DBuf<uint64_t> pa, pb, ln, k1, k2;
-    DBuf<uint32_t> i0, i1, i2;
-    pa.need(m, s);
-    pb.need(m, s);
-    ln.need(m, s);
-    i0.need(m, s);
-    k_mem_pack<<<mem_grid(ns), kMB, 0, s>>>(mpa.p, mpb.p, mlen.p, keep.p, kpos.p, ns, pa.p, pb.p,
-                                           ln.p, i0.p);
-    HIP_CHECK(hipGetLastError());
-    k1.need(m, s);
-    k2.need(m, s);
-    i1.need(m, s);
-    i2.need(m, s);
-    const int bb = bits_for(lb), ab = bits_for(la);
-    size_t t1 = 0, t2 = 0;
-    HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, t1, pb.p, k1.p, i0.p, i1.p, (int)m, 0,
-                                                 bb, s));
-    HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, t2, k2.p, k1.p, i1.p, i2.p, (int)m, 0,
-                                                 ab, s));
-    stmp.need(std::max<size_t>(std::max(t1, t2), 4), s);
-    t1 = std::max(t1, t2);
-    HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(stmp.p, t1, pb.p, k1.p, i0.p, i1.p, (int)m, 0,
-                                                 bb, s));
-    k_mem_gather<<<mem_grid(m), kMB, 0, s>>>(pa.p, i1.p, m, k2.p);
-    HIP_CHECK(hipGetLastError());
-    HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(stmp.p, t1, k2.p, k1.p, i1.p, i2.p, (int)m, 0,
-                                                 ab, s));
-    // k1: starts in a in order, i2: the match each came from
-    DBuf<uint64_t> flag, fpos;
-    flag.need(m, s);
-    fpos.need(m + 1, s);
-    k_mem_first<<<mem_grid(m), kMB, 0, s>>>(k1.p, pb.p, i2.p, m, flag.p);
-    HIP_CHECK(hipGetLastError());
-    ktmp.need(std::max<size_t>(scan_tmp_words(m), 1), s);
-    scan_exclusive(flag.p, fpos.p, m, ktmp.p, s);
-    const uint64_t count = read_dev(fpos.p + m, s);
-    if (cap) {
-      k_mem_out<<<mem_grid(m), kMB, 0, s>>>(k1.p, pb.p, ln.p, i2.p, flag.p, fpos.p, m, cap, d_pa,
-                                           d_pb, d_len);
-      HIP_CHECK(hipGetLastError());
-    }
-    sync(s);
-    *n_mems = count;
+    mems_core(g, 1, &a, &b, level, min_len, cap, nullptr, d_pa, d_pb, d_len, n_mems, stream);
+  });
+}
+
+lcg_status lcg_mems_batch(lcg_grammar_t g, uint32_t npairs, const uint32_t* a, const uint32_t* b,
+                          uint32_t level, uint64_t min_len, uint64_t cap, uint32_t* d_pair,
+                          uint64_t* d_pa, uint64_t* d_pb, uint64_t* d_len, uint64_t* n_mems,
+                          hipStream_t stream) {
+  return guard([&] {
+    live(g);
+    if (!n_mems) throw LcgError{LCG_EINVAL, "n_mems is NULL"};
+    if (cap && !d_pair) throw LcgError{LCG_EINVAL, "NULL output array"};
+    mems_core(g, npairs, a, b, level, min_len, cap, d_pair, d_pa, d_pb, d_len, n_mems, stream);
   });
 }
 

@@ -36,7 +36,8 @@ EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_res
            "lcg_slp_expand_strings", "lcg_slp_free", "lcg_extract", "lcg_build_file", "lcg_lce",
            "lcg_slp_encode", "lcg_slp_decode", "lcg_symbol_lce", "lcg_set_allocator",
            "lcg_slp_extract", "lcg_export", "lcg_host_free", "lcg_session_new",
-           "lcg_session_admit", "lcg_session_step", "lcg_session_free", "lcg_mems")
+           "lcg_session_admit", "lcg_session_step", "lcg_session_free", "lcg_mems",
+           "lcg_mems_batch")
 
 EXTRACT_MAX = 2048
 
@@ -180,6 +181,10 @@ def lib():
                            ctypes.c_uint64, ctypes.c_uint64, vp, vp, vp,
                            ctypes.POINTER(ctypes.c_uint64), vp]
     L.lcg_mems.restype = st
+    L.lcg_mems_batch.argtypes = [vp, ctypes.c_uint32, vp, vp, ctypes.c_uint32, ctypes.c_uint64,
+                                 ctypes.c_uint64, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64),
+                                 vp]
+    L.lcg_mems_batch.restype = st
     L.lcg_export.argtypes = [vp, ctypes.POINTER(HostGrammar)]
     L.lcg_export.restype = st
     L.lcg_host_free.argtypes = [ctypes.POINTER(HostGrammar)]
@@ -422,6 +427,29 @@ class Grammar:
                                   _stream(stream)))
             if n.value <= cap:
                 return tuple(t[:n.value] for t in out)
+            cap = n.value
+
+    def mems_batch(self, a, b, level, min_len, cap=1 << 20, stream=None):
+        """lcg_mems for the pairs (a[p], b[p]) in one call (lcg_mems_batch):
+        (pair, start in a, start in b, length) as int32 / int64 device
+        tensors sorted by pair, then start in a, then start in b."""
+        import numpy as np
+        import torch
+        ha = np.ascontiguousarray(a, np.uint32)
+        hb = np.ascontiguousarray(b, np.uint32)
+        if ha.shape != hb.shape:
+            raise ValueError("a and b must hold the same number of strings")
+        n = ctypes.c_uint64()
+        while True:
+            pair = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+            out = [torch.empty(max(cap, 1), dtype=torch.int64, device="cuda") for _ in range(3)]
+            _check(lib().lcg_mems_batch(self.h, len(ha), ha.ctypes.data_as(ctypes.c_void_p),
+                                        hb.ctypes.data_as(ctypes.c_void_p), level, min_len, cap,
+                                        ctypes.c_void_p(pair.data_ptr()),
+                                        *(ctypes.c_void_p(t.data_ptr()) for t in out),
+                                        ctypes.byref(n), _stream(stream)))
+            if n.value <= cap:
+                return (pair[:n.value],) + tuple(t[:n.value] for t in out)
             cap = n.value
 
     def postprocess(self, rl=True, simp=True, stream=None):
