@@ -519,6 +519,70 @@ __global__ __launch_bounds__(kMPT) void k_mem_parse_top(const LevelPtrs* __restr
   }
 }
 
+// The first and the last (up to) 8 bytes of every rule's expansion, level by
+// level: head holds byte t of the expansion in bits 8t.., tail byte n-1-t in
+// bits 8t.. (the last byte lowest); bytes past the expansion are zero.
+__global__ __launch_bounds__(kMB) void k_mem_ends1(const uint64_t* __restrict__ off,
+                                                   const uint8_t* __restrict__ rhs, uint32_t u,
+                                                   uint64_t* __restrict__ head,
+                                                   uint64_t* __restrict__ tail) {
+  for (uint32_t r = blockIdx.x * kMB + threadIdx.x; r < u; r += gridDim.x * kMB) {
+    const uint64_t a = off[r], n = off[r + 1] - a, k = n < 8 ? n : 8;
+    uint64_t h = 0, t = 0;
+    for (uint64_t i = 0; i < k; ++i) {
+      h |= (uint64_t)rhs[a + i] << (8 * i);
+      t |= (uint64_t)rhs[a + n - 1 - i] << (8 * i);
+    }
+    head[r] = h;
+    tail[r] = t;
+  }
+}
+
+// levels >= 2: from the children's ends and expansion lengths
+__global__ __launch_bounds__(kMB) void k_mem_ends(const uint64_t* __restrict__ off,
+                                                  const uint32_t* __restrict__ rhs, uint32_t u,
+                                                  const uint64_t* __restrict__ elen_c,
+                                                  const uint64_t* __restrict__ head_c,
+                                                  const uint64_t* __restrict__ tail_c,
+                                                  uint64_t* __restrict__ head,
+                                                  uint64_t* __restrict__ tail) {
+  for (uint32_t r = blockIdx.x * kMB + threadIdx.x; r < u; r += gridDim.x * kMB) {
+    const uint64_t a = off[r], b = off[r + 1];
+    uint64_t h = 0, t = 0;
+    uint32_t got = 0;
+    for (uint64_t x = a; x < b && got < 8; ++x) {
+      const uint32_t c = rhs[x];
+      const uint64_t k = min<uint64_t>(8 - got, elen_c[c]);
+      h |= (head_c[c] & (k == 8 ? ~0ull : ((1ull << (8 * k)) - 1))) << (8 * got);
+      got += (uint32_t)k;
+    }
+    got = 0;
+    for (uint64_t x = b; x > a && got < 8; --x) {
+      const uint32_t c = rhs[x - 1];
+      const uint64_t k = min<uint64_t>(8 - got, elen_c[c]);
+      t |= (tail_c[c] & (k == 8 ? ~0ull : ((1ull << (8 * k)) - 1))) << (8 * got);
+      got += (uint32_t)k;
+    }
+    head[r] = h;
+    tail[r] = t;
+  }
+}
+
+// The common prefix (with BACK, suffix) of exp(X) and exp(Y), lengths nx and
+// ny, from their 8-byte ends when it ends inside them: the count of equal
+// bytes, or kNoEnd when the first min(8, nx, ny) bytes are all equal and both
+// are longer than that (the cursor walk decides).
+constexpr uint64_t kNoEnd = ~0ull;
+
+__device__ __forceinline__ uint64_t ends_common(uint64_t ex, uint64_t ey, uint64_t nx,
+                                                uint64_t ny) {
+  const uint64_t km = min(min(nx, ny), (uint64_t)8);
+  const uint64_t d = ex ^ ey;
+  const uint64_t c = d ? (uint64_t)(__builtin_ctzll(d) >> 3) : 8;
+  if (c < km) return c;
+  return km == min(nx, ny) ? km : kNoEnd;
+}
+
 // expansion length of every symbol of the level-l parse
 __global__ __launch_bounds__(kMB) void k_mem_elen(const uint64_t* __restrict__ explen_l,
                                                   const uint32_t* __restrict__ cur, uint64_t n,
@@ -630,6 +694,7 @@ constexpr int kMemRun = 64;
 
 __global__ __launch_bounds__(64) void k_mem_extend(
     const LevelPtrs* __restrict__ lv_ptr, const uint64_t* const* __restrict__ explen, int level,
+    const uint64_t* __restrict__ head, const uint64_t* __restrict__ tail,
     const MemPair* __restrict__ pairs, const uint32_t* __restrict__ F,
     const uint64_t* __restrict__ G, const uint32_t* __restrict__ sp,
     const uint32_t* __restrict__ si, const uint32_t* __restrict__ sj, uint64_t ns,
@@ -643,7 +708,9 @@ __global__ __launch_bounds__(64) void k_mem_extend(
     uint64_t back = 0;
     if (i > M.sa && j > M.sb) {
       const uint64_t nx = G[i] - G[i - 1], ny = G[j] - G[j - 1];
-      back = lce_walk<true>(lv_ptr, explen, level, F[i - 1], nx, nx, level, F[j - 1], ny, ny);
+      const uint32_t X = F[i - 1], Y = F[j - 1];
+      back = ends_common(tail[X], tail[Y], nx, ny);
+      if (back == kNoEnd) back = lce_walk<true>(lv_ptr, explen, level, X, nx, nx, level, Y, ny, ny);
       if (back == nx || back == ny)
         back += lce_walk<true>(lv_ptr, explen, M.ta, M.ya, x - back, M.la, M.tb, M.yb, y - back,
                                M.lb);
@@ -661,7 +728,9 @@ __global__ __launch_bounds__(64) void k_mem_extend(
       bool rest = run == kMemRun;
       if (!rest) {
         const uint64_t nx = G[ii + 1] - G[ii], ny = G[jj + 1] - G[jj];
-        const uint64_t l1 = lce_walk<false>(lv_ptr, explen, level, F[ii], 0, nx, level, F[jj], 0, ny);
+        const uint32_t X = F[ii], Y = F[jj];
+        uint64_t l1 = ends_common(head[X], head[Y], nx, ny);
+        if (l1 == kNoEnd) l1 = lce_walk<false>(lv_ptr, explen, level, X, 0, nx, level, Y, 0, ny);
         fwd += l1;
         rest = l1 == nx || l1 == ny;
       }
@@ -734,6 +803,31 @@ inline int bits_for(uint64_t v) {  // radix-sort key width that holds 0..v
   int b = 1;
   while (b < 64 && (v >> b)) ++b;
   return b;
+}
+
+// the 8-byte ends of levels 1..level, kept with the grammar until it changes
+void ensure_ends(lcg_grammar* g, uint32_t level, hipStream_t s) {
+  if (g->ends_version != g->version) {
+    g->ends_first.clear();
+    g->ends_last.clear();
+    g->ends_version = g->version;
+  }
+  for (uint32_t l = (uint32_t)g->ends_first.size() + 1; l <= level; ++l) {
+    const Level& L = g->levels[l - 1];
+    DBuf<uint64_t> h, t;
+    h.need(std::max<uint32_t>(L.u, 1), s);
+    t.need(std::max<uint32_t>(L.u, 1), s);
+    if (l == 1) {
+      k_mem_ends1<<<mem_grid(L.u), kMB, 0, s>>>(L.off.p, L.rhs8.p, L.u, h.p, t.p);
+    } else {
+      k_mem_ends<<<mem_grid(L.u), kMB, 0, s>>>(L.off.p, L.rhs32.p, L.u, g->explen[l - 2].p,
+                                              g->ends_first[l - 2].p, g->ends_last[l - 2].p, h.p,
+                                              t.p);
+    }
+    HIP_CHECK(hipGetLastError());
+    g->ends_first.push_back(std::move(h));
+    g->ends_last.push_back(std::move(t));
+  }
 }
 
 inline void scan_into(DBuf<uint64_t>& tmp, const uint64_t* in, uint64_t* out, uint64_t n,
@@ -962,9 +1056,11 @@ void mems_core(lcg_grammar* g, uint32_t np, const uint32_t* ha, const uint32_t* 
   mpb.need(ns, s);
   mlen.need(ns, s);
   keep.need(ns, s);
+  ensure_ends(g, level, s);
   k_mem_extend<<<(unsigned)std::min<uint64_t>((ns + 63) / 64, 65536), 64, 0, s>>>(
-      g->level_ptrs.p, g->explen_ptrs.p, (int)level, pairs.p, F.p, G.p, sp.p, si.p, sj.p, ns,
-      min_len, mpa.p, mpb.p, mlen.p, keep.p);
+      g->level_ptrs.p, g->explen_ptrs.p, (int)level, g->ends_first[level - 1].p,
+      g->ends_last[level - 1].p, pairs.p, F.p, G.p, sp.p, si.p, sj.p, ns, min_len, mpa.p, mpb.p,
+      mlen.p, keep.p);
   HIP_CHECK(hipGetLastError());
   kpos.need(ns + 1, s);
   scan_into(tmp, keep.p, kpos.p, ns, s);

@@ -289,6 +289,10 @@ struct lcg_grammar {
   lcg::DBuf<const uint64_t*> explen_ptrs;
   lcg::DBuf<lcg::LevelPtrs> level_ptrs;  // per level: offsets and right-hand sides
   uint64_t explen_version = ~0ull;
+  // per rule of levels 1..ends_first.size(): the first and the last (up to)
+  // 8 bytes of its expansion (for lcg_mems); valid while ends_version == version
+  std::vector<lcg::DBuf<uint64_t>> ends_first, ends_last;
+  uint64_t ends_version = ~0ull;
   // set when a failed call could not restore the grammar: later calls refuse it
   bool poisoned = false;
   // reserve[i]: the rules lcg_reserve made dictionary room for at level i+1
