@@ -1,11 +1,14 @@
-// Random access into a level grammar: bytes [start, start + len) of string j
-// without expanding the rest of the string (the grammar's expansion lengths
-// locate every symbol, Sec. 2.2's exp(X) per rule).  One wave (one block for
-// queries longer than 256 bytes) answers one query: starting from C[j] it
-// keeps, level by level, only the symbols whose
-// expansion overlaps the range -- they cover disjoint pieces of at least one
-// byte each, so there are never more than len of them -- and the level-1
-// symbols finally write their bytes.
+// Queries on a level grammar without decompressing it: random access, the
+// longest common extensions of App. B's match completion, and its maximal
+// exact matches.
+//
+// Random access: bytes [start, start + len) of string j without expanding the
+// rest of the string (the grammar's expansion lengths locate every symbol,
+// Sec. 2.2's exp(X) per rule).  One wave (one block for queries longer than
+// 256 bytes) answers one query: starting from C[j] it keeps, level by level,
+// only the symbols whose expansion overlaps the range -- they cover disjoint
+// pieces of at least one byte each, so there are never more than len of
+// them -- and the level-1 symbols finally write their bytes.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
