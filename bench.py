@@ -875,6 +875,41 @@ def extra_legs(args, out, text, off, t, o, n, k, seed):
                          "build_ms": round(info["build_s"] * 1e3, 3)}
         print("[bench] stream from file: %.2f ms (%s)" % (st_s * 1e3, info), file=sys.stderr,
               flush=True)
+        # the same file with the sink in host memory and flush cycles: the
+        # buffer grammar is merged into the sink whenever it holds 1 GiB of
+        # device memory; the result must equal the one-call build
+        ref = lcg.new(seed)
+        lcg.build_file(ref, path, chunk_bytes=64 << 20)
+        want = ref.export()
+        ref.free()
+        kts = []
+        for i in range(max(1, min(args.steps, 3))):
+            g = lcg.new(seed)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sinfo = lcg.build_file_sink(g, path, 1 << 30, chunk_bytes=64 << 20)
+            torch.cuda.synchronize()
+            kts.append(time.perf_counter() - t0)
+            if i == 0:
+                got = g.export()
+                same = all(np.array_equal(a[f], b[f]) for a, b in zip(got["levels"], want["levels"])
+                           for f in ("rhs_off", "rhs", "fp")) and \
+                    len(got["levels"]) == len(want["levels"]) and \
+                    np.array_equal(got["c_sym"], want["c_sym"])
+                if not same:
+                    raise SystemExit("lcg_build_file_sink differs from lcg_build_file")
+            g.free()
+        sk_s = float(np.mean(kts))
+        out["stream_sink"] = {"what": "lcg_build_file_sink of the same file: the sink's levels in "
+                                      "host memory while streaming, the buffer grammar merged into "
+                                      "it at 1 GiB of device memory (result checked against "
+                                      "lcg_build_file)",
+                              "ms": round(sk_s * 1e3, 3), "gbps": round(n / sk_s / 1e9, 3),
+                              "chunks": sinfo["chunks"], "flushes": sinfo["flushes"],
+                              "flush_ms": round(sinfo["flush_s"] * 1e3, 3),
+                              "build_ms": round(sinfo["build_s"] * 1e3, 3)}
+        print("[bench] stream with a host sink: %.2f ms (%s)" % (sk_s * 1e3, sinfo),
+              file=sys.stderr, flush=True)
     finally:
         os.unlink(path)
 

@@ -287,6 +287,29 @@ lcg_status lcg_tune(const uint8_t* d_text, const uint64_t* d_offsets, uint32_t k
  */
 lcg_status lcg_build_file(lcg_grammar_t g, const char* path, uint64_t chunk_bytes,
                           const lcg_opts* opts, hipStream_t stream, uint64_t* h_info);
+/*
+ * Streaming build with a sink outside device memory (App. A.3's flush
+ * cycle on one device): the file is read and split as for lcg_build_file,
+ * but while it streams, the levels of `sink` (the running grammar, possibly
+ * non-empty) sit in pinned host memory.  Chunks are compressed into a buffer
+ * grammar on the device; once the buffer holds buffer_bytes of device memory
+ * or more (0: after every chunk), and at the end, it is merged into the sink
+ * (MergeGrams, one level of the sink on the device at a time, with the level
+ * below it) and freed.  Device memory while streaming is thus bounded by the
+ * buffer, one chunk's working memory and two of the sink's levels.  At the
+ * end the sink returns to the device; the result equals lcg_build_into of
+ * the whole file at once.  The buffer does not consult the sink while it
+ * compresses (it may relearn rules the sink has; the merge drops them).  The
+ * sink's round statistics do not cover the streamed strings.
+ *   h_info  NULL or uint64[8]: as for lcg_build_file, then the number of
+ *           flushes and the ns spent in them
+ * Errors: those of lcg_build_file; LCG_ENOMEM also for pinned host memory.
+ * A call that fails after its first flush leaves the sink refused by later
+ * calls (it may hold part of the file).
+ */
+lcg_status lcg_build_file_sink(lcg_grammar_t sink, const char* path, uint64_t chunk_bytes,
+                               uint64_t buffer_bytes, const lcg_opts* opts, hipStream_t stream,
+                               uint64_t* h_info);
 
 /*
  * Random access (the inverse path without expanding whole strings): for every

@@ -251,6 +251,33 @@ struct DBuf {
 };
 
 // ------------------------------------------------------------------ grammar
+// Pinned host memory holding a level moved out of device memory.
+struct HostCopy {
+  void* p = nullptr;
+  HostCopy() = default;
+  HostCopy(const HostCopy&) = delete;
+  HostCopy& operator=(const HostCopy&) = delete;
+  HostCopy(HostCopy&& o) noexcept : p(o.p) { o.p = nullptr; }
+  HostCopy& operator=(HostCopy&& o) noexcept {
+    if (this != &o) { reset(); p = o.p; o.p = nullptr; }
+    return *this;
+  }
+  ~HostCopy() { reset(); }
+  void reset() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+  }
+  void* need(size_t bytes) {
+    reset();
+    if (hipHostMalloc(&p, std::max<size_t>(bytes, 64), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      throw LcgError{LCG_ENOMEM, "pinned host allocation failed"};
+    }
+    return p;
+  }
+};
+
 struct Level {
   uint32_t u = 0;      // rules
   uint64_t q = 0;      // total rhs length
@@ -260,6 +287,10 @@ struct Level {
   DBuf<uint32_t> fp;   // F^i of each rule
   DBuf<Slot> table;    // dictionary H^i: every committed rule holds one slot
   uint64_t tcap = 0;
+  // while on_host the arrays above are released and their contents sit in
+  // pinned host memory (a sink grammar between flushes of a streaming build)
+  bool on_host = false;
+  HostCopy h_off, h_rhs, h_fp, h_table;
 };
 
 using Stat = std::array<uint64_t, LCG_STATS_FIELDS>;
@@ -328,6 +359,12 @@ inline T read_dev(const T* p, hipStream_t s) {
 // expansion lengths (and the per-level device tables) of g, computed once
 // per version of the grammar
 void ensure_explen(lcg_grammar* g, hipStream_t s);
+// A sink grammar (App. A.3): its levels moved to pinned host memory and back,
+// and the merge of a buffer grammar into it one level at a time.
+void sink_to_host(lcg_grammar* g, hipStream_t s);
+void sink_to_device(lcg_grammar* g, hipStream_t s);
+void sink_flush(lcg_grammar* sink, const lcg_grammar* buf, hipStream_t s);
+uint64_t device_bytes(const lcg_grammar* g);
 
 template <typename F>
 lcg_status guard(F&& f) {

@@ -909,7 +909,15 @@ static void build_core(lcg_grammar* g, const uint8_t* d_text, const uint64_t* d_
 }
 
 // MergeGrams(a, b): a absorbs b level by level (Sec. 3.6).
-static void merge_core(lcg_grammar* a, const lcg_grammar* b, Work& w, hipStream_t s) {
+static void level_to_host(Level& L, bool bytes, hipStream_t s);
+static void level_to_device(Level& L, bool bytes, hipStream_t s);
+
+// MergeGrams (Sec. 3.6) of b into a.  With a_host, a's levels sit in pinned
+// host memory and come to the device one at a time: level lv while its rules
+// are merged, with level lv - 1 (whose fingerprints name lv's keys) kept until
+// lv is done.
+static void merge_core(lcg_grammar* a, const lcg_grammar* b, Work& w, hipStream_t s,
+                       bool a_host = false) {
   ++a->version;
   if (a->seed != b->seed) throw LcgError{LCG_ESEED, "grammars use different hash families"};
   const uint32_t ka = a->k, kb = b->k;
@@ -923,6 +931,7 @@ static void merge_core(lcg_grammar* a, const lcg_grammar* b, Work& w, hipStream_
   int cur = 0;
   const uint32_t* remap_prev = nullptr;
   for (size_t lv = 1; lv <= b->levels.size(); ++lv) {
+    if (a_host && lv <= a->levels.size()) level_to_device(a->levels[lv - 1], lv == 1, s);
     ensure_level(a, lv, s);
     const Level& B = b->levels[lv - 1];
     const bool bytes = lv == 1;
@@ -952,9 +961,90 @@ static void merge_core(lcg_grammar* a, const lcg_grammar* b, Work& w, hipStream_
     }
     remap_prev = w.remap[cur].p;
     cur ^= 1;
+    if (a_host && lv >= 2) level_to_host(a->levels[lv - 2], lv == 2, s);
   }
+  if (a_host && !b->levels.empty())
+    level_to_host(a->levels[b->levels.size() - 1], b->levels.size() == 1, s);
   a->k += kb;
   sync(s);
+}
+
+// a level's arrays to pinned host memory (released on the device), and back
+static void level_to_host(Level& L, bool bytes, hipStream_t s) {
+  if (L.on_host) return;
+  const size_t rb = L.q * (bytes ? 1 : 4);
+  HIP_CHECK(hipMemcpyAsync(L.h_off.need((L.u + 1) * 8ull), L.off.p, (L.u + 1) * 8ull,
+                           hipMemcpyDeviceToHost, s));
+  if (rb)
+    HIP_CHECK(hipMemcpyAsync(L.h_rhs.need(rb), bytes ? (const void*)L.rhs8.p : (const void*)L.rhs32.p,
+                             rb, hipMemcpyDeviceToHost, s));
+  if (L.u)
+    HIP_CHECK(hipMemcpyAsync(L.h_fp.need(L.u * 4ull), L.fp.p, L.u * 4ull, hipMemcpyDeviceToHost, s));
+  if (L.tcap && L.table.p)
+    HIP_CHECK(hipMemcpyAsync(L.h_table.need(L.tcap * sizeof(Slot)), L.table.p,
+                             L.tcap * sizeof(Slot), hipMemcpyDeviceToHost, s));
+  sync(s);
+  L.off.reset();
+  L.rhs8.reset();
+  L.rhs32.reset();
+  L.fp.reset();
+  L.table.reset();
+  L.on_host = true;
+}
+
+static void level_to_device(Level& L, bool bytes, hipStream_t s) {
+  if (!L.on_host) return;
+  const size_t rb = L.q * (bytes ? 1 : 4);
+  L.off.need(L.u + 1, s);
+  HIP_CHECK(hipMemcpyAsync(L.off.p, L.h_off.p, (L.u + 1) * 8ull, hipMemcpyHostToDevice, s));
+  if (rb) {
+    if (bytes) {
+      L.rhs8.need(L.q, s);
+      HIP_CHECK(hipMemcpyAsync(L.rhs8.p, L.h_rhs.p, rb, hipMemcpyHostToDevice, s));
+    } else {
+      L.rhs32.need(L.q, s);
+      HIP_CHECK(hipMemcpyAsync(L.rhs32.p, L.h_rhs.p, rb, hipMemcpyHostToDevice, s));
+    }
+  }
+  if (L.u) {
+    L.fp.need(L.u, s);
+    HIP_CHECK(hipMemcpyAsync(L.fp.p, L.h_fp.p, L.u * 4ull, hipMemcpyHostToDevice, s));
+  }
+  if (L.tcap && L.h_table.p) {
+    L.table.need(L.tcap, s);
+    HIP_CHECK(hipMemcpyAsync(L.table.p, L.h_table.p, L.tcap * sizeof(Slot), hipMemcpyHostToDevice,
+                             s));
+  }
+  sync(s);
+  L.h_off.reset();
+  L.h_rhs.reset();
+  L.h_fp.reset();
+  L.h_table.reset();
+  L.on_host = false;
+}
+
+void sink_to_host(lcg_grammar* g, hipStream_t s) {
+  ++g->version;  // cached device views of the levels are stale
+  for (size_t i = 0; i < g->levels.size(); ++i) level_to_host(g->levels[i], i == 0, s);
+}
+
+void sink_to_device(lcg_grammar* g, hipStream_t s) {
+  ++g->version;
+  for (size_t i = 0; i < g->levels.size(); ++i) level_to_device(g->levels[i], i == 0, s);
+}
+
+void sink_flush(lcg_grammar* sink, const lcg_grammar* buf, hipStream_t s) {
+  Work w;
+  merge_core(sink, buf, w, s, true);
+}
+
+// device memory a grammar holds in its levels and C
+uint64_t device_bytes(const lcg_grammar* g) {
+  uint64_t b = g->c_level.cap + 4ull * g->c_sym.cap;
+  for (const Level& L : g->levels)
+    b += 8ull * L.off.cap + L.rhs8.cap + 4ull * L.rhs32.cap + 4ull * L.fp.cap +
+         sizeof(Slot) * L.table.cap;
+  return b;
 }
 
 static std::vector<uint64_t> fetch_offsets(const uint64_t* d_off, uint32_t k, hipStream_t s) {

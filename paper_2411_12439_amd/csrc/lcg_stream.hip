@@ -214,12 +214,16 @@ double now_s() {
 
 using namespace lcg;
 
-extern "C" {
+namespace {
 
-lcg_status lcg_build_file(lcg_grammar_t g, const char* path, uint64_t chunk_bytes,
-                          const lcg_opts* opts, hipStream_t stream, uint64_t* h_info) {
-  return guard([&] {
-    live(g);
+// The streaming build.  With sink, g is the sink of App. A.3: its levels stay
+// in pinned host memory while the chunks are compressed into a buffer
+// grammar on the device, which is merged into the sink (one level of the sink
+// on the device at a time) whenever the buffer holds buffer_bytes of device
+// memory or more, and at the end; then the sink returns to the device.
+void build_file(lcg_grammar* g, const char* path, uint64_t chunk_bytes, const lcg_opts* opts,
+                hipStream_t stream, uint64_t* h_info, bool sink, uint64_t buffer_bytes) {
+  {
     if (!path) throw LcgError{LCG_EINVAL, "path is NULL"};
     if (chunk_bytes < 4096 || chunk_bytes > (1ull << 36))
       throw LcgError{LCG_EINVAL, "chunk_bytes must be in 4 KiB .. 64 GiB"};
@@ -252,16 +256,34 @@ lcg_status lcg_build_file(lcg_grammar_t g, const char* path, uint64_t chunk_byte
     });
     hipStream_t copy_s = nullptr;
     hipEvent_t copied[2] = {nullptr, nullptr};
-    uint64_t strings = 0, bytes = 0, chunks = 0;
-    double wait_s = 0, build_s = 0;
+    uint64_t strings = 0, bytes = 0, chunks = 0, flushes = 0;
+    double wait_s = 0, build_s = 0, flush_s = 0;
+    lcg_grammar_t buf = nullptr;  // the buffer grammar (sink mode)
+    bool touched = false;         // a flush has started: the sink holds part of the stream
+    auto new_buffer = [&] {
+      const lcg_status st = lcg_new(g->seed, &buf);
+      if (st != LCG_OK) throw LcgError{st, std::string("buffer grammar: ") + lcg_last_error()};
+    };
+    auto flush = [&] {
+      const double tf = now_s();
+      touched = true;
+      sink_flush(g, buf, stream);
+      lcg_free(buf);
+      buf = nullptr;
+      ++flushes;
+      flush_s += now_s() - tf;
+    };
     auto finish = [&] {
       pipe.stop();
       reader.join();
+      if (buf) lcg_free(buf);
+      buf = nullptr;
       for (auto& e : copied)
         if (e) (void)hipEventDestroy(e);
       if (copy_s) (void)hipStreamDestroy(copy_s);
     };
     try {
+      if (sink) sink_to_host(g, stream);
       HIP_CHECK(hipStreamCreateWithFlags(&copy_s, hipStreamNonBlocking));
       for (auto& e : copied) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       DBuf<uint8_t> raw[2], text;
@@ -318,11 +340,13 @@ lcg_status lcg_build_file(lcg_grammar_t g, const char* path, uint64_t chunk_byte
           if (tail) k_set_u64<<<1, 1, 0, stream>>>(off.p + k, n - nl);
           if (k) {
             const double tb = now_s();
+            if (sink && !buf) new_buffer();
             const lcg_status st =
-                lcg_build_into(g, text.p, off.p, (uint32_t)k, &o, stream, nullptr);
+                lcg_build_into(sink ? buf : g, text.p, off.p, (uint32_t)k, &o, stream, nullptr);
             build_s += now_s() - tb;
             if (st != LCG_OK) throw LcgError{st, std::string("chunk ") + std::to_string(chunks) +
                                                      ": " + lcg_last_error()};
+            if (sink && device_bytes(buf) >= buffer_bytes) flush();
           }
           strings += k;
           bytes += n - nl;
@@ -334,8 +358,20 @@ lcg_status lcg_build_file(lcg_grammar_t g, const char* path, uint64_t chunk_byte
         slot ^= 1;
       }
       sync(copy_s);
+      if (sink) {
+        if (buf) flush();
+        sink_to_device(g, stream);
+      }
     } catch (...) {
       finish();
+      if (sink) {
+        if (touched) g->poisoned = true;  // it may hold part of the stream: refused from now on
+        try {
+          sink_to_device(g, stream);
+        } catch (...) {
+          g->poisoned = true;
+        }
+      }
       throw;
     }
     finish();
@@ -346,7 +382,32 @@ lcg_status lcg_build_file(lcg_grammar_t g, const char* path, uint64_t chunk_byte
       h_info[3] = (uint64_t)((now_s() - t0) * 1e9);
       h_info[4] = (uint64_t)(wait_s * 1e9);
       h_info[5] = (uint64_t)(build_s * 1e9);
+      if (sink) {
+        h_info[6] = flushes;
+        h_info[7] = (uint64_t)(flush_s * 1e9);
+      }
     }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+lcg_status lcg_build_file(lcg_grammar_t g, const char* path, uint64_t chunk_bytes,
+                          const lcg_opts* opts, hipStream_t stream, uint64_t* h_info) {
+  return guard([&] {
+    live(g);
+    build_file(g, path, chunk_bytes, opts, stream, h_info, false, 0);
+  });
+}
+
+lcg_status lcg_build_file_sink(lcg_grammar_t sink, const char* path, uint64_t chunk_bytes,
+                               uint64_t buffer_bytes, const lcg_opts* opts, hipStream_t stream,
+                               uint64_t* h_info) {
+  return guard([&] {
+    live(sink);
+    build_file(sink, path, chunk_bytes, opts, stream, h_info, true, buffer_bytes);
   });
 }
 

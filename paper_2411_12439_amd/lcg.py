@@ -37,7 +37,7 @@ EXPORTS = ("lcg_opts_init", "lcg_build", "lcg_build_into", "lcg_merge", "lcg_res
            "lcg_slp_encode", "lcg_slp_decode", "lcg_symbol_lce", "lcg_set_allocator",
            "lcg_slp_extract", "lcg_export", "lcg_host_free", "lcg_session_new",
            "lcg_session_admit", "lcg_session_step", "lcg_session_free", "lcg_mems",
-           "lcg_mems_batch")
+           "lcg_mems_batch", "lcg_build_file_sink")
 
 EXTRACT_MAX = 2048
 
@@ -172,6 +172,9 @@ def lib():
     L.lcg_build_file.argtypes = [vp, ctypes.c_char_p, ctypes.c_uint64, ctypes.POINTER(Opts), vp,
                                  u64p]
     L.lcg_build_file.restype = st
+    L.lcg_build_file_sink.argtypes = [vp, ctypes.c_char_p, ctypes.c_uint64, ctypes.c_uint64,
+                                      ctypes.POINTER(Opts), vp, u64p]
+    L.lcg_build_file_sink.restype = st
     L.lcg_extract.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, vp, vp, vp]
     L.lcg_lce.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, vp, ctypes.c_uint32, vp, vp]
     L.lcg_lce.restype = st
@@ -693,6 +696,20 @@ def build_file(g, path, chunk_bytes=64 << 20, stream=None, **opts):
                                 _stream(stream), _ptr(info, ctypes.c_uint64)))
     return {"bytes": int(info[0]), "strings": int(info[1]), "chunks": int(info[2]),
             "wall_s": info[3] / 1e9, "read_wait_s": info[4] / 1e9, "build_s": info[5] / 1e9}
+
+
+def build_file_sink(g, path, buffer_bytes, chunk_bytes=64 << 20, stream=None, **opts):
+    """Stream a file into the sink grammar g with flush cycles (lcg_build_file_sink):
+    g's levels wait in pinned host memory while chunks go into a buffer grammar
+    that is merged into g once it holds buffer_bytes of device memory.  Returns
+    the build_file dictionary plus {"flushes", "flush_s"}."""
+    o = make_opts(g.info()[0], **opts)
+    info = np.zeros(8, np.uint64)
+    _check(lib().lcg_build_file_sink(g.h, os.fsencode(path), chunk_bytes, buffer_bytes,
+                                     ctypes.byref(o), _stream(stream), _ptr(info, ctypes.c_uint64)))
+    return {"bytes": int(info[0]), "strings": int(info[1]), "chunks": int(info[2]),
+            "wall_s": info[3] / 1e9, "read_wait_s": info[4] / 1e9, "build_s": info[5] / 1e9,
+            "flushes": int(info[6]), "flush_s": info[7] / 1e9}
 
 
 def tune(text, offsets, seed=0, stream=None, cache=None, **base):

@@ -1,5 +1,6 @@
-"""Streaming builds from a file (lcg_build_file) against the oracle's build of
-the same strings.
+"""Streaming builds from a file (lcg_build_file, and lcg_build_file_sink with
+its sink in host memory and flush cycles) against the oracle's build of the
+same strings.
 
 Ranks are numbered by first occurrence (string order, then position), so
 compressing the file chunk by chunk into a running grammar must give the
@@ -115,5 +116,70 @@ def test_file_errors(L):
         g = L.new(SEED)
         info = L.build_file(g, path, chunk_bytes=4096)
         assert info["strings"] == 0 and g.info()[2] == 0
+    finally:
+        os.unlink(path)
+
+
+@pytest.mark.parametrize("buffer_bytes", [0, 48 << 20, 1 << 40])
+def test_sink_flush_cycles_equal_the_oracle(L, buffer_bytes):
+    """lcg_build_file_sink: the sink's levels wait in host memory while chunks
+    go into a buffer grammar, merged into the sink whenever it holds
+    buffer_bytes of device memory (0: after every chunk; a huge value: once, at
+    the end).  The sink, non-empty at the start, ends with the oracle's
+    grammar of all strings, rank for rank."""
+    from oracle import oracle as O
+    text, off = D.make_config("bacterial", scale=0.01)
+    strings = _strings(text, off)
+    first = len(strings) // 4
+    path = _write(strings[first:])
+    try:
+        ta, oa = L.to_device(*O.pack(strings[:first]))
+        g = L.build(ta, oa, seed=SEED)
+        info = L.build_file_sink(g, path, buffer_bytes, chunk_bytes=200 << 10)
+        print(info, flush=True)
+        assert info["strings"] == len(strings) - first
+        if buffer_bytes == 0:
+            assert info["flushes"] == info["chunks"] >= 4
+        elif buffer_bytes == 1 << 40:
+            assert info["flushes"] == 1
+        else:
+            assert 1 <= info["flushes"] <= info["chunks"]
+        _assert_same(g.export(), O.build(*O.pack(strings), SEED).export())
+        out, offs = g.expand_strings()
+        assert np.array_equal(out.cpu().numpy(), O.pack(strings)[0])
+        g.free()
+    finally:
+        os.unlink(path)
+
+
+def test_sink_errors(L):
+    from oracle import oracle as O
+    text, off = D.make_config("tiny", scale=0.05)
+    strings = _strings(text, off)
+    ta, oa = L.to_device(*O.pack(strings))
+    g = L.build(ta, oa, seed=SEED)
+    before = g.export()
+    # refused before anything streams: the sink is untouched and usable
+    with pytest.raises(L.LcgError) as e:
+        L.build_file_sink(g, "/nonexistent/collection.txt", 0)
+    assert e.value.name == "LCG_EINVAL"
+    _assert_same(g.export(), before)
+    # an empty file: no flush, nothing changes
+    fd, path = tempfile.mkstemp()
+    os.close(fd)
+    try:
+        info = L.build_file_sink(g, path, 0, chunk_bytes=4096)
+        assert info["strings"] == 0 and info["flushes"] == 0
+        _assert_same(g.export(), before)
+    finally:
+        os.unlink(path)
+    # a bad line after the first flushes: the sink is refused from then on
+    path = _write([b"ACGTACGTAC" * 100] * 20 + [b""] + [b"GG"])
+    try:
+        with pytest.raises(L.LcgError) as e:
+            L.build_file_sink(g, path, 0, chunk_bytes=4096)
+        assert e.value.name == "LCG_EINVAL"
+        with pytest.raises(L.LcgError):
+            g.export()
     finally:
         os.unlink(path)
