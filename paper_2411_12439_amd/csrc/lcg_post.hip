@@ -696,11 +696,21 @@ __global__ __launch_bounds__(kGrp) void k_pp_write(const uint64_t* __restrict__ 
       uint32_t y[kPer];
       stage_tile(rhs1, base0, b, s_y, y);
       uint64_t w[kPer];
+      uint32_t id[kPer];  // the new id of a kept symbol (one read of rk per position)
       bool rem[kPer];
 #pragma unroll
       for (int m = 0; m < kPer; ++m) {
         const bool valid = t0 + m < b;
-        rem[m] = valid && y[m] >= 256 && pp_rm(rk, y[m] - 256);
+        id[m] = y[m];
+        rem[m] = false;
+        if (valid && y[m] >= 256) {
+          const uint32_t z = y[m] - 256;
+          const uint64_t wd = rk[z >> 4];
+          const uint32_t rb = rm_bits((uint32_t)wd);
+          rem[m] = (rb >> (2 * (z & 15))) & 1;
+          id[m] = 256 + z - ((uint32_t)(wd >> 32) +
+                             (uint32_t)__builtin_popcount(rb & ((1u << (2 * (z & 15))) - 1)));
+        }
         w[m] = rem[m] ? W[y[m] - 256] : (valid ? 1 : 0);
       }
       uint64_t ex[kPer], tot;
@@ -710,8 +720,7 @@ __global__ __launch_bounds__(kGrp) void k_pp_write(const uint64_t* __restrict__ 
 #pragma unroll
       for (int m = 0; m < kPer; ++m) {
         if (t0 + m >= b || rem[m]) continue;
-        const uint32_t id = y[m] < 256 ? y[m] : pp_newid(rk, y[m] - 256);
-        rhs2[s_dest[jj[m]] + ex[m] - s_rs[jj[m]]] = id;
+        rhs2[s_dest[jj[m]] + ex[m] - s_rs[jj[m]]] = id[m];
       }
       carry += tot;
     }
