@@ -138,11 +138,11 @@ __device__ __forceinline__ void stage_tile(const uint32_t* __restrict__ rhs, uin
   for (int m = 0; m < kPer; ++m) y[m] = s_buf[kPer * threadIdx.x + m];
 }
 
-// the owner of t >= s_off[j], from j forward
+// the owner of t, given the owner j of t - 1 (or of t itself): rules are
+// never empty, so one position crosses at most one rule start
 __device__ __forceinline__ uint32_t owner_from(const uint64_t* s_off, uint32_t n, uint32_t j,
                                                uint64_t t) {
-  while (j + 1 < n && s_off[j + 1] <= t) ++j;
-  return j;
+  return j + (uint32_t)(j + 1 < n && s_off[j + 1] <= t);
 }
 
 __device__ __forceinline__ uint64_t lower_bound_u64(const uint64_t* a, uint64_t n, uint64_t key) {
